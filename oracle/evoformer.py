@@ -1,0 +1,251 @@
+"""FP64 CPU oracle of one Evoformer block, forward (and backward via autograd).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the product path never calls it.  It
+shares no code with the HIP path.
+
+It is the plain mathematical definition, written with einsum / matmul on
+float64 CPU tensors, with no blocking, fusion or reordering.  Gradients are
+those of this definition (torch autograd), pinned against central finite
+differences by the oracle tests.
+
+The paper (HelixFold, arXiv 2207.05477) names the operators but defers their
+equations to AlphaFold2 (Section "Challenges": the AlphaFold2 architecture;
+Section "Hyperparameter setting": the AlphaFold2 settings are followed
+strictly).  What the paper itself fixes:
+
+* tensor shapes: MSA [N_seq, N_res, C_m], pair [N_res, N_res, C_z] (Section
+  "Dynamic Axial Parallelism");
+* the attention family: row-wise and column-wise gated self-attention with an
+  optional gate before the output and a pair-derived bias added to the logits
+  ("nonbatched_bias") (Section "Fused Gated Self-Attention" and the caption of
+  the gated-attention figure; Section "Memory Read/Write In-place");
+* the two tracks of a block: the MSA stack, the outer product mean as the only
+  MSA-to-pair link, and the pair stack (Section "Branch Parallelism").
+
+The readings taken where the paper is silent:
+
+* LayerNorm: biased variance, eps = 1e-5, one affine per LayerNorm.
+* Attention logits scale 1/sqrt(head_dim), applied to q.k only (not the bias).
+* Masks replace the logits of masked keys by the constant MASK_LOGIT before
+  the softmax (not an additive penalty): a partially masked row gives masked
+  keys exactly zero weight, a fully masked row gives uniform weights, and no
+  gradient flows through a masked logit.  Queries are never masked.
+* Outer product mean: Linear_o(sum_s a_si (x) b_sj / (eps + n_ij)), the output
+  bias not divided, eps a runtime argument (default 1e-3).
+* Incoming triangle multiplication: x_ij = sum_k a_ki * b_kj.
+* Dropout is the identity.
+* Block order: row attention, column attention, MSA transition, outer product
+  mean, outgoing and incoming triangle multiplication, triangle attention
+  around the starting and the ending node, pair transition.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+F64 = torch.float64
+MASK_LOGIT = -1e30
+
+
+def layer_norm(x, g, b, eps):
+    """LayerNorm over the channel (last) axis with biased variance."""
+    mu = x.mean(-1, keepdim=True)
+    var = ((x - mu) ** 2).mean(-1, keepdim=True)
+    return (x - mu) / torch.sqrt(var + eps) * g + b
+
+
+def masked_softmax(logits, keep):
+    """Softmax over the last axis; logits where ``keep == 0`` are replaced by
+    MASK_LOGIT first (mask reading above)."""
+    s = torch.where(keep > 0, logits, torch.full_like(logits, MASK_LOGIT))
+    return torch.softmax(s, dim=-1)
+
+
+def row_attn(m, z, msa_mask, p, heads, head_dim, eps=1e-5):
+    """MSA row-wise gated self-attention with pair bias (the gated-attention
+    figure; "nonbatched_bias" of Section "Memory Read/Write In-place").
+
+    o^h_si = g^h_si * sum_j softmax_j(q^h_si . k^h_sj / sqrt(c) + b^h_ij) v^h_sj,
+    keys masked by msa_mask[s, j]; returns the update Linear_o(concat_h o)."""
+    S, R, _ = m.shape
+    H, c = heads, head_dim
+    y = layer_norm(m, p["ln_g"], p["ln_b"], eps)
+    yz = layer_norm(z, p["ln_z_g"], p["ln_z_b"], eps)
+    q = (y @ p["w_q"]).reshape(S, R, H, c)
+    k = (y @ p["w_k"]).reshape(S, R, H, c)
+    v = (y @ p["w_v"]).reshape(S, R, H, c)
+    bias = (yz @ p["w_bias"]).permute(2, 0, 1)                    # [H, i, j]
+    logits = torch.einsum("sihc,sjhc->shij", q, k) / math.sqrt(c) + bias[None]
+    a = masked_softmax(logits, msa_mask[:, None, None, :])
+    o = torch.einsum("shij,sjhc->sihc", a, v)
+    g = torch.sigmoid(y @ p["w_g"] + p["b_g"]).reshape(S, R, H, c)
+    return (g * o).reshape(S, R, H * c) @ p["w_o"] + p["b_o"]
+
+
+def col_attn(m, msa_mask, p, heads, head_dim, eps=1e-5):
+    """MSA column-wise gated self-attention (no pair bias): for each residue i
+    the MSA rows attend to each other; keys masked by msa_mask[t, i]."""
+    S, R, _ = m.shape
+    H, c = heads, head_dim
+    y = layer_norm(m, p["ln_g"], p["ln_b"], eps)
+    q = (y @ p["w_q"]).reshape(S, R, H, c)
+    k = (y @ p["w_k"]).reshape(S, R, H, c)
+    v = (y @ p["w_v"]).reshape(S, R, H, c)
+    logits = torch.einsum("sihc,tihc->ihst", q, k) / math.sqrt(c)
+    a = masked_softmax(logits, msa_mask.t()[:, None, None, :])
+    o = torch.einsum("ihst,tihc->sihc", a, v)
+    g = torch.sigmoid(y @ p["w_g"] + p["b_g"]).reshape(S, R, H, c)
+    return (g * o).reshape(S, R, H * c) @ p["w_o"] + p["b_o"]
+
+
+def col_global_attn(m, msa_mask, p, heads, head_dim, eps=1e-5, global_eps=1e-10):
+    """Column global attention of the extra-MSA stack: one masked-mean query
+    per residue column and head, single-head keys and values shared by all
+    heads, per-row gate."""
+    S, R, _ = m.shape
+    H, c = heads, head_dim
+    y = layer_norm(m, p["ln_g"], p["ln_b"], eps)
+    q = (y @ p["w_q"]).reshape(S, R, H, c)
+    k = y @ p["w_k"]                                              # [S, R, c]
+    v = y @ p["w_v"]
+    qbar = torch.einsum("si,sihc->ihc", msa_mask, q) / (msa_mask.sum(0)[:, None, None] + global_eps)
+    logits = torch.einsum("ihc,tic->iht", qbar, k) / math.sqrt(c)
+    a = masked_softmax(logits, msa_mask.t()[:, None, :])
+    o = torch.einsum("iht,tic->ihc", a, v)                        # [R, H, c]
+    g = torch.sigmoid(y @ p["w_g"] + p["b_g"]).reshape(S, R, H, c)
+    return (g * o[None]).reshape(S, R, H * c) @ p["w_o"] + p["b_o"]
+
+
+def transition(x, p, eps=1e-5):
+    """Two-layer MLP with ReLU on the LayerNormed input."""
+    y = layer_norm(x, p["ln_g"], p["ln_b"], eps)
+    return torch.relu(y @ p["w_1"] + p["b_1"]) @ p["w_2"] + p["b_2"]
+
+
+def outer_product_mean(m, msa_mask, p, eps=1e-5, opm_eps=1e-3):
+    """Outer product mean, the only MSA-to-pair communication of a block
+    (Section "Branch Parallelism").  O_ij = sum_s a_si (x) b_sj flattened as
+    p*c + q, divided by eps + n_ij with n_ij = sum_s M_si M_sj, then Linear_o."""
+    S, R, _ = m.shape
+    y = layer_norm(m, p["ln_g"], p["ln_b"], eps)
+    a = msa_mask[..., None] * (y @ p["w_a"] + p["b_a"])
+    b = msa_mask[..., None] * (y @ p["w_b"] + p["b_b"])
+    c = a.shape[-1]
+    outer = torch.einsum("sip,sjq->ijpq", a, b).reshape(R, R, c * c)
+    norm = msa_mask.t() @ msa_mask                                # n_ij
+    return (outer / (opm_eps + norm[..., None])) @ p["w_o"] + p["b_o"]
+
+
+def _tri_mul_proj(z, pair_mask, p, eps):
+    y = layer_norm(z, p["ln_g"], p["ln_b"], eps)
+    a = pair_mask[..., None] * torch.sigmoid(y @ p["w_ag"] + p["b_ag"]) * (y @ p["w_ap"] + p["b_ap"])
+    b = pair_mask[..., None] * torch.sigmoid(y @ p["w_bg"] + p["b_bg"]) * (y @ p["w_bp"] + p["b_bp"])
+    g = torch.sigmoid(y @ p["w_g"] + p["b_g"])
+    return a, b, g
+
+
+def tri_mul_out(z, pair_mask, p, eps=1e-5):
+    """Triangle multiplicative update with outgoing edges: x_ij = sum_k a_ik b_jk."""
+    a, b, g = _tri_mul_proj(z, pair_mask, p, eps)
+    x = torch.einsum("ikc,jkc->ijc", a, b)
+    return g * (layer_norm(x, p["ln_out_g"], p["ln_out_b"], eps) @ p["w_o"] + p["b_o"])
+
+
+def tri_mul_in(z, pair_mask, p, eps=1e-5):
+    """Triangle multiplicative update with incoming edges: x_ij = sum_k a_ki b_kj."""
+    a, b, g = _tri_mul_proj(z, pair_mask, p, eps)
+    x = torch.einsum("kic,kjc->ijc", a, b)
+    return g * (layer_norm(x, p["ln_out_g"], p["ln_out_b"], eps) @ p["w_o"] + p["b_o"])
+
+
+def tri_att_start(z, pair_mask, p, heads, head_dim, eps=1e-5):
+    """Triangle attention around the starting node:
+    o_ij = g_ij * sum_k softmax_k(q_ij . k_ik / sqrt(c) + b_jk) v_ik, keys masked by P_ik."""
+    R = z.shape[0]
+    H, c = heads, head_dim
+    y = layer_norm(z, p["ln_g"], p["ln_b"], eps)
+    q = (y @ p["w_q"]).reshape(R, R, H, c)
+    k = (y @ p["w_k"]).reshape(R, R, H, c)
+    v = (y @ p["w_v"]).reshape(R, R, H, c)
+    bias = (y @ p["w_bias"]).permute(2, 0, 1)                      # [H, j, k]
+    logits = torch.einsum("ijhc,ikhc->ihjk", q, k) / math.sqrt(c) + bias[None]
+    a = masked_softmax(logits, pair_mask[:, None, None, :])
+    o = torch.einsum("ihjk,ikhc->ijhc", a, v)
+    g = torch.sigmoid(y @ p["w_g"] + p["b_g"]).reshape(R, R, H, c)
+    return (g * o).reshape(R, R, H * c) @ p["w_o"] + p["b_o"]
+
+
+def tri_att_end(z, pair_mask, p, heads, head_dim, eps=1e-5):
+    """Triangle attention around the ending node:
+    o_ij = g_ij * sum_k softmax_k(q_ij . k_kj / sqrt(c) + b_ki) v_kj, keys masked by P_kj."""
+    R = z.shape[0]
+    H, c = heads, head_dim
+    y = layer_norm(z, p["ln_g"], p["ln_b"], eps)
+    q = (y @ p["w_q"]).reshape(R, R, H, c)
+    k = (y @ p["w_k"]).reshape(R, R, H, c)
+    v = (y @ p["w_v"]).reshape(R, R, H, c)
+    bias = (y @ p["w_bias"]).permute(2, 0, 1)                      # [H, k, i]
+    logits = torch.einsum("ijhc,kjhc->jhik", q, k) / math.sqrt(c) + bias.transpose(1, 2)[None]
+    a = masked_softmax(logits, pair_mask.t()[:, None, None, :])
+    o = torch.einsum("jhik,kjhc->ijhc", a, v)
+    g = torch.sigmoid(y @ p["w_g"] + p["b_g"]).reshape(R, R, H, c)
+    return (g * o).reshape(R, R, H * c) @ p["w_o"] + p["b_o"]
+
+
+def block(m, z, msa_mask, pair_mask, p, cfg):
+    """One Evoformer block (the extra-MSA block when cfg.extra_msa): residual
+    MSA stack, outer product mean, residual pair stack."""
+    eps = cfg.ln_eps
+    m = m + row_attn(m, z, msa_mask, p["row_attn"], cfg.msa_heads, cfg.msa_head_dim, eps)
+    if cfg.extra_msa:
+        m = m + col_global_attn(m, msa_mask, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim,
+                                eps, cfg.global_eps)
+    else:
+        m = m + col_attn(m, msa_mask, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim, eps)
+    m = m + transition(m, p["msa_trans"], eps)
+    z = z + outer_product_mean(m, msa_mask, p["opm"], eps, cfg.opm_eps)
+    z = z + tri_mul_out(z, pair_mask, p["tri_mul_out"], eps)
+    z = z + tri_mul_in(z, pair_mask, p["tri_mul_in"], eps)
+    z = z + tri_att_start(z, pair_mask, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps)
+    z = z + tri_att_end(z, pair_mask, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps)
+    z = z + transition(z, p["pair_trans"], eps)
+    return m, z
+
+
+def stack(m, z, msa_mask, pair_mask, blocks, cfg):
+    """Blocks applied in sequence with independent parameters."""
+    for p in blocks:
+        m, z = block(m, z, msa_mask, pair_mask, p, cfg)
+    return m, z
+
+
+def _leaf(t):
+    return t.detach().clone().to(F64).requires_grad_(True)
+
+
+def stack_fwd_bwd(inp, cfg, want_param_grads=True):
+    """Forward and backward of the stack on float64 copies of ``inp``.
+
+    Returns (m_out, z_out, grads) with grads = {"m", "z", "params"} where
+    grads["params"] mirrors inp["params"]; the loss is
+    <m_out, dm_out> + <z_out, dz_out>."""
+    m = _leaf(inp["m"])
+    z = _leaf(inp["z"])
+    blocks = [{s: {k: (_leaf(v) if want_param_grads else v.detach().to(F64))
+                   for k, v in blk[s].items()} for s in blk} for blk in inp["params"]]
+    m_out, z_out = stack(m, z, inp["msa_mask"].to(F64), inp["pair_mask"].to(F64), blocks, cfg)
+    loss = (m_out * inp["dm_out"].to(F64)).sum() + (z_out * inp["dz_out"].to(F64)).sum()
+    loss.backward()
+    grads = {"m": m.grad, "z": z.grad}
+    if want_param_grads:
+        grads["params"] = [{s: {k: v.grad for k, v in blk[s].items()} for s in blk}
+                           for blk in blocks]
+    return m_out.detach(), z_out.detach(), grads
+
+
+def stack_fwd(inp, cfg):
+    with torch.no_grad():
+        return stack(inp["m"].to(F64), inp["z"].to(F64), inp["msa_mask"].to(F64),
+                     inp["pair_mask"].to(F64), inp["params"], cfg)

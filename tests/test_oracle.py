@@ -1,0 +1,387 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+* brute-force pure-Python loops (tests/brute.py) on tiny inputs, every op and
+  the whole block, with masks that include fully masked rows and columns;
+* library routines (F.layer_norm, matmul) where an op reduces to one;
+* invariants fixed by the mathematics: transposition identities between the
+  starting/ending-node and outgoing/incoming ops, permutation equivariance,
+  LayerNorm shift-equivariance of the whole block, softmax normalisation and
+  mask semantics, closed forms (outer product mean with one MSA row);
+* central finite differences (gradcheck) for the oracle's gradients;
+* the paper's worked memory example (tests/golden/).
+"""
+import json
+import math
+import os
+
+import pytest
+import torch
+import torch.nn.functional as F
+
+import brute
+from oracle import evoformer as O
+from oracle import sizes
+from synth import EvoConfig, make_inputs
+
+F64 = torch.float64
+
+TINY = EvoConfig("tiny", n_seq=3, n_res=4, c_m=6, c_z=5, msa_heads=2, msa_head_dim=3,
+                 tri_heads=2, tri_head_dim=2, tri_mul_hidden=3, opm_hidden=2,
+                 transition_factor=2, mask_mode="random")
+TINY_X = TINY.replace(name="tiny_extra", extra_msa=True)
+
+
+def _inp(cfg=TINY, seed=5, mask_mode="random"):
+    return make_inputs(cfg, seed=seed, perturb=True, mask_mode=mask_mode)
+
+
+def _pl(p):
+    return {k: brute.t2l(v) for k, v in p.items()}
+
+
+def _close(a, b, tol=1e-10):
+    a = torch.as_tensor(a, dtype=F64)
+    b = torch.as_tensor(b, dtype=F64)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    err = (a - b).abs().max().item()
+    scale = max(1.0, b.abs().max().item())
+    assert err <= tol * scale, f"max abs err {err} (scale {scale})"
+
+
+# ---------------------------------------------------------------- LayerNorm
+
+def test_layer_norm_matches_library_and_invariants():
+    g = torch.Generator().manual_seed(1)
+    x = torch.randn(7, 11, dtype=F64, generator=g) * 3 + 2
+    gam = torch.randn(11, dtype=F64, generator=g)
+    bet = torch.randn(11, dtype=F64, generator=g)
+    ref = F.layer_norm(x, (11,), gam, bet, eps=1e-5)
+    _close(O.layer_norm(x, gam, bet, 1e-5), ref, 1e-12)
+    y = O.layer_norm(x, torch.ones(11, dtype=F64), torch.zeros(11, dtype=F64), 0.0)
+    _close(y.mean(-1), torch.zeros(7), 1e-12)
+    _close(y.var(-1, unbiased=False), torch.ones(7), 1e-12)
+
+
+# ---------------------------------------------------------------- softmax / masks
+
+def test_masked_softmax_semantics():
+    g = torch.Generator().manual_seed(2)
+    logits = torch.randn(5, 6, dtype=F64, generator=g) * 10
+    keep = (torch.rand(5, 6, generator=g) > 0.4).to(F64)
+    keep[0] = 0.0                       # fully masked row
+    keep[1] = 1.0
+    keep[1, 2] = 0.0
+    a = O.masked_softmax(logits, keep)
+    _close(a.sum(-1), torch.ones(5), 1e-14)
+    _close(a[0], torch.full((6,), 1 / 6, dtype=F64), 1e-14)   # uniform when fully masked
+    for r in range(1, 5):
+        if keep[r].sum() > 0:
+            assert torch.all(a[r][keep[r] == 0] == 0.0)       # exactly zero weight
+    for r in range(5):
+        _close(a[r], brute.softmax_masked(logits[r].tolist(), keep[r].tolist()), 1e-14)
+
+
+def test_masked_softmax_gradient_rows_sum_to_zero_and_masked_zero():
+    g = torch.Generator().manual_seed(3)
+    logits = torch.randn(4, 7, dtype=F64, generator=g).requires_grad_(True)
+    keep = (torch.rand(4, 7, generator=g) > 0.3).to(F64)
+    keep[2] = 0.0
+    up = torch.randn(4, 7, dtype=F64, generator=g)
+    (O.masked_softmax(logits, keep) * up).sum().backward()
+    d = logits.grad
+    _close(d.sum(-1), torch.zeros(4), 1e-13)       # sum_k dS_k = 0 (pair-bias grad rows)
+    assert torch.all(d[keep == 0] == 0.0)          # no gradient through masked logits
+
+
+# ---------------------------------------------------------------- brute force, per op
+
+def test_row_attn_vs_brute():
+    inp = _inp()
+    p = inp["params"][0]["row_attn"]
+    got = O.row_attn(inp["m"], inp["z"], inp["msa_mask"], p, TINY.msa_heads, TINY.msa_head_dim)
+    ref = brute.row_attn(brute.t2l(inp["m"]), brute.t2l(inp["z"]), brute.t2l(inp["msa_mask"]),
+                         _pl(p), TINY.msa_heads, TINY.msa_head_dim)
+    _close(got, ref)
+
+
+def test_col_attn_vs_brute():
+    inp = _inp()
+    p = inp["params"][0]["col_attn"]
+    got = O.col_attn(inp["m"], inp["msa_mask"], p, TINY.msa_heads, TINY.msa_head_dim)
+    ref = brute.col_attn(brute.t2l(inp["m"]), brute.t2l(inp["msa_mask"]), _pl(p),
+                         TINY.msa_heads, TINY.msa_head_dim)
+    _close(got, ref)
+
+
+def test_col_global_attn_vs_brute():
+    inp = _inp(TINY_X)
+    p = inp["params"][0]["col_attn"]
+    got = O.col_global_attn(inp["m"], inp["msa_mask"], p, TINY.msa_heads, TINY.msa_head_dim)
+    ref = brute.col_global_attn(brute.t2l(inp["m"]), brute.t2l(inp["msa_mask"]), _pl(p),
+                                TINY.msa_heads, TINY.msa_head_dim)
+    _close(got, ref)
+
+
+@pytest.mark.parametrize("sub", ["msa_trans", "pair_trans"])
+def test_transition_vs_brute(sub):
+    inp = _inp()
+    x = inp["m"] if sub == "msa_trans" else inp["z"]
+    p = inp["params"][0][sub]
+    _close(O.transition(x, p), brute.transition(brute.t2l(x), _pl(p)))
+
+
+def test_opm_vs_brute():
+    inp = _inp()
+    p = inp["params"][0]["opm"]
+    got = O.outer_product_mean(inp["m"], inp["msa_mask"], p)
+    ref = brute.outer_product_mean(brute.t2l(inp["m"]), brute.t2l(inp["msa_mask"]), _pl(p))
+    _close(got, ref)
+
+
+@pytest.mark.parametrize("sub", ["tri_mul_out", "tri_mul_in"])
+def test_tri_mul_vs_brute(sub):
+    inp = _inp()
+    p = inp["params"][0][sub]
+    fn = O.tri_mul_out if sub == "tri_mul_out" else O.tri_mul_in
+    bf = brute.tri_mul_out if sub == "tri_mul_out" else brute.tri_mul_in
+    _close(fn(inp["z"], inp["pair_mask"], p), bf(brute.t2l(inp["z"]), brute.t2l(inp["pair_mask"]), _pl(p)))
+
+
+@pytest.mark.parametrize("sub", ["tri_att_start", "tri_att_end"])
+def test_tri_att_vs_brute(sub):
+    inp = _inp()
+    p = inp["params"][0][sub]
+    fn = O.tri_att_start if sub == "tri_att_start" else O.tri_att_end
+    bf = brute.tri_att_start if sub == "tri_att_start" else brute.tri_att_end
+    got = fn(inp["z"], inp["pair_mask"], p, TINY.tri_heads, TINY.tri_head_dim)
+    ref = bf(brute.t2l(inp["z"]), brute.t2l(inp["pair_mask"]), _pl(p), TINY.tri_heads, TINY.tri_head_dim)
+    _close(got, ref)
+
+
+@pytest.mark.parametrize("cfg", [TINY, TINY_X], ids=["evoformer", "extra_msa"])
+def test_block_vs_brute(cfg):
+    inp = _inp(cfg)
+    p = inp["params"][0]
+    m, z = O.block(inp["m"], inp["z"], inp["msa_mask"], inp["pair_mask"], p, cfg)
+    pl = {s: _pl(p[s]) for s in p}
+    bm, bz = brute.block(brute.t2l(inp["m"]), brute.t2l(inp["z"]), brute.t2l(inp["msa_mask"]),
+                         brute.t2l(inp["pair_mask"]), pl, cfg)
+    _close(m, bm)
+    _close(z, bz)
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_col_attn_is_row_attn_without_bias_on_transposed_msa():
+    inp = _inp()
+    pc = inp["params"][0]["col_attn"]
+    pr = dict(pc)
+    pr["ln_z_g"] = torch.ones(TINY.c_z, dtype=F64)
+    pr["ln_z_b"] = torch.zeros(TINY.c_z, dtype=F64)
+    pr["w_bias"] = torch.zeros(TINY.c_z, TINY.msa_heads, dtype=F64)
+    mT = inp["m"].transpose(0, 1).contiguous()
+    zT = torch.zeros(TINY.n_seq, TINY.n_seq, TINY.c_z, dtype=F64)
+    row = O.row_attn(mT, zT, inp["msa_mask"].t(), pr, TINY.msa_heads, TINY.msa_head_dim)
+    col = O.col_attn(inp["m"], inp["msa_mask"], pc, TINY.msa_heads, TINY.msa_head_dim)
+    _close(col, row.transpose(0, 1), 1e-12)
+
+
+def test_tri_att_end_is_transposed_start():
+    inp = _inp()
+    p = inp["params"][0]["tri_att_start"]
+    z, P = inp["z"], inp["pair_mask"]
+    end = O.tri_att_end(z, P, p, TINY.tri_heads, TINY.tri_head_dim)
+    start_T = O.tri_att_start(z.transpose(0, 1), P.t(), p, TINY.tri_heads, TINY.tri_head_dim)
+    _close(end, start_T.transpose(0, 1), 1e-12)
+
+
+def test_tri_mul_in_is_transposed_out_with_swapped_operands():
+    inp = _inp()
+    p = inp["params"][0]["tri_mul_in"]
+    swapped = dict(p)
+    for x, y in (("w_ap", "w_bp"), ("b_ap", "b_bp"), ("w_ag", "w_bg"), ("b_ag", "b_bg")):
+        swapped[x], swapped[y] = p[y], p[x]
+    z, P = inp["z"], inp["pair_mask"]
+    tin = O.tri_mul_in(z, P, p)
+    tout_T = O.tri_mul_out(z.transpose(0, 1), P.t(), swapped)
+    _close(tin, tout_T.transpose(0, 1), 1e-12)
+
+
+def test_tri_mul_contraction_is_per_channel_matmul():
+    # x_ij = sum_k a_ik b_jk is, channel by channel, the matrix product A_c B_c^T
+    g = torch.Generator().manual_seed(4)
+    a = torch.randn(5, 5, 3, dtype=F64, generator=g)
+    b = torch.randn(5, 5, 3, dtype=F64, generator=g)
+    x_out = torch.einsum("ikc,jkc->ijc", a, b)
+    x_in = torch.einsum("kic,kjc->ijc", a, b)
+    for c in range(3):
+        _close(x_out[..., c], a[..., c] @ b[..., c].t(), 1e-13)
+        _close(x_in[..., c], a[..., c].t() @ b[..., c], 1e-13)
+
+
+def test_row_attn_equivariant_to_msa_row_and_residue_permutation():
+    inp = _inp(TINY.replace(n_seq=4, n_res=5))
+    p = inp["params"][0]["row_attn"]
+    m, z, M = inp["m"], inp["z"], inp["msa_mask"]
+    H, c = TINY.msa_heads, TINY.msa_head_dim
+    base = O.row_attn(m, z, M, p, H, c)
+    ps = torch.tensor([2, 0, 3, 1])
+    _close(O.row_attn(m[ps], z, M[ps], p, H, c), base[ps], 1e-12)
+    pr = torch.tensor([4, 2, 0, 1, 3])
+    got = O.row_attn(m[:, pr], z[pr][:, pr], M[:, pr], p, H, c)
+    _close(got, base[:, pr], 1e-12)
+
+
+def test_tri_att_start_equivariant_to_residue_permutation():
+    inp = _inp(TINY.replace(n_res=5))
+    p = inp["params"][0]["tri_att_start"]
+    z, P = inp["z"], inp["pair_mask"]
+    pr = torch.tensor([3, 0, 4, 2, 1])
+    base = O.tri_att_start(z, P, p, TINY.tri_heads, TINY.tri_head_dim)
+    got = O.tri_att_start(z[pr][:, pr], P[pr][:, pr], p, TINY.tri_heads, TINY.tri_head_dim)
+    _close(got, base[pr][:, pr], 1e-12)
+
+
+def test_masked_keys_do_not_influence_output():
+    # Perturbing m at (s=0, j=3) moves key/value 3 of MSA row 0, which is masked
+    # there, and query (0, 3) itself; every other query of row 0 is unchanged.
+    inp = _inp()
+    pr = inp["params"][0]["row_attn"]
+    m, zz, M = inp["m"].clone(), inp["z"], inp["msa_mask"].clone()
+    M[0] = 1.0
+    M[0, 3] = 0.0
+    out = O.row_attn(m, zz, M, pr, TINY.msa_heads, TINY.msa_head_dim)
+    m2 = m.clone()
+    m2[0, 3] += torch.linspace(-2.0, 3.0, TINY.c_m, dtype=F64) ** 2
+    out2 = O.row_attn(m2, zz, M, pr, TINY.msa_heads, TINY.msa_head_dim)
+    _close(out2[0, [0, 1, 2]], out[0, [0, 1, 2]], 1e-12)
+    assert (out2[0, 3] - out[0, 3]).abs().max() > 1e-3
+
+
+def test_opm_single_row_is_one_outer_product():
+    cfg = TINY.replace(n_seq=1, opm_eps=0.0)
+    inp = make_inputs(cfg, seed=9, perturb=True, mask_mode="full")
+    p = inp["params"][0]["opm"]
+    m = inp["m"]
+    got = O.outer_product_mean(m, inp["msa_mask"], p, opm_eps=0.0)
+    y = F.layer_norm(m[0], (cfg.c_m,), p["ln_g"], p["ln_b"], eps=1e-5)
+    a = y @ p["w_a"] + p["b_a"]
+    b = y @ p["w_b"] + p["b_b"]
+    R, ch = cfg.n_res, cfg.opm_hidden
+    for i in range(R):
+        for j in range(R):
+            flat = torch.outer(a[i], b[j]).reshape(ch * ch)
+            _close(got[i, j], flat @ p["w_o"] + p["b_o"], 1e-12)
+
+
+def test_opm_is_matmul_of_projections():
+    inp = _inp(mask_mode="full")
+    p = inp["params"][0]["opm"]
+    S, R, ch = TINY.n_seq, TINY.n_res, TINY.opm_hidden
+    y = F.layer_norm(inp["m"], (TINY.c_m,), p["ln_g"], p["ln_b"], eps=1e-5)
+    a = (y @ p["w_a"] + p["b_a"]).reshape(S, R * ch)
+    b = (y @ p["w_b"] + p["b_b"]).reshape(S, R * ch)
+    outer = (a.t() @ b).reshape(R, ch, R, ch).permute(0, 2, 1, 3).reshape(R, R, ch * ch)
+    ref = outer / (1e-3 + S) @ p["w_o"] + p["b_o"]
+    _close(O.outer_product_mean(inp["m"], inp["msa_mask"], p), ref, 1e-12)
+
+
+@pytest.mark.parametrize("cfg", [TINY, TINY_X], ids=["evoformer", "extra_msa"])
+def test_block_layernorm_shift_equivariance(cfg):
+    # Every update reads only LayerNormed inputs, so adding a per-position
+    # constant to all channels of m or z passes straight through the block.
+    inp = _inp(cfg)
+    p = inp["params"][0]
+    g = torch.Generator().manual_seed(11)
+    dm = torch.randn(cfg.n_seq, cfg.n_res, 1, dtype=F64, generator=g) * 3
+    dz = torch.randn(cfg.n_res, cfg.n_res, 1, dtype=F64, generator=g) * 3
+    m0, z0 = O.block(inp["m"], inp["z"], inp["msa_mask"], inp["pair_mask"], p, cfg)
+    m1, z1 = O.block(inp["m"] + dm, inp["z"] + dz, inp["msa_mask"], inp["pair_mask"], p, cfg)
+    _close(m1, m0 + dm, 1e-10)
+    _close(z1, z0 + dz, 1e-10)
+
+
+# ---------------------------------------------------------------- gradients
+
+def _gc(fn, *args):
+    assert torch.autograd.gradcheck(fn, args, eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def test_gradcheck_ops():
+    inp = _inp()
+    P = inp["params"][0]
+    M, Pm = inp["msa_mask"], inp["pair_mask"]
+    m = inp["m"].clone().requires_grad_(True)
+    z = inp["z"].clone().requires_grad_(True)
+    H, c, Ht, ct = TINY.msa_heads, TINY.msa_head_dim, TINY.tri_heads, TINY.tri_head_dim
+    wq = P["row_attn"]["w_q"].clone().requires_grad_(True)
+
+    def row(m_, z_, wq_):
+        p = dict(P["row_attn"]); p["w_q"] = wq_
+        return O.row_attn(m_, z_, M, p, H, c)
+    _gc(row, m, z, wq)
+    _gc(lambda m_: O.col_attn(m_, M, P["col_attn"], H, c), m)
+    _gc(lambda m_: O.transition(m_, P["msa_trans"]), m)
+    wo = P["opm"]["w_o"].clone().requires_grad_(True)
+
+    def opm(m_, wo_):
+        p = dict(P["opm"]); p["w_o"] = wo_
+        return O.outer_product_mean(m_, M, p)
+    _gc(opm, m, wo)
+    _gc(lambda z_: O.tri_mul_out(z_, Pm, P["tri_mul_out"]), z)
+    _gc(lambda z_: O.tri_mul_in(z_, Pm, P["tri_mul_in"]), z)
+    wb = P["tri_att_start"]["w_bias"].clone().requires_grad_(True)
+
+    def tas(z_, wb_):
+        p = dict(P["tri_att_start"]); p["w_bias"] = wb_
+        return O.tri_att_start(z_, Pm, p, Ht, ct)
+    _gc(tas, z, wb)
+    _gc(lambda z_: O.tri_att_end(z_, Pm, P["tri_att_end"], Ht, ct), z)
+
+
+def test_gradcheck_global_attn_and_block():
+    inp = _inp(TINY_X)
+    p = inp["params"][0]
+    m = inp["m"].clone().requires_grad_(True)
+    z = inp["z"].clone().requires_grad_(True)
+    _gc(lambda m_: O.col_global_attn(m_, inp["msa_mask"], p["col_attn"], 2, 3), m)
+    inp2 = _inp(TINY)
+    m2 = inp2["m"].clone().requires_grad_(True)
+    z2 = inp2["z"].clone().requires_grad_(True)
+    _gc(lambda a, b: O.block(a, b, inp2["msa_mask"], inp2["pair_mask"], inp2["params"][0], TINY), m2, z2)
+    assert z.shape[0] == TINY.n_res
+
+
+def test_stack_fwd_bwd_grads_match_gradcheck_direction():
+    # directional derivative of the stack loss vs a central difference
+    cfg = TINY.replace(n_blocks=2)
+    inp = make_inputs(cfg, seed=13, perturb=True)
+    m_out, z_out, grads = O.stack_fwd_bwd(inp, cfg)
+    g = torch.Generator().manual_seed(14)
+    vm = torch.randn(inp["m"].shape, dtype=F64, generator=g)
+    vz = torch.randn(inp["z"].shape, dtype=F64, generator=g)
+    h = 1e-5
+
+    def loss(dm_, dz_):
+        x = dict(inp); x["m"] = inp["m"] + dm_; x["z"] = inp["z"] + dz_
+        mo, zo = O.stack_fwd(x, cfg)
+        return (mo * inp["dm_out"]).sum() + (zo * inp["dz_out"]).sum()
+    fd = (loss(h * vm, h * vz) - loss(-h * vm, -h * vz)) / (2 * h)
+    an = (grads["m"] * vm).sum() + (grads["z"] * vz).sum()
+    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+# ---------------------------------------------------------------- paper's worked example
+
+def test_golden_logits_memory_example():
+    path = os.path.join(os.path.dirname(__file__), "golden", "logits_memory.json")
+    with open(path) as f:
+        cases = json.load(f)["cases"]
+    for cse in cases:
+        if cse["kind"] == "logits":
+            got = sizes.logits_bytes(cse["n_seq"], cse["n_head"], cse["n_res"], cse["elem_bytes"],
+                                     cse.get("chunk", 0))
+        else:
+            got = sizes.activation_bytes(cse["rows"], cse["cols"], cse["elem_bytes"], cse.get("chunk", 0))
+        exp = cse["bytes"] if "bytes" in cse else cse["gib"] * 2 ** 30
+        assert math.isclose(got, exp, rel_tol=1e-12), (cse, got)
