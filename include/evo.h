@@ -1,0 +1,266 @@
+/*
+ * evo.h -- C ABI of the MI355X (gfx950) Evoformer block library (libevo.so).
+ *
+ * One Evoformer block of AlphaFold2 as re-implemented in HelixFold
+ * (arXiv 2207.05477): gated self-attention with pair bias along MSA rows,
+ * along MSA columns (or the global column attention of the extra-MSA stack)
+ * and around the starting and ending node of the pair representation; the
+ * triangle multiplicative updates; the outer product mean; the transitions.
+ * Forward and backward, FP32 or BF16 activations.
+ *
+ * Layout (paper, Section "Dynamic Axial Parallelism"): the MSA representation
+ * is [N_seq, N_res, C_m] and the pair representation [N_res, N_res, C_z], one
+ * protein per call (mini-batch 1 per device, Section "Hyperparameter
+ * setting"), channel-last, dense row-major.
+ *
+ * Conventions shared by every entry point
+ *  - Return: evo_status_t.  On any error nothing has been enqueued; the
+ *    message is available from evo_last_error() (thread-local).
+ *  - Pointers: device pointers owned by the caller, unless stated.  The
+ *    library never allocates device memory; scratch comes from the caller's
+ *    workspace (ws, ws_bytes), sized by the matching *_workspace_bytes query.
+ *    Every device pointer must be 16-byte aligned.
+ *  - dtype: activations (x, pair, out, d_out, d_x, saved) are evo_dtype_t
+ *    (FP32 or BF16).  Parameters and parameter gradients are always FP32.
+ *    Masks are FP32 arrays of 0/1; NULL means all ones.
+ *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = default
+ *    stream) with no host synchronisation; device faults surface at the
+ *    caller's next synchronisation.
+ *  - Forward computes out = x + f(x); out may alias x.
+ *  - Backward writes d_x = d_out + J_f(x)^T d_out (d_x may alias d_out).
+ *    Cross-input gradients (d_pair, d_m of the outer product mean) and all
+ *    parameter gradients are ACCUMULATED (+=) into caller-initialised FP32 /
+ *    activation buffers.
+ *  - Determinism: no floating-point atomics; results are bitwise
+ *    reproducible run to run for equal inputs and launch configuration.
+ *  - Masked attention keys: the logit of a masked key is replaced by a large
+ *    negative constant, so a partially masked row gives masked keys zero
+ *    weight and a fully masked row averages all keys uniformly; no gradient
+ *    flows through masked logits.
+ */
+#ifndef EVO_H_
+#define EVO_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EVO_OK = 0,
+  EVO_EINVAL = 1,       /* null / misaligned pointer, bad enum value */
+  EVO_ESHAPE = 2,       /* unsupported sizes (e.g. head_dim not in {8,16,32,64}) */
+  EVO_EWORKSPACE = 3,   /* workspace too small */
+  EVO_EHIP = 4,         /* HIP runtime / launch error */
+  EVO_EUNSUPPORTED = 5  /* device is not gfx950 */
+} evo_status_t;
+
+typedef enum { EVO_F32 = 0, EVO_BF16 = 1 } evo_dtype_t;
+
+typedef enum { EVO_PHASE_FWD = 0, EVO_PHASE_BWD = 1 } evo_phase_t;
+
+/* ------------------------------------------------------------------ attention
+ * Gated multi-head self-attention (paper, Section "Fused Gated
+ * Self-Attention" and its gated-attention figure: row-wise and column-wise
+ * attention, gating before the output projection, a pair-derived
+ * "nonbatched_bias" added to the logits):
+ *   y = LayerNorm(x); q,k,v = y W_{q,k,v} (no bias); g = sigmoid(y W_g + b_g)
+ *   o = g * softmax(q k^T / sqrt(head_dim) + bias (+ key mask)) v
+ *   out = x + o W_o + b_o
+ * kinds (x = [n_outer, n_inner, c_in], mask = [n_outer, n_inner]):
+ *   ROW        MSA rows: for each s, queries/keys along residues;
+ *              bias b_ij = LayerNorm_z(pair_ij) W_bias, pair = [n_inner, n_inner, c_pair];
+ *              key mask mask[s, j].
+ *   COL        MSA columns: for each residue i, queries/keys along s; no bias;
+ *              key mask mask[t, i].
+ *   COL_GLOBAL extra-MSA global column attention: one masked-mean query per
+ *              (i, head), w_k, w_v are [c_in, head_dim] shared by all heads;
+ *              mean over s uses global_eps.
+ *   TRI_START  triangle attention around the starting node (x = z, square):
+ *              o_ij = sum_k softmax_k(q_ij.k_ik/sqrt(c) + b_jk) v_ik, key mask mask[i, k];
+ *              bias b_jk = y_jk W_bias (same LayerNorm as q, k, v).
+ *   TRI_END    around the ending node: o_ij = sum_k softmax_k(q_ij.k_kj/sqrt(c) + b_ki) v_kj,
+ *              key mask mask[k, j].
+ */
+typedef enum {
+  EVO_ATTN_ROW = 0,
+  EVO_ATTN_COL = 1,
+  EVO_ATTN_COL_GLOBAL = 2,
+  EVO_ATTN_TRI_START = 3,
+  EVO_ATTN_TRI_END = 4
+} evo_attn_kind_t;
+
+typedef struct {
+  int32_t kind;       /* evo_attn_kind_t */
+  int32_t dtype;      /* evo_dtype_t */
+  int64_t n_outer;    /* S for MSA kinds, N_res for TRI kinds */
+  int64_t n_inner;    /* N_res */
+  int64_t c_in;       /* channels of x */
+  int64_t c_pair;     /* ROW: channels of pair; otherwise ignored */
+  int32_t heads;
+  int32_t head_dim;   /* 8, 16, 32 or 64 */
+  float ln_eps;
+  float global_eps;   /* COL_GLOBAL only */
+  int64_t chunk;      /* TRI kinds, forward without saved: query rows per chunk (0 = all) */
+} evo_attn_desc_t;
+
+/* Parameter (or parameter-gradient) pointers, FP32, Linear weights [fan_in, fan_out]. */
+typedef struct {
+  float *ln_g, *ln_b;         /* [c_in] */
+  float *ln_z_g, *ln_z_b;     /* ROW: [c_pair]; else NULL */
+  float *w_q;                 /* [c_in, H*c] */
+  float *w_k, *w_v;           /* [c_in, H*c]; COL_GLOBAL: [c_in, c] */
+  float *w_bias;              /* ROW: [c_pair, H]; TRI: [c_in, H]; else NULL */
+  float *w_g, *b_g;           /* [c_in, H*c], [H*c] */
+  float *w_o, *b_o;           /* [H*c, c_in], [c_in] */
+} evo_attn_w_t;
+
+size_t evo_attn_workspace_bytes(const evo_attn_desc_t* desc, int32_t phase);
+/* Bytes of the buffer that evo_attn_fwd fills for evo_attn_bwd (0 if unsupported). */
+size_t evo_attn_saved_bytes(const evo_attn_desc_t* desc);
+
+/* out = x + Attn(x[, pair]).  saved: NULL for inference, else a buffer of
+ * evo_attn_saved_bytes(desc) that evo_attn_bwd consumes. */
+evo_status_t evo_attn_fwd(const evo_attn_desc_t* desc, const evo_attn_w_t* w,
+                          const void* x, const void* pair, const float* mask,
+                          void* out, void* saved, void* ws, size_t ws_bytes, void* stream);
+
+/* d_x = d_out + J^T d_out; ROW: d_pair += J_pair^T d_out; d_w += parameter gradients.
+ * x, pair, mask and w must be those of the forward that filled `saved`. */
+evo_status_t evo_attn_bwd(const evo_attn_desc_t* desc, const evo_attn_w_t* w,
+                          const void* x, const void* pair, const float* mask,
+                          const void* saved, const void* d_out, void* d_x, void* d_pair,
+                          const evo_attn_w_t* d_w, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ transition
+ * x + ReLU(LayerNorm(x) W_1 + b_1) W_2 + b_2, hidden = factor * c; x = [rows, c]. */
+typedef struct {
+  int32_t dtype;
+  int64_t rows, c, factor;
+  float ln_eps;
+} evo_trans_desc_t;
+
+typedef struct { float *ln_g, *ln_b, *w_1, *b_1, *w_2, *b_2; } evo_trans_w_t;
+
+size_t evo_transition_workspace_bytes(const evo_trans_desc_t* desc, int32_t phase);
+size_t evo_transition_saved_bytes(const evo_trans_desc_t* desc);
+evo_status_t evo_transition_fwd(const evo_trans_desc_t* desc, const evo_trans_w_t* w,
+                                const void* x, void* out, void* saved,
+                                void* ws, size_t ws_bytes, void* stream);
+evo_status_t evo_transition_bwd(const evo_trans_desc_t* desc, const evo_trans_w_t* w,
+                                const void* x, const void* saved, const void* d_out, void* d_x,
+                                const evo_trans_w_t* d_w, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ outer product mean
+ * The only MSA-to-pair link of a block (paper, Section "Branch Parallelism"):
+ *   y = LayerNorm(m); a = mask * (y W_a + b_a); b = mask * (y W_b + b_b)   [S, R, c_h]
+ *   O_ij = sum_s a_si (outer) b_sj, flattened p*c_h + q;  n_ij = sum_s mask_si mask_sj
+ *   z_out = z_in + (O_ij / (opm_eps + n_ij)) W_o + b_o
+ */
+typedef struct {
+  int32_t dtype;
+  int64_t n_seq, n_res, c_m, c_hidden, c_z;
+  float ln_eps, opm_eps;
+} evo_opm_desc_t;
+
+typedef struct { float *ln_g, *ln_b, *w_a, *b_a, *w_b, *b_b, *w_o, *b_o; } evo_opm_w_t;
+
+size_t opm_workspace_bytes(const evo_opm_desc_t* desc, int32_t phase);
+size_t opm_saved_bytes(const evo_opm_desc_t* desc);
+/* z_out = z_in + OPM(m); z_out may alias z_in. */
+evo_status_t opm_fwd(const evo_opm_desc_t* desc, const evo_opm_w_t* w, const void* m,
+                     const float* msa_mask, const void* z_in, void* z_out, void* saved,
+                     void* ws, size_t ws_bytes, void* stream);
+/* d_m += J_m^T dz_out (the pair gradient passes through unchanged); d_w += ... */
+evo_status_t opm_bwd(const evo_opm_desc_t* desc, const evo_opm_w_t* w, const void* m,
+                     const float* msa_mask, const void* saved, const void* dz_out, void* d_m,
+                     const evo_opm_w_t* d_w, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ triangle multiplication
+ *   y = LayerNorm(z); a = P * sigmoid(y W_ag + b_ag) * (y W_ap + b_ap); b likewise;
+ *   g = sigmoid(y W_g + b_g)
+ *   OUT: x_ij = sum_k a_ik b_jk      IN: x_ij = sum_k a_ki b_kj
+ *   z_out = z + g * (LayerNorm_out(x) W_o + b_o);   P = pair mask [R, R]
+ */
+typedef enum { EVO_TRI_OUT = 0, EVO_TRI_IN = 1 } evo_tri_dir_t;
+
+typedef struct {
+  int32_t dtype;
+  int32_t dir;        /* evo_tri_dir_t */
+  int64_t n_res, c_z, c_hidden;
+  float ln_eps;
+  int64_t chunk;      /* forward without saved: output rows per chunk (0 = all) */
+} evo_trimul_desc_t;
+
+typedef struct {
+  float *ln_g, *ln_b;
+  float *w_ap, *b_ap, *w_ag, *b_ag, *w_bp, *b_bp, *w_bg, *b_bg;   /* [c_z, c_h], [c_h] */
+  float *w_g, *b_g;                                               /* [c_z, c_z], [c_z] */
+  float *ln_out_g, *ln_out_b;                                     /* [c_h] */
+  float *w_o, *b_o;                                               /* [c_h, c_z], [c_z] */
+} evo_trimul_w_t;
+
+size_t tri_mul_workspace_bytes(const evo_trimul_desc_t* desc, int32_t phase);
+size_t tri_mul_saved_bytes(const evo_trimul_desc_t* desc);
+evo_status_t tri_mul_fwd(const evo_trimul_desc_t* desc, const evo_trimul_w_t* w,
+                         const void* z, const float* pair_mask, void* z_out, void* saved,
+                         void* ws, size_t ws_bytes, void* stream);
+evo_status_t tri_mul_bwd(const evo_trimul_desc_t* desc, const evo_trimul_w_t* w,
+                         const void* z, const float* pair_mask, const void* saved,
+                         const void* dz_out, void* dz, const evo_trimul_w_t* d_w,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ Evoformer block
+ * m <- m + RowAttn(m, z); m <- m + ColAttn(m) (ColGlobalAttn if extra_msa);
+ * m <- m + Transition(m); z <- z + OPM(m); z <- z + TriMulOut(z);
+ * z <- z + TriMulIn(z); z <- z + TriAttnStart(z); z <- z + TriAttnEnd(z);
+ * z <- z + Transition(z).   Dropout is the identity.
+ * The block is the activation-checkpoint boundary (paper, Section "Recompute"):
+ * the forward saves nothing and the backward recomputes the forward into the
+ * workspace before running the backward ops in reverse order.
+ */
+typedef struct {
+  int32_t dtype;
+  int32_t extra_msa;          /* 1: column attention is COL_GLOBAL */
+  int64_t n_seq, n_res, c_m, c_z;
+  int32_t msa_heads, msa_head_dim, tri_heads, tri_head_dim;
+  int64_t tri_mul_hidden, opm_hidden, transition_factor;
+  int64_t chunk;              /* forward only: pair-stack query-row chunk (0 = none) */
+  float ln_eps, opm_eps, global_eps;
+} evo_block_desc_t;
+
+typedef struct {
+  evo_attn_w_t row_attn, col_attn;
+  evo_trans_w_t msa_trans;
+  evo_opm_w_t opm;
+  evo_trimul_w_t tri_mul_out, tri_mul_in;
+  evo_attn_w_t tri_att_start, tri_att_end;
+  evo_trans_w_t pair_trans;
+} evo_block_w_t;
+
+size_t evoformer_block_workspace_bytes(const evo_block_desc_t* desc, int32_t phase);
+/* m_out/z_out may alias m/z. */
+evo_status_t evoformer_block_fwd(const evo_block_desc_t* desc, const evo_block_w_t* w,
+                                 const void* m, const void* z, const float* msa_mask,
+                                 const float* pair_mask, void* m_out, void* z_out,
+                                 void* ws, size_t ws_bytes, void* stream);
+/* dm = dm_out + J_m^T(...), dz likewise, d_w += parameter gradients of the block.
+ * dm/dz may alias dm_out/dz_out. */
+evo_status_t evoformer_block_bwd(const evo_block_desc_t* desc, const evo_block_w_t* w,
+                                 const void* m, const void* z, const float* msa_mask,
+                                 const float* pair_mask, const void* dm_out, const void* dz_out,
+                                 void* dm, void* dz, const evo_block_w_t* d_w,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ misc */
+const char* evo_version(void);
+const char* evo_last_error(void);
+/* EVO_OK if the current HIP device is gfx950, EVO_EUNSUPPORTED otherwise. */
+evo_status_t evo_device_check(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EVO_H_ */

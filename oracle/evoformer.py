@@ -230,19 +230,34 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True):
 
     Returns (m_out, z_out, grads) with grads = {"m", "z", "params"} where
     grads["params"] mirrors inp["params"]; the loss is
-    <m_out, dm_out> + <z_out, dz_out>."""
-    m = _leaf(inp["m"])
-    z = _leaf(inp["z"])
-    blocks = [{s: {k: (_leaf(v) if want_param_grads else v.detach().to(F64))
-                   for k, v in blk[s].items()} for s in blk} for blk in inp["params"]]
-    m_out, z_out = stack(m, z, inp["msa_mask"].to(F64), inp["pair_mask"].to(F64), blocks, cfg)
-    loss = (m_out * inp["dm_out"].to(F64)).sum() + (z_out * inp["dz_out"].to(F64)).sum()
-    loss.backward()
-    grads = {"m": m.grad, "z": z.grad}
+    <m_out, dm_out> + <z_out, dz_out>.  The chain rule is applied block by
+    block (each block's forward is re-run under autograd during the backward),
+    which keeps the memory of one block; the values are those of the plain
+    definition."""
+    msa_mask = inp["msa_mask"].to(F64)
+    pair_mask = inp["pair_mask"].to(F64)
+    acts = [(inp["m"].detach().to(F64), inp["z"].detach().to(F64))]
+    with torch.no_grad():
+        for p in inp["params"]:
+            acts.append(block(acts[-1][0], acts[-1][1], msa_mask, pair_mask, p, cfg))
+    dm = inp["dm_out"].to(F64)
+    dz = inp["dz_out"].to(F64)
+    pgrads = [None] * len(inp["params"])
+    for i in reversed(range(len(inp["params"]))):
+        m = _leaf(acts[i][0])
+        z = _leaf(acts[i][1])
+        blk = inp["params"][i]
+        leaves = {s: {k: (_leaf(v) if want_param_grads else v.detach().to(F64))
+                      for k, v in blk[s].items()} for s in blk}
+        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg)
+        ((mo * dm).sum() + (zo * dz).sum()).backward()
+        dm, dz = m.grad, z.grad
+        if want_param_grads:
+            pgrads[i] = {s: {k: v.grad for k, v in leaves[s].items()} for s in leaves}
+    grads = {"m": dm, "z": dz}
     if want_param_grads:
-        grads["params"] = [{s: {k: v.grad for k, v in blk[s].items()} for s in blk}
-                           for blk in blocks]
-    return m_out.detach(), z_out.detach(), grads
+        grads["params"] = pgrads
+    return acts[-1][0], acts[-1][1], grads
 
 
 def stack_fwd(inp, cfg):

@@ -1,0 +1,302 @@
+"""Python binding of libevo.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  PyTorch
+supplies device memory, the current HIP stream and data pointers; all
+arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi as A
+
+DTYPES = {"f32": (A.EVO_F32, torch.float32), "bf16": (A.EVO_BF16, torch.bfloat16)}
+BLOCK_SUBOPS = ("row_attn", "col_attn", "msa_trans", "opm", "tri_mul_out", "tri_mul_in",
+                "tri_att_start", "tri_att_end", "pair_trans")
+_ALIGN = 64  # FP32 elements = 256 bytes
+
+
+def _lib():
+    return A.load()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def act_dtype(name: str) -> torch.dtype:
+    return DTYPES[name][1]
+
+
+# ------------------------------------------------------------------ workspaces
+_WS: dict = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A reusable byte buffer per (device, stream); grows as needed."""
+    device = torch.device(device)
+    key = (device.index, torch.cuda.current_stream(device).cuda_stream)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf
+
+
+def release_workspaces():
+    _WS.clear()
+
+
+# ------------------------------------------------------------------ parameters
+class FlatParams:
+    """The parameters of one block in one contiguous FP32 device buffer, each
+    tensor at a 256-byte aligned offset; C weight structs point into it.  A
+    buffer of the same layout holds the parameter gradients."""
+
+    def __init__(self, named: dict, device, subops=BLOCK_SUBOPS):
+        self.layout = []
+        off = 0
+        for sub in subops:
+            for name, t in named[sub].items():
+                n = int(t.numel())
+                self.layout.append((sub, name, off, tuple(t.shape)))
+                off += (n + _ALIGN - 1) // _ALIGN * _ALIGN
+        self.numel = off
+        self.device = torch.device(device)
+        self.buffer = torch.zeros(off, dtype=torch.float32, device=self.device)
+        for sub, name, o, shape in self.layout:
+            src = named[sub][name].detach().to(device=self.device, dtype=torch.float32).reshape(-1)
+            self.buffer[o:o + src.numel()].copy_(src)
+
+    def views(self, buffer: torch.Tensor | None = None) -> dict:
+        buf = self.buffer if buffer is None else buffer
+        out: dict = {}
+        for sub, name, o, shape in self.layout:
+            n = 1
+            for s in shape:
+                n *= s
+            out.setdefault(sub, {})[name] = buf[o:o + n].view(shape)
+        return out
+
+    def zeros_like(self) -> torch.Tensor:
+        return torch.zeros_like(self.buffer)
+
+    def substruct(self, sub: str, buffer: torch.Tensor | None = None):
+        buf = self.buffer if buffer is None else buffer
+        s = A.SUBOP_STRUCT[sub]()
+        base = buf.data_ptr()
+        for sb, name, o, _ in self.layout:
+            if sb == sub:
+                setattr(s, name, base + 4 * o)
+        return s
+
+    def block_struct(self, buffer: torch.Tensor | None = None) -> A.BlockW:
+        w = A.BlockW()
+        for sub in BLOCK_SUBOPS:
+            setattr(w, sub, self.substruct(sub, buffer))
+        return w
+
+
+def weight_struct(sub: str, params: dict):
+    """C weight struct of one sub-op from individual FP32 device tensors."""
+    s = A.SUBOP_STRUCT[sub]()
+    for name, t in params.items():
+        if t.dtype != torch.float32:
+            raise ValueError(f"{sub}.{name}: parameters are FP32")
+        setattr(s, name, _ptr(t).value)
+    return s
+
+
+# ------------------------------------------------------------------ descriptors
+def block_desc(cfg, dtype: str | None = None, chunk: int | None = None) -> A.BlockDesc:
+    d = A.BlockDesc()
+    d.dtype = DTYPES[dtype or cfg.dtype][0]
+    d.extra_msa = 1 if cfg.extra_msa else 0
+    d.n_seq, d.n_res, d.c_m, d.c_z = cfg.n_seq, cfg.n_res, cfg.c_m, cfg.c_z
+    d.msa_heads, d.msa_head_dim = cfg.msa_heads, cfg.msa_head_dim
+    d.tri_heads, d.tri_head_dim = cfg.tri_heads, cfg.tri_head_dim
+    d.tri_mul_hidden, d.opm_hidden = cfg.tri_mul_hidden, cfg.opm_hidden
+    d.transition_factor = cfg.transition_factor
+    d.chunk = cfg.chunk if chunk is None else chunk
+    d.ln_eps, d.opm_eps, d.global_eps = cfg.ln_eps, cfg.opm_eps, cfg.global_eps
+    return d
+
+
+def attn_desc(kind: int, dtype: str, n_outer: int, n_inner: int, c_in: int, heads: int, head_dim: int,
+              c_pair: int = 0, ln_eps: float = 1e-5, global_eps: float = 1e-10, chunk: int = 0):
+    d = A.AttnDesc()
+    d.kind, d.dtype = kind, DTYPES[dtype][0]
+    d.n_outer, d.n_inner, d.c_in, d.c_pair = n_outer, n_inner, c_in, c_pair
+    d.heads, d.head_dim = heads, head_dim
+    d.ln_eps, d.global_eps, d.chunk = ln_eps, global_eps, chunk
+    return d
+
+
+def trans_desc(dtype: str, rows: int, c: int, factor: int = 4, ln_eps: float = 1e-5):
+    d = A.TransDesc()
+    d.dtype, d.rows, d.c, d.factor, d.ln_eps = DTYPES[dtype][0], rows, c, factor, ln_eps
+    return d
+
+
+def opm_desc(dtype: str, n_seq: int, n_res: int, c_m: int, c_hidden: int, c_z: int,
+             ln_eps: float = 1e-5, opm_eps: float = 1e-3):
+    d = A.OpmDesc()
+    d.dtype = DTYPES[dtype][0]
+    d.n_seq, d.n_res, d.c_m, d.c_hidden, d.c_z = n_seq, n_res, c_m, c_hidden, c_z
+    d.ln_eps, d.opm_eps = ln_eps, opm_eps
+    return d
+
+
+def trimul_desc(dtype: str, direction: int, n_res: int, c_z: int, c_hidden: int,
+                ln_eps: float = 1e-5, chunk: int = 0):
+    d = A.TrimulDesc()
+    d.dtype, d.dir = DTYPES[dtype][0], direction
+    d.n_res, d.c_z, d.c_hidden, d.ln_eps, d.chunk = n_res, c_z, c_hidden, ln_eps, chunk
+    return d
+
+
+# ------------------------------------------------------------------ block
+def evoformer_block_fwd(cfg, flat: FlatParams, m, z, msa_mask=None, pair_mask=None, m_out=None,
+                        z_out=None, dtype: str | None = None, chunk: int | None = None):
+    lib = _lib()
+    d = block_desc(cfg, dtype, chunk)
+    w = flat.block_struct()
+    m_out = torch.empty_like(m) if m_out is None else m_out
+    z_out = torch.empty_like(z) if z_out is None else z_out
+    nbytes = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_FWD)
+    if nbytes == 0:
+        A.check(A.EVO_ESHAPE, "evoformer_block_workspace_bytes")
+    ws = workspace(nbytes, m.device)
+    A.check(lib.evoformer_block_fwd(ctypes.byref(d), ctypes.byref(w), _ptr(m), _ptr(z), _ptr(msa_mask),
+                                    _ptr(pair_mask), _ptr(m_out), _ptr(z_out), _ptr(ws), ws.numel(),
+                                    _stream(m.device)), "evoformer_block_fwd")
+    return m_out, z_out
+
+
+def evoformer_block_bwd(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, dm_out, dz_out, dflat=None,
+                        dm=None, dz=None, dtype: str | None = None):
+    """Returns (dm, dz, dflat); dflat (same layout as flat.buffer) is accumulated into."""
+    lib = _lib()
+    d = block_desc(cfg, dtype, 0)
+    w = flat.block_struct()
+    dflat = flat.zeros_like() if dflat is None else dflat
+    dw = flat.block_struct(dflat)
+    dm = torch.empty_like(dm_out) if dm is None else dm
+    dz = torch.empty_like(dz_out) if dz is None else dz
+    nbytes = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
+    if nbytes == 0:
+        A.check(A.EVO_ESHAPE, "evoformer_block_workspace_bytes")
+    ws = workspace(nbytes, m.device)
+    A.check(lib.evoformer_block_bwd(ctypes.byref(d), ctypes.byref(w), _ptr(m), _ptr(z), _ptr(msa_mask),
+                                    _ptr(pair_mask), _ptr(dm_out), _ptr(dz_out), _ptr(dm), _ptr(dz),
+                                    ctypes.byref(dw), _ptr(ws), ws.numel(), _stream(m.device)),
+            "evoformer_block_bwd")
+    return dm, dz, dflat
+
+
+# ------------------------------------------------------------------ per-op entry points
+def evo_attn_fwd(desc, w_struct, x, pair=None, mask=None, out=None, keep_saved=True):
+    lib = _lib()
+    out = torch.empty_like(x) if out is None else out
+    saved = None
+    if keep_saved:
+        saved = torch.empty(max(lib.evo_attn_saved_bytes(ctypes.byref(desc)), 256), dtype=torch.uint8,
+                            device=x.device)
+    nbytes = lib.evo_attn_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_FWD)
+    ws = workspace(nbytes, x.device)
+    A.check(lib.evo_attn_fwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(x), _ptr(pair), _ptr(mask),
+                             _ptr(out), _ptr(saved), _ptr(ws), ws.numel(), _stream(x.device)), "evo_attn_fwd")
+    return out, saved
+
+
+def evo_attn_bwd(desc, w_struct, x, pair, mask, saved, d_out, dw_struct, d_x=None, d_pair=None):
+    lib = _lib()
+    d_x = torch.empty_like(d_out) if d_x is None else d_x
+    nbytes = lib.evo_attn_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD)
+    ws = workspace(nbytes, x.device)
+    A.check(lib.evo_attn_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(x), _ptr(pair), _ptr(mask),
+                             _ptr(saved), _ptr(d_out), _ptr(d_x), _ptr(d_pair), ctypes.byref(dw_struct),
+                             _ptr(ws), ws.numel(), _stream(x.device)), "evo_attn_bwd")
+    return d_x
+
+
+def evo_transition_fwd(desc, w_struct, x, out=None, keep_saved=True):
+    lib = _lib()
+    out = torch.empty_like(x) if out is None else out
+    saved = None
+    if keep_saved:
+        saved = torch.empty(max(lib.evo_transition_saved_bytes(ctypes.byref(desc)), 256),
+                            dtype=torch.uint8, device=x.device)
+    ws = workspace(lib.evo_transition_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_FWD), x.device)
+    A.check(lib.evo_transition_fwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(x), _ptr(out),
+                                   _ptr(saved), _ptr(ws), ws.numel(), _stream(x.device)),
+            "evo_transition_fwd")
+    return out, saved
+
+
+def evo_transition_bwd(desc, w_struct, x, saved, d_out, dw_struct, d_x=None):
+    lib = _lib()
+    d_x = torch.empty_like(d_out) if d_x is None else d_x
+    ws = workspace(lib.evo_transition_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD), x.device)
+    A.check(lib.evo_transition_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(x), _ptr(saved),
+                                   _ptr(d_out), _ptr(d_x), ctypes.byref(dw_struct), _ptr(ws), ws.numel(),
+                                   _stream(x.device)), "evo_transition_bwd")
+    return d_x
+
+
+def opm_fwd(desc, w_struct, m, msa_mask, z_in, z_out=None, keep_saved=True):
+    lib = _lib()
+    z_out = torch.empty_like(z_in) if z_out is None else z_out
+    saved = None
+    if keep_saved:
+        saved = torch.empty(max(lib.opm_saved_bytes(ctypes.byref(desc)), 256), dtype=torch.uint8,
+                            device=m.device)
+    ws = workspace(lib.opm_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_FWD), m.device)
+    A.check(lib.opm_fwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(m), _ptr(msa_mask), _ptr(z_in),
+                        _ptr(z_out), _ptr(saved), _ptr(ws), ws.numel(), _stream(m.device)), "opm_fwd")
+    return z_out, saved
+
+
+def opm_bwd(desc, w_struct, m, msa_mask, saved, dz_out, d_m, dw_struct):
+    """d_m is accumulated into."""
+    lib = _lib()
+    ws = workspace(lib.opm_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD), m.device)
+    A.check(lib.opm_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(m), _ptr(msa_mask), _ptr(saved),
+                        _ptr(dz_out), _ptr(d_m), ctypes.byref(dw_struct), _ptr(ws), ws.numel(),
+                        _stream(m.device)), "opm_bwd")
+    return d_m
+
+
+def tri_mul_fwd(desc, w_struct, z, pair_mask, z_out=None, keep_saved=True):
+    lib = _lib()
+    z_out = torch.empty_like(z) if z_out is None else z_out
+    saved = None
+    if keep_saved:
+        saved = torch.empty(max(lib.tri_mul_saved_bytes(ctypes.byref(desc)), 256), dtype=torch.uint8,
+                            device=z.device)
+    ws = workspace(lib.tri_mul_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_FWD), z.device)
+    A.check(lib.tri_mul_fwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(z), _ptr(pair_mask),
+                            _ptr(z_out), _ptr(saved), _ptr(ws), ws.numel(), _stream(z.device)), "tri_mul_fwd")
+    return z_out, saved
+
+
+def tri_mul_bwd(desc, w_struct, z, pair_mask, saved, dz_out, dw_struct, dz=None):
+    lib = _lib()
+    dz = torch.empty_like(dz_out) if dz is None else dz
+    ws = workspace(lib.tri_mul_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD), z.device)
+    A.check(lib.tri_mul_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(z), _ptr(pair_mask),
+                            _ptr(saved), _ptr(dz_out), _ptr(dz), ctypes.byref(dw_struct), _ptr(ws),
+                            ws.numel(), _stream(z.device)), "tri_mul_bwd")
+    return dz

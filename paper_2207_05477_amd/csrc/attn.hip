@@ -1,0 +1,518 @@
+// Attention core kernels for gfx950.
+//
+// Forward: a workgroup owns 64 queries of one (batch, head), 16 per wave64.
+// Key/value tiles of 64 keys are staged in LDS (keys row-major for the
+// logit product, values transposed for the context product).  Logits are
+// formed as S^T = K Q^T on MFMA so that every lane holds the 16 logits of a
+// single query; the online softmax (exp2 domain, FP32 statistics) needs only
+// a 4-lane reduction, and the context O^T = V^T P^T is accumulated with P
+// taken straight from registers.  Masked keys get the logit kMaskLogit
+// (replacement); keys past the end get -inf.
+//
+// Backward: probabilities are recomputed from the saved row max and
+// 1/row-sum.  One kernel produces dQ and, summed over a group of batches
+// in LDS, partial pair-bias gradients (deterministic, no atomics); a second
+// kernel produces dK and dV with the roles of queries and keys swapped.
+#include "attn.h"
+
+#include <type_traits>
+
+namespace evo {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr int KB = 64;   // keys (or queries, in the dK/dV kernel) per LDS tile
+
+template <typename T, int D>
+struct DF {
+  static constexpr bool BF = sizeof(T) == 2;
+  static constexpr int NKS = BF ? (D >= 32 ? D / 32 : 1) : D / 4;  // MFMA steps over d
+  static constexpr int NDT = (D + 15) / 16;                          // 16-row tiles over d
+  static constexpr int VEC = BF ? 8 : 4;                              // elements per 16 B
+  static constexpr int DP = D + VEC;                                  // LDS pitch, row-major tiles
+  static constexpr int TP = KB + VEC;                                 // LDS pitch, transposed tiles
+  static constexpr int DR = NDT * 16;                                 // rows of transposed tiles
+  using Frag = typename std::conditional<BF, bf16x8, float>::type;
+};
+
+// Operand fragment over d of one (position, head) row: lane group lg holds
+// d = 32*ks + 8*lg + 0..7 (BF16) or d = lg*D/4 + ks (FP32).
+template <typename T, int D>
+EVO_DEV void load_dfrag(const T* row, int lg, bool ok, typename DF<T, D>::Frag* f) {
+  if constexpr (DF<T, D>::BF) {
+#pragma unroll
+    for (int ks = 0; ks < DF<T, D>::NKS; ++ks) {
+      const int d0 = 32 * ks + 8 * lg;
+      if (ok && d0 < D) f[ks] = *(const bf16x8*)(row + d0);
+      else f[ks] = bf16x8{};
+    }
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < D / 4; ++ks) f[ks] = ok ? (float)row[lg * (D / 4) + ks] : 0.f;
+  }
+}
+
+template <typename T, int D>
+EVO_DEV f32x4 mfma_d(const typename DF<T, D>::Frag* a, const typename DF<T, D>::Frag* b) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < DF<T, D>::NKS; ++ks) {
+    if constexpr (DF<T, D>::BF) acc = mfma_bf16(a[ks], b[ks], acc);
+    else acc = mfma_f32(a[ks], b[ks], acc);
+  }
+  return acc;
+}
+
+// acc += A * B where A rows come from a transposed LDS tile (row `r`, 64
+// contiguous columns) and B is the 64 x 16 matrix whose 16x16 blocks t are
+// held in the MFMA output layout p[t] (lane holds rows 4*lg+i of column lr).
+template <typename T, int D>
+EVO_DEV f32x4 contract64(const T* trow, bool rok, const f32x4* p, int lg, f32x4 acc) {
+  if constexpr (DF<T, D>::BF) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      bf16x8 a = bf16x8{};
+      if (rok) {
+        const bf16x4 lo = *(const bf16x4*)(trow + 32 * u + 4 * lg);
+        const bf16x4 hi = *(const bf16x4*)(trow + 32 * u + 16 + 4 * lg);
+        a = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+      const f32x4 p0 = p[2 * u], p1 = p[2 * u + 1];
+      bf16x8 b = bf16x8{(bf16)p0[0], (bf16)p0[1], (bf16)p0[2], (bf16)p0[3],
+                        (bf16)p1[0], (bf16)p1[1], (bf16)p1[2], (bf16)p1[3]};
+      acc = mfma_bf16(a, b, acc);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f32x4 a = rok ? *(const f32x4*)(trow + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = mfma_f32(a[i], p[t][i], acc);
+    }
+  }
+  return acc;
+}
+
+// Stage a 64-row tile of (position, head) rows [p0, p0+64) of `src` into LDS:
+// row-major [64][DP] (if dst_rm) and/or transposed [DR][TP] (if dst_t).
+template <typename T, int D>
+EVO_DEV void stage_tile(const T* src, int64_t sp, int64_t p0, int64_t pend, T* dst_rm, T* dst_t,
+                        int tid) {
+  using F = DF<T, D>;
+  constexpr int VPR = D / F::VEC;  // vectors per row
+  for (int e = tid; e < KB * VPR; e += 256) {
+    const int r = e / VPR, dv = (e % VPR) * F::VEC;
+    const int64_t p = p0 + r;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    if (p < pend) val = *(const uint4*)(src + p * sp + dv);
+    if (dst_rm) *(uint4*)(dst_rm + r * F::DP + dv) = val;
+    if (dst_t) {
+      const T* ev = (const T*)&val;
+#pragma unroll
+      for (int i = 0; i < F::VEC; ++i) dst_t[(dv + i) * F::TP + r] = ev[i];
+    }
+  }
+}
+
+template <typename T, int D>
+EVO_DEV void zero_pad_rows(T* dst_t, int tid) {
+  using F = DF<T, D>;
+  if constexpr (F::DR > D) {
+    for (int e = tid; e < (F::DR - D) * F::TP; e += 256) dst_t[D * F::TP + e] = from_f32<T>(0.f);
+  }
+}
+
+// Store 4 consecutive d values (d = d0..d0+3) of one (position, head) row.
+template <typename T>
+EVO_DEV void store4(T* dst, f32x4 v) {
+  if constexpr (sizeof(T) == 2) {
+    *(bf16x4*)dst = bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+  } else {
+    *(f32x4*)dst = v;
+  }
+}
+
+// ============================================================== forward
+template <typename T, int D>
+__global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_log2) {
+  using F = DF<T, D>;
+  __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
+  __shared__ __attribute__((aligned(16))) T sVt[F::DR * F::TP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t b = blockIdx.z;
+  const int h = blockIdx.y;
+  const int64_t qend0 = a.q_count < 0 ? a.Lq : a.q_begin + a.q_count;
+  const int64_t qend = qend0 < a.Lq ? qend0 : a.Lq;
+  const int64_t qi = a.q_begin + (int64_t)blockIdx.x * 64 + wave * 16 + lr;
+  const bool qok = qi < qend;
+
+  const T* Q = (const T*)a.q + b * a.sb + h * D;
+  const T* K = (const T*)a.k + b * a.sb + h * D;
+  const T* V = (const T*)a.v + b * a.sb + h * D;
+
+  typename F::Frag qf[F::NKS];
+  load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
+
+  zero_pad_rows<T, D>(sVt, tid);
+  float m_run = -INFINITY, l_run = 0.f;
+  f32x4 oacc[F::NDT];
+#pragma unroll
+  for (int dt = 0; dt < F::NDT; ++dt) oacc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const float* bias = a.bias ? a.bias + h * a.bh + (qok ? qi : 0) * a.bq : nullptr;
+  const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
+
+  for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
+    __syncthreads();
+    stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, nullptr, tid);
+    stage_tile<T, D>(V, a.sp, kb0, a.Lk, nullptr, sVt, tid);
+    __syncthreads();
+    f32x4 s[4];
+    float mloc = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      typename F::Frag kf[F::NKS];
+      load_dfrag<T, D>(sK + (16 * t + lr) * F::DP, lg, true, kf);
+      s[t] = mfma_d<T, D>(kf, qf);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t key = kb0 + 16 * t + 4 * lg + i;
+        float x = s[t][i] * scale_log2;
+        if (key >= a.Lk) {
+          x = -INFINITY;
+        } else {
+          if (bias && qok) x += bias[key * a.bk] * kLog2e;
+          if (mask && mask[key * a.mk] == 0.f) x = kMaskLogit;
+        }
+        s[t][i] = x;
+        mloc = fmaxf(mloc, x);
+      }
+    }
+    mloc = fmaxf(mloc, __shfl_xor(mloc, 16, 64));
+    mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
+    const float m_new = fmaxf(m_run, mloc);
+    const float alpha = exp2f(m_run - m_new);
+    float lsum = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float p = exp2f(s[t][i] - m_new);
+        s[t][i] = p;
+        lsum += p;
+      }
+    lsum += __shfl_xor(lsum, 16, 64);
+    lsum += __shfl_xor(lsum, 32, 64);
+    l_run = l_run * alpha + lsum;
+    m_run = m_new;
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) {
+      oacc[dt] = oacc[dt] * alpha;
+      const int dr = 16 * dt + lr;
+      oacc[dt] = contract64<T, D>(sVt + dr * F::TP, true, s, lg, oacc[dt]);
+    }
+  }
+
+  if (!qok) return;
+  const float inv = 1.0f / l_run;
+  T* O = (T*)a.o + b * a.osb + qi * a.osp + h * D;
+  T* GO = a.go ? (T*)a.go + b * a.osb + qi * a.osp + h * D : nullptr;
+  const T* G = a.g ? (const T*)a.g + b * a.sb + qi * a.sp + h * D : nullptr;
+#pragma unroll
+  for (int dt = 0; dt < F::NDT; ++dt) {
+    const int d0 = 16 * dt + 4 * lg;
+    if (d0 < D) {
+      f32x4 o = oacc[dt] * inv;
+      store4<T>(O + d0, o);
+      if (GO) {
+        f32x4 gv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gv[i] = to_f32(G[d0 + i]) * o[i];
+        store4<T>(GO + d0, gv);
+      }
+    }
+  }
+  if (lg == 0 && a.st_max) {
+    const int64_t si = (b * a.stb + qi * a.stq) * a.H + h;
+    a.st_max[si] = m_run;
+    a.st_inv[si] = inv;
+  }
+}
+
+// ============================================================== backward: dQ and bias partials
+template <typename T, int D>
+__global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad gr, float scale_log2,
+                                                          float scale) {
+  using F = DF<T, D>;
+  __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
+  __shared__ __attribute__((aligned(16))) T sV[KB * F::DP];
+  __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
+  extern __shared__ float sacc[];  // [64][Lk + 1] bias-gradient accumulator
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int h = blockIdx.y;
+  const int64_t grp = blockIdx.z;
+  const int64_t b0 = grp * gr.group;
+  const int64_t b1 = b0 + gr.group < a.nbatch ? b0 + gr.group : a.nbatch;
+  const int64_t qloc = wave * 16 + lr;
+  const int64_t qi = (int64_t)blockIdx.x * 64 + qloc;
+  const bool qok = qi < a.Lq;
+  const int64_t acc_ld = a.Lk + 1;
+  const bool dbias = gr.dbias_part != nullptr;
+
+  zero_pad_rows<T, D>(sKt, tid);
+  if (dbias)
+    for (int64_t e = tid; e < 64 * acc_ld; e += 256) sacc[e] = 0.f;
+
+  for (int64_t b = b0; b < b1; ++b) {
+    const T* Q = (const T*)a.q + b * a.sb + h * D;
+    const T* K = (const T*)a.k + b * a.sb + h * D;
+    const T* V = (const T*)a.v + b * a.sb + h * D;
+    const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
+    typename F::Frag qf[F::NKS], of[F::NKS];
+    load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
+    load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
+    float mrow = 0.f, irow = 0.f, drow = 0.f;
+    if (qok) {
+      const int64_t si = (b * a.stb + qi * a.stq) * a.H + h;
+      mrow = a.st_max[si];
+      irow = a.st_inv[si];
+      drow = gr.Dsum[si];
+    }
+    const float* bias = a.bias ? a.bias + h * a.bh + (qok ? qi : 0) * a.bq : nullptr;
+    const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
+    f32x4 dq[F::NDT];
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) dq[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
+      __syncthreads();
+      stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, sKt, tid);
+      stage_tile<T, D>(V, a.sp, kb0, a.Lk, sV, nullptr, tid);
+      __syncthreads();
+      f32x4 ds[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        typename F::Frag kf[F::NKS], vf[F::NKS];
+        load_dfrag<T, D>(sK + (16 * t + lr) * F::DP, lg, true, kf);
+        load_dfrag<T, D>(sV + (16 * t + lr) * F::DP, lg, true, vf);
+        const f32x4 s = mfma_d<T, D>(kf, qf);
+        const f32x4 dp = mfma_d<T, D>(vf, of);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t key = kb0 + 16 * t + 4 * lg + i;
+          float r = 0.f;
+          if (qok && key < a.Lk) {
+            float x = s[i] * scale_log2;
+            if (bias) x += bias[key * a.bk] * kLog2e;
+            const bool masked = mask && mask[key * a.mk] == 0.f;
+            if (!masked) {
+              const float p = exp2f(x - mrow) * irow;
+              r = p * (dp[i] - drow);
+            }
+            if (dbias) sacc[qloc * acc_ld + key] += r;
+          }
+          ds[t][i] = r;
+        }
+      }
+#pragma unroll
+      for (int dt = 0; dt < F::NDT; ++dt) {
+        const int dr = 16 * dt + lr;
+        dq[dt] = contract64<T, D>(sKt + dr * F::TP, true, ds, lg, dq[dt]);
+      }
+    }
+    if (qok) {
+      T* DQ = (T*)gr.dq + b * gr.dsb + qi * gr.dsp + h * D;
+#pragma unroll
+      for (int dt = 0; dt < F::NDT; ++dt) {
+        const int d0 = 16 * dt + 4 * lg;
+        if (d0 < D) store4<T>(DQ + d0, dq[dt] * scale);
+      }
+    }
+  }
+  if (dbias) {
+    __syncthreads();
+    // partial slice laid out like the bias itself: [group][H][.. q*bq + key*bk ..]
+    float* out = gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk;
+    const int64_t q0 = (int64_t)blockIdx.x * 64;
+    for (int64_t e = tid; e < 64 * a.Lk; e += 256) {
+      const int64_t ql = e / a.Lk, key = e % a.Lk;
+      if (q0 + ql < a.Lq) out[(q0 + ql) * a.bq + key * a.bk] = sacc[ql * acc_ld + key];
+    }
+  }
+}
+
+// ============================================================== backward: dK, dV
+template <typename T, int D>
+__global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
+                                                            float scale) {
+  using F = DF<T, D>;
+  __shared__ __attribute__((aligned(16))) T sQ[KB * F::DP];
+  __shared__ __attribute__((aligned(16))) T sO[KB * F::DP];
+  __shared__ __attribute__((aligned(16))) T sQt[F::DR * F::TP];
+  __shared__ __attribute__((aligned(16))) T sOt[F::DR * F::TP];
+  __shared__ float sM[KB], sI[KB], sD[KB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t b = blockIdx.z;
+  const int h = blockIdx.y;
+  const int64_t key = (int64_t)blockIdx.x * 64 + wave * 16 + lr;
+  const bool kok = key < a.Lk;
+  const bool kmasked = kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
+
+  const T* Q = (const T*)a.q + b * a.sb + h * D;
+  const T* K = (const T*)a.k + b * a.sb + h * D;
+  const T* V = (const T*)a.v + b * a.sb + h * D;
+  const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
+  typename F::Frag kf[F::NKS], vf[F::NKS];
+  load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
+  load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
+  const float* bias = a.bias ? a.bias + h * a.bh + (kok ? key : 0) * a.bk : nullptr;
+
+  zero_pad_rows<T, D>(sQt, tid);
+  zero_pad_rows<T, D>(sOt, tid);
+  f32x4 dk[F::NDT], dv[F::NDT];
+#pragma unroll
+  for (int dt = 0; dt < F::NDT; ++dt) { dk[dt] = f32x4{0.f, 0.f, 0.f, 0.f}; dv[dt] = dk[dt]; }
+
+  for (int64_t qb0 = 0; qb0 < a.Lq; qb0 += KB) {
+    __syncthreads();
+    stage_tile<T, D>(Q, a.sp, qb0, a.Lq, sQ, sQt, tid);
+    stage_tile<T, D>(DO, a.osp, qb0, a.Lq, sO, sOt, tid);
+    if (tid < KB) {
+      const int64_t q = qb0 + tid;
+      float mv = 0.f, iv = 0.f, dvv = 0.f;
+      if (q < a.Lq) {
+        const int64_t si = (b * a.stb + q * a.stq) * a.H + h;
+        mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
+      }
+      sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv;
+    }
+    __syncthreads();
+    f32x4 P[4], DS[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      typename F::Frag qf[F::NKS], of[F::NKS];
+      load_dfrag<T, D>(sQ + (16 * t + lr) * F::DP, lg, true, qf);
+      load_dfrag<T, D>(sO + (16 * t + lr) * F::DP, lg, true, of);
+      const f32x4 s = mfma_d<T, D>(qf, kf);
+      const f32x4 dp = mfma_d<T, D>(of, vf);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ql = 16 * t + 4 * lg + i;
+        const int64_t q = qb0 + ql;
+        float p = 0.f, r = 0.f;
+        if (kok && q < a.Lq) {
+          float x = s[i] * scale_log2;
+          if (bias) x += bias[q * a.bq] * kLog2e;
+          if (kmasked) x = kMaskLogit;
+          p = exp2f(x - sM[ql]) * sI[ql];
+          if (!kmasked) r = p * (dp[i] - sD[ql]);
+        }
+        P[t][i] = p;
+        DS[t][i] = r;
+      }
+    }
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) {
+      const int dr = 16 * dt + lr;
+      dv[dt] = contract64<T, D>(sOt + dr * F::TP, true, P, lg, dv[dt]);
+      dk[dt] = contract64<T, D>(sQt + dr * F::TP, true, DS, lg, dk[dt]);
+    }
+  }
+  if (!kok) return;
+  T* DK = (T*)gr.dk + b * gr.dsb + key * gr.dsp + h * D;
+  T* DV = (T*)gr.dv + b * gr.dsb + key * gr.dsp + h * D;
+#pragma unroll
+  for (int dt = 0; dt < F::NDT; ++dt) {
+    const int d0 = 16 * dt + 4 * lg;
+    if (d0 < D) {
+      store4<T>(DK + d0, dk[dt] * scale);
+      store4<T>(DV + d0, dv[dt]);
+    }
+  }
+}
+
+// ============================================================== launchers
+static bool attn_shape_ok(const AttnCore& a) {
+  if (!(a.D == 8 || a.D == 16 || a.D == 32 || a.D == 64)) {
+    set_error("attention: head_dim %d not in {8,16,32,64}", a.D);
+    return false;
+  }
+  if (a.Lq <= 0 || a.Lk <= 0 || a.nbatch <= 0 || a.H <= 0) {
+    set_error("attention: empty problem");
+    return false;
+  }
+  return true;
+}
+
+template <typename T, int D>
+static void launch_fwd(const Ctx& c, const AttnCore& a) {
+  const int64_t nq = a.q_count < 0 ? a.Lq : a.q_count;
+  dim3 grid((unsigned)((nq + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
+  const float sl2 = kLog2e / sqrtf((float)D);
+  hipLaunchKernelGGL((attn_fwd_kernel<T, D>), grid, dim3(256), 0, c.stream, a, sl2);
+}
+
+template <typename T>
+evo_status_t attn_fwd(const Ctx& c, const AttnCore& a) {
+  if (c.dry) return EVO_OK;
+  if (!attn_shape_ok(a)) return EVO_ESHAPE;
+  switch (a.D) {
+    case 8: launch_fwd<T, 8>(c, a); break;
+    case 16: launch_fwd<T, 16>(c, a); break;
+    case 32: launch_fwd<T, 32>(c, a); break;
+    default: launch_fwd<T, 64>(c, a); break;
+  }
+  return check_launch("attn_fwd");
+}
+
+int64_t attn_bwd_groups(const AttnCore& a) {
+  const int64_t qblocks = (a.Lq + 63) / 64;
+  int64_t target = (1024 + qblocks * a.H - 1) / (qblocks * a.H);
+  if (target < 1) target = 1;
+  if (target > a.nbatch) target = a.nbatch;
+  const int64_t group = (a.nbatch + target - 1) / target;
+  return (a.nbatch + group - 1) / group;
+}
+
+template <typename T, int D>
+static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
+  const float sl2 = kLog2e / sqrtf((float)D);
+  const float sc = 1.0f / sqrtf((float)D);
+  const int64_t ngroups = attn_bwd_groups(a);
+  g.group = (a.nbatch + ngroups - 1) / ngroups;
+  size_t lds = 0;
+  if (g.dbias_part) {
+    lds = (size_t)64 * (a.Lk + 1) * sizeof(float);
+    if (lds > 120 * 1024) {
+      set_error("attention backward: %lld keys exceed the bias-gradient LDS tile", (long long)a.Lk);
+      return EVO_ESHAPE;
+    }
+  }
+  dim3 g1((unsigned)((a.Lq + 63) / 64), (unsigned)a.H, (unsigned)ngroups);
+  hipLaunchKernelGGL((attn_bwd_dq_kernel<T, D>), g1, dim3(256), lds, c.stream, a, g, sl2, sc);
+  EVO_TRY(check_launch("attn_bwd_dq"));
+  dim3 g2((unsigned)((a.Lk + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
+  hipLaunchKernelGGL((attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc);
+  return check_launch("attn_bwd_dkdv");
+}
+
+template <typename T>
+evo_status_t attn_bwd(const Ctx& c, const AttnCore& a, const AttnGrad& g) {
+  if (c.dry) return EVO_OK;
+  if (!attn_shape_ok(a)) return EVO_ESHAPE;
+  switch (a.D) {
+    case 8: return launch_bwd<T, 8>(c, a, g);
+    case 16: return launch_bwd<T, 16>(c, a, g);
+    case 32: return launch_bwd<T, 32>(c, a, g);
+    default: return launch_bwd<T, 64>(c, a, g);
+  }
+}
+
+template evo_status_t attn_fwd<float>(const Ctx&, const AttnCore&);
+template evo_status_t attn_fwd<bf16>(const Ctx&, const AttnCore&);
+template evo_status_t attn_bwd<float>(const Ctx&, const AttnCore&, const AttnGrad&);
+template evo_status_t attn_bwd<bf16>(const Ctx&, const AttnCore&, const AttnGrad&);
+
+}  // namespace evo

@@ -1,0 +1,97 @@
+// Shared device/host helpers for the gfx950 Evoformer kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+
+#include "evo.h"
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+
+#define EVO_DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------- conversions
+EVO_DEV float to_f32(float x) { return x; }
+EVO_DEV float to_f32(bf16 x) { return (float)x; }
+template <typename T> EVO_DEV T from_f32(float x);
+template <> EVO_DEV float from_f32<float>(float x) { return x; }
+template <> EVO_DEV bf16 from_f32<bf16>(float x) { return (bf16)x; }  // round to nearest even
+
+EVO_DEV float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// ---------------------------------------------------------------- wave reductions (wave64)
+EVO_DEV float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+EVO_DEV float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------- MFMA wrappers
+// 16x16 output tiles for both precisions.  Lane l of a wave holds output rows
+// 4*(l/16)+i (i = 0..3) of column l%16.  An operand fragment of lane l holds
+// row (A) / column (B) l%16 at a lane-group-dependent set of k indices; the two
+// operands of one product must use the same k set, any bijection works.
+EVO_DEV f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+EVO_DEV f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- host side
+namespace evo {
+
+void set_error(const char* fmt, ...);
+
+#define EVO_CHECK_ARG(cond, code, ...)      \
+  do {                                      \
+    if (!(cond)) {                          \
+      ::evo::set_error(__VA_ARGS__);        \
+      return (code);                        \
+    }                                       \
+  } while (0)
+
+#define EVO_TRY(expr)                       \
+  do {                                      \
+    evo_status_t _s = (expr);               \
+    if (_s != EVO_OK) return _s;            \
+  } while (0)
+
+evo_status_t check_launch(const char* what);
+
+// Bump allocator over a caller-owned workspace.  In dry mode it only counts
+// bytes, so one code path both sizes and carves the workspace.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  bool dry = false;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = dry ? nullptr : (void*)(base + off);
+    off += bytes;
+    return p;
+  }
+  template <typename T> T* take_n(size_t n) { return (T*)take(n * sizeof(T)); }
+  bool overflow() const { return !dry && off > cap; }
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  bool dry = false;      // size only: allocate from the arenas, launch nothing
+};
+
+inline size_t dtype_bytes(int dt) { return dt == EVO_BF16 ? 2 : 4; }
+
+}  // namespace evo

@@ -1,0 +1,179 @@
+// Helpers shared by the ops: weight-gradient GEMMs (deterministic split-K),
+// the small-N pair-bias projection and its backward, segmented column sums.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "ops.h"
+
+namespace evo {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+const char* last_error() { return g_err; }
+
+evo_status_t check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return EVO_EHIP;
+  }
+  return EVO_OK;
+}
+
+// ============================================================== weight gradients
+template <typename T>
+evo_status_t wgrad(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
+                   int64_t rows, int64_t M, int64_t N, float* dW) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int64_t split = (512 + tiles - 1) / tiles;
+  int64_t maxsplit = rows / 256 > 0 ? rows / 256 : 1;
+  if (split > maxsplit) split = maxsplit;
+  if (split < 1) split = 1;
+  float* part = ws.take_n<float>((size_t)split * M * N);
+  if (c.dry) return EVO_OK;
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = rows;
+  g.split_k = (int)split;
+  g.A = op_colmajor(X, ldx);
+  g.B = op_colmajor(dY, ldy);
+  g.epi = epi_rowmajor(part, N, true);
+  g.epi.batch = M * N;
+  if (split == 1) {   // single slice: accumulate straight into dW
+    g.epi.out = dW;
+    g.epi.accumulate = 1;
+    return gemm<T>(c, g);
+  }
+  EVO_TRY(gemm<T>(c, g));
+  return reduce_partials(c, part, split, M * N, M * N, dW, true);
+}
+
+// ============================================================== pair-bias projection
+template <typename T>
+__global__ __launch_bounds__(256) void rowproj_kernel(const T* __restrict__ x, int64_t rows, int C,
+                                                      const float* __restrict__ W, int H,
+                                                      float* __restrict__ out) {
+  extern __shared__ float sW[];  // [C][H]
+  for (int e = threadIdx.x; e < C * H; e += 256) sW[e] = W[e];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= rows) return;
+  float acc[16];
+#pragma unroll
+  for (int h = 0; h < 16; ++h) acc[h] = 0.f;
+  const T* xr = x + row * C;
+  for (int cc = 0; cc < C; ++cc) {
+    const float v = to_f32(xr[cc]);
+#pragma unroll
+    for (int h = 0; h < 16; ++h)
+      if (h < H) acc[h] += v * sW[cc * H + h];
+  }
+#pragma unroll
+  for (int h = 0; h < 16; ++h)
+    if (h < H) out[(int64_t)h * rows + row] = acc[h];
+}
+
+template <typename T>
+evo_status_t rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* W, int H, float* out) {
+  if (c.dry || rows == 0) return EVO_OK;
+  if (H > 16) { set_error("pair bias: %d heads > 16", H); return EVO_ESHAPE; }
+  hipLaunchKernelGGL((rowproj_kernel<T>), dim3((unsigned)((rows + 255) / 256)), dim3(256),
+                     (size_t)C * H * sizeof(float), c.stream, x, rows, C, W, H, out);
+  return check_launch("rowproj");
+}
+
+// dx[row][c] (+)= sum_h dout[h][row] W[c][h]
+__global__ __launch_bounds__(256) void rowproj_dx_kernel(int64_t rows, int C, const float* __restrict__ W,
+                                                         int H, const float* __restrict__ dout,
+                                                         float* dx, int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * C) return;
+  const int64_t row = e / C;
+  const int cc = (int)(e % C);
+  float s = 0.f;
+  for (int h = 0; h < H; ++h) s += dout[(int64_t)h * rows + row] * W[cc * H + h];
+  dx[e] = accumulate ? dx[e] + s : s;
+}
+
+// partial dW over 256-row blocks: part[blk][C*H]
+template <typename T>
+__global__ __launch_bounds__(256) void rowproj_dw_kernel(const T* __restrict__ x, int64_t rows, int C,
+                                                         int H, const float* __restrict__ dout,
+                                                         float* __restrict__ part) {
+  __shared__ float red[256 * 16];
+  const int per = 256 / C;            // row subsets (C divides 256)
+  const int cc = threadIdx.x % C, rs = threadIdx.x / C;
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  float acc[16];
+#pragma unroll
+  for (int h = 0; h < 16; ++h) acc[h] = 0.f;
+  for (int64_t r = r0 + rs; r < r0 + 256 && r < rows; r += per) {
+    const float v = to_f32(x[r * C + cc]);
+#pragma unroll
+    for (int h = 0; h < 16; ++h)
+      if (h < H) acc[h] += v * dout[(int64_t)h * rows + r];
+  }
+#pragma unroll
+  for (int h = 0; h < 16; ++h) red[threadIdx.x * 16 + h] = acc[h];
+  __syncthreads();
+  for (int e = threadIdx.x; e < C * H; e += 256) {
+    const int c2 = e / H, h = e % H;
+    float s = 0.f;
+    for (int q = 0; q < per; ++q) s += red[(q * C + c2) * 16 + h];
+    part[(int64_t)blockIdx.x * C * H + e] = s;
+  }
+}
+
+template <typename T>
+evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int C, const float* W,
+                         int H, const float* dout, float* dx, bool accumulate, float* dW) {
+  const int64_t nblk = (rows + 255) / 256;
+  float* part = ws.take_n<float>((size_t)nblk * C * H);
+  if (c.dry || rows == 0) return EVO_OK;
+  if (H > 16 || C > 256 || 256 % C) { set_error("pair bias bwd: unsupported C=%d H=%d", C, H); return EVO_ESHAPE; }
+  if (dx) {
+    const int64_t n = rows * C;
+    hipLaunchKernelGGL(rowproj_dx_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+                       rows, C, W, H, dout, dx, accumulate ? 1 : 0);
+    EVO_TRY(check_launch("rowproj_dx"));
+  }
+  hipLaunchKernelGGL((rowproj_dw_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, x, rows, C, H,
+                     dout, part);
+  EVO_TRY(check_launch("rowproj_dw"));
+  return reduce_partials(c, part, nblk, (int64_t)C * H, (int64_t)C * H, dW, true);
+}
+
+// ============================================================== segmented column sums
+template <typename T>
+evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, int64_t ld, int nseg,
+                             const int* seg_off, const int* seg_n, float* const* outs) {
+  const int64_t nblk = colsum_partials(rows);
+  float* part = ws.take_n<float>((size_t)nblk * ld);
+  if (c.dry || rows == 0) return EVO_OK;
+  int nb = 0;
+  EVO_TRY(colsum_partial<T>(c, x, rows, (int)ld, ld, part, &nb));
+  for (int s = 0; s < nseg; ++s) {
+    if (!outs[s]) continue;
+    EVO_TRY(reduce_partials(c, part + seg_off[s], nb, seg_n[s], ld, outs[s], true));
+  }
+  return EVO_OK;
+}
+
+#define EVO_INST_H(T)                                                                              \
+  template evo_status_t wgrad<T>(const Ctx&, Arena&, const T*, int64_t, const T*, int64_t, int64_t, \
+                                 int64_t, int64_t, float*);                                        \
+  template evo_status_t rowproj<T>(const Ctx&, const T*, int64_t, int, const float*, int, float*); \
+  template evo_status_t rowproj_bwd<T>(const Ctx&, Arena&, const T*, int64_t, int, const float*,   \
+                                       int, const float*, float*, bool, float*);                   \
+  template evo_status_t colsum_segments<T>(const Ctx&, Arena&, const T*, int64_t, int64_t, int,     \
+                                           const int*, const int*, float* const*);
+
+EVO_INST_H(float)
+EVO_INST_H(bf16)
+
+}  // namespace evo

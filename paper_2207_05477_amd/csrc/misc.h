@@ -1,0 +1,87 @@
+// LayerNorm, reductions, parameter packing and the elementwise glue kernels.
+#pragma once
+#include "common.h"
+
+namespace evo {
+
+// y = LayerNorm(x) over the last axis (rows x C, row pitch C), FP32 statistics.
+template <typename T>
+evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+                    float eps, T* y, float* mean, float* rstd);
+// Channel-major input x[C][P] -> y[P][C].
+template <typename T>
+evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
+                       float eps, T* y, float* mean, float* rstd);
+// dx = base + LayerNorm_backward(dy): base = resid (may alias dx) when given, else dx itself
+// when accumulate, else 0.  dgamma/dbeta partial sums go to part[nblk][2*C].
+template <typename T>
+evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
+                    const float* dy, int64_t rows, int C, const T* resid, bool accumulate, T* dx,
+                    float* part, int* nblk);
+int64_t ln_bwd_partials(int64_t rows);
+// Channel-major x[C][P], dy[P][C] -> dx[C][P].
+template <typename T>
+evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
+                       const float* dy, int64_t P, int C, T* dx, float* part, int* nblk);
+int64_t ln_bwd_cm_partials(int64_t P);
+
+// out[j] (+)= sum_i part[i * ld + j], i < n, j < C (fixed order).
+evo_status_t reduce_partials(const Ctx& c, const float* part, int64_t n, int64_t C, int64_t ld,
+                             float* out, bool accumulate);
+// Two outputs from one [n][2C] partial buffer (LayerNorm gamma / beta).
+evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C, float* out_a,
+                              float* out_b);
+// part[blk][C] = column sums of x[rows][C] (row pitch ld) over the rows of block blk.
+template <typename T>
+evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
+                            int* nblk);
+int64_t colsum_partials(int64_t rows);
+// out += column sums (convenience: partial + reduce, scratch from `part`).
+template <typename T>
+evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
+                        float* out);
+
+// Parameter packing: up to 8 FP32 segments W_i[K][n_i] concatenated along n.
+struct PackSeg { const float* w; const float* bias; int32_t n; };
+struct PackArgs {
+  PackSeg seg[8];
+  int32_t nseg = 0;
+  int32_t K = 0;
+  void* dst_t = nullptr;   // [sum n][K], kernel type   (forward B operand)
+  void* dst = nullptr;     // [K][sum n], kernel type   (backward B operand)
+  float* bias = nullptr;   // [sum n] FP32 (missing segment biases are 0)
+};
+template <typename T>
+evo_status_t pack_params(const Ctx& c, const PackArgs& a);
+
+template <typename T>
+evo_status_t fill_zero(const Ctx& c, T* p, int64_t n);
+template <typename T>
+evo_status_t copy_elems(const Ctx& c, const T* src, T* dst, int64_t n);
+
+// Attention gate backward. Per row r and head h (c = head_dim):
+//   dctx = dgo * g; dgpre = dgo * o * g (1 - g); D[r*H+h] = sum_d dctx * o
+// go/o/g/dgo have row pitches; dctx written with pitch ld_dctx, dgpre with ld_dg.
+template <typename T>
+evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, int64_t ld_dgo,
+                      const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
+                      T* dgpre, int64_t ld_dg, float* D);
+
+// Triangle multiplication projections, forward: raw[p][4*ch + cz] (ap | ag | bp | bg | g)
+// -> a[c][p], b[c][p] (channel-major, masked, gated), g[p][cz] = sigmoid(raw g).
+template <typename T>
+evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
+                         T* a, T* b, T* g);
+// Backward: da, db channel-major -> draw[p][4*ch] columns of ap, ag, bp, bg.
+template <typename T>
+evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
+                             const float* mask, const T* da, const T* db, T* draw);
+// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g).
+template <typename T>
+evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* dz, const T* t,
+                             const T* g, T* dt, T* draw);
+
+// scale[i*R + j] = 1 / (eps + sum_s mask[s,i] mask[s,j])  (mask NULL: all ones).
+evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, float eps, float* scale);
+
+}  // namespace evo

@@ -1,0 +1,581 @@
+// LayerNorm (wave-per-row, FP32 statistics), deterministic column reductions,
+// parameter packing and the elementwise kernels of the gated ops.
+#include "misc.h"
+
+namespace evo {
+
+// ============================================================== LayerNorm forward
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void ln_fwd_kernel(const T* __restrict__ x, int64_t rows, int C,
+                                                     const float* __restrict__ g,
+                                                     const float* __restrict__ b, float eps,
+                                                     T* __restrict__ y, float* __restrict__ mean,
+                                                     float* __restrict__ rstd) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const T* xr = x + row * C;
+  float v[NV];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int c = lane + 64 * i;
+    v[i] = c < C ? to_f32(xr[c]) : 0.f;
+    s += v[i];
+  }
+  const float mu = wave_sum(s) / (float)C;
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int c = lane + 64 * i;
+    const float d = c < C ? v[i] - mu : 0.f;
+    q += d * d;
+  }
+  const float rs = 1.0f / sqrtf(wave_sum(q) / (float)C + eps);
+  T* yr = y + row * C;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int c = lane + 64 * i;
+    if (c < C) yr[c] = from_f32<T>((v[i] - mu) * rs * g[c] + b[c]);
+  }
+  if (lane == 0) {
+    if (mean) mean[row] = mu;
+    if (rstd) rstd[row] = rs;
+  }
+}
+
+template <typename T>
+evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+                    float eps, T* y, float* mean, float* rstd) {
+  if (c.dry || rows == 0) return EVO_OK;
+  dim3 grid((unsigned)((rows + 3) / 4));
+  if (C <= 64) hipLaunchKernelGGL((ln_fwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else if (C <= 128) hipLaunchKernelGGL((ln_fwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else if (C <= 256) hipLaunchKernelGGL((ln_fwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else if (C <= 1024) hipLaunchKernelGGL((ln_fwd_kernel<T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else { set_error("layernorm: C=%d > 1024", C); return EVO_ESHAPE; }
+  return check_launch("ln_fwd");
+}
+
+// Channel-major forward: a block owns 64 positions; x tile [C][64] staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const T* __restrict__ x, int64_t P, int C,
+                                                        const float* __restrict__ g,
+                                                        const float* __restrict__ b, float eps,
+                                                        T* __restrict__ y, float* __restrict__ mean,
+                                                        float* __restrict__ rstd) {
+  extern __shared__ float tile[];  // [C][65]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  for (int e = tid; e < C * 64; e += 256) {
+    const int cc = e >> 6, pp = e & 63;
+    const int64_t p = p0 + pp;
+    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
+  }
+  __syncthreads();
+  for (int pp = wave * 16; pp < wave * 16 + 16; ++pp) {
+    const int64_t p = p0 + pp;
+    if (p >= P) break;
+    float s = 0.f;
+    for (int cc = lane; cc < C; cc += 64) s += tile[cc * 65 + pp];
+    const float mu = wave_sum(s) / (float)C;
+    float q = 0.f;
+    for (int cc = lane; cc < C; cc += 64) {
+      const float d = tile[cc * 65 + pp] - mu;
+      q += d * d;
+    }
+    const float rs = 1.0f / sqrtf(wave_sum(q) / (float)C + eps);
+    for (int cc = lane; cc < C; cc += 64)
+      y[p * C + cc] = from_f32<T>((tile[cc * 65 + pp] - mu) * rs * g[cc] + b[cc]);
+    if (lane == 0) { mean[p] = mu; rstd[p] = rs; }
+  }
+}
+
+template <typename T>
+evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
+                       float eps, T* y, float* mean, float* rstd) {
+  if (c.dry || P == 0) return EVO_OK;
+  if (C > 512) { set_error("layernorm(cm): C=%d > 512", C); return EVO_ESHAPE; }
+  size_t lds = (size_t)C * 65 * sizeof(float);
+  hipLaunchKernelGGL((ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
+                     x, P, C, g, b, eps, y, mean, rstd);
+  return check_launch("ln_fwd_cm");
+}
+
+// ============================================================== LayerNorm backward
+// A block owns 64 rows (16 per wave); per-lane gamma/beta partials are reduced
+// across the 4 waves through LDS and written to part[blk][2C].
+constexpr int LNB_ROWS = 64;
+
+int64_t ln_bwd_partials(int64_t rows) { return (rows + LNB_ROWS - 1) / LNB_ROWS; }
+
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void ln_bwd_kernel(const T* __restrict__ x,
+                                                     const float* __restrict__ mean,
+                                                     const float* __restrict__ rstd,
+                                                     const float* __restrict__ g,
+                                                     const float* __restrict__ dy, int64_t rows,
+                                                     int C, const T* resid, int accumulate, T* dx,
+                                                     float* __restrict__ part) {
+  __shared__ float red[4][2][NV * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float dg[NV], db[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) { dg[i] = 0.f; db[i] = 0.f; }
+  const int64_t r0 = (int64_t)blockIdx.x * LNB_ROWS + wave * (LNB_ROWS / 4);
+  for (int rr = 0; rr < LNB_ROWS / 4; ++rr) {
+    const int64_t row = r0 + rr;
+    if (row >= rows) break;
+    const float mu = mean[row], rs = rstd[row];
+    float xh[NV], gd[NV];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int c = lane + 64 * i;
+      if (c < C) {
+        const float d = dy[row * C + c];
+        xh[i] = (to_f32(x[row * C + c]) - mu) * rs;
+        gd[i] = d * g[c];
+        s1 += gd[i];
+        s2 += gd[i] * xh[i];
+        dg[i] += d * xh[i];
+        db[i] += d;
+      } else {
+        xh[i] = 0.f; gd[i] = 0.f;
+      }
+    }
+    const float a = wave_sum(s1) / (float)C, bb = wave_sum(s2) / (float)C;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int c = lane + 64 * i;
+      if (c < C) {
+        float v = rs * (gd[i] - a - xh[i] * bb);
+        if (resid) v += to_f32(resid[row * C + c]);
+        else if (accumulate) v += to_f32(dx[row * C + c]);
+        dx[row * C + c] = from_f32<T>(v);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) { red[wave][0][lane + 64 * i] = dg[i]; red[wave][1][lane + 64 * i] = db[i]; }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float sg = red[0][0][c] + red[1][0][c] + red[2][0][c] + red[3][0][c];
+    float sb = red[0][1][c] + red[1][1][c] + red[2][1][c] + red[3][1][c];
+    part[(int64_t)blockIdx.x * 2 * C + c] = sg;
+    part[(int64_t)blockIdx.x * 2 * C + C + c] = sb;
+  }
+}
+
+template <typename T>
+evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
+                    const float* dy, int64_t rows, int C, const T* resid, bool accumulate, T* dx,
+                    float* part, int* nblk) {
+  *nblk = (int)ln_bwd_partials(rows);
+  if (c.dry || rows == 0) return EVO_OK;
+  dim3 grid((unsigned)*nblk);
+  const int acc = accumulate ? 1 : 0;
+  if (C <= 64) hipLaunchKernelGGL((ln_bwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else if (C <= 128) hipLaunchKernelGGL((ln_bwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else if (C <= 256) hipLaunchKernelGGL((ln_bwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else if (C <= 512) hipLaunchKernelGGL((ln_bwd_kernel<T, 8>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else { set_error("layernorm bwd: C=%d > 512", C); return EVO_ESHAPE; }
+  return check_launch("ln_bwd");
+}
+
+// Channel-major backward: x[C][P], dy[P][C] -> dx[C][P]; 64 positions per block.
+int64_t ln_bwd_cm_partials(int64_t P) { return (P + 63) / 64; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const T* __restrict__ x,
+                                                        const float* __restrict__ mean,
+                                                        const float* __restrict__ rstd,
+                                                        const float* __restrict__ g,
+                                                        const float* __restrict__ dy, int64_t P,
+                                                        int C, T* __restrict__ dx,
+                                                        float* __restrict__ part) {
+  extern __shared__ float sm[];  // tile [C][65] then red [4][2][C]
+  float* tile = sm;
+  float* red = sm + C * 65;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  for (int e = tid; e < C * 64; e += 256) {
+    const int cc = e >> 6, pp = e & 63;
+    const int64_t p = p0 + pp;
+    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
+  }
+  for (int e = tid; e < 8 * C; e += 256) red[e] = 0.f;
+  __syncthreads();
+  float* myred = red + wave * 2 * C;
+  for (int pp = wave * 16; pp < wave * 16 + 16; ++pp) {
+    const int64_t p = p0 + pp;
+    if (p >= P) break;
+    const float mu = mean[p], rs = rstd[p];
+    float s1 = 0.f, s2 = 0.f;
+    for (int cc = lane; cc < C; cc += 64) {
+      const float d = dy[p * C + cc];
+      const float xh = (tile[cc * 65 + pp] - mu) * rs;
+      const float gd = d * g[cc];
+      s1 += gd;
+      s2 += gd * xh;
+      myred[cc] += d * xh;
+      myred[C + cc] += d;
+    }
+    const float a = wave_sum(s1) / (float)C, bb = wave_sum(s2) / (float)C;
+    for (int cc = lane; cc < C; cc += 64) {
+      const float d = dy[p * C + cc];
+      const float xh = (tile[cc * 65 + pp] - mu) * rs;
+      tile[cc * 65 + pp] = rs * (d * g[cc] - a - xh * bb);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < C * 64; e += 256) {
+    const int cc = e >> 6, pp = e & 63;
+    const int64_t p = p0 + pp;
+    if (p < P) dx[(int64_t)cc * P + p] = from_f32<T>(tile[cc * 65 + pp]);
+  }
+  for (int cc = tid; cc < C; cc += 256) {
+    float sg = 0.f, sb = 0.f;
+    for (int w = 0; w < 4; ++w) { sg += red[w * 2 * C + cc]; sb += red[w * 2 * C + C + cc]; }
+    part[(int64_t)blockIdx.x * 2 * C + cc] = sg;
+    part[(int64_t)blockIdx.x * 2 * C + C + cc] = sb;
+  }
+}
+
+template <typename T>
+evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
+                       const float* dy, int64_t P, int C, T* dx, float* part, int* nblk) {
+  *nblk = (int)ln_bwd_cm_partials(P);
+  if (c.dry || P == 0) return EVO_OK;
+  if (C > 256) { set_error("layernorm bwd(cm): C=%d > 256", C); return EVO_ESHAPE; }
+  size_t lds = ((size_t)C * 65 + 8 * C) * sizeof(float);
+  hipLaunchKernelGGL((ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
+                     rstd, g, dy, P, C, dx, part);
+  return check_launch("ln_bwd_cm");
+}
+
+// ============================================================== reductions
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ part, int64_t n,
+                                                              int64_t C, int64_t ld, float* out,
+                                                              int accumulate) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= C) return;
+  float s = 0.f;
+  for (int64_t i = 0; i < n; ++i) s += part[i * ld + j];
+  out[j] = accumulate ? out[j] + s : s;
+}
+
+evo_status_t reduce_partials(const Ctx& c, const float* part, int64_t n, int64_t C, int64_t ld,
+                             float* out, bool accumulate) {
+  if (c.dry || C == 0) return EVO_OK;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
+                     part, n, C, ld, out, accumulate ? 1 : 0);
+  return check_launch("reduce_partials");
+}
+
+evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C, float* out_a,
+                              float* out_b) {
+  EVO_TRY(reduce_partials(c, part, n, C, 2 * C, out_a, true));
+  return reduce_partials(c, part + C, n, C, 2 * C, out_b, true);
+}
+
+constexpr int CS_ROWS = 128;
+int64_t colsum_partials(int64_t rows) { return (rows + CS_ROWS - 1) / CS_ROWS; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ x, int64_t rows, int C,
+                                                     int64_t ld, float* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * CS_ROWS;
+  const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) s += to_f32(x[r * ld + c]);
+    part[(int64_t)blockIdx.x * C + c] = s;
+  }
+}
+
+template <typename T>
+evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
+                            int* nblk) {
+  *nblk = (int)colsum_partials(rows);
+  if (c.dry || rows == 0) return EVO_OK;
+  hipLaunchKernelGGL((colsum_kernel<T>), dim3((unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
+  return check_launch("colsum");
+}
+
+template <typename T>
+evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
+                        float* out) {
+  int nb = 0;
+  EVO_TRY(colsum_partial<T>(c, x, rows, C, ld, part, &nb));
+  return reduce_partials(c, part, nb, C, C, out, true);
+}
+
+// ============================================================== packing / fill
+template <typename T>
+__global__ __launch_bounds__(256) void pack_kernel(PackArgs a, int ntot) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)a.K * ntot) return;
+  const int k = (int)(e / ntot), n = (int)(e % ntot);
+  int s = 0, nl = n;
+  while (s < a.nseg - 1 && nl >= a.seg[s].n) { nl -= a.seg[s].n; ++s; }
+  const float v = a.seg[s].w[(int64_t)k * a.seg[s].n + nl];
+  if (a.dst) ((T*)a.dst)[(int64_t)k * ntot + n] = from_f32<T>(v);
+  if (a.dst_t) ((T*)a.dst_t)[(int64_t)n * a.K + k] = from_f32<T>(v);
+  if (a.bias && k == 0) a.bias[n] = a.seg[s].bias ? a.seg[s].bias[nl] : 0.f;
+}
+
+template <typename T>
+evo_status_t pack_params(const Ctx& c, const PackArgs& a) {
+  if (c.dry) return EVO_OK;
+  int ntot = 0;
+  for (int s = 0; s < a.nseg; ++s) {
+    EVO_CHECK_ARG(a.seg[s].w != nullptr, EVO_EINVAL, "null parameter pointer (segment %d)", s);
+    ntot += a.seg[s].n;
+  }
+  const int64_t n = (int64_t)a.K * ntot;
+  hipLaunchKernelGGL((pack_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, ntot);
+  return check_launch("pack_params");
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_zero_kernel(T* p, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) p[e] = from_f32<T>(0.f);
+}
+
+template <typename T>
+evo_status_t fill_zero(const Ctx& c, T* p, int64_t n) {
+  if (c.dry || n == 0) return EVO_OK;
+  hipLaunchKernelGGL((fill_zero_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, p, n);
+  return check_launch("fill_zero");
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void copy_kernel(const T* __restrict__ s, T* __restrict__ d, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) d[e] = s[e];
+}
+
+template <typename T>
+evo_status_t copy_elems(const Ctx& c, const T* src, T* dst, int64_t n) {
+  if (c.dry || n == 0 || src == dst) return EVO_OK;
+  hipLaunchKernelGGL((copy_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
+  return check_launch("copy");
+}
+
+// ============================================================== attention gate backward
+template <typename T>
+__global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int hd, const T* dgo,
+                                                       int64_t ld_dgo, const T* o, int64_t ld_o,
+                                                       const T* g, int64_t ld_g, T* dctx,
+                                                       int64_t ld_dctx, T* dgp, int64_t ld_dg,
+                                                       float* D) {
+  const int HC = H * hd;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = e / HC;
+  const int col = (int)(e % HC);
+  float contrib = 0.f;
+  if (row < rows) {
+    const float dy = to_f32(dgo[row * ld_dgo + col]);
+    const float ov = to_f32(o[row * ld_o + col]);
+    const float gv = to_f32(g[row * ld_g + col]);
+    const float dc = dy * gv;
+    dctx[row * ld_dctx + col] = from_f32<T>(dc);
+    dgp[row * ld_dg + col] = from_f32<T>(dy * ov * gv * (1.f - gv));
+    contrib = to_f32(from_f32<T>(dc)) * ov;
+  }
+  // head_dim lanes are consecutive and aligned inside the wave (hd | 64)
+  for (int off = hd >> 1; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
+  if (row < rows && (col % hd) == 0) D[row * H + col / hd] = contrib;
+}
+
+template <typename T>
+evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, int64_t ld_dgo,
+                      const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
+                      T* dgpre, int64_t ld_dg, float* D) {
+  if (c.dry || rows == 0) return EVO_OK;
+  const int64_t n = rows * H * hd;
+  hipLaunchKernelGGL((gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+                     rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
+  return check_launch("gate_bwd");
+}
+
+// ============================================================== triangle multiplication glue
+// Tiles of 64 positions x 32 channels, transposed through LDS so that both the
+// row-major projection output and the channel-major operands move coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int cz, const T* raw,
+                                                          const float* mask, T* a, T* b) {
+  __shared__ float ta[32][65], tb[32][65];
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 32;
+  const int ld = 4 * ch + cz;
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int pp = e >> 5, cc = e & 31;
+    const int64_t p = p0 + pp;
+    const int c = c0 + cc;
+    float va = 0.f, vb = 0.f;
+    if (p < P && c < ch) {
+      const T* r = raw + p * ld;
+      const float mk = mask ? mask[p] : 1.f;
+      va = mk * sigmoidf_(to_f32(r[ch + c])) * to_f32(r[c]);
+      vb = mk * sigmoidf_(to_f32(r[3 * ch + c])) * to_f32(r[2 * ch + c]);
+    }
+    ta[cc][pp] = va;
+    tb[cc][pp] = vb;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int cc = e >> 6, pp = e & 63;
+    const int64_t p = p0 + pp;
+    const int c = c0 + cc;
+    if (p < P && c < ch) {
+      a[(int64_t)c * P + p] = from_f32<T>(ta[cc][pp]);
+      b[(int64_t)c * P + p] = from_f32<T>(tb[cc][pp]);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sigmoid_cols_kernel(int64_t P, int ch, int cz, const T* raw, T* g) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= P * cz) return;
+  const int64_t p = e / cz;
+  const int n = (int)(e % cz);
+  g[e] = from_f32<T>(sigmoidf_(to_f32(raw[p * (4 * ch + cz) + 4 * ch + n])));
+}
+
+template <typename T>
+evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
+                         T* a, T* b, T* g) {
+  if (c.dry || P == 0) return EVO_OK;
+  dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
+  hipLaunchKernelGGL((trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b);
+  EVO_TRY(check_launch("trimul_proj"));
+  const int64_t n = P * cz;
+  hipLaunchKernelGGL((sigmoid_cols_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+                     P, ch, cz, raw, g);
+  return check_launch("trimul_gate");
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch, int cz, const T* raw,
+                                                              const float* mask, const T* da,
+                                                              const T* db, T* draw) {
+  __shared__ float ta[32][65], tb[32][65];
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 32;
+  const int ld = 4 * ch + cz;
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int cc = e >> 6, pp = e & 63;
+    const int64_t p = p0 + pp;
+    const int c = c0 + cc;
+    ta[cc][pp] = (p < P && c < ch) ? to_f32(da[(int64_t)c * P + p]) : 0.f;
+    tb[cc][pp] = (p < P && c < ch) ? to_f32(db[(int64_t)c * P + p]) : 0.f;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int pp = e >> 5, cc = e & 31;
+    const int64_t p = p0 + pp;
+    const int c = c0 + cc;
+    if (p < P && c < ch) {
+      const T* r = raw + p * ld;
+      T* d = draw + p * ld;
+      const float mk = mask ? mask[p] : 1.f;
+      const float ap = to_f32(r[c]), sa = sigmoidf_(to_f32(r[ch + c]));
+      const float bp = to_f32(r[2 * ch + c]), sb = sigmoidf_(to_f32(r[3 * ch + c]));
+      const float dav = ta[cc][pp] * mk, dbv = tb[cc][pp] * mk;
+      d[c] = from_f32<T>(dav * sa);
+      d[ch + c] = from_f32<T>(dav * ap * sa * (1.f - sa));
+      d[2 * ch + c] = from_f32<T>(dbv * sb);
+      d[3 * ch + c] = from_f32<T>(dbv * bp * sb * (1.f - sb));
+    }
+  }
+}
+
+template <typename T>
+evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
+                             const float* mask, const T* da, const T* db, T* draw) {
+  if (c.dry || P == 0) return EVO_OK;
+  dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
+  hipLaunchKernelGGL((trimul_proj_bwd_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, da, db, draw);
+  return check_launch("trimul_proj_bwd");
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch, int cz, const T* dz,
+                                                              const T* t, const T* g, T* dt, T* draw) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= P * cz) return;
+  const int64_t p = e / cz;
+  const int n = (int)(e % cz);
+  const float d = to_f32(dz[e]), gv = to_f32(g[e]), tv = to_f32(t[e]);
+  dt[e] = from_f32<T>(d * gv);
+  draw[p * (4 * ch + cz) + 4 * ch + n] = from_f32<T>(d * tv * gv * (1.f - gv));
+}
+
+template <typename T>
+evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* dz, const T* t,
+                             const T* g, T* dt, T* draw) {
+  if (c.dry || P == 0) return EVO_OK;
+  const int64_t n = P * cz;
+  hipLaunchKernelGGL((trimul_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     c.stream, P, ch, cz, dz, t, g, dt, draw);
+  return check_launch("trimul_gate_bwd");
+}
+
+// ============================================================== outer product mean count
+__global__ __launch_bounds__(256) void opm_norm_kernel(const float* mask, int64_t S, int64_t R, float eps,
+                                                       float* scale) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= R * R) return;
+  const int64_t i = e / R, j = e % R;
+  float n = 0.f;
+  if (mask) {
+    for (int64_t s = 0; s < S; ++s) n += mask[s * R + i] * mask[s * R + j];
+  } else {
+    n = (float)S;
+  }
+  scale[e] = 1.0f / (eps + n);
+}
+
+evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, float eps, float* scale) {
+  if (c.dry) return EVO_OK;
+  const int64_t n = R * R;
+  hipLaunchKernelGGL(opm_norm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, mask, S,
+                     R, eps, scale);
+  return check_launch("opm_norm");
+}
+
+// ============================================================== instantiations
+#define EVO_INST(T)                                                                                \
+  template evo_status_t ln_fwd<T>(const Ctx&, const T*, int64_t, int, const float*, const float*,  \
+                                  float, T*, float*, float*);                                      \
+  template evo_status_t ln_fwd_cm<T>(const Ctx&, const T*, int64_t, int, const float*,             \
+                                     const float*, float, T*, float*, float*);                     \
+  template evo_status_t ln_bwd<T>(const Ctx&, const T*, const float*, const float*, const float*,  \
+                                  const float*, int64_t, int, const T*, bool, T*, float*, int*);   \
+  template evo_status_t ln_bwd_cm<T>(const Ctx&, const T*, const float*, const float*,             \
+                                     const float*, const float*, int64_t, int, T*, float*, int*);  \
+  template evo_status_t colsum_partial<T>(const Ctx&, const T*, int64_t, int, int64_t, float*,     \
+                                          int*);                                                   \
+  template evo_status_t colsum_add<T>(const Ctx&, const T*, int64_t, int, int64_t, float*, float*); \
+  template evo_status_t pack_params<T>(const Ctx&, const PackArgs&);                               \
+  template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \
+  template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
+  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const T*, int64_t, const T*,    \
+                                    int64_t, const T*, int64_t, T*, int64_t, T*, int64_t, float*); \
+  template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const T*, const float*, T*,  \
+                                       T*, T*);                                                    \
+  template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const T*, const float*,  \
+                                           const T*, const T*, T*);                                \
+  template evo_status_t trimul_gate_bwd<T>(const Ctx&, int64_t, int, int, const T*, const T*,      \
+                                           const T*, T*, T*);
+
+EVO_INST(float)
+EVO_INST(bf16)
+
+}  // namespace evo

@@ -1,0 +1,315 @@
+// Gated self-attention op (all kinds): LayerNorm -> fused q|k|v|gate
+// projection (one GEMM, sigmoid gate in the epilogue) -> pair-bias projection
+// -> attention core -> output projection with bias and residual in the
+// epilogue; and its backward.
+#include "ops.h"
+
+namespace evo {
+
+namespace {
+
+struct AttnShape {
+  int kind;
+  int64_t no, ni, rows, cin, cpair;
+  int H, D, HC, NQ;
+  bool global, row, tri;
+};
+
+AttnShape attn_shape(const evo_attn_desc_t& d) {
+  AttnShape s;
+  s.kind = d.kind;
+  s.no = d.n_outer; s.ni = d.n_inner; s.rows = d.n_outer * d.n_inner;
+  s.cin = d.c_in; s.cpair = d.c_pair;
+  s.H = d.heads; s.D = d.head_dim; s.HC = d.heads * d.head_dim;
+  s.global = d.kind == EVO_ATTN_COL_GLOBAL;
+  s.row = d.kind == EVO_ATTN_ROW;
+  s.tri = d.kind == EVO_ATTN_TRI_START || d.kind == EVO_ATTN_TRI_END;
+  s.NQ = s.global ? 2 * s.HC + 2 * s.D : 4 * s.HC;
+  return s;
+}
+
+template <typename T>
+struct AttnSaved {
+  T* y; float* mean; float* rstd;
+  T* yz; float* zmean; float* zrstd;
+  T* qkvg;
+  float* bias;
+  T* o; T* go;
+  float* st_max; float* st_inv;
+  float* gctx;
+  void carve(Arena& a, const AttnShape& s) {
+    y = a.take_n<T>(s.rows * s.cin);
+    mean = a.take_n<float>(s.rows);
+    rstd = a.take_n<float>(s.rows);
+    yz = nullptr; zmean = zrstd = nullptr; bias = nullptr; gctx = nullptr;
+    if (s.row) {
+      yz = a.take_n<T>(s.ni * s.ni * s.cpair);
+      zmean = a.take_n<float>(s.ni * s.ni);
+      zrstd = a.take_n<float>(s.ni * s.ni);
+      bias = a.take_n<float>((int64_t)s.H * s.ni * s.ni);
+    }
+    if (s.tri) bias = a.take_n<float>((int64_t)s.H * s.rows);
+    qkvg = a.take_n<T>(s.rows * s.NQ);
+    if (s.global) {
+      gctx = a.take_n<float>(s.ni * s.HC);
+      st_max = a.take_n<float>(s.ni * s.H);
+      st_inv = a.take_n<float>(s.ni * s.H);
+      o = nullptr;
+    } else {
+      o = a.take_n<T>(s.rows * s.HC);
+      st_max = a.take_n<float>(s.rows * s.H);
+      st_inv = a.take_n<float>(s.rows * s.H);
+    }
+    go = a.take_n<T>(s.rows * s.HC);
+  }
+};
+
+// Strides of the attention core for each kind (see evo.h for the index maps).
+AttnCore core_for(const AttnShape& s, const void* qkvg, void* o, void* go, const float* bias,
+                  const float* mask, float* smax, float* sinv) {
+  AttnCore a;
+  const int64_t ld = s.NQ, HC = s.HC;
+  const char* base = (const char*)qkvg;
+  (void)base;
+  a.H = s.H; a.D = s.D;
+  a.o = o; a.go = go;
+  a.bias = bias; a.mask = mask;
+  a.st_max = smax; a.st_inv = sinv;
+  const bool batch_outer = s.kind == EVO_ATTN_ROW || s.kind == EVO_ATTN_TRI_START;
+  if (batch_outer) {
+    a.nbatch = s.no; a.Lq = a.Lk = s.ni;
+    a.sb = s.ni * ld; a.sp = ld; a.osb = s.ni * HC; a.osp = HC;
+    a.stb = s.ni; a.stq = 1;
+    a.mb = s.ni; a.mk = 1;
+    a.bh = s.ni * s.ni; a.bq = s.ni; a.bk = 1;
+  } else {  // COL, TRI_END: batch is the inner index, queries/keys run over the outer index
+    a.nbatch = s.ni; a.Lq = a.Lk = s.no;
+    a.sb = ld; a.sp = s.ni * ld; a.osb = HC; a.osp = s.ni * HC;
+    a.stb = 1; a.stq = s.ni;
+    a.mb = 1; a.mk = s.ni;
+    a.bh = s.no * s.no; a.bq = 1; a.bk = s.no;
+  }
+  return a;
+}
+
+template <typename T>
+void set_qkvg(AttnCore& a, const T* qkvg, const AttnShape& s) {
+  a.q = qkvg;
+  a.k = qkvg + s.HC;
+  a.v = qkvg + 2 * s.HC;
+  a.g = qkvg + 3 * s.HC;
+}
+
+}  // namespace
+
+template <typename T>
+evo_status_t gattn_fwd(const Ctx& c, int64_t S, int64_t R, int H, int D, const T* qkvg, const float* mask,
+                       float eps, float* gctx, float* smax, float* sinv, T* go);
+template <typename T>
+evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int D, const T* qkvg,
+                       const float* mask, float eps, const float* gctx, const float* smax,
+                       const float* sinv, const T* dgo, T* dqkvg);
+
+template <typename T>
+evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
+                         const evo_attn_w_t& w, const T* x, const T* pair, const float* mask, T* out) {
+  const AttnShape s = attn_shape(d);
+  AttnSaved<T> S;
+  S.carve(sv, s);
+  T* wt_qkvg = ws.take_n<T>((int64_t)s.NQ * s.cin);
+  float* b_qkvg = ws.take_n<float>(s.NQ);
+  T* wt_o = ws.take_n<T>((int64_t)s.cin * s.HC);
+  if (c.dry) return EVO_OK;
+
+  // parameters: forward operands [n][k] in the compute type
+  PackArgs pk;
+  pk.K = (int)s.cin;
+  pk.seg[0] = {w.w_q, nullptr, s.HC};
+  pk.seg[1] = {w.w_k, nullptr, s.global ? s.D : s.HC};
+  pk.seg[2] = {w.w_v, nullptr, s.global ? s.D : s.HC};
+  pk.seg[3] = {w.w_g, w.b_g, s.HC};
+  pk.nseg = 4;
+  pk.dst_t = wt_qkvg;
+  pk.bias = b_qkvg;
+  EVO_TRY(pack_params<T>(c, pk));
+  PackArgs po;
+  po.K = s.HC;
+  po.seg[0] = {w.w_o, nullptr, (int)s.cin};
+  po.nseg = 1;
+  po.dst_t = wt_o;
+  EVO_TRY(pack_params<T>(c, po));
+
+  EVO_TRY(ln_fwd<T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd));
+  {
+    GemmArgs g;
+    g.M = s.rows; g.N = s.NQ; g.K = s.cin;
+    g.A = op_rowmajor(S.y, s.cin);
+    g.B = op_rowmajor(wt_qkvg, s.cin);
+    g.epi = epi_rowmajor(S.qkvg, s.NQ, false);
+    g.epi.bias = b_qkvg;
+    g.epi.act = ACT_SIGMOID;
+    g.epi.act_n0 = s.NQ - s.HC;
+    EVO_TRY(gemm<T>(c, g));
+  }
+  if (s.row) {
+    const int64_t P = s.ni * s.ni;
+    EVO_TRY(ln_fwd<T>(c, pair, P, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, S.yz, S.zmean, S.zrstd));
+    EVO_TRY(rowproj<T>(c, S.yz, P, (int)s.cpair, w.w_bias, s.H, S.bias));
+  } else if (s.tri) {
+    EVO_TRY(rowproj<T>(c, S.y, s.rows, (int)s.cin, w.w_bias, s.H, S.bias));
+  }
+  if (s.global) {
+    EVO_TRY(gattn_fwd<T>(c, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
+                         S.st_inv, S.go));
+  } else {
+    AttnCore a = core_for(s, S.qkvg, S.o, S.go, S.bias, mask, S.st_max, S.st_inv);
+    set_qkvg<T>(a, S.qkvg, s);
+    EVO_TRY(attn_fwd<T>(c, a));
+  }
+  {
+    GemmArgs g;
+    g.M = s.rows; g.N = s.cin; g.K = s.HC;
+    g.A = op_rowmajor(S.go, s.HC);
+    g.B = op_rowmajor(wt_o, s.HC);
+    g.epi = epi_rowmajor(out, s.cin, false);
+    g.epi.bias = w.b_o;
+    g.epi.resid = x;
+    g.epi.r_m = s.cin;
+    g.epi.r_n = 1;
+    EVO_TRY(gemm<T>(c, g));
+  }
+  return EVO_OK;
+}
+
+template <typename T>
+evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
+                         const evo_attn_w_t& w, const T* x, const T* pair, const float* mask,
+                         const T* dout, T* dx, T* dpair, const evo_attn_w_t& dw) {
+  const AttnShape s = attn_shape(d);
+  AttnSaved<T> S;
+  S.carve(sv, s);
+  T* w_qkvg = ws.take_n<T>((int64_t)s.cin * s.NQ);     // [c_in][NQ]
+  T* w_o = ws.take_n<T>((int64_t)s.HC * s.cin);        // [HC][c_in]
+  T* dgo = ws.take_n<T>(s.rows * s.HC);
+  T* dctx = s.global ? nullptr : ws.take_n<T>(s.rows * s.HC);
+  T* dqkvg = ws.take_n<T>(s.rows * s.NQ);
+  float* Dsum = s.global ? nullptr : ws.take_n<float>(s.rows * s.H);
+  float* dy = ws.take_n<float>(s.rows * s.cin);
+  float* dbias = nullptr;
+  float* dbias_part = nullptr;
+  AttnCore a;
+  int64_t ngroups = 0;
+  if (!s.global) {
+    a = core_for(s, S.qkvg, S.o, S.go, S.bias, mask, S.st_max, S.st_inv);
+    set_qkvg<T>(a, S.qkvg, s);
+    if (s.row || s.tri) {
+      ngroups = attn_bwd_groups(a);
+      dbias_part = ws.take_n<float>((size_t)ngroups * s.H * a.Lq * a.Lk);
+      dbias = ws.take_n<float>((size_t)s.H * a.Lq * a.Lk);
+    }
+  }
+  const int64_t mark = ws.off;   // scratch below is reused by each step
+  (void)mark;
+
+  if (!c.dry) {
+    PackArgs pk;
+    pk.K = (int)s.cin;
+    pk.seg[0] = {w.w_q, nullptr, s.HC};
+    pk.seg[1] = {w.w_k, nullptr, s.global ? s.D : s.HC};
+    pk.seg[2] = {w.w_v, nullptr, s.global ? s.D : s.HC};
+    pk.seg[3] = {w.w_g, nullptr, s.HC};
+    pk.nseg = 4;
+    pk.dst = w_qkvg;
+    EVO_TRY(pack_params<T>(c, pk));
+    PackArgs po;
+    po.K = s.HC;
+    po.seg[0] = {w.w_o, nullptr, (int)s.cin};
+    po.nseg = 1;
+    po.dst = w_o;
+    EVO_TRY(pack_params<T>(c, po));
+  }
+
+  // output projection
+  {
+    int off = 0, n = (int)s.cin;
+    float* outs[1] = {dw.b_o};
+    EVO_TRY(colsum_segments<T>(c, ws, dout, s.rows, s.cin, 1, &off, &n, outs));
+    EVO_TRY(wgrad<T>(c, ws, S.go, s.HC, dout, s.cin, s.rows, s.HC, s.cin, dw.w_o));
+    GemmArgs g;
+    g.M = s.rows; g.N = s.HC; g.K = s.cin;
+    g.A = op_rowmajor(dout, s.cin);
+    g.B = op_rowmajor(w_o, s.cin);
+    g.epi = epi_rowmajor(dgo, s.HC, false);
+    EVO_TRY(gemm<T>(c, g));
+  }
+  if (s.global) {
+    EVO_TRY(gattn_bwd<T>(c, ws, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
+                         S.st_inv, dgo, dqkvg));
+  } else {
+    // gate and attention core
+    EVO_TRY(gate_bwd<T>(c, s.rows, s.H, s.D, dgo, s.HC, S.o, s.HC, S.qkvg + 3 * s.HC, s.NQ, dctx,
+                        s.HC, dqkvg + 3 * s.HC, s.NQ, Dsum));
+    AttnGrad gr;
+    gr.dctx = dctx;
+    gr.Dsum = Dsum;
+    gr.dq = dqkvg; gr.dk = dqkvg + s.HC; gr.dv = dqkvg + 2 * s.HC;
+    gr.dsb = a.sb; gr.dsp = a.sp;
+    gr.dbias_part = dbias_part;
+    EVO_TRY(attn_bwd<T>(c, a, gr));
+    if (dbias_part) {
+      const int64_t nb = s.H * a.Lq * a.Lk;
+      EVO_TRY(reduce_partials(c, dbias_part, ngroups, nb, nb, dbias, false));
+    }
+  }
+  // gate bias and projection weights
+  {
+    int off = (int)(s.NQ - s.HC), n = s.HC;
+    float* outs[1] = {dw.b_g};
+    EVO_TRY(colsum_segments<T>(c, ws, dqkvg, s.rows, s.NQ, 1, &off, &n, outs));
+    const int kv = s.global ? s.D : s.HC;
+    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg, s.NQ, s.rows, s.cin, s.HC, dw.w_q));
+    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg + s.HC, s.NQ, s.rows, s.cin, kv, dw.w_k));
+    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg + s.HC + kv, s.NQ, s.rows, s.cin, kv, dw.w_v));
+    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg + s.NQ - s.HC, s.NQ, s.rows, s.cin, s.HC, dw.w_g));
+    GemmArgs g;
+    g.M = s.rows; g.N = s.cin; g.K = s.NQ;
+    g.A = op_rowmajor(dqkvg, s.NQ);
+    g.B = op_rowmajor(w_qkvg, s.NQ);
+    g.epi = epi_rowmajor(dy, s.cin, true);
+    EVO_TRY(gemm<T>(c, g));
+  }
+  // pair bias
+  if (s.row) {
+    const int64_t P = s.ni * s.ni;
+    float* dyz = ws.take_n<float>(P * s.cpair);
+    EVO_TRY(rowproj_bwd<T>(c, ws, S.yz, P, (int)s.cpair, w.w_bias, s.H, dbias, dyz, false, dw.w_bias));
+    float* part = ws.take_n<float>((size_t)ln_bwd_partials(P) * 2 * s.cpair);
+    int nb = 0;
+    EVO_TRY(ln_bwd<T>(c, pair, S.zmean, S.zrstd, w.ln_z_g, dyz, P, (int)s.cpair, nullptr, true, dpair,
+                      part, &nb));
+    if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)s.cpair, dw.ln_z_g, dw.ln_z_b));
+  } else if (s.tri) {
+    EVO_TRY(rowproj_bwd<T>(c, ws, S.y, s.rows, (int)s.cin, w.w_bias, s.H, dbias, dy, true, dw.w_bias));
+  }
+  // input LayerNorm and residual
+  float* part = ws.take_n<float>((size_t)ln_bwd_partials(s.rows) * 2 * s.cin);
+  int nb = 0;
+  EVO_TRY(ln_bwd<T>(c, x, S.mean, S.rstd, w.ln_g, dy, s.rows, (int)s.cin, dout, false, dx, part, &nb));
+  if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)s.cin, dw.ln_g, dw.ln_b));
+  return EVO_OK;
+}
+
+template evo_status_t attn_fwd_op<float>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
+                                         const evo_attn_w_t&, const float*, const float*, const float*,
+                                         float*);
+template evo_status_t attn_fwd_op<bf16>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
+                                        const evo_attn_w_t&, const bf16*, const bf16*, const float*,
+                                        bf16*);
+template evo_status_t attn_bwd_op<float>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
+                                         const evo_attn_w_t&, const float*, const float*, const float*,
+                                         const float*, float*, float*, const evo_attn_w_t&);
+template evo_status_t attn_bwd_op<bf16>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
+                                        const evo_attn_w_t&, const bf16*, const bf16*, const float*,
+                                        const bf16*, bf16*, bf16*, const evo_attn_w_t&);
+
+}  // namespace evo

@@ -1,0 +1,459 @@
+// Transition, outer product mean and triangle multiplicative update ops.
+#include "ops.h"
+
+namespace evo {
+
+// ============================================================== transition
+template <typename T>
+static void trans_carve(Arena& a, const evo_trans_desc_t& d, T** y, float** mean, float** rstd, T** h) {
+  *y = a.take_n<T>(d.rows * d.c);
+  *mean = a.take_n<float>(d.rows);
+  *rstd = a.take_n<float>(d.rows);
+  *h = a.take_n<T>(d.rows * d.c * d.factor);
+}
+
+template <typename T>
+evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
+                          const evo_trans_w_t& w, const T* x, T* out) {
+  T *y, *h; float *mean, *rstd;
+  trans_carve<T>(sv, d, &y, &mean, &rstd, &h);
+  const int64_t C = d.c, HID = d.c * d.factor;
+  T* wt1 = ws.take_n<T>(HID * C);
+  T* wt2 = ws.take_n<T>(C * HID);
+  float* b1 = ws.take_n<float>(HID);
+  if (c.dry) return EVO_OK;
+  PackArgs p1; p1.K = (int)C; p1.seg[0] = {w.w_1, w.b_1, (int)HID}; p1.nseg = 1; p1.dst_t = wt1; p1.bias = b1;
+  EVO_TRY(pack_params<T>(c, p1));
+  PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst_t = wt2;
+  EVO_TRY(pack_params<T>(c, p2));
+  EVO_TRY(ln_fwd<T>(c, x, d.rows, (int)C, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd));
+  {
+    GemmArgs g;
+    g.M = d.rows; g.N = HID; g.K = C;
+    g.A = op_rowmajor(y, C);
+    g.B = op_rowmajor(wt1, C);
+    g.epi = epi_rowmajor(h, HID, false);
+    g.epi.bias = b1;
+    g.epi.act = ACT_RELU;
+    EVO_TRY(gemm<T>(c, g));
+  }
+  GemmArgs g;
+  g.M = d.rows; g.N = C; g.K = HID;
+  g.A = op_rowmajor(h, HID);
+  g.B = op_rowmajor(wt2, HID);
+  g.epi = epi_rowmajor(out, C, false);
+  g.epi.bias = w.b_2;
+  g.epi.resid = x; g.epi.r_m = C; g.epi.r_n = 1;
+  return gemm<T>(c, g);
+}
+
+template <typename T>
+evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
+                          const evo_trans_w_t& w, const T* x, const T* dout, T* dx,
+                          const evo_trans_w_t& dw) {
+  T *y, *h; float *mean, *rstd;
+  trans_carve<T>(sv, d, &y, &mean, &rstd, &h);
+  const int64_t C = d.c, HID = d.c * d.factor;
+  T* w1 = ws.take_n<T>(C * HID);     // [C][HID]
+  T* w2 = ws.take_n<T>(HID * C);     // [HID][C]
+  T* dh = ws.take_n<T>(d.rows * HID);
+  float* dy = ws.take_n<float>(d.rows * C);
+  if (!c.dry) {
+    PackArgs p1; p1.K = (int)C; p1.seg[0] = {w.w_1, nullptr, (int)HID}; p1.nseg = 1; p1.dst = w1;
+    EVO_TRY(pack_params<T>(c, p1));
+    PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst = w2;
+    EVO_TRY(pack_params<T>(c, p2));
+  }
+  int off0 = 0, nC = (int)C, nH = (int)HID;
+  float* ob2[1] = {dw.b_2};
+  EVO_TRY(colsum_segments<T>(c, ws, dout, d.rows, C, 1, &off0, &nC, ob2));
+  EVO_TRY(wgrad<T>(c, ws, h, HID, dout, C, d.rows, HID, C, dw.w_2));
+  {
+    GemmArgs g;
+    g.M = d.rows; g.N = HID; g.K = C;
+    g.A = op_rowmajor(dout, C);
+    g.B = op_rowmajor(w2, C);
+    g.epi = epi_rowmajor(dh, HID, false);
+    g.epi.relu_ref = h; g.epi.r_m = HID; g.epi.r_n = 1;
+    if (!c.dry) EVO_TRY(gemm<T>(c, g));
+  }
+  float* ob1[1] = {dw.b_1};
+  EVO_TRY(colsum_segments<T>(c, ws, dh, d.rows, HID, 1, &off0, &nH, ob1));
+  EVO_TRY(wgrad<T>(c, ws, y, C, dh, HID, d.rows, C, HID, dw.w_1));
+  {
+    GemmArgs g;
+    g.M = d.rows; g.N = C; g.K = HID;
+    g.A = op_rowmajor(dh, HID);
+    g.B = op_rowmajor(w1, HID);
+    g.epi = epi_rowmajor(dy, C, true);
+    if (!c.dry) EVO_TRY(gemm<T>(c, g));
+  }
+  float* part = ws.take_n<float>((size_t)ln_bwd_partials(d.rows) * 2 * C);
+  int nb = 0;
+  EVO_TRY(ln_bwd<T>(c, x, mean, rstd, w.ln_g, dy, d.rows, (int)C, dout, false, dx, part, &nb));
+  if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)C, dw.ln_g, dw.ln_b));
+  return EVO_OK;
+}
+
+// ============================================================== outer product mean
+template <typename T>
+struct OpmSaved {
+  T* y; float* mean; float* rstd; T* ab; T* on; float* scale;
+  void carve(Arena& a, const evo_opm_desc_t& d) {
+    const int64_t SR = d.n_seq * d.n_res, RR = d.n_res * d.n_res, ch = d.c_hidden;
+    y = a.take_n<T>(SR * d.c_m);
+    mean = a.take_n<float>(SR);
+    rstd = a.take_n<float>(SR);
+    ab = a.take_n<T>(SR * 2 * ch);
+    on = a.take_n<T>(RR * ch * ch);
+    scale = a.take_n<float>(RR);
+  }
+};
+
+template <typename T>
+evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
+                        const evo_opm_w_t& w, const T* m, const float* mask, const T* zin, T* zout) {
+  OpmSaved<T> S;
+  S.carve(sv, d);
+  const int64_t S_ = d.n_seq, R = d.n_res, SR = S_ * R, RR = R * R, ch = d.c_hidden, cm = d.c_m,
+                cz = d.c_z, ch2 = ch * ch;
+  const int sh = ilog2(ch);
+  T* wt_ab = ws.take_n<T>(2 * ch * cm);
+  float* b_ab = ws.take_n<float>(2 * ch);
+  T* wt_o = ws.take_n<T>(cz * ch2);
+  if (c.dry) return EVO_OK;
+  PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, w.b_a, (int)ch}; pa.seg[1] = {w.w_b, w.b_b, (int)ch};
+  pa.nseg = 2; pa.dst_t = wt_ab; pa.bias = b_ab;
+  EVO_TRY(pack_params<T>(c, pa));
+  PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
+  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(ln_fwd<T>(c, m, SR, (int)cm, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd));
+  {  // a | b = mask * (y W + b)
+    GemmArgs g;
+    g.M = SR; g.N = 2 * ch; g.K = cm;
+    g.A = op_rowmajor(S.y, cm);
+    g.B = op_rowmajor(wt_ab, cm);
+    g.epi = epi_rowmajor(S.ab, 2 * ch, false);
+    g.epi.bias = b_ab;
+    if (mask) { g.epi.scale = mask; g.epi.sm_shift = 0; g.epi.sm_ld = 1; g.epi.sn_shift = 31; g.epi.sn_ld = 0; }
+    EVO_TRY(gemm<T>(c, g));
+  }
+  EVO_TRY(opm_norm(c, mask, S_, R, d.opm_eps, S.scale));
+  {  // On[i][j][p][q] = sum_s a[s][i][p] b[s][j][q] / (eps + n_ij)
+    GemmArgs g;
+    g.M = R * ch; g.N = R * ch; g.K = S_;
+    g.A.ptr = S.ab; g.A.r_lo = 1; g.A.r_hi = 2 * ch; g.A.r_shift = sh; g.A.k_lo = R * 2 * ch; g.A.k_contig = 0;
+    g.B = g.A; g.B.ptr = S.ab + ch;
+    g.epi.out = S.on; g.epi.out_f32 = 0;
+    g.epi.m_lo = ch; g.epi.m_hi = R * ch2; g.epi.m_shift = sh;
+    g.epi.n_lo = 1; g.epi.n_hi = ch2; g.epi.n_shift = sh;
+    g.epi.scale = S.scale; g.epi.sm_shift = sh; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1;
+    EVO_TRY(gemm<T>(c, g));
+  }
+  GemmArgs g;
+  g.M = RR; g.N = cz; g.K = ch2;
+  g.A = op_rowmajor(S.on, ch2);
+  g.B = op_rowmajor(wt_o, ch2);
+  g.epi = epi_rowmajor(zout, cz, false);
+  g.epi.bias = w.b_o;
+  g.epi.resid = zin; g.epi.r_m = cz; g.epi.r_n = 1;
+  return gemm<T>(c, g);
+}
+
+template <typename T>
+evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
+                        const evo_opm_w_t& w, const T* m, const float* mask, const T* dz, T* dm,
+                        const evo_opm_w_t& dw) {
+  OpmSaved<T> S;
+  S.carve(sv, d);
+  const int64_t S_ = d.n_seq, R = d.n_res, SR = S_ * R, RR = R * R, ch = d.c_hidden, cm = d.c_m,
+                cz = d.c_z, ch2 = ch * ch;
+  const int sh = ilog2(ch);
+  T* w_ab = ws.take_n<T>(cm * 2 * ch);   // [cm][2ch]
+  T* w_o = ws.take_n<T>(ch2 * cz);       // [ch2][cz]
+  T* dO = ws.take_n<T>(RR * ch2);
+  T* dab = ws.take_n<T>(SR * 2 * ch);
+  float* dy = ws.take_n<float>(SR * cm);
+  if (!c.dry) {
+    PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, nullptr, (int)ch}; pa.seg[1] = {w.w_b, nullptr, (int)ch};
+    pa.nseg = 2; pa.dst = w_ab;
+    EVO_TRY(pack_params<T>(c, pa));
+    PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst = w_o;
+    EVO_TRY(pack_params<T>(c, po));
+  }
+  int off0 = 0, ncz = (int)cz;
+  float* obo[1] = {dw.b_o};
+  EVO_TRY(colsum_segments<T>(c, ws, dz, RR, cz, 1, &off0, &ncz, obo));
+  EVO_TRY(wgrad<T>(c, ws, S.on, ch2, dz, cz, RR, ch2, cz, dw.w_o));
+  if (!c.dry) {
+    {  // dO = (dz W_o^T) / (eps + n_ij)
+      GemmArgs g;
+      g.M = RR; g.N = ch2; g.K = cz;
+      g.A = op_rowmajor(dz, cz);
+      g.B = op_rowmajor(w_o, cz);
+      g.epi = epi_rowmajor(dO, ch2, false);
+      g.epi.scale = S.scale; g.epi.sm_shift = 0; g.epi.sm_ld = 1; g.epi.sn_shift = 31; g.epi.sn_ld = 0;
+      EVO_TRY(gemm<T>(c, g));
+    }
+    {  // da[s][i][p] = mask_si * sum_{j,q} dO[i][j][p][q] b[s][j][q]
+      GemmArgs g;
+      g.M = R * ch; g.N = S_; g.K = R * ch;
+      g.A.ptr = dO; g.A.r_lo = ch; g.A.r_hi = R * ch2; g.A.r_shift = sh;
+      g.A.k_lo = 1; g.A.k_hi = ch2; g.A.k_shift = sh; g.A.k_contig = 1;
+      g.B.ptr = S.ab + ch; g.B.r_lo = R * 2 * ch;
+      g.B.k_lo = 1; g.B.k_hi = 2 * ch; g.B.k_shift = sh; g.B.k_contig = 1;
+      g.epi.out = dab; g.epi.out_f32 = 0;
+      g.epi.m_lo = 1; g.epi.m_hi = 2 * ch; g.epi.m_shift = sh;
+      g.epi.n_lo = R * 2 * ch;
+      if (mask) { g.epi.scale = mask; g.epi.sm_shift = sh; g.epi.sm_ld = 1; g.epi.sn_shift = 0; g.epi.sn_ld = R; }
+      EVO_TRY(gemm<T>(c, g));
+    }
+    {  // db[s][j][q] = mask_sj * sum_{i,p} dO[i][j][p][q] a[s][i][p]
+      GemmArgs g;
+      g.M = R * ch; g.N = S_; g.K = R * ch;
+      g.A.ptr = dO; g.A.r_lo = 1; g.A.r_hi = ch2; g.A.r_shift = sh;
+      g.A.k_lo = ch; g.A.k_hi = R * ch2; g.A.k_shift = sh; g.A.k_contig = 0;
+      g.B.ptr = S.ab; g.B.r_lo = R * 2 * ch;
+      g.B.k_lo = 1; g.B.k_hi = 2 * ch; g.B.k_shift = sh; g.B.k_contig = 1;
+      g.epi.out = dab + ch; g.epi.out_f32 = 0;
+      g.epi.m_lo = 1; g.epi.m_hi = 2 * ch; g.epi.m_shift = sh;
+      g.epi.n_lo = R * 2 * ch;
+      if (mask) { g.epi.scale = mask; g.epi.sm_shift = sh; g.epi.sm_ld = 1; g.epi.sn_shift = 0; g.epi.sn_ld = R; }
+      EVO_TRY(gemm<T>(c, g));
+    }
+  }
+  int offs[2] = {0, (int)ch}, ns[2] = {(int)ch, (int)ch};
+  float* obab[2] = {dw.b_a, dw.b_b};
+  EVO_TRY(colsum_segments<T>(c, ws, dab, SR, 2 * ch, 2, offs, ns, obab));
+  EVO_TRY(wgrad<T>(c, ws, S.y, cm, dab, 2 * ch, SR, cm, ch, dw.w_a));
+  EVO_TRY(wgrad<T>(c, ws, S.y, cm, dab + ch, 2 * ch, SR, cm, ch, dw.w_b));
+  if (!c.dry) {
+    GemmArgs g;
+    g.M = SR; g.N = cm; g.K = 2 * ch;
+    g.A = op_rowmajor(dab, 2 * ch);
+    g.B = op_rowmajor(w_ab, 2 * ch);
+    g.epi = epi_rowmajor(dy, cm, true);
+    EVO_TRY(gemm<T>(c, g));
+  }
+  float* part = ws.take_n<float>((size_t)ln_bwd_partials(SR) * 2 * cm);
+  int nb = 0;
+  EVO_TRY(ln_bwd<T>(c, m, S.mean, S.rstd, w.ln_g, dy, SR, (int)cm, nullptr, true, dm, part, &nb));
+  if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)cm, dw.ln_g, dw.ln_b));
+  return EVO_OK;
+}
+
+// ============================================================== triangle multiplication
+template <typename T>
+struct TriSaved {
+  T* y; float* mean; float* rstd; T* raw; T* a; T* b; T* g; T* x; T* xn; float* mean2; float* rstd2;
+  void carve(Arena& ar, const evo_trimul_desc_t& d) {
+    const int64_t P = d.n_res * d.n_res, ch = d.c_hidden, cz = d.c_z;
+    y = ar.take_n<T>(P * cz);
+    mean = ar.take_n<float>(P);
+    rstd = ar.take_n<float>(P);
+    raw = ar.take_n<T>(P * (4 * ch + cz));
+    a = ar.take_n<T>(P * ch);
+    b = ar.take_n<T>(P * ch);
+    g = ar.take_n<T>(P * cz);
+    x = ar.take_n<T>(P * ch);
+    xn = ar.take_n<T>(P * ch);
+    mean2 = ar.take_n<float>(P);
+    rstd2 = ar.take_n<float>(P);
+  }
+};
+
+template <typename T>
+evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
+                           const evo_trimul_w_t& w, const T* z, const float* mask, T* zout) {
+  TriSaved<T> S;
+  S.carve(sv, d);
+  const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
+  T* wt_p = ws.take_n<T>(NP * cz);
+  float* b_p = ws.take_n<float>(NP);
+  T* wt_o = ws.take_n<T>(cz * ch);
+  if (c.dry) return EVO_OK;
+  PackArgs pp;
+  pp.K = (int)cz;
+  pp.seg[0] = {w.w_ap, w.b_ap, (int)ch};
+  pp.seg[1] = {w.w_ag, w.b_ag, (int)ch};
+  pp.seg[2] = {w.w_bp, w.b_bp, (int)ch};
+  pp.seg[3] = {w.w_bg, w.b_bg, (int)ch};
+  pp.seg[4] = {w.w_g, w.b_g, (int)cz};
+  pp.nseg = 5;
+  pp.dst_t = wt_p;
+  pp.bias = b_p;
+  EVO_TRY(pack_params<T>(c, pp));
+  PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
+  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(ln_fwd<T>(c, z, P, (int)cz, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd));
+  {
+    GemmArgs g;
+    g.M = P; g.N = NP; g.K = cz;
+    g.A = op_rowmajor(S.y, cz);
+    g.B = op_rowmajor(wt_p, cz);
+    g.epi = epi_rowmajor(S.raw, NP, false);
+    g.epi.bias = b_p;
+    EVO_TRY(gemm<T>(c, g));
+  }
+  EVO_TRY(trimul_proj<T>(c, P, (int)ch, (int)cz, S.raw, mask, S.a, S.b, S.g));
+  {  // per-channel contraction, channel-major operands [ch][R][R]
+    GemmArgs g;
+    g.M = R; g.N = R; g.K = R; g.batch = (int)ch;
+    if (d.dir == EVO_TRI_OUT) {   // X_c = A_c B_c^T
+      g.A = op_rowmajor(S.a, R);
+      g.B = op_rowmajor(S.b, R);
+    } else {                      // X_c = A_c^T B_c
+      g.A = op_colmajor(S.a, R);
+      g.B = op_colmajor(S.b, R);
+    }
+    g.A.batch = P; g.B.batch = P;
+    g.epi = epi_rowmajor(S.x, R, false);
+    g.epi.batch = P;
+    EVO_TRY(gemm<T>(c, g));
+  }
+  EVO_TRY(ln_fwd_cm<T>(c, S.x, P, (int)ch, w.ln_out_g, w.ln_out_b, d.ln_eps, S.xn, S.mean2, S.rstd2));
+  GemmArgs g;
+  g.M = P; g.N = cz; g.K = ch;
+  g.A = op_rowmajor(S.xn, ch);
+  g.B = op_rowmajor(wt_o, ch);
+  g.epi = epi_rowmajor(zout, cz, false);
+  g.epi.bias = w.b_o;
+  g.epi.gate = S.g; g.epi.g_m = cz; g.epi.g_n = 1;
+  g.epi.resid = z; g.epi.r_m = cz; g.epi.r_n = 1;
+  return gemm<T>(c, g);
+}
+
+template <typename T>
+evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
+                           const evo_trimul_w_t& w, const T* z, const float* mask, const T* dzo,
+                           T* dz, const evo_trimul_w_t& dw) {
+  TriSaved<T> S;
+  S.carve(sv, d);
+  const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
+  T* w_p = ws.take_n<T>(cz * NP);      // [cz][NP]
+  T* wt_o = ws.take_n<T>(cz * ch);     // [cz][ch]
+  T* w_o = ws.take_n<T>(ch * cz);      // [ch][cz]
+  T* t = ws.take_n<T>(P * cz);
+  T* dt = ws.take_n<T>(P * cz);
+  T* draw = ws.take_n<T>(P * NP);
+  float* dxn = ws.take_n<float>(P * ch);
+  T* dx = ws.take_n<T>(P * ch);
+  T* da = ws.take_n<T>(P * ch);
+  T* db = ws.take_n<T>(P * ch);
+  float* dy = ws.take_n<float>(P * cz);
+  if (!c.dry) {
+    PackArgs pp;
+    pp.K = (int)cz;
+    pp.seg[0] = {w.w_ap, nullptr, (int)ch};
+    pp.seg[1] = {w.w_ag, nullptr, (int)ch};
+    pp.seg[2] = {w.w_bp, nullptr, (int)ch};
+    pp.seg[3] = {w.w_bg, nullptr, (int)ch};
+    pp.seg[4] = {w.w_g, nullptr, (int)cz};
+    pp.nseg = 5;
+    pp.dst = w_p;
+    EVO_TRY(pack_params<T>(c, pp));
+    PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o; po.dst = w_o;
+    EVO_TRY(pack_params<T>(c, po));
+    {  // t = LN_out(x) W_o + b_o
+      GemmArgs g;
+      g.M = P; g.N = cz; g.K = ch;
+      g.A = op_rowmajor(S.xn, ch);
+      g.B = op_rowmajor(wt_o, ch);
+      g.epi = epi_rowmajor(t, cz, false);
+      g.epi.bias = w.b_o;
+      EVO_TRY(gemm<T>(c, g));
+    }
+    EVO_TRY(trimul_gate_bwd<T>(c, P, (int)ch, (int)cz, dzo, t, S.g, dt, draw));
+  }
+  int off0 = 0, ncz = (int)cz;
+  float* obo[1] = {dw.b_o};
+  EVO_TRY(colsum_segments<T>(c, ws, dt, P, cz, 1, &off0, &ncz, obo));
+  EVO_TRY(wgrad<T>(c, ws, S.xn, ch, dt, cz, P, ch, cz, dw.w_o));
+  if (!c.dry) {
+    GemmArgs g;
+    g.M = P; g.N = ch; g.K = cz;
+    g.A = op_rowmajor(dt, cz);
+    g.B = op_rowmajor(w_o, cz);
+    g.epi = epi_rowmajor(dxn, ch, true);
+    EVO_TRY(gemm<T>(c, g));
+  }
+  {
+    float* part = ws.take_n<float>((size_t)ln_bwd_cm_partials(P) * 2 * ch);
+    int nb = 0;
+    EVO_TRY(ln_bwd_cm<T>(c, S.x, S.mean2, S.rstd2, w.ln_out_g, dxn, P, (int)ch, dx, part, &nb));
+    if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)ch, dw.ln_out_g, dw.ln_out_b));
+  }
+  if (!c.dry) {
+    GemmArgs g;
+    g.M = R; g.N = R; g.K = R; g.batch = (int)ch;
+    if (d.dir == EVO_TRI_OUT) {
+      // da_c[i][k] = sum_j dx_c[i][j] b_c[j][k]
+      g.A = op_rowmajor(dx, R);
+      g.B = op_colmajor(S.b, R);
+      g.A.batch = P; g.B.batch = P;
+      g.epi = epi_rowmajor(da, R, false); g.epi.batch = P;
+      EVO_TRY(gemm<T>(c, g));
+      // db_c[j][k] = sum_i dx_c[i][j] a_c[i][k]
+      g.A = op_colmajor(dx, R);
+      g.B = op_colmajor(S.a, R);
+      g.A.batch = P; g.B.batch = P;
+      g.epi = epi_rowmajor(db, R, false); g.epi.batch = P;
+      EVO_TRY(gemm<T>(c, g));
+    } else {
+      // da_c[k][i] = sum_j b_c[k][j] dx_c[i][j]
+      g.A = op_rowmajor(S.b, R);
+      g.B = op_rowmajor(dx, R);
+      g.A.batch = P; g.B.batch = P;
+      g.epi = epi_rowmajor(da, R, false); g.epi.batch = P;
+      EVO_TRY(gemm<T>(c, g));
+      // db_c[k][j] = sum_i a_c[k][i] dx_c[i][j]
+      g.A = op_rowmajor(S.a, R);
+      g.B = op_colmajor(dx, R);
+      g.A.batch = P; g.B.batch = P;
+      g.epi = epi_rowmajor(db, R, false); g.epi.batch = P;
+      EVO_TRY(gemm<T>(c, g));
+    }
+    EVO_TRY(trimul_proj_bwd<T>(c, P, (int)ch, (int)cz, S.raw, mask, da, db, draw));
+  }
+  int offs[5] = {0, (int)ch, (int)(2 * ch), (int)(3 * ch), (int)(4 * ch)};
+  int ns[5] = {(int)ch, (int)ch, (int)ch, (int)ch, (int)cz};
+  float* obp[5] = {dw.b_ap, dw.b_ag, dw.b_bp, dw.b_bg, dw.b_g};
+  EVO_TRY(colsum_segments<T>(c, ws, draw, P, NP, 5, offs, ns, obp));
+  float* owp[5] = {dw.w_ap, dw.w_ag, dw.w_bp, dw.w_bg, dw.w_g};
+  for (int s = 0; s < 5; ++s) EVO_TRY(wgrad<T>(c, ws, S.y, cz, draw + offs[s], NP, P, cz, ns[s], owp[s]));
+  if (!c.dry) {
+    GemmArgs g;
+    g.M = P; g.N = cz; g.K = NP;
+    g.A = op_rowmajor(draw, NP);
+    g.B = op_rowmajor(w_p, NP);
+    g.epi = epi_rowmajor(dy, cz, true);
+    EVO_TRY(gemm<T>(c, g));
+  }
+  float* part = ws.take_n<float>((size_t)ln_bwd_partials(P) * 2 * cz);
+  int nb = 0;
+  EVO_TRY(ln_bwd<T>(c, z, S.mean, S.rstd, w.ln_g, dy, P, (int)cz, dzo, false, dz, part, &nb));
+  if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)cz, dw.ln_g, dw.ln_b));
+  return EVO_OK;
+}
+
+#define EVO_INST_P(T)                                                                              \
+  template evo_status_t trans_fwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trans_desc_t&,       \
+                                        const evo_trans_w_t&, const T*, T*);                       \
+  template evo_status_t trans_bwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trans_desc_t&,       \
+                                        const evo_trans_w_t&, const T*, const T*, T*,              \
+                                        const evo_trans_w_t&);                                     \
+  template evo_status_t opm_fwd_op<T>(const Ctx&, Arena&, Arena&, const evo_opm_desc_t&,           \
+                                      const evo_opm_w_t&, const T*, const float*, const T*, T*);   \
+  template evo_status_t opm_bwd_op<T>(const Ctx&, Arena&, Arena&, const evo_opm_desc_t&,           \
+                                      const evo_opm_w_t&, const T*, const float*, const T*, T*,    \
+                                      const evo_opm_w_t&);                                         \
+  template evo_status_t trimul_fwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,     \
+                                         const evo_trimul_w_t&, const T*, const float*, T*);       \
+  template evo_status_t trimul_bwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,     \
+                                         const evo_trimul_w_t&, const T*, const float*, const T*,  \
+                                         T*, const evo_trimul_w_t&);
+
+EVO_INST_P(float)
+EVO_INST_P(bf16)
+
+}  // namespace evo

@@ -1,0 +1,72 @@
+"""Shared helpers of the GPU parity tests (comparison metrics, device copies)."""
+from __future__ import annotations
+
+import sys
+
+import torch
+
+F64 = torch.float64
+TOL = {"f32": 1e-4, "bf16": 2e-2}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev_dtype(name):
+    return {"f32": torch.float32, "bf16": torch.bfloat16}[name]
+
+
+def to_dev(x, dtype="f32"):
+    return x.to(dev_dtype(dtype)).cuda().contiguous()
+
+
+def params_dev(p):
+    return {k: v.to(torch.float32).cuda().contiguous() for k, v in p.items()}
+
+
+def rel_err(got, ref):
+    """Normwise relative error ||got - ref||_2 / ||ref||_2 (float64 on the CPU)."""
+    got = got.detach().to("cpu", F64)
+    ref = ref.detach().to("cpu", F64)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    den = ref.norm().item()
+    num = (got - ref).norm().item()
+    if den == 0.0:
+        return num
+    return num / den
+
+
+def check(name, got, ref, tol, report=None):
+    e = rel_err(got, ref)
+    if report is not None:
+        report[name] = e
+    assert torch.isfinite(got.detach().float()).all(), f"{name}: non-finite values"
+    assert e <= tol, f"{name}: normwise relative error {e:.3e} > {tol:.1e}"
+    return e
+
+
+def oracle_grads(fn, inputs: dict, upstream):
+    """Gradients of <fn(**inputs), upstream> w.r.t. every float64 leaf in `inputs`
+    (nested dicts of tensors allowed)."""
+    leaves = {}
+
+    def mk(v, path):
+        if isinstance(v, dict):
+            return {k: mk(x, path + (k,)) for k, x in v.items()}
+        if isinstance(v, torch.Tensor) and v.dtype == F64:
+            t = v.detach().clone().requires_grad_(True)
+            leaves[path] = t
+            return t
+        return v
+    args = {k: mk(v, (k,)) for k, v in inputs.items()}
+    out = fn(**args)
+    (out * upstream).sum().backward()
+    grads = {}
+    for path, t in leaves.items():
+        d = grads
+        for p in path[:-1]:
+            d = d.setdefault(p, {})
+        d[path[-1]] = t.grad if t.grad is not None else torch.zeros_like(t)
+    return out.detach(), grads

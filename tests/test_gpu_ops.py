@@ -1,0 +1,232 @@
+"""GPU parity of every sub-operation entry point against the FP64 oracle.
+
+Forward: the residual update out - x.  Backward: d_x (including the identity
+path), cross-input gradients and every parameter gradient.  Shapes are ragged
+(N_res = 40 is not a multiple of any tile) and masks are random with a fully
+masked MSA column and pair row, so the uniform-weight reading of fully masked
+softmax rows is exercised.  Tolerance: normwise relative 1e-4 (FP32), 2e-2 (BF16).
+"""
+import pytest
+import torch
+
+from oracle import evoformer as O
+from synth import EvoConfig, make_inputs, round_inputs
+
+from gpu_util import TOL, check, oracle_grads, params_dev, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+OPCFG = EvoConfig("op", n_seq=12, n_res=40, c_m=32, c_z=16, msa_heads=2, msa_head_dim=16,
+                  tri_heads=2, tri_head_dim=8, tri_mul_hidden=16, opm_hidden=8,
+                  mask_mode="random")
+
+
+def _setup(dtype, cfg=OPCFG, seed=7):
+    from paper_2207_05477_amd import binding as B  # noqa: F401
+    inp = make_inputs(cfg, seed=seed, perturb=True)
+    return round_inputs(inp, dtype)
+
+
+def _zeros_like(p):
+    return {k: torch.zeros_like(v) for k, v in p.items()}
+
+
+def _check_param_grads(tag, dpar, gref, tol):
+    for k in dpar:
+        check(f"{tag} d{k}", dpar[k], gref[k], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("hd", [8, 16, 32, 64])
+def test_row_attn(dtype, hd):
+    from paper_2207_05477_amd import binding as B, _abi as A
+    cfg = OPCFG.replace(msa_head_dim=hd, msa_heads=2 if hd < 64 else 1)
+    say(f"row_attn dtype={dtype} hd={hd}")
+    inp = _setup(dtype, cfg)
+    tol = TOL[dtype]
+    H, D = cfg.msa_heads, cfg.msa_head_dim
+    p = inp["params"][0]["row_attn"]
+    M = inp["msa_mask"]
+    upd, g = oracle_grads(lambda m, z, p: O.row_attn(m, z, M, p, H, D),
+                          {"m": inp["m"], "z": inp["z"], "p": p}, inp["dm_out"])
+    desc = B.attn_desc(A.EVO_ATTN_ROW, dtype, cfg.n_seq, cfg.n_res, cfg.c_m, H, D, c_pair=cfg.c_z)
+    pd = params_dev(p)
+    w = B.weight_struct("row_attn", pd)
+    x, pair, mask = to_dev(inp["m"], dtype), to_dev(inp["z"], dtype), M.float().cuda()
+    out, saved = B.evo_attn_fwd(desc, w, x, pair, mask)
+    torch.cuda.synchronize()
+    check("row fwd", out.double().cpu() - inp["m"], upd, tol)
+    dpar = _zeros_like(pd)
+    dpair = torch.zeros_like(pair)
+    dx = B.evo_attn_bwd(desc, w, x, pair, mask, saved, to_dev(inp["dm_out"], dtype),
+                        B.weight_struct("row_attn", dpar), d_pair=dpair)
+    torch.cuda.synchronize()
+    check("row dx", dx, inp["dm_out"] + g["m"], tol)
+    check("row dpair", dpair, g["z"], tol)
+    _check_param_grads("row", dpar, g["p"], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_col_attn(dtype):
+    from paper_2207_05477_amd import binding as B, _abi as A
+    say(f"col_attn dtype={dtype}")
+    inp = _setup(dtype)
+    tol = TOL[dtype]
+    cfg = OPCFG
+    H, D = cfg.msa_heads, cfg.msa_head_dim
+    p = inp["params"][0]["col_attn"]
+    M = inp["msa_mask"]
+    upd, g = oracle_grads(lambda m, p: O.col_attn(m, M, p, H, D), {"m": inp["m"], "p": p}, inp["dm_out"])
+    desc = B.attn_desc(A.EVO_ATTN_COL, dtype, cfg.n_seq, cfg.n_res, cfg.c_m, H, D)
+    pd = params_dev(p)
+    w = B.weight_struct("col_attn", pd)
+    x, mask = to_dev(inp["m"], dtype), M.float().cuda()
+    out, saved = B.evo_attn_fwd(desc, w, x, None, mask)
+    torch.cuda.synchronize()
+    check("col fwd", out.double().cpu() - inp["m"], upd, tol)
+    dpar = _zeros_like(pd)
+    dx = B.evo_attn_bwd(desc, w, x, None, mask, saved, to_dev(inp["dm_out"], dtype),
+                        B.weight_struct("col_attn", dpar))
+    torch.cuda.synchronize()
+    check("col dx", dx, inp["dm_out"] + g["m"], tol)
+    _check_param_grads("col", dpar, g["p"], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_col_global_attn(dtype):
+    from paper_2207_05477_amd import binding as B, _abi as A
+    say(f"col_global_attn dtype={dtype}")
+    cfg = OPCFG.replace(extra_msa=True, msa_heads=4, msa_head_dim=8)
+    inp = _setup(dtype, cfg)
+    tol = TOL[dtype]
+    H, D = cfg.msa_heads, cfg.msa_head_dim
+    p = inp["params"][0]["col_attn"]
+    M = inp["msa_mask"]
+    upd, g = oracle_grads(lambda m, p: O.col_global_attn(m, M, p, H, D, 1e-5, cfg.global_eps),
+                          {"m": inp["m"], "p": p}, inp["dm_out"])
+    desc = B.attn_desc(A.EVO_ATTN_COL_GLOBAL, dtype, cfg.n_seq, cfg.n_res, cfg.c_m, H, D,
+                       global_eps=cfg.global_eps)
+    pd = params_dev(p)
+    w = B.weight_struct("col_attn", pd)
+    x, mask = to_dev(inp["m"], dtype), M.float().cuda()
+    out, saved = B.evo_attn_fwd(desc, w, x, None, mask)
+    torch.cuda.synchronize()
+    check("gcol fwd", out.double().cpu() - inp["m"], upd, tol)
+    dpar = _zeros_like(pd)
+    dx = B.evo_attn_bwd(desc, w, x, None, mask, saved, to_dev(inp["dm_out"], dtype),
+                        B.weight_struct("col_attn", dpar))
+    torch.cuda.synchronize()
+    check("gcol dx", dx, inp["dm_out"] + g["m"], tol)
+    _check_param_grads("gcol", dpar, g["p"], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("kind", ["start", "end"])
+def test_tri_attn(dtype, kind):
+    from paper_2207_05477_amd import binding as B, _abi as A
+    say(f"tri_attn_{kind} dtype={dtype}")
+    inp = _setup(dtype)
+    tol = TOL[dtype]
+    cfg = OPCFG
+    H, D = cfg.tri_heads, cfg.tri_head_dim
+    sub = "tri_att_start" if kind == "start" else "tri_att_end"
+    fn = O.tri_att_start if kind == "start" else O.tri_att_end
+    p = inp["params"][0][sub]
+    P = inp["pair_mask"]
+    upd, g = oracle_grads(lambda z, p: fn(z, P, p, H, D), {"z": inp["z"], "p": p}, inp["dz_out"])
+    k = A.EVO_ATTN_TRI_START if kind == "start" else A.EVO_ATTN_TRI_END
+    desc = B.attn_desc(k, dtype, cfg.n_res, cfg.n_res, cfg.c_z, H, D)
+    pd = params_dev(p)
+    w = B.weight_struct(sub, pd)
+    x, mask = to_dev(inp["z"], dtype), P.float().cuda()
+    out, saved = B.evo_attn_fwd(desc, w, x, None, mask)
+    torch.cuda.synchronize()
+    check(f"{sub} fwd", out.double().cpu() - inp["z"], upd, tol)
+    dpar = _zeros_like(pd)
+    dx = B.evo_attn_bwd(desc, w, x, None, mask, saved, to_dev(inp["dz_out"], dtype),
+                        B.weight_struct(sub, dpar))
+    torch.cuda.synchronize()
+    check(f"{sub} dx", dx, inp["dz_out"] + g["z"], tol)
+    _check_param_grads(sub, dpar, g["p"], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("direction", ["out", "in"])
+def test_tri_mul(dtype, direction):
+    from paper_2207_05477_amd import binding as B, _abi as A
+    say(f"tri_mul_{direction} dtype={dtype}")
+    inp = _setup(dtype)
+    tol = TOL[dtype]
+    cfg = OPCFG
+    sub = f"tri_mul_{direction}"
+    fn = O.tri_mul_out if direction == "out" else O.tri_mul_in
+    p = inp["params"][0][sub]
+    P = inp["pair_mask"]
+    upd, g = oracle_grads(lambda z, p: fn(z, P, p), {"z": inp["z"], "p": p}, inp["dz_out"])
+    desc = B.trimul_desc(dtype, A.EVO_TRI_OUT if direction == "out" else A.EVO_TRI_IN, cfg.n_res,
+                         cfg.c_z, cfg.tri_mul_hidden)
+    pd = params_dev(p)
+    w = B.weight_struct(sub, pd)
+    x, mask = to_dev(inp["z"], dtype), P.float().cuda()
+    out, saved = B.tri_mul_fwd(desc, w, x, mask)
+    torch.cuda.synchronize()
+    check(f"{sub} fwd", out.double().cpu() - inp["z"], upd, tol)
+    dpar = _zeros_like(pd)
+    dz = B.tri_mul_bwd(desc, w, x, mask, saved, to_dev(inp["dz_out"], dtype), B.weight_struct(sub, dpar))
+    torch.cuda.synchronize()
+    check(f"{sub} dz", dz, inp["dz_out"] + g["z"], tol)
+    _check_param_grads(sub, dpar, g["p"], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_opm(dtype):
+    from paper_2207_05477_amd import binding as B
+    say(f"opm dtype={dtype}")
+    inp = _setup(dtype)
+    tol = TOL[dtype]
+    cfg = OPCFG
+    p = inp["params"][0]["opm"]
+    M = inp["msa_mask"]
+    upd, g = oracle_grads(lambda m, p: O.outer_product_mean(m, M, p, 1e-5, cfg.opm_eps),
+                          {"m": inp["m"], "p": p}, inp["dz_out"])
+    desc = B.opm_desc(dtype, cfg.n_seq, cfg.n_res, cfg.c_m, cfg.opm_hidden, cfg.c_z, opm_eps=cfg.opm_eps)
+    pd = params_dev(p)
+    w = B.weight_struct("opm", pd)
+    m, z, mask = to_dev(inp["m"], dtype), to_dev(inp["z"], dtype), M.float().cuda()
+    zo, saved = B.opm_fwd(desc, w, m, mask, z)
+    torch.cuda.synchronize()
+    check("opm fwd", zo.double().cpu() - inp["z"], upd, tol)
+    dpar = _zeros_like(pd)
+    dm = torch.zeros_like(m)
+    B.opm_bwd(desc, w, m, mask, saved, to_dev(inp["dz_out"], dtype), dm, B.weight_struct("opm", dpar))
+    torch.cuda.synchronize()
+    check("opm dm", dm, g["m"], tol)
+    _check_param_grads("opm", dpar, g["p"], tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("which", ["msa", "pair"])
+def test_transition(dtype, which):
+    from paper_2207_05477_amd import binding as B
+    say(f"transition_{which} dtype={dtype}")
+    inp = _setup(dtype)
+    tol = TOL[dtype]
+    sub = "msa_trans" if which == "msa" else "pair_trans"
+    x64 = inp["m"] if which == "msa" else inp["z"]
+    up = inp["dm_out"] if which == "msa" else inp["dz_out"]
+    p = inp["params"][0][sub]
+    upd, g = oracle_grads(lambda x, p: O.transition(x, p), {"x": x64, "p": p}, up)
+    C = x64.shape[-1]
+    rows = x64.numel() // C
+    desc = B.trans_desc(dtype, rows, C, OPCFG.transition_factor)
+    pd = params_dev(p)
+    w = B.weight_struct(sub, pd)
+    x = to_dev(x64, dtype)
+    out, saved = B.evo_transition_fwd(desc, w, x)
+    torch.cuda.synchronize()
+    check(f"{sub} fwd", out.double().cpu() - x64, upd, tol)
+    dpar = _zeros_like(pd)
+    dx = B.evo_transition_bwd(desc, w, x, saved, to_dev(up, dtype), B.weight_struct(sub, dpar))
+    torch.cuda.synchronize()
+    check(f"{sub} dx", dx, up + g["x"], tol)
+    _check_param_grads(sub, dpar, g["p"], tol)
