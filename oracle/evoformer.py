@@ -35,6 +35,10 @@ The readings taken where the paper is silent:
   bias not divided, eps a runtime argument (default 1e-3).
 * Incoming triangle multiplication: x_ij = sum_k a_ki * b_kj.
 * Dropout is the identity.
+* The ReLU of the transitions decides on the exact pre-activation, or, when
+  compared with a BF16 implementation, on the BF16-formed pre-activation
+  (relu_decision="bf16"): a discrete decision is taken in the precision of the
+  implementation under test, the values stay float64.
 * Block order: row attention, column attention, MSA transition, outer product
   mean, outgoing and incoming triangle multiplication, triangle attention
   around the starting and the ending node, pair transition.
@@ -118,10 +122,29 @@ def col_global_attn(m, msa_mask, p, heads, head_dim, eps=1e-5, global_eps=1e-10)
     return (g * o[None]).reshape(S, R, H * c) @ p["w_o"] + p["b_o"]
 
 
-def transition(x, p, eps=1e-5):
-    """Two-layer MLP with ReLU on the LayerNormed input."""
+def _bf16(t):
+    return t.detach().to(torch.bfloat16).to(F64)
+
+
+def transition(x, p, eps=1e-5, relu_decision=None):
+    """Two-layer MLP with ReLU on the LayerNormed input.
+
+    The ReLU is a discrete decision taken by floating point.  With
+    relu_decision="bf16" the decision (which hidden units are active) is taken
+    on the pre-activation formed from the BF16-rounded LayerNorm output and
+    BF16-rounded W_1, as a BF16 implementation forms it; the values that pass
+    stay the exact float64 ones.  None takes the decision on the exact value."""
     y = layer_norm(x, p["ln_g"], p["ln_b"], eps)
-    return torch.relu(y @ p["w_1"] + p["b_1"]) @ p["w_2"] + p["b_2"]
+    pre = y @ p["w_1"] + p["b_1"]
+    if relu_decision is None:
+        h = torch.relu(pre)
+    elif relu_decision == "bf16":
+        with torch.no_grad():
+            active = (_bf16(y) @ _bf16(p["w_1"]) + p["b_1"].detach()) > 0
+        h = pre * active.to(F64)
+    else:
+        raise ValueError(relu_decision)
+    return h @ p["w_2"] + p["b_2"]
 
 
 def outer_product_mean(m, msa_mask, p, eps=1e-5, opm_eps=1e-3):
@@ -194,7 +217,7 @@ def tri_att_end(z, pair_mask, p, heads, head_dim, eps=1e-5):
     return (g * o).reshape(R, R, H * c) @ p["w_o"] + p["b_o"]
 
 
-def block(m, z, msa_mask, pair_mask, p, cfg):
+def block(m, z, msa_mask, pair_mask, p, cfg, relu_decision=None):
     """One Evoformer block (the extra-MSA block when cfg.extra_msa): residual
     MSA stack, outer product mean, residual pair stack."""
     eps = cfg.ln_eps
@@ -204,20 +227,20 @@ def block(m, z, msa_mask, pair_mask, p, cfg):
                                 eps, cfg.global_eps)
     else:
         m = m + col_attn(m, msa_mask, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim, eps)
-    m = m + transition(m, p["msa_trans"], eps)
+    m = m + transition(m, p["msa_trans"], eps, relu_decision)
     z = z + outer_product_mean(m, msa_mask, p["opm"], eps, cfg.opm_eps)
     z = z + tri_mul_out(z, pair_mask, p["tri_mul_out"], eps)
     z = z + tri_mul_in(z, pair_mask, p["tri_mul_in"], eps)
     z = z + tri_att_start(z, pair_mask, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps)
     z = z + tri_att_end(z, pair_mask, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps)
-    z = z + transition(z, p["pair_trans"], eps)
+    z = z + transition(z, p["pair_trans"], eps, relu_decision)
     return m, z
 
 
-def stack(m, z, msa_mask, pair_mask, blocks, cfg):
+def stack(m, z, msa_mask, pair_mask, blocks, cfg, relu_decision=None):
     """Blocks applied in sequence with independent parameters."""
     for p in blocks:
-        m, z = block(m, z, msa_mask, pair_mask, p, cfg)
+        m, z = block(m, z, msa_mask, pair_mask, p, cfg, relu_decision)
     return m, z
 
 
@@ -225,7 +248,7 @@ def _leaf(t):
     return t.detach().clone().to(F64).requires_grad_(True)
 
 
-def stack_fwd_bwd(inp, cfg, want_param_grads=True):
+def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None):
     """Forward and backward of the stack on float64 copies of ``inp``.
 
     Returns (m_out, z_out, grads) with grads = {"m", "z", "params"} where
@@ -239,7 +262,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True):
     acts = [(inp["m"].detach().to(F64), inp["z"].detach().to(F64))]
     with torch.no_grad():
         for p in inp["params"]:
-            acts.append(block(acts[-1][0], acts[-1][1], msa_mask, pair_mask, p, cfg))
+            acts.append(block(acts[-1][0], acts[-1][1], msa_mask, pair_mask, p, cfg, relu_decision))
     dm = inp["dm_out"].to(F64)
     dz = inp["dz_out"].to(F64)
     pgrads = [None] * len(inp["params"])
@@ -249,7 +272,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True):
         blk = inp["params"][i]
         leaves = {s: {k: (_leaf(v) if want_param_grads else v.detach().to(F64))
                       for k, v in blk[s].items()} for s in blk}
-        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg)
+        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg, relu_decision)
         ((mo * dm).sum() + (zo * dz).sum()).backward()
         dm, dz = m.grad, z.grad
         if want_param_grads:
@@ -260,7 +283,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True):
     return acts[-1][0], acts[-1][1], grads
 
 
-def stack_fwd(inp, cfg):
+def stack_fwd(inp, cfg, relu_decision=None):
     with torch.no_grad():
         return stack(inp["m"].to(F64), inp["z"].to(F64), inp["msa_mask"].to(F64),
-                     inp["pair_mask"].to(F64), inp["params"], cfg)
+                     inp["pair_mask"].to(F64), inp["params"], cfg, relu_decision)

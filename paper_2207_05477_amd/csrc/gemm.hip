@@ -233,7 +233,10 @@ evo_status_t gemm(const Ctx& ctx, const GemmArgs& g) {
   if (ctx.dry) return EVO_OK;
   if (g.M <= 0 || g.N <= 0) return EVO_OK;
   constexpr int VEC = GemmTraits<T>::VEC;
-  if (g.K % VEC) { set_error("gemm: K=%lld not a multiple of %d", (long long)g.K, VEC); return EVO_ESHAPE; }
+  if ((g.A.k_contig || g.B.k_contig) && g.K % VEC) {
+    set_error("gemm: K=%lld not a multiple of %d for loads along k", (long long)g.K, VEC);
+    return EVO_ESHAPE;
+  }
   if (!operand_ok(g.A, g.M, VEC, "A") || !operand_ok(g.B, g.N, VEC, "B")) return EVO_ESHAPE;
   if (!g.epi.out) { set_error("gemm: null output"); return EVO_EINVAL; }
   if (g.split_k > 1 && !g.epi.out_f32) { set_error("gemm: split-K needs FP32 partials"); return EVO_EINVAL; }

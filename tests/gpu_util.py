@@ -38,8 +38,13 @@ def rel_err(got, ref):
     return num / den
 
 
-def check(name, got, ref, tol, report=None):
-    e = rel_err(got, ref)
+def check(name, got, ref, tol, report=None, floor=0.0):
+    """Normwise relative error against ref; `floor` bounds the denominator from
+    below for tensors that are zero by an identity (then the error is relative
+    to the magnitude of a sibling quantity without the cancellation)."""
+    got64 = got.detach().to("cpu", F64)
+    ref64 = ref.detach().to("cpu", F64)
+    e = (got64 - ref64).norm().item() / max(ref64.norm().item(), floor, 1e-300)
     if report is not None:
         report[name] = e
     assert torch.isfinite(got.detach().float()).all(), f"{name}: non-finite values"

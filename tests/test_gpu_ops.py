@@ -63,6 +63,10 @@ def test_row_attn(dtype, hd):
     torch.cuda.synchronize()
     check("row dx", dx, inp["dm_out"] + g["m"], tol)
     check("row dpair", dpair, g["z"], tol)
+    # The pair-bias LayerNorm shift gradient is zero by an identity (the bias
+    # gradient sums to zero over keys): bound it by its sibling's magnitude.
+    zb = dpar.pop("ln_z_b")
+    check("row dln_z_b", zb, g["p"]["ln_z_b"], tol, floor=g["p"]["ln_z_g"].norm().item())
     _check_param_grads("row", dpar, g["p"], tol)
 
 
@@ -215,7 +219,8 @@ def test_transition(dtype, which):
     x64 = inp["m"] if which == "msa" else inp["z"]
     up = inp["dm_out"] if which == "msa" else inp["dz_out"]
     p = inp["params"][0][sub]
-    upd, g = oracle_grads(lambda x, p: O.transition(x, p), {"x": x64, "p": p}, up)
+    dec = "bf16" if dtype == "bf16" else None
+    upd, g = oracle_grads(lambda x, p: O.transition(x, p, 1e-5, dec), {"x": x64, "p": p}, up)
     C = x64.shape[-1]
     rows = x64.numel() // C
     desc = B.trans_desc(dtype, rows, C, OPCFG.transition_factor)

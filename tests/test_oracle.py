@@ -385,3 +385,21 @@ def test_golden_logits_memory_example():
             got = sizes.activation_bytes(cse["rows"], cse["cols"], cse["elem_bytes"], cse.get("chunk", 0))
         exp = cse["bytes"] if "bytes" in cse else cse["gib"] * 2 ** 30
         assert math.isclose(got, exp, rel_tol=1e-12), (cse, got)
+
+
+def test_transition_bf16_relu_decision_only_moves_near_zero_units():
+    # The BF16 decision mode changes the ReLU mask only where the exact
+    # pre-activation is within BF16 rounding of zero; elsewhere the output is
+    # the exact one.
+    inp = _inp(TINY.replace(n_seq=6, n_res=7, c_m=16), mask_mode="full")
+    p = inp["params"][0]["msa_trans"]
+    x = inp["m"]
+    exact = O.transition(x, p)
+    dec = O.transition(x, p, 1e-5, "bf16")
+    y = F.layer_norm(x, (x.shape[-1],), p["ln_g"], p["ln_b"], eps=1e-5)
+    pre = y @ p["w_1"] + p["b_1"]
+    pre_b = y.to(torch.bfloat16).double() @ p["w_1"].to(torch.bfloat16).double() + p["b_1"]
+    flips = (pre > 0) != (pre_b > 0)
+    assert torch.all(pre[flips].abs() < 0.05)
+    rows_clean = ~flips.any(-1)
+    _close(dec[rows_clean], exact[rows_clean], 1e-12)
