@@ -254,6 +254,28 @@ evo_status_t evoformer_block_bwd(const evo_block_desc_t* desc, const evo_block_w
                                  void* dm, void* dz, const evo_block_w_t* d_w,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ launch profiler
+ * Optional per-launch timing for roofline reports.  Between evo_profile_begin
+ * and evo_profile_end every kernel the library enqueues is bracketed by two
+ * HIP events recorded on the stream it is launched on.  evo_profile_end waits
+ * for those events and returns one record per kernel instance (template
+ * instantiation) with the launch count, the summed event durations and the
+ * summed algorithmic FLOPs and bytes of its launches (the products and the
+ * compulsory reads/writes the launch's own inputs and outputs imply).
+ * Returns the number of records written (at most max_records), -1 on error.
+ * Not thread-safe with respect to concurrent library calls.
+ */
+typedef struct {
+  char name[120];
+  int64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} evo_kernel_stat_t;
+
+void evo_profile_begin(void);
+int32_t evo_profile_end(evo_kernel_stat_t* records, int32_t max_records);
+
 /* ------------------------------------------------------------------ misc */
 const char* evo_version(void);
 const char* evo_last_error(void);

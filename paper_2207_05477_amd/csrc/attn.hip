@@ -15,6 +15,7 @@
 // kernel produces dK and dV with the roles of queries and keys swapped.
 #include "attn.h"
 
+#include <string>
 #include <type_traits>
 
 namespace evo {
@@ -447,11 +448,21 @@ static bool attn_shape_ok(const AttnCore& a) {
 }
 
 template <typename T, int D>
+static std::string kname(const char* k) {
+  return std::string(k) + "<" + tname<T>() + ", " + std::to_string(D) + ">";
+}
+
+template <typename T, int D>
 static void launch_fwd(const Ctx& c, const AttnCore& a) {
+  static const std::string nm = kname<T, D>("attn_fwd_kernel");
   const int64_t nq = a.q_count < 0 ? a.Lq : a.q_count;
   dim3 grid((unsigned)((nq + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
   const float sl2 = kLog2e / sqrtf((float)D);
-  hipLaunchKernelGGL((attn_fwd_kernel<T, D>), grid, dim3(256), 0, c.stream, a, sl2);
+  const double bh = (double)a.nbatch * a.H;
+  const double flops = 4.0 * bh * nq * a.Lk * D;
+  const double bytes = bh * ((double)nq * D * 4 + (double)a.Lk * D * 2) * sizeof(T) +
+                       (a.bias ? (double)a.H * nq * a.Lk * 4.0 : 0.0) + bh * nq * 8.0;
+  EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D>), grid, dim3(256), 0, c.stream, a, sl2);
 }
 
 template <typename T>
@@ -490,11 +501,20 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
       return EVO_ESHAPE;
     }
   }
+  static const std::string n1 = kname<T, D>("attn_bwd_dq_kernel");
+  static const std::string n2 = kname<T, D>("attn_bwd_dkdv_kernel");
+  const double bh = (double)a.nbatch * a.H, ll = (double)a.Lq * a.Lk;
+  // algorithmic products: dP and dQ here, dK and dV in the second kernel
+  const double f1 = 4.0 * bh * ll * D, f2 = 4.0 * bh * ll * D;
+  const double b1 = bh * ((double)a.Lq * D * 3 + (double)a.Lk * D * 2) * sizeof(T) + bh * a.Lq * 12.0 +
+                    (g.dbias_part ? (double)ngroups * a.H * ll * 4.0 + a.H * ll * 4.0 : 0.0);
+  const double b2 = bh * ((double)a.Lq * D * 2 + (double)a.Lk * D * 4) * sizeof(T) + bh * a.Lq * 12.0 +
+                    (a.bias ? a.H * ll * 4.0 : 0.0);
   dim3 g1((unsigned)((a.Lq + 63) / 64), (unsigned)a.H, (unsigned)ngroups);
-  hipLaunchKernelGGL((attn_bwd_dq_kernel<T, D>), g1, dim3(256), lds, c.stream, a, g, sl2, sc);
+  EVO_LAUNCH(n1.c_str(), f1, b1, (attn_bwd_dq_kernel<T, D>), g1, dim3(256), lds, c.stream, a, g, sl2, sc);
   EVO_TRY(check_launch("attn_bwd_dq"));
   dim3 g2((unsigned)((a.Lk + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
-  hipLaunchKernelGGL((attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc);
+  EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc);
   return check_launch("attn_bwd_dkdv");
 }
 

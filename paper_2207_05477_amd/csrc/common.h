@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <string>
+
 #include "evo.h"
 
 typedef __bf16 bf16;
@@ -69,6 +71,28 @@ void set_error(const char* fmt, ...);
   } while (0)
 
 evo_status_t check_launch(const char* what);
+
+// Launch profiler (see evo_profile_begin): slot handle or -1 when disabled.
+int prof_begin(const char* name, hipStream_t s, double flops, double bytes);
+void prof_end(int slot, hipStream_t s);
+
+#define EVO_LAUNCH(name, flops, bytes, kernel, grid, block, lds, stream, ...)        \
+  do {                                                                             \
+    const int _ps = ::evo::prof_begin(name, stream, flops, bytes);                 \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);             \
+    ::evo::prof_end(_ps, stream);                                                  \
+  } while (0)
+
+// Per-instantiation kernel name "lit<T>" for the profiler.
+#define EVO_KNAME(lit, T)                                                                  \
+  ([]() -> const char* {                                                                   \
+    static const std::string s_ = std::string(lit) + "<" + ::evo::tname<T>() + ">";       \
+    return s_.c_str();                                                                     \
+  }())
+
+template <typename T> inline const char* tname();
+template <> inline const char* tname<float>() { return "float"; }
+template <> inline const char* tname<__bf16>() { return "__bf16"; }
 
 // Bump allocator over a caller-owned workspace.  In dry mode it only counts
 // bytes, so one code path both sizes and carves the workspace.

@@ -109,11 +109,11 @@ evo_status_t gattn_fwd(const Ctx& c, int64_t S, int64_t R, int H, int D, const T
   if (c.dry) return EVO_OK;
   const size_t lds = (8 + (size_t)H * D + (size_t)H * S) * sizeof(float);
   if (lds > 150 * 1024) { set_error("global attention: %lld rows exceed LDS", (long long)S); return EVO_ESHAPE; }
-  hipLaunchKernelGGL((gattn_fwd_kernel<T>), dim3((unsigned)R), dim3(GA_THREADS), lds, c.stream, S, R, H, D,
+  EVO_LAUNCH(EVO_KNAME("gattn_fwd_kernel", T), 4.0 * (double)S * R * H * D, (double)S * R * (2 * H * D + 2 * D) * sizeof(T), (gattn_fwd_kernel<T>), dim3((unsigned)R), dim3(GA_THREADS), lds, c.stream, S, R, H, D,
                      qkvg, mask, eps, gctx, smax, sinv);
   EVO_TRY(check_launch("gattn_fwd"));
   const int64_t n = S * R * H * D;
-  hipLaunchKernelGGL((gattn_gate_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, S, R,
+  EVO_LAUNCH(EVO_KNAME("gattn_gate_kernel", T), 0.0, (double)n * 2 * sizeof(T), (gattn_gate_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, S, R,
                      H, D, qkvg, gctx, go);
   return check_launch("gattn_gate");
 }
@@ -221,10 +221,10 @@ evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int
   const size_t lds = (8 + 3 * (size_t)H * D + 2 * (size_t)H * S) * sizeof(float);
   if (lds > 150 * 1024) { set_error("global attention bwd: %lld rows exceed LDS", (long long)S); return EVO_ESHAPE; }
   const int64_t n = S * R * H * D;
-  hipLaunchKernelGGL((gattn_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, S, R,
+  EVO_LAUNCH(EVO_KNAME("gattn_gate_bwd_kernel", T), 0.0, (double)n * 3 * sizeof(T), (gattn_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, S, R,
                      H, D, qkvg, gctx, dgo, dqkvg);
   EVO_TRY(check_launch("gattn_gate_bwd"));
-  hipLaunchKernelGGL((gattn_bwd_kernel<T>), dim3((unsigned)R), dim3(GA_THREADS), lds, c.stream, S, R, H, D, qkvg,
+  EVO_LAUNCH(EVO_KNAME("gattn_bwd_kernel", T), 8.0 * (double)S * R * H * D, (double)S * R * (3 * H * D + 4 * D) * sizeof(T), (gattn_bwd_kernel<T>), dim3((unsigned)R), dim3(GA_THREADS), lds, c.stream, S, R, H, D, qkvg,
                      mask, eps, dgo, dqkvg);
   return check_launch("gattn_bwd");
 }

@@ -2,6 +2,8 @@
 // v_mfma_f32_16x16x4_f32, FP32 accumulation, 256 threads (4 wave64s) per
 // workgroup, double-buffered LDS tiles with a register prefetch of the next
 // k-tile, fused elementwise epilogue.
+#include <string>
+
 #include "gemm.h"
 
 namespace evo {
@@ -223,9 +225,21 @@ static bool operand_ok(const GemmOperand& o, int64_t rows, int vec, const char* 
 
 template <typename T, int BM, int BN, int WMW, int WNW>
 static void launch(const Ctx& ctx, const GemmArgs& g) {
+  static const std::string nm = std::string("gemm_kernel<") + tname<T>() + ", " + std::to_string(BM) +
+                                ", " + std::to_string(BN) + ", " + std::to_string(WMW) + ", " +
+                                std::to_string(WNW) + ">";
   dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
             (unsigned)(g.split_k > 1 ? g.split_k : g.batch));
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WMW, WNW>), grid, dim3(256), 0, ctx.stream, g);
+  const double nb = g.split_k > 1 ? 1.0 : (double)g.batch;
+  const double nout = g.split_k > 1 ? (double)g.split_k : (double)g.batch;
+  const double mn = (double)g.M * g.N;
+  const double flops = 2.0 * mn * g.K * nb;
+  double bytes = ((double)g.M * g.K + (double)g.N * g.K) * sizeof(T) * nb +
+                 mn * nout * (g.epi.out_f32 ? 4.0 : sizeof(T)) * (g.epi.accumulate ? 2.0 : 1.0);
+  if (g.epi.resid) bytes += mn * nb * sizeof(T);
+  if (g.epi.gate) bytes += mn * nb * sizeof(T);
+  if (g.epi.relu_ref) bytes += mn * nb * sizeof(T);
+  EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW>), grid, dim3(256), 0, ctx.stream, g);
 }
 
 template <typename T>

@@ -3,6 +3,11 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "ops.h"
 
 namespace evo {
@@ -24,6 +29,45 @@ evo_status_t check_launch(const char* what) {
     return EVO_EHIP;
   }
   return EVO_OK;
+}
+
+// ============================================================== launch profiler
+namespace {
+struct ProfSlot {
+  const char* name;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfSlot> g_slots;
+std::vector<hipEvent_t> g_pool;
+hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+int prof_begin(const char* name, hipStream_t s, double flops, double bytes) {
+  if (!g_prof_on) return -1;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfSlot sl{name, pool_event(), pool_event(), flops, bytes};
+  if (!sl.a || !sl.b) return -1;
+  hipEventRecord(sl.a, s);
+  g_slots.push_back(sl);
+  return (int)g_slots.size() - 1;
+}
+
+void prof_end(int slot, hipStream_t s) {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEventRecord(g_slots[slot].b, s);
 }
 
 // ============================================================== weight gradients
@@ -82,7 +126,7 @@ template <typename T>
 evo_status_t rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* W, int H, float* out) {
   if (c.dry || rows == 0) return EVO_OK;
   if (H > 16) { set_error("pair bias: %d heads > 16", H); return EVO_ESHAPE; }
-  hipLaunchKernelGGL((rowproj_kernel<T>), dim3((unsigned)((rows + 255) / 256)), dim3(256),
+  EVO_LAUNCH(EVO_KNAME("rowproj_kernel", T), 2.0 * (double)rows * C * H, (double)rows * C * sizeof(T) + (double)H * rows * 4.0, (rowproj_kernel<T>), dim3((unsigned)((rows + 255) / 256)), dim3(256),
                      (size_t)C * H * sizeof(float), c.stream, x, rows, C, W, H, out);
   return check_launch("rowproj");
 }
@@ -138,11 +182,11 @@ evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int 
   if (H > 16 || C > 256 || 256 % C) { set_error("pair bias bwd: unsupported C=%d H=%d", C, H); return EVO_ESHAPE; }
   if (dx) {
     const int64_t n = rows * C;
-    hipLaunchKernelGGL(rowproj_dx_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+    EVO_LAUNCH("rowproj_dx_kernel", 2.0 * (double)rows * C * H, (double)rows * C * (accumulate ? 8.0 : 4.0) + (double)H * rows * 4.0, rowproj_dx_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                        rows, C, W, H, dout, dx, accumulate ? 1 : 0);
     EVO_TRY(check_launch("rowproj_dx"));
   }
-  hipLaunchKernelGGL((rowproj_dw_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, x, rows, C, H,
+  EVO_LAUNCH(EVO_KNAME("rowproj_dw_kernel", T), 2.0 * (double)rows * C * H, (double)rows * C * sizeof(T) + (double)H * rows * 4.0, (rowproj_dw_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, x, rows, C, H,
                      dout, part);
   EVO_TRY(check_launch("rowproj_dw"));
   return reduce_partials(c, part, nblk, (int64_t)C * H, (int64_t)C * H, dW, true);
@@ -177,3 +221,33 @@ EVO_INST_H(float)
 EVO_INST_H(bf16)
 
 }  // namespace evo
+
+extern "C" void evo_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(evo::g_prof_mu);
+  for (auto& sl : evo::g_slots) { evo::g_pool.push_back(sl.a); evo::g_pool.push_back(sl.b); }
+  evo::g_slots.clear();
+  evo::g_prof_on = true;
+}
+
+extern "C" int32_t evo_profile_end(evo_kernel_stat_t* rec, int32_t max_records) {
+  std::lock_guard<std::mutex> lk(evo::g_prof_mu);
+  evo::g_prof_on = false;
+  struct Agg { int64_t n = 0; double ms = 0, flops = 0, bytes = 0; };
+  std::map<std::string, Agg> agg;
+  for (auto& sl : evo::g_slots) {
+    if (hipEventSynchronize(sl.b) != hipSuccess) { evo::set_error("profile: event wait failed"); return -1; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sl.a, sl.b) != hipSuccess) { evo::set_error("profile: elapsed failed"); return -1; }
+    Agg& a = agg[sl.name];
+    a.n += 1; a.ms += ms; a.flops += sl.flops; a.bytes += sl.bytes;
+  }
+  int32_t k = 0;
+  for (auto& kv : agg) {
+    if (k >= max_records) break;
+    evo_kernel_stat_t& r = rec[k++];
+    memset(&r, 0, sizeof(r));
+    strncpy(r.name, kv.first.c_str(), sizeof(r.name) - 1);
+    r.launches = kv.second.n; r.total_ms = kv.second.ms; r.flops = kv.second.flops; r.bytes = kv.second.bytes;
+  }
+  return k;
+}

@@ -49,10 +49,10 @@ evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* 
                     float eps, T* y, float* mean, float* rstd) {
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)((rows + 3) / 4));
-  if (C <= 64) hipLaunchKernelGGL((ln_fwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
-  else if (C <= 128) hipLaunchKernelGGL((ln_fwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
-  else if (C <= 256) hipLaunchKernelGGL((ln_fwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
-  else if (C <= 1024) hipLaunchKernelGGL((ln_fwd_kernel<T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  else if (C <= 1024) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
   else { set_error("layernorm: C=%d > 1024", C); return EVO_ESHAPE; }
   return check_launch("ln_fwd");
 }
@@ -97,7 +97,7 @@ evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* 
   if (c.dry || P == 0) return EVO_OK;
   if (C > 512) { set_error("layernorm(cm): C=%d > 512", C); return EVO_ESHAPE; }
   size_t lds = (size_t)C * 65 * sizeof(float);
-  hipLaunchKernelGGL((ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
+  EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_kernel", T), 0.0, (double)P * C * 2 * sizeof(T) + P * 8.0, (ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
                      x, P, C, g, b, eps, y, mean, rstd);
   return check_launch("ln_fwd_cm");
 }
@@ -175,10 +175,10 @@ evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rs
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)*nblk);
   const int acc = accumulate ? 1 : 0;
-  if (C <= 64) hipLaunchKernelGGL((ln_bwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
-  else if (C <= 128) hipLaunchKernelGGL((ln_bwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
-  else if (C <= 256) hipLaunchKernelGGL((ln_bwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
-  else if (C <= 512) hipLaunchKernelGGL((ln_bwd_kernel<T, 8>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else if (C <= 512) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 8>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
   else { set_error("layernorm bwd: C=%d > 512", C); return EVO_ESHAPE; }
   return check_launch("ln_bwd");
 }
@@ -249,7 +249,7 @@ evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float*
   if (c.dry || P == 0) return EVO_OK;
   if (C > 256) { set_error("layernorm bwd(cm): C=%d > 256", C); return EVO_ESHAPE; }
   size_t lds = ((size_t)C * 65 + 8 * C) * sizeof(float);
-  hipLaunchKernelGGL((ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
+  EVO_LAUNCH(EVO_KNAME("ln_bwd_cm_kernel", T), 0.0, (double)P * C * (2 * sizeof(T) + 4.0) + P * 8.0, (ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
                      rstd, g, dy, P, C, dx, part);
   return check_launch("ln_bwd_cm");
 }
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
 evo_status_t reduce_partials(const Ctx& c, const float* part, int64_t n, int64_t C, int64_t ld,
                              float* out, bool accumulate) {
   if (c.dry || C == 0) return EVO_OK;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
+  EVO_LAUNCH("reduce_partials_kernel", 0.0, ((double)n + 1) * C * 4.0, reduce_partials_kernel, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
                      part, n, C, ld, out, accumulate ? 1 : 0);
   return check_launch("reduce_partials");
 }
@@ -299,7 +299,7 @@ evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64
                             int* nblk) {
   *nblk = (int)colsum_partials(rows);
   if (c.dry || rows == 0) return EVO_OK;
-  hipLaunchKernelGGL((colsum_kernel<T>), dim3((unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
+  EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>), dim3((unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
   return check_launch("colsum");
 }
 
@@ -334,7 +334,7 @@ evo_status_t pack_params(const Ctx& c, const PackArgs& a) {
     ntot += a.seg[s].n;
   }
   const int64_t n = (int64_t)a.K * ntot;
-  hipLaunchKernelGGL((pack_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, ntot);
+  EVO_LAUNCH(EVO_KNAME("pack_kernel", T), 0.0, (double)n * (4.0 + sizeof(T) * ((a.dst ? 1 : 0) + (a.dst_t ? 1 : 0))), (pack_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, ntot);
   return check_launch("pack_params");
 }
 
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(T* p, int64_t n) {
 template <typename T>
 evo_status_t fill_zero(const Ctx& c, T* p, int64_t n) {
   if (c.dry || n == 0) return EVO_OK;
-  hipLaunchKernelGGL((fill_zero_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, p, n);
+  EVO_LAUNCH(EVO_KNAME("fill_zero_kernel", T), 0.0, (double)n * sizeof(T), (fill_zero_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, p, n);
   return check_launch("fill_zero");
 }
 
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const T* __restrict__ s, T* _
 template <typename T>
 evo_status_t copy_elems(const Ctx& c, const T* src, T* dst, int64_t n) {
   if (c.dry || n == 0 || src == dst) return EVO_OK;
-  hipLaunchKernelGGL((copy_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
+  EVO_LAUNCH(EVO_KNAME("copy_kernel", T), 0.0, (double)n * 2 * sizeof(T), (copy_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
   return check_launch("copy");
 }
 
@@ -396,7 +396,7 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, i
                       T* dgpre, int64_t ld_dg, float* D) {
   if (c.dry || rows == 0) return EVO_OK;
   const int64_t n = rows * H * hd;
-  hipLaunchKernelGGL((gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+  EVO_LAUNCH(EVO_KNAME("gate_bwd_kernel", T), 0.0, (double)n * 5 * sizeof(T) + rows * H * 4.0, (gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                      rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
   return check_launch("gate_bwd");
 }
@@ -452,10 +452,10 @@ evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, 
                          T* a, T* b, T* g) {
   if (c.dry || P == 0) return EVO_OK;
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
-  hipLaunchKernelGGL((trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b);
+  EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * 6 * sizeof(T), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b);
   EVO_TRY(check_launch("trimul_proj"));
   const int64_t n = P * cz;
-  hipLaunchKernelGGL((sigmoid_cols_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+  EVO_LAUNCH(EVO_KNAME("sigmoid_cols_kernel", T), 0.0, (double)n * 2 * sizeof(T), (sigmoid_cols_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                      P, ch, cz, raw, g);
   return check_launch("trimul_gate");
 }
@@ -501,7 +501,7 @@ evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* r
                              const float* mask, const T* da, const T* db, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
-  hipLaunchKernelGGL((trimul_proj_bwd_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, da, db, draw);
+  EVO_LAUNCH(EVO_KNAME("trimul_proj_bwd_kernel", T), 0.0, (double)P * ch * 10 * sizeof(T), (trimul_proj_bwd_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, da, db, draw);
   return check_launch("trimul_proj_bwd");
 }
 
@@ -522,7 +522,7 @@ evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* d
                              const T* g, T* dt, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   const int64_t n = P * cz;
-  hipLaunchKernelGGL((trimul_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+  EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", T), 0.0, (double)n * 5 * sizeof(T), (trimul_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      c.stream, P, ch, cz, dz, t, g, dt, draw);
   return check_launch("trimul_gate_bwd");
 }
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void opm_norm_kernel(const float* mask, int64_
 evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, float eps, float* scale) {
   if (c.dry) return EVO_OK;
   const int64_t n = R * R;
-  hipLaunchKernelGGL(opm_norm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, mask, S,
+  EVO_LAUNCH("opm_norm_kernel", 2.0 * (double)S * R * R, (double)R * R * 4.0 + (mask ? (double)S * R * 4.0 : 0.0), opm_norm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, mask, S,
                      R, eps, scale);
   return check_launch("opm_norm");
 }
