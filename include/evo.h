@@ -103,7 +103,9 @@ typedef struct {
   int32_t head_dim;   /* 8, 16, 32 or 64 */
   float ln_eps;
   float global_eps;   /* COL_GLOBAL only */
-  int64_t chunk;      /* TRI kinds, forward without saved: query rows per chunk (0 = all) */
+  int64_t chunk;      /* TRI kinds, forward without saved: batch rows per chunk (0 = all); a
+                         power of two dividing n_inner: starting node chunks rows i, ending node
+                         columns j */
 } evo_attn_desc_t;
 
 /* Parameter (or parameter-gradient) pointers, FP32, Linear weights [fan_in, fan_out]. */
@@ -163,6 +165,7 @@ typedef struct {
   int32_t dtype;
   int64_t n_seq, n_res, c_m, c_hidden, c_z;
   float ln_eps, opm_eps;
+  int64_t chunk;      /* forward without saved: output rows i per chunk (0 = all) */
 } evo_opm_desc_t;
 
 typedef struct { float *ln_g, *ln_b, *w_a, *b_a, *w_b, *b_b, *w_o, *b_o; } evo_opm_w_t;
@@ -191,7 +194,8 @@ typedef struct {
   int32_t dir;        /* evo_tri_dir_t */
   int64_t n_res, c_z, c_hidden;
   float ln_eps;
-  int64_t chunk;      /* forward without saved: output rows per chunk (0 = all) */
+  int64_t chunk;      /* forward without saved: output rows i per chunk (0 = all); a power of
+                         two dividing n_res */
 } evo_trimul_desc_t;
 
 typedef struct {
@@ -227,7 +231,11 @@ typedef struct {
   int64_t n_seq, n_res, c_m, c_z;
   int32_t msa_heads, msa_head_dim, tri_heads, tri_head_dim;
   int64_t tri_mul_hidden, opm_hidden, transition_factor;
-  int64_t chunk;              /* forward only: pair-stack query-row chunk (0 = none) */
+  int64_t chunk;              /* forward only: row chunk of the outer product mean, triangle
+                                 multiplication and triangle attention (0 = none; else a power
+                                 of two dividing n_res).  Chunked results equal unchunked ones
+                                 (paper, Section "Subbatch VS DAP": the split axis is
+                                 independent). */
   float ln_eps, opm_eps, global_eps;
 } evo_block_desc_t;
 

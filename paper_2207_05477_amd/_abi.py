@@ -42,7 +42,8 @@ class TransW(ctypes.Structure):
 
 class OpmDesc(ctypes.Structure):
     _fields_ = [("dtype", c_int32), ("n_seq", c_int64), ("n_res", c_int64), ("c_m", c_int64),
-                ("c_hidden", c_int64), ("c_z", c_int64), ("ln_eps", c_float), ("opm_eps", c_float)]
+                ("c_hidden", c_int64), ("c_z", c_int64), ("ln_eps", c_float), ("opm_eps", c_float),
+                ("chunk", c_int64)]
 
 
 class OpmW(ctypes.Structure):

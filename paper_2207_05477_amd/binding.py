@@ -151,11 +151,11 @@ def trans_desc(dtype: str, rows: int, c: int, factor: int = 4, ln_eps: float = 1
 
 
 def opm_desc(dtype: str, n_seq: int, n_res: int, c_m: int, c_hidden: int, c_z: int,
-             ln_eps: float = 1e-5, opm_eps: float = 1e-3):
+             ln_eps: float = 1e-5, opm_eps: float = 1e-3, chunk: int = 0):
     d = A.OpmDesc()
     d.dtype = DTYPES[dtype][0]
     d.n_seq, d.n_res, d.c_m, d.c_hidden, d.c_z = n_seq, n_res, c_m, c_hidden, c_z
-    d.ln_eps, d.opm_eps = ln_eps, opm_eps
+    d.ln_eps, d.opm_eps, d.chunk = ln_eps, opm_eps, chunk
     return d
 
 

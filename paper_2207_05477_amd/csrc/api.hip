@@ -33,6 +33,9 @@ evo_status_t check_attn_desc(const evo_attn_desc_t* d) {
     REQ(d->c_in <= 256 && 256 % d->c_in == 0, EVO_ESHAPE, "triangle attention: c_in must divide 256");
   }
   REQ(d->chunk >= 0, EVO_EINVAL, "attention: negative chunk");
+  if (d->chunk > 0 && d->chunk < d->n_inner && (d->kind == EVO_ATTN_TRI_START || d->kind == EVO_ATTN_TRI_END))
+    REQ(is_pow2(d->chunk) && d->chunk >= 8 && d->n_inner % d->chunk == 0, EVO_ESHAPE,
+        "attention: chunk %lld must be a power of two >= 8 dividing n_inner", (long long)d->chunk);
   return EVO_OK;
 }
 
@@ -50,6 +53,9 @@ evo_status_t check_opm_desc(const evo_opm_desc_t* d) {
       "outer product mean: bad shape");
   REQ(is_pow2(d->c_hidden) && d->c_hidden >= 8 && d->c_hidden <= 64, EVO_ESHAPE,
       "outer product mean: c_hidden %lld must be a power of two in [8, 64]", (long long)d->c_hidden);
+  REQ(d->chunk >= 0, EVO_EINVAL, "outer product mean: negative chunk");
+  if (d->chunk > 0 && d->chunk < d->n_res)
+    REQ(d->n_res % d->chunk == 0, EVO_ESHAPE, "outer product mean: chunk must divide n_res");
   return EVO_OK;
 }
 
@@ -60,6 +66,9 @@ evo_status_t check_trimul_desc(const evo_trimul_desc_t* d) {
   REQ(mult8(d->n_res) && mult8(d->c_z) && mult8(d->c_hidden) && d->c_z <= 512 && d->c_hidden <= 256,
       EVO_ESHAPE, "triangle multiplication: bad shape");
   REQ(d->chunk >= 0, EVO_EINVAL, "triangle multiplication: negative chunk");
+  if (d->chunk > 0 && d->chunk < d->n_res)
+    REQ(is_pow2(d->chunk) && d->chunk >= 8 && d->n_res % d->chunk == 0, EVO_ESHAPE,
+        "triangle multiplication: chunk %lld must be a power of two >= 8 dividing n_res", (long long)d->chunk);
   return EVO_OK;
 }
 
@@ -336,6 +345,7 @@ evo_status_t opm_fwd(const evo_opm_desc_t* d, const evo_opm_w_t* w, const void* 
   EVO_TRY(check_opm_desc(d));
   EVO_TRY(weights_ok(w));
   EVO_TRY(ptrs_ok({m, z_in, z_out}, {msa_mask, saved}));
+  REQ(!(saved && d->chunk > 0), EVO_EINVAL, "outer product mean: chunked forward keeps no saved state");
   const size_t need_sv = opm_saved_bytes(d);
   return run_checked(stream, ws, ws_bytes, [&](const Ctx& c, Arena& a) -> evo_status_t {
     Arena sv = live_arena(saved, need_sv);

@@ -42,6 +42,7 @@ evo_opm_desc_t block_opm_desc(const evo_block_desc_t& b) {
   d.dtype = b.dtype;
   d.n_seq = b.n_seq; d.n_res = b.n_res; d.c_m = b.c_m; d.c_hidden = b.opm_hidden; d.c_z = b.c_z;
   d.ln_eps = b.ln_eps; d.opm_eps = b.opm_eps;
+  d.chunk = b.chunk;
   return d;
 }
 
@@ -107,7 +108,8 @@ evo_status_t block_bwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, co
   evo_attn_desc_t d_tas = block_attn_desc(d, EVO_ATTN_TRI_START), d_tae = block_attn_desc(d, EVO_ATTN_TRI_END);
   d_tas.chunk = 0; d_tae.chunk = 0;
   const evo_trans_desc_t d_tm = block_trans_desc(d, true), d_tz = block_trans_desc(d, false);
-  const evo_opm_desc_t d_opm = block_opm_desc(d);
+  evo_opm_desc_t d_opm = block_opm_desc(d);
+  d_opm.chunk = 0;
   evo_trimul_desc_t d_mo = block_trimul_desc(d, EVO_TRI_OUT), d_mi = block_trimul_desc(d, EVO_TRI_IN);
   d_mo.chunk = 0; d_mi.chunk = 0;
 

@@ -78,13 +78,15 @@ EVO_DEV void epilogue_apply(const GemmEpilogue& e, int z, int64_t m, int64_t n, 
   if (e.act == ACT_RELU) v = fmaxf(v, 0.0f);
   else if (e.act == ACT_SIGMOID && n >= e.act_n0) v = sigmoidf_(v);
   const int64_t zo = (int64_t)z * e.batch;
+  int64_t off = zo + addr2(m, e.m_lo, e.m_hi, e.m_shift) + addr2(n, e.n_lo, e.n_hi, e.n_shift);
+  // auxiliary inputs: own plain strides, or the output's addressing when the m-stride is < 0
+  const int64_t roff = e.r_m < 0 ? off : zo + m * e.r_m + n * e.r_n;
   if (e.relu_ref) {
-    float r = to_f32(((const T*)e.relu_ref)[zo + m * e.r_m + n * e.r_n]);
+    float r = to_f32(((const T*)e.relu_ref)[roff]);
     v = r > 0.0f ? v : 0.0f;
   }
-  if (e.gate) v *= to_f32(((const T*)e.gate)[zo + m * e.g_m + n * e.g_n]);
-  if (e.resid) v += to_f32(((const T*)e.resid)[zo + m * e.r_m + n * e.r_n]);
-  int64_t off = zo + addr2(m, e.m_lo, e.m_hi, e.m_shift) + addr2(n, e.n_lo, e.n_hi, e.n_shift);
+  if (e.gate) v *= to_f32(((const T*)e.gate)[e.g_m < 0 ? off : zo + m * e.g_m + n * e.g_n]);
+  if (e.resid) v += to_f32(((const T*)e.resid)[roff]);
   if (e.out_f32) {
     float* o = (float*)e.out + off;
     *o = e.accumulate ? (*o + v) : v;

@@ -8,6 +8,15 @@ namespace evo {
 template <typename T>
 evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
                     float eps, T* y, float* mean, float* rstd);
+// Same with row r of x at x + ((r >> rshift) * rhi + (r & (2^rshift - 1)) * C)
+// (a chunk of rows of a larger matrix); y is dense.
+template <typename T>
+evo_status_t ln_fwd_rows(const Ctx& c, const T* x, int64_t rows, int C, int rshift, int64_t rhi,
+                         const float* g, const float* b, float eps, T* y, float* mean, float* rstd);
+// out[h][row] = sum_c LayerNorm(x)[row][c] W[c][h] without storing the LayerNorm output.
+template <typename T>
+evo_status_t ln_rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+                        float eps, const float* W, int H, float* out);
 // Channel-major input x[C][P] -> y[P][C].
 template <typename T>
 evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
@@ -69,9 +78,10 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, i
 
 // Triangle multiplication projections, forward: raw[p][4*ch + cz] (ap | ag | bp | bg | g)
 // -> a[c][p], b[c][p] (channel-major, masked, gated), g[p][cz] = sigmoid(raw g).
+// a and b have channel stride ld_ab (>= P; pointers may be offset into larger tensors).
 template <typename T>
 evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
-                         T* a, T* b, T* g);
+                         T* a, T* b, int64_t ld_ab, T* g);
 // Backward: da, db channel-major -> draw[p][4*ch] columns of ap, ag, bp, bg.
 template <typename T>
 evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,

@@ -10,11 +10,11 @@ __global__ __launch_bounds__(256) void ln_fwd_kernel(const T* __restrict__ x, in
                                                      const float* __restrict__ g,
                                                      const float* __restrict__ b, float eps,
                                                      T* __restrict__ y, float* __restrict__ mean,
-                                                     float* __restrict__ rstd) {
+                                                     float* __restrict__ rstd, int rshift, int64_t rhi) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  const T* xr = x + row * C;
+  const T* xr = x + (rshift < 0 ? row * C : (row >> rshift) * rhi + (row & ((1LL << rshift) - 1)) * C);
   float v[NV];
   float s = 0.f;
 #pragma unroll
@@ -45,16 +45,84 @@ __global__ __launch_bounds__(256) void ln_fwd_kernel(const T* __restrict__ x, in
 }
 
 template <typename T>
-evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
-                    float eps, T* y, float* mean, float* rstd) {
+evo_status_t ln_fwd_rows(const Ctx& c, const T* x, int64_t rows, int C, int rshift, int64_t rhi,
+                         const float* g, const float* b, float eps, T* y, float* mean, float* rstd) {
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)((rows + 3) / 4));
-  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
-  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
-  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
-  else if (C <= 1024) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, (double)rows * C * 2 * sizeof(T) + rows * 8.0, (ln_fwd_kernel<T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd);
+  const double bytes = (double)rows * C * 2 * sizeof(T) + rows * 8.0;
+  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else if (C <= 1024) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
   else { set_error("layernorm: C=%d > 1024", C); return EVO_ESHAPE; }
   return check_launch("ln_fwd");
+}
+
+template <typename T>
+evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+                    float eps, T* y, float* mean, float* rstd) {
+  return ln_fwd_rows<T>(c, x, rows, C, -1, 0, g, b, eps, y, mean, rstd);
+}
+
+// Fused LayerNorm + small projection (pair bias of the chunked forward): one
+// wave per row, FP32 statistics, H dot products reduced across the wave.
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void ln_rowproj_kernel(const T* __restrict__ x, int64_t rows, int C,
+                                                         const float* __restrict__ g,
+                                                         const float* __restrict__ b, float eps,
+                                                         const float* __restrict__ W, int H,
+                                                         float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const T* xr = x + row * C;
+  float v[NV];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int c = lane + 64 * i;
+    v[i] = c < C ? to_f32(xr[c]) : 0.f;
+    s += v[i];
+  }
+  const float mu = wave_sum(s) / (float)C;
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int c = lane + 64 * i;
+    const float d = c < C ? v[i] - mu : 0.f;
+    q += d * d;
+  }
+  const float rs = 1.0f / sqrtf(wave_sum(q) / (float)C + eps);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int c = lane + 64 * i;
+    // the projection reads the LayerNorm output in the storage precision
+    v[i] = c < C ? to_f32(from_f32<T>((v[i] - mu) * rs * g[c] + b[c])) : 0.f;
+  }
+  for (int h = 0; h < H; ++h) {
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int c = lane + 64 * i;
+      if (c < C) acc += v[i] * W[c * H + h];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) out[(int64_t)h * rows + row] = acc;
+  }
+}
+
+template <typename T>
+evo_status_t ln_rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+                        float eps, const float* W, int H, float* out) {
+  if (c.dry || rows == 0) return EVO_OK;
+  dim3 grid((unsigned)((rows + 3) / 4));
+  const double bytes = (double)rows * C * sizeof(T) + (double)rows * H * 4.0;
+  const double flops = 2.0 * rows * C * H;
+  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", T), flops, bytes, (ln_rowproj_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", T), flops, bytes, (ln_rowproj_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", T), flops, bytes, (ln_rowproj_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  else { set_error("layernorm projection: C=%d > 256", C); return EVO_ESHAPE; }
+  return check_launch("ln_rowproj");
 }
 
 // Channel-major forward: a block owns 64 positions; x tile [C][64] staged in LDS.
@@ -406,7 +474,7 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, i
 // row-major projection output and the channel-major operands move coalesced.
 template <typename T>
 __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int cz, const T* raw,
-                                                          const float* mask, T* a, T* b) {
+                                                          const float* mask, T* a, T* b, int64_t ld_ab) {
   __shared__ float ta[32][65], tb[32][65];
   const int tid = threadIdx.x;
   const int64_t p0 = (int64_t)blockIdx.x * 64;
@@ -432,8 +500,8 @@ __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int
     const int64_t p = p0 + pp;
     const int c = c0 + cc;
     if (p < P && c < ch) {
-      a[(int64_t)c * P + p] = from_f32<T>(ta[cc][pp]);
-      b[(int64_t)c * P + p] = from_f32<T>(tb[cc][pp]);
+      a[(int64_t)c * ld_ab + p] = from_f32<T>(ta[cc][pp]);
+      b[(int64_t)c * ld_ab + p] = from_f32<T>(tb[cc][pp]);
     }
   }
 }
@@ -449,10 +517,10 @@ __global__ __launch_bounds__(256) void sigmoid_cols_kernel(int64_t P, int ch, in
 
 template <typename T>
 evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
-                         T* a, T* b, T* g) {
+                         T* a, T* b, int64_t ld_ab, T* g) {
   if (c.dry || P == 0) return EVO_OK;
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
-  EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * 6 * sizeof(T), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b);
+  EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * 6 * sizeof(T), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
   EVO_TRY(check_launch("trimul_proj"));
   const int64_t n = P * cz;
   EVO_LAUNCH(EVO_KNAME("sigmoid_cols_kernel", T), 0.0, (double)n * 2 * sizeof(T), (sigmoid_cols_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
@@ -554,6 +622,10 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
 #define EVO_INST(T)                                                                                \
   template evo_status_t ln_fwd<T>(const Ctx&, const T*, int64_t, int, const float*, const float*,  \
                                   float, T*, float*, float*);                                      \
+  template evo_status_t ln_fwd_rows<T>(const Ctx&, const T*, int64_t, int, int, int64_t,            \
+                                       const float*, const float*, float, T*, float*, float*);     \
+  template evo_status_t ln_rowproj<T>(const Ctx&, const T*, int64_t, int, const float*,            \
+                                      const float*, float, const float*, int, float*);             \
   template evo_status_t ln_fwd_cm<T>(const Ctx&, const T*, int64_t, int, const float*,             \
                                      const float*, float, T*, float*, float*);                     \
   template evo_status_t ln_bwd<T>(const Ctx&, const T*, const float*, const float*, const float*,  \
@@ -569,7 +641,7 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const T*, int64_t, const T*,    \
                                     int64_t, const T*, int64_t, T*, int64_t, T*, int64_t, float*); \
   template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const T*, const float*, T*,  \
-                                       T*, T*);                                                    \
+                                       T*, int64_t, T*);                                           \
   template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const T*, const float*,  \
                                            const T*, const T*, T*);                                \
   template evo_status_t trimul_gate_bwd<T>(const Ctx&, int64_t, int, int, const T*, const T*,      \

@@ -42,12 +42,7 @@ struct AttnSaved {
     mean = a.take_n<float>(s.rows);
     rstd = a.take_n<float>(s.rows);
     yz = nullptr; zmean = zrstd = nullptr; bias = nullptr; gctx = nullptr;
-    if (s.row) {
-      yz = a.take_n<T>(s.ni * s.ni * s.cpair);
-      zmean = a.take_n<float>(s.ni * s.ni);
-      zrstd = a.take_n<float>(s.ni * s.ni);
-      bias = a.take_n<float>((int64_t)s.H * s.ni * s.ni);
-    }
+    if (s.row) bias = a.take_n<float>((int64_t)s.H * s.ni * s.ni);
     if (s.tri) bias = a.take_n<float>((int64_t)s.H * s.rows);
     qkvg = a.take_n<T>(s.rows * s.NQ);
     if (s.global) {
@@ -110,10 +105,99 @@ evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int
                        const float* mask, float eps, const float* gctx, const float* smax,
                        const float* sinv, const T* dgo, T* dqkvg);
 
+// Forward of triangle attention in chunks of `chunk` batch rows (starting node:
+// rows i; ending node: columns j), keeping no saved state.  Only the chunk's
+// LayerNorm / projection / context buffers exist; the pair bias (all rows) is
+// formed once.  Equal to the unchunked forward (same per-row arithmetic).
+template <typename T>
+static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn_desc_t& d,
+                                         const AttnShape& s, const evo_attn_w_t& w, const T* x,
+                                         const float* mask, T* out) {
+  const int64_t R = s.ni, C = d.chunk, CR = C * R, cin = s.cin;
+  const int sh = ilog2(C);
+  const bool start = s.kind == EVO_ATTN_TRI_START;
+  T* wt_qkvg = ws.take_n<T>((int64_t)s.NQ * cin);
+  float* b_qkvg = ws.take_n<float>(s.NQ);
+  T* wt_o = ws.take_n<T>(cin * s.HC);
+  float* bias = ws.take_n<float>((int64_t)s.H * R * R);
+  T* y = ws.take_n<T>(CR * cin);
+  float* mean = ws.take_n<float>(CR);
+  float* rstd = ws.take_n<float>(CR);
+  T* qkvg = ws.take_n<T>(CR * s.NQ);
+  T* o = ws.take_n<T>(CR * s.HC);
+  T* go = ws.take_n<T>(CR * s.HC);
+  if (c.dry) return EVO_OK;
+  PackArgs pk;
+  pk.K = (int)cin;
+  pk.seg[0] = {w.w_q, nullptr, s.HC};
+  pk.seg[1] = {w.w_k, nullptr, s.HC};
+  pk.seg[2] = {w.w_v, nullptr, s.HC};
+  pk.seg[3] = {w.w_g, w.b_g, s.HC};
+  pk.nseg = 4;
+  pk.dst_t = wt_qkvg;
+  pk.bias = b_qkvg;
+  EVO_TRY(pack_params<T>(c, pk));
+  PackArgs po;
+  po.K = s.HC;
+  po.seg[0] = {w.w_o, nullptr, (int)cin};
+  po.nseg = 1;
+  po.dst_t = wt_o;
+  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(ln_rowproj<T>(c, x, R * R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias));
+  for (int64_t c0 = 0; c0 < R; c0 += C) {
+    // chunk rows: starting node (i, j) = (c0 + ii, j) contiguous; ending node
+    // (i, j) = (i, c0 + jj) with local row i*C + jj
+    const T* xs = start ? x + c0 * R * cin : x + c0 * cin;
+    EVO_TRY(ln_fwd_rows<T>(c, xs, CR, (int)cin, start ? -1 : sh, R * cin, w.ln_g, w.ln_b, d.ln_eps, y,
+                           mean, rstd));
+    GemmArgs g;
+    g.M = CR; g.N = s.NQ; g.K = cin;
+    g.A = op_rowmajor(y, cin);
+    g.B = op_rowmajor(wt_qkvg, cin);
+    g.epi = epi_rowmajor(qkvg, s.NQ, false);
+    g.epi.bias = b_qkvg;
+    g.epi.act = ACT_SIGMOID;
+    g.epi.act_n0 = s.NQ - s.HC;
+    EVO_TRY(gemm<T>(c, g));
+    AttnCore a;
+    a.H = s.H; a.D = s.D; a.o = o; a.go = go; a.bias = bias; a.bh = R * R;
+    a.nbatch = C; a.Lq = a.Lk = R;
+    if (start) {
+      a.sb = R * s.NQ; a.sp = s.NQ; a.osb = R * s.HC; a.osp = s.HC;
+      a.mask = mask ? mask + c0 * R : nullptr; a.mb = R; a.mk = 1;
+      a.bq = R; a.bk = 1;
+    } else {
+      a.sb = s.NQ; a.sp = C * s.NQ; a.osb = s.HC; a.osp = C * s.HC;
+      a.mask = mask ? mask + c0 : nullptr; a.mb = 1; a.mk = R;
+      a.bq = 1; a.bk = R;
+    }
+    set_qkvg<T>(a, qkvg, s);
+    EVO_TRY(attn_fwd<T>(c, a));
+    GemmArgs go_;
+    go_.M = CR; go_.N = cin; go_.K = s.HC;
+    go_.A = op_rowmajor(go, s.HC);
+    go_.B = op_rowmajor(wt_o, s.HC);
+    go_.epi.out_f32 = 0;
+    go_.epi.bias = w.b_o;
+    go_.epi.r_m = -1;   // residual addressed like the output
+    if (start) {
+      go_.epi.out = out + c0 * R * cin; go_.epi.m_lo = cin; go_.epi.n_lo = 1;
+      go_.epi.resid = x + c0 * R * cin;
+    } else {
+      go_.epi.out = out + c0 * cin; go_.epi.m_lo = cin; go_.epi.m_hi = R * cin; go_.epi.m_shift = sh;
+      go_.epi.n_lo = 1;
+      go_.epi.resid = x + c0 * cin;
+    }
+    EVO_TRY(gemm<T>(c, go_));
+  }
+  return EVO_OK;
+}
+
 template <typename T>
 evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
                          const evo_attn_w_t& w, const T* x, const T* pair, const float* mask, T* out) {
   const AttnShape s = attn_shape(d);
+  if (s.tri && d.chunk > 0 && d.chunk < s.ni) return attn_fwd_tri_chunked<T>(c, ws, d, s, w, x, mask, out);
   AttnSaved<T> S;
   S.carve(sv, s);
   T* wt_qkvg = ws.take_n<T>((int64_t)s.NQ * s.cin);
@@ -152,11 +236,10 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY(gemm<T>(c, g));
   }
   if (s.row) {
-    const int64_t P = s.ni * s.ni;
-    EVO_TRY(ln_fwd<T>(c, pair, P, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, S.yz, S.zmean, S.zrstd));
-    EVO_TRY(rowproj<T>(c, S.yz, P, (int)s.cpair, w.w_bias, s.H, S.bias));
+    EVO_TRY(ln_rowproj<T>(c, pair, s.ni * s.ni, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, w.w_bias, s.H,
+                          S.bias));
   } else if (s.tri) {
-    EVO_TRY(rowproj<T>(c, S.y, s.rows, (int)s.cin, w.w_bias, s.H, S.bias));
+    EVO_TRY(ln_rowproj<T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, S.bias));
   }
   if (s.global) {
     EVO_TRY(gattn_fwd<T>(c, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
@@ -280,7 +363,12 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   }
   // pair bias
   if (s.row) {
+    // the pair LayerNorm output is recomputed here (the forward projects it without storing it)
     const int64_t P = s.ni * s.ni;
+    S.yz = ws.take_n<T>(P * s.cpair);
+    S.zmean = ws.take_n<float>(P);
+    S.zrstd = ws.take_n<float>(P);
+    EVO_TRY(ln_fwd<T>(c, pair, P, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, S.yz, S.zmean, S.zrstd));
     float* dyz = ws.take_n<float>(P * s.cpair);
     EVO_TRY(rowproj_bwd<T>(c, ws, S.yz, P, (int)s.cpair, w.w_bias, s.H, dbias, dyz, false, dw.w_bias));
     float* part = ws.take_n<float>((size_t)ln_bwd_partials(P) * 2 * s.cpair);

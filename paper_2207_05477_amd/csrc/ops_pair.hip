@@ -114,7 +114,18 @@ template <typename T>
 evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
                         const evo_opm_w_t& w, const T* m, const float* mask, const T* zin, T* zout) {
   OpmSaved<T> S;
-  S.carve(sv, d);
+  const bool chunked = d.chunk > 0 && d.chunk < d.n_res;
+  if (chunked) {
+    // no saved state: the outer product exists only for `chunk` rows i at a time
+    S.y = ws.take_n<T>(d.n_seq * d.n_res * d.c_m);
+    S.mean = ws.take_n<float>(d.n_seq * d.n_res);
+    S.rstd = ws.take_n<float>(d.n_seq * d.n_res);
+    S.ab = ws.take_n<T>(d.n_seq * d.n_res * 2 * d.c_hidden);
+    S.on = ws.take_n<T>(d.chunk * d.n_res * d.c_hidden * d.c_hidden);
+    S.scale = ws.take_n<float>(d.n_res * d.n_res);
+  } else {
+    S.carve(sv, d);
+  }
   const int64_t S_ = d.n_seq, R = d.n_res, SR = S_ * R, RR = R * R, ch = d.c_hidden, cm = d.c_m,
                 cz = d.c_z, ch2 = ch * ch;
   const int sh = ilog2(ch);
@@ -139,25 +150,30 @@ evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
     EVO_TRY(gemm<T>(c, g));
   }
   EVO_TRY(opm_norm(c, mask, S_, R, d.opm_eps, S.scale));
-  {  // On[i][j][p][q] = sum_s a[s][i][p] b[s][j][q] / (eps + n_ij)
+  const int64_t C = chunked ? d.chunk : R;
+  for (int64_t i0 = 0; i0 < R; i0 += C) {
+    {  // On[i][j][p][q] = sum_s a[s][i][p] b[s][j][q] / (eps + n_ij), rows i of this chunk
+      GemmArgs g;
+      g.M = C * ch; g.N = R * ch; g.K = S_;
+      g.A.ptr = S.ab + i0 * 2 * ch; g.A.r_lo = 1; g.A.r_hi = 2 * ch; g.A.r_shift = sh;
+      g.A.k_lo = R * 2 * ch; g.A.k_contig = 0;
+      g.B = g.A; g.B.ptr = S.ab + ch;
+      g.epi.out = S.on; g.epi.out_f32 = 0;
+      g.epi.m_lo = ch; g.epi.m_hi = R * ch2; g.epi.m_shift = sh;
+      g.epi.n_lo = 1; g.epi.n_hi = ch2; g.epi.n_shift = sh;
+      g.epi.scale = S.scale + i0 * R; g.epi.sm_shift = sh; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1;
+      EVO_TRY(gemm<T>(c, g));
+    }
     GemmArgs g;
-    g.M = R * ch; g.N = R * ch; g.K = S_;
-    g.A.ptr = S.ab; g.A.r_lo = 1; g.A.r_hi = 2 * ch; g.A.r_shift = sh; g.A.k_lo = R * 2 * ch; g.A.k_contig = 0;
-    g.B = g.A; g.B.ptr = S.ab + ch;
-    g.epi.out = S.on; g.epi.out_f32 = 0;
-    g.epi.m_lo = ch; g.epi.m_hi = R * ch2; g.epi.m_shift = sh;
-    g.epi.n_lo = 1; g.epi.n_hi = ch2; g.epi.n_shift = sh;
-    g.epi.scale = S.scale; g.epi.sm_shift = sh; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1;
+    g.M = C * R; g.N = cz; g.K = ch2;
+    g.A = op_rowmajor(S.on, ch2);
+    g.B = op_rowmajor(wt_o, ch2);
+    g.epi = epi_rowmajor(zout + i0 * R * cz, cz, false);
+    g.epi.bias = w.b_o;
+    g.epi.resid = zin + i0 * R * cz; g.epi.r_m = cz; g.epi.r_n = 1;
     EVO_TRY(gemm<T>(c, g));
   }
-  GemmArgs g;
-  g.M = RR; g.N = cz; g.K = ch2;
-  g.A = op_rowmajor(S.on, ch2);
-  g.B = op_rowmajor(wt_o, ch2);
-  g.epi = epi_rowmajor(zout, cz, false);
-  g.epi.bias = w.b_o;
-  g.epi.resid = zin; g.epi.r_m = cz; g.epi.r_n = 1;
-  return gemm<T>(c, g);
+  return EVO_OK;
 }
 
 template <typename T>
@@ -262,9 +278,89 @@ struct TriSaved {
   }
 };
 
+// Forward in chunks of `chunk` output rows i, keeping no saved state: the
+// projections run over row chunks into the full channel-major a, b and the
+// gate g; contraction, output LayerNorm and output projection then run per
+// chunk of output rows (x_ij for i in the chunk needs a's rows i and all of b).
+template <typename T>
+static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul_desc_t& d,
+                                       const evo_trimul_w_t& w, const T* z, const float* mask, T* zout) {
+  const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz, C = d.chunk,
+                CR = C * R;
+  T* wt_p = ws.take_n<T>(NP * cz);
+  float* b_p = ws.take_n<float>(NP);
+  T* wt_o = ws.take_n<T>(cz * ch);
+  T* a = ws.take_n<T>(P * ch);
+  T* b = ws.take_n<T>(P * ch);
+  T* g = ws.take_n<T>(P * cz);
+  T* y = ws.take_n<T>(CR * cz);
+  float* mean = ws.take_n<float>(CR);
+  float* rstd = ws.take_n<float>(CR);
+  T* raw = ws.take_n<T>(CR * NP);
+  T* x = ws.take_n<T>(CR * ch);
+  T* xn = ws.take_n<T>(CR * ch);
+  if (c.dry) return EVO_OK;
+  PackArgs pp;
+  pp.K = (int)cz;
+  pp.seg[0] = {w.w_ap, w.b_ap, (int)ch};
+  pp.seg[1] = {w.w_ag, w.b_ag, (int)ch};
+  pp.seg[2] = {w.w_bp, w.b_bp, (int)ch};
+  pp.seg[3] = {w.w_bg, w.b_bg, (int)ch};
+  pp.seg[4] = {w.w_g, w.b_g, (int)cz};
+  pp.nseg = 5;
+  pp.dst_t = wt_p;
+  pp.bias = b_p;
+  EVO_TRY(pack_params<T>(c, pp));
+  PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
+  EVO_TRY(pack_params<T>(c, po));
+  for (int64_t c0 = 0; c0 < R; c0 += C) {
+    const int64_t p0 = c0 * R;
+    EVO_TRY(ln_fwd<T>(c, z + p0 * cz, CR, (int)cz, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd));
+    GemmArgs gp;
+    gp.M = CR; gp.N = NP; gp.K = cz;
+    gp.A = op_rowmajor(y, cz);
+    gp.B = op_rowmajor(wt_p, cz);
+    gp.epi = epi_rowmajor(raw, NP, false);
+    gp.epi.bias = b_p;
+    EVO_TRY(gemm<T>(c, gp));
+    EVO_TRY(trimul_proj<T>(c, CR, (int)ch, (int)cz, raw, mask ? mask + p0 : nullptr, a + p0, b + p0, P,
+                           g + p0 * cz));
+  }
+  float* mean2 = mean;
+  float* rstd2 = rstd;
+  for (int64_t c0 = 0; c0 < R; c0 += C) {
+    const int64_t p0 = c0 * R;
+    GemmArgs gx;
+    gx.M = C; gx.N = R; gx.K = R; gx.batch = (int)ch;
+    if (d.dir == EVO_TRI_OUT) {
+      gx.A = op_rowmajor(a + c0 * R, R);
+      gx.B = op_rowmajor(b, R);
+    } else {
+      gx.A = op_colmajor(a + c0, R);
+      gx.B = op_colmajor(b, R);
+    }
+    gx.A.batch = P; gx.B.batch = P;
+    gx.epi = epi_rowmajor(x, R, false);
+    gx.epi.batch = CR;
+    EVO_TRY(gemm<T>(c, gx));
+    EVO_TRY(ln_fwd_cm<T>(c, x, CR, (int)ch, w.ln_out_g, w.ln_out_b, d.ln_eps, xn, mean2, rstd2));
+    GemmArgs go;
+    go.M = CR; go.N = cz; go.K = ch;
+    go.A = op_rowmajor(xn, ch);
+    go.B = op_rowmajor(wt_o, ch);
+    go.epi = epi_rowmajor(zout + p0 * cz, cz, false);
+    go.epi.bias = w.b_o;
+    go.epi.gate = g + p0 * cz; go.epi.g_m = cz; go.epi.g_n = 1;
+    go.epi.resid = z + p0 * cz; go.epi.r_m = cz; go.epi.r_n = 1;
+    EVO_TRY(gemm<T>(c, go));
+  }
+  return EVO_OK;
+}
+
 template <typename T>
 evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
                            const evo_trimul_w_t& w, const T* z, const float* mask, T* zout) {
+  if (d.chunk > 0 && d.chunk < d.n_res) return trimul_fwd_chunked<T>(c, ws, d, w, z, mask, zout);
   TriSaved<T> S;
   S.carve(sv, d);
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
@@ -295,7 +391,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     g.epi.bias = b_p;
     EVO_TRY(gemm<T>(c, g));
   }
-  EVO_TRY(trimul_proj<T>(c, P, (int)ch, (int)cz, S.raw, mask, S.a, S.b, S.g));
+  EVO_TRY(trimul_proj<T>(c, P, (int)ch, (int)cz, S.raw, mask, S.a, S.b, P, S.g));
   {  // per-channel contraction, channel-major operands [ch][R][R]
     GemmArgs g;
     g.M = R; g.N = R; g.K = R; g.batch = (int)ch;
