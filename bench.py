@@ -132,6 +132,34 @@ def roofline_of(stats, dtype):
             "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms}
 
 
+KERNEL_SOURCES = {"gemm_kernel": "gemm.hip", "attn_": "attn.hip", "ln_": "misc.hip", "gattn_": "gattn.hip"}
+
+
+def kernel_source_hash(kernel_name: str):
+    import hashlib
+    for prefix, fname in KERNEL_SOURCES.items():
+        if kernel_name.startswith(prefix):
+            path = os.path.join(ROOT, "paper_2207_05477_amd", "csrc", fname)
+            with open(path, "rb") as f:
+                return hashlib.sha256(f.read()).hexdigest()[:16]
+    return None
+
+
+def recorded_traffic(kernel_name: str, launches_per_step: float):
+    """HBM bytes per launch of `kernel_name` from the committed counter summary
+    (profiles/traffic.json, FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of
+    known size); None when absent or when the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get("kernels", {}).get(kernel_name)
+    if not ent or ent.get("source_sha") != kernel_source_hash(kernel_name):
+        return None
+    return ent["bytes_per_launch"]
+
+
 def cpu_baseline(cfg, flops_step):
     """The FP64 oracle (as it stands) on the host cores: one block fwd+bwd of a
     bounded sample of the workload."""
@@ -156,6 +184,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--only", choices=["f32", "bf16"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -165,32 +196,45 @@ def main():
     from paper_2207_05477_amd import _abi as A
     A.load()
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written", file=sys.stderr)
+        del src, dst
     cfg = synth.get("C1")
     flops_step = 3.0 * block_flops(cfg)       # forward + backward (2x forward), algorithmic
 
-    inp, flat, w = make_workload(cfg, "f32", dev)
-    ms = time_steps(cfg, "f32", flat, w, args.steps, args.warmup)
-    stats = profile_steps(cfg, "f32", flat, w, args.profile_steps)
-    roof = roofline_of(stats, "f32")
-    roof["launches_per_step"] = stats[0]["launches"] / args.profile_steps
-    del w, flat, inp
+    ms, roof, stats = None, None, []
+    if args.only != "bf16":
+        inp, flat, w = make_workload(cfg, "f32", dev)
+        ms = time_steps(cfg, "f32", flat, w, args.steps, args.warmup)
+        print(f"f32 step {ms:.3f} ms", file=sys.stderr, flush=True)
+        stats = profile_steps(cfg, "f32", flat, w, args.profile_steps)
+        roof = roofline_of(stats, "f32")
+        roof["launches_per_step"] = stats[0]["launches"] / args.profile_steps
+        roof["traffic"] = recorded_traffic(roof["kernel"], roof["launches_per_step"])
+        del w, flat, inp
 
     bf16 = None
-    if not args.no_bf16:
+    if not args.no_bf16 and args.only != "f32":
         cfg16 = cfg.replace(dtype="bf16")
         inp, flat, w = make_workload(cfg16, "bf16", dev)
         ms16 = time_steps(cfg16, "bf16", flat, w, args.steps, args.warmup)
         st16 = profile_steps(cfg16, "bf16", flat, w, args.profile_steps)
         r16 = roofline_of(st16, "bf16")
         r16["launches_per_step"] = st16[0]["launches"] / args.profile_steps
+        r16["traffic"] = recorded_traffic(r16["kernel"], r16["launches_per_step"])
+        print(f"bf16 step {ms16:.3f} ms", file=sys.stderr, flush=True)
         bf16 = {"ms_per_step": ms16, "tflops": flops_step / (ms16 * 1e-3) / 1e12,
-                "speedup_vs_f32": ms / ms16, "roofline": r16,
+                "speedup_vs_f32": (ms / ms16) if ms else None, "roofline": r16,
                 "top_kernels": [{k: s[k] for k in ("name", "launches", "total_ms")} for s in st16[:8]]}
         del w, flat, inp
 
     out = {
         "metric": "Evoformer block fwd+bwd ms & TFLOP/s at N_res=256, BF16 vs FP32, % MFMA peak",
-        "value": flops_step / (ms * 1e-3) / 1e12,
+        "value": flops_step / (ms * 1e-3) / 1e12 if ms else None,
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
