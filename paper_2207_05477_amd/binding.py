@@ -106,6 +106,7 @@ class FlatParams:
         w = A.BlockW()
         for sub in BLOCK_SUBOPS:
             setattr(w, sub, self.substruct(sub, buffer))
+        w._keep = self.buffer if buffer is None else buffer
         return w
 
 
@@ -116,6 +117,7 @@ def weight_struct(sub: str, params: dict):
         if t.dtype != torch.float32:
             raise ValueError(f"{sub}.{name}: parameters are FP32")
         setattr(s, name, _ptr(t).value)
+    s._keep = dict(params)   # the struct holds raw pointers: keep the tensors alive with it
     return s
 
 

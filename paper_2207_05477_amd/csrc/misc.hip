@@ -323,6 +323,10 @@ evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float*
 }
 
 // ============================================================== reductions
+// Deterministic column reductions out[j] (+)= sum_{i<n} part[i*ld + j] in a
+// fixed order.  Wide problems: one thread per column.  Narrow, deep problems
+// (few columns, many partials): a block of 8 columns x 32 row groups, each
+// thread summing a strided subset of rows, then a fixed tree over the groups.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ part, int64_t n,
                                                               int64_t C, int64_t ld, float* out,
                                                               int accumulate) {
@@ -333,11 +337,38 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
   out[j] = accumulate ? out[j] + s : s;
 }
 
+constexpr int RN_COLS = 8, RN_ROWS = 32;
+
+__global__ __launch_bounds__(256) void reduce_partials_narrow_kernel(const float* __restrict__ part, int64_t n,
+                                                                     int64_t C, int64_t ld, float* out,
+                                                                     int accumulate) {
+  __shared__ float red[RN_ROWS][RN_COLS + 1];
+  const int tc = threadIdx.x % RN_COLS, tr = threadIdx.x / RN_COLS;
+  const int64_t j = (int64_t)blockIdx.x * RN_COLS + tc;
+  float s = 0.f;
+  if (j < C)
+    for (int64_t i = tr; i < n; i += RN_ROWS) s += part[i * ld + j];
+  red[tr][tc] = s;
+  __syncthreads();
+  for (int w = RN_ROWS / 2; w > 0; w >>= 1) {
+    if (tr < w) red[tr][tc] += red[tr + w][tc];
+    __syncthreads();
+  }
+  if (tr == 0 && j < C) out[j] = accumulate ? out[j] + red[0][tc] : red[0][tc];
+}
+
 evo_status_t reduce_partials(const Ctx& c, const float* part, int64_t n, int64_t C, int64_t ld,
                              float* out, bool accumulate) {
   if (c.dry || C == 0) return EVO_OK;
-  EVO_LAUNCH("reduce_partials_kernel", 0.0, ((double)n + 1) * C * 4.0, reduce_partials_kernel, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
-                     part, n, C, ld, out, accumulate ? 1 : 0);
+  const double bytes = ((double)n + 1) * C * 4.0;
+  if (C >= 65536 || n < 64) {
+    EVO_LAUNCH("reduce_partials_kernel", 0.0, bytes, reduce_partials_kernel, dim3((unsigned)((C + 255) / 256)),
+               dim3(256), 0, c.stream, part, n, C, ld, out, accumulate ? 1 : 0);
+  } else {
+    EVO_LAUNCH("reduce_partials_narrow_kernel", 0.0, bytes, reduce_partials_narrow_kernel,
+               dim3((unsigned)((C + RN_COLS - 1) / RN_COLS)), dim3(256), 0, c.stream, part, n, C, ld, out,
+               accumulate ? 1 : 0);
+  }
   return check_launch("reduce_partials");
 }
 
@@ -347,18 +378,36 @@ evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C,
   return reduce_partials(c, part + C, n, C, 2 * C, out_b, true);
 }
 
-constexpr int CS_ROWS = 128;
+// Column sums over blocks of CS_ROWS rows; all 256 threads work: thread t owns
+// column t % C (C <= 256) in row group t / C, or columns t, t + 256, ... (C > 256).
+constexpr int CS_ROWS = 256;
 int64_t colsum_partials(int64_t rows) { return (rows + CS_ROWS - 1) / CS_ROWS; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ x, int64_t rows, int C,
                                                      int64_t ld, float* __restrict__ part) {
+  __shared__ float red[256];
   const int64_t r0 = (int64_t)blockIdx.x * CS_ROWS;
   const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
-  for (int c = threadIdx.x; c < C; c += 256) {
+  if (C <= 256) {
+    const int groups = 256 / C;
+    const int cc = threadIdx.x % C, g = threadIdx.x / C;
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) s += to_f32(x[r * ld + c]);
-    part[(int64_t)blockIdx.x * C + c] = s;
+    if (g < groups)
+      for (int64_t r = r0 + g; r < r1; r += groups) s += to_f32(x[r * ld + cc]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+      float t = 0.f;
+      for (int q = 0; q < groups; ++q) t += red[q * C + threadIdx.x];
+      part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
+    }
+  } else {
+    for (int cc = threadIdx.x; cc < C; cc += 256) {
+      float s = 0.f;
+      for (int64_t r = r0; r < r1; ++r) s += to_f32(x[r * ld + cc]);
+      part[(int64_t)blockIdx.x * C + cc] = s;
+    }
   }
 }
 
@@ -367,7 +416,8 @@ evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64
                             int* nblk) {
   *nblk = (int)colsum_partials(rows);
   if (c.dry || rows == 0) return EVO_OK;
-  EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>), dim3((unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
+  EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>),
+             dim3((unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
   return check_launch("colsum");
 }
 

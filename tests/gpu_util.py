@@ -47,6 +47,7 @@ def check(name, got, ref, tol, report=None, floor=0.0):
     e = (got64 - ref64).norm().item() / max(ref64.norm().item(), floor, 1e-300)
     if report is not None:
         report[name] = e
+    say(f"    {name}: {e:.3e}")
     assert torch.isfinite(got.detach().float()).all(), f"{name}: non-finite values"
     assert e <= tol, f"{name}: normwise relative error {e:.3e} > {tol:.1e}"
     return e
@@ -75,3 +76,20 @@ def oracle_grads(fn, inputs: dict, upstream):
             d = d.setdefault(p, {})
         d[path[-1]] = t.grad if t.grad is not None else torch.zeros_like(t)
     return out.detach(), grads
+
+
+def kink_free(inp):
+    """The same inputs with the transitions' W_1 set to zero: every ReLU
+    pre-activation is then the bias alone, so every ReLU decision is exact in
+    any precision (the block's only discrete decisions).  All other sub-ops keep
+    their general parameters."""
+    for blk in inp["params"]:
+        for sub in ("msa_trans", "pair_trans"):
+            blk[sub]["w_1"] = torch.zeros_like(blk[sub]["w_1"])
+    return inp
+
+
+# Coarse gate for gradients of full-parameter blocks: ReLU kinks in the
+# transitions flip with the upstream rounding of the block's own forward, each
+# flip moving a whole gradient entry (see DESIGN.md, parity status).
+KINK_TOL = {"f32": 1e-3, "bf16": 0.15}

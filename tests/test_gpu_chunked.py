@@ -29,7 +29,8 @@ def test_chunked_op_equals_unchunked_and_oracle(dtype, op):
     cfg = CCFG
     inp = round_inputs(make_inputs(cfg, seed=11, perturb=True), dtype)
     p = inp["params"][0][op]
-    w = B.weight_struct(op, params_dev(p))
+    pd = params_dev(p)
+    w = B.weight_struct(op, pd)
     z, P = to_dev(inp["z"], dtype), inp["pair_mask"].float().cuda()
     outs = []
     for chunk in (0, 16):
