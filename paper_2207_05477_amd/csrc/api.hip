@@ -198,8 +198,8 @@ size_t evo_attn_saved_bytes(const evo_attn_desc_t* d) {
   Ctx c; c.dry = true;
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_attn_w_t w; memset(&w, 0, sizeof(w));
-  if (d->dtype == EVO_BF16) attn_fwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
-  else attn_fwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
+  if (d->dtype == EVO_BF16) attn_fwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
+  else attn_fwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
   return sv.off;
 }
 
@@ -209,11 +209,11 @@ size_t evo_attn_workspace_bytes(const evo_attn_desc_t* d, int32_t phase) {
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_attn_w_t w; memset(&w, 0, sizeof(w));
   if (phase == EVO_PHASE_FWD) {  // sized for saved == NULL: saved tensors live in the workspace
-    if (d->dtype == EVO_BF16) attn_fwd_op<bf16>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
-    else attn_fwd_op<float>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
+    if (d->dtype == EVO_BF16) attn_fwd_op<bf16, bf16>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
+    else attn_fwd_op<float, float>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
   } else {
-    if (d->dtype == EVO_BF16) attn_bwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w);
-    else attn_bwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w);
+    if (d->dtype == EVO_BF16) attn_bwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w);
+    else attn_bwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w);
   }
   return ws.off;
 }
@@ -231,8 +231,8 @@ evo_status_t evo_attn_fwd(const evo_attn_desc_t* d, const evo_attn_w_t* w, const
     if (saved && c.dry) { sv = Arena(); sv.dry = true; }
     Arena& svr = saved ? sv : a;
     if (d->dtype == EVO_BF16)
-      return attn_fwd_op<bf16>(c, a, svr, *d, *w, (const bf16*)x, (const bf16*)pair, mask, (bf16*)out);
-    return attn_fwd_op<float>(c, a, svr, *d, *w, (const float*)x, (const float*)pair, mask, (float*)out);
+      return attn_fwd_op<bf16, bf16>(c, a, svr, *d, *w, (const bf16*)x, (const bf16*)pair, mask, (bf16*)out);
+    return attn_fwd_op<float, float>(c, a, svr, *d, *w, (const float*)x, (const float*)pair, mask, (float*)out);
   });
 }
 
@@ -249,9 +249,9 @@ evo_status_t evo_attn_bwd(const evo_attn_desc_t* d, const evo_attn_w_t* w, const
     Arena sv = live_arena(const_cast<void*>(saved), need_sv);
     sv.dry = c.dry;
     if (d->dtype == EVO_BF16)
-      return attn_bwd_op<bf16>(c, a, sv, *d, *w, (const bf16*)x, (const bf16*)pair, mask, (const bf16*)d_out,
+      return attn_bwd_op<bf16, bf16>(c, a, sv, *d, *w, (const bf16*)x, (const bf16*)pair, mask, (const bf16*)d_out,
                                (bf16*)d_x, (bf16*)d_pair, *d_w);
-    return attn_bwd_op<float>(c, a, sv, *d, *w, (const float*)x, (const float*)pair, mask, (const float*)d_out,
+    return attn_bwd_op<float, float>(c, a, sv, *d, *w, (const float*)x, (const float*)pair, mask, (const float*)d_out,
                               (float*)d_x, (float*)d_pair, *d_w);
   });
 }
@@ -262,8 +262,8 @@ size_t evo_transition_saved_bytes(const evo_trans_desc_t* d) {
   Ctx c; c.dry = true;
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_trans_w_t w; memset(&w, 0, sizeof(w));
-  if (d->dtype == EVO_BF16) trans_fwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr);
-  else trans_fwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr);
+  if (d->dtype == EVO_BF16) trans_fwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr);
+  else trans_fwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr);
   return sv.off;
 }
 
@@ -273,11 +273,11 @@ size_t evo_transition_workspace_bytes(const evo_trans_desc_t* d, int32_t phase) 
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_trans_w_t w; memset(&w, 0, sizeof(w));
   if (phase == EVO_PHASE_FWD) {
-    if (d->dtype == EVO_BF16) trans_fwd_op<bf16>(c, ws, ws, *d, w, nullptr, nullptr);
-    else trans_fwd_op<float>(c, ws, ws, *d, w, nullptr, nullptr);
+    if (d->dtype == EVO_BF16) trans_fwd_op<bf16, bf16>(c, ws, ws, *d, w, nullptr, nullptr);
+    else trans_fwd_op<float, float>(c, ws, ws, *d, w, nullptr, nullptr);
   } else {
-    if (d->dtype == EVO_BF16) trans_bwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, w);
-    else trans_bwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, w);
+    if (d->dtype == EVO_BF16) trans_bwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, w);
+    else trans_bwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, w);
   }
   return ws.off;
 }
@@ -292,8 +292,8 @@ evo_status_t evo_transition_fwd(const evo_trans_desc_t* d, const evo_trans_w_t* 
     Arena sv = live_arena(saved, need_sv);
     sv.dry = c.dry;
     Arena& svr = saved ? sv : a;
-    if (d->dtype == EVO_BF16) return trans_fwd_op<bf16>(c, a, svr, *d, *w, (const bf16*)x, (bf16*)out);
-    return trans_fwd_op<float>(c, a, svr, *d, *w, (const float*)x, (float*)out);
+    if (d->dtype == EVO_BF16) return trans_fwd_op<bf16, bf16>(c, a, svr, *d, *w, (const bf16*)x, (bf16*)out);
+    return trans_fwd_op<float, float>(c, a, svr, *d, *w, (const float*)x, (float*)out);
   });
 }
 
@@ -309,8 +309,8 @@ evo_status_t evo_transition_bwd(const evo_trans_desc_t* d, const evo_trans_w_t* 
     Arena sv = live_arena(const_cast<void*>(saved), need_sv);
     sv.dry = c.dry;
     if (d->dtype == EVO_BF16)
-      return trans_bwd_op<bf16>(c, a, sv, *d, *w, (const bf16*)x, (const bf16*)d_out, (bf16*)d_x, *d_w);
-    return trans_bwd_op<float>(c, a, sv, *d, *w, (const float*)x, (const float*)d_out, (float*)d_x, *d_w);
+      return trans_bwd_op<bf16, bf16>(c, a, sv, *d, *w, (const bf16*)x, (const bf16*)d_out, (bf16*)d_x, *d_w);
+    return trans_bwd_op<float, float>(c, a, sv, *d, *w, (const float*)x, (const float*)d_out, (float*)d_x, *d_w);
   });
 }
 
@@ -320,8 +320,8 @@ size_t opm_saved_bytes(const evo_opm_desc_t* d) {
   Ctx c; c.dry = true;
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_opm_w_t w; memset(&w, 0, sizeof(w));
-  if (d->dtype == EVO_BF16) opm_fwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
-  else opm_fwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
+  if (d->dtype == EVO_BF16) opm_fwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
+  else opm_fwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr);
   return sv.off;
 }
 
@@ -331,11 +331,11 @@ size_t opm_workspace_bytes(const evo_opm_desc_t* d, int32_t phase) {
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_opm_w_t w; memset(&w, 0, sizeof(w));
   if (phase == EVO_PHASE_FWD) {
-    if (d->dtype == EVO_BF16) opm_fwd_op<bf16>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
-    else opm_fwd_op<float>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
+    if (d->dtype == EVO_BF16) opm_fwd_op<bf16, bf16>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
+    else opm_fwd_op<float, float>(c, ws, ws, *d, w, nullptr, nullptr, nullptr, nullptr);
   } else {
-    if (d->dtype == EVO_BF16) opm_bwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
-    else opm_bwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
+    if (d->dtype == EVO_BF16) opm_bwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
+    else opm_bwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
   }
   return ws.off;
 }
@@ -352,8 +352,8 @@ evo_status_t opm_fwd(const evo_opm_desc_t* d, const evo_opm_w_t* w, const void* 
     sv.dry = c.dry;
     Arena& svr = saved ? sv : a;
     if (d->dtype == EVO_BF16)
-      return opm_fwd_op<bf16>(c, a, svr, *d, *w, (const bf16*)m, msa_mask, (const bf16*)z_in, (bf16*)z_out);
-    return opm_fwd_op<float>(c, a, svr, *d, *w, (const float*)m, msa_mask, (const float*)z_in, (float*)z_out);
+      return opm_fwd_op<bf16, bf16>(c, a, svr, *d, *w, (const bf16*)m, msa_mask, (const bf16*)z_in, (bf16*)z_out);
+    return opm_fwd_op<float, float>(c, a, svr, *d, *w, (const float*)m, msa_mask, (const float*)z_in, (float*)z_out);
   });
 }
 
@@ -369,8 +369,8 @@ evo_status_t opm_bwd(const evo_opm_desc_t* d, const evo_opm_w_t* w, const void* 
     Arena sv = live_arena(const_cast<void*>(saved), need_sv);
     sv.dry = c.dry;
     if (d->dtype == EVO_BF16)
-      return opm_bwd_op<bf16>(c, a, sv, *d, *w, (const bf16*)m, msa_mask, (const bf16*)dz_out, (bf16*)d_m, *d_w);
-    return opm_bwd_op<float>(c, a, sv, *d, *w, (const float*)m, msa_mask, (const float*)dz_out, (float*)d_m, *d_w);
+      return opm_bwd_op<bf16, bf16>(c, a, sv, *d, *w, (const bf16*)m, msa_mask, (const bf16*)dz_out, (bf16*)d_m, *d_w);
+    return opm_bwd_op<float, float>(c, a, sv, *d, *w, (const float*)m, msa_mask, (const float*)dz_out, (float*)d_m, *d_w);
   });
 }
 
@@ -380,8 +380,8 @@ size_t tri_mul_saved_bytes(const evo_trimul_desc_t* d) {
   Ctx c; c.dry = true;
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_trimul_w_t w; memset(&w, 0, sizeof(w));
-  if (d->dtype == EVO_BF16) trimul_fwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr);
-  else trimul_fwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr);
+  if (d->dtype == EVO_BF16) trimul_fwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr);
+  else trimul_fwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr);
   return sv.off;
 }
 
@@ -391,11 +391,11 @@ size_t tri_mul_workspace_bytes(const evo_trimul_desc_t* d, int32_t phase) {
   Arena ws, sv; ws.dry = sv.dry = true;
   evo_trimul_w_t w; memset(&w, 0, sizeof(w));
   if (phase == EVO_PHASE_FWD) {
-    if (d->dtype == EVO_BF16) trimul_fwd_op<bf16>(c, ws, ws, *d, w, nullptr, nullptr, nullptr);
-    else trimul_fwd_op<float>(c, ws, ws, *d, w, nullptr, nullptr, nullptr);
+    if (d->dtype == EVO_BF16) trimul_fwd_op<bf16, bf16>(c, ws, ws, *d, w, nullptr, nullptr, nullptr);
+    else trimul_fwd_op<float, float>(c, ws, ws, *d, w, nullptr, nullptr, nullptr);
   } else {
-    if (d->dtype == EVO_BF16) trimul_bwd_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
-    else trimul_bwd_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
+    if (d->dtype == EVO_BF16) trimul_bwd_op<bf16, bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
+    else trimul_bwd_op<float, float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, w);
   }
   return ws.off;
 }
@@ -413,8 +413,8 @@ evo_status_t tri_mul_fwd(const evo_trimul_desc_t* d, const evo_trimul_w_t* w, co
     sv.dry = c.dry;
     Arena& svr = saved ? sv : a;
     if (d->dtype == EVO_BF16)
-      return trimul_fwd_op<bf16>(c, a, svr, *d, *w, (const bf16*)z, pair_mask, (bf16*)z_out);
-    return trimul_fwd_op<float>(c, a, svr, *d, *w, (const float*)z, pair_mask, (float*)z_out);
+      return trimul_fwd_op<bf16, bf16>(c, a, svr, *d, *w, (const bf16*)z, pair_mask, (bf16*)z_out);
+    return trimul_fwd_op<float, float>(c, a, svr, *d, *w, (const float*)z, pair_mask, (float*)z_out);
   });
 }
 
@@ -430,8 +430,8 @@ evo_status_t tri_mul_bwd(const evo_trimul_desc_t* d, const evo_trimul_w_t* w, co
     Arena sv = live_arena(const_cast<void*>(saved), need_sv);
     sv.dry = c.dry;
     if (d->dtype == EVO_BF16)
-      return trimul_bwd_op<bf16>(c, a, sv, *d, *w, (const bf16*)z, pair_mask, (const bf16*)dz_out, (bf16*)dz, *d_w);
-    return trimul_bwd_op<float>(c, a, sv, *d, *w, (const float*)z, pair_mask, (const float*)dz_out, (float*)dz, *d_w);
+      return trimul_bwd_op<bf16, bf16>(c, a, sv, *d, *w, (const bf16*)z, pair_mask, (const bf16*)dz_out, (bf16*)dz, *d_w);
+    return trimul_bwd_op<float, float>(c, a, sv, *d, *w, (const float*)z, pair_mask, (const float*)dz_out, (float*)dz, *d_w);
   });
 }
 

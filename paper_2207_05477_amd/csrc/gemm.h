@@ -44,9 +44,10 @@ struct GemmEpilogue {
   const void* relu_ref = nullptr;      // kernel type, addressed like resid
   const void* gate = nullptr;          // kernel type, gate[m * g_m + n * g_n]
   int64_t g_m = 0, g_n = 0;
-  const void* resid = nullptr;         // kernel type, resid[m * r_m + n * r_n]
+  const void* resid = nullptr;         // kernel type (FP32 if resid_f32), resid[m * r_m + n * r_n]
                                        // (r_m < 0 / g_m < 0: addressed like the output)
   int64_t r_m = 0, r_n = 0;
+  int32_t resid_f32 = 0;
 };
 
 struct GemmArgs {

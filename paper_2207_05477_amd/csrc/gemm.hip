@@ -86,7 +86,7 @@ EVO_DEV void epilogue_apply(const GemmEpilogue& e, int z, int64_t m, int64_t n, 
     v = r > 0.0f ? v : 0.0f;
   }
   if (e.gate) v *= to_f32(((const T*)e.gate)[e.g_m < 0 ? off : zo + m * e.g_m + n * e.g_n]);
-  if (e.resid) v += to_f32(((const T*)e.resid)[roff]);
+  if (e.resid) v += e.resid_f32 ? ((const float*)e.resid)[roff] : to_f32(((const T*)e.resid)[roff]);
   if (e.out_f32) {
     float* o = (float*)e.out + off;
     *o = e.accumulate ? (*o + v) : v;

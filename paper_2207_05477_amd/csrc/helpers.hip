@@ -196,14 +196,22 @@ evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int 
 template <typename T>
 evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, int64_t ld, int nseg,
                              const int* seg_off, const int* seg_n, float* const* outs) {
-  const int64_t nblk = colsum_partials(rows);
-  float* part = ws.take_n<float>((size_t)nblk * ld);
-  if (c.dry || rows == 0) return EVO_OK;
-  int nb = 0;
-  EVO_TRY(colsum_partial<T>(c, x, rows, (int)ld, ld, part, &nb));
+  int lo = 1 << 30, hi = 0;
   for (int s = 0; s < nseg; ++s) {
     if (!outs[s]) continue;
-    EVO_TRY(reduce_partials(c, part + seg_off[s], nb, seg_n[s], ld, outs[s], true));
+    lo = seg_off[s] < lo ? seg_off[s] : lo;
+    hi = seg_off[s] + seg_n[s] > hi ? seg_off[s] + seg_n[s] : hi;
+  }
+  if (hi <= lo) return EVO_OK;
+  const int span = hi - lo;
+  const int64_t nblk = colsum_partials(rows);
+  float* part = ws.take_n<float>((size_t)nblk * span);
+  if (c.dry || rows == 0) return EVO_OK;
+  int nb = 0;
+  EVO_TRY(colsum_partial<T>(c, x + lo, rows, span, ld, part, &nb));
+  for (int s = 0; s < nseg; ++s) {
+    if (!outs[s]) continue;
+    EVO_TRY(reduce_partials(c, part + (seg_off[s] - lo), nb, seg_n[s], span, outs[s], true));
   }
   return EVO_OK;
 }

@@ -5,17 +5,18 @@
 namespace evo {
 
 // y = LayerNorm(x) over the last axis (rows x C, row pitch C), FP32 statistics.
-template <typename T>
-evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
-                    float eps, T* y, float* mean, float* rstd);
+template <typename TI, typename TO = TI>
+evo_status_t ln_fwd(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
+                    float eps, TO* y, float* mean, float* rstd);
 // Same with row r of x at x + ((r >> rshift) * rhi + (r & (2^rshift - 1)) * C)
 // (a chunk of rows of a larger matrix); y is dense.
-template <typename T>
-evo_status_t ln_fwd_rows(const Ctx& c, const T* x, int64_t rows, int C, int rshift, int64_t rhi,
-                         const float* g, const float* b, float eps, T* y, float* mean, float* rstd);
-// out[h][row] = sum_c LayerNorm(x)[row][c] W[c][h] without storing the LayerNorm output.
-template <typename T>
-evo_status_t ln_rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+template <typename TI, typename TO = TI>
+evo_status_t ln_fwd_rows(const Ctx& c, const TI* x, int64_t rows, int C, int rshift, int64_t rhi,
+                         const float* g, const float* b, float eps, TO* y, float* mean, float* rstd);
+// out[h][row] = sum_c LayerNorm(x)[row][c] W[c][h] without storing the LayerNorm output
+// (the LayerNorm output is rounded to TO first, as a stored one would be).
+template <typename TI, typename TO = TI>
+evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
                         float eps, const float* W, int H, float* out);
 // Channel-major input x[C][P] -> y[P][C].
 template <typename T>
@@ -67,6 +68,9 @@ template <typename T>
 evo_status_t fill_zero(const Ctx& c, T* p, int64_t n);
 template <typename T>
 evo_status_t copy_elems(const Ctx& c, const T* src, T* dst, int64_t n);
+// dst = src converted (round to nearest even when narrowing).
+template <typename TI, typename TO>
+evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n);
 
 // Attention gate backward. Per row r and head h (c = head_dim):
 //   dctx = dgo * g; dgpre = dgo * o * g (1 - g); D[r*H+h] = sum_d dctx * o
@@ -87,8 +91,8 @@ template <typename T>
 evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
                              const float* mask, const T* da, const T* db, T* draw);
 // Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g).
-template <typename T>
-evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* dz, const T* t,
+template <typename T, typename X = T>
+evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const T* t,
                              const T* g, T* dt, T* draw);
 
 // scale[i*R + j] = 1 / (eps + sum_s mask[s,i] mask[s,j])  (mask NULL: all ones).

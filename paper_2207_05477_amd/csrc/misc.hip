@@ -5,8 +5,8 @@
 namespace evo {
 
 // ============================================================== LayerNorm forward
-template <typename T, int NV>
-__global__ __launch_bounds__(256) void ln_fwd_kernel(const T* __restrict__ x, int64_t rows, int C,
+template <typename TI, typename T, int NV>
+__global__ __launch_bounds__(256) void ln_fwd_kernel(const TI* __restrict__ x, int64_t rows, int C,
                                                      const float* __restrict__ g,
                                                      const float* __restrict__ b, float eps,
                                                      T* __restrict__ y, float* __restrict__ mean,
@@ -14,7 +14,7 @@ __global__ __launch_bounds__(256) void ln_fwd_kernel(const T* __restrict__ x, in
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  const T* xr = x + (rshift < 0 ? row * C : (row >> rshift) * rhi + (row & ((1LL << rshift) - 1)) * C);
+  const TI* xr = x + (rshift < 0 ? row * C : (row >> rshift) * rhi + (row & ((1LL << rshift) - 1)) * C);
   float v[NV];
   float s = 0.f;
 #pragma unroll
@@ -44,30 +44,30 @@ __global__ __launch_bounds__(256) void ln_fwd_kernel(const T* __restrict__ x, in
   }
 }
 
-template <typename T>
-evo_status_t ln_fwd_rows(const Ctx& c, const T* x, int64_t rows, int C, int rshift, int64_t rhi,
+template <typename TI, typename T>
+evo_status_t ln_fwd_rows(const Ctx& c, const TI* x, int64_t rows, int C, int rshift, int64_t rhi,
                          const float* g, const float* b, float eps, T* y, float* mean, float* rstd) {
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)((rows + 3) / 4));
-  const double bytes = (double)rows * C * 2 * sizeof(T) + rows * 8.0;
-  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
-  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
-  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
-  else if (C <= 1024) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", T), 0.0, bytes, (ln_fwd_kernel<T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  const double bytes = (double)rows * C * (sizeof(TI) + sizeof(T)) + rows * 8.0;
+  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else if (C <= 1024) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 16>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
   else { set_error("layernorm: C=%d > 1024", C); return EVO_ESHAPE; }
   return check_launch("ln_fwd");
 }
 
-template <typename T>
-evo_status_t ln_fwd(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+template <typename TI, typename T>
+evo_status_t ln_fwd(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
                     float eps, T* y, float* mean, float* rstd) {
-  return ln_fwd_rows<T>(c, x, rows, C, -1, 0, g, b, eps, y, mean, rstd);
+  return ln_fwd_rows<TI, T>(c, x, rows, C, -1, 0, g, b, eps, y, mean, rstd);
 }
 
 // Fused LayerNorm + small projection (pair bias of the chunked forward): one
 // wave per row, FP32 statistics, H dot products reduced across the wave.
-template <typename T, int NV>
-__global__ __launch_bounds__(256) void ln_rowproj_kernel(const T* __restrict__ x, int64_t rows, int C,
+template <typename TI, typename T, int NV>
+__global__ __launch_bounds__(256) void ln_rowproj_kernel(const TI* __restrict__ x, int64_t rows, int C,
                                                          const float* __restrict__ g,
                                                          const float* __restrict__ b, float eps,
                                                          const float* __restrict__ W, int H,
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void ln_rowproj_kernel(const T* __restrict__ x
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  const T* xr = x + row * C;
+  const TI* xr = x + row * C;
   float v[NV];
   float s = 0.f;
 #pragma unroll
@@ -111,16 +111,16 @@ __global__ __launch_bounds__(256) void ln_rowproj_kernel(const T* __restrict__ x
   }
 }
 
-template <typename T>
-evo_status_t ln_rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* g, const float* b,
+template <typename TI, typename T>
+evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
                         float eps, const float* W, int H, float* out) {
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)((rows + 3) / 4));
-  const double bytes = (double)rows * C * sizeof(T) + (double)rows * H * 4.0;
+  const double bytes = (double)rows * C * sizeof(TI) + (double)rows * H * 4.0;
   const double flops = 2.0 * rows * C * H;
-  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", T), flops, bytes, (ln_rowproj_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
-  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", T), flops, bytes, (ln_rowproj_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
-  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", T), flops, bytes, (ln_rowproj_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
   else { set_error("layernorm projection: C=%d > 256", C); return EVO_ESHAPE; }
   return check_launch("ln_rowproj");
 }
@@ -378,37 +378,27 @@ evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C,
   return reduce_partials(c, part + C, n, C, 2 * C, out_b, true);
 }
 
-// Column sums over blocks of CS_ROWS rows; all 256 threads work: thread t owns
-// column t % C (C <= 256) in row group t / C, or columns t, t + 256, ... (C > 256).
+// Column sums over blocks of CS_ROWS rows.  A workgroup owns 64 columns x
+// CS_ROWS rows (grid: column tiles x row blocks); its 256 threads are 64
+// columns x 4 row groups, reduced through LDS in a fixed order.
 constexpr int CS_ROWS = 256;
 int64_t colsum_partials(int64_t rows) { return (rows + CS_ROWS - 1) / CS_ROWS; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ x, int64_t rows, int C,
                                                      int64_t ld, float* __restrict__ part) {
-  __shared__ float red[256];
-  const int64_t r0 = (int64_t)blockIdx.x * CS_ROWS;
+  __shared__ float red[4][64];
+  const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+  const int cc = blockIdx.x * 64 + tc;
+  const int64_t r0 = (int64_t)blockIdx.y * CS_ROWS;
   const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
-  if (C <= 256) {
-    const int groups = 256 / C;
-    const int cc = threadIdx.x % C, g = threadIdx.x / C;
-    float s = 0.f;
-    if (g < groups)
-      for (int64_t r = r0 + g; r < r1; r += groups) s += to_f32(x[r * ld + cc]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < C) {
-      float t = 0.f;
-      for (int q = 0; q < groups; ++q) t += red[q * C + threadIdx.x];
-      part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
-    }
-  } else {
-    for (int cc = threadIdx.x; cc < C; cc += 256) {
-      float s = 0.f;
-      for (int64_t r = r0; r < r1; ++r) s += to_f32(x[r * ld + cc]);
-      part[(int64_t)blockIdx.x * C + cc] = s;
-    }
-  }
+  float s = 0.f;
+  if (cc < C)
+    for (int64_t r = r0 + tr; r < r1; r += 4) s += to_f32(x[r * ld + cc]);
+  red[tr][tc] = s;
+  __syncthreads();
+  if (tr == 0 && cc < C)
+    part[(int64_t)blockIdx.y * C + cc] = (red[0][tc] + red[1][tc]) + (red[2][tc] + red[3][tc]);
 }
 
 template <typename T>
@@ -417,7 +407,7 @@ evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64
   *nblk = (int)colsum_partials(rows);
   if (c.dry || rows == 0) return EVO_OK;
   EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>),
-             dim3((unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
+             dim3((unsigned)((C + 63) / 64), (unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
   return check_launch("colsum");
 }
 
@@ -480,6 +470,20 @@ evo_status_t copy_elems(const Ctx& c, const T* src, T* dst, int64_t n) {
   if (c.dry || n == 0 || src == dst) return EVO_OK;
   EVO_LAUNCH(EVO_KNAME("copy_kernel", T), 0.0, (double)n * 2 * sizeof(T), (copy_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
   return check_launch("copy");
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void convert_kernel(const TI* __restrict__ s, TO* __restrict__ d, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) d[e] = from_f32<TO>(to_f32(s[e]));
+}
+
+template <typename TI, typename TO>
+evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n) {
+  if (c.dry || n == 0) return EVO_OK;
+  EVO_LAUNCH(EVO_KNAME("convert_kernel", TO), 0.0, (double)n * (sizeof(TI) + sizeof(TO)),
+             (convert_kernel<TI, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
+  return check_launch("convert");
 }
 
 // ============================================================== attention gate backward
@@ -623,8 +627,8 @@ evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* r
   return check_launch("trimul_proj_bwd");
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch, int cz, const T* dz,
+template <typename T, typename X>
+__global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch, int cz, const X* dz,
                                                               const T* t, const T* g, T* dt, T* draw) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= P * cz) return;
@@ -635,12 +639,12 @@ __global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch,
   draw[p * (4 * ch + cz) + 4 * ch + n] = from_f32<T>(d * tv * gv * (1.f - gv));
 }
 
-template <typename T>
-evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* dz, const T* t,
+template <typename T, typename X>
+evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const T* t,
                              const T* g, T* dt, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   const int64_t n = P * cz;
-  EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", T), 0.0, (double)n * 5 * sizeof(T), (trimul_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+  EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", X), 0.0, (double)n * 5 * sizeof(T), (trimul_gate_bwd_kernel<T, X>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      c.stream, P, ch, cz, dz, t, g, dt, draw);
   return check_launch("trimul_gate_bwd");
 }
@@ -670,12 +674,12 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
 
 // ============================================================== instantiations
 #define EVO_INST(T)                                                                                \
-  template evo_status_t ln_fwd<T>(const Ctx&, const T*, int64_t, int, const float*, const float*,  \
-                                  float, T*, float*, float*);                                      \
-  template evo_status_t ln_fwd_rows<T>(const Ctx&, const T*, int64_t, int, int, int64_t,            \
-                                       const float*, const float*, float, T*, float*, float*);     \
-  template evo_status_t ln_rowproj<T>(const Ctx&, const T*, int64_t, int, const float*,            \
-                                      const float*, float, const float*, int, float*);             \
+  template evo_status_t ln_fwd<T, T>(const Ctx&, const T*, int64_t, int, const float*, const float*, \
+                                     float, T*, float*, float*);                                   \
+  template evo_status_t ln_fwd_rows<T, T>(const Ctx&, const T*, int64_t, int, int, int64_t,         \
+                                          const float*, const float*, float, T*, float*, float*);  \
+  template evo_status_t ln_rowproj<T, T>(const Ctx&, const T*, int64_t, int, const float*,         \
+                                         const float*, float, const float*, int, float*);          \
   template evo_status_t ln_fwd_cm<T>(const Ctx&, const T*, int64_t, int, const float*,             \
                                      const float*, float, T*, float*, float*);                     \
   template evo_status_t ln_bwd<T>(const Ctx&, const T*, const float*, const float*, const float*,  \
@@ -694,10 +698,24 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
                                        T*, int64_t, T*);                                           \
   template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const T*, const float*,  \
                                            const T*, const T*, T*);                                \
-  template evo_status_t trimul_gate_bwd<T>(const Ctx&, int64_t, int, int, const T*, const T*,      \
-                                           const T*, T*, T*);
+  template evo_status_t trimul_gate_bwd<T, T>(const Ctx&, int64_t, int, int, const T*, const T*,   \
+                                              const T*, T*, T*);
 
 EVO_INST(float)
 EVO_INST(bf16)
+
+// mixed: FP32 residual stream around BF16 compute
+template evo_status_t ln_fwd<float, bf16>(const Ctx&, const float*, int64_t, int, const float*, const float*,
+                                          float, bf16*, float*, float*);
+template evo_status_t ln_fwd_rows<float, bf16>(const Ctx&, const float*, int64_t, int, int, int64_t,
+                                               const float*, const float*, float, bf16*, float*, float*);
+template evo_status_t ln_rowproj<float, bf16>(const Ctx&, const float*, int64_t, int, const float*,
+                                              const float*, float, const float*, int, float*);
+template evo_status_t trimul_gate_bwd<bf16, float>(const Ctx&, int64_t, int, int, const float*, const bf16*,
+                                                   const bf16*, bf16*, bf16*);
+template evo_status_t convert_elems<float, bf16>(const Ctx&, const float*, bf16*, int64_t);
+template evo_status_t convert_elems<bf16, float>(const Ctx&, const bf16*, float*, int64_t);
+template evo_status_t convert_elems<float, float>(const Ctx&, const float*, float*, int64_t);
+template evo_status_t convert_elems<bf16, bf16>(const Ctx&, const bf16*, bf16*, int64_t);
 
 }  // namespace evo

@@ -7,6 +7,8 @@
 #include "gemm.h"
 #include "misc.h"
 
+#include <type_traits>
+
 namespace evo {
 
 // ---- helpers shared by the ops
@@ -27,40 +29,63 @@ evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, 
                              int nseg, const int* seg_off, const int* seg_n, float* const* outs);
 
 inline int ilog2(int64_t v) { int s = 0; while ((1LL << s) < v) ++s; return s; }
+
+// Residual-stream type X (x, out, d_out, d_x) may be wider than the compute
+// type T (GEMM operands, saved intermediates): FP32 residuals around BF16 compute.
+template <typename X> constexpr bool is_f32() { return std::is_same<X, float>::value; }
+template <typename X> inline void epi_out(GemmEpilogue& e, X* out, int64_t ld) {
+  e.out = out; e.m_lo = ld; e.n_lo = 1; e.out_f32 = is_f32<X>() ? 1 : 0;
+}
+template <typename X> inline void epi_resid(GemmEpilogue& e, const X* r, int64_t r_m, int64_t r_n) {
+  e.resid = r; e.r_m = r_m; e.r_n = r_n; e.resid_f32 = is_f32<X>() ? 1 : 0;
+}
+// p as a compute-type tensor: itself, or a converted copy in the workspace.
+template <typename T, typename X>
+inline const T* as_compute(const Ctx& c, Arena& ws, const X* p, int64_t n, evo_status_t* st) {
+  *st = EVO_OK;
+  if constexpr (std::is_same<T, X>::value) {
+    (void)c; (void)ws; (void)n;
+    return p;
+  } else {
+    T* b = ws.take_n<T>(n);
+    *st = convert_elems<X, T>(c, p, b, n);
+    return b;
+  }
+}
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// ---- ops (T = float or bf16)
-template <typename T>
+// ---- ops (T = float or bf16; X = residual-stream type, T or float)
+template <typename T, typename X = T>
 evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
-                         const evo_attn_w_t& w, const T* x, const T* pair, const float* mask, T* out);
-template <typename T>
+                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask, X* out);
+template <typename T, typename X = T>
 evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
-                         const evo_attn_w_t& w, const T* x, const T* pair, const float* mask,
-                         const T* dout, T* dx, T* dpair, const evo_attn_w_t& dw);
+                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask,
+                         const X* dout, X* dx, X* dpair, const evo_attn_w_t& dw);
 
-template <typename T>
+template <typename T, typename X = T>
 evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
-                          const evo_trans_w_t& w, const T* x, T* out);
-template <typename T>
+                          const evo_trans_w_t& w, const X* x, X* out);
+template <typename T, typename X = T>
 evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
-                          const evo_trans_w_t& w, const T* x, const T* dout, T* dx,
+                          const evo_trans_w_t& w, const X* x, const X* dout, X* dx,
                           const evo_trans_w_t& dw);
 
-template <typename T>
+template <typename T, typename X = T>
 evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
-                        const evo_opm_w_t& w, const T* m, const float* mask, const T* zin, T* zout);
-template <typename T>
+                        const evo_opm_w_t& w, const X* m, const float* mask, const X* zin, X* zout);
+template <typename T, typename X = T>
 evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
-                        const evo_opm_w_t& w, const T* m, const float* mask, const T* dz, T* dm,
+                        const evo_opm_w_t& w, const X* m, const float* mask, const X* dz, X* dm,
                         const evo_opm_w_t& dw);
 
-template <typename T>
+template <typename T, typename X = T>
 evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
-                           const evo_trimul_w_t& w, const T* z, const float* mask, T* zout);
-template <typename T>
+                           const evo_trimul_w_t& w, const X* z, const float* mask, X* zout);
+template <typename T, typename X = T>
 evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
-                           const evo_trimul_w_t& w, const T* z, const float* mask, const T* dzo,
-                           T* dz, const evo_trimul_w_t& dw);
+                           const evo_trimul_w_t& w, const X* z, const float* mask, const X* dzo,
+                           X* dz, const evo_trimul_w_t& dw);
 
 // ---- argument validation shared by the ABI entry points
 evo_status_t check_attn_desc(const evo_attn_desc_t* d);

@@ -109,10 +109,10 @@ evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int
 // rows i; ending node: columns j), keeping no saved state.  Only the chunk's
 // LayerNorm / projection / context buffers exist; the pair bias (all rows) is
 // formed once.  Equal to the unchunked forward (same per-row arithmetic).
-template <typename T>
+template <typename T, typename X>
 static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn_desc_t& d,
-                                         const AttnShape& s, const evo_attn_w_t& w, const T* x,
-                                         const float* mask, T* out) {
+                                         const AttnShape& s, const evo_attn_w_t& w, const X* x,
+                                         const float* mask, X* out) {
   const int64_t R = s.ni, C = d.chunk, CR = C * R, cin = s.cin;
   const int sh = ilog2(C);
   const bool start = s.kind == EVO_ATTN_TRI_START;
@@ -143,13 +143,13 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
   po.nseg = 1;
   po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, po));
-  EVO_TRY(ln_rowproj<T>(c, x, R * R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias));
+  EVO_TRY((ln_rowproj<X, T>(c, x, R * R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias)));
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     // chunk rows: starting node (i, j) = (c0 + ii, j) contiguous; ending node
     // (i, j) = (i, c0 + jj) with local row i*C + jj
-    const T* xs = start ? x + c0 * R * cin : x + c0 * cin;
-    EVO_TRY(ln_fwd_rows<T>(c, xs, CR, (int)cin, start ? -1 : sh, R * cin, w.ln_g, w.ln_b, d.ln_eps, y,
-                           mean, rstd));
+    const X* xs = start ? x + c0 * R * cin : x + c0 * cin;
+    EVO_TRY((ln_fwd_rows<X, T>(c, xs, CR, (int)cin, start ? -1 : sh, R * cin, w.ln_g, w.ln_b, d.ln_eps, y,
+                               mean, rstd)));
     GemmArgs g;
     g.M = CR; g.N = s.NQ; g.K = cin;
     g.A = op_rowmajor(y, cin);
@@ -177,7 +177,8 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
     go_.M = CR; go_.N = cin; go_.K = s.HC;
     go_.A = op_rowmajor(go, s.HC);
     go_.B = op_rowmajor(wt_o, s.HC);
-    go_.epi.out_f32 = 0;
+    go_.epi.out_f32 = is_f32<X>() ? 1 : 0;
+    go_.epi.resid_f32 = is_f32<X>() ? 1 : 0;
     go_.epi.bias = w.b_o;
     go_.epi.r_m = -1;   // residual addressed like the output
     if (start) {
@@ -193,11 +194,11 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
   return EVO_OK;
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
-                         const evo_attn_w_t& w, const T* x, const T* pair, const float* mask, T* out) {
+                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask, X* out) {
   const AttnShape s = attn_shape(d);
-  if (s.tri && d.chunk > 0 && d.chunk < s.ni) return attn_fwd_tri_chunked<T>(c, ws, d, s, w, x, mask, out);
+  if (s.tri && d.chunk > 0 && d.chunk < s.ni) return attn_fwd_tri_chunked<T, X>(c, ws, d, s, w, x, mask, out);
   AttnSaved<T> S;
   S.carve(sv, s);
   T* wt_qkvg = ws.take_n<T>((int64_t)s.NQ * s.cin);
@@ -223,7 +224,7 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, po));
 
-  EVO_TRY(ln_fwd<T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd));
+  EVO_TRY((ln_fwd<X, T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {
     GemmArgs g;
     g.M = s.rows; g.N = s.NQ; g.K = s.cin;
@@ -236,10 +237,10 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY(gemm<T>(c, g));
   }
   if (s.row) {
-    EVO_TRY(ln_rowproj<T>(c, pair, s.ni * s.ni, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, w.w_bias, s.H,
-                          S.bias));
+    EVO_TRY((ln_rowproj<X, T>(c, pair, s.ni * s.ni, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, w.w_bias,
+                              s.H, S.bias)));
   } else if (s.tri) {
-    EVO_TRY(ln_rowproj<T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, S.bias));
+    EVO_TRY((ln_rowproj<X, T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, S.bias)));
   }
   if (s.global) {
     EVO_TRY(gattn_fwd<T>(c, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
@@ -254,23 +255,24 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     g.M = s.rows; g.N = s.cin; g.K = s.HC;
     g.A = op_rowmajor(S.go, s.HC);
     g.B = op_rowmajor(wt_o, s.HC);
-    g.epi = epi_rowmajor(out, s.cin, false);
+    epi_out<X>(g.epi, out, s.cin);
     g.epi.bias = w.b_o;
-    g.epi.resid = x;
-    g.epi.r_m = s.cin;
-    g.epi.r_n = 1;
+    epi_resid<X>(g.epi, x, s.cin, 1);
     EVO_TRY(gemm<T>(c, g));
   }
   return EVO_OK;
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
-                         const evo_attn_w_t& w, const T* x, const T* pair, const float* mask,
-                         const T* dout, T* dx, T* dpair, const evo_attn_w_t& dw) {
+                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask,
+                         const X* dout, X* dx, X* dpair, const evo_attn_w_t& dw) {
   const AttnShape s = attn_shape(d);
   AttnSaved<T> S;
   S.carve(sv, s);
+  evo_status_t cst;
+  const T* dout_t = as_compute<T, X>(c, ws, dout, s.rows * s.cin, &cst);
+  EVO_TRY(cst);
   T* w_qkvg = ws.take_n<T>((int64_t)s.cin * s.NQ);     // [c_in][NQ]
   T* w_o = ws.take_n<T>((int64_t)s.HC * s.cin);        // [HC][c_in]
   T* dgo = ws.take_n<T>(s.rows * s.HC);
@@ -316,11 +318,11 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   {
     int off = 0, n = (int)s.cin;
     float* outs[1] = {dw.b_o};
-    EVO_TRY(colsum_segments<T>(c, ws, dout, s.rows, s.cin, 1, &off, &n, outs));
-    EVO_TRY(wgrad<T>(c, ws, S.go, s.HC, dout, s.cin, s.rows, s.HC, s.cin, dw.w_o));
+    EVO_TRY(colsum_segments<X>(c, ws, dout, s.rows, s.cin, 1, &off, &n, outs));
+    EVO_TRY(wgrad<T>(c, ws, S.go, s.HC, dout_t, s.cin, s.rows, s.HC, s.cin, dw.w_o));
     GemmArgs g;
     g.M = s.rows; g.N = s.HC; g.K = s.cin;
-    g.A = op_rowmajor(dout, s.cin);
+    g.A = op_rowmajor(dout_t, s.cin);
     g.B = op_rowmajor(w_o, s.cin);
     g.epi = epi_rowmajor(dgo, s.HC, false);
     EVO_TRY(gemm<T>(c, g));
@@ -368,12 +370,12 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     S.yz = ws.take_n<T>(P * s.cpair);
     S.zmean = ws.take_n<float>(P);
     S.zrstd = ws.take_n<float>(P);
-    EVO_TRY(ln_fwd<T>(c, pair, P, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, S.yz, S.zmean, S.zrstd));
+    EVO_TRY((ln_fwd<X, T>(c, pair, P, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, S.yz, S.zmean, S.zrstd)));
     float* dyz = ws.take_n<float>(P * s.cpair);
     EVO_TRY(rowproj_bwd<T>(c, ws, S.yz, P, (int)s.cpair, w.w_bias, s.H, dbias, dyz, false, dw.w_bias));
     float* part = ws.take_n<float>((size_t)ln_bwd_partials(P) * 2 * s.cpair);
     int nb = 0;
-    EVO_TRY(ln_bwd<T>(c, pair, S.zmean, S.zrstd, w.ln_z_g, dyz, P, (int)s.cpair, nullptr, true, dpair,
+    EVO_TRY(ln_bwd<X>(c, pair, S.zmean, S.zrstd, w.ln_z_g, dyz, P, (int)s.cpair, nullptr, true, dpair,
                       part, &nb));
     if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)s.cpair, dw.ln_z_g, dw.ln_z_b));
   } else if (s.tri) {
@@ -382,22 +384,20 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   // input LayerNorm and residual
   float* part = ws.take_n<float>((size_t)ln_bwd_partials(s.rows) * 2 * s.cin);
   int nb = 0;
-  EVO_TRY(ln_bwd<T>(c, x, S.mean, S.rstd, w.ln_g, dy, s.rows, (int)s.cin, dout, false, dx, part, &nb));
+  EVO_TRY(ln_bwd<X>(c, x, S.mean, S.rstd, w.ln_g, dy, s.rows, (int)s.cin, dout, false, dx, part, &nb));
   if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)s.cin, dw.ln_g, dw.ln_b));
   return EVO_OK;
 }
 
-template evo_status_t attn_fwd_op<float>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
-                                         const evo_attn_w_t&, const float*, const float*, const float*,
-                                         float*);
-template evo_status_t attn_fwd_op<bf16>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
-                                        const evo_attn_w_t&, const bf16*, const bf16*, const float*,
-                                        bf16*);
-template evo_status_t attn_bwd_op<float>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
-                                         const evo_attn_w_t&, const float*, const float*, const float*,
-                                         const float*, float*, float*, const evo_attn_w_t&);
-template evo_status_t attn_bwd_op<bf16>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,
-                                        const evo_attn_w_t&, const bf16*, const bf16*, const float*,
-                                        const bf16*, bf16*, bf16*, const evo_attn_w_t&);
+#define EVO_INST_A(T, X)                                                                           \
+  template evo_status_t attn_fwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,      \
+                                          const evo_attn_w_t&, const X*, const X*, const float*, X*); \
+  template evo_status_t attn_bwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,      \
+                                          const evo_attn_w_t&, const X*, const X*, const float*,   \
+                                          const X*, X*, X*, const evo_attn_w_t&);
+
+EVO_INST_A(float, float)
+EVO_INST_A(bf16, bf16)
+EVO_INST_A(bf16, float)
 
 }  // namespace evo

@@ -12,9 +12,9 @@ static void trans_carve(Arena& a, const evo_trans_desc_t& d, T** y, float** mean
   *h = a.take_n<T>(d.rows * d.c * d.factor);
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
-                          const evo_trans_w_t& w, const T* x, T* out) {
+                          const evo_trans_w_t& w, const X* x, X* out) {
   T *y, *h; float *mean, *rstd;
   trans_carve<T>(sv, d, &y, &mean, &rstd, &h);
   const int64_t C = d.c, HID = d.c * d.factor;
@@ -26,7 +26,7 @@ evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   EVO_TRY(pack_params<T>(c, p1));
   PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst_t = wt2;
   EVO_TRY(pack_params<T>(c, p2));
-  EVO_TRY(ln_fwd<T>(c, x, d.rows, (int)C, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd));
+  EVO_TRY((ln_fwd<X, T>(c, x, d.rows, (int)C, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd)));
   {
     GemmArgs g;
     g.M = d.rows; g.N = HID; g.K = C;
@@ -41,18 +41,21 @@ evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   g.M = d.rows; g.N = C; g.K = HID;
   g.A = op_rowmajor(h, HID);
   g.B = op_rowmajor(wt2, HID);
-  g.epi = epi_rowmajor(out, C, false);
+  epi_out<X>(g.epi, out, C);
   g.epi.bias = w.b_2;
-  g.epi.resid = x; g.epi.r_m = C; g.epi.r_n = 1;
+  epi_resid<X>(g.epi, x, C, 1);
   return gemm<T>(c, g);
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
-                          const evo_trans_w_t& w, const T* x, const T* dout, T* dx,
+                          const evo_trans_w_t& w, const X* x, const X* dout, X* dx,
                           const evo_trans_w_t& dw) {
   T *y, *h; float *mean, *rstd;
   trans_carve<T>(sv, d, &y, &mean, &rstd, &h);
+  evo_status_t cst;
+  const T* dout_t = as_compute<T, X>(c, ws, dout, d.rows * d.c, &cst);
+  EVO_TRY(cst);
   const int64_t C = d.c, HID = d.c * d.factor;
   T* w1 = ws.take_n<T>(C * HID);     // [C][HID]
   T* w2 = ws.take_n<T>(HID * C);     // [HID][C]
@@ -66,12 +69,12 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   }
   int off0 = 0, nC = (int)C, nH = (int)HID;
   float* ob2[1] = {dw.b_2};
-  EVO_TRY(colsum_segments<T>(c, ws, dout, d.rows, C, 1, &off0, &nC, ob2));
-  EVO_TRY(wgrad<T>(c, ws, h, HID, dout, C, d.rows, HID, C, dw.w_2));
+  EVO_TRY(colsum_segments<X>(c, ws, dout, d.rows, C, 1, &off0, &nC, ob2));
+  EVO_TRY(wgrad<T>(c, ws, h, HID, dout_t, C, d.rows, HID, C, dw.w_2));
   {
     GemmArgs g;
     g.M = d.rows; g.N = HID; g.K = C;
-    g.A = op_rowmajor(dout, C);
+    g.A = op_rowmajor(dout_t, C);
     g.B = op_rowmajor(w2, C);
     g.epi = epi_rowmajor(dh, HID, false);
     g.epi.relu_ref = h; g.epi.r_m = HID; g.epi.r_n = 1;
@@ -90,7 +93,7 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   }
   float* part = ws.take_n<float>((size_t)ln_bwd_partials(d.rows) * 2 * C);
   int nb = 0;
-  EVO_TRY(ln_bwd<T>(c, x, mean, rstd, w.ln_g, dy, d.rows, (int)C, dout, false, dx, part, &nb));
+  EVO_TRY(ln_bwd<X>(c, x, mean, rstd, w.ln_g, dy, d.rows, (int)C, dout, false, dx, part, &nb));
   if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)C, dw.ln_g, dw.ln_b));
   return EVO_OK;
 }
@@ -110,9 +113,9 @@ struct OpmSaved {
   }
 };
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
-                        const evo_opm_w_t& w, const T* m, const float* mask, const T* zin, T* zout) {
+                        const evo_opm_w_t& w, const X* m, const float* mask, const X* zin, X* zout) {
   OpmSaved<T> S;
   const bool chunked = d.chunk > 0 && d.chunk < d.n_res;
   if (chunked) {
@@ -138,7 +141,7 @@ evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   EVO_TRY(pack_params<T>(c, pa));
   PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, po));
-  EVO_TRY(ln_fwd<T>(c, m, SR, (int)cm, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd));
+  EVO_TRY((ln_fwd<X, T>(c, m, SR, (int)cm, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {  // a | b = mask * (y W + b)
     GemmArgs g;
     g.M = SR; g.N = 2 * ch; g.K = cm;
@@ -168,20 +171,23 @@ evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
     g.M = C * R; g.N = cz; g.K = ch2;
     g.A = op_rowmajor(S.on, ch2);
     g.B = op_rowmajor(wt_o, ch2);
-    g.epi = epi_rowmajor(zout + i0 * R * cz, cz, false);
+    epi_out<X>(g.epi, zout + i0 * R * cz, cz);
     g.epi.bias = w.b_o;
-    g.epi.resid = zin + i0 * R * cz; g.epi.r_m = cz; g.epi.r_n = 1;
+    epi_resid<X>(g.epi, zin + i0 * R * cz, cz, 1);
     EVO_TRY(gemm<T>(c, g));
   }
   return EVO_OK;
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t& d,
-                        const evo_opm_w_t& w, const T* m, const float* mask, const T* dz, T* dm,
+                        const evo_opm_w_t& w, const X* m, const float* mask, const X* dz_x, X* dm,
                         const evo_opm_w_t& dw) {
   OpmSaved<T> S;
   S.carve(sv, d);
+  evo_status_t cst;
+  const T* dz = as_compute<T, X>(c, ws, dz_x, d.n_res * d.n_res * d.c_z, &cst);
+  EVO_TRY(cst);
   const int64_t S_ = d.n_seq, R = d.n_res, SR = S_ * R, RR = R * R, ch = d.c_hidden, cm = d.c_m,
                 cz = d.c_z, ch2 = ch * ch;
   const int sh = ilog2(ch);
@@ -199,7 +205,7 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   }
   int off0 = 0, ncz = (int)cz;
   float* obo[1] = {dw.b_o};
-  EVO_TRY(colsum_segments<T>(c, ws, dz, RR, cz, 1, &off0, &ncz, obo));
+  EVO_TRY(colsum_segments<X>(c, ws, dz_x, RR, cz, 1, &off0, &ncz, obo));
   EVO_TRY(wgrad<T>(c, ws, S.on, ch2, dz, cz, RR, ch2, cz, dw.w_o));
   if (!c.dry) {
     {  // dO = (dz W_o^T) / (eps + n_ij)
@@ -253,7 +259,7 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   }
   float* part = ws.take_n<float>((size_t)ln_bwd_partials(SR) * 2 * cm);
   int nb = 0;
-  EVO_TRY(ln_bwd<T>(c, m, S.mean, S.rstd, w.ln_g, dy, SR, (int)cm, nullptr, true, dm, part, &nb));
+  EVO_TRY(ln_bwd<X>(c, m, S.mean, S.rstd, w.ln_g, dy, SR, (int)cm, nullptr, true, dm, part, &nb));
   if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)cm, dw.ln_g, dw.ln_b));
   return EVO_OK;
 }
@@ -282,9 +288,9 @@ struct TriSaved {
 // projections run over row chunks into the full channel-major a, b and the
 // gate g; contraction, output LayerNorm and output projection then run per
 // chunk of output rows (x_ij for i in the chunk needs a's rows i and all of b).
-template <typename T>
+template <typename T, typename X>
 static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul_desc_t& d,
-                                       const evo_trimul_w_t& w, const T* z, const float* mask, T* zout) {
+                                       const evo_trimul_w_t& w, const X* z, const float* mask, X* zout) {
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz, C = d.chunk,
                 CR = C * R;
   T* wt_p = ws.take_n<T>(NP * cz);
@@ -315,7 +321,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
   EVO_TRY(pack_params<T>(c, po));
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     const int64_t p0 = c0 * R;
-    EVO_TRY(ln_fwd<T>(c, z + p0 * cz, CR, (int)cz, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd));
+    EVO_TRY((ln_fwd<X, T>(c, z + p0 * cz, CR, (int)cz, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd)));
     GemmArgs gp;
     gp.M = CR; gp.N = NP; gp.K = cz;
     gp.A = op_rowmajor(y, cz);
@@ -348,19 +354,19 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
     go.M = CR; go.N = cz; go.K = ch;
     go.A = op_rowmajor(xn, ch);
     go.B = op_rowmajor(wt_o, ch);
-    go.epi = epi_rowmajor(zout + p0 * cz, cz, false);
+    epi_out<X>(go.epi, zout + p0 * cz, cz);
     go.epi.bias = w.b_o;
     go.epi.gate = g + p0 * cz; go.epi.g_m = cz; go.epi.g_n = 1;
-    go.epi.resid = z + p0 * cz; go.epi.r_m = cz; go.epi.r_n = 1;
+    epi_resid<X>(go.epi, z + p0 * cz, cz, 1);
     EVO_TRY(gemm<T>(c, go));
   }
   return EVO_OK;
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
-                           const evo_trimul_w_t& w, const T* z, const float* mask, T* zout) {
-  if (d.chunk > 0 && d.chunk < d.n_res) return trimul_fwd_chunked<T>(c, ws, d, w, z, mask, zout);
+                           const evo_trimul_w_t& w, const X* z, const float* mask, X* zout) {
+  if (d.chunk > 0 && d.chunk < d.n_res) return trimul_fwd_chunked<T, X>(c, ws, d, w, z, mask, zout);
   TriSaved<T> S;
   S.carve(sv, d);
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
@@ -381,7 +387,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   EVO_TRY(pack_params<T>(c, pp));
   PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, po));
-  EVO_TRY(ln_fwd<T>(c, z, P, (int)cz, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd));
+  EVO_TRY((ln_fwd<X, T>(c, z, P, (int)cz, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {
     GemmArgs g;
     g.M = P; g.N = NP; g.K = cz;
@@ -412,17 +418,17 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   g.M = P; g.N = cz; g.K = ch;
   g.A = op_rowmajor(S.xn, ch);
   g.B = op_rowmajor(wt_o, ch);
-  g.epi = epi_rowmajor(zout, cz, false);
+  epi_out<X>(g.epi, zout, cz);
   g.epi.bias = w.b_o;
   g.epi.gate = S.g; g.epi.g_m = cz; g.epi.g_n = 1;
-  g.epi.resid = z; g.epi.r_m = cz; g.epi.r_n = 1;
+  epi_resid<X>(g.epi, z, cz, 1);
   return gemm<T>(c, g);
 }
 
-template <typename T>
+template <typename T, typename X>
 evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
-                           const evo_trimul_w_t& w, const T* z, const float* mask, const T* dzo,
-                           T* dz, const evo_trimul_w_t& dw) {
+                           const evo_trimul_w_t& w, const X* z, const float* mask, const X* dzo,
+                           X* dz, const evo_trimul_w_t& dw) {
   TriSaved<T> S;
   S.carve(sv, d);
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
@@ -459,7 +465,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
       g.epi.bias = w.b_o;
       EVO_TRY(gemm<T>(c, g));
     }
-    EVO_TRY(trimul_gate_bwd<T>(c, P, (int)ch, (int)cz, dzo, t, S.g, dt, draw));
+    EVO_TRY((trimul_gate_bwd<T, X>(c, P, (int)ch, (int)cz, dzo, t, S.g, dt, draw)));
   }
   int off0 = 0, ncz = (int)cz;
   float* obo[1] = {dw.b_o};
@@ -527,29 +533,30 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   }
   float* part = ws.take_n<float>((size_t)ln_bwd_partials(P) * 2 * cz);
   int nb = 0;
-  EVO_TRY(ln_bwd<T>(c, z, S.mean, S.rstd, w.ln_g, dy, P, (int)cz, dzo, false, dz, part, &nb));
+  EVO_TRY(ln_bwd<X>(c, z, S.mean, S.rstd, w.ln_g, dy, P, (int)cz, dzo, false, dz, part, &nb));
   if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)cz, dw.ln_g, dw.ln_b));
   return EVO_OK;
 }
 
-#define EVO_INST_P(T)                                                                              \
-  template evo_status_t trans_fwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trans_desc_t&,       \
-                                        const evo_trans_w_t&, const T*, T*);                       \
-  template evo_status_t trans_bwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trans_desc_t&,       \
-                                        const evo_trans_w_t&, const T*, const T*, T*,              \
-                                        const evo_trans_w_t&);                                     \
-  template evo_status_t opm_fwd_op<T>(const Ctx&, Arena&, Arena&, const evo_opm_desc_t&,           \
-                                      const evo_opm_w_t&, const T*, const float*, const T*, T*);   \
-  template evo_status_t opm_bwd_op<T>(const Ctx&, Arena&, Arena&, const evo_opm_desc_t&,           \
-                                      const evo_opm_w_t&, const T*, const float*, const T*, T*,    \
-                                      const evo_opm_w_t&);                                         \
-  template evo_status_t trimul_fwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,     \
-                                         const evo_trimul_w_t&, const T*, const float*, T*);       \
-  template evo_status_t trimul_bwd_op<T>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,     \
-                                         const evo_trimul_w_t&, const T*, const float*, const T*,  \
-                                         T*, const evo_trimul_w_t&);
+#define EVO_INST_P(T, X)                                                                           \
+  template evo_status_t trans_fwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_trans_desc_t&,    \
+                                           const evo_trans_w_t&, const X*, X*);                    \
+  template evo_status_t trans_bwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_trans_desc_t&,    \
+                                           const evo_trans_w_t&, const X*, const X*, X*,           \
+                                           const evo_trans_w_t&);                                  \
+  template evo_status_t opm_fwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_opm_desc_t&,        \
+                                         const evo_opm_w_t&, const X*, const float*, const X*, X*); \
+  template evo_status_t opm_bwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_opm_desc_t&,        \
+                                         const evo_opm_w_t&, const X*, const float*, const X*, X*, \
+                                         const evo_opm_w_t&);                                      \
+  template evo_status_t trimul_fwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,  \
+                                            const evo_trimul_w_t&, const X*, const float*, X*);    \
+  template evo_status_t trimul_bwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,  \
+                                            const evo_trimul_w_t&, const X*, const float*,         \
+                                            const X*, X*, const evo_trimul_w_t&);
 
-EVO_INST_P(float)
-EVO_INST_P(bf16)
+EVO_INST_P(float, float)
+EVO_INST_P(bf16, bf16)
+EVO_INST_P(bf16, float)
 
 }  // namespace evo
