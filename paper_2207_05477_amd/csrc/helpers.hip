@@ -196,9 +196,10 @@ evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int 
 template <typename T>
 evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, int64_t ld, int nseg,
                              const int* seg_off, const int* seg_n, float* const* outs) {
+  // the span covers every segment (null outputs included) so that a size
+  // query with null gradient pointers carves the same scratch as a real call
   int lo = 1 << 30, hi = 0;
   for (int s = 0; s < nseg; ++s) {
-    if (!outs[s]) continue;
     lo = seg_off[s] < lo ? seg_off[s] : lo;
     hi = seg_off[s] + seg_n[s] > hi ? seg_off[s] + seg_n[s] : hi;
   }

@@ -93,3 +93,11 @@ def kink_free(inp):
 # transitions flip with the upstream rounding of the block's own forward, each
 # flip moving a whole gradient entry (parity status).
 KINK_TOL = {"f32": 1e-3, "bf16": 0.15}
+
+
+def device_view(inp, dtype):
+    """Inputs as the implementation in `dtype` computes with them: activations
+    and upstream gradients in `dtype`; in BF16 also the matrix-operand weights
+    (the kernels multiply BF16 copies of them), parameters otherwise FP32."""
+    from synth import round_inputs
+    return round_inputs(inp, dtype, weights_dtype="bf16" if dtype == "bf16" else None)

@@ -127,3 +127,30 @@ def test_binding_fails_loudly_without_library(tmp_path):
             A.load(str(tmp_path / "missing.so"))
         finally:
             A._lib = A._lib_saved
+
+
+@pytest.mark.parametrize("name", ["C0", "C1", "C2", "C3", "C4b"])
+def test_workspace_query_matches_a_real_call(name):
+    # A call with real (non-null) parameter and gradient pointers carves its
+    # workspace in a dry pass before touching the device; with exactly the
+    # queried size it must pass the workspace check (and then stop at the
+    # device check here, where there is no GPU).
+    A, lib = _lib()
+    from paper_2207_05477_amd import binding as B
+    cfg = synth.get(name)
+    d = B.block_desc(cfg)
+    w = A.BlockW()
+    dw = A.BlockW()
+    for i, (sub, cls) in enumerate(A.BlockW._fields_):
+        setattr(w, sub, _full_weights(A, cls, i))
+        setattr(dw, sub, _full_weights(A, cls, i + 32))
+    need_f = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_FWD)
+    st = lib.evoformer_block_fwd(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), _fake(3), _fake(4),
+                                 _fake(5), _fake(6), _fake(7), need_f, None)
+    assert st in (A.EVO_EHIP, A.EVO_EUNSUPPORTED), lib.evo_last_error()
+    if cfg.backward:
+        need_b = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
+        st = lib.evoformer_block_bwd(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), _fake(3), _fake(4),
+                                     _fake(5), _fake(6), _fake(7), _fake(8), ctypes.byref(dw), _fake(9), need_b,
+                                     None)
+        assert st in (A.EVO_EHIP, A.EVO_EUNSUPPORTED), lib.evo_last_error()

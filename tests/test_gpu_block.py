@@ -7,9 +7,9 @@ import pytest
 import torch
 
 from oracle import evoformer as O
-from synth import EvoConfig, get, make_inputs, round_inputs
+from synth import EvoConfig, get, make_inputs
 
-from gpu_util import KINK_TOL, TOL, check, kink_free, say, to_dev
+from gpu_util import device_view, KINK_TOL, TOL, check, kink_free, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ def _run(cfg, dtype, seed=32, backward=True, perturb=False, mask_mode=None, repo
     at the tolerance.  kinks=True: full parameters, forward gated at the
     tolerance, gradients at the coarse kink gate."""
     from paper_2207_05477_amd import binding as B
-    inp = round_inputs(make_inputs(cfg, seed=seed, perturb=perturb, mask_mode=mask_mode), dtype)
+    inp = device_view(make_inputs(cfg, seed=seed, perturb=perturb, mask_mode=mask_mode), dtype)
     if not kinks:
         inp = kink_free(inp)
     tol = TOL[dtype]
@@ -99,7 +99,7 @@ def test_extra_msa_block_c3_bf16_forward():
 def test_block_is_deterministic():
     from paper_2207_05477_amd import binding as B
     cfg = SMALL
-    inp = round_inputs(make_inputs(cfg, seed=3, perturb=True), "f32")
+    inp = device_view(make_inputs(cfg, seed=3, perturb=True), "f32")
     flat = B.FlatParams(inp["params"][0], "cuda")
     m, z = to_dev(inp["m"]), to_dev(inp["z"])
     mm, pm = inp["msa_mask"].float().cuda(), inp["pair_mask"].float().cuda()

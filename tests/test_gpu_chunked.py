@@ -11,9 +11,9 @@ import pytest
 import torch
 
 from oracle import evoformer as O
-from synth import EvoConfig, get, make_inputs, round_inputs
+from synth import EvoConfig, get, make_inputs
 
-from gpu_util import TOL, check, params_dev, say, to_dev
+from gpu_util import device_view, TOL, check, params_dev, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +27,7 @@ def test_chunked_op_equals_unchunked_and_oracle(dtype, op):
     from paper_2207_05477_amd import binding as B, _abi as A
     say(f"chunked {op} {dtype}")
     cfg = CCFG
-    inp = round_inputs(make_inputs(cfg, seed=11, perturb=True), dtype)
+    inp = device_view(make_inputs(cfg, seed=11, perturb=True), dtype)
     p = inp["params"][0][op]
     pd = params_dev(p)
     w = B.weight_struct(op, pd)
@@ -65,7 +65,7 @@ def test_chunked_op_equals_unchunked_and_oracle(dtype, op):
 
 def _block_chunk_pair(cfg, dtype, seed):
     from paper_2207_05477_amd import binding as B
-    inp = round_inputs(make_inputs(cfg, seed=seed), dtype)
+    inp = device_view(make_inputs(cfg, seed=seed), dtype)
     flat = B.FlatParams(inp["params"][0], "cuda")
     m, z = to_dev(inp["m"], dtype), to_dev(inp["z"], dtype)
     mm, pm = inp["msa_mask"].float().cuda(), inp["pair_mask"].float().cuda()

@@ -10,9 +10,9 @@ import pytest
 import torch
 
 from oracle import evoformer as O
-from synth import EvoConfig, make_inputs, round_inputs
+from synth import EvoConfig, make_inputs
 
-from gpu_util import TOL, check, oracle_grads, params_dev, say, to_dev
+from gpu_util import device_view, TOL, check, oracle_grads, params_dev, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ OPCFG = EvoConfig("op", n_seq=12, n_res=40, c_m=32, c_z=16, msa_heads=2, msa_hea
 def _setup(dtype, cfg=OPCFG, seed=7):
     from paper_2207_05477_amd import binding as B  # noqa: F401
     inp = make_inputs(cfg, seed=seed, perturb=True)
-    return round_inputs(inp, dtype)
+    return device_view(inp, dtype)
 
 
 def _zeros_like(p):

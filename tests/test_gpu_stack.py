@@ -6,9 +6,9 @@ import pytest
 import torch
 
 from oracle import evoformer as O
-from synth import EvoConfig, make_inputs, round_inputs
+from synth import EvoConfig, make_inputs
 
-from gpu_util import KINK_TOL, TOL, check, kink_free, say, to_dev
+from gpu_util import device_view, KINK_TOL, TOL, check, kink_free, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +19,7 @@ STACK = EvoConfig("stack3", n_seq=12, n_res=40, c_m=32, c_z=16, msa_heads=2, msa
 
 def _stack_run(cfg, dtype, seed, kinks=False, perturb=True):
     from paper_2207_05477_amd.autograd import EvoformerStack
-    inp = round_inputs(make_inputs(cfg, seed=seed, perturb=perturb), dtype)
+    inp = device_view(make_inputs(cfg, seed=seed, perturb=perturb), dtype)
     if not kinks:
         inp = kink_free(inp)
     model = EvoformerStack(cfg, inp["params"], "cuda")
