@@ -90,8 +90,9 @@ def time_steps(cfg, dtype, flat, w, steps, warmup):
     return t0.elapsed_time(t1) / steps
 
 
-def profile_steps(cfg, dtype, flat, w, steps):
-    """Per-kernel-instance event timings over `steps` steps (library profiler)."""
+def profile_steps(cfg, dtype, flat, w, steps, detail=False):
+    """Per-kernel-instance event timings over `steps` steps (library profiler);
+    with `detail`, keyed "kernel@sub-operation"."""
     from paper_2207_05477_amd import _abi as A
     lib = A.load()
 
@@ -101,12 +102,16 @@ def profile_steps(cfg, dtype, flat, w, steps):
     lib.evo_profile_begin.restype = None
     lib.evo_profile_end.argtypes = [ctypes.POINTER(Stat), ctypes.c_int32]
     lib.evo_profile_end.restype = ctypes.c_int32
+    lib.evo_profile_set_detail.argtypes = [ctypes.c_int32]
+    lib.evo_profile_set_detail.restype = None
     torch.cuda.synchronize()
+    lib.evo_profile_set_detail(1 if detail else 0)
     lib.evo_profile_begin()
     for _ in range(steps):
         step(cfg, dtype, flat, w)
-    recs = (Stat * 256)()
-    n = lib.evo_profile_end(recs, 256)
+    recs = (Stat * 1024)()
+    n = lib.evo_profile_end(recs, 1024)
+    lib.evo_profile_set_detail(0)
     if n < 0:
         raise RuntimeError(lib.evo_last_error().decode())
     out = []
@@ -118,9 +123,13 @@ def profile_steps(cfg, dtype, flat, w, steps):
 
 
 def roofline_of(stats, dtype):
+    """Roofline of the dominant kernel: MFMA-bound when its algorithmic
+    intensity (FLOP per algorithmic byte) is above the ridge point of `dtype`,
+    else HBM-bound."""
     top = stats[0]
     avg_ms = top["total_ms"] / top["launches"]
-    if top["flops"] > 0:
+    ridge = PEAK[dtype] / HBM_PEAK
+    if top["flops"] > 0 and (top["bytes"] <= 0 or top["flops"] / top["bytes"] >= ridge):
         achieved = top["flops"] / (top["total_ms"] * 1e-3) / 1e12
         peak = PEAK[dtype] / 1e12
         return {"kernel": top["name"], "bound": "mfma", "achieved": achieved, "peak": peak,
@@ -129,7 +138,24 @@ def roofline_of(stats, dtype):
     achieved = top["bytes"] / (top["total_ms"] * 1e-3) / 1e9
     peak = HBM_PEAK / 1e9
     return {"kernel": top["name"], "bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s",
-            "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms}
+            "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms, "launches_per_step": None}
+
+
+def print_breakdown(stats, dtype, steps, file=sys.stderr):
+    """Per-(kernel, sub-operation) time per step with each entry's own bound."""
+    ridge = PEAK[dtype] / HBM_PEAK
+    tot = sum(s["total_ms"] for s in stats) / steps
+    print(f"-- {dtype}: {tot:.3f} ms/step in {sum(s['launches'] for s in stats) // steps} launches", file=file)
+    for s in stats:
+        ms = s["total_ms"] / steps
+        sec = s["total_ms"] * 1e-3
+        if s["flops"] > 0 and (s["bytes"] <= 0 or s["flops"] / s["bytes"] >= ridge):
+            frac = s["flops"] / sec / PEAK[dtype]
+            kind = "mfma"
+        else:
+            frac = s["bytes"] / sec / HBM_PEAK
+            kind = "hbm"
+        print(f"{ms:8.3f} ms {s['launches'] // steps:4d}x {kind} {100 * frac:5.1f}%  {s['name']}", file=file)
 
 
 KERNEL_SOURCES = {"gemm_kernel": "gemm.hip", "attn_": "attn.hip", "ln_": "misc.hip", "gattn_": "gattn.hip"}
@@ -187,6 +213,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--only", choices=["f32", "bf16"], default=None)
+    ap.add_argument("--breakdown", action="store_true",
+                    help="print a per-(kernel, sub-operation) time breakdown to stderr")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -215,6 +243,9 @@ def main():
         roof = roofline_of(stats, "f32")
         roof["launches_per_step"] = stats[0]["launches"] / args.profile_steps
         roof["traffic"] = recorded_traffic(roof["kernel"], roof["launches_per_step"])
+        if args.breakdown:
+            print_breakdown(profile_steps(cfg, "f32", flat, w, args.profile_steps, detail=True), "f32",
+                            args.profile_steps)
         del w, flat, inp
 
     bf16 = None
@@ -226,6 +257,9 @@ def main():
         r16 = roofline_of(st16, "bf16")
         r16["launches_per_step"] = st16[0]["launches"] / args.profile_steps
         r16["traffic"] = recorded_traffic(r16["kernel"], r16["launches_per_step"])
+        if args.breakdown:
+            print_breakdown(profile_steps(cfg16, "bf16", flat, w, args.profile_steps, detail=True), "bf16",
+                            args.profile_steps)
         print(f"bf16 step {ms16:.3f} ms", file=sys.stderr, flush=True)
         bf16 = {"ms_per_step": ms16, "tflops": flops_step / (ms16 * 1e-3) / 1e12,
                 "speedup_vs_f32": (ms / ms16) if ms else None, "roofline": r16,

@@ -283,6 +283,9 @@ typedef struct {
 
 void evo_profile_begin(void);
 int32_t evo_profile_end(evo_kernel_stat_t* records, int32_t max_records);
+/* detail != 0: records are keyed "kernel@sub-operation" instead of by kernel
+ * instance alone (for a per-sub-operation breakdown). */
+void evo_profile_set_detail(int32_t detail);
 
 /* ------------------------------------------------------------------ misc */
 const char* evo_version(void);

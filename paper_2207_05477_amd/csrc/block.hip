@@ -80,21 +80,22 @@ static evo_status_t block_fwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   Scratch sc;
   sc.base = ws;
   const int col_kind = d.extra_msa ? EVO_ATTN_COL_GLOBAL : EVO_ATTN_COL;
-#define EVO_STEP(call)            \
+#define EVO_STEP(tag, call)       \
   do {                            \
+    ProfTag pt_(tag);             \
     Arena a = sc.fresh();         \
     EVO_TRY(call);                \
     sc.done(a);                   \
   } while (0)
-  EVO_STEP((attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_ROW), w.row_attn, m, z, mm, mo)));
-  EVO_STEP((attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, col_kind), w.col_attn, mo, nullptr, mm, mo)));
-  EVO_STEP((trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, true), w.msa_trans, mo, mo)));
-  EVO_STEP((opm_fwd_op<T, X>(c, a, a, block_opm_desc(d), w.opm, mo, mm, z, zo)));
-  EVO_STEP((trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, zo, pm, zo)));
-  EVO_STEP((trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, zo, pm, zo)));
-  EVO_STEP((attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, zo, nullptr, pm, zo)));
-  EVO_STEP((attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, zo, nullptr, pm, zo)));
-  EVO_STEP((trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, false), w.pair_trans, zo, zo)));
+  EVO_STEP("row.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_ROW), w.row_attn, m, z, mm, mo)));
+  EVO_STEP("col.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, col_kind), w.col_attn, mo, nullptr, mm, mo)));
+  EVO_STEP("msa_trans.fwd", (trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, true), w.msa_trans, mo, mo)));
+  EVO_STEP("opm.fwd", (opm_fwd_op<T, X>(c, a, a, block_opm_desc(d), w.opm, mo, mm, z, zo)));
+  EVO_STEP("tri_mul_out.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, zo, pm, zo)));
+  EVO_STEP("tri_mul_in.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, zo, pm, zo)));
+  EVO_STEP("tri_att_start.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, zo, nullptr, pm, zo)));
+  EVO_STEP("tri_att_end.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, zo, nullptr, pm, zo)));
+  EVO_STEP("pair_trans.fwd", (trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, false), w.pair_trans, zo, zo)));
 #undef EVO_STEP
   ws.off = sc.end();
   return EVO_OK;
@@ -152,44 +153,38 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   };
   Scratch sc;
   sc.base = ws;
-#define EVO_STEP(call)            \
+#define EVO_STEPS(i, tag, call)   \
   do {                            \
-    Arena a = sc.fresh();         \
-    EVO_TRY(call);                \
-    sc.done(a);                   \
-  } while (0)
-#define EVO_STEPS(i, call)        \
-  do {                            \
+    ProfTag pt_(tag);             \
     Arena a = sc.fresh();         \
     Arena s = S(i);               \
     EVO_TRY(call);                \
     sc.done(a);                   \
   } while (0)
   // recompute the forward, keeping what the backward needs
-  EVO_STEPS(0, (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, m1)));
-  EVO_STEPS(1, (attn_fwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, m2)));
-  EVO_STEPS(2, (trans_fwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, m3)));
-  EVO_STEPS(3, (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m3, mm, z, z1)));
-  EVO_STEPS(4, (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, z2)));
-  EVO_STEPS(5, (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, z3)));
-  EVO_STEPS(6, (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, z4)));
-  EVO_STEPS(7, (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, z5)));
-  EVO_STEPS(8, (trans_fwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, z6)));
+  EVO_STEPS(0, "row.recompute", (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, m1)));
+  EVO_STEPS(1, "col.recompute", (attn_fwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, m2)));
+  EVO_STEPS(2, "msa_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, m3)));
+  EVO_STEPS(3, "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m3, mm, z, z1)));
+  EVO_STEPS(4, "tri_mul_out.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, z2)));
+  EVO_STEPS(5, "tri_mul_in.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, z3)));
+  EVO_STEPS(6, "tri_att_start.recompute", (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, z4)));
+  EVO_STEPS(7, "tri_att_end.recompute", (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, z5)));
+  EVO_STEPS(8, "pair_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, z6)));
   // backward in reverse order; the pair gradient is updated in place in dz
   if (!c.dry) {
     EVO_TRY(copy_elems<X>(c, dzo, dz, RRc));
     EVO_TRY(copy_elems<X>(c, dmo, dm, SRc));
   }
-  EVO_STEPS(8, (trans_bwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, dz, dz, dw.pair_trans)));
-  EVO_STEPS(7, (attn_bwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, dz, dz, nullptr, dw.tri_att_end)));
-  EVO_STEPS(6, (attn_bwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, dz, dz, nullptr, dw.tri_att_start)));
-  EVO_STEPS(5, (trimul_bwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, dz, dz, dw.tri_mul_in)));
-  EVO_STEPS(4, (trimul_bwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, dz, dz, dw.tri_mul_out)));
-  EVO_STEPS(3, (opm_bwd_op<T, X>(c, a, s, d_opm, w.opm, m3, mm, dz, dm, dw.opm)));
-  EVO_STEPS(2, (trans_bwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, dm, dm, dw.msa_trans)));
-  EVO_STEPS(1, (attn_bwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, dm, dm, nullptr, dw.col_attn)));
-  EVO_STEPS(0, (attn_bwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, dm, dm, dz, dw.row_attn)));
-#undef EVO_STEP
+  EVO_STEPS(8, "pair_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, dz, dz, dw.pair_trans)));
+  EVO_STEPS(7, "tri_att_end.bwd", (attn_bwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, dz, dz, nullptr, dw.tri_att_end)));
+  EVO_STEPS(6, "tri_att_start.bwd", (attn_bwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, dz, dz, nullptr, dw.tri_att_start)));
+  EVO_STEPS(5, "tri_mul_in.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, dz, dz, dw.tri_mul_in)));
+  EVO_STEPS(4, "tri_mul_out.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, dz, dz, dw.tri_mul_out)));
+  EVO_STEPS(3, "opm.bwd", (opm_bwd_op<T, X>(c, a, s, d_opm, w.opm, m3, mm, dz, dm, dw.opm)));
+  EVO_STEPS(2, "msa_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, dm, dm, dw.msa_trans)));
+  EVO_STEPS(1, "col.bwd", (attn_bwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, dm, dm, nullptr, dw.col_attn)));
+  EVO_STEPS(0, "row.bwd", (attn_bwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, dm, dm, dz, dw.row_attn)));
 #undef EVO_STEPS
   ws.off = sc.end();
   return EVO_OK;

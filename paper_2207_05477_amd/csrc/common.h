@@ -75,6 +75,12 @@ evo_status_t check_launch(const char* what);
 // Launch profiler (see evo_profile_begin): slot handle or -1 when disabled.
 int prof_begin(const char* name, hipStream_t s, double flops, double bytes);
 void prof_end(int slot, hipStream_t s);
+// Sub-operation tag attached to the launches made while it is alive (detail mode).
+// Tags nest: a launch is keyed by the chain of live tags, outermost first.
+struct ProfTag {
+  explicit ProfTag(const char* tag);
+  ~ProfTag();
+};
 
 #define EVO_LAUNCH(name, flops, bytes, kernel, grid, block, lds, stream, ...)        \
   do {                                                                             \

@@ -54,9 +54,22 @@ hipEvent_t pool_event() {
 }
 }  // namespace
 
+thread_local std::vector<const char*> g_tags;
+bool g_prof_detail = false;
+std::vector<std::string> g_names;   // "kernel@tag/tag" names of the slots (detail mode)
+
+ProfTag::ProfTag(const char* tag) { g_tags.push_back(tag); }
+ProfTag::~ProfTag() { g_tags.pop_back(); }
+
 int prof_begin(const char* name, hipStream_t s, double flops, double bytes) {
   if (!g_prof_on) return -1;
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_prof_detail) {
+    std::string key = std::string(name) + "@";
+    for (size_t i = 0; i < g_tags.size(); ++i) key += (i ? "/" : "") + std::string(g_tags[i]);
+    g_names.push_back(key);
+    name = nullptr;
+  }
   ProfSlot sl{name, pool_event(), pool_event(), flops, bytes};
   if (!sl.a || !sl.b) return -1;
   hipEventRecord(sl.a, s);
@@ -235,7 +248,13 @@ extern "C" void evo_profile_begin(void) {
   std::lock_guard<std::mutex> lk(evo::g_prof_mu);
   for (auto& sl : evo::g_slots) { evo::g_pool.push_back(sl.a); evo::g_pool.push_back(sl.b); }
   evo::g_slots.clear();
+  evo::g_names.clear();
   evo::g_prof_on = true;
+}
+
+extern "C" void evo_profile_set_detail(int32_t detail) {
+  std::lock_guard<std::mutex> lk(evo::g_prof_mu);
+  evo::g_prof_detail = detail != 0;
 }
 
 extern "C" int32_t evo_profile_end(evo_kernel_stat_t* rec, int32_t max_records) {
@@ -243,11 +262,12 @@ extern "C" int32_t evo_profile_end(evo_kernel_stat_t* rec, int32_t max_records) 
   evo::g_prof_on = false;
   struct Agg { int64_t n = 0; double ms = 0, flops = 0, bytes = 0; };
   std::map<std::string, Agg> agg;
+  size_t ni = 0;
   for (auto& sl : evo::g_slots) {
     if (hipEventSynchronize(sl.b) != hipSuccess) { evo::set_error("profile: event wait failed"); return -1; }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, sl.a, sl.b) != hipSuccess) { evo::set_error("profile: elapsed failed"); return -1; }
-    Agg& a = agg[sl.name];
+    Agg& a = agg[sl.name ? std::string(sl.name) : evo::g_names[ni++]];
     a.n += 1; a.ms += ms; a.flops += sl.flops; a.bytes += sl.bytes;
   }
   int32_t k = 0;

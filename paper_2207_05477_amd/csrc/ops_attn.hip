@@ -316,6 +316,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
 
   // output projection
   {
+    ProfTag t_("out_proj");
     int off = 0, n = (int)s.cin;
     float* outs[1] = {dw.b_o};
     EVO_TRY(colsum_segments<X>(c, ws, dout, s.rows, s.cin, 1, &off, &n, outs));
@@ -328,10 +329,12 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY(gemm<T>(c, g));
   }
   if (s.global) {
+    ProfTag t_("core");
     EVO_TRY(gattn_bwd<T>(c, ws, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
                          S.st_inv, dgo, dqkvg));
   } else {
     // gate and attention core
+    ProfTag t_("core");
     EVO_TRY(gate_bwd<T>(c, s.rows, s.H, s.D, dgo, s.HC, S.o, s.HC, S.qkvg + 3 * s.HC, s.NQ, dctx,
                         s.HC, dqkvg + 3 * s.HC, s.NQ, Dsum));
     AttnGrad gr;
@@ -348,6 +351,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   }
   // gate bias and projection weights
   {
+    ProfTag t_("in_proj");
     int off = (int)(s.NQ - s.HC), n = s.HC;
     float* outs[1] = {dw.b_g};
     EVO_TRY(colsum_segments<T>(c, ws, dqkvg, s.rows, s.NQ, 1, &off, &n, outs));
@@ -365,6 +369,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   }
   // pair bias
   if (s.row) {
+    ProfTag t_("pair_bias");
     // the pair LayerNorm output is recomputed here (the forward projects it without storing it)
     const int64_t P = s.ni * s.ni;
     S.yz = ws.take_n<T>(P * s.cpair);
@@ -379,6 +384,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
                       part, &nb));
     if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)s.cpair, dw.ln_z_g, dw.ln_z_b));
   } else if (s.tri) {
+    ProfTag t_("pair_bias");
     EVO_TRY(rowproj_bwd<T>(c, ws, S.y, s.rows, (int)s.cin, w.w_bias, s.H, dbias, dy, true, dw.w_bias));
   }
   // input LayerNorm and residual

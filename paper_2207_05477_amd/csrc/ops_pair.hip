@@ -399,6 +399,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   }
   EVO_TRY(trimul_proj<T>(c, P, (int)ch, (int)cz, S.raw, mask, S.a, S.b, P, S.g));
   {  // per-channel contraction, channel-major operands [ch][R][R]
+    ProfTag t_("contract");
     GemmArgs g;
     g.M = R; g.N = R; g.K = R; g.batch = (int)ch;
     if (d.dir == EVO_TRI_OUT) {   // X_c = A_c B_c^T
@@ -486,6 +487,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)ch, dw.ln_out_g, dw.ln_out_b));
   }
   if (!c.dry) {
+    ProfTag t_("contract");
     GemmArgs g;
     g.M = R; g.N = R; g.K = R; g.batch = (int)ch;
     if (d.dir == EVO_TRI_OUT) {
@@ -522,7 +524,10 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   float* obp[5] = {dw.b_ap, dw.b_ag, dw.b_bp, dw.b_bg, dw.b_g};
   EVO_TRY(colsum_segments<T>(c, ws, draw, P, NP, 5, offs, ns, obp));
   float* owp[5] = {dw.w_ap, dw.w_ag, dw.w_bp, dw.w_bg, dw.w_g};
-  for (int s = 0; s < 5; ++s) EVO_TRY(wgrad<T>(c, ws, S.y, cz, draw + offs[s], NP, P, cz, ns[s], owp[s]));
+  {
+    ProfTag t_("wgrad_proj");
+    for (int s = 0; s < 5; ++s) EVO_TRY(wgrad<T>(c, ws, S.y, cz, draw + offs[s], NP, P, cz, ns[s], owp[s]));
+  }
   if (!c.dry) {
     GemmArgs g;
     g.M = P; g.N = cz; g.K = NP;

@@ -31,7 +31,7 @@ def test_header_functions_are_exported_and_bound():
     assert len(declared) >= 24
     for name in declared:
         assert hasattr(lib, name), f"libevo.so does not export {name}"
-    missing = set(declared) - set(A.EXPORTS) - {"evo_profile_begin", "evo_profile_end"}
+    missing = set(declared) - set(A.EXPORTS) - {"evo_profile_begin", "evo_profile_end", "evo_profile_set_detail"}
     assert not missing, f"binding lacks prototypes for {missing}"
 
 
