@@ -121,7 +121,7 @@ evo_status_t gattn_fwd(const Ctx& c, int64_t S, int64_t R, int H, int D, const T
 // dg (pre-sigmoid) for every row; dctx[i][h][d] = sum_s dgo * g.
 template <typename T>
 __global__ __launch_bounds__(256) void gattn_gate_bwd_kernel(int64_t S, int64_t R, int H, int D, const T* qkvg,
-                                                             const float* gctx, const T* dgo, T* dqkvg) {
+                                                             const float* gctx, const float* dgo, T* dqkvg) {
   const int HC = H * D, NQ = 2 * HC + 2 * D;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= S * R * HC) return;
@@ -129,12 +129,12 @@ __global__ __launch_bounds__(256) void gattn_gate_bwd_kernel(int64_t S, int64_t 
   const int c = (int)(e % HC);
   const int64_t i = row % R;
   const float g = to_f32(qkvg[row * NQ + HC + 2 * D + c]);
-  dqkvg[row * NQ + HC + 2 * D + c] = from_f32<T>(to_f32(dgo[e]) * gctx[i * HC + c] * g * (1.f - g));
+  dqkvg[row * NQ + HC + 2 * D + c] = from_f32<T>(dgo[e] * gctx[i * HC + c] * g * (1.f - g));
 }
 
 template <typename T>
 __global__ __launch_bounds__(GA_THREADS) void gattn_bwd_kernel(int64_t S, int64_t R, int H, int D, const T* qkvg,
-                                                               const float* mask, float eps, const T* dgo,
+                                                               const float* mask, float eps, const float* dgo,
                                                                T* dqkvg) {
   extern __shared__ float sm[];
   const int HC = H * D, NQ = 2 * HC + 2 * D;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(GA_THREADS) void gattn_bwd_kernel(int64_t S, int64_
   for (int e = threadIdx.x; e < HC; e += GA_THREADS) {
     float acc = 0.f;
     for (int64_t s = 0; s < S; ++s)
-      acc += to_f32(dgo[(s * R + i) * HC + e]) * to_f32(qkvg[(s * R + i) * NQ + HC + 2 * D + e]);
+      acc += dgo[(s * R + i) * HC + e] * to_f32(qkvg[(s * R + i) * NQ + HC + 2 * D + e]);
     dctx[e] = acc;
   }
   __syncthreads();
@@ -215,13 +215,13 @@ __global__ __launch_bounds__(GA_THREADS) void gattn_bwd_kernel(int64_t S, int64_
 template <typename T>
 evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int D, const T* qkvg,
                        const float* mask, float eps, const float* gctx, const float* smax, const float* sinv,
-                       const T* dgo, T* dqkvg) {
+                       const float* dgo, T* dqkvg) {
   (void)ws; (void)smax; (void)sinv;
   if (c.dry) return EVO_OK;
   const size_t lds = (8 + 3 * (size_t)H * D + 2 * (size_t)H * S) * sizeof(float);
   if (lds > 150 * 1024) { set_error("global attention bwd: %lld rows exceed LDS", (long long)S); return EVO_ESHAPE; }
   const int64_t n = S * R * H * D;
-  EVO_LAUNCH(EVO_KNAME("gattn_gate_bwd_kernel", T), 0.0, (double)n * 3 * sizeof(T), (gattn_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, S, R,
+  EVO_LAUNCH(EVO_KNAME("gattn_gate_bwd_kernel", T), 0.0, (double)n * (4.0 + 2 * sizeof(T)), (gattn_gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, S, R,
                      H, D, qkvg, gctx, dgo, dqkvg);
   EVO_TRY(check_launch("gattn_gate_bwd"));
   EVO_LAUNCH(EVO_KNAME("gattn_bwd_kernel", T), 8.0 * (double)S * R * H * D, (double)S * R * (3 * H * D + 4 * D) * sizeof(T), (gattn_bwd_kernel<T>), dim3((unsigned)R), dim3(GA_THREADS), lds, c.stream, S, R, H, D, qkvg,
@@ -236,6 +236,6 @@ template evo_status_t gattn_fwd<bf16>(const Ctx&, int64_t, int64_t, int, int, co
 template evo_status_t gattn_bwd<float>(const Ctx&, Arena&, int64_t, int64_t, int, int, const float*, const float*,
                                        float, const float*, const float*, const float*, const float*, float*);
 template evo_status_t gattn_bwd<bf16>(const Ctx&, Arena&, int64_t, int64_t, int, int, const bf16*, const float*,
-                                      float, const float*, const float*, const float*, const bf16*, bf16*);
+                                      float, const float*, const float*, const float*, const float*, bf16*);
 
 }  // namespace evo

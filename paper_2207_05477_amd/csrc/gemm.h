@@ -42,8 +42,9 @@ struct GemmEpilogue {
   int32_t sm_shift = 0, sn_shift = 0;
   int64_t sm_ld = 0, sn_ld = 0;
   const void* relu_ref = nullptr;      // kernel type, addressed like resid
-  const void* gate = nullptr;          // kernel type, gate[m * g_m + n * g_n]
+  const void* gate = nullptr;          // kernel type (FP32 if gate_f32), gate[m * g_m + n * g_n]
   int64_t g_m = 0, g_n = 0;
+  int32_t gate_f32 = 0;
   const void* resid = nullptr;         // kernel type (FP32 if resid_f32), resid[m * r_m + n * r_n]
                                        // (r_m < 0 / g_m < 0: addressed like the output)
   int64_t r_m = 0, r_n = 0;

@@ -85,7 +85,10 @@ EVO_DEV void epilogue_apply(const GemmEpilogue& e, int z, int64_t m, int64_t n, 
     float r = to_f32(((const T*)e.relu_ref)[roff]);
     v = r > 0.0f ? v : 0.0f;
   }
-  if (e.gate) v *= to_f32(((const T*)e.gate)[e.g_m < 0 ? off : zo + m * e.g_m + n * e.g_n]);
+  if (e.gate) {
+    const int64_t goff = e.g_m < 0 ? off : zo + m * e.g_m + n * e.g_n;
+    v *= e.gate_f32 ? ((const float*)e.gate)[goff] : to_f32(((const T*)e.gate)[goff]);
+  }
   if (e.resid) v += e.resid_f32 ? ((const float*)e.resid)[roff] : to_f32(((const T*)e.resid)[roff]);
   if (e.out_f32) {
     float* o = (float*)e.out + off;
@@ -238,8 +241,8 @@ static void launch(const Ctx& ctx, const GemmArgs& g) {
   const double flops = 2.0 * mn * g.K * nb;
   double bytes = ((double)g.M * g.K + (double)g.N * g.K) * sizeof(T) * nb +
                  mn * nout * (g.epi.out_f32 ? 4.0 : sizeof(T)) * (g.epi.accumulate ? 2.0 : 1.0);
-  if (g.epi.resid) bytes += mn * nb * sizeof(T);
-  if (g.epi.gate) bytes += mn * nb * sizeof(T);
+  if (g.epi.resid) bytes += mn * nb * (g.epi.resid_f32 ? 4.0 : (double)sizeof(T));
+  if (g.epi.gate) bytes += mn * nb * (g.epi.gate_f32 ? 4.0 : (double)sizeof(T));
   if (g.epi.relu_ref) bytes += mn * nb * sizeof(T);
   EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW>), grid, dim3(256), 0, ctx.stream, g);
 }

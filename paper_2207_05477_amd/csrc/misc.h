@@ -18,9 +18,9 @@ evo_status_t ln_fwd_rows(const Ctx& c, const TI* x, int64_t rows, int C, int rsh
 template <typename TI, typename TO = TI>
 evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
                         float eps, const float* W, int H, float* out);
-// Channel-major input x[C][P] -> y[P][C].
+// Channel-major FP32 input x[C][P] -> y[P][C].
 template <typename T>
-evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
+evo_status_t ln_fwd_cm(const Ctx& c, const float* x, int64_t P, int C, const float* g, const float* b,
                        float eps, T* y, float* mean, float* rstd);
 // dx = base + LayerNorm_backward(dy): base = resid (may alias dx) when given, else dx itself
 // when accumulate, else 0.  dgamma/dbeta partial sums go to part[nblk][2*C].
@@ -29,9 +29,9 @@ evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rs
                     const float* dy, int64_t rows, int C, const T* resid, bool accumulate, T* dx,
                     float* part, int* nblk);
 int64_t ln_bwd_partials(int64_t rows);
-// Channel-major x[C][P], dy[P][C] -> dx[C][P].
+// Channel-major FP32 x[C][P], dy[P][C] -> dx[C][P].
 template <typename T>
-evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
+evo_status_t ln_bwd_cm(const Ctx& c, const float* x, const float* mean, const float* rstd, const float* g,
                        const float* dy, int64_t P, int C, T* dx, float* part, int* nblk);
 int64_t ln_bwd_cm_partials(int64_t P);
 
@@ -74,26 +74,26 @@ evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n);
 
 // Attention gate backward. Per row r and head h (c = head_dim):
 //   dctx = dgo * g; dgpre = dgo * o * g (1 - g); D[r*H+h] = sum_d dctx * o
-// go/o/g/dgo have row pitches; dctx written with pitch ld_dctx, dgpre with ld_dg.
+// go/o/g/dgo have row pitches; dctx written with pitch ld_dctx, dgpre with ld_dg.  dgo is FP32.
 template <typename T>
-evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, int64_t ld_dgo,
+evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
                       const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
                       T* dgpre, int64_t ld_dg, float* D);
 
-// Triangle multiplication projections, forward: raw[p][4*ch + cz] (ap | ag | bp | bg | g)
-// -> a[c][p], b[c][p] (channel-major, masked, gated), g[p][cz] = sigmoid(raw g).
+// Triangle multiplication projections, forward: FP32 raw[p][4*ch + cz] (ap | ag | bp | bg | g)
+// -> a[c][p], b[c][p] (channel-major, masked, gated), FP32 g[p][cz] = sigmoid(raw g).
 // a and b have channel stride ld_ab (>= P; pointers may be offset into larger tensors).
 template <typename T>
-evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
-                         T* a, T* b, int64_t ld_ab, T* g);
-// Backward: da, db channel-major -> draw[p][4*ch] columns of ap, ag, bp, bg.
+evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* raw, const float* mask,
+                         T* a, T* b, int64_t ld_ab, float* g);
+// Backward: FP32 da, db channel-major -> draw[p][4*ch] columns of ap, ag, bp, bg.
 template <typename T>
-evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
-                             const float* mask, const T* da, const T* db, T* draw);
-// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g).
+evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const float* raw,
+                             const float* mask, const float* da, const float* db, T* draw);
+// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g)  (t, g FP32).
 template <typename T, typename X = T>
-evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const T* t,
-                             const T* g, T* dt, T* draw);
+evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
+                             const float* g, T* dt, T* draw);
 
 // scale[i*R + j] = 1 / (eps + sum_s mask[s,i] mask[s,j])  (mask NULL: all ones).
 evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, float eps, float* scale);

@@ -127,7 +127,7 @@ evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const fl
 
 // Channel-major forward: a block owns 64 positions; x tile [C][64] staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const T* __restrict__ x, int64_t P, int C,
+__global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const float* __restrict__ x, int64_t P, int C,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ b, float eps,
                                                         T* __restrict__ y, float* __restrict__ mean,
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const T* __restrict__ x,
   for (int e = tid; e < C * 64; e += 256) {
     const int cc = e >> 6, pp = e & 63;
     const int64_t p = p0 + pp;
-    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
+    tile[cc * 65 + pp] = p < P ? x[(int64_t)cc * P + p] : 0.f;
   }
   __syncthreads();
   for (int pp = wave * 16; pp < wave * 16 + 16; ++pp) {
@@ -160,12 +160,12 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const T* __restrict__ x,
 }
 
 template <typename T>
-evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
+evo_status_t ln_fwd_cm(const Ctx& c, const float* x, int64_t P, int C, const float* g, const float* b,
                        float eps, T* y, float* mean, float* rstd) {
   if (c.dry || P == 0) return EVO_OK;
   if (C > 512) { set_error("layernorm(cm): C=%d > 512", C); return EVO_ESHAPE; }
   size_t lds = (size_t)C * 65 * sizeof(float);
-  EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_kernel", T), 0.0, (double)P * C * 2 * sizeof(T) + P * 8.0, (ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
+  EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_kernel", T), 0.0, (double)P * C * (4.0 + sizeof(T)) + P * 8.0, (ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
                      x, P, C, g, b, eps, y, mean, rstd);
   return check_launch("ln_fwd_cm");
 }
@@ -255,7 +255,7 @@ evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rs
 int64_t ln_bwd_cm_partials(int64_t P) { return (P + 63) / 64; }
 
 template <typename T>
-__global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const T* __restrict__ x,
+__global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const float* __restrict__ x,
                                                         const float* __restrict__ mean,
                                                         const float* __restrict__ rstd,
                                                         const float* __restrict__ g,
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const T* __restrict__ x,
   for (int e = tid; e < C * 64; e += 256) {
     const int cc = e >> 6, pp = e & 63;
     const int64_t p = p0 + pp;
-    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
+    tile[cc * 65 + pp] = p < P ? x[(int64_t)cc * P + p] : 0.f;
   }
   for (int e = tid; e < 8 * C; e += 256) red[e] = 0.f;
   __syncthreads();
@@ -311,13 +311,13 @@ __global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const T* __restrict__ x,
 }
 
 template <typename T>
-evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
+evo_status_t ln_bwd_cm(const Ctx& c, const float* x, const float* mean, const float* rstd, const float* g,
                        const float* dy, int64_t P, int C, T* dx, float* part, int* nblk) {
   *nblk = (int)ln_bwd_cm_partials(P);
   if (c.dry || P == 0) return EVO_OK;
   if (C > 256) { set_error("layernorm bwd(cm): C=%d > 256", C); return EVO_ESHAPE; }
   size_t lds = ((size_t)C * 65 + 8 * C) * sizeof(float);
-  EVO_LAUNCH(EVO_KNAME("ln_bwd_cm_kernel", T), 0.0, (double)P * C * (2 * sizeof(T) + 4.0) + P * 8.0, (ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
+  EVO_LAUNCH(EVO_KNAME("ln_bwd_cm_kernel", T), 0.0, (double)P * C * (8.0 + sizeof(T)) + P * 8.0, (ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
                      rstd, g, dy, P, C, dx, part);
   return check_launch("ln_bwd_cm");
 }
@@ -488,7 +488,7 @@ evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n) {
 
 // ============================================================== attention gate backward
 template <typename T>
-__global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int hd, const T* dgo,
+__global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int hd, const float* dgo,
                                                        int64_t ld_dgo, const T* o, int64_t ld_o,
                                                        const T* g, int64_t ld_g, T* dctx,
                                                        int64_t ld_dctx, T* dgp, int64_t ld_dg,
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int 
   const int col = (int)(e % HC);
   float contrib = 0.f;
   if (row < rows) {
-    const float dy = to_f32(dgo[row * ld_dgo + col]);
+    const float dy = dgo[row * ld_dgo + col];
     const float ov = to_f32(o[row * ld_o + col]);
     const float gv = to_f32(g[row * ld_g + col]);
     const float dc = dy * gv;
@@ -513,12 +513,12 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int 
 }
 
 template <typename T>
-evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, int64_t ld_dgo,
+evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
                       const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
                       T* dgpre, int64_t ld_dg, float* D) {
   if (c.dry || rows == 0) return EVO_OK;
   const int64_t n = rows * H * hd;
-  EVO_LAUNCH(EVO_KNAME("gate_bwd_kernel", T), 0.0, (double)n * 5 * sizeof(T) + rows * H * 4.0, (gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+  EVO_LAUNCH(EVO_KNAME("gate_bwd_kernel", T), 0.0, (double)n * (4.0 + 4 * sizeof(T)) + rows * H * 4.0, (gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                      rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
   return check_launch("gate_bwd");
 }
@@ -527,7 +527,7 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const T* dgo, i
 // Tiles of 64 positions x 32 channels, transposed through LDS so that both the
 // row-major projection output and the channel-major operands move coalesced.
 template <typename T>
-__global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int cz, const T* raw,
+__global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int cz, const float* raw,
                                                           const float* mask, T* a, T* b, int64_t ld_ab) {
   __shared__ float ta[32][65], tb[32][65];
   const int tid = threadIdx.x;
@@ -540,10 +540,10 @@ __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int
     const int c = c0 + cc;
     float va = 0.f, vb = 0.f;
     if (p < P && c < ch) {
-      const T* r = raw + p * ld;
+      const float* r = raw + p * ld;
       const float mk = mask ? mask[p] : 1.f;
-      va = mk * sigmoidf_(to_f32(r[ch + c])) * to_f32(r[c]);
-      vb = mk * sigmoidf_(to_f32(r[3 * ch + c])) * to_f32(r[2 * ch + c]);
+      va = mk * sigmoidf_(r[ch + c]) * r[c];
+      vb = mk * sigmoidf_(r[3 * ch + c]) * r[2 * ch + c];
     }
     ta[cc][pp] = va;
     tb[cc][pp] = vb;
@@ -560,32 +560,32 @@ __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void sigmoid_cols_kernel(int64_t P, int ch, int cz, const T* raw, T* g) {
+__global__ __launch_bounds__(256) void sigmoid_cols_kernel(int64_t P, int ch, int cz, const float* raw,
+                                                           float* g) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= P * cz) return;
   const int64_t p = e / cz;
   const int n = (int)(e % cz);
-  g[e] = from_f32<T>(sigmoidf_(to_f32(raw[p * (4 * ch + cz) + 4 * ch + n])));
+  g[e] = sigmoidf_(raw[p * (4 * ch + cz) + 4 * ch + n]);
 }
 
 template <typename T>
-evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
-                         T* a, T* b, int64_t ld_ab, T* g) {
+evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* raw, const float* mask,
+                         T* a, T* b, int64_t ld_ab, float* g) {
   if (c.dry || P == 0) return EVO_OK;
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
-  EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * 6 * sizeof(T), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
+  EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * (16.0 + 2 * sizeof(T)), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
   EVO_TRY(check_launch("trimul_proj"));
   const int64_t n = P * cz;
-  EVO_LAUNCH(EVO_KNAME("sigmoid_cols_kernel", T), 0.0, (double)n * 2 * sizeof(T), (sigmoid_cols_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+  EVO_LAUNCH("sigmoid_cols_kernel", 0.0, (double)n * 8.0, sigmoid_cols_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                      P, ch, cz, raw, g);
   return check_launch("trimul_gate");
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch, int cz, const T* raw,
-                                                              const float* mask, const T* da,
-                                                              const T* db, T* draw) {
+__global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch, int cz, const float* raw,
+                                                              const float* mask, const float* da,
+                                                              const float* db, T* draw) {
   __shared__ float ta[32][65], tb[32][65];
   const int tid = threadIdx.x;
   const int64_t p0 = (int64_t)blockIdx.x * 64;
@@ -595,8 +595,8 @@ __global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch,
     const int cc = e >> 6, pp = e & 63;
     const int64_t p = p0 + pp;
     const int c = c0 + cc;
-    ta[cc][pp] = (p < P && c < ch) ? to_f32(da[(int64_t)c * P + p]) : 0.f;
-    tb[cc][pp] = (p < P && c < ch) ? to_f32(db[(int64_t)c * P + p]) : 0.f;
+    ta[cc][pp] = (p < P && c < ch) ? da[(int64_t)c * P + p] : 0.f;
+    tb[cc][pp] = (p < P && c < ch) ? db[(int64_t)c * P + p] : 0.f;
   }
   __syncthreads();
   for (int e = tid; e < 64 * 32; e += 256) {
@@ -604,11 +604,11 @@ __global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch,
     const int64_t p = p0 + pp;
     const int c = c0 + cc;
     if (p < P && c < ch) {
-      const T* r = raw + p * ld;
+      const float* r = raw + p * ld;
       T* d = draw + p * ld;
       const float mk = mask ? mask[p] : 1.f;
-      const float ap = to_f32(r[c]), sa = sigmoidf_(to_f32(r[ch + c]));
-      const float bp = to_f32(r[2 * ch + c]), sb = sigmoidf_(to_f32(r[3 * ch + c]));
+      const float ap = r[c], sa = sigmoidf_(r[ch + c]);
+      const float bp = r[2 * ch + c], sb = sigmoidf_(r[3 * ch + c]);
       const float dav = ta[cc][pp] * mk, dbv = tb[cc][pp] * mk;
       d[c] = from_f32<T>(dav * sa);
       d[ch + c] = from_f32<T>(dav * ap * sa * (1.f - sa));
@@ -619,32 +619,33 @@ __global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch,
 }
 
 template <typename T>
-evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
-                             const float* mask, const T* da, const T* db, T* draw) {
+evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const float* raw,
+                             const float* mask, const float* da, const float* db, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
-  EVO_LAUNCH(EVO_KNAME("trimul_proj_bwd_kernel", T), 0.0, (double)P * ch * 10 * sizeof(T), (trimul_proj_bwd_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, da, db, draw);
+  EVO_LAUNCH(EVO_KNAME("trimul_proj_bwd_kernel", T), 0.0, (double)P * ch * (24.0 + 4 * sizeof(T)), (trimul_proj_bwd_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, da, db, draw);
   return check_launch("trimul_proj_bwd");
 }
 
 template <typename T, typename X>
 __global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch, int cz, const X* dz,
-                                                              const T* t, const T* g, T* dt, T* draw) {
+                                                              const float* t, const float* g, T* dt,
+                                                              T* draw) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= P * cz) return;
   const int64_t p = e / cz;
   const int n = (int)(e % cz);
-  const float d = to_f32(dz[e]), gv = to_f32(g[e]), tv = to_f32(t[e]);
+  const float d = to_f32(dz[e]), gv = g[e], tv = t[e];
   dt[e] = from_f32<T>(d * gv);
   draw[p * (4 * ch + cz) + 4 * ch + n] = from_f32<T>(d * tv * gv * (1.f - gv));
 }
 
 template <typename T, typename X>
-evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const T* t,
-                             const T* g, T* dt, T* draw) {
+evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
+                             const float* g, T* dt, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   const int64_t n = P * cz;
-  EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", X), 0.0, (double)n * 5 * sizeof(T), (trimul_gate_bwd_kernel<T, X>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+  EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", X), 0.0, (double)n * (sizeof(X) + 8.0 + 2 * sizeof(T)), (trimul_gate_bwd_kernel<T, X>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      c.stream, P, ch, cz, dz, t, g, dt, draw);
   return check_launch("trimul_gate_bwd");
 }
@@ -680,11 +681,11 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
                                           const float*, const float*, float, T*, float*, float*);  \
   template evo_status_t ln_rowproj<T, T>(const Ctx&, const T*, int64_t, int, const float*,         \
                                          const float*, float, const float*, int, float*);          \
-  template evo_status_t ln_fwd_cm<T>(const Ctx&, const T*, int64_t, int, const float*,             \
+  template evo_status_t ln_fwd_cm<T>(const Ctx&, const float*, int64_t, int, const float*,         \
                                      const float*, float, T*, float*, float*);                     \
   template evo_status_t ln_bwd<T>(const Ctx&, const T*, const float*, const float*, const float*,  \
                                   const float*, int64_t, int, const T*, bool, T*, float*, int*);   \
-  template evo_status_t ln_bwd_cm<T>(const Ctx&, const T*, const float*, const float*,             \
+  template evo_status_t ln_bwd_cm<T>(const Ctx&, const float*, const float*, const float*,         \
                                      const float*, const float*, int64_t, int, T*, float*, int*);  \
   template evo_status_t colsum_partial<T>(const Ctx&, const T*, int64_t, int, int64_t, float*,     \
                                           int*);                                                   \
@@ -692,14 +693,14 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t pack_params<T>(const Ctx&, const PackArgs&);                               \
   template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \
   template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
-  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const T*, int64_t, const T*,    \
+  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t, const T*, \
                                     int64_t, const T*, int64_t, T*, int64_t, T*, int64_t, float*); \
-  template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const T*, const float*, T*,  \
-                                       T*, int64_t, T*);                                           \
-  template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const T*, const float*,  \
-                                           const T*, const T*, T*);                                \
-  template evo_status_t trimul_gate_bwd<T, T>(const Ctx&, int64_t, int, int, const T*, const T*,   \
-                                              const T*, T*, T*);
+  template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const float*, const float*,  \
+                                       T*, T*, int64_t, float*);                                   \
+  template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const float*,           \
+                                           const float*, const float*, const float*, T*);          \
+  template evo_status_t trimul_gate_bwd<T, T>(const Ctx&, int64_t, int, int, const T*,           \
+                                              const float*, const float*, T*, T*);
 
 EVO_INST(float)
 EVO_INST(bf16)
@@ -711,8 +712,8 @@ template evo_status_t ln_fwd_rows<float, bf16>(const Ctx&, const float*, int64_t
                                                const float*, const float*, float, bf16*, float*, float*);
 template evo_status_t ln_rowproj<float, bf16>(const Ctx&, const float*, int64_t, int, const float*,
                                               const float*, float, const float*, int, float*);
-template evo_status_t trimul_gate_bwd<bf16, float>(const Ctx&, int64_t, int, int, const float*, const bf16*,
-                                                   const bf16*, bf16*, bf16*);
+template evo_status_t trimul_gate_bwd<bf16, float>(const Ctx&, int64_t, int, int, const float*, const float*,
+                                                   const float*, bf16*, bf16*);
 template evo_status_t convert_elems<float, bf16>(const Ctx&, const float*, bf16*, int64_t);
 template evo_status_t convert_elems<bf16, float>(const Ctx&, const bf16*, float*, int64_t);
 template evo_status_t convert_elems<float, float>(const Ctx&, const float*, float*, int64_t);

@@ -103,7 +103,7 @@ evo_status_t gattn_fwd(const Ctx& c, int64_t S, int64_t R, int H, int D, const T
 template <typename T>
 evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int D, const T* qkvg,
                        const float* mask, float eps, const float* gctx, const float* smax,
-                       const float* sinv, const T* dgo, T* dqkvg);
+                       const float* sinv, const float* dgo, T* dqkvg);
 
 // Forward of triangle attention in chunks of `chunk` batch rows (starting node:
 // rows i; ending node: columns j), keeping no saved state.  Only the chunk's
@@ -275,7 +275,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   EVO_TRY(cst);
   T* w_qkvg = ws.take_n<T>((int64_t)s.cin * s.NQ);     // [c_in][NQ]
   T* w_o = ws.take_n<T>((int64_t)s.HC * s.cin);        // [HC][c_in]
-  T* dgo = ws.take_n<T>(s.rows * s.HC);
+  float* dgo = ws.take_n<float>(s.rows * s.HC);   // FP32: consumed by the gate backward only
   T* dctx = s.global ? nullptr : ws.take_n<T>(s.rows * s.HC);
   T* dqkvg = ws.take_n<T>(s.rows * s.NQ);
   float* Dsum = s.global ? nullptr : ws.take_n<float>(s.rows * s.H);
@@ -325,7 +325,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     g.M = s.rows; g.N = s.HC; g.K = s.cin;
     g.A = op_rowmajor(dout_t, s.cin);
     g.B = op_rowmajor(w_o, s.cin);
-    g.epi = epi_rowmajor(dgo, s.HC, false);
+    g.epi = epi_rowmajor(dgo, s.HC, true);
     EVO_TRY(gemm<T>(c, g));
   }
   if (s.global) {

@@ -267,17 +267,20 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
 // ============================================================== triangle multiplication
 template <typename T>
 struct TriSaved {
-  T* y; float* mean; float* rstd; T* raw; T* a; T* b; T* g; T* x; T* xn; float* mean2; float* rstd2;
+  // raw (projection output), g (output gate) and x (contraction output) feed
+  // only elementwise work and LayerNorm: FP32 whatever the compute type.
+  T* y; float* mean; float* rstd; float* raw; T* a; T* b; float* g; float* x; T* xn; float* mean2;
+  float* rstd2;
   void carve(Arena& ar, const evo_trimul_desc_t& d) {
     const int64_t P = d.n_res * d.n_res, ch = d.c_hidden, cz = d.c_z;
     y = ar.take_n<T>(P * cz);
     mean = ar.take_n<float>(P);
     rstd = ar.take_n<float>(P);
-    raw = ar.take_n<T>(P * (4 * ch + cz));
+    raw = ar.take_n<float>(P * (4 * ch + cz));
     a = ar.take_n<T>(P * ch);
     b = ar.take_n<T>(P * ch);
-    g = ar.take_n<T>(P * cz);
-    x = ar.take_n<T>(P * ch);
+    g = ar.take_n<float>(P * cz);
+    x = ar.take_n<float>(P * ch);
     xn = ar.take_n<T>(P * ch);
     mean2 = ar.take_n<float>(P);
     rstd2 = ar.take_n<float>(P);
@@ -298,12 +301,12 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
   T* wt_o = ws.take_n<T>(cz * ch);
   T* a = ws.take_n<T>(P * ch);
   T* b = ws.take_n<T>(P * ch);
-  T* g = ws.take_n<T>(P * cz);
+  float* g = ws.take_n<float>(P * cz);
   T* y = ws.take_n<T>(CR * cz);
   float* mean = ws.take_n<float>(CR);
   float* rstd = ws.take_n<float>(CR);
-  T* raw = ws.take_n<T>(CR * NP);
-  T* x = ws.take_n<T>(CR * ch);
+  float* raw = ws.take_n<float>(CR * NP);
+  float* x = ws.take_n<float>(CR * ch);
   T* xn = ws.take_n<T>(CR * ch);
   if (c.dry) return EVO_OK;
   PackArgs pp;
@@ -326,7 +329,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
     gp.M = CR; gp.N = NP; gp.K = cz;
     gp.A = op_rowmajor(y, cz);
     gp.B = op_rowmajor(wt_p, cz);
-    gp.epi = epi_rowmajor(raw, NP, false);
+    gp.epi = epi_rowmajor(raw, NP, true);
     gp.epi.bias = b_p;
     EVO_TRY(gemm<T>(c, gp));
     EVO_TRY(trimul_proj<T>(c, CR, (int)ch, (int)cz, raw, mask ? mask + p0 : nullptr, a + p0, b + p0, P,
@@ -346,7 +349,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
       gx.B = op_colmajor(b, R);
     }
     gx.A.batch = P; gx.B.batch = P;
-    gx.epi = epi_rowmajor(x, R, false);
+    gx.epi = epi_rowmajor(x, R, true);
     gx.epi.batch = CR;
     EVO_TRY(gemm<T>(c, gx));
     EVO_TRY(ln_fwd_cm<T>(c, x, CR, (int)ch, w.ln_out_g, w.ln_out_b, d.ln_eps, xn, mean2, rstd2));
@@ -356,7 +359,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
     go.B = op_rowmajor(wt_o, ch);
     epi_out<X>(go.epi, zout + p0 * cz, cz);
     go.epi.bias = w.b_o;
-    go.epi.gate = g + p0 * cz; go.epi.g_m = cz; go.epi.g_n = 1;
+    go.epi.gate = g + p0 * cz; go.epi.g_m = cz; go.epi.g_n = 1; go.epi.gate_f32 = 1;
     epi_resid<X>(go.epi, z + p0 * cz, cz, 1);
     EVO_TRY(gemm<T>(c, go));
   }
@@ -393,7 +396,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     g.M = P; g.N = NP; g.K = cz;
     g.A = op_rowmajor(S.y, cz);
     g.B = op_rowmajor(wt_p, cz);
-    g.epi = epi_rowmajor(S.raw, NP, false);
+    g.epi = epi_rowmajor(S.raw, NP, true);
     g.epi.bias = b_p;
     EVO_TRY(gemm<T>(c, g));
   }
@@ -410,7 +413,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
       g.B = op_colmajor(S.b, R);
     }
     g.A.batch = P; g.B.batch = P;
-    g.epi = epi_rowmajor(S.x, R, false);
+    g.epi = epi_rowmajor(S.x, R, true);
     g.epi.batch = P;
     EVO_TRY(gemm<T>(c, g));
   }
@@ -421,7 +424,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   g.B = op_rowmajor(wt_o, ch);
   epi_out<X>(g.epi, zout, cz);
   g.epi.bias = w.b_o;
-  g.epi.gate = S.g; g.epi.g_m = cz; g.epi.g_n = 1;
+  g.epi.gate = S.g; g.epi.g_m = cz; g.epi.g_n = 1; g.epi.gate_f32 = 1;
   epi_resid<X>(g.epi, z, cz, 1);
   return gemm<T>(c, g);
 }
@@ -436,13 +439,13 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   T* w_p = ws.take_n<T>(cz * NP);      // [cz][NP]
   T* wt_o = ws.take_n<T>(cz * ch);     // [cz][ch]
   T* w_o = ws.take_n<T>(ch * cz);      // [ch][cz]
-  T* t = ws.take_n<T>(P * cz);
+  float* t = ws.take_n<float>(P * cz);
   T* dt = ws.take_n<T>(P * cz);
   T* draw = ws.take_n<T>(P * NP);
   float* dxn = ws.take_n<float>(P * ch);
   T* dx = ws.take_n<T>(P * ch);
-  T* da = ws.take_n<T>(P * ch);
-  T* db = ws.take_n<T>(P * ch);
+  float* da = ws.take_n<float>(P * ch);
+  float* db = ws.take_n<float>(P * ch);
   float* dy = ws.take_n<float>(P * cz);
   if (!c.dry) {
     PackArgs pp;
@@ -462,7 +465,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
       g.M = P; g.N = cz; g.K = ch;
       g.A = op_rowmajor(S.xn, ch);
       g.B = op_rowmajor(wt_o, ch);
-      g.epi = epi_rowmajor(t, cz, false);
+      g.epi = epi_rowmajor(t, cz, true);
       g.epi.bias = w.b_o;
       EVO_TRY(gemm<T>(c, g));
     }
@@ -495,26 +498,26 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
       g.A = op_rowmajor(dx, R);
       g.B = op_colmajor(S.b, R);
       g.A.batch = P; g.B.batch = P;
-      g.epi = epi_rowmajor(da, R, false); g.epi.batch = P;
+      g.epi = epi_rowmajor(da, R, true); g.epi.batch = P;
       EVO_TRY(gemm<T>(c, g));
       // db_c[j][k] = sum_i dx_c[i][j] a_c[i][k]
       g.A = op_colmajor(dx, R);
       g.B = op_colmajor(S.a, R);
       g.A.batch = P; g.B.batch = P;
-      g.epi = epi_rowmajor(db, R, false); g.epi.batch = P;
+      g.epi = epi_rowmajor(db, R, true); g.epi.batch = P;
       EVO_TRY(gemm<T>(c, g));
     } else {
       // da_c[k][i] = sum_j b_c[k][j] dx_c[i][j]
       g.A = op_rowmajor(S.b, R);
       g.B = op_rowmajor(dx, R);
       g.A.batch = P; g.B.batch = P;
-      g.epi = epi_rowmajor(da, R, false); g.epi.batch = P;
+      g.epi = epi_rowmajor(da, R, true); g.epi.batch = P;
       EVO_TRY(gemm<T>(c, g));
       // db_c[k][j] = sum_i a_c[k][i] dx_c[i][j]
       g.A = op_rowmajor(S.a, R);
       g.B = op_colmajor(dx, R);
       g.A.batch = P; g.B.batch = P;
-      g.epi = epi_rowmajor(db, R, false); g.epi.batch = P;
+      g.epi = epi_rowmajor(db, R, true); g.epi.batch = P;
       EVO_TRY(gemm<T>(c, g));
     }
     EVO_TRY(trimul_proj_bwd<T>(c, P, (int)ch, (int)cz, S.raw, mask, da, db, draw));
