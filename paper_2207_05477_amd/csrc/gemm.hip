@@ -11,74 +11,150 @@ namespace evo {
 template <typename T> struct GemmTraits;
 template <> struct GemmTraits<bf16> { static constexpr int BK = 64; static constexpr int VEC = 8; };
 template <> struct GemmTraits<float> { static constexpr int BK = 32; static constexpr int VEC = 4; };
+// VEC elements make one 16-byte group; a BK-wide LDS row holds 8 groups.
 
 EVO_DEV int64_t addr2(int64_t r, int64_t lo, int64_t hi, int shift) {
   return shift < 0 ? r * lo : (r >> shift) * hi + (r & ((1LL << shift) - 1)) * lo;
 }
 
-// One operand tile of BROWS rows x BK reduction indices, global -> registers -> LDS.
-template <typename T, int BROWS>
+// LDS tile [rows][BK]: row r starts at r * LDK elements (one group of padding);
+// its 16-byte groups are XOR-permuted by (r >> 3) & 7, so that the transposing
+// stores of row-contiguous operands (eight rows per lane) and the fragment
+// reads of the MFMA loop both spread over the banks.
+EVO_DEV int swz(int r) { return (r >> 3) & 7; }
+
+template <int NB> struct Chunk;
+template <> struct Chunk<2> { typedef uint16_t type; };
+template <> struct Chunk<4> { typedef uint32_t type; };
+template <> struct Chunk<8> { typedef uint2 type; };
+template <> struct Chunk<16> { typedef uint4 type; };
+
+// One operand tile (BROWS rows x BK reduction indices), global -> registers -> LDS.
+// k-contiguous operands keep two register slots, so that the global loads of a
+// tile are issued two k-tiles ahead of its use; the transposing loader keeps
+// one (its registers are dearer).  k-contiguous operands move as 16-byte vectors
+// along k.  Row-contiguous operands (rows contiguous, k strided) are read as
+// 16-byte vectors of VEC rows at KB consecutive k, transposed in registers and
+// stored as KB-element runs along k.  `ks`: plain k addressing (k_shift < 0),
+// the per-tile offset is a constant step.  KC: the operand is k-contiguous.
+template <typename T, int BROWS, bool KC>
 struct TileLoader {
   static constexpr int BK = GemmTraits<T>::BK;
   static constexpr int VEC = GemmTraits<T>::VEC;
+  static constexpr int LDK = BK + VEC;
+  // k-contiguous layout
   static constexpr int NV = BROWS * BK / VEC;
   static constexpr int PASSES = (NV + 255) / 256;
-  uint4 regs[PASSES];
-  int64_t rowoff[PASSES];
-  int r_[PASSES], k_[PASSES];
-  bool ok[PASSES];
+  // row-contiguous layout
+  static constexpr int KB0 = BROWS * BK / (VEC * 256);
+  static constexpr int KB = KB0 < 1 ? 1 : (KB0 > VEC ? VEC : KB0);
+  static constexpr int RB = BROWS / VEC;
+  static constexpr int NBLK = RB * (BK / KB);
+  static constexpr int NR = KC ? PASSES : KB;
+  static constexpr int SLOTS = KC ? 2 : 1;
+  static_assert(NBLK <= 256, "one transposed block per thread");
 
-  EVO_DEV void init(const GemmOperand& op, int64_t rows_total, int64_t row0, int tid) {
+  uint4 regs[SLOTS][NR];
+  const T* ptr[PASSES];
+  int kk_[PASSES];
+  int lds_[PASSES];
+  bool ok[PASSES];
+  bool ks, rfull;
+
+  EVO_DEV void init(const GemmOperand& op, const T* base, int64_t rows_total, int64_t row0, int64_t kbeg,
+                    int tid) {
+    ks = op.k_shift < 0;
+    rfull = row0 + BROWS <= rows_total && (KC ? NV % 256 == 0 : NBLK == 256);
+    if constexpr (KC) {
 #pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      int v = tid + 256 * p;
-      int r, k;
-      if (op.k_contig) { r = v / (BK / VEC); k = (v % (BK / VEC)) * VEC; }
-      else             { k = v / (BROWS / VEC); r = (v % (BROWS / VEC)) * VEC; }
-      r_[p] = r; k_[p] = k;
-      int64_t gr = row0 + r;
-      ok[p] = (v < NV) && (gr < rows_total);
-      rowoff[p] = ok[p] ? addr2(gr, op.r_lo, op.r_hi, op.r_shift) : 0;
+      for (int p = 0; p < PASSES; ++p) {
+        const int v = tid + 256 * p;
+        const int r = v >> 3, g = v & 7;
+        kk_[p] = g * VEC;
+        ok[p] = (v < NV) && (row0 + r < rows_total);
+        const int64_t roff = ok[p] ? addr2(row0 + r, op.r_lo, op.r_hi, op.r_shift) : 0;
+        ptr[p] = base + roff + (ks ? kbeg + kk_[p] : 0);
+        lds_[p] = r * LDK + VEC * (g ^ swz(r));
+      }
+    } else {
+      const int rb = tid % RB, kb = tid / RB;
+      const int r0 = rb * VEC;
+      kk_[0] = kb * KB;
+      ok[0] = (tid < NBLK) && (row0 + r0 < rows_total);
+      const int64_t roff = ok[0] ? addr2(row0 + r0, 1, op.r_hi, op.r_shift) : 0;
+      ptr[0] = base + roff + (ks ? (kbeg + kk_[0]) * op.k_lo : 0);
+      lds_[0] = r0;
     }
   }
-  EVO_DEV void load(const GemmOperand& op, const T* base, int64_t k0, int64_t kend) {
+  // k0: first reduction index of the tile; kt_off = k0 - kbeg
+  template <int S>
+  EVO_DEV void load(const GemmOperand& op, int64_t k0, int64_t kt_off, int64_t kend) {
+    const bool full = k0 + BK <= kend;   // uniform: no reduction index of the tile is out of range
+    if constexpr (KC) {
+      if (ks && full && rfull) {
 #pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      int64_t gk = k0 + k_[p];
-      if (ok[p] && gk < kend) {
-        int64_t off = rowoff[p] + addr2(gk, op.k_lo, op.k_hi, op.k_shift);
-        regs[p] = *(const uint4*)(base + off);
+        for (int p = 0; p < PASSES; ++p) regs[S][p] = *(const uint4*)(ptr[p] + kt_off);
       } else {
-        regs[p] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) {
+          const int64_t gk = k0 + kk_[p];
+          if (ok[p] && gk < kend) {
+            const T* a = ks ? ptr[p] + kt_off : ptr[p] + addr2(gk, 1, op.k_hi, op.k_shift);
+            regs[S][p] = *(const uint4*)a;
+          } else {
+            regs[S][p] = make_uint4(0, 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      if (ks && full && rfull) {
+        const T* a = ptr[0] + kt_off * op.k_lo;
+#pragma unroll
+        for (int q = 0; q < KB; ++q) regs[S][q] = *(const uint4*)(a + q * op.k_lo);
+      } else {
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const int64_t gk = k0 + kk_[0] + q;
+          if (ok[0] && gk < kend) {
+            const T* a = ks ? ptr[0] + (kt_off + q) * op.k_lo : ptr[0] + addr2(gk, op.k_lo, op.k_hi, op.k_shift);
+            regs[S][q] = *(const uint4*)a;
+          } else {
+            regs[S][q] = make_uint4(0, 0, 0, 0);
+          }
+        }
       }
     }
   }
-  template <int LDK>
-  EVO_DEV void store(const GemmOperand& op, T* lds, int tid) {
+  template <int S>
+  EVO_DEV void store(T* lds, int tid) {
+    if constexpr (KC) {
 #pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      int v = tid + 256 * p;
-      if (v >= NV) continue;
-      if (op.k_contig) {
-        *(uint4*)(lds + r_[p] * LDK + k_[p]) = regs[p];
-      } else {
-        const T* e = (const T*)&regs[p];
+      for (int p = 0; p < PASSES; ++p)
+        if (tid + 256 * p < NV) *(uint4*)(lds + lds_[p]) = regs[S][p];
+    } else {
+      if (tid >= NBLK) return;
+      typedef typename Chunk<KB * sizeof(T)>::type C;
+      const int r0 = lds_[0], k0 = kk_[0];
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) lds[(r_[p] + i) * LDK + k_[p]] = e[i];
+      for (int i = 0; i < VEC; ++i) {
+        const int r = r0 + i;
+        union { C c; T e[KB]; } u;
+#pragma unroll
+        for (int q = 0; q < KB; ++q) u.e[q] = ((const T*)&regs[S][q])[i];
+        *(C*)(lds + r * LDK + VEC * ((k0 / VEC) ^ swz(r)) + (k0 % VEC)) = u.c;
       }
     }
   }
 };
 
+// Epilogue value of output element (m, n) before the store (see GemmEpilogue).
 template <typename T>
-EVO_DEV void epilogue_apply(const GemmEpilogue& e, int z, int64_t m, int64_t n, float acc) {
+EVO_DEV float epi_value(const GemmEpilogue& e, int64_t zo, int64_t off, int64_t m, int64_t n, float acc) {
   float v = e.alpha * acc;
   if (e.bias) v += e.bias[n];
   if (e.scale) v *= e.scale[(m >> e.sm_shift) * e.sm_ld + (n >> e.sn_shift) * e.sn_ld];
   if (e.act == ACT_RELU) v = fmaxf(v, 0.0f);
   else if (e.act == ACT_SIGMOID && n >= e.act_n0) v = sigmoidf_(v);
-  const int64_t zo = (int64_t)z * e.batch;
-  int64_t off = zo + addr2(m, e.m_lo, e.m_hi, e.m_shift) + addr2(n, e.n_lo, e.n_hi, e.n_shift);
   // auxiliary inputs: own plain strides, or the output's addressing when the m-stride is < 0
   const int64_t roff = e.r_m < 0 ? off : zo + m * e.r_m + n * e.r_n;
   if (e.relu_ref) {
@@ -90,6 +166,11 @@ EVO_DEV void epilogue_apply(const GemmEpilogue& e, int z, int64_t m, int64_t n, 
     v *= e.gate_f32 ? ((const float*)e.gate)[goff] : to_f32(((const T*)e.gate)[goff]);
   }
   if (e.resid) v += e.resid_f32 ? ((const float*)e.resid)[roff] : to_f32(((const T*)e.resid)[roff]);
+  return v;
+}
+
+template <typename T>
+EVO_DEV void epi_store1(const GemmEpilogue& e, int64_t off, float v) {
   if (e.out_f32) {
     float* o = (float*)e.out + off;
     *o = e.accumulate ? (*o + v) : v;
@@ -98,20 +179,170 @@ EVO_DEV void epilogue_apply(const GemmEpilogue& e, int z, int64_t m, int64_t n, 
   }
 }
 
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+// Four consecutive outputs n..n+3 of row m (contiguous, 4-aligned when vec4).
+template <typename T>
+EVO_DEV void epi_store4(const GemmEpilogue& e, int z, int64_t m, int64_t n, int64_t N, f32x4 acc, bool vec4) {
+  const int64_t zo = (int64_t)z * e.batch;
+  if (vec4 && n + 3 < N) {
+    const int64_t off = zo + addr2(m, e.m_lo, e.m_hi, e.m_shift) + addr2(n, 1, e.n_hi, e.n_shift);
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = epi_value<T>(e, zo, off + r, m, n + r, acc[r]);
+    if (e.out_f32) {
+      f32x4* o = (f32x4*)((float*)e.out + off);
+      f32x4 w = f32x4{v[0], v[1], v[2], v[3]};
+      if (e.accumulate) w += *o;
+      *o = w;
+    } else {
+      typedef __attribute__((__vector_size__(4 * sizeof(T)))) T tx4;
+      tx4 w;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[r] = from_f32<T>(v[r]);
+      *(tx4*)((T*)e.out + off) = w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (n + r >= N) break;
+    const int64_t off = zo + addr2(m, e.m_lo, e.m_hi, e.m_shift) + addr2(n + r, e.n_lo, e.n_hi, e.n_shift);
+    epi_store1<T>(e, off, epi_value<T>(e, zo, off, m, n + r, acc[r]));
+  }
+}
+
+// Epilogue over an accumulator tile in LDS for plain strides: the output and
+// every auxiliary input are addressed as base + m * ld + n with unit n-stride,
+// 4-aligned, so values move as 4-element vectors.  (The host sets `fast` only
+// when that holds.)  Each thread owns one 8-column slice of the tile and walks
+// its rows; offsets are 32-bit relative to per-tile bases.
+template <typename T, int BM, int BN, int ELD>
+EVO_DEV void epi_tile_fast(const GemmEpilogue& e, int z, int64_t m0, int64_t n0, int64_t M, int64_t N,
+                           const float* et, int tid) {
+  typedef __attribute__((__vector_size__(4 * sizeof(T)))) T tx4;
+  constexpr int CPR = BN / 8;             // 8-column slices per row
+  constexpr int RPP = 256 / CPR;          // rows per pass
+  const int cs = tid % CPR, r0 = tid / CPR;
+  const int nl = cs * 8;
+  const int64_t zo = (int64_t)z * e.batch;
+  const int ld = (int)e.m_lo;
+  const int rld = e.r_m < 0 ? ld : (int)e.r_m;
+  const int gld = e.g_m < 0 ? ld : (int)e.g_m;
+  const int64_t obase = zo + m0 * e.m_lo + n0 + nl;
+  const int64_t rbase = e.r_m < 0 ? obase : zo + m0 * e.r_m + n0 + nl;
+  const int64_t gbase = e.g_m < 0 ? obase : zo + m0 * e.g_m + n0 + nl;
+  const int ml_lim = (int)(M - m0 < BM ? M - m0 : BM);
+  const int nvalid = (int)(N - n0 - nl < 8 ? N - n0 - nl : 8);
+  if (nvalid <= 0) return;
+  float* outf = (float*)e.out + obase;
+  T* outt = (T*)e.out + obase;
+  const float* rf = e.resid_f32 ? (const float*)e.resid + rbase : nullptr;
+  const T* rt = e.resid && !e.resid_f32 ? (const T*)e.resid + rbase : nullptr;
+  const T* rr = e.relu_ref ? (const T*)e.relu_ref + rbase : nullptr;
+  const float* gf = e.gate && e.gate_f32 ? (const float*)e.gate + gbase : nullptr;
+  const T* gt = e.gate && !e.gate_f32 ? (const T*)e.gate + gbase : nullptr;
+  f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f}, b1 = b0;
+  if (e.bias && nvalid == 8) {
+    b0 = *(const f32x4*)(e.bias + n0 + nl);
+    b1 = *(const f32x4*)(e.bias + n0 + nl + 4);
+  }
+  const int sig0 = e.act == ACT_SIGMOID ? (int)(e.act_n0 - n0 - nl) : 1 << 30;   // first sigmoid column
+  for (int ml = r0; ml < ml_lim; ml += RPP) {
+    f32x4 v0 = *(const f32x4*)(et + ml * ELD + nl);
+    f32x4 v1 = *(const f32x4*)(et + ml * ELD + nl + 4);
+    if (nvalid < 8) {
+      // ragged right edge of the output
+      const float a8[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+      for (int r = 0; r < nvalid; ++r) {
+        const int64_t off = obase + (int64_t)ml * ld + r;
+        epi_store1<T>(e, off, epi_value<T>(e, zo, off, m0 + ml, n0 + nl + r, a8[r]));
+      }
+      continue;
+    }
+    v0 *= e.alpha;
+    v1 *= e.alpha;
+    v0 += b0;
+    v1 += b1;
+    if (e.act == ACT_RELU) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { v0[r] = fmaxf(v0[r], 0.0f); v1[r] = fmaxf(v1[r], 0.0f); }
+    } else if (sig0 < 8) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r >= sig0) v0[r] = sigmoidf_(v0[r]);
+        if (r + 4 >= sig0) v1[r] = sigmoidf_(v1[r]);
+      }
+    }
+    const int ro = ml * rld;
+    if (rr) {
+      const tx4 q0 = *(const tx4*)(rr + ro), q1 = *(const tx4*)(rr + ro + 4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v0[r] = to_f32(q0[r]) > 0.0f ? v0[r] : 0.0f;
+        v1[r] = to_f32(q1[r]) > 0.0f ? v1[r] : 0.0f;
+      }
+    }
+    if (gf) {
+      const int go = ml * gld;
+      v0 *= *(const f32x4*)(gf + go);
+      v1 *= *(const f32x4*)(gf + go + 4);
+    } else if (gt) {
+      const int go = ml * gld;
+      const tx4 q0 = *(const tx4*)(gt + go), q1 = *(const tx4*)(gt + go + 4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { v0[r] *= to_f32(q0[r]); v1[r] *= to_f32(q1[r]); }
+    }
+    if (rf) {
+      v0 += *(const f32x4*)(rf + ro);
+      v1 += *(const f32x4*)(rf + ro + 4);
+    } else if (rt) {
+      const tx4 q0 = *(const tx4*)(rt + ro), q1 = *(const tx4*)(rt + ro + 4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { v0[r] += to_f32(q0[r]); v1[r] += to_f32(q1[r]); }
+    }
+    const int oo = ml * ld;
+    if (e.out_f32) {
+      f32x4* o = (f32x4*)(outf + oo);
+      if (e.accumulate) { v0 += o[0]; v1 += o[1]; }
+      o[0] = v0;
+      o[1] = v1;
+    } else {
+      tx4 w0, w1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { w0[r] = from_f32<T>(v0[r]); w1[r] = from_f32<T>(v1[r]); }
+      *(tx4*)(outt + oo) = w0;
+      *(tx4*)(outt + oo + 4) = w1;
+    }
+  }
+}
+
+// The MFMA is issued with the B fragment first, so that each lane's four
+// accumulator rows are four consecutive n of one m.  The accumulator tile then
+// goes through LDS (FP32) and the epilogue walks it row by row: 4-element
+// vectors, whole output rows per group of lanes.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, bool KCA, bool KCB>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int32_t ntn, int32_t flags) {
   constexpr int BK = GemmTraits<T>::BK;
-  constexpr int LDK = BK + 16 / (int)sizeof(T);      // padded LDS row pitch (elements)
+  constexpr int VEC = GemmTraits<T>::VEC;
+  constexpr int LDK = BK + VEC;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int ELD = BN + 4;                                   // epilogue tile pitch (floats)
+  constexpr int MAIN_BYTES = 2 * (BM + BN) * LDK * (int)sizeof(T);
+  constexpr int EPI_BYTES = BM * ELD * 4;
   static_assert(WAVES_M * WAVES_N == 4, "4 waves");
   static_assert(TM >= 1 && TN >= 1, "wave tile");
-  __shared__ __attribute__((aligned(16))) T lds[2][(BM + BN) * LDK];
+  __shared__ __attribute__((aligned(16))) char smem[MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES];
+  T (*lds)[(BM + BN) * LDK] = (T (*)[(BM + BN) * LDK])smem;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; give
+  // each XCD a contiguous run of tiles (shared row panels stay in its L2).
+  int tile = blockIdx.x;
+  const int ntiles = gridDim.x;
+  if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
+  const int64_t m0 = (int64_t)(tile / ntn) * BM;
+  const int64_t n0 = (int64_t)(tile % ntn) * BN;
   const int z = blockIdx.z;
 
   const T* Ap = (const T*)g.A.ptr;
@@ -126,83 +357,461 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     Bp += (int64_t)z * g.B.batch;
   }
 
-  TileLoader<T, BM> la;
-  TileLoader<T, BN> lb;
-  la.init(g.A, g.M, m0, tid);
-  lb.init(g.B, g.N, n0, tid);
+  TileLoader<T, BM, KCA> la;
+  TileLoader<T, BN, KCB> lb;
+  la.init(g.A, Ap, g.M, m0, kbeg, tid);
+  lb.init(g.B, Bp, g.N, n0, kbeg, tid);
 
-  f32x4 acc[TM][TN];
+  f32x4 acc[TN][TM];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TN; ++j)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int nk = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
   if (nk > 0) {
-    la.load(g.A, Ap, kbeg, kend);
-    lb.load(g.B, Bp, kbeg, kend);
-    la.template store<LDK>(g.A, lds[0], tid);
-    lb.template store<LDK>(g.B, lds[0] + BM * LDK, tid);
+    la.template load<0>(g.A, kbeg, 0, kend);
+    lb.template load<0>(g.B, kbeg, 0, kend);
+  }
+  if (nk > 1) {
+    if constexpr (KCA) la.template load<1>(g.A, kbeg + BK, BK, kend);
+    if constexpr (KCB) lb.template load<1>(g.B, kbeg + BK, BK, kend);
+  }
+  if (nk > 0) {
+    la.template store<0>(lds[0], tid);
+    lb.template store<0>(lds[0] + BM * LDK, tid);
   }
   __syncthreads();
 
   const int lr = lane & 15, lg = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      la.load(g.A, Ap, kbeg + (int64_t)(kt + 1) * BK, kend);
-      lb.load(g.B, Bp, kbeg + (int64_t)(kt + 1) * BK, kend);
-    }
-    const T* sA = lds[cur] + (wm * WM + lr) * LDK;
-    const T* sB = lds[cur] + BM * LDK + (wn * WN + lr) * LDK;
-    if constexpr (sizeof(T) == 2) {
+  // per-fragment LDS row offsets and swizzles
+  int arow[TM], asw[TM], brow[TN], bsw[TN];
 #pragma unroll
-      for (int ks = 0; ks < BK / 32; ++ks) {
+  for (int i = 0; i < TM; ++i) {
+    const int r = wm * WM + i * 16 + lr;
+    arow[i] = r * LDK;
+    asw[i] = swz(r);
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int r = wn * WN + j * 16 + lr;
+    brow[j] = BM * LDK + r * LDK;
+    bsw[j] = swz(r);
+  }
+
+  auto compute = [&](const T* s) {
+#pragma unroll
+    for (int kq = 0; kq < 2; ++kq) {   // two k-steps of four groups per tile
+      const int grp = kq * 4 + lg;
+      if constexpr (sizeof(T) == 2) {
         bf16x8 af[TM], bfr[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8*)(sA + i * 16 * LDK + ks * 32 + lg * 8);
+        for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8*)(s + arow[i] + VEC * (grp ^ asw[i]));
 #pragma unroll
-        for (int j = 0; j < TN; ++j) bfr[j] = *(const bf16x8*)(sB + j * 16 * LDK + ks * 32 + lg * 8);
+        for (int j = 0; j < TN; ++j) bfr[j] = *(const bf16x8*)(s + brow[j] + VEC * (grp ^ bsw[j]));
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = mfma_bf16(af[i], bfr[j], acc[i][j]);
-      }
-    } else {
-#pragma unroll
-      for (int kq = 0; kq < BK / 16; ++kq) {
+          for (int i = 0; i < TM; ++i) acc[j][i] = mfma_bf16(bfr[j], af[i], acc[j][i]);
+      } else {
         f32x4 af[TM], bfr[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) af[i] = *(const f32x4*)(sA + i * 16 * LDK + kq * 16 + lg * 4);
+        for (int i = 0; i < TM; ++i) af[i] = *(const f32x4*)(s + arow[i] + VEC * (grp ^ asw[i]));
 #pragma unroll
-        for (int j = 0; j < TN; ++j) bfr[j] = *(const f32x4*)(sB + j * 16 * LDK + kq * 16 + lg * 4);
+        for (int j = 0; j < TN; ++j) bfr[j] = *(const f32x4*)(s + brow[j] + VEC * (grp ^ bsw[j]));
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int i = 0; i < TM; ++i)
+          for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = mfma_f32(af[i][t], bfr[j][t], acc[i][j]);
+            for (int i = 0; i < TM; ++i) acc[j][i] = mfma_f32(bfr[j][t], af[i][t], acc[j][i]);
       }
     }
+  };
+
+  // Tile kt sits in LDS buffer kt & 1.  A two-slot (k-contiguous) loader has
+  // tile kt + 1 waiting in slot (kt + 1) & 1 and fetches tile kt + 2 into slot
+  // kt & 1 (freed when tile kt went to LDS); a one-slot loader fetches tile
+  // kt + 1 at the start of the iteration.  Only loads and stores branch on the
+  // slot, so the register slots stay compile-time.
+#define EVO_ADVANCE(L, OP, KCX)                                                  \
+  do {                                                                           \
+    if constexpr (KCX) {                                                         \
+      if (kt + 2 < nk) {                                                         \
+        const int64_t off = (int64_t)(kt + 2) * BK;                              \
+        if (cur == 0) L.template load<0>(OP, kbeg + off, off, kend);             \
+        else L.template load<1>(OP, kbeg + off, off, kend);                      \
+      }                                                                          \
+    } else if (kt + 1 < nk) {                                                    \
+      const int64_t off = (int64_t)(kt + 1) * BK;                                \
+      L.template load<0>(OP, kbeg + off, off, kend);                             \
+    }                                                                            \
+  } while (0)
+#define EVO_COMMIT(L, DST, KCX)                                                  \
+  do {                                                                           \
+    if (kt + 1 < nk) {                                                           \
+      if constexpr (KCX) {                                                       \
+        if (cur == 0) L.template store<1>(DST, tid);                             \
+        else L.template store<0>(DST, tid);                                      \
+      } else {                                                                   \
+        L.template store<0>(DST, tid);                                           \
+      }                                                                          \
+    }                                                                            \
+  } while (0)
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    EVO_ADVANCE(la, g.A, KCA);
+    EVO_ADVANCE(lb, g.B, KCB);
+    compute(lds[cur]);
+    EVO_COMMIT(la, lds[cur ^ 1], KCA);
+    EVO_COMMIT(lb, lds[cur ^ 1] + BM * LDK, KCB);
+    __syncthreads();
+  }
+#undef EVO_ADVANCE
+#undef EVO_COMMIT
+
+  // the last loop iteration ended with a barrier: the operand tiles are dead
+  float* et = (float*)smem;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+      *(f32x4*)(et + (wm * WM + i * 16 + lr) * ELD + wn * WN + j * 16 + lg * 4) = acc[j][i];
+  __syncthreads();
+  if (flags & 2) {
+    epi_tile_fast<T, BM, BN, ELD>(g.epi, z, m0, n0, g.M, g.N, et, tid);
+    return;
+  }
+  constexpr int CPR = BN / 4;   // 4-element chunks per row
+  for (int c = tid; c < BM * CPR; c += 256) {
+    const int ml = c / CPR, nl = (c % CPR) * 4;
+    const int64_t m = m0 + ml, n = n0 + nl;
+    if (m < g.M && n < g.N) epi_store4<T>(g.epi, z, m, n, g.N, *(const f32x4*)(et + ml * ELD + nl), (flags & 1) != 0);
+  }
+}
+
+// ============================================================== plain-stride kernel
+// The common case: every operand and the output addressed with one row stride,
+// 4-aligned outputs.  Loads and stores go through buffer resources with 32-bit
+// offsets (the k-tile step is a scalar offset), rows beyond the problem are
+// clamped to the last row (their products only feed discarded outputs),
+// reduction indices beyond the range read as zero, and out-of-range output
+// elements get an offset past the resource's extent, which the hardware drops.
+typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(int)))) int i32x2;
+constexpr int kBufFlags = 0x00020000;   // raw 32-bit buffer, gfx9 family
+constexpr uint32_t kOOB = 0x80000000u;  // an offset beyond every extent
+
+struct PlainInfo {
+  int32_t lda, ldb;            // row stride of A / B (elements)
+  uint32_t ext_a, ext_b;       // bytes of one A / B slice
+  int32_t ldo;                 // output row stride (elements)
+  uint32_t ext_o;              // bytes of one output slice
+  int32_t ldr, ldg;            // resid/relu_ref and gate row strides (elements)
+  uint32_t ext_r, ext_g;
+};
+
+EVO_DEV __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, kBufFlags);
+}
+
+template <typename T, int BROWS, bool KC>
+struct PlainLoader {
+  static constexpr int BK = GemmTraits<T>::BK;
+  static constexpr int VEC = GemmTraits<T>::VEC;
+  static constexpr int LDK = BK + VEC;
+  static constexpr int NV = BROWS * BK / VEC;
+  static constexpr int PASSES = (NV + 255) / 256;
+  static constexpr int KB0 = BROWS * BK / (VEC * 256);
+  static constexpr int KB = KB0 < 1 ? 1 : (KB0 > VEC ? VEC : KB0);
+  static constexpr int RB = BROWS / VEC;
+  static constexpr int NBLK = RB * (BK / KB);
+  static constexpr int NR = KC ? PASSES : KB;
+  static constexpr int SLOTS = KC ? 2 : 1;
+
+  __amdgpu_buffer_rsrc_t rs;
+  i32x4 regs[SLOTS][NR];
+  uint32_t voff[PASSES];
+  int kk_[PASSES];
+  int lds_[PASSES];
+  uint32_t step;     // bytes per k-tile
+  uint32_t krow;     // bytes between consecutive k (row-contiguous)
+
+  EVO_DEV void init(const void* base, uint32_t ext, int ld, int rows, int row0, int kbeg, int tid) {
+    rs = rsrc(base, ext);
+    if constexpr (KC) {
+      step = BK * sizeof(T);
+#pragma unroll
+      for (int p = 0; p < PASSES; ++p) {
+        const int v = tid + 256 * p;
+        const int r = v >> 3, g = v & 7;
+        kk_[p] = g * VEC;
+        int gr = row0 + r;
+        gr = gr < rows ? gr : rows - 1;
+        voff[p] = (v < NV) ? (uint32_t)((gr * ld + kbeg + kk_[p]) * (int)sizeof(T)) : kOOB;
+        lds_[p] = r * LDK + VEC * (g ^ swz(r));
+      }
+    } else {
+      step = (uint32_t)(BK * ld * (int)sizeof(T));
+      krow = (uint32_t)(ld * (int)sizeof(T));
+      const int rb = tid % RB, kb = tid / RB;
+      int r0 = row0 + rb * VEC;
+      r0 = r0 < rows ? r0 : rows - VEC;
+      kk_[0] = kb * KB;
+      voff[0] = tid < NBLK ? (uint32_t)(((kbeg + kk_[0]) * ld + r0) * (int)sizeof(T)) : kOOB;
+      lds_[0] = rb * VEC;
+    }
+  }
+  // tile kt; `krem` = reduction indices left from the tile start (< BK on a tail tile)
+  template <int S>
+  EVO_DEV void load(int kt, int krem) {
+    const uint32_t so = (uint32_t)kt * step;
+    if constexpr (KC) {
+#pragma unroll
+      for (int p = 0; p < PASSES; ++p) {
+        regs[S][p] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[p], so, 0);
+        if (krem < BK && kk_[p] >= krem) regs[S][p] = i32x4{0, 0, 0, 0};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        regs[S][q] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[0] + q * krow, so, 0);
+        if (krem < BK && kk_[0] + q >= krem) regs[S][q] = i32x4{0, 0, 0, 0};
+      }
+    }
+  }
+  template <int S>
+  EVO_DEV void store(T* lds, int tid) {
+    if constexpr (KC) {
+#pragma unroll
+      for (int p = 0; p < PASSES; ++p)
+        if (tid + 256 * p < NV) *(i32x4*)(lds + lds_[p]) = regs[S][p];
+    } else {
+      if (tid >= NBLK) return;
+      typedef typename Chunk<KB * sizeof(T)>::type C;
+      const int r0 = lds_[0], k0 = kk_[0];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        const int r = r0 + i;
+        union { C c; T e[KB]; } u;
+#pragma unroll
+        for (int q = 0; q < KB; ++q) u.e[q] = ((const T*)&regs[S][q])[i];
+        *(C*)(lds + r * LDK + VEC * ((k0 / VEC) ^ swz(r)) + (k0 % VEC)) = u.c;
+      }
+    }
+  }
+};
+
+template <typename T>
+EVO_DEV f32x4 load4(__amdgpu_buffer_rsrc_t r, uint32_t off, bool f32) {
+  if (f32) {
+    const i32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return f32x4{__int_as_float(q[0]), __int_as_float(q[1]), __int_as_float(q[2]), __int_as_float(q[3])};
+  }
+  if constexpr (sizeof(T) == 2) {
+    const i32x2 q = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    const T* e = (const T*)&q;
+    return f32x4{to_f32(e[0]), to_f32(e[1]), to_f32(e[2]), to_f32(e[3])};
+  } else {
+    const i32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return f32x4{__int_as_float(q[0]), __int_as_float(q[1]), __int_as_float(q[2]), __int_as_float(q[3])};
+  }
+}
+
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, bool KCA, bool KCB>
+__global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
+  constexpr int BK = GemmTraits<T>::BK;
+  constexpr int VEC = GemmTraits<T>::VEC;
+  constexpr int LDK = BK + VEC;
+  constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert(WAVES_M * WAVES_N == 4, "4 waves");
+  __shared__ __attribute__((aligned(16))) T lds[2][(BM + BN) * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  int tile = blockIdx.x;
+  const int ntiles = gridDim.x;
+  if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
+  const int m0 = (tile / ntn) * BM;
+  const int n0 = (tile % ntn) * BN;
+  const int z = blockIdx.z;
+  const int M = (int)g.M, N = (int)g.N;
+
+  const T* Ap = (const T*)g.A.ptr;
+  const T* Bp = (const T*)g.B.ptr;
+  int kbeg = 0, kend = (int)g.K;
+  if (g.split_k > 1) {
+    const int per = (((int)g.K + g.split_k - 1) / g.split_k + BK - 1) / BK * BK;
+    kbeg = z * per;
+    kend = kbeg + per < (int)g.K ? kbeg + per : (int)g.K;
+  } else {
+    Ap += (int64_t)z * g.A.batch;
+    Bp += (int64_t)z * g.B.batch;
+  }
+  PlainLoader<T, BM, KCA> la;
+  PlainLoader<T, BN, KCB> lb;
+  la.init(Ap, pi.ext_a, pi.lda, M, m0, kbeg, tid);
+  lb.init(Bp, pi.ext_b, pi.ldb, N, n0, kbeg, tid);
+
+  f32x4 acc[TN][TM];
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+#pragma unroll
+    for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    la.template load<0>(0, kend - kbeg);
+    lb.template load<0>(0, kend - kbeg);
+  }
+  if (nk > 1) {
+    if constexpr (KCA) la.template load<1>(1, kend - kbeg - BK);
+    if constexpr (KCB) lb.template load<1>(1, kend - kbeg - BK);
+  }
+  if (nk > 0) {
+    la.template store<0>(lds[0], tid);
+    lb.template store<0>(lds[0] + BM * LDK, tid);
+  }
+  __syncthreads();
+
+  const int lr = lane & 15, lg = lane >> 4;
+  int arow[TM], asw[TM], brow[TN], bsw[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int r = wm * WM + i * 16 + lr;
+    arow[i] = r * LDK;
+    asw[i] = swz(r);
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int r = wn * WN + j * 16 + lr;
+    brow[j] = BM * LDK + r * LDK;
+    bsw[j] = swz(r);
+  }
+  auto compute = [&](const T* s) {
+#pragma unroll
+    for (int kq = 0; kq < 2; ++kq) {
+      const int grp = kq * 4 + lg;
+      if constexpr (sizeof(T) == 2) {
+        bf16x8 af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8*)(s + arow[i] + VEC * (grp ^ asw[i]));
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bfr[j] = *(const bf16x8*)(s + brow[j] + VEC * (grp ^ bsw[j]));
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int i = 0; i < TM; ++i) acc[j][i] = mfma_bf16(bfr[j], af[i], acc[j][i]);
+      } else {
+        f32x4 af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = *(const f32x4*)(s + arow[i] + VEC * (grp ^ asw[i]));
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bfr[j] = *(const f32x4*)(s + brow[j] + VEC * (grp ^ bsw[j]));
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int i = 0; i < TM; ++i) acc[j][i] = mfma_f32(bfr[j][t], af[i][t], acc[j][i]);
+      }
+    }
+  };
+  // same pipeline as gemm_kernel: tile kt in LDS buffer kt & 1, later tiles in registers
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if constexpr (KCA) {
+      if (kt + 2 < nk) {
+        if (cur == 0) la.template load<0>(kt + 2, kend - kbeg - (kt + 2) * BK);
+        else la.template load<1>(kt + 2, kend - kbeg - (kt + 2) * BK);
+      }
+    } else if (kt + 1 < nk) {
+      la.template load<0>(kt + 1, kend - kbeg - (kt + 1) * BK);
+    }
+    if constexpr (KCB) {
+      if (kt + 2 < nk) {
+        if (cur == 0) lb.template load<0>(kt + 2, kend - kbeg - (kt + 2) * BK);
+        else lb.template load<1>(kt + 2, kend - kbeg - (kt + 2) * BK);
+      }
+    } else if (kt + 1 < nk) {
+      lb.template load<0>(kt + 1, kend - kbeg - (kt + 1) * BK);
+    }
+    compute(lds[cur]);
     if (kt + 1 < nk) {
-      la.template store<LDK>(g.A, lds[cur ^ 1], tid);
-      lb.template store<LDK>(g.B, lds[cur ^ 1] + BM * LDK, tid);
+      T* dst = lds[cur ^ 1];
+      if constexpr (KCA) {
+        if (cur == 0) la.template store<1>(dst, tid);
+        else la.template store<0>(dst, tid);
+      } else {
+        la.template store<0>(dst, tid);
+      }
+      if constexpr (KCB) {
+        if (cur == 0) lb.template store<1>(dst + BM * LDK, tid);
+        else lb.template store<0>(dst + BM * LDK, tid);
+      } else {
+        lb.template store<0>(dst + BM * LDK, tid);
+      }
     }
     __syncthreads();
   }
 
+  // epilogue straight from the accumulators: lane holds n..n+3 of row m
+  const GemmEpilogue& e = g.epi;
+  const int64_t zo = (int64_t)z * e.batch;
+  const bool of32 = e.out_f32 != 0;
+  const size_t osz = of32 ? 4 : sizeof(T);
+  const __amdgpu_buffer_rsrc_t ro = rsrc((const char*)e.out + zo * osz, pi.ext_o);
+  const size_t rsz = e.resid_f32 ? 4 : sizeof(T);
+  const size_t gsz = e.gate_f32 ? 4 : sizeof(T);
+  __amdgpu_buffer_rsrc_t rr = ro, rg = ro, rrl = ro;
+  if (e.resid) rr = rsrc((const char*)e.resid + zo * rsz, pi.ext_r);
+  if (e.relu_ref) rrl = rsrc((const char*)e.relu_ref + zo * sizeof(T), pi.ext_r);
+  if (e.gate) rg = rsrc((const char*)e.gate + zo * gsz, pi.ext_g);
+  const float alpha = e.alpha;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn * WN + j * 16 + lg * 4;
+    const bool colok = n < N;
+    f32x4 bj = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (e.bias && colok) bj = *(const f32x4*)(e.bias + n);
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t n = n0 + wn * WN + j * 16 + lr;
-      if (n >= g.N) continue;
+    for (int i = 0; i < TM; ++i) {
+      const int m = m0 + wm * WM + i * 16 + lr;
+      const bool ok = colok && m < M;
+      f32x4 v = acc[j][i] * alpha + bj;
+      if (e.act == ACT_RELU) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm * WM + i * 16 + lg * 4 + r;
-        if (m < g.M) epilogue_apply<T>(g.epi, z, m, n, acc[i][j][r]);
+        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.0f);
+      } else if (e.act == ACT_SIGMOID) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (n + r >= e.act_n0) v[r] = sigmoidf_(v[r]);
+      }
+      const uint32_t eo = (uint32_t)(m * pi.ldr + n);   // aux element offset
+      if (e.relu_ref) {
+        const f32x4 q = load4<T>(rrl, ok ? eo * (uint32_t)sizeof(T) : kOOB, false);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = q[r] > 0.0f ? v[r] : 0.0f;
+      }
+      if (e.gate) v *= load4<T>(rg, ok ? (uint32_t)(m * pi.ldg + n) * (uint32_t)gsz : kOOB, e.gate_f32 != 0);
+      if (e.resid) v += load4<T>(rr, ok ? eo * (uint32_t)rsz : kOOB, e.resid_f32 != 0);
+      const uint32_t oo = ok ? (uint32_t)(m * pi.ldo + n) * (uint32_t)osz : kOOB;
+      if (of32) {
+        if (e.accumulate) v += load4<T>(ro, oo, true);
+        const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
+      } else if constexpr (sizeof(T) == 2) {
+        union { i32x2 q; T e4[4]; } u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u.e4[r] = from_f32<T>(v[r]);
+        __builtin_amdgcn_raw_buffer_store_b64(u.q, ro, oo, 0, 0);
+      } else {
+        const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
       }
     }
+  }
 }
 
 static bool pow2_ok(int32_t shift, int vec) {
@@ -228,13 +837,65 @@ static bool operand_ok(const GemmOperand& o, int64_t rows, int vec, const char* 
   return true;
 }
 
+// Plain-stride eligibility (see gemm_plain_kernel) and its strides / extents.
+template <typename T>
+static bool plain_info(const GemmArgs& g, PlainInfo& pi) {
+  const int64_t lim = (1LL << 31) - 4096;
+  const size_t sz = sizeof(T);
+  auto op = [&](const GemmOperand& o, int64_t rows, int32_t& ld, uint32_t& ext) {
+    if (o.r_shift >= 0 || o.k_shift >= 0) return false;
+    const int64_t l = o.k_contig ? o.r_lo : o.k_lo;
+    const int64_t e = o.k_contig ? ((rows - 1) * l + g.K) * (int64_t)sz : ((g.K - 1) * l + rows) * (int64_t)sz;
+    if (l <= 0 || l > lim || e > lim || e <= 0) return false;
+    ld = (int32_t)l;
+    ext = (uint32_t)e;
+    return true;
+  };
+  if (g.K <= 0 || !op(g.A, g.M, pi.lda, pi.ext_a) || !op(g.B, g.N, pi.ldb, pi.ext_b)) return false;
+  const GemmEpilogue& e = g.epi;
+  const int64_t osz = e.out_f32 ? 4 : (int64_t)sz;
+  if (e.m_shift >= 0 || e.n_shift >= 0 || e.n_lo != 1 || e.scale || g.N % 4 || e.m_lo % 4 || e.m_lo <= 0) return false;
+  if ((g.split_k > 1 || g.batch > 1) && e.batch % 4) return false;
+  if (((uintptr_t)e.out) % (4 * osz) || (e.bias && ((uintptr_t)e.bias) % 16)) return false;
+  auto ext_of = [&](int64_t ld, int64_t esz, uint32_t& ext) {
+    const int64_t x = ((g.M - 1) * ld + g.N) * esz;
+    if (ld > lim || x > lim) return false;
+    ext = (uint32_t)x;
+    return true;
+  };
+  pi.ldo = (int32_t)e.m_lo;
+  if (!ext_of(e.m_lo, osz, pi.ext_o)) return false;
+  auto aux = [&](const void* p, int64_t sm, int64_t sn, int64_t esz, int32_t& ld, uint32_t& ext) {
+    ld = pi.ldo;
+    ext = pi.ext_o;
+    if (!p) return true;
+    if (((uintptr_t)p) % (4 * esz)) return false;
+    if (sm < 0) return ext_of(e.m_lo, esz, ext);
+    if (sn != 1 || sm % 4) return false;
+    ld = (int32_t)sm;
+    return ext_of(sm, esz, ext);
+  };
+  const void* rp = e.resid ? e.resid : e.relu_ref;
+  if (e.resid && e.relu_ref && e.resid_f32) return false;   // one stride/extent serves both: same element size
+  const int64_t rsz = e.resid ? (e.resid_f32 ? 4 : (int64_t)sz) : (int64_t)sz;
+  if (!aux(rp, e.r_m, e.r_n, rsz, pi.ldr, pi.ext_r)) return false;
+  if (!aux(e.gate, e.g_m, e.g_n, e.gate_f32 ? 4 : (int64_t)sz, pi.ldg, pi.ext_g)) return false;
+  return true;
+}
+
 template <typename T, int BM, int BN, int WMW, int WNW>
 static void launch(const Ctx& ctx, const GemmArgs& g) {
   static const std::string nm = std::string("gemm_kernel<") + tname<T>() + ", " + std::to_string(BM) +
                                 ", " + std::to_string(BN) + ", " + std::to_string(WMW) + ", " +
                                 std::to_string(WNW) + ">";
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
-            (unsigned)(g.split_k > 1 ? g.split_k : g.batch));
+  const int64_t ntn = (g.N + BN - 1) / BN, ntm = (g.M + BM - 1) / BM;
+  dim3 grid((unsigned)(ntn * ntm), 1, (unsigned)(g.split_k > 1 ? g.split_k : g.batch));
+  // four consecutive n of one m form one aligned vector of the output
+  const GemmEpilogue& e = g.epi;
+  const size_t osz = e.out_f32 ? 4 : sizeof(T);
+  const bool vec4 = e.n_lo == 1 && (e.n_shift < 0 || e.n_shift >= 2) && (e.n_shift < 0 || e.n_hi % 4 == 0) &&
+                    (e.m_shift < 0 ? e.m_lo % 4 == 0 : (e.m_lo % 4 == 0 && e.m_hi % 4 == 0)) &&
+                    e.batch % 4 == 0 && ((uintptr_t)e.out) % (4 * osz) == 0;
   const double nb = g.split_k > 1 ? 1.0 : (double)g.batch;
   const double nout = g.split_k > 1 ? (double)g.split_k : (double)g.batch;
   const double mn = (double)g.M * g.N;
@@ -244,7 +905,40 @@ static void launch(const Ctx& ctx, const GemmArgs& g) {
   if (g.epi.resid) bytes += mn * nb * (g.epi.resid_f32 ? 4.0 : (double)sizeof(T));
   if (g.epi.gate) bytes += mn * nb * (g.epi.gate_f32 ? 4.0 : (double)sizeof(T));
   if (g.epi.relu_ref) bytes += mn * nb * sizeof(T);
-  EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW>), grid, dim3(256), 0, ctx.stream, g);
+  // plain strides everywhere, 4-aligned: vector epilogue without index arithmetic
+  auto al16 = [](const void* p) { return ((uintptr_t)p) % 16 == 0; };
+  const size_t tsz = sizeof(T);
+  auto aux_ok = [&](const void* p, int64_t sm, int64_t sn, bool f32) {
+    if (!p) return true;
+    if (((uintptr_t)p) % (4 * (f32 ? 4 : tsz))) return false;
+    return sm < 0 || (sn == 1 && sm % 4 == 0);
+  };
+  const int64_t lim = 1 << 24;   // 32-bit in-tile offsets
+  const bool fast = vec4 && e.m_shift < 0 && e.n_shift < 0 && !e.scale && (!e.bias || al16(e.bias)) &&
+                    e.m_lo < lim && e.r_m < lim && e.g_m < lim &&
+                    aux_ok(e.resid, e.r_m, e.r_n, e.resid_f32 != 0) &&
+                    aux_ok(e.relu_ref, e.r_m, e.r_n, false) && aux_ok(e.gate, e.g_m, e.g_n, e.gate_f32 != 0);
+  const int32_t nt = (int32_t)ntn, v4 = (vec4 ? 1 : 0) | (fast ? 2 : 0);
+  PlainInfo pi;
+  if (plain_info<T>(g, pi)) {
+    if (g.A.k_contig && g.B.k_contig)
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, true, true>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+    else if (g.A.k_contig)
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, true, false>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+    else if (g.B.k_contig)
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, false, true>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+    else
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, false, false>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+    return;
+  }
+  if (g.A.k_contig && g.B.k_contig)
+    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, true, true>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+  else if (g.A.k_contig)
+    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, true, false>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+  else if (g.B.k_contig)
+    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, false, true>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+  else
+    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, false, false>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
 }
 
 template <typename T>
