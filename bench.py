@@ -7,7 +7,9 @@ initial-training crop N_seq=128, N_res=256, c_m=256, c_z=128, MSA attention
 outer-product-mean hidden 32, FP32 (the headline workload).  The same block in
 BF16 storage with FP32 accumulation is timed beside it.
 
-Prints one JSON line (see the README of the measurement contract in the design doc).
+Prints one JSON line: the FP32 throughput in TFLOP/s of algorithmic work
+(value), the BF16 twin, the roofline of the dominant kernel measured with HIP
+events around its launches, and the FP64 oracle's throughput on the host.
 """
 from __future__ import annotations
 
@@ -158,7 +160,7 @@ def print_breakdown(stats, dtype, steps, file=sys.stderr):
         print(f"{ms:8.3f} ms {s['launches'] // steps:4d}x {kind} {100 * frac:5.1f}%  {s['name']}", file=file)
 
 
-KERNEL_SOURCES = {"gemm_kernel": "gemm.hip", "attn_": "attn.hip", "ln_": "misc.hip", "gattn_": "gattn.hip"}
+KERNEL_SOURCES = {"gemm_": "gemm.hip", "attn_": "attn.hip", "ln_": "misc.hip", "gattn_": "gattn.hip"}
 
 
 def kernel_source_hash(kernel_name: str):

@@ -42,6 +42,12 @@ The readings taken where the paper is silent:
 * Block order: row attention, column attention, MSA transition, outer product
   mean, outgoing and incoming triangle multiplication, triangle attention
   around the starting and the ending node, pair transition.
+* A stack whose activations are stored in BFloat16 (Section "BFloat16": the
+  intermediate activations are BF16, the parameters FP32) hands BF16 tensors
+  from block to block: with boundary="bf16" the stack rounds each block's
+  output before the next block and each inter-block gradient before the
+  block below, and computes every block exactly on those values.  The
+  stack's own inputs, outputs and returned gradients are not rounded here.
 """
 from __future__ import annotations
 
@@ -237,9 +243,20 @@ def block(m, z, msa_mask, pair_mask, p, cfg, relu_decision=None):
     return m, z
 
 
-def stack(m, z, msa_mask, pair_mask, blocks, cfg, relu_decision=None):
+def _store(t, boundary):
+    """A tensor handed between blocks, in the stack's storage precision."""
+    if boundary is None:
+        return t
+    if boundary == "bf16":
+        return _bf16(t)
+    raise ValueError(boundary)
+
+
+def stack(m, z, msa_mask, pair_mask, blocks, cfg, relu_decision=None, boundary=None):
     """Blocks applied in sequence with independent parameters."""
-    for p in blocks:
+    for i, p in enumerate(blocks):
+        if i > 0:
+            m, z = _store(m, boundary), _store(z, boundary)
         m, z = block(m, z, msa_mask, pair_mask, p, cfg, relu_decision)
     return m, z
 
@@ -248,7 +265,7 @@ def _leaf(t):
     return t.detach().clone().to(F64).requires_grad_(True)
 
 
-def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None):
+def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None, boundary=None):
     """Forward and backward of the stack on float64 copies of ``inp``.
 
     Returns (m_out, z_out, grads) with grads = {"m", "z", "params"} where
@@ -256,13 +273,18 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None):
     <m_out, dm_out> + <z_out, dz_out>.  The chain rule is applied block by
     block (each block's forward is re-run under autograd during the backward),
     which keeps the memory of one block; the values are those of the plain
-    definition."""
+    definition.  `boundary`: storage precision between blocks (see the module
+    docstring)."""
     msa_mask = inp["msa_mask"].to(F64)
     pair_mask = inp["pair_mask"].to(F64)
     acts = [(inp["m"].detach().to(F64), inp["z"].detach().to(F64))]
     with torch.no_grad():
-        for p in inp["params"]:
-            acts.append(block(acts[-1][0], acts[-1][1], msa_mask, pair_mask, p, cfg, relu_decision))
+        for i, p in enumerate(inp["params"]):
+            mi, zi = acts[-1]
+            if i > 0:
+                mi, zi = _store(mi, boundary), _store(zi, boundary)
+                acts[-1] = (mi, zi)
+            acts.append(block(mi, zi, msa_mask, pair_mask, p, cfg, relu_decision))
     dm = inp["dm_out"].to(F64)
     dz = inp["dz_out"].to(F64)
     pgrads = [None] * len(inp["params"])
@@ -275,6 +297,8 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None):
         mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg, relu_decision)
         ((mo * dm).sum() + (zo * dz).sum()).backward()
         dm, dz = m.grad, z.grad
+        if i > 0:
+            dm, dz = _store(dm, boundary), _store(dz, boundary)
         if want_param_grads:
             pgrads[i] = {s: {k: v.grad for k, v in leaves[s].items()} for s in leaves}
     grads = {"m": dm, "z": dz}
@@ -283,7 +307,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None):
     return acts[-1][0], acts[-1][1], grads
 
 
-def stack_fwd(inp, cfg, relu_decision=None):
+def stack_fwd(inp, cfg, relu_decision=None, boundary=None):
     with torch.no_grad():
         return stack(inp["m"].to(F64), inp["z"].to(F64), inp["msa_mask"].to(F64),
-                     inp["pair_mask"].to(F64), inp["params"], cfg, relu_decision)
+                     inp["pair_mask"].to(F64), inp["params"], cfg, relu_decision, boundary)

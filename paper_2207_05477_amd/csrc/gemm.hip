@@ -885,9 +885,14 @@ static bool plain_info(const GemmArgs& g, PlainInfo& pi) {
 
 template <typename T, int BM, int BN, int WMW, int WNW>
 static void launch(const Ctx& ctx, const GemmArgs& g) {
-  static const std::string nm = std::string("gemm_kernel<") + tname<T>() + ", " + std::to_string(BM) +
-                                ", " + std::to_string(BN) + ", " + std::to_string(WMW) + ", " +
-                                std::to_string(WNW) + ">";
+  // profiler names spell the kernel instantiation (as a trace shows it)
+  static const std::string shape = std::string(tname<T>()) + ", " + std::to_string(BM) + ", " + std::to_string(BN) + ", " +
+                                   std::to_string(WMW) + ", " + std::to_string(WNW);
+  static const std::string names[2][4] = {
+      {"gemm_kernel<" + shape + ", false, false>", "gemm_kernel<" + shape + ", false, true>",
+       "gemm_kernel<" + shape + ", true, false>", "gemm_kernel<" + shape + ", true, true>"},
+      {"gemm_plain_kernel<" + shape + ", false, false>", "gemm_plain_kernel<" + shape + ", false, true>",
+       "gemm_plain_kernel<" + shape + ", true, false>", "gemm_plain_kernel<" + shape + ", true, true>"}};
   const int64_t ntn = (g.N + BN - 1) / BN, ntm = (g.M + BM - 1) / BM;
   dim3 grid((unsigned)(ntn * ntm), 1, (unsigned)(g.split_k > 1 ? g.split_k : g.batch));
   // four consecutive n of one m form one aligned vector of the output
@@ -920,25 +925,27 @@ static void launch(const Ctx& ctx, const GemmArgs& g) {
                     aux_ok(e.relu_ref, e.r_m, e.r_n, false) && aux_ok(e.gate, e.g_m, e.g_n, e.gate_f32 != 0);
   const int32_t nt = (int32_t)ntn, v4 = (vec4 ? 1 : 0) | (fast ? 2 : 0);
   PlainInfo pi;
-  if (plain_info<T>(g, pi)) {
+  const bool plain = plain_info<T>(g, pi);
+  const char* nm = names[plain ? 1 : 0][(g.A.k_contig ? 2 : 0) + (g.B.k_contig ? 1 : 0)].c_str();
+  if (plain) {
     if (g.A.k_contig && g.B.k_contig)
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, true, true>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+      EVO_LAUNCH(nm, flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, true, true>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
     else if (g.A.k_contig)
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, true, false>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+      EVO_LAUNCH(nm, flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, true, false>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
     else if (g.B.k_contig)
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, false, true>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+      EVO_LAUNCH(nm, flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, false, true>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
     else
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, false, false>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
+      EVO_LAUNCH(nm, flops, bytes, (gemm_plain_kernel<T, BM, BN, WMW, WNW, false, false>), grid, dim3(256), 0, ctx.stream, g, pi, nt);
     return;
   }
   if (g.A.k_contig && g.B.k_contig)
-    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, true, true>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+    EVO_LAUNCH(nm, flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, true, true>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
   else if (g.A.k_contig)
-    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, true, false>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+    EVO_LAUNCH(nm, flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, true, false>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
   else if (g.B.k_contig)
-    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, false, true>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+    EVO_LAUNCH(nm, flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, false, true>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
   else
-    EVO_LAUNCH(nm.c_str(), flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, false, false>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
+    EVO_LAUNCH(nm, flops, bytes, (gemm_kernel<T, BM, BN, WMW, WNW, false, false>), grid, dim3(256), 0, ctx.stream, g, nt, v4);
 }
 
 template <typename T>

@@ -85,29 +85,53 @@ void prof_end(int slot, hipStream_t s) {
 
 // ============================================================== weight gradients
 template <typename T>
-evo_status_t wgrad(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
-                   int64_t rows, int64_t M, int64_t N, float* dW) {
+evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
+                            int64_t rows, int64_t M, int nseg, const int* seg_off, const int* seg_n,
+                            float* const* dW) {
+  // the span covers every segment (null outputs included): a size query with
+  // null gradient pointers carves the same scratch as a real call
+  int lo = 1 << 30, hi = 0;
+  for (int s = 0; s < nseg; ++s) {
+    lo = seg_off[s] < lo ? seg_off[s] : lo;
+    hi = seg_off[s] + seg_n[s] > hi ? seg_off[s] + seg_n[s] : hi;
+  }
+  if (hi <= lo) return EVO_OK;
+  const int64_t N = hi - lo;
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
   int64_t split = (512 + tiles - 1) / tiles;
   int64_t maxsplit = rows / 256 > 0 ? rows / 256 : 1;
   if (split > maxsplit) split = maxsplit;
   if (split < 1) split = 1;
-  float* part = ws.take_n<float>((size_t)split * M * N);
+  const bool direct = split == 1 && nseg == 1;
+  float* part = direct ? nullptr : ws.take_n<float>((size_t)split * M * N);
   if (c.dry) return EVO_OK;
+  bool any = false;
+  for (int s = 0; s < nseg; ++s) any = any || dW[s];
+  if (!any) return EVO_OK;
   GemmArgs g;
   g.M = M; g.N = N; g.K = rows;
   g.split_k = (int)split;
   g.A = op_colmajor(X, ldx);
-  g.B = op_colmajor(dY, ldy);
-  g.epi = epi_rowmajor(part, N, true);
-  g.epi.batch = M * N;
-  if (split == 1) {   // single slice: accumulate straight into dW
-    g.epi.out = dW;
+  g.B = op_colmajor(dY + lo, ldy);
+  if (direct) {   // single slice, single segment: accumulate straight into dW
+    g.epi = epi_rowmajor(dW[0], N, true);
     g.epi.accumulate = 1;
     return gemm<T>(c, g);
   }
+  g.epi = epi_rowmajor(part, N, true);
+  g.epi.batch = M * N;
   EVO_TRY(gemm<T>(c, g));
-  return reduce_partials(c, part, split, M * N, M * N, dW, true);
+  RedSegs rs;
+  rs.nseg = nseg;
+  for (int s = 0; s < nseg; ++s) { rs.off[s] = seg_off[s] - lo; rs.n[s] = seg_n[s]; rs.out[s] = dW[s]; }
+  return reduce_segments(c, part, split, M, N, rs, true);
+}
+
+template <typename T>
+evo_status_t wgrad(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
+                   int64_t rows, int64_t M, int64_t N, float* dW) {
+  const int off = 0, n = (int)N;
+  return wgrad_segments<T>(c, ws, X, ldx, dY, ldy, rows, M, 1, &off, &n, &dW);
 }
 
 // ============================================================== pair-bias projection
@@ -144,44 +168,73 @@ evo_status_t rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float*
   return check_launch("rowproj");
 }
 
-// dx[row][c] (+)= sum_h dout[h][row] W[c][h]
+// dx[row][c] (+)= sum_h dout[h][row] W[c][h]: a block owns 32 rows; dout for
+// them and W sit in LDS; each lane produces 4 consecutive channels of a row.
 __global__ __launch_bounds__(256) void rowproj_dx_kernel(int64_t rows, int C, const float* __restrict__ W,
                                                          int H, const float* __restrict__ dout,
                                                          float* dx, int accumulate) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= rows * C) return;
-  const int64_t row = e / C;
-  const int cc = (int)(e % C);
-  float s = 0.f;
-  for (int h = 0; h < H; ++h) s += dout[(int64_t)h * rows + row] * W[cc * H + h];
-  dx[e] = accumulate ? dx[e] + s : s;
+  extern __shared__ float sm[];          // W [C][H], then dout [H][32]
+  float* sW = sm;
+  float* sd = sm + C * H;
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int nrow = rows - r0 < 32 ? (int)(rows - r0) : 32;
+  for (int e = tid; e < C * H; e += 256) sW[e] = W[e];
+  for (int e = tid; e < 32 * H; e += 256) {
+    const int h = e >> 5, rr = e & 31;
+    sd[e] = rr < nrow ? dout[(int64_t)h * rows + r0 + rr] : 0.f;
+  }
+  __syncthreads();
+  const int cpr = C >> 2;                // lanes per row
+  for (int e = tid; e < 32 * cpr; e += 256) {
+    const int rr = e / cpr, c0 = (e - rr * cpr) * 4;
+    if (rr >= nrow) continue;
+    f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int h = 0; h < H; ++h) {
+      const float d = sd[h * 32 + rr];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] += d * sW[(c0 + k) * H + h];
+    }
+    f32x4* o = (f32x4*)(dx + (r0 + rr) * C + c0);
+    if (accumulate) s += *o;
+    *o = s;
+  }
 }
 
-// partial dW over 256-row blocks: part[blk][C*H]
+// partial dW over 256-row blocks: part[blk][C*H]; the block's dout rows are
+// staged in LDS, each thread owns one channel and a quarter of the rows.
 template <typename T>
 __global__ __launch_bounds__(256) void rowproj_dw_kernel(const T* __restrict__ x, int64_t rows, int C,
                                                          int H, const float* __restrict__ dout,
                                                          float* __restrict__ part) {
-  __shared__ float red[256 * 16];
+  __shared__ float sd[16 * 256];
+  __shared__ float red[256 * 17];
+  const int tid = threadIdx.x;
   const int per = 256 / C;            // row subsets (C divides 256)
-  const int cc = threadIdx.x % C, rs = threadIdx.x / C;
+  const int cc = tid % C, rs = tid / C;
   const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int nrow = rows - r0 < 256 ? (int)(rows - r0) : 256;
+  for (int e = tid; e < H * 256; e += 256) {
+    const int h = e >> 8, rr = e & 255;
+    sd[e] = rr < nrow ? dout[(int64_t)h * rows + r0 + rr] : 0.f;
+  }
+  __syncthreads();
   float acc[16];
 #pragma unroll
   for (int h = 0; h < 16; ++h) acc[h] = 0.f;
-  for (int64_t r = r0 + rs; r < r0 + 256 && r < rows; r += per) {
-    const float v = to_f32(x[r * C + cc]);
+  for (int rr = rs; rr < nrow; rr += per) {
+    const float v = to_f32(x[(r0 + rr) * C + cc]);
 #pragma unroll
     for (int h = 0; h < 16; ++h)
-      if (h < H) acc[h] += v * dout[(int64_t)h * rows + r];
+      if (h < H) acc[h] += v * sd[h * 256 + rr];
   }
 #pragma unroll
-  for (int h = 0; h < 16; ++h) red[threadIdx.x * 16 + h] = acc[h];
+  for (int h = 0; h < 16; ++h) red[tid * 17 + h] = acc[h];
   __syncthreads();
-  for (int e = threadIdx.x; e < C * H; e += 256) {
-    const int c2 = e / H, h = e % H;
+  for (int e = tid; e < C * H; e += 256) {
+    const int c2 = e / H, h = e - c2 * H;
     float s = 0.f;
-    for (int q = 0; q < per; ++q) s += red[(q * C + c2) * 16 + h];
+    for (int q = 0; q < per; ++q) s += red[(q * C + c2) * 17 + h];
     part[(int64_t)blockIdx.x * C * H + e] = s;
   }
 }
@@ -195,7 +248,10 @@ evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int 
   if (H > 16 || C > 256 || 256 % C) { set_error("pair bias bwd: unsupported C=%d H=%d", C, H); return EVO_ESHAPE; }
   if (dx) {
     const int64_t n = rows * C;
-    EVO_LAUNCH("rowproj_dx_kernel", 2.0 * (double)rows * C * H, (double)rows * C * (accumulate ? 8.0 : 4.0) + (double)H * rows * 4.0, rowproj_dx_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
+    (void)n;
+    if (C % 4 || ((uintptr_t)dx) % 16) { set_error("pair bias bwd: C=%d not a multiple of 4", C); return EVO_ESHAPE; }
+    const size_t lds = ((size_t)C * H + 32 * (size_t)H) * sizeof(float);
+    EVO_LAUNCH("rowproj_dx_kernel", 2.0 * (double)rows * C * H, (double)rows * C * (accumulate ? 8.0 : 4.0) + (double)H * rows * 4.0, rowproj_dx_kernel, dim3((unsigned)((rows + 31) / 32)), dim3(256), lds, c.stream,
                        rows, C, W, H, dout, dx, accumulate ? 1 : 0);
     EVO_TRY(check_launch("rowproj_dx"));
   }
@@ -221,18 +277,23 @@ evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, 
   const int64_t nblk = colsum_partials(rows);
   float* part = ws.take_n<float>((size_t)nblk * span);
   if (c.dry || rows == 0) return EVO_OK;
+  bool any = false;
+  for (int s = 0; s < nseg; ++s) any = any || outs[s];
+  if (!any) return EVO_OK;
   int nb = 0;
   EVO_TRY(colsum_partial<T>(c, x + lo, rows, span, ld, part, &nb));
-  for (int s = 0; s < nseg; ++s) {
-    if (!outs[s]) continue;
-    EVO_TRY(reduce_partials(c, part + (seg_off[s] - lo), nb, seg_n[s], span, outs[s], true));
-  }
-  return EVO_OK;
+  RedSegs rs;
+  rs.nseg = nseg;
+  for (int s = 0; s < nseg; ++s) { rs.off[s] = seg_off[s] - lo; rs.n[s] = seg_n[s]; rs.out[s] = outs[s]; }
+  return reduce_segments(c, part, nb, 1, span, rs, true);
 }
 
 #define EVO_INST_H(T)                                                                              \
   template evo_status_t wgrad<T>(const Ctx&, Arena&, const T*, int64_t, const T*, int64_t, int64_t, \
                                  int64_t, int64_t, float*);                                        \
+  template evo_status_t wgrad_segments<T>(const Ctx&, Arena&, const T*, int64_t, const T*, int64_t, \
+                                          int64_t, int64_t, int, const int*, const int*,            \
+                                          float* const*);                                          \
   template evo_status_t rowproj<T>(const Ctx&, const T*, int64_t, int, const float*, int, float*); \
   template evo_status_t rowproj_bwd<T>(const Ctx&, Arena&, const T*, int64_t, int, const float*,   \
                                        int, const float*, float*, bool, float*);                   \

@@ -38,6 +38,18 @@ int64_t ln_bwd_cm_partials(int64_t P);
 // out[j] (+)= sum_i part[i * ld + j], i < n, j < C (fixed order).
 evo_status_t reduce_partials(const Ctx& c, const float* part, int64_t n, int64_t C, int64_t ld,
                              float* out, bool accumulate);
+// Segmented reduction in one launch.  part is [n][M][ld]; segment s covers
+// columns [off_s, off_s + n_s) and accumulates (or stores)
+//   out_s[m * n_s + j] (+)= sum_{i<n} part[(i * M + m) * ld + off_s + j]
+// in a fixed order.  Up to 8 segments; null outputs are skipped.
+struct RedSegs {
+  int32_t nseg = 0;
+  int32_t off[8];
+  int32_t n[8];
+  float* out[8];
+};
+evo_status_t reduce_segments(const Ctx& c, const float* part, int64_t n, int64_t M, int64_t ld,
+                             const RedSegs& segs, bool accumulate);
 // Two outputs from one [n][2C] partial buffer (LayerNorm gamma / beta).
 evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C, float* out_a,
                               float* out_b);

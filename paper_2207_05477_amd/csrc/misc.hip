@@ -64,50 +64,66 @@ evo_status_t ln_fwd(const Ctx& c, const TI* x, int64_t rows, int C, const float*
   return ln_fwd_rows<TI, T>(c, x, rows, C, -1, 0, g, b, eps, y, mean, rstd);
 }
 
-// Fused LayerNorm + small projection (pair bias of the chunked forward): one
-// wave per row, FP32 statistics, H dot products reduced across the wave.
-template <typename TI, typename T, int NV>
+// Fused LayerNorm + small projection (pair bias): a block owns RPB rows; the
+// row tile goes through LDS (coalesced loads), then 256 / RPB lanes share a
+// row: each reduces an interleaved share of the channels for the statistics
+// and the H dot products, and xor-shuffles combine the shares.
+template <typename TI, typename T, int RPB>
 __global__ __launch_bounds__(256) void ln_rowproj_kernel(const TI* __restrict__ x, int64_t rows, int C,
                                                          const float* __restrict__ g,
                                                          const float* __restrict__ b, float eps,
                                                          const float* __restrict__ W, int H,
                                                          float* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows) return;
-  const TI* xr = x + row * C;
-  float v[NV];
+  constexpr int LPR = 256 / RPB;          // lanes per row
+  extern __shared__ float sm[];           // tile [RPB][C + 4], then W [C][H]
+  const int ldt = C + 4;
+  float* tile = sm;
+  float* sW = sm + RPB * ldt;
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * RPB;
+  const int nrow = rows - r0 < RPB ? (int)(rows - r0) : RPB;
+  for (int e = tid; e < C * H; e += 256) sW[e] = W[e];
+  for (int e = tid; e < RPB * C; e += 256) {
+    const int rr = e / C, cc = e - rr * C;
+    tile[rr * ldt + cc] = rr < nrow ? to_f32(x[(r0 + rr) * C + cc]) : 0.f;
+  }
+  __syncthreads();
+  const int rr = tid / LPR, q = tid % LPR;
+  const float* t = tile + rr * ldt;
   float s = 0.f;
+  for (int cc = q; cc < C; cc += LPR) s += t[cc];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int c = lane + 64 * i;
-    v[i] = c < C ? to_f32(xr[c]) : 0.f;
-    s += v[i];
+  for (int o = 1; o < LPR; o <<= 1) s += __shfl_xor(s, o, 64);
+  const float mu = s / (float)C;
+  float v = 0.f;
+  for (int cc = q; cc < C; cc += LPR) {
+    const float d = t[cc] - mu;
+    v += d * d;
   }
-  const float mu = wave_sum(s) / (float)C;
-  float q = 0.f;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int c = lane + 64 * i;
-    const float d = c < C ? v[i] - mu : 0.f;
-    q += d * d;
-  }
-  const float rs = 1.0f / sqrtf(wave_sum(q) / (float)C + eps);
+  for (int o = 1; o < LPR; o <<= 1) v += __shfl_xor(v, o, 64);
+  const float rs = 1.0f / sqrtf(v / (float)C + eps);
+  float acc[16];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int c = lane + 64 * i;
+  for (int h = 0; h < 16; ++h) acc[h] = 0.f;
+  for (int cc = q; cc < C; cc += LPR) {
     // the projection reads the LayerNorm output in the storage precision
-    v[i] = c < C ? to_f32(from_f32<T>((v[i] - mu) * rs * g[c] + b[c])) : 0.f;
-  }
-  for (int h = 0; h < H; ++h) {
-    float acc = 0.f;
+    const float yv = to_f32(from_f32<T>((t[cc] - mu) * rs * g[cc] + b[cc]));
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int c = lane + 64 * i;
-      if (c < C) acc += v[i] * W[c * H + h];
+    for (int h = 0; h < 16; ++h)
+      if (h < H) acc[h] += yv * sW[cc * H + h];
+  }
+#pragma unroll
+  for (int h = 0; h < 16; ++h) {
+    if (h < H) {
+#pragma unroll
+      for (int o = 1; o < LPR; o <<= 1) acc[h] += __shfl_xor(acc[h], o, 64);
     }
-    acc = wave_sum(acc);
-    if (lane == 0) out[(int64_t)h * rows + row] = acc;
+  }
+  if (rr < nrow) {
+#pragma unroll
+    for (int h = 0; h < 16; ++h)
+      if (h < H && h % LPR == q) out[(int64_t)h * rows + r0 + rr] = acc[h];
   }
 }
 
@@ -115,13 +131,18 @@ template <typename TI, typename T>
 evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
                         float eps, const float* W, int H, float* out) {
   if (c.dry || rows == 0) return EVO_OK;
-  dim3 grid((unsigned)((rows + 3) / 4));
+  if (C > 256 || H > 16) { set_error("layernorm projection: C=%d H=%d unsupported", C, H); return EVO_ESHAPE; }
   const double bytes = (double)rows * C * sizeof(TI) + (double)rows * H * 4.0;
   const double flops = 2.0 * rows * C * H;
-  if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
-  else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
-  else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
-  else { set_error("layernorm projection: C=%d > 256", C); return EVO_ESHAPE; }
+  if (C <= 128) {
+    const size_t lds = ((size_t)64 * (C + 4) + (size_t)C * H) * sizeof(float);
+    EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 64>),
+               dim3((unsigned)((rows + 63) / 64)), dim3(256), lds, c.stream, x, rows, C, g, b, eps, W, H, out);
+  } else {
+    const size_t lds = ((size_t)32 * (C + 4) + (size_t)C * H) * sizeof(float);
+    EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 32>),
+               dim3((unsigned)((rows + 31) / 32)), dim3(256), lds, c.stream, x, rows, C, g, b, eps, W, H, out);
+  }
   return check_launch("ln_rowproj");
 }
 
@@ -372,10 +393,80 @@ evo_status_t reduce_partials(const Ctx& c, const float* part, int64_t n, int64_t
   return check_launch("reduce_partials");
 }
 
+// Segmented version: flattened column e = m * ld + c of a [M][ld] slice; each
+// column finds its segment (if any) and writes out_s[m * n_s + c - off_s].
+EVO_DEV int seg_of(const RedSegs& s, int c) {
+  int r = -1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < s.nseg && c >= s.off[k] && c < s.off[k] + s.n[k]) r = k;
+  return r;
+}
+
+__global__ __launch_bounds__(256) void reduce_segments_kernel(const float* __restrict__ part, int64_t n,
+                                                              int64_t M, int64_t ld, RedSegs segs,
+                                                              int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * ld) return;
+  const int64_t m = e / ld;
+  const int c = (int)(e - m * ld);
+  const int k = seg_of(segs, c);
+  if (k < 0 || !segs.out[k]) return;
+  float s = 0.f;
+  for (int64_t i = 0; i < n; ++i) s += part[i * M * ld + e];
+  float* o = segs.out[k] + m * segs.n[k] + (c - segs.off[k]);
+  *o = accumulate ? *o + s : s;
+}
+
+__global__ __launch_bounds__(256) void reduce_segments_narrow_kernel(const float* __restrict__ part, int64_t n,
+                                                                     int64_t M, int64_t ld, RedSegs segs,
+                                                                     int accumulate) {
+  __shared__ float red[RN_ROWS][RN_COLS + 1];
+  const int tc = threadIdx.x % RN_COLS, tr = threadIdx.x / RN_COLS;
+  const int64_t e = (int64_t)blockIdx.x * RN_COLS + tc;
+  const bool in = e < M * ld;
+  float s = 0.f;
+  if (in)
+    for (int64_t i = tr; i < n; i += RN_ROWS) s += part[i * M * ld + e];
+  red[tr][tc] = s;
+  __syncthreads();
+  for (int w = RN_ROWS / 2; w > 0; w >>= 1) {
+    if (tr < w) red[tr][tc] += red[tr + w][tc];
+    __syncthreads();
+  }
+  if (tr != 0 || !in) return;
+  const int64_t m = e / ld;
+  const int c = (int)(e - m * ld);
+  const int k = seg_of(segs, c);
+  if (k < 0 || !segs.out[k]) return;
+  float* o = segs.out[k] + m * segs.n[k] + (c - segs.off[k]);
+  *o = accumulate ? *o + red[0][tc] : red[0][tc];
+}
+
+evo_status_t reduce_segments(const Ctx& c, const float* part, int64_t n, int64_t M, int64_t ld,
+                             const RedSegs& segs, bool accumulate) {
+  if (c.dry || M * ld == 0 || segs.nseg == 0) return EVO_OK;
+  if (segs.nseg > 8) { set_error("reduce: %d segments > 8", segs.nseg); return EVO_EINVAL; }
+  const int64_t C = M * ld;
+  const double bytes = ((double)n + 1) * C * 4.0;
+  if (C >= 65536 || n < 64) {
+    EVO_LAUNCH("reduce_segments_kernel", 0.0, bytes, reduce_segments_kernel, dim3((unsigned)((C + 255) / 256)),
+               dim3(256), 0, c.stream, part, n, M, ld, segs, accumulate ? 1 : 0);
+  } else {
+    EVO_LAUNCH("reduce_segments_narrow_kernel", 0.0, bytes, reduce_segments_narrow_kernel,
+               dim3((unsigned)((C + RN_COLS - 1) / RN_COLS)), dim3(256), 0, c.stream, part, n, M, ld, segs,
+               accumulate ? 1 : 0);
+  }
+  return check_launch("reduce_segments");
+}
+
 evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C, float* out_a,
                               float* out_b) {
-  EVO_TRY(reduce_partials(c, part, n, C, 2 * C, out_a, true));
-  return reduce_partials(c, part + C, n, C, 2 * C, out_b, true);
+  RedSegs s;
+  s.nseg = 2;
+  s.off[0] = 0; s.n[0] = C; s.out[0] = out_a;
+  s.off[1] = C; s.n[1] = C; s.out[1] = out_b;
+  return reduce_segments(c, part, n, 1, 2 * C, s, true);
 }
 
 // Column sums over blocks of CS_ROWS rows.  A workgroup owns 64 columns x

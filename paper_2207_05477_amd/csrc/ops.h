@@ -16,6 +16,12 @@ namespace evo {
 template <typename T>
 evo_status_t wgrad(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
                    int64_t rows, int64_t M, int64_t N, float* dW);
+// Segments of one weight-gradient GEMM: dW_s[M][n_s] += X^T dY[:, off_s : off_s + n_s]
+// for each s (one GEMM over the span of all segments, one segmented reduction).
+template <typename T>
+evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
+                            int64_t rows, int64_t M, int nseg, const int* seg_off, const int* seg_n,
+                            float* const* dW);
 // out[h][row] = sum_c x[row][c] W[c][h]  (H <= 16), FP32 out.
 template <typename T>
 evo_status_t rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* W, int H, float* out);

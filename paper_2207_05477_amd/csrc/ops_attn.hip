@@ -356,10 +356,10 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     float* outs[1] = {dw.b_g};
     EVO_TRY(colsum_segments<T>(c, ws, dqkvg, s.rows, s.NQ, 1, &off, &n, outs));
     const int kv = s.global ? s.D : s.HC;
-    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg, s.NQ, s.rows, s.cin, s.HC, dw.w_q));
-    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg + s.HC, s.NQ, s.rows, s.cin, kv, dw.w_k));
-    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg + s.HC + kv, s.NQ, s.rows, s.cin, kv, dw.w_v));
-    EVO_TRY(wgrad<T>(c, ws, S.y, s.cin, dqkvg + s.NQ - s.HC, s.NQ, s.rows, s.cin, s.HC, dw.w_g));
+    const int woff[4] = {0, s.HC, s.HC + kv, (int)(s.NQ - s.HC)};
+    const int wn[4] = {s.HC, kv, kv, s.HC};
+    float* const wout[4] = {dw.w_q, dw.w_k, dw.w_v, dw.w_g};
+    EVO_TRY(wgrad_segments<T>(c, ws, S.y, s.cin, dqkvg, s.NQ, s.rows, s.cin, 4, woff, wn, wout));
     GemmArgs g;
     g.M = s.rows; g.N = s.cin; g.K = s.NQ;
     g.A = op_rowmajor(dqkvg, s.NQ);

@@ -247,8 +247,11 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   int offs[2] = {0, (int)ch}, ns[2] = {(int)ch, (int)ch};
   float* obab[2] = {dw.b_a, dw.b_b};
   EVO_TRY(colsum_segments<T>(c, ws, dab, SR, 2 * ch, 2, offs, ns, obab));
-  EVO_TRY(wgrad<T>(c, ws, S.y, cm, dab, 2 * ch, SR, cm, ch, dw.w_a));
-  EVO_TRY(wgrad<T>(c, ws, S.y, cm, dab + ch, 2 * ch, SR, cm, ch, dw.w_b));
+  {
+    const int woff[2] = {0, (int)ch}, wn[2] = {(int)ch, (int)ch};
+    float* const wout[2] = {dw.w_a, dw.w_b};
+    EVO_TRY(wgrad_segments<T>(c, ws, S.y, cm, dab, 2 * ch, SR, cm, 2, woff, wn, wout));
+  }
   if (!c.dry) {
     GemmArgs g;
     g.M = SR; g.N = cm; g.K = 2 * ch;
@@ -529,7 +532,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   float* owp[5] = {dw.w_ap, dw.w_ag, dw.w_bp, dw.w_bg, dw.w_g};
   {
     ProfTag t_("wgrad_proj");
-    for (int s = 0; s < 5; ++s) EVO_TRY(wgrad<T>(c, ws, S.y, cz, draw + offs[s], NP, P, cz, ns[s], owp[s]));
+    EVO_TRY(wgrad_segments<T>(c, ws, S.y, cz, draw, NP, P, cz, 5, offs, ns, owp));
   }
   if (!c.dry) {
     GemmArgs g;

@@ -90,9 +90,10 @@ def kink_free(inp):
 
 
 # Coarse gate for gradients of full-parameter blocks: ReLU kinks in the
-# transitions flip with the upstream rounding of the block's own forward, each
-# flip moving a whole gradient entry (parity status).
-KINK_TOL = {"f32": 1e-3, "bf16": 0.15}
+# transitions flip with the rounding of the block's own forward (any change of
+# summation order moves which units sit within rounding of zero), and each flip
+# moves whole gradient entries.  The kink-free variants are the parity gate.
+KINK_TOL = {"f32": 2e-2, "bf16": 0.15}
 
 
 def device_view(inp, dtype):

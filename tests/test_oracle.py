@@ -371,6 +371,41 @@ def test_stack_fwd_bwd_grads_match_gradcheck_direction():
     assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
 
 
+def test_stack_bf16_boundary_one_block_is_plain():
+    # a single block has no internal boundary: the storage reading changes nothing
+    cfg = TINY.replace(n_blocks=1)
+    inp = make_inputs(cfg, seed=15, perturb=True)
+    a = O.stack_fwd_bwd(inp, cfg)
+    b = O.stack_fwd_bwd(inp, cfg, boundary="bf16")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert torch.equal(a[2]["m"], b[2]["m"]) and torch.equal(a[2]["z"], b[2]["z"])
+
+
+def test_stack_bf16_boundary_rounds_between_blocks():
+    # two blocks: the second block sees the BF16-stored output of the first, and
+    # the first block's backward sees the BF16-stored gradient of the second
+    cfg = TINY.replace(n_blocks=2)
+    inp = make_inputs(cfg, seed=16, perturb=True)
+    mo, zo, g = O.stack_fwd_bwd(inp, cfg, boundary="bf16")
+    mm, pm = inp["msa_mask"], inp["pair_mask"]
+    rnd = lambda t: t.detach().to(torch.bfloat16).to(F64)
+    with torch.no_grad():
+        m1, z1 = O.block(inp["m"], inp["z"], mm, pm, inp["params"][0], cfg)
+        m2, z2 = O.block(rnd(m1), rnd(z1), mm, pm, inp["params"][1], cfg)
+    assert torch.equal(mo, m2) and torch.equal(zo, z2)
+    assert not torch.equal(rnd(m1), m1)            # the rounding is not a no-op here
+    # block 1's input gradient, rounded, drives block 0's backward
+    m1r, z1r = rnd(m1).requires_grad_(True), rnd(z1).requires_grad_(True)
+    a, b = O.block(m1r, z1r, mm, pm, inp["params"][1], cfg)
+    ((a * inp["dm_out"]).sum() + (b * inp["dz_out"]).sum()).backward()
+    m0 = inp["m"].clone().requires_grad_(True)
+    z0 = inp["z"].clone().requires_grad_(True)
+    a, b = O.block(m0, z0, mm, pm, inp["params"][0], cfg)
+    ((a * rnd(m1r.grad)).sum() + (b * rnd(z1r.grad)).sum()).backward()
+    assert torch.allclose(g["m"], m0.grad, rtol=1e-12, atol=1e-12)
+    assert torch.allclose(g["z"], z0.grad, rtol=1e-12, atol=1e-12)
+
+
 # ---------------------------------------------------------------- paper's worked example
 
 def test_golden_logits_memory_example():
