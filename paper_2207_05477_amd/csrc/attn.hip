@@ -94,22 +94,97 @@ EVO_DEV f32x4 contract64(const T* trow, bool rok, const f32x4* p, int lg, f32x4 
 }
 
 // Stage a 64-row tile of (position, head) rows [p0, p0+64) of `src` into LDS:
-// row-major [64][DP] (if dst_rm) and/or transposed [DR][TP] (if dst_t).
+// row-major [64][DP] (if dst_rm) and/or transposed [DR][TP] (if dst_t).  The
+// transposed copy takes two rows per lane so that each store moves a pair of
+// rows of one d (4 or 8 bytes) into consecutive LDS words.
 template <typename T, int D>
 EVO_DEV void stage_tile(const T* src, int64_t sp, int64_t p0, int64_t pend, T* dst_rm, T* dst_t,
                         int tid) {
   using F = DF<T, D>;
   constexpr int VPR = D / F::VEC;  // vectors per row
+  if (dst_t) {
+    for (int e = tid; e < (KB / 2) * VPR; e += 256) {
+      const int j = e % (KB / 2), dv = (e / (KB / 2)) * F::VEC;
+      const int r = 2 * j;
+      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+      if (p0 + r < pend) v0 = *(const uint4*)(src + (p0 + r) * sp + dv);
+      if (p0 + r + 1 < pend) v1 = *(const uint4*)(src + (p0 + r + 1) * sp + dv);
+      if (dst_rm) {
+        *(uint4*)(dst_rm + r * F::DP + dv) = v0;
+        *(uint4*)(dst_rm + (r + 1) * F::DP + dv) = v1;
+      }
+      const T* e0 = (const T*)&v0;
+      const T* e1 = (const T*)&v1;
+#pragma unroll
+      for (int i = 0; i < F::VEC; ++i) {
+        typedef __attribute__((__vector_size__(2 * sizeof(T)))) T t2;
+        *(t2*)(dst_t + (dv + i) * F::TP + r) = t2{e0[i], e1[i]};
+      }
+    }
+    return;
+  }
   for (int e = tid; e < KB * VPR; e += 256) {
     const int r = e / VPR, dv = (e % VPR) * F::VEC;
     const int64_t p = p0 + r;
     uint4 val = make_uint4(0, 0, 0, 0);
     if (p < pend) val = *(const uint4*)(src + p * sp + dv);
-    if (dst_rm) *(uint4*)(dst_rm + r * F::DP + dv) = val;
-    if (dst_t) {
-      const T* ev = (const T*)&val;
+    *(uint4*)(dst_rm + r * F::DP + dv) = val;
+  }
+}
+
+// Bias tile in LDS, log2 domain: sb[r * BP + c] = log2(e) * bias[(r0 + r) * sr + (c0 + c) * sc]
+// for rows r < 64 and columns c < 64 in range (0 elsewhere); the loads run
+// along whichever of the two strides is 1.
+constexpr int BP = 68;
+// Row pitch of the bias-gradient accumulator: a multiple of 64 keys plus 4, so
+// that each lane's aligned 4-key vector lands on its own banks.
+inline __host__ __device__ int64_t attn_acc_ld(int64_t Lk) { return (Lk + 63) / 64 * 64 + 4; }
+EVO_DEV void stage_bias(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
+                        int64_t cend, float* sb, int tid) {
+  const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
+  const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
+  if (sc == 1) {
+    // rows of 64 contiguous floats: 16 lanes x float4 per row
+    const float* base = bias + r0 * sr + c0;
+    const bool vec = (nc == 64) && ((((uintptr_t)base) | (uintptr_t)(sr * 4)) % 16 == 0);
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int r = e >> 4, c = (e & 15) * 4;
+      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (r < nr) {
+        const float* src = base + r * sr + c;
+        if (vec) {
+          v = *(const f32x4*)src;
+        } else {
 #pragma unroll
-      for (int i = 0; i < F::VEC; ++i) dst_t[(dv + i) * F::TP + r] = ev[i];
+          for (int i = 0; i < 4; ++i) v[i] = c + i < nc ? src[i] : 0.f;
+        }
+      }
+      *(f32x4*)(sb + r * BP + c) = v * kLog2e;
+    }
+  } else if (sr == 1) {
+    // columns of 64 contiguous floats (along r): float4 loads, transposed stores
+    const float* base = bias + c0 * sc + r0;
+    const bool vec = (nr == 64) && ((((uintptr_t)base) | (uintptr_t)(sc * 4)) % 16 == 0);
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int c = e >> 4, r = (e & 15) * 4;
+      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (c < nc) {
+        const float* src = base + c * sc + r;
+        if (vec) {
+          v = *(const f32x4*)src;
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = r + i < nr ? src[i] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[i] * kLog2e;
+    }
+  } else {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      const bool ok = r < nr && c < nc;
+      sb[r * BP + c] = ok ? bias[(c0 + c) * sc + (r0 + r) * sr] * kLog2e : 0.f;
     }
   }
 }
@@ -138,13 +213,17 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
   using F = DF<T, D>;
   __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sVt[F::DR * F::TP];
+  __shared__ __attribute__((aligned(16))) float sB[64 * BP];
+  __shared__ float sMk[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int64_t b = blockIdx.z;
   const int h = blockIdx.y;
   const int64_t qend0 = a.q_count < 0 ? a.Lq : a.q_begin + a.q_count;
   const int64_t qend = qend0 < a.Lq ? qend0 : a.Lq;
-  const int64_t qi = a.q_begin + (int64_t)blockIdx.x * 64 + wave * 16 + lr;
+  const int64_t q0 = a.q_begin + (int64_t)blockIdx.x * 64;
+  const int ql = wave * 16 + lr;
+  const int64_t qi = q0 + ql;
   const bool qok = qi < qend;
 
   const T* Q = (const T*)a.q + b * a.sb + h * D;
@@ -160,13 +239,15 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
 #pragma unroll
   for (int dt = 0; dt < F::NDT; ++dt) oacc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const float* bias = a.bias ? a.bias + h * a.bh + (qok ? qi : 0) * a.bq : nullptr;
+  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
   const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
 
   for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
     __syncthreads();
     stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, nullptr, tid);
     stage_tile<T, D>(V, a.sp, kb0, a.Lk, nullptr, sVt, tid);
+    if (bias) stage_bias(bias, a.bq, a.bk, q0, qend, kb0, a.Lk, sB, tid);
+    if (tid < KB) sMk[tid] = (mask && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
     __syncthreads();
     f32x4 s[4];
     float mloc = -INFINITY;
@@ -175,15 +256,16 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
       typename F::Frag kf[F::NKS];
       load_dfrag<T, D>(sK + (16 * t + lr) * F::DP, lg, true, kf);
       s[t] = mfma_d<T, D>(kf, qf);
+      const f32x4 bv = bias ? *(const f32x4*)(sB + ql * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t key = kb0 + 16 * t + 4 * lg + i;
+        const int kl = 16 * t + 4 * lg + i;
         float x = s[t][i] * scale_log2;
-        if (key >= a.Lk) {
+        if (kb0 + kl >= a.Lk) {
           x = -INFINITY;
         } else {
-          if (bias && qok) x += bias[key * a.bk] * kLog2e;
-          if (mask && mask[key * a.mk] == 0.f) x = kMaskLogit;
+          if (bias) x += bv[i];
+          if (sMk[kl] == 0.f) x = kMaskLogit;
         }
         s[t][i] = x;
         mloc = fmaxf(mloc, x);
@@ -248,7 +330,9 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
   __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sV[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
-  extern __shared__ float sacc[];  // [64][Lk + 1] bias-gradient accumulator
+  __shared__ __attribute__((aligned(16))) float sB[64 * BP];
+  __shared__ float sMk[KB];
+  extern __shared__ float sacc[];  // [64][acc_ld] bias-gradient accumulator
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int h = blockIdx.y;
@@ -258,7 +342,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
   const int64_t qloc = wave * 16 + lr;
   const int64_t qi = (int64_t)blockIdx.x * 64 + qloc;
   const bool qok = qi < a.Lq;
-  const int64_t acc_ld = a.Lk + 1;
+  const int64_t acc_ld = attn_acc_ld(a.Lk);
   const bool dbias = gr.dbias_part != nullptr;
 
   zero_pad_rows<T, D>(sKt, tid);
@@ -280,8 +364,9 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
       irow = a.st_inv[si];
       drow = gr.Dsum[si];
     }
-    const float* bias = a.bias ? a.bias + h * a.bh + (qok ? qi : 0) * a.bq : nullptr;
+    const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
     const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
+    const int64_t q0 = (int64_t)blockIdx.x * 64;
     f32x4 dq[F::NDT];
 #pragma unroll
     for (int dt = 0; dt < F::NDT; ++dt) dq[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -290,6 +375,8 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
       __syncthreads();
       stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, sKt, tid);
       stage_tile<T, D>(V, a.sp, kb0, a.Lk, sV, nullptr, tid);
+      if (bias) stage_bias(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, sB, tid);
+      if (tid < KB) sMk[tid] = (mask && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
       __syncthreads();
       f32x4 ds[4];
 #pragma unroll
@@ -299,21 +386,26 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
         load_dfrag<T, D>(sV + (16 * t + lr) * F::DP, lg, true, vf);
         const f32x4 s = mfma_d<T, D>(kf, qf);
         const f32x4 dp = mfma_d<T, D>(vf, of);
+        const f32x4 bv = bias ? *(const f32x4*)(sB + qloc * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int64_t key = kb0 + 16 * t + 4 * lg + i;
           float r = 0.f;
           if (qok && key < a.Lk) {
             float x = s[i] * scale_log2;
-            if (bias) x += bias[key * a.bk] * kLog2e;
-            const bool masked = mask && mask[key * a.mk] == 0.f;
+            if (bias) x += bv[i];
+            const bool masked = sMk[16 * t + 4 * lg + i] == 0.f;
             if (!masked) {
               const float p = exp2f(x - mrow) * irow;
               r = p * (dp[i] - drow);
             }
-            if (dbias) sacc[qloc * acc_ld + key] += r;
           }
           ds[t][i] = r;
+        }
+        // each lane owns these four accumulator entries: plain vector add
+        if (dbias && qok) {
+          f32x4* acc4 = (f32x4*)(sacc + qloc * acc_ld + kb0 + 16 * t + 4 * lg);
+          *acc4 = *acc4 + ds[t];
         }
       }
 #pragma unroll
@@ -336,9 +428,16 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
     // partial slice laid out like the bias itself: [group][H][.. q*bq + key*bk ..]
     float* out = gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk;
     const int64_t q0 = (int64_t)blockIdx.x * 64;
-    for (int64_t e = tid; e < 64 * a.Lk; e += 256) {
-      const int64_t ql = e / a.Lk, key = e % a.Lk;
-      if (q0 + ql < a.Lq) out[(q0 + ql) * a.bq + key * a.bk] = sacc[ql * acc_ld + key];
+    const int nq = a.Lq - q0 < 64 ? (int)(a.Lq - q0) : 64;
+    if (a.bk == 1) {          // rows of keys contiguous
+      for (int ql = 0; ql < nq; ++ql)
+        for (int64_t key = tid; key < a.Lk; key += 256) out[(q0 + ql) * a.bq + key] = sacc[ql * acc_ld + key];
+    } else {                  // queries contiguous
+      for (int64_t kbase = 0; kbase < a.Lk; kbase += 4) {
+        const int ql = tid & 63;
+        const int64_t key = kbase + (tid >> 6);
+        if (ql < nq && key < a.Lk) out[(q0 + ql) * a.bq + key * a.bk] = sacc[ql * acc_ld + key];
+      }
     }
   }
 }
@@ -352,6 +451,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
   __shared__ __attribute__((aligned(16))) T sO[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sQt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) T sOt[F::DR * F::TP];
+  __shared__ __attribute__((aligned(16))) float sB[64 * BP];
   __shared__ float sM[KB], sI[KB], sD[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
@@ -368,7 +468,9 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
   typename F::Frag kf[F::NKS], vf[F::NKS];
   load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
   load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
-  const float* bias = a.bias ? a.bias + h * a.bh + (kok ? key : 0) * a.bk : nullptr;
+  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int kl = wave * 16 + lr;
 
   zero_pad_rows<T, D>(sQt, tid);
   zero_pad_rows<T, D>(sOt, tid);
@@ -380,6 +482,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
     __syncthreads();
     stage_tile<T, D>(Q, a.sp, qb0, a.Lq, sQ, sQt, tid);
     stage_tile<T, D>(DO, a.osp, qb0, a.Lq, sO, sOt, tid);
+    if (bias) stage_bias(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, sB, tid);
     if (tid < KB) {
       const int64_t q = qb0 + tid;
       float mv = 0.f, iv = 0.f, dvv = 0.f;
@@ -398,6 +501,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
       load_dfrag<T, D>(sO + (16 * t + lr) * F::DP, lg, true, of);
       const f32x4 s = mfma_d<T, D>(qf, kf);
       const f32x4 dp = mfma_d<T, D>(of, vf);
+      const f32x4 bv = bias ? *(const f32x4*)(sB + kl * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int ql = 16 * t + 4 * lg + i;
@@ -405,7 +509,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
         float p = 0.f, r = 0.f;
         if (kok && q < a.Lq) {
           float x = s[i] * scale_log2;
-          if (bias) x += bias[q * a.bq] * kLog2e;
+          if (bias) x += bv[i];
           if (kmasked) x = kMaskLogit;
           p = exp2f(x - sM[ql]) * sI[ql];
           if (!kmasked) r = p * (dp[i] - sD[ql]);
@@ -495,7 +599,7 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   g.group = (a.nbatch + ngroups - 1) / ngroups;
   size_t lds = 0;
   if (g.dbias_part) {
-    lds = (size_t)64 * (a.Lk + 1) * sizeof(float);
+    lds = (size_t)64 * attn_acc_ld(a.Lk) * sizeof(float);
     if (lds > 120 * 1024) {
       set_error("attention backward: %lld keys exceed the bias-gradient LDS tile", (long long)a.Lk);
       return EVO_ESHAPE;
