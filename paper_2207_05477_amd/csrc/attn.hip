@@ -136,9 +136,6 @@ EVO_DEV void stage_tile(const T* src, int64_t sp, int64_t p0, int64_t pend, T* d
 // for rows r < 64 and columns c < 64 in range (0 elsewhere); the loads run
 // along whichever of the two strides is 1.
 constexpr int BP = 68;
-// Row pitch of the bias-gradient accumulator: a multiple of 64 keys plus 4, so
-// that each lane's aligned 4-key vector lands on its own banks.
-inline __host__ __device__ int64_t attn_acc_ld(int64_t Lk) { return (Lk + 63) / 64 * 64 + 4; }
 EVO_DEV void stage_bias(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
                         int64_t cend, float* sb, int tid) {
   const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
@@ -323,130 +320,147 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
 }
 
 // ============================================================== backward: dQ and bias partials
+// A workgroup owns 64 queries of one head for a group of up to GM batches
+// (bias shared across the batch axis).  Key tiles run in the outer loop so
+// that the bias tile is staged once and the bias gradient of the tile, summed
+// over the group's batches in registers, is written once as this group's
+// partial; the dQ accumulators of the group's batches stay in registers.
+template <int D> struct DqGroup { static constexpr int GM = D <= 16 ? 8 : 4; };
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                           float scale) {
   using F = DF<T, D>;
+  constexpr int GM = DqGroup<D>::GM;
   __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sV[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) float sB[64 * BP];
   __shared__ float sMk[KB];
-  extern __shared__ float sacc[];  // [64][acc_ld] bias-gradient accumulator
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int h = blockIdx.y;
   const int64_t grp = blockIdx.z;
   const int64_t b0 = grp * gr.group;
   const int64_t b1 = b0 + gr.group < a.nbatch ? b0 + gr.group : a.nbatch;
-  const int64_t qloc = wave * 16 + lr;
-  const int64_t qi = (int64_t)blockIdx.x * 64 + qloc;
+  const int qloc = wave * 16 + lr;
+  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  const int64_t qi = q0 + qloc;
   const bool qok = qi < a.Lq;
-  const int64_t acc_ld = attn_acc_ld(a.Lk);
   const bool dbias = gr.dbias_part != nullptr;
+  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
+  float* dbp = dbias ? gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk : nullptr;
 
   zero_pad_rows<T, D>(sKt, tid);
-  if (dbias)
-    for (int64_t e = tid; e < 64 * acc_ld; e += 256) sacc[e] = 0.f;
-
-  for (int64_t b = b0; b < b1; ++b) {
-    const T* Q = (const T*)a.q + b * a.sb + h * D;
-    const T* K = (const T*)a.k + b * a.sb + h * D;
-    const T* V = (const T*)a.v + b * a.sb + h * D;
-    const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
-    typename F::Frag qf[F::NKS], of[F::NKS];
-    load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
-    load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
-    float mrow = 0.f, irow = 0.f, drow = 0.f;
-    if (qok) {
-      const int64_t si = (b * a.stb + qi * a.stq) * a.H + h;
-      mrow = a.st_max[si];
-      irow = a.st_inv[si];
-      drow = gr.Dsum[si];
-    }
-    const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
-    const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
-    const int64_t q0 = (int64_t)blockIdx.x * 64;
-    f32x4 dq[F::NDT];
+  f32x4 dq[GM][F::NDT];
 #pragma unroll
-    for (int dt = 0; dt < F::NDT; ++dt) dq[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int bi = 0; bi < GM; ++bi)
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) dq[bi][dt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
+  for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
+    f32x4 dbacc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dbacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int bi = 0; bi < GM; ++bi) {
+      const int64_t b = b0 + bi;
+      if (b >= b1) break;
+      const T* Q = (const T*)a.q + b * a.sb + h * D;
+      const T* K = (const T*)a.k + b * a.sb + h * D;
+      const T* V = (const T*)a.v + b * a.sb + h * D;
+      const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
+      const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
       __syncthreads();
       stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, sKt, tid);
       stage_tile<T, D>(V, a.sp, kb0, a.Lk, sV, nullptr, tid);
-      if (bias) stage_bias(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, sB, tid);
+      if (bi == 0 && bias) stage_bias(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, sB, tid);
       if (tid < KB) sMk[tid] = (mask && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
       __syncthreads();
+      typename F::Frag qf[F::NKS], of[F::NKS];
+      load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
+      load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
+      float mrow = 0.f, irow = 0.f, drow = 0.f;
+      if (qok) {
+        const int64_t si = (b * a.stb + qi * a.stq) * a.H + h;
+        mrow = a.st_max[si];
+        irow = a.st_inv[si];
+        drow = gr.Dsum[si];
+      }
       f32x4 ds[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         typename F::Frag kf[F::NKS], vf[F::NKS];
         load_dfrag<T, D>(sK + (16 * t + lr) * F::DP, lg, true, kf);
         load_dfrag<T, D>(sV + (16 * t + lr) * F::DP, lg, true, vf);
-        const f32x4 s = mfma_d<T, D>(kf, qf);
+        const f32x4 sv = mfma_d<T, D>(kf, qf);
         const f32x4 dp = mfma_d<T, D>(vf, of);
         const f32x4 bv = bias ? *(const f32x4*)(sB + qloc * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int64_t key = kb0 + 16 * t + 4 * lg + i;
+          const int kl = 16 * t + 4 * lg + i;
           float r = 0.f;
-          if (qok && key < a.Lk) {
-            float x = s[i] * scale_log2;
+          if (qok && kb0 + kl < a.Lk) {
+            float x = sv[i] * scale_log2;
             if (bias) x += bv[i];
-            const bool masked = sMk[16 * t + 4 * lg + i] == 0.f;
-            if (!masked) {
+            if (sMk[kl] != 0.f) {
               const float p = exp2f(x - mrow) * irow;
               r = p * (dp[i] - drow);
             }
           }
           ds[t][i] = r;
         }
-        // each lane owns these four accumulator entries: plain vector add
-        if (dbias && qok) {
-          f32x4* acc4 = (f32x4*)(sacc + qloc * acc_ld + kb0 + 16 * t + 4 * lg);
-          *acc4 = *acc4 + ds[t];
-        }
+        dbacc[t] = dbacc[t] + ds[t];
       }
 #pragma unroll
       for (int dt = 0; dt < F::NDT; ++dt) {
         const int dr = 16 * dt + lr;
-        dq[dt] = contract64<T, D>(sKt + dr * F::TP, true, ds, lg, dq[dt]);
+        dq[bi][dt] = contract64<T, D>(sKt + dr * F::TP, true, ds, lg, dq[bi][dt]);
       }
     }
-    if (qok) {
-      T* DQ = (T*)gr.dq + b * gr.dsb + qi * gr.dsp + h * D;
+    // this group's bias-gradient partial for the tile, laid out like the bias
+    if (dbias && qok) {
 #pragma unroll
-      for (int dt = 0; dt < F::NDT; ++dt) {
-        const int d0 = 16 * dt + 4 * lg;
-        if (d0 < D) store4<T>(DQ + d0, dq[dt] * scale);
+      for (int t = 0; t < 4; ++t) {
+        const int64_t key = kb0 + 16 * t + 4 * lg;
+        const int64_t off = qi * a.bq + key * a.bk;
+        if (a.bk == 1 && key + 3 < a.Lk && (off & 3) == 0) {
+          *(f32x4*)(dbp + off) = dbacc[t];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (key + i < a.Lk) dbp[off + i * a.bk] = dbacc[t][i];
+        }
       }
     }
   }
-  if (dbias) {
-    __syncthreads();
-    // partial slice laid out like the bias itself: [group][H][.. q*bq + key*bk ..]
-    float* out = gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk;
-    const int64_t q0 = (int64_t)blockIdx.x * 64;
-    const int nq = a.Lq - q0 < 64 ? (int)(a.Lq - q0) : 64;
-    if (a.bk == 1) {          // rows of keys contiguous
-      for (int ql = 0; ql < nq; ++ql)
-        for (int64_t key = tid; key < a.Lk; key += 256) out[(q0 + ql) * a.bq + key] = sacc[ql * acc_ld + key];
-    } else {                  // queries contiguous
-      for (int64_t kbase = 0; kbase < a.Lk; kbase += 4) {
-        const int ql = tid & 63;
-        const int64_t key = kbase + (tid >> 6);
-        if (ql < nq && key < a.Lk) out[(q0 + ql) * a.bq + key * a.bk] = sacc[ql * acc_ld + key];
-      }
+  if (!qok) return;
+#pragma unroll
+  for (int bi = 0; bi < GM; ++bi) {
+    const int64_t b = b0 + bi;
+    if (b >= b1) break;
+    T* DQ = (T*)gr.dq + b * gr.dsb + qi * gr.dsp + h * D;
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) {
+      const int d0 = 16 * dt + 4 * lg;
+      if (d0 < D) store4<T>(DQ + d0, dq[bi][dt] * scale);
     }
   }
 }
 
 // ============================================================== backward: dK, dV
+// Roles of queries and keys swapped: a workgroup owns 64 keys of one head for
+// a group of up to GM batches; query tiles run in the outer loop so that the
+// bias tile (keys x queries) is staged once for the group.  GM = 1: measured
+// on gfx950, the registers of more batches cost more occupancy than the shared
+// bias tile saves.
+template <int D> struct DkvGroup { static constexpr int GM = 1; };
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
-                                                            float scale) {
+                                                            float scale, int32_t group) {
   using F = DF<T, D>;
+  constexpr int GM = DkvGroup<D>::GM;
   __shared__ __attribute__((aligned(16))) T sQ[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sO[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sQt[F::DR * F::TP];
@@ -455,85 +469,96 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
   __shared__ float sM[KB], sI[KB], sD[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t b = blockIdx.z;
   const int h = blockIdx.y;
-  const int64_t key = (int64_t)blockIdx.x * 64 + wave * 16 + lr;
-  const bool kok = key < a.Lk;
-  const bool kmasked = kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
-
-  const T* Q = (const T*)a.q + b * a.sb + h * D;
-  const T* K = (const T*)a.k + b * a.sb + h * D;
-  const T* V = (const T*)a.v + b * a.sb + h * D;
-  const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
-  typename F::Frag kf[F::NKS], vf[F::NKS];
-  load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
-  load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
-  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int64_t b0 = (int64_t)blockIdx.z * group;
+  const int64_t b1 = b0 + group < a.nbatch ? b0 + group : a.nbatch;
   const int kl = wave * 16 + lr;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int64_t key = k0 + kl;
+  const bool kok = key < a.Lk;
+  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
 
   zero_pad_rows<T, D>(sQt, tid);
   zero_pad_rows<T, D>(sOt, tid);
-  f32x4 dk[F::NDT], dv[F::NDT];
+  f32x4 dk[GM][F::NDT], dv[GM][F::NDT];
 #pragma unroll
-  for (int dt = 0; dt < F::NDT; ++dt) { dk[dt] = f32x4{0.f, 0.f, 0.f, 0.f}; dv[dt] = dk[dt]; }
+  for (int bi = 0; bi < GM; ++bi)
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) { dk[bi][dt] = f32x4{0.f, 0.f, 0.f, 0.f}; dv[bi][dt] = dk[bi][dt]; }
 
   for (int64_t qb0 = 0; qb0 < a.Lq; qb0 += KB) {
-    __syncthreads();
-    stage_tile<T, D>(Q, a.sp, qb0, a.Lq, sQ, sQt, tid);
-    stage_tile<T, D>(DO, a.osp, qb0, a.Lq, sO, sOt, tid);
-    if (bias) stage_bias(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, sB, tid);
-    if (tid < KB) {
-      const int64_t q = qb0 + tid;
-      float mv = 0.f, iv = 0.f, dvv = 0.f;
-      if (q < a.Lq) {
-        const int64_t si = (b * a.stb + q * a.stq) * a.H + h;
-        mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
-      }
-      sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv;
-    }
-    __syncthreads();
-    f32x4 P[4], DS[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      typename F::Frag qf[F::NKS], of[F::NKS];
-      load_dfrag<T, D>(sQ + (16 * t + lr) * F::DP, lg, true, qf);
-      load_dfrag<T, D>(sO + (16 * t + lr) * F::DP, lg, true, of);
-      const f32x4 s = mfma_d<T, D>(qf, kf);
-      const f32x4 dp = mfma_d<T, D>(of, vf);
-      const f32x4 bv = bias ? *(const f32x4*)(sB + kl * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ql = 16 * t + 4 * lg + i;
-        const int64_t q = qb0 + ql;
-        float p = 0.f, r = 0.f;
-        if (kok && q < a.Lq) {
-          float x = s[i] * scale_log2;
-          if (bias) x += bv[i];
-          if (kmasked) x = kMaskLogit;
-          p = exp2f(x - sM[ql]) * sI[ql];
-          if (!kmasked) r = p * (dp[i] - sD[ql]);
+    for (int bi = 0; bi < GM; ++bi) {
+      const int64_t b = b0 + bi;
+      if (b >= b1) break;
+      const T* Q = (const T*)a.q + b * a.sb + h * D;
+      const T* K = (const T*)a.k + b * a.sb + h * D;
+      const T* V = (const T*)a.v + b * a.sb + h * D;
+      const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
+      const bool kmasked = kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
+      __syncthreads();
+      stage_tile<T, D>(Q, a.sp, qb0, a.Lq, sQ, sQt, tid);
+      stage_tile<T, D>(DO, a.osp, qb0, a.Lq, sO, sOt, tid);
+      if (bi == 0 && bias) stage_bias(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, sB, tid);
+      if (tid < KB) {
+        const int64_t q = qb0 + tid;
+        float mv = 0.f, iv = 0.f, dvv = 0.f;
+        if (q < a.Lq) {
+          const int64_t si = (b * a.stb + q * a.stq) * a.H + h;
+          mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
         }
-        P[t][i] = p;
-        DS[t][i] = r;
+        sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv;
       }
-    }
+      __syncthreads();
+      typename F::Frag kf[F::NKS], vf[F::NKS];
+      load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
+      load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
+      f32x4 P[4], DS[4];
 #pragma unroll
-    for (int dt = 0; dt < F::NDT; ++dt) {
-      const int dr = 16 * dt + lr;
-      dv[dt] = contract64<T, D>(sOt + dr * F::TP, true, P, lg, dv[dt]);
-      dk[dt] = contract64<T, D>(sQt + dr * F::TP, true, DS, lg, dk[dt]);
+      for (int t = 0; t < 4; ++t) {
+        typename F::Frag qf[F::NKS], of[F::NKS];
+        load_dfrag<T, D>(sQ + (16 * t + lr) * F::DP, lg, true, qf);
+        load_dfrag<T, D>(sO + (16 * t + lr) * F::DP, lg, true, of);
+        const f32x4 sv = mfma_d<T, D>(qf, kf);
+        const f32x4 dp = mfma_d<T, D>(of, vf);
+        const f32x4 bv = bias ? *(const f32x4*)(sB + kl * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int ql = 16 * t + 4 * lg + i;
+          float p = 0.f, r = 0.f;
+          if (kok && qb0 + ql < a.Lq) {
+            float x = sv[i] * scale_log2;
+            if (bias) x += bv[i];
+            if (kmasked) x = kMaskLogit;
+            p = exp2f(x - sM[ql]) * sI[ql];
+            if (!kmasked) r = p * (dp[i] - sD[ql]);
+          }
+          P[t][i] = p;
+          DS[t][i] = r;
+        }
+      }
+#pragma unroll
+      for (int dt = 0; dt < F::NDT; ++dt) {
+        const int dr = 16 * dt + lr;
+        dv[bi][dt] = contract64<T, D>(sOt + dr * F::TP, true, P, lg, dv[bi][dt]);
+        dk[bi][dt] = contract64<T, D>(sQt + dr * F::TP, true, DS, lg, dk[bi][dt]);
+      }
     }
   }
   if (!kok) return;
-  T* DK = (T*)gr.dk + b * gr.dsb + key * gr.dsp + h * D;
-  T* DV = (T*)gr.dv + b * gr.dsb + key * gr.dsp + h * D;
 #pragma unroll
-  for (int dt = 0; dt < F::NDT; ++dt) {
-    const int d0 = 16 * dt + 4 * lg;
-    if (d0 < D) {
-      store4<T>(DK + d0, dk[dt] * scale);
-      store4<T>(DV + d0, dv[dt]);
+  for (int bi = 0; bi < GM; ++bi) {
+    const int64_t b = b0 + bi;
+    if (b >= b1) break;
+    T* DK = (T*)gr.dk + b * gr.dsb + key * gr.dsp + h * D;
+    T* DV = (T*)gr.dv + b * gr.dsb + key * gr.dsp + h * D;
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) {
+      const int d0 = 16 * dt + 4 * lg;
+      if (d0 < D) {
+        store4<T>(DK + d0, dk[bi][dt] * scale);
+        store4<T>(DV + d0, dv[bi][dt]);
+      }
     }
   }
 }
@@ -583,11 +608,14 @@ evo_status_t attn_fwd(const Ctx& c, const AttnCore& a) {
 }
 
 int64_t attn_bwd_groups(const AttnCore& a) {
+  // about 1024 workgroups, and at most the batches one workgroup keeps in registers
   const int64_t qblocks = (a.Lq + 63) / 64;
   int64_t target = (1024 + qblocks * a.H - 1) / (qblocks * a.H);
   if (target < 1) target = 1;
   if (target > a.nbatch) target = a.nbatch;
-  const int64_t group = (a.nbatch + target - 1) / target;
+  int64_t group = (a.nbatch + target - 1) / target;
+  const int64_t gmax = a.D <= 16 ? DqGroup<16>::GM : DqGroup<64>::GM;
+  if (group > gmax) group = gmax;
   return (a.nbatch + group - 1) / group;
 }
 
@@ -597,14 +625,7 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   const float sc = 1.0f / sqrtf((float)D);
   const int64_t ngroups = attn_bwd_groups(a);
   g.group = (a.nbatch + ngroups - 1) / ngroups;
-  size_t lds = 0;
-  if (g.dbias_part) {
-    lds = (size_t)64 * attn_acc_ld(a.Lk) * sizeof(float);
-    if (lds > 120 * 1024) {
-      set_error("attention backward: %lld keys exceed the bias-gradient LDS tile", (long long)a.Lk);
-      return EVO_ESHAPE;
-    }
-  }
+  const size_t lds = 0;
   static const std::string n1 = kname<T, D>("attn_bwd_dq_kernel");
   static const std::string n2 = kname<T, D>("attn_bwd_dkdv_kernel");
   const double bh = (double)a.nbatch * a.H, ll = (double)a.Lq * a.Lk;
@@ -617,8 +638,12 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   dim3 g1((unsigned)((a.Lq + 63) / 64), (unsigned)a.H, (unsigned)ngroups);
   EVO_LAUNCH(n1.c_str(), f1, b1, (attn_bwd_dq_kernel<T, D>), g1, dim3(256), lds, c.stream, a, g, sl2, sc);
   EVO_TRY(check_launch("attn_bwd_dq"));
-  dim3 g2((unsigned)((a.Lk + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
-  EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc);
+  // batches per dK/dV workgroup: the bias tile is shared across them (one batch when there is no bias)
+  int32_t kgroup = a.bias ? DkvGroup<D>::GM : 1;
+  const int64_t kblocks = (a.Lk + 63) / 64;
+  while (kgroup > 1 && kblocks * a.H * ((a.nbatch + kgroup - 1) / kgroup) < 512) kgroup /= 2;
+  dim3 g2((unsigned)kblocks, (unsigned)a.H, (unsigned)((a.nbatch + kgroup - 1) / kgroup));
+  EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc, kgroup);
   return check_launch("attn_bwd_dkdv");
 }
 
