@@ -2,6 +2,7 @@
 // v_mfma_f32_16x16x4_f32, FP32 accumulation, 256 threads (4 wave64s) per
 // workgroup, double-buffered LDS tiles with a register prefetch of the next
 // k-tile, fused elementwise epilogue.
+#include <algorithm>
 #include <string>
 
 #include "gemm.h"
@@ -491,7 +492,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int32_t ntn, int3
 }
 
 // ============================================================== plain-stride kernel
-// The common case: every operand and the output addressed with one row stride,
+// The common case: operands whose k-tile advance is a constant step (plain k,
+// or two-level k whose low block divides the tile), rows at fixed offsets,
 // 4-aligned outputs.  Loads and stores go through buffer resources with 32-bit
 // offsets (the k-tile step is a scalar offset), rows beyond the problem are
 // clamped to the last row (their products only feed discarded outputs),
@@ -503,7 +505,6 @@ constexpr int kBufFlags = 0x00020000;   // raw 32-bit buffer, gfx9 family
 constexpr uint32_t kOOB = 0x80000000u;  // an offset beyond every extent
 
 struct PlainInfo {
-  int32_t lda, ldb;            // row stride of A / B (elements)
   uint32_t ext_a, ext_b;       // bytes of one A / B slice
   int32_t ldo;                 // output row stride (elements)
   uint32_t ext_o;              // bytes of one output slice
@@ -537,10 +538,16 @@ struct PlainLoader {
   uint32_t step;     // bytes per k-tile
   uint32_t krow;     // bytes between consecutive k (row-contiguous)
 
-  EVO_DEV void init(const void* base, uint32_t ext, int ld, int rows, int row0, int kbeg, int tid) {
+  EVO_DEV static int a32(int r, int lo, int hi, int shift) {
+    return shift < 0 ? r * lo : (r >> shift) * hi + (r & ((1 << shift) - 1)) * lo;
+  }
+  EVO_DEV void init(const void* base, uint32_t ext, const GemmOperand& op, int rows, int row0, int kbeg,
+                    int tid) {
     rs = rsrc(base, ext);
+    const int rlo = (int)op.r_lo, rhi = (int)op.r_hi, klo = (int)op.k_lo, khi = (int)op.k_hi;
+    // per k-tile step: BK along plain k, BK >> k_shift low blocks along two-level k
+    step = (uint32_t)((op.k_shift < 0 ? BK * klo : (BK >> op.k_shift) * khi) * (int)sizeof(T));
     if constexpr (KC) {
-      step = BK * sizeof(T);
 #pragma unroll
       for (int p = 0; p < PASSES; ++p) {
         const int v = tid + 256 * p;
@@ -548,17 +555,20 @@ struct PlainLoader {
         kk_[p] = g * VEC;
         int gr = row0 + r;
         gr = gr < rows ? gr : rows - 1;
-        voff[p] = (v < NV) ? (uint32_t)((gr * ld + kbeg + kk_[p]) * (int)sizeof(T)) : kOOB;
+        voff[p] = (v < NV) ? (uint32_t)((a32(gr, rlo, rhi, op.r_shift) + a32(kbeg + kk_[p], klo, khi, op.k_shift)) *
+                                        (int)sizeof(T))
+                           : kOOB;
         lds_[p] = r * LDK + VEC * (g ^ swz(r));
       }
     } else {
-      step = (uint32_t)(BK * ld * (int)sizeof(T));
-      krow = (uint32_t)(ld * (int)sizeof(T));
+      krow = (uint32_t)(klo * (int)sizeof(T));
       const int rb = tid % RB, kb = tid / RB;
       int r0 = row0 + rb * VEC;
       r0 = r0 < rows ? r0 : rows - VEC;
       kk_[0] = kb * KB;
-      voff[0] = tid < NBLK ? (uint32_t)(((kbeg + kk_[0]) * ld + r0) * (int)sizeof(T)) : kOOB;
+      voff[0] = tid < NBLK ? (uint32_t)((a32(kbeg + kk_[0], klo, khi, op.k_shift) + a32(r0, rlo, rhi, op.r_shift)) *
+                                        (int)sizeof(T))
+                           : kOOB;
       lds_[0] = rb * VEC;
     }
   }
@@ -651,8 +661,8 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
   }
   PlainLoader<T, BM, KCA> la;
   PlainLoader<T, BN, KCB> lb;
-  la.init(Ap, pi.ext_a, pi.lda, M, m0, kbeg, tid);
-  lb.init(Bp, pi.ext_b, pi.ldb, N, n0, kbeg, tid);
+  la.init(Ap, pi.ext_a, g.A, M, m0, kbeg, tid);
+  lb.init(Bp, pi.ext_b, g.B, N, n0, kbeg, tid);
 
   f32x4 acc[TN][TM];
 #pragma unroll
@@ -769,10 +779,12 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
   if (e.relu_ref) rrl = rsrc((const char*)e.relu_ref + zo * sizeof(T), pi.ext_r);
   if (e.gate) rg = rsrc((const char*)e.gate + zo * gsz, pi.ext_g);
   const float alpha = e.alpha;
+  const int mlo = (int)e.m_lo, mhi = (int)e.m_hi, nhi = (int)e.n_hi;
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int n = n0 + wn * WN + j * 16 + lg * 4;
     const bool colok = n < N;
+    const int no = PlainLoader<T, BM, KCA>::a32(n, 1, nhi, e.n_shift);
     f32x4 bj = f32x4{0.f, 0.f, 0.f, 0.f};
     if (e.bias && colok) bj = *(const f32x4*)(e.bias + n);
 #pragma unroll
@@ -788,15 +800,23 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
         for (int r = 0; r < 4; ++r)
           if (n + r >= e.act_n0) v[r] = sigmoidf_(v[r]);
       }
-      const uint32_t eo = (uint32_t)(m * pi.ldr + n);   // aux element offset
+      const int mo = PlainLoader<T, BM, KCA>::a32(m, mlo, mhi, e.m_shift);
+      if (e.scale) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          v[r] *= ok ? e.scale[(m >> e.sm_shift) * e.sm_ld + ((n + r) >> e.sn_shift) * e.sn_ld] : 0.f;
+      }
+      const uint32_t eo = (uint32_t)(e.r_m < 0 ? mo + no : m * pi.ldr + n);   // aux element offset
       if (e.relu_ref) {
         const f32x4 q = load4<T>(rrl, ok ? eo * (uint32_t)sizeof(T) : kOOB, false);
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = q[r] > 0.0f ? v[r] : 0.0f;
       }
-      if (e.gate) v *= load4<T>(rg, ok ? (uint32_t)(m * pi.ldg + n) * (uint32_t)gsz : kOOB, e.gate_f32 != 0);
+      if (e.gate)
+        v *= load4<T>(rg, ok ? (uint32_t)(e.g_m < 0 ? mo + no : m * pi.ldg + n) * (uint32_t)gsz : kOOB,
+                      e.gate_f32 != 0);
       if (e.resid) v += load4<T>(rr, ok ? eo * (uint32_t)rsz : kOOB, e.resid_f32 != 0);
-      const uint32_t oo = ok ? (uint32_t)(m * pi.ldo + n) * (uint32_t)osz : kOOB;
+      const uint32_t oo = ok ? (uint32_t)(mo + no) * (uint32_t)osz : kOOB;
       if (of32) {
         if (e.accumulate) v += load4<T>(ro, oo, true);
         const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
@@ -837,49 +857,63 @@ static bool operand_ok(const GemmOperand& o, int64_t rows, int vec, const char* 
   return true;
 }
 
-// Plain-stride eligibility (see gemm_plain_kernel) and its strides / extents.
+// Largest offset addr2(x) over x < n (two-level addressing need not be monotonic).
+static int64_t max_off(int64_t n, int64_t lo, int64_t hi, int32_t shift) {
+  if (n <= 0) return 0;
+  if (shift < 0) return (n - 1) * lo;
+  const int64_t mask = (1LL << shift) - 1, top = (n - 1) >> shift;
+  int64_t m = top * hi + ((n - 1) & mask) * lo;
+  if (top > 0) m = std::max(m, (top - 1) * hi + mask * lo);
+  return m;
+}
+
+// Plain-kernel eligibility (see gemm_plain_kernel) and the extents of its buffers.
 template <typename T>
 static bool plain_info(const GemmArgs& g, PlainInfo& pi) {
+  constexpr int BK = GemmTraits<T>::BK, VEC = GemmTraits<T>::VEC;
   const int64_t lim = (1LL << 31) - 4096;
-  const size_t sz = sizeof(T);
-  auto op = [&](const GemmOperand& o, int64_t rows, int32_t& ld, uint32_t& ext) {
-    if (o.r_shift >= 0 || o.k_shift >= 0) return false;
-    const int64_t l = o.k_contig ? o.r_lo : o.k_lo;
-    const int64_t e = o.k_contig ? ((rows - 1) * l + g.K) * (int64_t)sz : ((g.K - 1) * l + rows) * (int64_t)sz;
-    if (l <= 0 || l > lim || e > lim || e <= 0) return false;
-    ld = (int32_t)l;
+  const int64_t sz = sizeof(T);
+  auto op = [&](const GemmOperand& o, int64_t rows, uint32_t& ext) {
+    // k: plain, or two-level with a low block that divides the k-tile and holds a load vector
+    if (o.k_shift >= 0 && (o.k_shift > 30 || (1LL << o.k_shift) < VEC || BK % (1LL << o.k_shift))) return false;
+    if (o.r_shift > 30) return false;
+    const int64_t e = (max_off(rows, o.r_lo, o.r_hi, o.r_shift) + max_off(g.K, o.k_lo, o.k_hi, o.k_shift) + 1) * sz;
+    if (e <= 0 || e > lim || o.r_lo > lim || o.r_hi > lim || o.k_lo > lim || o.k_hi > lim) return false;
     ext = (uint32_t)e;
     return true;
   };
-  if (g.K <= 0 || !op(g.A, g.M, pi.lda, pi.ext_a) || !op(g.B, g.N, pi.ldb, pi.ext_b)) return false;
+  if (g.K <= 0 || !op(g.A, g.M, pi.ext_a) || !op(g.B, g.N, pi.ext_b)) return false;
   const GemmEpilogue& e = g.epi;
-  const int64_t osz = e.out_f32 ? 4 : (int64_t)sz;
-  if (e.m_shift >= 0 || e.n_shift >= 0 || e.n_lo != 1 || e.scale || g.N % 4 || e.m_lo % 4 || e.m_lo <= 0) return false;
+  const int64_t osz = e.out_f32 ? 4 : sz;
+  if (e.n_lo != 1 || g.N % 4 || (e.n_shift >= 0 && (e.n_shift < 2 || e.n_hi % 4)) || e.m_lo % 4 ||
+      (e.m_shift >= 0 && e.m_hi % 4) || e.m_lo <= 0 || e.m_shift > 30 || e.n_shift > 30)
+    return false;
   if ((g.split_k > 1 || g.batch > 1) && e.batch % 4) return false;
   if (((uintptr_t)e.out) % (4 * osz) || (e.bias && ((uintptr_t)e.bias) % 16)) return false;
-  auto ext_of = [&](int64_t ld, int64_t esz, uint32_t& ext) {
-    const int64_t x = ((g.M - 1) * ld + g.N) * esz;
-    if (ld > lim || x > lim) return false;
+  const int64_t out_max = max_off(g.M, e.m_lo, e.m_hi, e.m_shift) + max_off(g.N, 1, e.n_hi, e.n_shift);
+  auto ext_of = [&](int64_t maxoff, int64_t esz, uint32_t& ext) {
+    const int64_t x = (maxoff + 1) * esz;
+    if (x > lim) return false;
     ext = (uint32_t)x;
     return true;
   };
+  if (!ext_of(out_max, osz, pi.ext_o) || e.m_lo > lim || e.m_hi > lim || e.n_hi > lim) return false;
   pi.ldo = (int32_t)e.m_lo;
-  if (!ext_of(e.m_lo, osz, pi.ext_o)) return false;
   auto aux = [&](const void* p, int64_t sm, int64_t sn, int64_t esz, int32_t& ld, uint32_t& ext) {
     ld = pi.ldo;
     ext = pi.ext_o;
     if (!p) return true;
     if (((uintptr_t)p) % (4 * esz)) return false;
-    if (sm < 0) return ext_of(e.m_lo, esz, ext);
-    if (sn != 1 || sm % 4) return false;
+    if (sm < 0) return ext_of(out_max, esz, ext);
+    if (sn != 1 || sm % 4 || sm > lim) return false;
     ld = (int32_t)sm;
-    return ext_of(sm, esz, ext);
+    return ext_of((g.M - 1) * sm + g.N - 1, esz, ext);
   };
   const void* rp = e.resid ? e.resid : e.relu_ref;
   if (e.resid && e.relu_ref && e.resid_f32) return false;   // one stride/extent serves both: same element size
-  const int64_t rsz = e.resid ? (e.resid_f32 ? 4 : (int64_t)sz) : (int64_t)sz;
+  const int64_t rsz = e.resid ? (e.resid_f32 ? 4 : sz) : sz;
   if (!aux(rp, e.r_m, e.r_n, rsz, pi.ldr, pi.ext_r)) return false;
-  if (!aux(e.gate, e.g_m, e.g_n, e.gate_f32 ? 4 : (int64_t)sz, pi.ldg, pi.ext_g)) return false;
+  if (!aux(e.gate, e.g_m, e.g_n, e.gate_f32 ? 4 : sz, pi.ldg, pi.ext_g)) return false;
   return true;
 }
 

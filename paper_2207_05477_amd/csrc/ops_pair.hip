@@ -217,30 +217,32 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
       g.epi.scale = S.scale; g.epi.sm_shift = 0; g.epi.sm_ld = 1; g.epi.sn_shift = 31; g.epi.sn_ld = 0;
       EVO_TRY(gemm<T>(c, g));
     }
-    {  // da[s][i][p] = mask_si * sum_{j,q} dO[i][j][p][q] b[s][j][q]
+    // da and db as [s][(i, p)] products (rows s, columns (i, p) contiguous within
+    // blocks of ch), so that the output moves as row vectors.
+    {  // da[s][i][p] = mask_si * sum_{j,q} b[s][j][q] dO[i][j][p][q]
       GemmArgs g;
-      g.M = R * ch; g.N = S_; g.K = R * ch;
-      g.A.ptr = dO; g.A.r_lo = ch; g.A.r_hi = R * ch2; g.A.r_shift = sh;
-      g.A.k_lo = 1; g.A.k_hi = ch2; g.A.k_shift = sh; g.A.k_contig = 1;
-      g.B.ptr = S.ab + ch; g.B.r_lo = R * 2 * ch;
-      g.B.k_lo = 1; g.B.k_hi = 2 * ch; g.B.k_shift = sh; g.B.k_contig = 1;
+      g.M = S_; g.N = R * ch; g.K = R * ch;
+      g.A.ptr = S.ab + ch; g.A.r_lo = R * 2 * ch;
+      g.A.k_lo = 1; g.A.k_hi = 2 * ch; g.A.k_shift = sh; g.A.k_contig = 1;
+      g.B.ptr = dO; g.B.r_lo = ch; g.B.r_hi = R * ch2; g.B.r_shift = sh;
+      g.B.k_lo = 1; g.B.k_hi = ch2; g.B.k_shift = sh; g.B.k_contig = 1;
       g.epi.out = dab; g.epi.out_f32 = 0;
-      g.epi.m_lo = 1; g.epi.m_hi = 2 * ch; g.epi.m_shift = sh;
-      g.epi.n_lo = R * 2 * ch;
-      if (mask) { g.epi.scale = mask; g.epi.sm_shift = sh; g.epi.sm_ld = 1; g.epi.sn_shift = 0; g.epi.sn_ld = R; }
+      g.epi.m_lo = R * 2 * ch;
+      g.epi.n_lo = 1; g.epi.n_hi = 2 * ch; g.epi.n_shift = sh;
+      if (mask) { g.epi.scale = mask; g.epi.sm_shift = 0; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1; }
       EVO_TRY(gemm<T>(c, g));
     }
-    {  // db[s][j][q] = mask_sj * sum_{i,p} dO[i][j][p][q] a[s][i][p]
+    {  // db[s][j][q] = mask_sj * sum_{i,p} a[s][i][p] dO[i][j][p][q]
       GemmArgs g;
-      g.M = R * ch; g.N = S_; g.K = R * ch;
-      g.A.ptr = dO; g.A.r_lo = 1; g.A.r_hi = ch2; g.A.r_shift = sh;
-      g.A.k_lo = ch; g.A.k_hi = R * ch2; g.A.k_shift = sh; g.A.k_contig = 0;
-      g.B.ptr = S.ab; g.B.r_lo = R * 2 * ch;
-      g.B.k_lo = 1; g.B.k_hi = 2 * ch; g.B.k_shift = sh; g.B.k_contig = 1;
+      g.M = S_; g.N = R * ch; g.K = R * ch;
+      g.A.ptr = S.ab; g.A.r_lo = R * 2 * ch;
+      g.A.k_lo = 1; g.A.k_hi = 2 * ch; g.A.k_shift = sh; g.A.k_contig = 1;
+      g.B.ptr = dO; g.B.r_lo = 1; g.B.r_hi = ch2; g.B.r_shift = sh;
+      g.B.k_lo = ch; g.B.k_hi = R * ch2; g.B.k_shift = sh; g.B.k_contig = 0;
       g.epi.out = dab + ch; g.epi.out_f32 = 0;
-      g.epi.m_lo = 1; g.epi.m_hi = 2 * ch; g.epi.m_shift = sh;
-      g.epi.n_lo = R * 2 * ch;
-      if (mask) { g.epi.scale = mask; g.epi.sm_shift = sh; g.epi.sm_ld = 1; g.epi.sn_shift = 0; g.epi.sn_ld = R; }
+      g.epi.m_lo = R * 2 * ch;
+      g.epi.n_lo = 1; g.epi.n_hi = 2 * ch; g.epi.n_shift = sh;
+      if (mask) { g.epi.scale = mask; g.epi.sm_shift = 0; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1; }
       EVO_TRY(gemm<T>(c, g));
     }
   }
