@@ -27,10 +27,44 @@ template <> EVO_DEV bf16 from_f32<bf16>(float x) { return (bf16)x; }  // round t
 
 EVO_DEV float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
+// ---------------------------------------------------------------- 8-wide vector access
+// p must be 16-byte aligned (32-byte for float is not required: two 16-byte accesses).
+EVO_DEV void ld8(const float* p, float v[8]) {
+  const f32x4 a = *(const f32x4*)p, b = *(const f32x4*)(p + 4);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { v[i] = a[i]; v[4 + i] = b[i]; }
+}
+EVO_DEV void ld8(const bf16* p, float v[8]) {
+  const bf16x8 a = *(const bf16x8*)p;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (float)a[i];
+}
+EVO_DEV void st8(float* p, const float v[8]) {
+  f32x4 a, b;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { a[i] = v[i]; b[i] = v[4 + i]; }
+  *(f32x4*)p = a;
+  *(f32x4*)(p + 4) = b;
+}
+EVO_DEV void st8(bf16* p, const float v[8]) {
+  bf16x8 a;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = (bf16)v[i];
+  *(bf16x8*)p = a;
+}
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 // ---------------------------------------------------------------- wave reductions (wave64)
 EVO_DEV float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of a
+// group gets the group's sum.
+template <int G> EVO_DEV float group_sum(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 EVO_DEV float wave_max(float v) {

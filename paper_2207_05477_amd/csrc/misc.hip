@@ -44,12 +44,101 @@ __global__ __launch_bounds__(256) void ln_fwd_kernel(const TI* __restrict__ x, i
   }
 }
 
+// Vectorised form (C % 8 == 0, C <= 1024, 16-byte aligned rows): LPR lanes
+// share a row, lane l owning the 8-channel chunks j*LPR + l (j < NC), so a wave
+// normalises 64 / LPR rows at once with 16-byte accesses.
+template <typename TI, typename T, int LPR, int NC>
+__global__ __launch_bounds__(256) void ln_fwd_vec_kernel(const TI* __restrict__ x, int64_t rows, int C,
+                                                         const float* __restrict__ g,
+                                                         const float* __restrict__ b, float eps,
+                                                         T* __restrict__ y, float* __restrict__ mean,
+                                                         float* __restrict__ rstd, int rshift, int64_t rhi) {
+  constexpr int RPB = 256 / LPR;
+  const int l = threadIdx.x & (LPR - 1);
+  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+  const bool ok = row < rows;
+  const TI* xr = x + (rshift < 0 ? row * C : (row >> rshift) * rhi + (row & ((1LL << rshift) - 1)) * C);
+  float v[NC][8];
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c0 = (j * LPR + l) * 8;
+    if (ok && c0 < C) ld8(xr + c0, v[j]);
+    else
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[j][i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[j][i];
+  }
+  const float mu = group_sum<LPR>(s) / (float)C;
+  float q = 0.f;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c0 = (j * LPR + l) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float d = c0 < C ? v[j][i] - mu : 0.f;
+      q += d * d;
+    }
+  }
+  const float rs = 1.0f / sqrtf(group_sum<LPR>(q) / (float)C + eps);
+  if (!ok) return;
+  T* yr = y + row * C;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c0 = (j * LPR + l) * 8;
+    if (c0 < C) {
+      float gg[8], bb[8], o[8];
+      ld8(g + c0, gg);
+      ld8(b + c0, bb);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) o[i] = (v[j][i] - mu) * rs * gg[i] + bb[i];
+      st8(yr + c0, o);
+    }
+  }
+  if (l == 0) {
+    if (mean) mean[row] = mu;
+    if (rstd) rstd[row] = rs;
+  }
+}
+
+// Lanes per row of the vectorised LayerNorm kernels: the smallest power of two
+// >= C / 8, at least 4 and at most 64.
+static int ln_lanes(int C) {
+  int l = 4;
+  while (l < 64 && l * 8 < C) l <<= 1;
+  return l;
+}
+
+template <typename TI, typename T, int LPR>
+static void ln_fwd_vec_launch(const Ctx& c, double bytes, const TI* x, int64_t rows, int C, int rshift,
+                              int64_t rhi, const float* g, const float* b, float eps, T* y, float* mean,
+                              float* rstd) {
+  constexpr int RPB = 256 / LPR;
+  dim3 grid((unsigned)((rows + RPB - 1) / RPB));
+  if (C <= 8 * LPR)
+    EVO_LAUNCH(EVO_KNAME("ln_fwd_vec_kernel", TI), 0.0, bytes, (ln_fwd_vec_kernel<TI, T, LPR, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+  else
+    EVO_LAUNCH(EVO_KNAME("ln_fwd_vec_kernel", TI), 0.0, bytes, (ln_fwd_vec_kernel<TI, T, LPR, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
+}
+
 template <typename TI, typename T>
 evo_status_t ln_fwd_rows(const Ctx& c, const TI* x, int64_t rows, int C, int rshift, int64_t rhi,
                          const float* g, const float* b, float eps, T* y, float* mean, float* rstd) {
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)((rows + 3) / 4));
   const double bytes = (double)rows * C * (sizeof(TI) + sizeof(T)) + rows * 8.0;
+  if (C % 8 == 0 && C <= 1024 && (rshift < 0 || rhi % 8 == 0) && aligned16(x) && aligned16(y) &&
+      aligned16(g) && aligned16(b)) {
+    switch (ln_lanes(C)) {
+      case 4: ln_fwd_vec_launch<TI, T, 4>(c, bytes, x, rows, C, rshift, rhi, g, b, eps, y, mean, rstd); break;
+      case 8: ln_fwd_vec_launch<TI, T, 8>(c, bytes, x, rows, C, rshift, rhi, g, b, eps, y, mean, rstd); break;
+      case 16: ln_fwd_vec_launch<TI, T, 16>(c, bytes, x, rows, C, rshift, rhi, g, b, eps, y, mean, rstd); break;
+      case 32: ln_fwd_vec_launch<TI, T, 32>(c, bytes, x, rows, C, rshift, rhi, g, b, eps, y, mean, rstd); break;
+      default: ln_fwd_vec_launch<TI, T, 64>(c, bytes, x, rows, C, rshift, rhi, g, b, eps, y, mean, rstd); break;
+    }
+    return check_launch("ln_fwd");
+  }
   if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
   else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 2>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
   else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_fwd_kernel", TI), 0.0, bytes, (ln_fwd_kernel<TI, T, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
@@ -256,6 +345,119 @@ __global__ __launch_bounds__(256) void ln_bwd_kernel(const T* __restrict__ x,
   }
 }
 
+// Vectorised backward (C % 8 == 0, C <= 1024, 16-byte aligned): the lane
+// layout of ln_fwd_vec_kernel, 64 rows per block as 64 / (4 * 64 / LPR)
+// iterations of 256 / LPR rows.  The gamma/beta partials are summed over the
+// row groups of a wave by xor shuffles, then over the 4 waves through LDS, in a
+// fixed order.
+template <typename T, int LPR, int NC>
+__global__ __launch_bounds__(256) void ln_bwd_vec_kernel(const T* __restrict__ x,
+                                                         const float* __restrict__ mean,
+                                                         const float* __restrict__ rstd,
+                                                         const float* __restrict__ g,
+                                                         const float* __restrict__ dy, int64_t rows,
+                                                         int C, const T* resid, int accumulate, T* dx,
+                                                         float* __restrict__ part) {
+  constexpr int RPI = 256 / LPR;  // rows per iteration of the block
+  static_assert(LNB_ROWS % RPI == 0, "row groups must tile the block's rows");
+  __shared__ float red[4][2][NC * LPR * 8];
+  const int l = threadIdx.x & (LPR - 1), wave = threadIdx.x >> 6;
+  float dg[NC][8], db[NC][8], gam[NC][8];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c0 = (j * LPR + l) * 8;
+    if (c0 < C) ld8(g + c0, gam[j]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      dg[j][i] = 0.f;
+      db[j][i] = 0.f;
+      if (c0 >= C) gam[j][i] = 0.f;
+    }
+  }
+  for (int it = 0; it < LNB_ROWS / RPI; ++it) {
+    const int64_t row = (int64_t)blockIdx.x * LNB_ROWS + it * RPI + threadIdx.x / LPR;
+    const bool ok = row < rows;
+    const float mu = ok ? mean[row] : 0.f, rs = ok ? rstd[row] : 0.f;
+    float xh[NC][8], d[NC][8];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c0 = (j * LPR + l) * 8;
+      if (ok && c0 < C) {
+        ld8(x + row * C + c0, xh[j]);
+        ld8(dy + row * C + c0, d[j]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) { xh[j][i] = mu; d[j][i] = 0.f; }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        xh[j][i] = (xh[j][i] - mu) * rs;
+        const float gd = d[j][i] * gam[j][i];
+        s1 += gd;
+        s2 += gd * xh[j][i];
+        dg[j][i] += d[j][i] * xh[j][i];
+        db[j][i] += d[j][i];
+      }
+    }
+    const float a = group_sum<LPR>(s1) / (float)C, bb = group_sum<LPR>(s2) / (float)C;
+    if (!ok) continue;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c0 = (j * LPR + l) * 8;
+      if (c0 >= C) continue;
+      float v[8], r[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = rs * (d[j][i] * gam[j][i] - a - xh[j][i] * bb);
+      if (resid) {
+        ld8(resid + row * C + c0, r);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] += r[i];
+      } else if (accumulate) {
+        ld8(dx + row * C + c0, r);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] += r[i];
+      }
+      st8(dx + row * C + c0, v);
+    }
+  }
+  // row groups of the wave -> lanes 0..LPR-1
+#pragma unroll
+  for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        dg[j][i] += __shfl_xor(dg[j][i], o, 64);
+        db[j][i] += __shfl_xor(db[j][i], o, 64);
+      }
+  if ((threadIdx.x & 63) < LPR)
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        red[wave][0][(j * LPR + l) * 8 + i] = dg[j][i];
+        red[wave][1][(j * LPR + l) * 8 + i] = db[j][i];
+      }
+  __syncthreads();
+  for (int cc = threadIdx.x; cc < C; cc += 256) {
+    const float sg = (red[0][0][cc] + red[1][0][cc]) + (red[2][0][cc] + red[3][0][cc]);
+    const float sb = (red[0][1][cc] + red[1][1][cc]) + (red[2][1][cc] + red[3][1][cc]);
+    part[(int64_t)blockIdx.x * 2 * C + cc] = sg;
+    part[(int64_t)blockIdx.x * 2 * C + C + cc] = sb;
+  }
+}
+
+template <typename T, int LPR>
+static void ln_bwd_vec_launch(const Ctx& c, double bytes, unsigned nblk, const T* x, const float* mean,
+                              const float* rstd, const float* g, const float* dy, int64_t rows, int C,
+                              const T* resid, int acc, T* dx, float* part) {
+  if (C <= 8 * LPR)
+    EVO_LAUNCH(EVO_KNAME("ln_bwd_vec_kernel", T), 0.0, bytes, (ln_bwd_vec_kernel<T, LPR, 1>), dim3(nblk), dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+  else
+    EVO_LAUNCH(EVO_KNAME("ln_bwd_vec_kernel", T), 0.0, bytes, (ln_bwd_vec_kernel<T, LPR, 2>), dim3(nblk), dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
+}
+
 template <typename T>
 evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
                     const float* dy, int64_t rows, int C, const T* resid, bool accumulate, T* dx,
@@ -264,6 +466,18 @@ evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rs
   if (c.dry || rows == 0) return EVO_OK;
   dim3 grid((unsigned)*nblk);
   const int acc = accumulate ? 1 : 0;
+  if (C % 8 == 0 && C <= 1024 && aligned16(x) && aligned16(g) && aligned16(dy) && aligned16(dx) &&
+      (!resid || aligned16(resid))) {
+    const double bytes = (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0;
+    switch (ln_lanes(C)) {
+      case 4: ln_bwd_vec_launch<T, 4>(c, bytes, grid.x, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part); break;
+      case 8: ln_bwd_vec_launch<T, 8>(c, bytes, grid.x, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part); break;
+      case 16: ln_bwd_vec_launch<T, 16>(c, bytes, grid.x, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part); break;
+      case 32: ln_bwd_vec_launch<T, 32>(c, bytes, grid.x, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part); break;
+      default: ln_bwd_vec_launch<T, 64>(c, bytes, grid.x, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part); break;
+    }
+    return check_launch("ln_bwd");
+  }
   if (C <= 64) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 1>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
   else if (C <= 128) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 2>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
   else if (C <= 256) EVO_LAUNCH(EVO_KNAME("ln_bwd_kernel", T), 0.0, (double)rows * C * (2 * sizeof(T) + 4.0 + ((resid || acc) ? sizeof(T) : 0)) + rows * 8.0, (ln_bwd_kernel<T, 4>), grid, dim3(256), 0, c.stream, x, mean, rstd, g, dy, rows, C, resid, acc, dx, part);
@@ -492,11 +706,57 @@ __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ x, in
     part[(int64_t)blockIdx.y * C + cc] = (red[0][tc] + red[1][tc]) + (red[2][tc] + red[3][tc]);
 }
 
+// Vectorised form (C % 8 == 0, ld % 8 == 0, 16-byte aligned x): TPR threads
+// cover 8 * TPR consecutive columns of a row, so the 256 threads stride over
+// the block's CS_ROWS rows 256 / TPR rows at a time; the row groups are summed
+// through LDS in a fixed order.
+template <typename T, int TPR>
+__global__ __launch_bounds__(256) void colsum_vec_kernel(const T* __restrict__ x, int64_t rows, int C,
+                                                         int64_t ld, float* __restrict__ part) {
+  constexpr int RG = 256 / TPR;
+  __shared__ float red[RG][TPR * 8 + 4];
+  const int tc = threadIdx.x & (TPR - 1), tr = threadIdx.x / TPR;
+  const int c0 = (blockIdx.x * TPR + tc) * 8;
+  const int64_t r0 = (int64_t)blockIdx.y * CS_ROWS;
+  const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
+  float s[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s[i] = 0.f;
+  if (c0 < C)
+    for (int64_t r = r0 + tr; r < r1; r += RG) {
+      float v[8];
+      ld8(x + r * ld + c0, v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[i] += v[i];
+    }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[tr][tc * 8 + i] = s[i];
+  __syncthreads();
+  for (int e = threadIdx.x; e < TPR * 8; e += 256) {
+    const int cc = blockIdx.x * TPR * 8 + e;
+    if (cc >= C) continue;
+    float t = 0.f;
+    for (int q = 0; q < RG; ++q) t += red[q][e];
+    part[(int64_t)blockIdx.y * C + cc] = t;
+  }
+}
+
 template <typename T>
 evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
                             int* nblk) {
   *nblk = (int)colsum_partials(rows);
   if (c.dry || rows == 0) return EVO_OK;
+  if (C % 8 == 0 && ld % 8 == 0 && aligned16(x)) {
+    const double bytes = (double)rows * C * sizeof(T);
+    const unsigned nb = (unsigned)*nblk;
+    if (C <= 64)
+      EVO_LAUNCH(EVO_KNAME("colsum_vec_kernel", T), 0.0, bytes, (colsum_vec_kernel<T, 8>), dim3((unsigned)((C + 63) / 64), nb), dim3(256), 0, c.stream, x, rows, C, ld, part);
+    else if (C <= 128)
+      EVO_LAUNCH(EVO_KNAME("colsum_vec_kernel", T), 0.0, bytes, (colsum_vec_kernel<T, 16>), dim3(1, nb), dim3(256), 0, c.stream, x, rows, C, ld, part);
+    else
+      EVO_LAUNCH(EVO_KNAME("colsum_vec_kernel", T), 0.0, bytes, (colsum_vec_kernel<T, 32>), dim3((unsigned)((C + 255) / 256), nb), dim3(256), 0, c.stream, x, rows, C, ld, part);
+    return check_launch("colsum");
+  }
   EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>),
              dim3((unsigned)((C + 63) / 64), (unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
   return check_launch("colsum");
@@ -570,8 +830,23 @@ __global__ __launch_bounds__(256) void convert_kernel(const TI* __restrict__ s, 
 }
 
 template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void convert_vec_kernel(const TI* __restrict__ s, TO* __restrict__ d, int64_t n8) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n8) return;
+  float v[8];
+  ld8(s + e * 8, v);
+  st8(d + e * 8, v);
+}
+
+template <typename TI, typename TO>
 evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n) {
   if (c.dry || n == 0) return EVO_OK;
+  if (n % 8 == 0 && aligned16(src) && aligned16(dst)) {
+    const int64_t n8 = n / 8;
+    EVO_LAUNCH(EVO_KNAME("convert_vec_kernel", TO), 0.0, (double)n * (sizeof(TI) + sizeof(TO)),
+               (convert_vec_kernel<TI, TO>), dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, c.stream, src, dst, n8);
+    return check_launch("convert");
+  }
   EVO_LAUNCH(EVO_KNAME("convert_kernel", TO), 0.0, (double)n * (sizeof(TI) + sizeof(TO)),
              (convert_kernel<TI, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
   return check_launch("convert");
