@@ -179,7 +179,8 @@ static evo_status_t run_checked(void* stream, void* ws, size_t ws_bytes, F fn) {
   Ctx c;
   c.stream = (hipStream_t)stream;
   Arena a = live_arena(ws, ws_bytes);
-  return fn(c, a);
+  // parameter-gradient reductions of a backward entry point: one launch at its end
+  return with_batched_reductions(c, [&](const Ctx& cq) { return fn(cq, a); });
 }
 
 }  // namespace evo

@@ -153,13 +153,14 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   };
   Scratch sc;
   sc.base = ws;
-#define EVO_STEPS(i, tag, call)   \
-  do {                            \
-    ProfTag pt_(tag);             \
-    Arena a = sc.fresh();         \
-    Arena s = S(i);               \
-    EVO_TRY(call);                \
-    sc.done(a);                   \
+  // each sub-op's parameter-gradient reductions run as one launch at its end
+#define EVO_STEPS(i, tag, call)                                                \
+  do {                                                                         \
+    ProfTag pt_(tag);                                                          \
+    Arena a = sc.fresh();                                                      \
+    Arena s = S(i);                                                            \
+    EVO_TRY(with_batched_reductions(c, [&](const Ctx& c) { return call; })); \
+    sc.done(a);                                                                \
   } while (0)
   // recompute the forward, keeping what the backward needs
   EVO_STEPS(0, "row.recompute", (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, m1)));

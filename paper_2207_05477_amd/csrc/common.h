@@ -151,9 +151,13 @@ struct Arena {
   bool overflow() const { return !dry && off > cap; }
 };
 
+struct RedQueue;
 struct Ctx {
   hipStream_t stream = nullptr;
   bool dry = false;      // size only: allocate from the arenas, launch nothing
+  // When set, parameter-gradient reductions are queued here and run as one
+  // batched launch by flush_reductions (see misc.h).
+  RedQueue* defer = nullptr;
 };
 
 inline size_t dtype_bytes(int dt) { return dt == EVO_BF16 ? 2 : 4; }

@@ -258,7 +258,9 @@ evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int 
   EVO_LAUNCH(EVO_KNAME("rowproj_dw_kernel", T), 2.0 * (double)rows * C * H, (double)rows * C * sizeof(T) + (double)H * rows * 4.0, (rowproj_dw_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, x, rows, C, H,
                      dout, part);
   EVO_TRY(check_launch("rowproj_dw"));
-  return reduce_partials(c, part, nblk, (int64_t)C * H, (int64_t)C * H, dW, true);
+  RedSegs rs;
+  rs.nseg = 1; rs.off[0] = 0; rs.n[0] = C * H; rs.out[0] = dW;
+  return reduce_segments(c, part, nblk, 1, (int64_t)C * H, rs, true);
 }
 
 // ============================================================== segmented column sums

@@ -50,6 +50,35 @@ struct RedSegs {
 };
 evo_status_t reduce_segments(const Ctx& c, const float* part, int64_t n, int64_t M, int64_t ld,
                              const RedSegs& segs, bool accumulate);
+// With c.defer set, an accumulating reduce_segments is queued instead of
+// launched: the queue holds the partial-buffer pointer, so the buffer must stay
+// untouched until flush_reductions runs the queued reductions, all in one
+// launch (outputs of queued reductions must not overlap).  Parameter gradients
+// of a backward op use this: their partials live in the op's scratch and
+// nothing in the op reads the gradients.
+struct RedJob {
+  const float* part;
+  int64_t n, M, ld;
+  RedSegs segs;
+};
+constexpr int RED_MAX_JOBS = 12;
+struct RedQueue {
+  int njobs = 0;
+  RedJob jobs[RED_MAX_JOBS];
+};
+evo_status_t flush_reductions(const Ctx& c, RedQueue& q);
+// Runs f(ctx) with its parameter-gradient reductions deferred to one launch at
+// the end (a fresh queue: reductions queued by an enclosing scope are not
+// touched and those of f are all run before it returns).
+template <typename F>
+evo_status_t with_batched_reductions(const Ctx& c, F&& f) {
+  if (c.dry) return f(c);
+  RedQueue q;
+  Ctx cq = c;
+  cq.defer = &q;
+  EVO_TRY(f(cq));
+  return flush_reductions(c, q);
+}
 // Two outputs from one [n][2C] partial buffer (LayerNorm gamma / beta).
 evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C, float* out_a,
                               float* out_b);

@@ -657,10 +657,117 @@ __global__ __launch_bounds__(256) void reduce_segments_narrow_kernel(const float
   *o = accumulate ? *o + red[0][tc] : red[0][tc];
 }
 
+// Batched form: blocks [start_j, start_{j+1}) serve job j.  A job's block is
+// (256 / rg) column threads x rg row groups; each thread sums 4 consecutive
+// flattened columns over the partial rows i = tr (mod rg), and the rg group
+// sums are added in order by the first group.
+struct RedJobDev {
+  const float* part;
+  int64_t n, stride;
+  int32_t E, ld, rg, vec4;
+  RedSegs segs;
+};
+struct RedBatchArgs {
+  int32_t njobs;
+  int32_t start[RED_MAX_JOBS + 1];
+  RedJobDev jobs[RED_MAX_JOBS];
+};
+
+__global__ __launch_bounds__(256) void reduce_batch_kernel(const RedBatchArgs a) {
+  __shared__ f32x4 red[256];
+  int j = 0;
+  while (j + 1 < a.njobs && (int)blockIdx.x >= a.start[j + 1]) ++j;
+  const float* part = a.jobs[j].part;
+  const int64_t n = a.jobs[j].n, stride = a.jobs[j].stride;
+  const int E = a.jobs[j].E, rg = a.jobs[j].rg;
+  const int cw = 256 / rg;
+  const int tc = threadIdx.x % cw, tr = threadIdx.x / cw;
+  const int e0 = ((int)blockIdx.x - a.start[j]) * cw * 4 + tc * 4;
+  f32x4 s = {0.f, 0.f, 0.f, 0.f};
+  if (e0 < E) {
+    if (a.jobs[j].vec4) {
+      for (int64_t i = tr; i < n; i += rg) s += *(const f32x4*)(part + i * stride + e0);
+    } else {
+      for (int64_t i = tr; i < n; i += rg)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (e0 + q < E) s[q] += part[i * stride + e0 + q];
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (tr != 0 || e0 >= E) return;
+  f32x4 t = red[tc];
+  for (int r = 1; r < rg; ++r) t += red[r * cw + tc];
+  const int ld = a.jobs[j].ld;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = e0 + q;
+    if (e >= E) break;
+    const int m = e / ld, cc = e - m * ld;
+    const int k = seg_of(a.jobs[j].segs, cc);
+    if (k < 0 || !a.jobs[j].segs.out[k]) continue;
+    float* o = a.jobs[j].segs.out[k] + (int64_t)m * a.jobs[j].segs.n[k] + (cc - a.jobs[j].segs.off[k]);
+    *o += t[q];
+  }
+}
+
+evo_status_t flush_reductions(const Ctx& c, RedQueue& q) {
+  if (c.dry || q.njobs == 0) { q.njobs = 0; return EVO_OK; }
+  RedBatchArgs a;
+  memset(&a, 0, sizeof(a));
+  a.njobs = q.njobs;
+  double bytes = 0.0;
+  int nblk = 0;
+  for (int j = 0; j < q.njobs; ++j) {
+    const RedJob& J = q.jobs[j];
+    RedJobDev& D = a.jobs[j];
+    const int64_t E = J.M * J.ld;
+    if (E >= (1LL << 30)) { set_error("reduce: %lld columns too many", (long long)E); return EVO_EINVAL; }
+    D.part = J.part; D.n = J.n; D.stride = E; D.E = (int32_t)E; D.ld = (int32_t)J.ld; D.segs = J.segs;
+    D.vec4 = (E % 4 == 0 && aligned16(J.part)) ? 1 : 0;
+    // row groups: about 16 partial rows per thread, 1..64 groups
+    int rg = 1;
+    while (rg < 64 && J.n > 16 * rg) rg <<= 1;
+    D.rg = rg;
+    const int64_t cols_per_blk = (int64_t)(256 / rg) * 4;
+    a.start[j] = nblk;
+    nblk += (int)((E + cols_per_blk - 1) / cols_per_blk);
+    bytes += ((double)J.n + 2.0) * E * 4.0;
+  }
+  a.start[q.njobs] = nblk;
+  q.njobs = 0;
+  EVO_LAUNCH("reduce_batch_kernel", 0.0, bytes, reduce_batch_kernel, dim3((unsigned)nblk), dim3(256), 0,
+             c.stream, a);
+  return check_launch("reduce_batch");
+}
+
+// Whether an output range of segs ([M][n_t] from out_t) overlaps one of a queued job.
+static bool overlaps_queued(const RedQueue& q, int64_t M, const RedSegs& segs) {
+  for (int j = 0; j < q.njobs; ++j)
+    for (int s = 0; s < q.jobs[j].segs.nseg; ++s)
+      for (int t = 0; t < segs.nseg; ++t) {
+        const float* a0 = q.jobs[j].segs.out[s];
+        const float* b0 = segs.out[t];
+        if (!a0 || !b0) continue;
+        const float* a1 = a0 + q.jobs[j].M * q.jobs[j].segs.n[s];
+        const float* b1 = b0 + M * segs.n[t];
+        if (a0 < b1 && b0 < a1) return true;
+      }
+  return false;
+}
+
 evo_status_t reduce_segments(const Ctx& c, const float* part, int64_t n, int64_t M, int64_t ld,
                              const RedSegs& segs, bool accumulate) {
   if (c.dry || M * ld == 0 || segs.nseg == 0) return EVO_OK;
   if (segs.nseg > 8) { set_error("reduce: %d segments > 8", segs.nseg); return EVO_EINVAL; }
+  if (c.defer && accumulate && n > 0) {
+    RedQueue& q = *c.defer;
+    if (q.njobs == RED_MAX_JOBS || overlaps_queued(q, M, segs)) EVO_TRY(flush_reductions(c, q));
+    RedJob& J = q.jobs[q.njobs++];
+    J.part = part; J.n = n; J.M = M; J.ld = ld; J.segs = segs;
+    return EVO_OK;
+  }
   const int64_t C = M * ld;
   const double bytes = ((double)n + 1) * C * 4.0;
   if (C >= 65536 || n < 64) {
