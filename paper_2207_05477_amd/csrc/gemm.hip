@@ -7,6 +7,8 @@
 
 #include "gemm.h"
 
+#include <type_traits>
+
 namespace evo {
 
 template <typename T> struct GemmTraits;
@@ -528,10 +530,9 @@ struct PlainLoader {
   static constexpr int RB = BROWS / VEC;
   static constexpr int NBLK = RB * (BK / KB);
   static constexpr int NR = KC ? PASSES : KB;
-  static constexpr int SLOTS = KC ? 2 : 1;
 
   __amdgpu_buffer_rsrc_t rs;
-  i32x4 regs[SLOTS][NR];
+  i32x4 regs[1][NR];
   uint32_t voff[PASSES];
   int kk_[PASSES];
   int lds_[PASSES];
@@ -572,40 +573,48 @@ struct PlainLoader {
       lds_[0] = rb * VEC;
     }
   }
-  // tile kt; `krem` = reduction indices left from the tile start (< BK on a tail tile)
+  // Tile kt into register slot S.  The slot must be a compile-time constant and
+  // nothing may inspect the loaded values before store(): the loads then stay
+  // in flight until the LDS store that consumes them.
   template <int S>
-  EVO_DEV void load(int kt, int krem) {
+  EVO_DEV void load(int kt) {
     const uint32_t so = (uint32_t)kt * step;
     if constexpr (KC) {
 #pragma unroll
-      for (int p = 0; p < PASSES; ++p) {
-        regs[S][p] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[p], so, 0);
-        if (krem < BK && kk_[p] >= krem) regs[S][p] = i32x4{0, 0, 0, 0};
-      }
+      for (int p = 0; p < PASSES; ++p) regs[S][p] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[p], so, 0);
     } else {
 #pragma unroll
-      for (int q = 0; q < KB; ++q) {
+      for (int q = 0; q < KB; ++q)
         regs[S][q] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[0] + q * krow, so, 0);
-        if (krem < BK && kk_[0] + q >= krem) regs[S][q] = i32x4{0, 0, 0, 0};
-      }
     }
   }
+  // Slot S to LDS; `krem` = reduction indices left from the tile start: on a
+  // tail tile (krem < BK) the indices beyond it are stored as zeros.
   template <int S>
-  EVO_DEV void store(T* lds, int tid) {
+  EVO_DEV void store(T* lds, int tid, int krem) {
     if constexpr (KC) {
 #pragma unroll
-      for (int p = 0; p < PASSES; ++p)
-        if (tid + 256 * p < NV) *(i32x4*)(lds + lds_[p]) = regs[S][p];
+      for (int p = 0; p < PASSES; ++p) {
+        i32x4 v = regs[S][p];
+        if (krem < BK && kk_[p] >= krem) v = i32x4{0, 0, 0, 0};
+        if (tid + 256 * p < NV) *(i32x4*)(lds + lds_[p]) = v;
+      }
     } else {
       if (tid >= NBLK) return;
       typedef typename Chunk<KB * sizeof(T)>::type C;
       const int r0 = lds_[0], k0 = kk_[0];
+      i32x4 v[KB];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        v[q] = regs[S][q];
+        if (krem < BK && k0 + q >= krem) v[q] = i32x4{0, 0, 0, 0};
+      }
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
         const int r = r0 + i;
         union { C c; T e[KB]; } u;
 #pragma unroll
-        for (int q = 0; q < KB; ++q) u.e[q] = ((const T*)&regs[S][q])[i];
+        for (int q = 0; q < KB; ++q) u.e[q] = ((const T*)&v[q])[i];
         *(C*)(lds + r * LDK + VEC * ((k0 / VEC) ^ swz(r)) + (k0 % VEC)) = u.c;
       }
     }
@@ -671,17 +680,12 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
     for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const int kspan = kend - kbeg;
   if (nk > 0) {
-    la.template load<0>(0, kend - kbeg);
-    lb.template load<0>(0, kend - kbeg);
-  }
-  if (nk > 1) {
-    if constexpr (KCA) la.template load<1>(1, kend - kbeg - BK);
-    if constexpr (KCB) lb.template load<1>(1, kend - kbeg - BK);
-  }
-  if (nk > 0) {
-    la.template store<0>(lds[0], tid);
-    lb.template store<0>(lds[0] + BM * LDK, tid);
+    la.template load<0>(0);
+    lb.template load<0>(0);
+    la.template store<0>(lds[0], tid, kspan);
+    lb.template store<0>(lds[0] + BM * LDK, tid, kspan);
   }
   __syncthreads();
 
@@ -728,40 +732,21 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
       }
     }
   };
-  // same pipeline as gemm_kernel: tile kt in LDS buffer kt & 1, later tiles in registers
+  // Tile kt is in LDS buffer kt & 1; tile kt + 1 is loaded into registers
+  // before the products of tile kt and stored to the other buffer after them,
+  // so its load latency overlaps one k-step of matrix-core work.
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if constexpr (KCA) {
-      if (kt + 2 < nk) {
-        if (cur == 0) la.template load<0>(kt + 2, kend - kbeg - (kt + 2) * BK);
-        else la.template load<1>(kt + 2, kend - kbeg - (kt + 2) * BK);
-      }
-    } else if (kt + 1 < nk) {
-      la.template load<0>(kt + 1, kend - kbeg - (kt + 1) * BK);
-    }
-    if constexpr (KCB) {
-      if (kt + 2 < nk) {
-        if (cur == 0) lb.template load<0>(kt + 2, kend - kbeg - (kt + 2) * BK);
-        else lb.template load<1>(kt + 2, kend - kbeg - (kt + 2) * BK);
-      }
-    } else if (kt + 1 < nk) {
-      lb.template load<0>(kt + 1, kend - kbeg - (kt + 1) * BK);
+    if (kt + 1 < nk) {
+      la.template load<0>(kt + 1);
+      lb.template load<0>(kt + 1);
     }
     compute(lds[cur]);
     if (kt + 1 < nk) {
       T* dst = lds[cur ^ 1];
-      if constexpr (KCA) {
-        if (cur == 0) la.template store<1>(dst, tid);
-        else la.template store<0>(dst, tid);
-      } else {
-        la.template store<0>(dst, tid);
-      }
-      if constexpr (KCB) {
-        if (cur == 0) lb.template store<1>(dst + BM * LDK, tid);
-        else lb.template store<0>(dst + BM * LDK, tid);
-      } else {
-        lb.template store<0>(dst + BM * LDK, tid);
-      }
+      const int krem = kspan - (kt + 1) * BK;
+      la.template store<0>(dst, tid, krem);
+      lb.template store<0>(dst + BM * LDK, tid, krem);
     }
     __syncthreads();
   }

@@ -2,6 +2,8 @@
 #pragma once
 #include "common.h"
 
+#include <initializer_list>
+
 namespace evo {
 
 // y = LayerNorm(x) over the last axis (rows x C, row pitch C), FP32 statistics.
@@ -104,6 +106,9 @@ struct PackArgs {
 };
 template <typename T>
 evo_status_t pack_params(const Ctx& c, const PackArgs& a);
+// Several groups (up to 3) in one launch.
+template <typename T>
+evo_status_t pack_params(const Ctx& c, std::initializer_list<const PackArgs*> list);
 
 template <typename T>
 evo_status_t fill_zero(const Ctx& c, T* p, int64_t n);

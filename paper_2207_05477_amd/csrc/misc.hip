@@ -878,11 +878,25 @@ evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t l
 }
 
 // ============================================================== packing / fill
+// Up to PACK_MAX parameter groups in one launch: blocks [start_g, start_{g+1})
+// pack group g, one element (k, n) of its [K][sum n] concatenation per thread.
+constexpr int PACK_MAX = 3;
+struct PackBatch {
+  PackArgs a[PACK_MAX];
+  int32_t ntot[PACK_MAX];
+  int32_t start[PACK_MAX + 1];
+  int32_t n;
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void pack_kernel(PackArgs a, int ntot) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)a.K * ntot) return;
-  const int k = (int)(e / ntot), n = (int)(e % ntot);
+__global__ __launch_bounds__(256) void pack_kernel(const PackBatch b) {
+  int q = 0;
+  while (q + 1 < b.n && (int)blockIdx.x >= b.start[q + 1]) ++q;
+  const PackArgs& a = b.a[q];
+  const int ntot = b.ntot[q];
+  const int e = ((int)blockIdx.x - b.start[q]) * 256 + (int)threadIdx.x;
+  if (e >= a.K * ntot) return;
+  const int k = e / ntot, n = e - k * ntot;
   int s = 0, nl = n;
   while (s < a.nseg - 1 && nl >= a.seg[s].n) { nl -= a.seg[s].n; ++s; }
   const float v = a.seg[s].w[(int64_t)k * a.seg[s].n + nl];
@@ -892,16 +906,37 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a, int ntot) {
 }
 
 template <typename T>
-evo_status_t pack_params(const Ctx& c, const PackArgs& a) {
+evo_status_t pack_params(const Ctx& c, std::initializer_list<const PackArgs*> list) {
   if (c.dry) return EVO_OK;
-  int ntot = 0;
-  for (int s = 0; s < a.nseg; ++s) {
-    EVO_CHECK_ARG(a.seg[s].w != nullptr, EVO_EINVAL, "null parameter pointer (segment %d)", s);
-    ntot += a.seg[s].n;
+  EVO_CHECK_ARG(list.size() <= (size_t)PACK_MAX, EVO_EINVAL, "pack: %zu groups > %d", list.size(), PACK_MAX);
+  PackBatch b;
+  memset(&b, 0, sizeof(b));
+  double bytes = 0.0;
+  int nblk = 0;
+  for (const PackArgs* a : list) {
+    int ntot = 0;
+    for (int s = 0; s < a->nseg; ++s) {
+      EVO_CHECK_ARG(a->seg[s].w != nullptr, EVO_EINVAL, "null parameter pointer (segment %d)", s);
+      ntot += a->seg[s].n;
+    }
+    const int64_t n = (int64_t)a->K * ntot;
+    EVO_CHECK_ARG(n < (1LL << 30), EVO_EINVAL, "pack: %lld elements too many", (long long)n);
+    b.a[b.n] = *a;
+    b.ntot[b.n] = ntot;
+    b.start[b.n] = nblk;
+    ++b.n;
+    nblk += (int)((n + 255) / 256);
+    bytes += (double)n * (4.0 + sizeof(T) * ((a->dst ? 1 : 0) + (a->dst_t ? 1 : 0)));
   }
-  const int64_t n = (int64_t)a.K * ntot;
-  EVO_LAUNCH(EVO_KNAME("pack_kernel", T), 0.0, (double)n * (4.0 + sizeof(T) * ((a.dst ? 1 : 0) + (a.dst_t ? 1 : 0))), (pack_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, ntot);
+  b.start[b.n] = nblk;
+  if (nblk == 0) return EVO_OK;
+  EVO_LAUNCH(EVO_KNAME("pack_kernel", T), 0.0, bytes, (pack_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, b);
   return check_launch("pack_params");
+}
+
+template <typename T>
+evo_status_t pack_params(const Ctx& c, const PackArgs& a) {
+  return pack_params<T>(c, {&a});
 }
 
 template <typename T>
@@ -1164,6 +1199,7 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
                                           int*);                                                   \
   template evo_status_t colsum_add<T>(const Ctx&, const T*, int64_t, int, int64_t, float*, float*); \
   template evo_status_t pack_params<T>(const Ctx&, const PackArgs&);                               \
+  template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<const PackArgs*>);        \
   template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \
   template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
   template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t, const T*, \

@@ -136,13 +136,12 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
   pk.nseg = 4;
   pk.dst_t = wt_qkvg;
   pk.bias = b_qkvg;
-  EVO_TRY(pack_params<T>(c, pk));
   PackArgs po;
   po.K = s.HC;
   po.seg[0] = {w.w_o, nullptr, (int)cin};
   po.nseg = 1;
   po.dst_t = wt_o;
-  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(pack_params<T>(c, {&pk, &po}));
   EVO_TRY((ln_rowproj<X, T>(c, x, R * R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias)));
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     // chunk rows: starting node (i, j) = (c0 + ii, j) contiguous; ending node
@@ -216,13 +215,12 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   pk.nseg = 4;
   pk.dst_t = wt_qkvg;
   pk.bias = b_qkvg;
-  EVO_TRY(pack_params<T>(c, pk));
   PackArgs po;
   po.K = s.HC;
   po.seg[0] = {w.w_o, nullptr, (int)s.cin};
   po.nseg = 1;
   po.dst_t = wt_o;
-  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(pack_params<T>(c, {&pk, &po}));
 
   EVO_TRY((ln_fwd<X, T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {
@@ -305,13 +303,12 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     pk.seg[3] = {w.w_g, nullptr, s.HC};
     pk.nseg = 4;
     pk.dst = w_qkvg;
-    EVO_TRY(pack_params<T>(c, pk));
     PackArgs po;
     po.K = s.HC;
     po.seg[0] = {w.w_o, nullptr, (int)s.cin};
     po.nseg = 1;
     po.dst = w_o;
-    EVO_TRY(pack_params<T>(c, po));
+    EVO_TRY(pack_params<T>(c, {&pk, &po}));
   }
 
   // output projection

@@ -23,9 +23,8 @@ evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   float* b1 = ws.take_n<float>(HID);
   if (c.dry) return EVO_OK;
   PackArgs p1; p1.K = (int)C; p1.seg[0] = {w.w_1, w.b_1, (int)HID}; p1.nseg = 1; p1.dst_t = wt1; p1.bias = b1;
-  EVO_TRY(pack_params<T>(c, p1));
   PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst_t = wt2;
-  EVO_TRY(pack_params<T>(c, p2));
+  EVO_TRY(pack_params<T>(c, {&p1, &p2}));
   EVO_TRY((ln_fwd<X, T>(c, x, d.rows, (int)C, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd)));
   {
     GemmArgs g;
@@ -63,9 +62,8 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   float* dy = ws.take_n<float>(d.rows * C);
   if (!c.dry) {
     PackArgs p1; p1.K = (int)C; p1.seg[0] = {w.w_1, nullptr, (int)HID}; p1.nseg = 1; p1.dst = w1;
-    EVO_TRY(pack_params<T>(c, p1));
     PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst = w2;
-    EVO_TRY(pack_params<T>(c, p2));
+    EVO_TRY(pack_params<T>(c, {&p1, &p2}));
   }
   int off0 = 0, nC = (int)C, nH = (int)HID;
   float* ob2[1] = {dw.b_2};
@@ -138,9 +136,8 @@ evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   if (c.dry) return EVO_OK;
   PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, w.b_a, (int)ch}; pa.seg[1] = {w.w_b, w.b_b, (int)ch};
   pa.nseg = 2; pa.dst_t = wt_ab; pa.bias = b_ab;
-  EVO_TRY(pack_params<T>(c, pa));
   PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
-  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(pack_params<T>(c, {&pa, &po}));
   EVO_TRY((ln_fwd<X, T>(c, m, SR, (int)cm, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {  // a | b = mask * (y W + b)
     GemmArgs g;
@@ -199,9 +196,8 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   if (!c.dry) {
     PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, nullptr, (int)ch}; pa.seg[1] = {w.w_b, nullptr, (int)ch};
     pa.nseg = 2; pa.dst = w_ab;
-    EVO_TRY(pack_params<T>(c, pa));
     PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst = w_o;
-    EVO_TRY(pack_params<T>(c, po));
+    EVO_TRY(pack_params<T>(c, {&pa, &po}));
   }
   int off0 = 0, ncz = (int)cz;
   float* obo[1] = {dw.b_o};
@@ -324,9 +320,8 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
   pp.nseg = 5;
   pp.dst_t = wt_p;
   pp.bias = b_p;
-  EVO_TRY(pack_params<T>(c, pp));
   PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
-  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(pack_params<T>(c, {&pp, &po}));
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     const int64_t p0 = c0 * R;
     EVO_TRY((ln_fwd<X, T>(c, z + p0 * cz, CR, (int)cz, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd)));
@@ -392,9 +387,8 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   pp.nseg = 5;
   pp.dst_t = wt_p;
   pp.bias = b_p;
-  EVO_TRY(pack_params<T>(c, pp));
   PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
-  EVO_TRY(pack_params<T>(c, po));
+  EVO_TRY(pack_params<T>(c, {&pp, &po}));
   EVO_TRY((ln_fwd<X, T>(c, z, P, (int)cz, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {
     GemmArgs g;
@@ -462,9 +456,8 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     pp.seg[4] = {w.w_g, nullptr, (int)cz};
     pp.nseg = 5;
     pp.dst = w_p;
-    EVO_TRY(pack_params<T>(c, pp));
     PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o; po.dst = w_o;
-    EVO_TRY(pack_params<T>(c, po));
+    EVO_TRY(pack_params<T>(c, {&pp, &po}));
     {  // t = LN_out(x) W_o + b_o
       GemmArgs g;
       g.M = P; g.N = cz; g.K = ch;
