@@ -93,98 +93,134 @@ EVO_DEV f32x4 contract64(const T* trow, bool rok, const f32x4* p, int lg, f32x4 
   return acc;
 }
 
-// Stage a 64-row tile of (position, head) rows [p0, p0+64) of `src` into LDS:
-// row-major [64][DP] (if dst_rm) and/or transposed [DR][TP] (if dst_t).  The
-// transposed copy takes two rows per lane so that each store moves a pair of
-// rows of one d (4 or 8 bytes) into consecutive LDS words.
-template <typename T, int D>
-EVO_DEV void stage_tile(const T* src, int64_t sp, int64_t p0, int64_t pend, T* dst_rm, T* dst_t,
-                        int tid) {
+// exp2 on the hardware unit (one instruction; results below 2^-126 flush to
+// zero: probabilities that small relative to the row maximum do not matter).
+EVO_DEV float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Register staging of a 64-row tile of (position, head) rows [p0, p0 + 64) of
+// `src` (rows from pend on read as zeros): load() issues all global loads of
+// the tile, store() writes the LDS copies, so that the loads of a stage are in
+// flight together.  Row-major copy [64][DP]; with TR also a transposed copy
+// [DR][TP], taken two rows per lane so that each store moves a pair of rows
+// of one d (4 or 8 bytes) into consecutive LDS words.
+EVO_DEV uint32_t u4word(const uint4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+
+template <typename T, int D, bool TR>
+struct RowsStage {
   using F = DF<T, D>;
-  constexpr int VPR = D / F::VEC;  // vectors per row
-  if (dst_t) {
-    for (int e = tid; e < (KB / 2) * VPR; e += 256) {
-      const int j = e % (KB / 2), dv = (e / (KB / 2)) * F::VEC;
-      const int r = 2 * j;
-      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
-      if (p0 + r < pend) v0 = *(const uint4*)(src + (p0 + r) * sp + dv);
-      if (p0 + r + 1 < pend) v1 = *(const uint4*)(src + (p0 + r + 1) * sp + dv);
-      if (dst_rm) {
-        *(uint4*)(dst_rm + r * F::DP + dv) = v0;
-        *(uint4*)(dst_rm + (r + 1) * F::DP + dv) = v1;
-      }
-      const T* e0 = (const T*)&v0;
-      const T* e1 = (const T*)&v1;
+  static constexpr int VPR = D / F::VEC;                        // vectors per row
+  static constexpr int NV = TR ? (KB / 2) * VPR : KB * VPR;     // row pairs or rows x vectors
+  static constexpr int NI = (NV + 255) / 256;
+  uint4 v0[NI], v1[TR ? NI : 1];
+
+  EVO_DEV void load(const T* src, int64_t sp, int64_t p0, int64_t pend, int tid) {
+    const int lim = pend - p0 < KB ? (int)(pend - p0) : KB;
+    const T* base = src + p0 * sp;
 #pragma unroll
-      for (int i = 0; i < F::VEC; ++i) {
-        typedef __attribute__((__vector_size__(2 * sizeof(T)))) T t2;
-        *(t2*)(dst_t + (dv + i) * F::TP + r) = t2{e0[i], e1[i]};
+    for (int it = 0; it < NI; ++it) {
+      const int e = tid + 256 * it;
+      v0[it] = make_uint4(0, 0, 0, 0);
+      if constexpr (TR) v1[it] = make_uint4(0, 0, 0, 0);
+      if (e < NV) {
+        if constexpr (TR) {
+          const int r = 2 * (e % (KB / 2)), dv = (e / (KB / 2)) * F::VEC;
+          if (r < lim) v0[it] = *(const uint4*)(base + (int64_t)r * sp + dv);
+          if (r + 1 < lim) v1[it] = *(const uint4*)(base + (int64_t)(r + 1) * sp + dv);
+        } else {
+          const int r = e / VPR, dv = (e % VPR) * F::VEC;
+          if (r < lim) v0[it] = *(const uint4*)(base + (int64_t)r * sp + dv);
+        }
       }
     }
-    return;
   }
-  for (int e = tid; e < KB * VPR; e += 256) {
-    const int r = e / VPR, dv = (e % VPR) * F::VEC;
-    const int64_t p = p0 + r;
-    uint4 val = make_uint4(0, 0, 0, 0);
-    if (p < pend) val = *(const uint4*)(src + p * sp + dv);
-    *(uint4*)(dst_rm + r * F::DP + dv) = val;
+  EVO_DEV void store(T* dst_rm, T* dst_t, int tid) const {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int e = tid + 256 * it;
+      if (e >= NV) continue;
+      if constexpr (TR) {
+        const int r = 2 * (e % (KB / 2)), dv = (e / (KB / 2)) * F::VEC;
+        if (dst_rm) {
+          *(uint4*)(dst_rm + r * F::DP + dv) = v0[it];
+          *(uint4*)(dst_rm + (r + 1) * F::DP + dv) = v1[it];
+        }
+#pragma unroll
+        for (int i = 0; i < F::VEC; ++i) {
+          T* d = dst_t + (dv + i) * F::TP + r;
+          if constexpr (F::BF) {
+            // element i of a row is half i & 1 of word i >> 1
+            const uint32_t w0 = u4word(v0[it], i >> 1), w1 = u4word(v1[it], i >> 1);
+            *(uint32_t*)d = (i & 1) ? ((w0 >> 16) | (w1 & 0xffff0000u)) : ((w0 & 0xffffu) | (w1 << 16));
+          } else {
+            *(uint2*)d = make_uint2(u4word(v0[it], i), u4word(v1[it], i));
+          }
+        }
+      } else {
+        const int r = e / VPR, dv = (e % VPR) * F::VEC;
+        *(uint4*)(dst_rm + r * F::DP + dv) = v0[it];
+      }
+    }
   }
-}
+};
 
 // Bias tile in LDS, log2 domain: sb[r * BP + c] = log2(e) * bias[(r0 + r) * sr + (c0 + c) * sc]
 // for rows r < 64 and columns c < 64 in range (0 elsewhere); the loads run
-// along whichever of the two strides is 1.
+// along whichever of the two strides is 1.  Register staged like RowsStage.
 constexpr int BP = 68;
-EVO_DEV void stage_bias(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
-                        int64_t cend, float* sb, int tid) {
-  const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
-  const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
-  if (sc == 1) {
-    // rows of 64 contiguous floats: 16 lanes x float4 per row
-    const float* base = bias + r0 * sr + c0;
-    const bool vec = (nc == 64) && ((((uintptr_t)base) | (uintptr_t)(sr * 4)) % 16 == 0);
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int r = e >> 4, c = (e & 15) * 4;
-      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (r < nr) {
-        const float* src = base + r * sr + c;
+struct BiasStage {
+  f32x4 v[4];
+  EVO_DEV void load(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
+                    int64_t cend, int tid) {
+    if (sc != 1 && sr != 1) return;   // strided both ways: read in store()
+    // 64 vectors of 64 contiguous floats (rows if sc == 1, columns if sr == 1)
+    const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
+    const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
+    const int64_t so = sc == 1 ? sr : sc;   // stride between the vectors
+    const int nvec = sc == 1 ? nr : nc, nlen = sc == 1 ? nc : nr;
+    const float* base = bias + r0 * sr + c0 * sc;
+    const bool vec = (nlen == 64) && ((((uintptr_t)base) | (uintptr_t)(so * 4)) % 16 == 0);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int e = tid + 256 * it;
+      const int av = e >> 4, l = (e & 15) * 4;
+      v[it] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (av < nvec) {
+        const float* src = base + av * so + l;
         if (vec) {
-          v = *(const f32x4*)src;
+          v[it] = *(const f32x4*)src;
         } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = c + i < nc ? src[i] : 0.f;
+          for (int i = 0; i < 4; ++i) v[it][i] = l + i < nlen ? src[i] : 0.f;
         }
       }
-      *(f32x4*)(sb + r * BP + c) = v * kLog2e;
-    }
-  } else if (sr == 1) {
-    // columns of 64 contiguous floats (along r): float4 loads, transposed stores
-    const float* base = bias + c0 * sc + r0;
-    const bool vec = (nr == 64) && ((((uintptr_t)base) | (uintptr_t)(sc * 4)) % 16 == 0);
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int c = e >> 4, r = (e & 15) * 4;
-      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (c < nc) {
-        const float* src = base + c * sc + r;
-        if (vec) {
-          v = *(const f32x4*)src;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = r + i < nr ? src[i] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[i] * kLog2e;
-    }
-  } else {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int c = e >> 6, r = e & 63;
-      const bool ok = r < nr && c < nc;
-      sb[r * BP + c] = ok ? bias[(c0 + c) * sc + (r0 + r) * sr] * kLog2e : 0.f;
     }
   }
-}
+  EVO_DEV void store(float* sb, const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend,
+                     int64_t c0, int64_t cend, int tid) const {
+    if (sc == 1) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int e = tid + 256 * it;
+        *(f32x4*)(sb + (e >> 4) * BP + (e & 15) * 4) = v[it] * kLog2e;
+      }
+    } else if (sr == 1) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int e = tid + 256 * it;
+        const int c = e >> 4, r = (e & 15) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[it][i] * kLog2e;
+      }
+    } else {
+      const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
+      const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
+      for (int e = tid; e < 64 * 64; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        sb[r * BP + c] = (r < nr && c < nc) ? bias[(c0 + c) * sc + (r0 + r) * sr] * kLog2e : 0.f;
+      }
+    }
+  }
+};
 
 template <typename T, int D>
 EVO_DEV void zero_pad_rows(T* dst_t, int tid) {
@@ -211,7 +247,7 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
   __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sVt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) float sB[64 * BP];
-  __shared__ float sMk[KB];
+  __shared__ __attribute__((aligned(16))) float sMk[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int64_t b = blockIdx.z;
@@ -239,31 +275,41 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
   const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
   const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
 
+  // all global loads of a key tile are issued together, then stored to LDS
+  // (a tile-ahead prefetch measured slower: its registers cost occupancy)
+  RowsStage<T, D, false> stK;
+  RowsStage<T, D, true> stV;
+  BiasStage stB;
   for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
+    stK.load(K, a.sp, kb0, a.Lk, tid);
+    stV.load(V, a.sp, kb0, a.Lk, tid);
+    if (bias) stB.load(bias, a.bq, a.bk, q0, qend, kb0, a.Lk, tid);
+    const float mkv = (mask && tid < KB && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
     __syncthreads();
-    stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, nullptr, tid);
-    stage_tile<T, D>(V, a.sp, kb0, a.Lk, nullptr, sVt, tid);
-    if (bias) stage_bias(bias, a.bq, a.bk, q0, qend, kb0, a.Lk, sB, tid);
-    if (tid < KB) sMk[tid] = (mask && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
+    stK.store(sK, nullptr, tid);
+    stV.store(nullptr, sVt, tid);
+    if (bias) stB.store(sB, bias, a.bq, a.bk, q0, qend, kb0, a.Lk, tid);
+    if (tid < KB) sMk[tid] = mkv;
     __syncthreads();
+    const int klim = a.Lk - kb0 < KB ? (int)(a.Lk - kb0) : KB;   // keys of the tile in range
     f32x4 s[4];
-    float mloc = -INFINITY;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       typename F::Frag kf[F::NKS];
       load_dfrag<T, D>(sK + (16 * t + lr) * F::DP, lg, true, kf);
       s[t] = mfma_d<T, D>(kf, qf);
+    }
+    // logits in the log2 domain: masked keys replaced, keys past the end -inf
+    float mloc = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
       const f32x4 bv = bias ? *(const f32x4*)(sB + ql * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+      const f32x4 mk = *(const f32x4*)(sMk + 16 * t + 4 * lg);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int kl = 16 * t + 4 * lg + i;
-        float x = s[t][i] * scale_log2;
-        if (kb0 + kl >= a.Lk) {
-          x = -INFINITY;
-        } else {
-          if (bias) x += bv[i];
-          if (sMk[kl] == 0.f) x = kMaskLogit;
-        }
+        float x = fmaf(s[t][i], scale_log2, bv[i]);
+        x = mk[i] == 0.f ? kMaskLogit : x;
+        x = 16 * t + 4 * lg + i < klim ? x : -INFINITY;
         s[t][i] = x;
         mloc = fmaxf(mloc, x);
       }
@@ -271,13 +317,13 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
     mloc = fmaxf(mloc, __shfl_xor(mloc, 16, 64));
     mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
     const float m_new = fmaxf(m_run, mloc);
-    const float alpha = exp2f(m_run - m_new);
+    const float alpha = exp2_hw(m_run - m_new);
     float lsum = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float p = exp2f(s[t][i] - m_new);
+        const float p = exp2_hw(s[t][i] - m_new);
         s[t][i] = p;
         lsum += p;
       }
@@ -336,7 +382,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
   __shared__ __attribute__((aligned(16))) T sV[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) float sB[64 * BP];
-  __shared__ float sMk[KB];
+  __shared__ __attribute__((aligned(16))) float sMk[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int h = blockIdx.y;
@@ -371,12 +417,14 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
       const T* V = (const T*)a.v + b * a.sb + h * D;
       const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
       const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
-      __syncthreads();
-      stage_tile<T, D>(K, a.sp, kb0, a.Lk, sK, sKt, tid);
-      stage_tile<T, D>(V, a.sp, kb0, a.Lk, sV, nullptr, tid);
-      if (bi == 0 && bias) stage_bias(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, sB, tid);
-      if (tid < KB) sMk[tid] = (mask && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
-      __syncthreads();
+      // every global load of the stage first, then the LDS stores
+      RowsStage<T, D, true> stK;
+      RowsStage<T, D, false> stV;
+      BiasStage stB;
+      stK.load(K, a.sp, kb0, a.Lk, tid);
+      stV.load(V, a.sp, kb0, a.Lk, tid);
+      if (bi == 0 && bias) stB.load(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
+      const float mkv = (mask && tid < KB && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
       typename F::Frag qf[F::NKS], of[F::NKS];
       load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
       load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
@@ -387,6 +435,15 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
         irow = a.st_inv[si];
         drow = gr.Dsum[si];
       }
+      __syncthreads();
+      stK.store(sK, sKt, tid);
+      stV.store(sV, nullptr, tid);
+      if (bi == 0 && bias) stB.store(sB, bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
+      if (tid < KB) sMk[tid] = mkv;
+      __syncthreads();
+      const int klim = a.Lk - kb0 < KB ? (int)(a.Lk - kb0) : KB;
+      // dS = P (dP - D) for valid, unmasked keys (selected, so that values of
+      // discarded lanes never reach the sums)
       f32x4 ds[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -396,19 +453,12 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
         const f32x4 sv = mfma_d<T, D>(kf, qf);
         const f32x4 dp = mfma_d<T, D>(vf, of);
         const f32x4 bv = bias ? *(const f32x4*)(sB + qloc * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 mk = *(const f32x4*)(sMk + 16 * t + 4 * lg);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int kl = 16 * t + 4 * lg + i;
-          float r = 0.f;
-          if (qok && kb0 + kl < a.Lk) {
-            float x = sv[i] * scale_log2;
-            if (bias) x += bv[i];
-            if (sMk[kl] != 0.f) {
-              const float p = exp2f(x - mrow) * irow;
-              r = p * (dp[i] - drow);
-            }
-          }
-          ds[t][i] = r;
+          const float x = fmaf(sv[i], scale_log2, bv[i]);
+          const float r = exp2_hw(x - mrow) * irow * (dp[i] - drow);
+          ds[t][i] = (qok && 16 * t + 4 * lg + i < klim && mk[i] != 0.f) ? r : 0.f;
         }
         dbacc[t] = dbacc[t] + ds[t];
       }
@@ -466,7 +516,9 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
   __shared__ __attribute__((aligned(16))) T sQt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) T sOt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) float sB[64 * BP];
-  __shared__ float sM[KB], sI[KB], sD[KB];
+  __shared__ __attribute__((aligned(16))) float sM[KB];
+  __shared__ __attribute__((aligned(16))) float sI[KB];
+  __shared__ __attribute__((aligned(16))) float sD[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int h = blockIdx.y;
@@ -496,23 +548,27 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
       const T* V = (const T*)a.v + b * a.sb + h * D;
       const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
       const bool kmasked = kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
-      __syncthreads();
-      stage_tile<T, D>(Q, a.sp, qb0, a.Lq, sQ, sQt, tid);
-      stage_tile<T, D>(DO, a.osp, qb0, a.Lq, sO, sOt, tid);
-      if (bi == 0 && bias) stage_bias(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, sB, tid);
-      if (tid < KB) {
-        const int64_t q = qb0 + tid;
-        float mv = 0.f, iv = 0.f, dvv = 0.f;
-        if (q < a.Lq) {
-          const int64_t si = (b * a.stb + q * a.stq) * a.H + h;
-          mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
-        }
-        sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv;
+      // every global load of the stage first, then the LDS stores
+      RowsStage<T, D, true> stQ, stO;
+      BiasStage stB;
+      stQ.load(Q, a.sp, qb0, a.Lq, tid);
+      stO.load(DO, a.osp, qb0, a.Lq, tid);
+      if (bi == 0 && bias) stB.load(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
+      float mv = 0.f, iv = 0.f, dvv = 0.f;
+      if (tid < KB && qb0 + tid < a.Lq) {
+        const int64_t si = (b * a.stb + (qb0 + tid) * a.stq) * a.H + h;
+        mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
       }
-      __syncthreads();
       typename F::Frag kf[F::NKS], vf[F::NKS];
       load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
       load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
+      __syncthreads();
+      stQ.store(sQ, sQt, tid);
+      stO.store(sO, sOt, tid);
+      if (bi == 0 && bias) stB.store(sB, bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
+      if (tid < KB) { sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv; }
+      __syncthreads();
+      const int qlim = a.Lq - qb0 < KB ? (int)(a.Lq - qb0) : KB;   // queries of the tile in range
       f32x4 P[4], DS[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -522,19 +578,18 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
         const f32x4 sv = mfma_d<T, D>(qf, kf);
         const f32x4 dp = mfma_d<T, D>(of, vf);
         const f32x4 bv = bias ? *(const f32x4*)(sB + kl * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 m4 = *(const f32x4*)(sM + 16 * t + 4 * lg);
+        const f32x4 i4 = *(const f32x4*)(sI + 16 * t + 4 * lg);
+        const f32x4 d4 = *(const f32x4*)(sD + 16 * t + 4 * lg);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int ql = 16 * t + 4 * lg + i;
-          float p = 0.f, r = 0.f;
-          if (kok && qb0 + ql < a.Lq) {
-            float x = sv[i] * scale_log2;
-            if (bias) x += bv[i];
-            if (kmasked) x = kMaskLogit;
-            p = exp2f(x - sM[ql]) * sI[ql];
-            if (!kmasked) r = p * (dp[i] - sD[ql]);
-          }
-          P[t][i] = p;
-          DS[t][i] = r;
+          float x = fmaf(sv[i], scale_log2, bv[i]);
+          x = kmasked ? kMaskLogit : x;
+          const float p = exp2_hw(x - m4[i]) * i4[i];
+          const float r = p * (dp[i] - d4[i]);
+          const bool ok = kok && 16 * t + 4 * lg + i < qlim;
+          P[t][i] = ok ? p : 0.f;
+          DS[t][i] = (ok && !kmasked) ? r : 0.f;
         }
       }
 #pragma unroll
