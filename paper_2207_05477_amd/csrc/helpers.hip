@@ -239,12 +239,154 @@ __global__ __launch_bounds__(256) void rowproj_dw_kernel(const T* __restrict__ x
   }
 }
 
+// Vectorised backward (C % 8 == 0, C <= 512, H <= HM): LPR = C / 8 lanes per
+// row, each owning 8 channels (16-byte accesses).  A block owns RB rows; their
+// dout values are staged in LDS as [row][HM] (coalesced loads along the rows),
+// so a lane reads a row's HM values with vector broadcasts.
+constexpr int RPV_RB = 256;
+template <int HM>
+EVO_DEV void stage_dout_rows(const float* dout, int64_t rows, int64_t r0, int H, float* sd, int tid) {
+  for (int e = tid; e < HM * RPV_RB; e += 256) {
+    const int h = e / RPV_RB, rr = e - h * RPV_RB;
+    sd[rr * HM + h] = (h < H && r0 + rr < rows) ? dout[(int64_t)h * rows + r0 + rr] : 0.f;
+  }
+}
+
+// dx[row][c] (+)= sum_h dout[h][row] W[c][h]; the lane's W slice stays in registers.
+template <int LPR, int HM>
+__global__ __launch_bounds__(256) void rowproj_dx_vec_kernel(int64_t rows, int C, const float* __restrict__ W,
+                                                             int H, const float* __restrict__ dout, float* dx,
+                                                             int accumulate) {
+  __shared__ __attribute__((aligned(16))) float sd[RPV_RB * HM];
+  constexpr int RPI = 256 / LPR;
+  const int tid = threadIdx.x, l = tid & (LPR - 1);
+  const int c0 = l * 8;
+  const bool cok = c0 < C;
+  const int64_t r0 = (int64_t)blockIdx.x * RPV_RB;
+  stage_dout_rows<HM>(dout, rows, r0, H, sd, tid);
+  float w[8][HM];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int h = 0; h < HM; ++h) w[i][h] = (cok && h < H) ? W[(c0 + i) * H + h] : 0.f;
+  __syncthreads();
+  for (int rr = tid / LPR; rr < RPV_RB; rr += RPI) {
+    const int64_t row = r0 + rr;
+    if (row >= rows || !cok) continue;
+    float d[HM];
+#pragma unroll
+    for (int h = 0; h < HM; h += 4) {
+      const f32x4 q = *(const f32x4*)(sd + rr * HM + h);
+      d[h] = q[0]; d[h + 1] = q[1]; d[h + 2] = q[2]; d[h + 3] = q[3];
+    }
+    float o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float t = 0.f;
+#pragma unroll
+      for (int h = 0; h < HM; ++h) t += d[h] * w[i][h];
+      o[i] = t;
+    }
+    float* px = dx + row * C + c0;
+    if (accumulate) {
+      float prev[8];
+      ld8(px, prev);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) o[i] += prev[i];
+    }
+    st8(px, o);
+  }
+}
+
+// part[blk][c * H + h] = sum over the block's rows of x[row][c] dout[h][row]:
+// per-lane sums over the rows it visits, then the lanes sharing channels are
+// combined by xor shuffles (within a wave) and through LDS (across the 4
+// waves), in a fixed order.
+template <typename T, int LPR, int HM>
+__global__ __launch_bounds__(256) void rowproj_dw_vec_kernel(const T* __restrict__ x, int64_t rows, int C, int H,
+                                                             const float* __restrict__ dout,
+                                                             float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) float sd[RPV_RB * HM];
+  __shared__ float red[4][8 * LPR * HM];
+  constexpr int RPI = 256 / LPR;
+  const int tid = threadIdx.x, l = tid & (LPR - 1), wave = tid >> 6;
+  const int c0 = l * 8;
+  const bool cok = c0 < C;
+  const int64_t r0 = (int64_t)blockIdx.x * RPV_RB;
+  stage_dout_rows<HM>(dout, rows, r0, H, sd, tid);
+  __syncthreads();
+  float acc[8][HM];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int h = 0; h < HM; ++h) acc[i][h] = 0.f;
+  for (int rr = tid / LPR; rr < RPV_RB; rr += RPI) {
+    const int64_t row = r0 + rr;
+    if (row >= rows || !cok) continue;
+    float v[8], d[HM];
+    ld8(x + row * C + c0, v);
+#pragma unroll
+    for (int h = 0; h < HM; h += 4) {
+      const f32x4 q = *(const f32x4*)(sd + rr * HM + h);
+      d[h] = q[0]; d[h + 1] = q[1]; d[h + 2] = q[2]; d[h + 3] = q[3];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int h = 0; h < HM; ++h) acc[i][h] += v[i] * d[h];
+  }
+  // lanes l, l + LPR, ... of a wave hold the same channels
+#pragma unroll
+  for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int h = 0; h < HM; ++h) acc[i][h] += __shfl_xor(acc[i][h], o, 64);
+  if ((tid & 63) < LPR)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int h = 0; h < HM; ++h) red[wave][(c0 + i) * HM + h] = acc[i][h];
+  __syncthreads();
+  for (int e = tid; e < C * H; e += 256) {
+    const int cc = e / H, h = e - cc * H;
+    const int k = cc * HM + h;
+    part[(int64_t)blockIdx.x * C * H + e] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  }
+}
+
+template <typename T, int LPR, int HM>
+static void rowproj_bwd_vec_launch(const Ctx& c, const T* x, int64_t rows, int C, const float* W, int H,
+                                   const float* dout, float* dx, bool accumulate, float* part, int64_t nblk) {
+  if (dx)
+    EVO_LAUNCH("rowproj_dx_vec_kernel", 2.0 * (double)rows * C * H, (double)rows * C * (accumulate ? 8.0 : 4.0) + (double)H * rows * 4.0, (rowproj_dx_vec_kernel<LPR, HM>), dim3((unsigned)nblk), dim3(256), 0, c.stream,
+               rows, C, W, H, dout, dx, accumulate ? 1 : 0);
+  EVO_LAUNCH(EVO_KNAME("rowproj_dw_vec_kernel", T), 2.0 * (double)rows * C * H, (double)rows * C * sizeof(T) + (double)H * rows * 4.0, (rowproj_dw_vec_kernel<T, LPR, HM>), dim3((unsigned)nblk), dim3(256), 0, c.stream,
+             x, rows, C, H, dout, part);
+}
+
 template <typename T>
 evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int C, const float* W,
                          int H, const float* dout, float* dx, bool accumulate, float* dW) {
   const int64_t nblk = (rows + 255) / 256;
   float* part = ws.take_n<float>((size_t)nblk * C * H);
   if (c.dry || rows == 0) return EVO_OK;
+  if (C % 8 == 0 && C <= 256 && H <= 8 && aligned16(x) && (!dx || aligned16(dx))) {
+    switch (C / 8 <= 4 ? 4 : C / 8 <= 8 ? 8 : C / 8 <= 16 ? 16 : 32) {
+#define EVO_RPV(L)                                                                                    \
+  case L:                                                                                             \
+    if (H <= 4) rowproj_bwd_vec_launch<T, L, 4>(c, x, rows, C, W, H, dout, dx, accumulate, part, nblk); \
+    else rowproj_bwd_vec_launch<T, L, 8>(c, x, rows, C, W, H, dout, dx, accumulate, part, nblk);        \
+    break;
+      EVO_RPV(4) EVO_RPV(8) EVO_RPV(16) EVO_RPV(32)
+#undef EVO_RPV
+      default: break;
+    }
+    EVO_TRY(check_launch("rowproj_bwd"));
+    RedSegs rs;
+    rs.nseg = 1; rs.off[0] = 0; rs.n[0] = C * H; rs.out[0] = dW;
+    return reduce_segments(c, part, nblk, 1, (int64_t)C * H, rs, true);
+  }
   if (H > 16 || C > 256 || 256 % C) { set_error("pair bias bwd: unsupported C=%d H=%d", C, H); return EVO_ESHAPE; }
   if (dx) {
     const int64_t n = rows * C;

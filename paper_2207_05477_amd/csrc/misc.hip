@@ -216,6 +216,78 @@ __global__ __launch_bounds__(256) void ln_rowproj_kernel(const TI* __restrict__ 
   }
 }
 
+// Vectorised form (C % 8 == 0, C <= 512, H <= HM): the lane layout of
+// ln_fwd_vec_kernel with one 8-channel chunk per lane; the lane's W slice
+// (8 channels x HM heads) stays in registers while a thread walks RIT rows
+// spaced 256 / LPR apart; the H dot products are summed over the row's lanes by
+// xor shuffles.
+constexpr int LRP_RIT = 8;
+template <typename TI, typename T, int LPR, int HM>
+__global__ __launch_bounds__(256) void ln_rowproj_vec_kernel(const TI* __restrict__ x, int64_t rows, int C,
+                                                             const float* __restrict__ g,
+                                                             const float* __restrict__ b, float eps,
+                                                             const float* __restrict__ W, int H,
+                                                             float* __restrict__ out) {
+  constexpr int RPI = 256 / LPR;   // rows per iteration of the block
+  const int l = threadIdx.x & (LPR - 1);
+  const int c0 = l * 8;
+  const bool cok = c0 < C;
+  float w[8][HM], gg[8], bb[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    gg[i] = cok ? g[c0 + i] : 0.f;
+    bb[i] = cok ? b[c0 + i] : 0.f;
+#pragma unroll
+    for (int h = 0; h < HM; ++h) w[i][h] = (cok && h < H) ? W[(c0 + i) * H + h] : 0.f;
+  }
+  for (int it = 0; it < LRP_RIT; ++it) {
+    const int64_t row = ((int64_t)blockIdx.x * LRP_RIT + it) * RPI + threadIdx.x / LPR;
+    const bool ok = row < rows;
+    float v[8];
+    if (ok && cok) ld8(x + row * C + c0, v);
+    else
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.f;
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[i];
+    const float mu = group_sum<LPR>(s) / (float)C;
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float d = cok ? v[i] - mu : 0.f;
+      q += d * d;
+    }
+    const float rs = 1.0f / sqrtf(group_sum<LPR>(q) / (float)C + eps);
+    float acc[HM];
+#pragma unroll
+    for (int h = 0; h < HM; ++h) acc[h] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      // the projection reads the LayerNorm output in the storage precision
+      const float yv = to_f32(from_f32<T>((v[i] - mu) * rs * gg[i] + bb[i]));
+#pragma unroll
+      for (int h = 0; h < HM; ++h) acc[h] += yv * w[i][h];
+    }
+#pragma unroll
+    for (int h = 0; h < HM; ++h) {
+      acc[h] = group_sum<LPR>(acc[h]);
+      if (ok && h < H && l == h % LPR) out[(int64_t)h * rows + row] = acc[h];
+    }
+  }
+}
+
+template <typename TI, typename T, int LPR>
+static void ln_rowproj_vec_launch(const Ctx& c, double flops, double bytes, const TI* x, int64_t rows, int C,
+                                  const float* g, const float* b, float eps, const float* W, int H, float* out) {
+  constexpr int RPB = 256 / LPR * LRP_RIT;
+  const dim3 grid((unsigned)((rows + RPB - 1) / RPB));
+  if (H <= 4)
+    EVO_LAUNCH(EVO_KNAME("ln_rowproj_vec_kernel", TI), flops, bytes, (ln_rowproj_vec_kernel<TI, T, LPR, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+  else
+    EVO_LAUNCH(EVO_KNAME("ln_rowproj_vec_kernel", TI), flops, bytes, (ln_rowproj_vec_kernel<TI, T, LPR, 8>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+}
+
 template <typename TI, typename T>
 evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
                         float eps, const float* W, int H, float* out) {
@@ -223,6 +295,15 @@ evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const fl
   if (C > 256 || H > 16) { set_error("layernorm projection: C=%d H=%d unsupported", C, H); return EVO_ESHAPE; }
   const double bytes = (double)rows * C * sizeof(TI) + (double)rows * H * 4.0;
   const double flops = 2.0 * rows * C * H;
+  if (C % 8 == 0 && H <= 8 && aligned16(x)) {
+    switch (C / 8 <= 4 ? 4 : C / 8 <= 8 ? 8 : C / 8 <= 16 ? 16 : 32) {
+      case 4: ln_rowproj_vec_launch<TI, T, 4>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
+      case 8: ln_rowproj_vec_launch<TI, T, 8>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
+      case 16: ln_rowproj_vec_launch<TI, T, 16>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
+      default: ln_rowproj_vec_launch<TI, T, 32>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
+    }
+    return check_launch("ln_rowproj");
+  }
   if (C <= 128) {
     const size_t lds = ((size_t)64 * (C + 4) + (size_t)C * H) * sizeof(float);
     EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 64>),
