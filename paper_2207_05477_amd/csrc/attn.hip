@@ -230,15 +230,6 @@ EVO_DEV void zero_pad_rows(T* dst_t, int tid) {
   }
 }
 
-// Store 4 consecutive d values (d = d0..d0+3) of one (position, head) row.
-template <typename T>
-EVO_DEV void store4(T* dst, f32x4 v) {
-  if constexpr (sizeof(T) == 2) {
-    *(bf16x4*)dst = bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
-  } else {
-    *(f32x4*)dst = v;
-  }
-}
 
 // ============================================================== forward
 template <typename T, int D>

@@ -52,6 +52,15 @@ EVO_DEV void st8(bf16* p, const float v[8]) {
   for (int i = 0; i < 8; ++i) a[i] = (bf16)v[i];
   *(bf16x8*)p = a;
 }
+// 4 consecutive values (8-byte aligned for BF16, 16-byte for float).
+template <typename T>
+EVO_DEV void store4(T* dst, f32x4 v) {
+  if constexpr (sizeof(T) == 2) {
+    *(bf16x4*)dst = bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+  } else {
+    *(f32x4*)dst = v;
+  }
+}
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // ---------------------------------------------------------------- wave reductions (wave64)

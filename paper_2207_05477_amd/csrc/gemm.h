@@ -55,6 +55,7 @@ struct GemmArgs {
   int64_t M = 0, N = 0, K = 0;
   int32_t batch = 1;       // independent problems (blockIdx.z)
   int32_t split_k = 1;     // > 1: blockIdx.z splits K, partial results to out + z * epi.batch
+  int32_t big_tiles = 0;   // 1: 128 x 128 tiles whatever M x N (split-K problems with few tiles)
   GemmOperand A, B;        // A rows = m, B rows = n
   GemmEpilogue epi;
 };

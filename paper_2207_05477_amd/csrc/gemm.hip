@@ -765,6 +765,13 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
   if (e.gate) rg = rsrc((const char*)e.gate + zo * gsz, pi.ext_g);
   const float alpha = e.alpha;
   const int mlo = (int)e.m_lo, mhi = (int)e.m_hi, nhi = (int)e.n_hi;
+  // row and column offsets of the lane's outputs, once per row / column block
+  int mrow[TM], moff[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    mrow[i] = m0 + wm * WM + i * 16 + lr;
+    moff[i] = PlainLoader<T, BM, KCA>::a32(mrow[i], mlo, mhi, e.m_shift);
+  }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int n = n0 + wn * WN + j * 16 + lg * 4;
@@ -774,7 +781,7 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
     if (e.bias && colok) bj = *(const f32x4*)(e.bias + n);
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-      const int m = m0 + wm * WM + i * 16 + lr;
+      const int m = mrow[i];
       const bool ok = colok && m < M;
       f32x4 v = acc[j][i] * alpha + bj;
       if (e.act == ACT_RELU) {
@@ -785,11 +792,15 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
         for (int r = 0; r < 4; ++r)
           if (n + r >= e.act_n0) v[r] = sigmoidf_(v[r]);
       }
-      const int mo = PlainLoader<T, BM, KCA>::a32(m, mlo, mhi, e.m_shift);
+      const int mo = moff[i];
       if (e.scale) {
+        if (e.sn_shift >= 2) {   // n is a multiple of 4: the lane's 4 columns share one entry
+          v *= ok ? e.scale[(m >> e.sm_shift) * e.sm_ld + (n >> e.sn_shift) * e.sn_ld] : 0.f;
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          v[r] *= ok ? e.scale[(m >> e.sm_shift) * e.sm_ld + ((n + r) >> e.sn_shift) * e.sn_ld] : 0.f;
+          for (int r = 0; r < 4; ++r)
+            v[r] *= ok ? e.scale[(m >> e.sm_shift) * e.sm_ld + ((n + r) >> e.sn_shift) * e.sn_ld] : 0.f;
+        }
       }
       const uint32_t eo = (uint32_t)(e.r_m < 0 ? mo + no : m * pi.ldr + n);   // aux element offset
       if (e.relu_ref) {
@@ -979,7 +990,8 @@ evo_status_t gemm(const Ctx& ctx, const GemmArgs& g) {
   if (!operand_ok(g.A, g.M, VEC, "A") || !operand_ok(g.B, g.N, VEC, "B")) return EVO_ESHAPE;
   if (!g.epi.out) { set_error("gemm: null output"); return EVO_EINVAL; }
   if (g.split_k > 1 && !g.epi.out_f32) { set_error("gemm: split-K needs FP32 partials"); return EVO_EINVAL; }
-  if (g.M <= 16) launch<T, 16, 128, 1, 4>(ctx, g);
+  if (g.big_tiles && g.M > 16) launch<T, 128, 128, 2, 2>(ctx, g);
+  else if (g.M <= 16) launch<T, 16, 128, 1, 4>(ctx, g);
   else if (g.N <= 64 || g.M * g.N <= (int64_t)128 * 128 * 128) launch<T, 64, 64, 2, 2>(ctx, g);
   else if (g.N <= 128) launch<T, 128, 64, 2, 2>(ctx, g);
   else launch<T, 128, 128, 2, 2>(ctx, g);

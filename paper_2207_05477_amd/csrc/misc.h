@@ -141,6 +141,12 @@ template <typename T, typename X = T>
 evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
                              const float* g, T* dt, T* draw);
 
+// Outer-product-mean input gradients from split-K partials:
+//   dab[s][i][off + p] = mask[s][i] * sum_k part[k][s][i][p]   (part FP32 [nsplit][S][R][ch],
+// dab rows [R][2 ch], mask NULL: ones; ch a multiple of 4).
+template <typename T>
+evo_status_t opm_dab_reduce(const Ctx& c, const float* part, int nsplit, int64_t S, int64_t R, int ch,
+                            const float* mask, T* dab, int off);
 // scale[i*R + j] = 1 / (eps + sum_s mask[s,i] mask[s,j])  (mask NULL: all ones).
 evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, float eps, float* scale);
 

@@ -1240,24 +1240,68 @@ evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* d
 }
 
 // ============================================================== outer product mean count
-__global__ __launch_bounds__(256) void opm_norm_kernel(const float* mask, int64_t S, int64_t R, float eps,
-                                                       float* scale) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= R * R) return;
-  const int64_t i = e / R, j = e % R;
+// One thread per 4 consecutive p of one (s, i): the split partials are summed in order.
+template <typename T>
+__global__ __launch_bounds__(256) void opm_dab_reduce_kernel(const float* __restrict__ part, int nsplit,
+                                                             int64_t S, int64_t R, int ch,
+                                                             const float* __restrict__ mask, T* dab, int off) {
+  const int64_t n = S * R * ch;
+  const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (e >= n) return;
+  f32x4 v = *(const f32x4*)(part + e);
+  for (int k = 1; k < nsplit; ++k) v += *(const f32x4*)(part + (int64_t)k * n + e);
+  const int64_t si = e / ch;           // s * R + i
+  const int p = (int)(e - si * ch);
+  if (mask) v *= mask[si];
+  store4<T>(dab + si * 2 * ch + off + p, v);
+}
+
+template <typename T>
+evo_status_t opm_dab_reduce(const Ctx& c, const float* part, int nsplit, int64_t S, int64_t R, int ch,
+                            const float* mask, T* dab, int off) {
+  if (c.dry) return EVO_OK;
+  if (ch % 4) { set_error("outer product mean: c_hidden %d not a multiple of 4", ch); return EVO_ESHAPE; }
+  const int64_t q = S * R * ch / 4;
+  EVO_LAUNCH(EVO_KNAME("opm_dab_reduce_kernel", T), 0.0, (double)S * R * ch * (4.0 * nsplit + sizeof(T)),
+             (opm_dab_reduce_kernel<T>), dim3((unsigned)((q + 255) / 256)), dim3(256), 0, c.stream, part, nsplit,
+             S, R, ch, mask, dab, off);
+  return check_launch("opm_dab_reduce");
+}
+
+// A block owns 16 x 16 outputs (i, j); chunks of 64 mask rows s for its 16
+// columns i and 16 columns j are staged in LDS, and each thread sums its
+// products over s in order.
+constexpr int OPN_S = 64;
+__global__ __launch_bounds__(256) void opm_norm_kernel(const float* __restrict__ mask, int64_t S, int64_t R,
+                                                       float eps, float* __restrict__ scale) {
+  __shared__ float si[OPN_S][16], sj[OPN_S][16];
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16;
+  const int64_t i = i0 + ti, j = j0 + tj;
   float n = 0.f;
   if (mask) {
-    for (int64_t s = 0; s < S; ++s) n += mask[s * R + i] * mask[s * R + j];
+    for (int64_t s0 = 0; s0 < S; s0 += OPN_S) {
+      __syncthreads();
+      for (int e = tid; e < OPN_S * 16; e += 256) {
+        const int ss = e >> 4, t = e & 15;
+        const bool sok = s0 + ss < S;
+        si[ss][t] = (sok && i0 + t < R) ? mask[(s0 + ss) * R + i0 + t] : 0.f;
+        sj[ss][t] = (sok && j0 + t < R) ? mask[(s0 + ss) * R + j0 + t] : 0.f;
+      }
+      __syncthreads();
+      const int ns = S - s0 < OPN_S ? (int)(S - s0) : OPN_S;
+      for (int ss = 0; ss < ns; ++ss) n += si[ss][ti] * sj[ss][tj];
+    }
   } else {
     n = (float)S;
   }
-  scale[e] = 1.0f / (eps + n);
+  if (i < R && j < R) scale[i * R + j] = 1.0f / (eps + n);
 }
 
 evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, float eps, float* scale) {
   if (c.dry) return EVO_OK;
-  const int64_t n = R * R;
-  EVO_LAUNCH("opm_norm_kernel", 2.0 * (double)S * R * R, (double)R * R * 4.0 + (mask ? (double)S * R * 4.0 : 0.0), opm_norm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, mask, S,
+  const unsigned nb = (unsigned)((R + 15) / 16);
+  EVO_LAUNCH("opm_norm_kernel", 2.0 * (double)S * R * R, (double)R * R * 4.0 + (mask ? (double)S * R * 4.0 : 0.0), opm_norm_kernel, dim3(nb, nb), dim3(256), 0, c.stream, mask, S,
                      R, eps, scale);
   return check_launch("opm_norm");
 }
@@ -1279,6 +1323,8 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t colsum_partial<T>(const Ctx&, const T*, int64_t, int, int64_t, float*,     \
                                           int*);                                                   \
   template evo_status_t colsum_add<T>(const Ctx&, const T*, int64_t, int, int64_t, float*, float*); \
+  template evo_status_t opm_dab_reduce<T>(const Ctx&, const float*, int, int64_t, int64_t, int,       \
+                                          const float*, T*, int);                                  \
   template evo_status_t pack_params<T>(const Ctx&, const PackArgs&);                               \
   template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<const PackArgs*>);        \
   template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \

@@ -193,6 +193,10 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   T* dO = ws.take_n<T>(RR * ch2);
   T* dab = ws.take_n<T>(SR * 2 * ch);
   float* dy = ws.take_n<float>(SR * cm);
+  // da and db have only S_ rows: 128 x 128 tiles split OPM_SPLIT ways along
+  // their R * ch reduction (FP32 partials), summed with the mask in one pass
+  constexpr int OPM_SPLIT = 4;
+  float* dpart = ws.take_n<float>((size_t)OPM_SPLIT * SR * ch);
   if (!c.dry) {
     PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, nullptr, (int)ch}; pa.seg[1] = {w.w_b, nullptr, (int)ch};
     pa.nseg = 2; pa.dst = w_ab;
@@ -214,32 +218,32 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
       EVO_TRY(gemm<T>(c, g));
     }
     // da and db as [s][(i, p)] products (rows s, columns (i, p) contiguous within
-    // blocks of ch), so that the output moves as row vectors.
+    // blocks of ch), so that the partials move as row vectors.
     {  // da[s][i][p] = mask_si * sum_{j,q} b[s][j][q] dO[i][j][p][q]
       GemmArgs g;
       g.M = S_; g.N = R * ch; g.K = R * ch;
+      g.split_k = OPM_SPLIT; g.big_tiles = 1;
       g.A.ptr = S.ab + ch; g.A.r_lo = R * 2 * ch;
       g.A.k_lo = 1; g.A.k_hi = 2 * ch; g.A.k_shift = sh; g.A.k_contig = 1;
       g.B.ptr = dO; g.B.r_lo = ch; g.B.r_hi = R * ch2; g.B.r_shift = sh;
       g.B.k_lo = 1; g.B.k_hi = ch2; g.B.k_shift = sh; g.B.k_contig = 1;
-      g.epi.out = dab; g.epi.out_f32 = 0;
-      g.epi.m_lo = R * 2 * ch;
-      g.epi.n_lo = 1; g.epi.n_hi = 2 * ch; g.epi.n_shift = sh;
-      if (mask) { g.epi.scale = mask; g.epi.sm_shift = 0; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1; }
+      g.epi = epi_rowmajor(dpart, R * ch, true);
+      g.epi.batch = SR * ch;
       EVO_TRY(gemm<T>(c, g));
+      EVO_TRY(opm_dab_reduce<T>(c, dpart, OPM_SPLIT, S_, R, (int)ch, mask, dab, 0));
     }
     {  // db[s][j][q] = mask_sj * sum_{i,p} a[s][i][p] dO[i][j][p][q]
       GemmArgs g;
       g.M = S_; g.N = R * ch; g.K = R * ch;
+      g.split_k = OPM_SPLIT; g.big_tiles = 1;
       g.A.ptr = S.ab; g.A.r_lo = R * 2 * ch;
       g.A.k_lo = 1; g.A.k_hi = 2 * ch; g.A.k_shift = sh; g.A.k_contig = 1;
       g.B.ptr = dO; g.B.r_lo = 1; g.B.r_hi = ch2; g.B.r_shift = sh;
       g.B.k_lo = ch; g.B.k_hi = R * ch2; g.B.k_shift = sh; g.B.k_contig = 0;
-      g.epi.out = dab + ch; g.epi.out_f32 = 0;
-      g.epi.m_lo = R * 2 * ch;
-      g.epi.n_lo = 1; g.epi.n_hi = 2 * ch; g.epi.n_shift = sh;
-      if (mask) { g.epi.scale = mask; g.epi.sm_shift = 0; g.epi.sm_ld = R; g.epi.sn_shift = sh; g.epi.sn_ld = 1; }
+      g.epi = epi_rowmajor(dpart, R * ch, true);
+      g.epi.batch = SR * ch;
       EVO_TRY(gemm<T>(c, g));
+      EVO_TRY(opm_dab_reduce<T>(c, dpart, OPM_SPLIT, S_, R, (int)ch, mask, dab, (int)ch));
     }
   }
   int offs[2] = {0, (int)ch}, ns[2] = {(int)ch, (int)ch};
