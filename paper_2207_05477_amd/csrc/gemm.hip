@@ -637,15 +637,25 @@ EVO_DEV f32x4 load4(__amdgpu_buffer_rsrc_t r, uint32_t off, bool f32) {
   }
 }
 
+// LDS buffers of the plain kernel: with both operands k-contiguous (the
+// stores are plain vector copies) one buffer and two barriers per k-step, so
+// that three workgroups fit on a CU; with a transposing operand two buffers.
+template <bool KCA, bool KCB> struct PlainPipe {
+  static constexpr int NBUF = (KCA && KCB) ? 1 : 2;
+  static constexpr int WAVES_PER_EU = (KCA && KCB) ? 3 : 1;   // 1: no request
+};
+
 template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, bool KCA, bool KCB>
-__global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlainPipe<KCA, KCB>::WAVES_PER_EU)))
+void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
   constexpr int BK = GemmTraits<T>::BK;
   constexpr int VEC = GemmTraits<T>::VEC;
   constexpr int LDK = BK + VEC;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int TM = WM / 16, TN = WN / 16;
   static_assert(WAVES_M * WAVES_N == 4, "4 waves");
-  __shared__ __attribute__((aligned(16))) T lds[2][(BM + BN) * LDK];
+  constexpr int NBUF = PlainPipe<KCA, KCB>::NBUF;
+  __shared__ __attribute__((aligned(16))) T lds[NBUF][(BM + BN) * LDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
@@ -686,6 +696,10 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
     lb.template load<0>(0);
     la.template store<0>(lds[0], tid, kspan);
     lb.template store<0>(lds[0] + BM * LDK, tid, kspan);
+  }
+  if (nk > 1) {
+    la.template load<0>(1);
+    lb.template load<0>(1);
   }
   __syncthreads();
 
@@ -732,23 +746,43 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, PlainInfo p
       }
     }
   };
-  // Tile kt is in LDS buffer kt & 1; tile kt + 1 is loaded into registers
-  // before the products of tile kt and stored to the other buffer after them,
-  // so its load latency overlaps one k-step of matrix-core work.
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      la.template load<0>(kt + 1);
-      lb.template load<0>(kt + 1);
+  if constexpr (NBUF == 1) {
+    // One buffer: the products of tile kt, a barrier, the store of tile kt + 1
+    // (loaded during the products) and the loads of tile kt + 2, a barrier.
+    for (int kt = 0; kt < nk; ++kt) {
+      compute(lds[0]);
+      if (kt + 1 < nk) {
+        __syncthreads();
+        const int krem = kspan - (kt + 1) * BK;
+        la.template store<0>(lds[0], tid, krem);
+        lb.template store<0>(lds[0] + BM * LDK, tid, krem);
+        if (kt + 2 < nk) {
+          la.template load<0>(kt + 2);
+          lb.template load<0>(kt + 2);
+        }
+        __syncthreads();
+      }
     }
-    compute(lds[cur]);
-    if (kt + 1 < nk) {
-      T* dst = lds[cur ^ 1];
-      const int krem = kspan - (kt + 1) * BK;
-      la.template store<0>(dst, tid, krem);
-      lb.template store<0>(dst + BM * LDK, tid, krem);
+  } else {
+    // Two buffers, tile kt in buffer kt & 1.  A step first stores tile kt + 1
+    // (its loads were issued a whole step earlier) into the other buffer, then
+    // issues the loads of tile kt + 2 into the freed registers, then runs the
+    // products of tile kt; one barrier ends the step.
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) {
+        T* dst = lds[cur ^ 1];
+        const int krem = kspan - (kt + 1) * BK;
+        la.template store<0>(dst, tid, krem);
+        lb.template store<0>(dst + BM * LDK, tid, krem);
+        if (kt + 2 < nk) {
+          la.template load<0>(kt + 2);
+          lb.template load<0>(kt + 2);
+        }
+      }
+      compute(lds[cur]);
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // epilogue straight from the accumulators: lane holds n..n+3 of row m
