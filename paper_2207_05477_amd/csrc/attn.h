@@ -43,6 +43,6 @@ struct AttnGrad {
 
 template <typename T> evo_status_t attn_fwd(const Ctx& c, const AttnCore& a);
 template <typename T> evo_status_t attn_bwd(const Ctx& c, const AttnCore& a, const AttnGrad& g);
-int64_t attn_bwd_groups(const AttnCore& a);   // number of bias-gradient partial slices
+template <typename T> int64_t attn_bwd_groups(const AttnCore& a);   // number of bias-gradient partial slices
 
 }  // namespace evo

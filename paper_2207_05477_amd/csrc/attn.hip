@@ -362,13 +362,17 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
 // that the bias tile is staged once and the bias gradient of the tile, summed
 // over the group's batches in registers, is written once as this group's
 // partial; the dQ accumulators of the group's batches stay in registers.
-template <int D> struct DqGroup { static constexpr int GM = D <= 16 ? 8 : 4; };
+// Batches per dQ workgroup: FP32 halves the group (its fragments are twice as
+// large; a larger group costs occupancy, measured slower).
+template <typename T, int D> struct DqGroup {
+  static constexpr int GM = (D <= 16 ? 8 : 4) / (sizeof(T) == 2 ? 1 : 2);
+};
 
 template <typename T, int D>
 __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                           float scale) {
   using F = DF<T, D>;
-  constexpr int GM = DqGroup<D>::GM;
+  constexpr int GM = DqGroup<T, D>::GM;
   __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sV[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
@@ -653,6 +657,7 @@ evo_status_t attn_fwd(const Ctx& c, const AttnCore& a) {
   return check_launch("attn_fwd");
 }
 
+template <typename T>
 int64_t attn_bwd_groups(const AttnCore& a) {
   // about 1024 workgroups, and at most the batches one workgroup keeps in registers
   const int64_t qblocks = (a.Lq + 63) / 64;
@@ -660,7 +665,7 @@ int64_t attn_bwd_groups(const AttnCore& a) {
   if (target < 1) target = 1;
   if (target > a.nbatch) target = a.nbatch;
   int64_t group = (a.nbatch + target - 1) / target;
-  const int64_t gmax = a.D <= 16 ? DqGroup<16>::GM : DqGroup<64>::GM;
+  const int64_t gmax = a.D <= 16 ? DqGroup<T, 16>::GM : DqGroup<T, 64>::GM;
   if (group > gmax) group = gmax;
   return (a.nbatch + group - 1) / group;
 }
@@ -669,7 +674,7 @@ template <typename T, int D>
 static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   const float sl2 = kLog2e / sqrtf((float)D);
   const float sc = 1.0f / sqrtf((float)D);
-  const int64_t ngroups = attn_bwd_groups(a);
+  const int64_t ngroups = attn_bwd_groups<T>(a);
   g.group = (a.nbatch + ngroups - 1) / ngroups;
   const size_t lds = 0;
   static const std::string n1 = kname<T, D>("attn_bwd_dq_kernel");
@@ -692,6 +697,9 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc, kgroup);
   return check_launch("attn_bwd_dkdv");
 }
+
+template int64_t attn_bwd_groups<float>(const AttnCore&);
+template int64_t attn_bwd_groups<bf16>(const AttnCore&);
 
 template <typename T>
 evo_status_t attn_bwd(const Ctx& c, const AttnCore& a, const AttnGrad& g) {

@@ -286,7 +286,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     a = core_for(s, S.qkvg, S.o, S.go, S.bias, mask, S.st_max, S.st_inv);
     set_qkvg<T>(a, S.qkvg, s);
     if (s.row || s.tri) {
-      ngroups = attn_bwd_groups(a);
+      ngroups = attn_bwd_groups<T>(a);
       dbias_part = ws.take_n<float>((size_t)ngroups * s.H * a.Lq * a.Lk);
       dbias = ws.take_n<float>((size_t)s.H * a.Lq * a.Lk);
     }
