@@ -799,6 +799,15 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
   if (e.gate) rg = rsrc((const char*)e.gate + zo * gsz, pi.ext_g);
   const float alpha = e.alpha;
   const int mlo = (int)e.m_lo, mhi = (int)e.m_hi, nhi = (int)e.n_hi;
+  // BF16 outputs with plain rows go out through LDS as whole 16-byte row
+  // chunks: a lane's own 8-byte pieces (a quarter of a 128-byte line per store)
+  // were measured to double the bytes written to HBM.
+  constexpr int TPO = BN + 8;   // LDS row pitch of the staged output tile (elements)
+  static_assert(sizeof(T) != 2 || BM * TPO <= (BM + BN) * LDK, "staged output tile fits the operand LDS");
+  const bool stage = sizeof(T) == 2 && !of32 && e.m_shift < 0 && e.n_shift < 0 && (N & 7) == 0 &&
+                     (mlo & 7) == 0 && ((((uintptr_t)e.out) + (uintptr_t)zo * osz) & 15) == 0;
+  T* sto = &lds[0][0];
+  if (stage) __syncthreads();   // the operand tiles are no longer read
   // row and column offsets of the lane's outputs, once per row / column block
   int mrow[TM], moff[TM];
 #pragma unroll
@@ -855,10 +864,25 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
         union { i32x2 q; T e4[4]; } u;
 #pragma unroll
         for (int r = 0; r < 4; ++r) u.e4[r] = from_f32<T>(v[r]);
-        __builtin_amdgcn_raw_buffer_store_b64(u.q, ro, oo, 0, 0);
+        if (stage)
+          *(i32x2*)(sto + (wm * WM + i * 16 + lr) * TPO + wn * WN + j * 16 + lg * 4) = u.q;
+        else
+          __builtin_amdgcn_raw_buffer_store_b64(u.q, ro, oo, 0, 0);
       } else {
         const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
         __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
+      }
+    }
+  }
+  if constexpr (sizeof(T) == 2) {
+    if (stage) {
+      __syncthreads();
+      constexpr int CPR = BN / 8;   // 16-byte chunks per tile row
+      for (int c2 = tid; c2 < BM * CPR; c2 += 256) {
+        const int r = c2 / CPR, cl = (c2 - r * CPR) * 8;
+        const int m = m0 + r, n = n0 + cl;
+        const uint32_t off = (m < M && n < N) ? (uint32_t)(m * mlo + n) * 2u : kOOB;
+        __builtin_amdgcn_raw_buffer_store_b128(*(const i32x4*)(sto + r * TPO + cl), ro, off, 0, 0);
       }
     }
   }
