@@ -169,10 +169,15 @@ struct RowsStage {
 constexpr int BP = 68;
 struct BiasStage {
   f32x4 v[4];
+  // Element (r, c) of the tile for slot `it` of thread `tid` (a lane covers 4
+  // consecutive elements along the unit-stride axis):
+  //   sc == 1: row r = e >> 4, columns c = 4 (e & 15) .. + 3;
+  //   sr == 1: column c = 16 it + (tid & 15), rows r = 4 (tid >> 4) .. + 3, so
+  //            that the 16 lanes of a group store 16 consecutive columns of one
+  //            row (transposing stores without bank conflicts).
   EVO_DEV void load(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
                     int64_t cend, int tid) {
     if (sc != 1 && sr != 1) return;   // strided both ways: read in store()
-    // 64 vectors of 64 contiguous floats (rows if sc == 1, columns if sr == 1)
     const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
     const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
     const int64_t so = sc == 1 ? sr : sc;   // stride between the vectors
@@ -182,7 +187,8 @@ struct BiasStage {
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int e = tid + 256 * it;
-      const int av = e >> 4, l = (e & 15) * 4;
+      const int av = sc == 1 ? e >> 4 : 16 * it + (tid & 15);   // vector index (row or column)
+      const int l = sc == 1 ? (e & 15) * 4 : (tid >> 4) * 4;    // offset along the vector
       v[it] = f32x4{0.f, 0.f, 0.f, 0.f};
       if (av < nvec) {
         const float* src = base + av * so + l;
@@ -206,8 +212,7 @@ struct BiasStage {
     } else if (sr == 1) {
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
-        const int e = tid + 256 * it;
-        const int c = e >> 4, r = (e & 15) * 4;
+        const int c = 16 * it + (tid & 15), r = (tid >> 4) * 4;
 #pragma unroll
         for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[it][i] * kLog2e;
       }
