@@ -22,6 +22,7 @@ namespace evo {
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int KB = 64;   // keys (or queries, in the dK/dV kernel) per LDS tile
+constexpr float kLazy = 8.0f;   // forward: log2 headroom before the running maximum moves
 
 template <typename T, int D>
 struct DF {
@@ -133,6 +134,30 @@ struct RowsStage {
       }
     }
   }
+  // Like load(), but rows from pend on repeat row pend - 1 (pend > p0): for
+  // kernels whose logits of keys past the end are -inf whatever the key row
+  // holds, so that no lane branches or zero-fills.
+  EVO_DEV void load_clamped(const T* src, int64_t sp, int64_t p0, int64_t pend, int tid) {
+    const int last = (pend - p0 < KB ? (int)(pend - p0) : KB) - 1;
+    const T* base = src + p0 * sp;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int e = tid + 256 * it;
+      // (zero-filled first: without it the compiler keeps the stage in scratch)
+      v0[it] = make_uint4(0, 0, 0, 0);
+      if constexpr (TR) v1[it] = make_uint4(0, 0, 0, 0);
+      if (NV % 256 == 0 || e < NV) {
+        if constexpr (TR) {
+          const int r = 2 * (e % (KB / 2)), dv = (e / (KB / 2)) * F::VEC;
+          v0[it] = *(const uint4*)(base + (int64_t)(r < last ? r : last) * sp + dv);
+          v1[it] = *(const uint4*)(base + (int64_t)(r + 1 < last ? r + 1 : last) * sp + dv);
+        } else {
+          const int r = e / VPR, dv = (e % VPR) * F::VEC;
+          v0[it] = *(const uint4*)(base + (int64_t)(r < last ? r : last) * sp + dv);
+        }
+      }
+    }
+  }
   EVO_DEV void store(T* dst_rm, T* dst_t, int tid) const {
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
@@ -236,14 +261,99 @@ EVO_DEV void zero_pad_rows(T* dst_t, int tid) {
 }
 
 
+// Forward logits, log2 domain: x = (s * km[k] + xb[q][k]) + ka[k], s = q . k,
+// with per-key (km, ka) = (scale, 0) for a valid key, (0, kMaskLogit) for a
+// masked key and (0, -inf) for a key past the end, and xb = log2(e) * bias
+// (0 without bias; finite for every staged column).  Two operations per
+// logit; s and xb are finite and |xb| is far below |kMaskLogit|, so masked and
+// out-of-range logits are the replacement values exactly, and a valid key's
+// logit is fma(s, scale, xb) + 0, bit for bit the backward's recomputation.
+EVO_DEV void key_fold(const float* mask, int64_t mk, int64_t k, int64_t kend, float scale, float& mul,
+                      float& add) {
+  const bool in = k < kend;
+  const float mv = mask ? mask[(in ? k : kend - 1) * mk] : 1.f;   // clamped: no divergent load
+  mul = (in && mv != 0.f) ? scale : 0.f;
+  add = !in ? -INFINITY : (mv == 0.f ? kMaskLogit : 0.f);
+}
+
+// Layout of the bias tile load, fixed per launch: none; unit stride along
+// keys (tile rows contiguous) or along queries (tile columns contiguous), both
+// with 16-byte vector loads and every tile whole along the unit-stride axis;
+// anything else (general strides, ragged tiles, unaligned rows) with clamped
+// scalar loads.
+enum { BIAS_NONE = 0, BIAS_ROWS = 1, BIAS_COLS = 2, BIAS_STRIDED = 3 };
+
+// Bias tile (rows = queries, columns = keys) in the log2 domain:
+// sb[r * BP + c] = log2(e) * bias[(r0 + r) * sr + (c0 + c) * sc].  Loads clamp
+// rows and columns into range (out-of-range entries are finite copies, never
+// used: their keys get -inf, their queries are discarded), so no lane
+// zero-fills or branches per element.  Register staged; element mapping as in
+// BiasStage (BIAS_ROWS like sc == 1, the other layouts like sr == 1).
+template <int BM>
+struct LogBiasStage {
+  f32x4 v[4];
+  EVO_DEV void load(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
+                    int64_t cend, int tid) {
+    if constexpr (BM == BIAS_ROWS) {
+      const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
+      const float* base = bias + r0 * sr + c0;
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int e = tid + 256 * it;
+        const int r = (e >> 4) < nr ? (e >> 4) : nr - 1;
+        v[it] = *(const f32x4*)(base + r * sr + (e & 15) * 4);
+      }
+    } else if constexpr (BM == BIAS_COLS) {
+      const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
+      const float* base = bias + r0 + c0 * sc;
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        int c = 16 * it + (tid & 15);
+        c = c < nc ? c : nc - 1;
+        v[it] = *(const f32x4*)(base + c * sc + (tid >> 4) * 4);
+      }
+    } else if constexpr (BM == BIAS_STRIDED) {
+      const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
+      const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
+      const int cb = tid & 15, rb = (tid >> 4) * 4;
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int c = 16 * it + cb, cc = c < nc ? c : nc - 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rr = rb + i < nr ? rb + i : nr - 1;
+          v[it][i] = bias[(c0 + cc) * sc + (r0 + rr) * sr];
+        }
+      }
+    }
+  }
+  EVO_DEV void store(float* sb, int tid) const {
+    if constexpr (BM == BIAS_ROWS) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int e = tid + 256 * it;
+        *(f32x4*)(sb + (e >> 4) * BP + (e & 15) * 4) = v[it] * kLog2e;
+      }
+    } else if constexpr (BM != BIAS_NONE) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int c = 16 * it + (tid & 15), r = (tid >> 4) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[it][i] * kLog2e;
+      }
+    }
+  }
+};
+
 // ============================================================== forward
-template <typename T, int D>
+template <typename T, int D, int BM>
 __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_log2) {
   using F = DF<T, D>;
   __shared__ __attribute__((aligned(16))) T sK[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sVt[F::DR * F::TP];
-  __shared__ __attribute__((aligned(16))) float sB[64 * BP];
-  __shared__ __attribute__((aligned(16))) float sMk[KB];
+  __shared__ __attribute__((aligned(16))) float sB[BM != BIAS_NONE ? 64 * BP : 4];
+  __shared__ __attribute__((aligned(16))) float sKs[KB];
+  __shared__ __attribute__((aligned(16))) float sKa[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int64_t b = blockIdx.z;
@@ -267,27 +377,31 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
   f32x4 oacc[F::NDT];
 #pragma unroll
   for (int dt = 0; dt < F::NDT; ++dt) oacc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // BF16: the row sum of the probabilities comes out of the context product
+  // as row 0 of one more 16-row tile whose V^T rows are (1, 0, ..., 0), so
+  // that it sums the same BF16 probabilities as the context.
+  f32x4 lacc = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
+  const float* bias = BM != BIAS_NONE ? a.bias + h * a.bh : nullptr;
   const float* mask = a.mask ? a.mask + b * a.mb : nullptr;
 
   // all global loads of a key tile are issued together, then stored to LDS
   // (a tile-ahead prefetch measured slower: its registers cost occupancy)
   RowsStage<T, D, false> stK;
   RowsStage<T, D, true> stV;
-  BiasStage stB;
+  LogBiasStage<BM> stB;
   for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
-    stK.load(K, a.sp, kb0, a.Lk, tid);
-    stV.load(V, a.sp, kb0, a.Lk, tid);
-    if (bias) stB.load(bias, a.bq, a.bk, q0, qend, kb0, a.Lk, tid);
-    const float mkv = (mask && tid < KB && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
+    stK.load_clamped(K, a.sp, kb0, a.Lk, tid);
+    stV.load_clamped(V, a.sp, kb0, a.Lk, tid);
+    if constexpr (BM != BIAS_NONE) stB.load(bias, a.bq, a.bk, q0, qend, kb0, a.Lk, tid);
+    float kmul = 0.f, kadd = 0.f;
+    if (tid < KB) key_fold(mask, a.mk, kb0 + tid, a.Lk, scale_log2, kmul, kadd);
     __syncthreads();
     stK.store(sK, nullptr, tid);
     stV.store(nullptr, sVt, tid);
-    if (bias) stB.store(sB, bias, a.bq, a.bk, q0, qend, kb0, a.Lk, tid);
-    if (tid < KB) sMk[tid] = mkv;
+    if constexpr (BM != BIAS_NONE) stB.store(sB, tid);
+    if (tid < KB) { sKs[tid] = kmul; sKa[tid] = kadd; }
     __syncthreads();
-    const int klim = a.Lk - kb0 < KB ? (int)(a.Lk - kb0) : KB;   // keys of the tile in range
     f32x4 s[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -295,45 +409,68 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
       load_dfrag<T, D>(sK + (16 * t + lr) * F::DP, lg, true, kf);
       s[t] = mfma_d<T, D>(kf, qf);
     }
-    // logits in the log2 domain: masked keys replaced, keys past the end -inf
+    // logits in the log2 domain (see key_fold)
     float mloc = -INFINITY;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const f32x4 bv = bias ? *(const f32x4*)(sB + ql * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
-      const f32x4 mk = *(const f32x4*)(sMk + 16 * t + 4 * lg);
+      const f32x4 km = *(const f32x4*)(sKs + 16 * t + 4 * lg);
+      const f32x4 ka = *(const f32x4*)(sKa + 16 * t + 4 * lg);
+      const f32x4 xb = BM != BIAS_NONE ? *(const f32x4*)(sB + ql * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float x = fmaf(s[t][i], scale_log2, bv[i]);
-        x = mk[i] == 0.f ? kMaskLogit : x;
-        x = 16 * t + 4 * lg + i < klim ? x : -INFINITY;
+        const float x = BM != BIAS_NONE ? fmaf(s[t][i], km[i], xb[i]) + ka[i] : fmaf(s[t][i], km[i], ka[i]);
         s[t][i] = x;
         mloc = fmaxf(mloc, x);
       }
     }
     mloc = fmaxf(mloc, __shfl_xor(mloc, 16, 64));
     mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
-    const float m_new = fmaxf(m_run, mloc);
-    const float alpha = exp2_hw(m_run - m_new);
+    // Lazy rescaling: the reference point m_run moves only when a logit
+    // exceeds it by more than kLazy (probabilities relative to it then stay
+    // below 2^kLazy), and the wave rescales its accumulators only when one of
+    // its queries moved.  Any reference point gives the same normalized
+    // result; the saved statistics are taken relative to the final one.
+    const bool grow = mloc > m_run + kLazy;
+    if (__builtin_amdgcn_ballot_w64(grow)) {
+      const float m_new = grow ? mloc : m_run;
+      const float alpha = exp2_hw(m_run - m_new);
+      m_run = m_new;
+#pragma unroll
+      for (int dt = 0; dt < F::NDT; ++dt) oacc[dt] = oacc[dt] * alpha;
+      if constexpr (F::BF) lacc = lacc * alpha;
+      else l_run = l_run * alpha;
+    }
     float lsum = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float p = exp2_hw(s[t][i] - m_new);
+        const float p = exp2_hw(s[t][i] - m_run);
         s[t][i] = p;
-        lsum += p;
+        if constexpr (!F::BF) lsum += p;
       }
-    lsum += __shfl_xor(lsum, 16, 64);
-    lsum += __shfl_xor(lsum, 32, 64);
-    l_run = l_run * alpha + lsum;
-    m_run = m_new;
 #pragma unroll
     for (int dt = 0; dt < F::NDT; ++dt) {
-      oacc[dt] = oacc[dt] * alpha;
       const int dr = 16 * dt + lr;
       oacc[dt] = contract64<T, D>(sVt + dr * F::TP, true, s, lg, oacc[dt]);
     }
+    if constexpr (F::BF) {
+      const bf16 one = lr == 0 ? (bf16)1.0f : (bf16)0.0f;
+      const bf16x8 ones = bf16x8{one, one, one, one, one, one, one, one};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const f32x4 p0 = s[2 * u], p1 = s[2 * u + 1];
+        const bf16x8 pb = bf16x8{(bf16)p0[0], (bf16)p0[1], (bf16)p0[2], (bf16)p0[3],
+                                 (bf16)p1[0], (bf16)p1[1], (bf16)p1[2], (bf16)p1[3]};
+        lacc = mfma_bf16(ones, pb, lacc);
+      }
+    } else {
+      lsum += __shfl_xor(lsum, 16, 64);
+      lsum += __shfl_xor(lsum, 32, 64);
+      l_run += lsum;
+    }
   }
+  if constexpr (F::BF) l_run = __shfl(lacc[0], lr, 64);   // row 0 of the sum tile: lanes 0..15
 
   if (!qok) return;
   const float inv = 1.0f / l_run;
@@ -374,7 +511,7 @@ template <typename T, int D> struct DqGroup {
 };
 
 template <typename T, int D>
-__global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad gr, float scale_log2,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void attn_bwd_dq_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                           float scale) {
   using F = DF<T, D>;
   constexpr int GM = DqGroup<T, D>::GM;
@@ -382,7 +519,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
   __shared__ __attribute__((aligned(16))) T sV[KB * F::DP];
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) float sB[64 * BP];
-  __shared__ __attribute__((aligned(16))) float sMk[KB];
+  __shared__ __attribute__((aligned(16))) float sKa[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int h = blockIdx.y;
@@ -424,26 +561,37 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
       stK.load(K, a.sp, kb0, a.Lk, tid);
       stV.load(V, a.sp, kb0, a.Lk, tid);
       if (bi == 0 && bias) stB.load(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
-      const float mkv = (mask && tid < KB && kb0 + tid < a.Lk) ? mask[(kb0 + tid) * a.mk] : 1.f;
+      // Per-key addend of the logits: 0 for a valid key, -inf for a masked key
+      // or one past the end, whose probability is then exactly 0.  (In the
+      // forward a masked key has the replacement logit, which gives it
+      // probability 0 unless the whole row is masked; a wholly masked row,
+      // recognisable by its maximum, has no logit gradient at all and gets
+      // irow = 0 below.)
+      float kadd = 0.f;
+      if (tid < KB) {
+        const bool in = kb0 + tid < a.Lk;
+        kadd = (in && !(mask && mask[(kb0 + tid) * a.mk] == 0.f)) ? 0.f : -INFINITY;
+      }
       typename F::Frag qf[F::NKS], of[F::NKS];
       load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
       load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
-      float mrow = 0.f, irow = 0.f, drow = 0.f;
+      // queries past the end: mrow = +inf and irow = 0 give dS = 0 exactly
+      float mrow = INFINITY, irow = 0.f, drow = 0.f;
       if (qok) {
         const int64_t si = (b * a.stb + qi * a.stq) * a.H + h;
         mrow = a.st_max[si];
         irow = a.st_inv[si];
         drow = gr.Dsum[si];
+        if (mrow < 0.5f * kMaskLogit) irow = 0.f;
       }
       __syncthreads();
       stK.store(sK, sKt, tid);
       stV.store(sV, nullptr, tid);
       if (bi == 0 && bias) stB.store(sB, bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
-      if (tid < KB) sMk[tid] = mkv;
+      if (tid < KB) sKa[tid] = kadd;
       __syncthreads();
-      const int klim = a.Lk - kb0 < KB ? (int)(a.Lk - kb0) : KB;
-      // dS = P (dP - D) for valid, unmasked keys (selected, so that values of
-      // discarded lanes never reach the sums)
+      // dS = P (dP - D); exactly 0 for masked keys, keys past the end and
+      // queries past the end (see kadd, mrow, irow)
       f32x4 ds[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -453,12 +601,11 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_kernel(AttnCore a, AttnGrad g
         const f32x4 sv = mfma_d<T, D>(kf, qf);
         const f32x4 dp = mfma_d<T, D>(vf, of);
         const f32x4 bv = bias ? *(const f32x4*)(sB + qloc * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
-        const f32x4 mk = *(const f32x4*)(sMk + 16 * t + 4 * lg);
+        const f32x4 ka = *(const f32x4*)(sKa + 16 * t + 4 * lg);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float x = fmaf(sv[i], scale_log2, bv[i]);
-          const float r = exp2_hw(x - mrow) * irow * (dp[i] - drow);
-          ds[t][i] = (qok && 16 * t + 4 * lg + i < klim && mk[i] != 0.f) ? r : 0.f;
+          const float x = fmaf(sv[i], scale_log2, bv[i]) + ka[i];
+          ds[t][i] = exp2_hw(x - mrow) * irow * (dp[i] - drow);
         }
         dbacc[t] = dbacc[t] + ds[t];
       }
@@ -548,13 +695,18 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
       const T* V = (const T*)a.v + b * a.sb + h * D;
       const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
       const bool kmasked = kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
+      // a masked key's logit is the replacement value, a key past the end
+      // (its lane's results are discarded) gets -inf so that P stays finite
+      const bool krep = kmasked || !kok;
+      const float xrep = kok ? kMaskLogit : -INFINITY;
       // every global load of the stage first, then the LDS stores
       RowsStage<T, D, true> stQ, stO;
       BiasStage stB;
       stQ.load(Q, a.sp, qb0, a.Lq, tid);
       stO.load(DO, a.osp, qb0, a.Lq, tid);
       if (bi == 0 && bias) stB.load(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
-      float mv = 0.f, iv = 0.f, dvv = 0.f;
+      // queries past the end: m = +inf and 1/l = 0 give P = dS = 0 exactly
+      float mv = INFINITY, iv = 0.f, dvv = 0.f;
       if (tid < KB && qb0 + tid < a.Lq) {
         const int64_t si = (b * a.stb + (qb0 + tid) * a.stq) * a.H + h;
         mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
@@ -568,7 +720,6 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
       if (bi == 0 && bias) stB.store(sB, bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
       if (tid < KB) { sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv; }
       __syncthreads();
-      const int qlim = a.Lq - qb0 < KB ? (int)(a.Lq - qb0) : KB;   // queries of the tile in range
       f32x4 P[4], DS[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -584,12 +735,12 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float x = fmaf(sv[i], scale_log2, bv[i]);
-          x = kmasked ? kMaskLogit : x;
+          x = krep ? xrep : x;
           const float p = exp2_hw(x - m4[i]) * i4[i];
-          const float r = p * (dp[i] - d4[i]);
-          const bool ok = kok && 16 * t + 4 * lg + i < qlim;
-          P[t][i] = ok ? p : 0.f;
-          DS[t][i] = (ok && !kmasked) ? r : 0.f;
+          P[t][i] = p;
+          // a masked key's logit is a constant: no logit gradient (its
+          // probability still weighs V in wholly masked rows)
+          DS[t][i] = krep ? 0.f : p * (dp[i] - d4[i]);
         }
       }
 #pragma unroll
@@ -640,13 +791,34 @@ template <typename T, int D>
 static void launch_fwd(const Ctx& c, const AttnCore& a) {
   static const std::string nm = kname<T, D>("attn_fwd_kernel");
   const int64_t nq = a.q_count < 0 ? a.Lq : a.q_count;
+  // vector bias loads: 16-byte aligned rows and whole 64-wide tiles along the unit stride
+  const bool al = ((uintptr_t)a.bias % 16) == 0 && a.bh % 4 == 0;
+  const int bm = !a.bias                                                      ? BIAS_NONE
+                 : (a.bk == 1 && al && a.bq % 4 == 0 && a.Lk % 64 == 0)         ? BIAS_ROWS
+                 : (a.bq == 1 && al && a.bk % 4 == 0 && a.q_begin % 4 == 0 &&
+                    (a.q_begin + nq) <= a.Lq && nq % 64 == 0)                   ? BIAS_COLS
+                                                                                : BIAS_STRIDED;
   dim3 grid((unsigned)((nq + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
   const float sl2 = kLog2e / sqrtf((float)D);
   const double bh = (double)a.nbatch * a.H;
   const double flops = 4.0 * bh * nq * a.Lk * D;
   const double bytes = bh * ((double)nq * D * 4 + (double)a.Lk * D * 2) * sizeof(T) +
                        (a.bias ? (double)a.H * nq * a.Lk * 4.0 : 0.0) + bh * nq * 8.0;
-  EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D>), grid, dim3(256), 0, c.stream, a, sl2);
+  switch (bm) {
+    case BIAS_NONE:
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_NONE>), grid, dim3(256), 0, c.stream, a, sl2);
+      break;
+    case BIAS_ROWS:
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_ROWS>), grid, dim3(256), 0, c.stream, a, sl2);
+      break;
+    case BIAS_COLS:
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_COLS>), grid, dim3(256), 0, c.stream, a, sl2);
+      break;
+    default:
+      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_STRIDED>), grid, dim3(256), 0, c.stream, a,
+                 sl2);
+      break;
+  }
 }
 
 template <typename T>

@@ -127,8 +127,9 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dg
                       T* dgpre, int64_t ld_dg, float* D);
 
 // Triangle multiplication projections, forward: FP32 raw[p][4*ch + cz] (ap | ag | bp | bg | g)
-// -> a[c][p], b[c][p] (channel-major, masked, gated), FP32 g[p][cz] = sigmoid(raw g).
-// a and b have channel stride ld_ab (>= P; pointers may be offset into larger tensors).
+// -> a[c][p], b[c][p] (channel-major, masked, gated), and, when g is not null,
+// FP32 g[p][cz] = sigmoid(raw g).  a and b have channel stride ld_ab (>= P;
+// pointers may be offset into larger tensors).
 template <typename T>
 evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* raw, const float* mask,
                          T* a, T* b, int64_t ld_ab, float* g);
@@ -136,10 +137,11 @@ evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* r
 template <typename T>
 evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const float* raw,
                              const float* mask, const float* da, const float* db, T* draw);
-// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g)  (t, g FP32).
+// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g)  (t, g FP32;
+// g[p * ld_g + n]).
 template <typename T, typename X = T>
 evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
-                             const float* g, T* dt, T* draw);
+                             const float* g, int64_t ld_g, T* dt, T* draw);
 
 // Outer-product-mean input gradients from split-K partials:
 //   dab[s][i][off + p] = mask[s][i] * sum_k part[k][s][i][p]   (part FP32 [nsplit][S][R][ch],

@@ -1166,12 +1166,70 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int 
   if (row < rows && (col % hd) == 0) D[row * H + col / hd] = contrib;
 }
 
+// Vector form: a lane takes 8 consecutive columns of one head (hd / 8 = LPH
+// lanes per head, consecutive and aligned inside the wave).
+template <typename T, int LPH>
+__global__ __launch_bounds__(256) void gate_bwd_vec_kernel(int64_t rows, int H, int hd, const float* dgo,
+                                                           int64_t ld_dgo, const T* o, int64_t ld_o,
+                                                           const T* g, int64_t ld_g, T* dctx,
+                                                           int64_t ld_dctx, T* dgp, int64_t ld_dg,
+                                                           float* D) {
+  const int HC8 = H * hd / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = e / HC8;
+  const int col = (int)(e % HC8) * 8;
+  float contrib = 0.f;
+  if (row < rows) {
+    float dy[8], ov[8], gv[8], dc[8], dg[8];
+    ld8(dgo + row * ld_dgo + col, dy);
+    ld8(o + row * ld_o + col, ov);
+    ld8(g + row * ld_g + col, gv);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      dc[i] = dy[i] * gv[i];
+      dg[i] = dy[i] * ov[i] * gv[i] * (1.f - gv[i]);
+      contrib += to_f32(from_f32<T>(dc[i])) * ov[i];
+    }
+    st8(dctx + row * ld_dctx + col, dc);
+    st8(dgp + row * ld_dg + col, dg);
+  }
+  contrib = group_sum<LPH>(contrib);
+  if (row < rows && (col % hd) == 0) D[row * H + col / hd] = contrib;
+}
+
 template <typename T>
 evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
                       const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
                       T* dgpre, int64_t ld_dg, float* D) {
   if (c.dry || rows == 0) return EVO_OK;
   const int64_t n = rows * H * hd;
+  const bool vec = (hd == 8 || hd == 16 || hd == 32 || hd == 64) && ld_dgo % 8 == 0 && ld_o % 8 == 0 && ld_g % 8 == 0 &&
+                   ld_dctx % 8 == 0 && ld_dg % 8 == 0 && aligned16(dgo) && aligned16(o) && aligned16(g) &&
+                   aligned16(dctx) && aligned16(dgpre);
+  if (vec) {
+    const int64_t n8 = n / 8;
+    const dim3 grid((unsigned)((n8 + 255) / 256));
+    const double bytes = (double)n * (4.0 + 4 * sizeof(T)) + rows * H * 4.0;
+    switch (hd / 8) {
+      case 1:
+        EVO_LAUNCH(EVO_KNAME("gate_bwd_vec_kernel", T), 0.0, bytes, (gate_bwd_vec_kernel<T, 1>), grid, dim3(256), 0,
+                   c.stream, rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
+        break;
+      case 2:
+        EVO_LAUNCH(EVO_KNAME("gate_bwd_vec_kernel", T), 0.0, bytes, (gate_bwd_vec_kernel<T, 2>), grid, dim3(256), 0,
+                   c.stream, rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
+        break;
+      case 4:
+        EVO_LAUNCH(EVO_KNAME("gate_bwd_vec_kernel", T), 0.0, bytes, (gate_bwd_vec_kernel<T, 4>), grid, dim3(256), 0,
+                   c.stream, rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
+        break;
+      default:
+        EVO_LAUNCH(EVO_KNAME("gate_bwd_vec_kernel", T), 0.0, bytes, (gate_bwd_vec_kernel<T, 8>), grid, dim3(256), 0,
+                   c.stream, rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
+        break;
+    }
+    return check_launch("gate_bwd");
+  }
   EVO_LAUNCH(EVO_KNAME("gate_bwd_kernel", T), 0.0, (double)n * (4.0 + 4 * sizeof(T)) + rows * H * 4.0, (gate_bwd_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                      rows, H, hd, dgo, ld_dgo, o, ld_o, g, ld_g, dctx, ld_dctx, dgpre, ld_dg, D);
   return check_launch("gate_bwd");
@@ -1230,6 +1288,7 @@ evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* r
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
   EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * (16.0 + 2 * sizeof(T)), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
   EVO_TRY(check_launch("trimul_proj"));
+  if (!g) return EVO_OK;
   const int64_t n = P * cz;
   EVO_LAUNCH("sigmoid_cols_kernel", 0.0, (double)n * 8.0, sigmoid_cols_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
                      P, ch, cz, raw, g);
@@ -1283,24 +1342,24 @@ evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const floa
 
 template <typename T, typename X>
 __global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch, int cz, const X* dz,
-                                                              const float* t, const float* g, T* dt,
-                                                              T* draw) {
+                                                              const float* t, const float* g, int64_t ld_g,
+                                                              T* dt, T* draw) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= P * cz) return;
   const int64_t p = e / cz;
   const int n = (int)(e % cz);
-  const float d = to_f32(dz[e]), gv = g[e], tv = t[e];
+  const float d = to_f32(dz[e]), gv = g[p * ld_g + n], tv = t[e];
   dt[e] = from_f32<T>(d * gv);
   draw[p * (4 * ch + cz) + 4 * ch + n] = from_f32<T>(d * tv * gv * (1.f - gv));
 }
 
 template <typename T, typename X>
 evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
-                             const float* g, T* dt, T* draw) {
+                             const float* g, int64_t ld_g, T* dt, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   const int64_t n = P * cz;
   EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", X), 0.0, (double)n * (sizeof(X) + 8.0 + 2 * sizeof(T)), (trimul_gate_bwd_kernel<T, X>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     c.stream, P, ch, cz, dz, t, g, dt, draw);
+                     c.stream, P, ch, cz, dz, t, g, ld_g, dt, draw);
   return check_launch("trimul_gate_bwd");
 }
 
@@ -1401,7 +1460,7 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const float*,           \
                                            const float*, const float*, const float*, T*);          \
   template evo_status_t trimul_gate_bwd<T, T>(const Ctx&, int64_t, int, int, const T*,           \
-                                              const float*, const float*, T*, T*);
+                                              const float*, const float*, int64_t, T*, T*);
 
 EVO_INST(float)
 EVO_INST(bf16)
@@ -1414,7 +1473,7 @@ template evo_status_t ln_fwd_rows<float, bf16>(const Ctx&, const float*, int64_t
 template evo_status_t ln_rowproj<float, bf16>(const Ctx&, const float*, int64_t, int, const float*,
                                               const float*, float, const float*, int, float*);
 template evo_status_t trimul_gate_bwd<bf16, float>(const Ctx&, int64_t, int, int, const float*, const float*,
-                                                   const float*, bf16*, bf16*);
+                                                   const float*, int64_t, bf16*, bf16*);
 template evo_status_t convert_elems<float, bf16>(const Ctx&, const float*, bf16*, int64_t);
 template evo_status_t convert_elems<bf16, float>(const Ctx&, const bf16*, float*, int64_t);
 template evo_status_t convert_elems<float, float>(const Ctx&, const float*, float*, int64_t);

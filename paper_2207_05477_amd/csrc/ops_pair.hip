@@ -272,9 +272,10 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
 // ============================================================== triangle multiplication
 template <typename T>
 struct TriSaved {
-  // raw (projection output), g (output gate) and x (contraction output) feed
-  // only elementwise work and LayerNorm: FP32 whatever the compute type.
-  T* y; float* mean; float* rstd; float* raw; T* a; T* b; float* g; float* x; T* xn; float* mean2;
+  // raw (projection output; its last cz columns hold the output gate after
+  // the sigmoid) and x (contraction output) feed only elementwise work and
+  // LayerNorm: FP32 whatever the compute type.
+  T* y; float* mean; float* rstd; float* raw; T* a; T* b; float* x; T* xn; float* mean2;
   float* rstd2;
   void carve(Arena& ar, const evo_trimul_desc_t& d) {
     const int64_t P = d.n_res * d.n_res, ch = d.c_hidden, cz = d.c_z;
@@ -284,7 +285,6 @@ struct TriSaved {
     raw = ar.take_n<float>(P * (4 * ch + cz));
     a = ar.take_n<T>(P * ch);
     b = ar.take_n<T>(P * ch);
-    g = ar.take_n<float>(P * cz);
     x = ar.take_n<float>(P * ch);
     xn = ar.take_n<T>(P * ch);
     mean2 = ar.take_n<float>(P);
@@ -337,7 +337,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
     gp.epi.bias = b_p;
     EVO_TRY(gemm<T>(c, gp));
     EVO_TRY(trimul_proj<T>(c, CR, (int)ch, (int)cz, raw, mask ? mask + p0 : nullptr, a + p0, b + p0, P,
-                           g + p0 * cz));
+                           g + p0 * cz));   // (raw is per chunk: the gate is kept apart)
   }
   float* mean2 = mean;
   float* rstd2 = rstd;
@@ -401,9 +401,11 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     g.B = op_rowmajor(wt_p, cz);
     g.epi = epi_rowmajor(S.raw, NP, true);
     g.epi.bias = b_p;
+    g.epi.act = ACT_SIGMOID;   // output gate columns: sigmoid in the epilogue
+    g.epi.act_n0 = 4 * ch;
     EVO_TRY(gemm<T>(c, g));
   }
-  EVO_TRY(trimul_proj<T>(c, P, (int)ch, (int)cz, S.raw, mask, S.a, S.b, P, S.g));
+  EVO_TRY(trimul_proj<T>(c, P, (int)ch, (int)cz, S.raw, mask, S.a, S.b, P, nullptr));
   {  // per-channel contraction, channel-major operands [ch][R][R]
     ProfTag t_("contract");
     GemmArgs g;
@@ -427,7 +429,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   g.B = op_rowmajor(wt_o, ch);
   epi_out<X>(g.epi, zout, cz);
   g.epi.bias = w.b_o;
-  g.epi.gate = S.g; g.epi.g_m = cz; g.epi.g_n = 1; g.epi.gate_f32 = 1;
+  g.epi.gate = S.raw + 4 * ch; g.epi.g_m = NP; g.epi.g_n = 1; g.epi.gate_f32 = 1;
   epi_resid<X>(g.epi, z, cz, 1);
   return gemm<T>(c, g);
 }
@@ -471,7 +473,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
       g.epi.bias = w.b_o;
       EVO_TRY(gemm<T>(c, g));
     }
-    EVO_TRY((trimul_gate_bwd<T, X>(c, P, (int)ch, (int)cz, dzo, t, S.g, dt, draw)));
+    EVO_TRY((trimul_gate_bwd<T, X>(c, P, (int)ch, (int)cz, dzo, t, S.raw + 4 * ch, NP, dt, draw)));
   }
   int off0 = 0, ncz = (int)cz;
   float* obo[1] = {dw.b_o};
