@@ -510,7 +510,7 @@ template <typename T, int D> struct DqGroup {
   static constexpr int GM = (D <= 16 ? 8 : 4) / (sizeof(T) == 2 ? 1 : 2);
 };
 
-template <typename T, int D>
+template <typename T, int D, int BM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void attn_bwd_dq_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                           float scale) {
   using F = DF<T, D>;
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const int64_t qi = q0 + qloc;
   const bool qok = qi < a.Lq;
   const bool dbias = gr.dbias_part != nullptr;
-  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
+  const float* bias = BM != BIAS_NONE ? a.bias + h * a.bh : nullptr;
   float* dbp = dbias ? gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk : nullptr;
 
   zero_pad_rows<T, D>(sKt, tid);
@@ -557,10 +557,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
       // every global load of the stage first, then the LDS stores
       RowsStage<T, D, true> stK;
       RowsStage<T, D, false> stV;
-      BiasStage stB;
+      LogBiasStage<BM> stB;
       stK.load(K, a.sp, kb0, a.Lk, tid);
       stV.load(V, a.sp, kb0, a.Lk, tid);
-      if (bi == 0 && bias) stB.load(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
+      if (BM != BIAS_NONE && bi == 0) stB.load(bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
       // Per-key addend of the logits: 0 for a valid key, -inf for a masked key
       // or one past the end, whose probability is then exactly 0.  (In the
       // forward a masked key has the replacement logit, which gives it
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
       __syncthreads();
       stK.store(sK, sKt, tid);
       stV.store(sV, nullptr, tid);
-      if (bi == 0 && bias) stB.store(sB, bias, a.bq, a.bk, q0, a.Lq, kb0, a.Lk, tid);
+      if (BM != BIAS_NONE && bi == 0) stB.store(sB, tid);
       if (tid < KB) sKa[tid] = kadd;
       __syncthreads();
       // dS = P (dP - D); exactly 0 for masked keys, keys past the end and
@@ -600,7 +600,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         load_dfrag<T, D>(sV + (16 * t + lr) * F::DP, lg, true, vf);
         const f32x4 sv = mfma_d<T, D>(kf, qf);
         const f32x4 dp = mfma_d<T, D>(vf, of);
-        const f32x4 bv = bias ? *(const f32x4*)(sB + qloc * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 bv = BM != BIAS_NONE ? *(const f32x4*)(sB + qloc * BP + 16 * t + 4 * lg)
+                                         : f32x4{0.f, 0.f, 0.f, 0.f};
         const f32x4 ka = *(const f32x4*)(sKa + 16 * t + 4 * lg);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -653,8 +654,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 // bias tile saves.
 template <int D> struct DkvGroup { static constexpr int GM = 1; };
 
-template <typename T, int D>
-__global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
+template <typename T, int D, int BM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                             float scale, int32_t group) {
   using F = DF<T, D>;
   constexpr int GM = DkvGroup<D>::GM;
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
   const int64_t k0 = (int64_t)blockIdx.x * 64;
   const int64_t key = k0 + kl;
   const bool kok = key < a.Lk;
-  const float* bias = a.bias ? a.bias + h * a.bh : nullptr;
+  const float* bias = BM != BIAS_NONE ? a.bias + h * a.bh : nullptr;
 
   zero_pad_rows<T, D>(sQt, tid);
   zero_pad_rows<T, D>(sOt, tid);
@@ -701,10 +702,10 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
       const float xrep = kok ? kMaskLogit : -INFINITY;
       // every global load of the stage first, then the LDS stores
       RowsStage<T, D, true> stQ, stO;
-      BiasStage stB;
+      LogBiasStage<BM> stB;
       stQ.load(Q, a.sp, qb0, a.Lq, tid);
       stO.load(DO, a.osp, qb0, a.Lq, tid);
-      if (bi == 0 && bias) stB.load(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
+      if (BM != BIAS_NONE && bi == 0) stB.load(bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
       // queries past the end: m = +inf and 1/l = 0 give P = dS = 0 exactly
       float mv = INFINITY, iv = 0.f, dvv = 0.f;
       if (tid < KB && qb0 + tid < a.Lq) {
@@ -717,7 +718,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
       __syncthreads();
       stQ.store(sQ, sQt, tid);
       stO.store(sO, sOt, tid);
-      if (bi == 0 && bias) stB.store(sB, bias, a.bk, a.bq, k0, a.Lk, qb0, a.Lq, tid);
+      if (BM != BIAS_NONE && bi == 0) stB.store(sB, tid);
       if (tid < KB) { sM[tid] = mv; sI[tid] = iv; sD[tid] = dvv; }
       __syncthreads();
       f32x4 P[4], DS[4];
@@ -728,7 +729,8 @@ __global__ __launch_bounds__(256) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad
         load_dfrag<T, D>(sO + (16 * t + lr) * F::DP, lg, true, of);
         const f32x4 sv = mfma_d<T, D>(qf, kf);
         const f32x4 dp = mfma_d<T, D>(of, vf);
-        const f32x4 bv = bias ? *(const f32x4*)(sB + kl * BP + 16 * t + 4 * lg) : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 bv = BM != BIAS_NONE ? *(const f32x4*)(sB + kl * BP + 16 * t + 4 * lg)
+                                         : f32x4{0.f, 0.f, 0.f, 0.f};
         const f32x4 m4 = *(const f32x4*)(sM + 16 * t + 4 * lg);
         const f32x4 i4 = *(const f32x4*)(sI + 16 * t + 4 * lg);
         const f32x4 d4 = *(const f32x4*)(sD + 16 * t + 4 * lg);
@@ -787,38 +789,41 @@ static std::string kname(const char* k) {
   return std::string(k) + "<" + tname<T>() + ", " + std::to_string(D) + ">";
 }
 
+// Bias tile layout of a launch whose tiles have rows [r_begin, r_begin + nrows)
+// and columns [0, ncols) of a bias with strides (sr, sc): vector loads need
+// 16-byte aligned vectors and whole 64-wide tiles along the unit stride.
+static int bias_mode(const float* bias, int64_t bh, int64_t sr, int64_t sc, int64_t r_begin, int64_t nrows,
+                     int64_t ncols) {
+  if (!bias) return BIAS_NONE;
+  const bool al = ((uintptr_t)bias % 16) == 0 && bh % 4 == 0;
+  if (sc == 1 && al && sr % 4 == 0 && ncols % 64 == 0) return BIAS_ROWS;
+  if (sr == 1 && al && sc % 4 == 0 && r_begin % 4 == 0 && nrows % 64 == 0) return BIAS_COLS;
+  return BIAS_STRIDED;
+}
+
+#define EVO_BIAS_SWITCH(bm, KERNEL, ...)                \
+  switch (bm) {                                         \
+    case BIAS_NONE: KERNEL(BIAS_NONE, __VA_ARGS__); break;  \
+    case BIAS_ROWS: KERNEL(BIAS_ROWS, __VA_ARGS__); break;  \
+    case BIAS_COLS: KERNEL(BIAS_COLS, __VA_ARGS__); break;  \
+    default: KERNEL(BIAS_STRIDED, __VA_ARGS__); break;  \
+  }
+
 template <typename T, int D>
 static void launch_fwd(const Ctx& c, const AttnCore& a) {
   static const std::string nm = kname<T, D>("attn_fwd_kernel");
   const int64_t nq = a.q_count < 0 ? a.Lq : a.q_count;
-  // vector bias loads: 16-byte aligned rows and whole 64-wide tiles along the unit stride
-  const bool al = ((uintptr_t)a.bias % 16) == 0 && a.bh % 4 == 0;
-  const int bm = !a.bias                                                      ? BIAS_NONE
-                 : (a.bk == 1 && al && a.bq % 4 == 0 && a.Lk % 64 == 0)         ? BIAS_ROWS
-                 : (a.bq == 1 && al && a.bk % 4 == 0 && a.q_begin % 4 == 0 &&
-                    (a.q_begin + nq) <= a.Lq && nq % 64 == 0)                   ? BIAS_COLS
-                                                                                : BIAS_STRIDED;
+  const int bm = bias_mode(a.bias, a.bh, a.bq, a.bk, a.q_begin, nq, a.Lk);
   dim3 grid((unsigned)((nq + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
   const float sl2 = kLog2e / sqrtf((float)D);
   const double bh = (double)a.nbatch * a.H;
   const double flops = 4.0 * bh * nq * a.Lk * D;
   const double bytes = bh * ((double)nq * D * 4 + (double)a.Lk * D * 2) * sizeof(T) +
                        (a.bias ? (double)a.H * nq * a.Lk * 4.0 : 0.0) + bh * nq * 8.0;
-  switch (bm) {
-    case BIAS_NONE:
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_NONE>), grid, dim3(256), 0, c.stream, a, sl2);
-      break;
-    case BIAS_ROWS:
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_ROWS>), grid, dim3(256), 0, c.stream, a, sl2);
-      break;
-    case BIAS_COLS:
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_COLS>), grid, dim3(256), 0, c.stream, a, sl2);
-      break;
-    default:
-      EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BIAS_STRIDED>), grid, dim3(256), 0, c.stream, a,
-                 sl2);
-      break;
-  }
+#define EVO_FWD(BMV, _) \
+  EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BMV>), grid, dim3(256), 0, c.stream, a, sl2)
+  EVO_BIAS_SWITCH(bm, EVO_FWD, 0)
+#undef EVO_FWD
 }
 
 template <typename T>
@@ -864,14 +869,24 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   const double b2 = bh * ((double)a.Lq * D * 2 + (double)a.Lk * D * 4) * sizeof(T) + bh * a.Lq * 12.0 +
                     (a.bias ? a.H * ll * 4.0 : 0.0);
   dim3 g1((unsigned)((a.Lq + 63) / 64), (unsigned)a.H, (unsigned)ngroups);
-  EVO_LAUNCH(n1.c_str(), f1, b1, (attn_bwd_dq_kernel<T, D>), g1, dim3(256), lds, c.stream, a, g, sl2, sc);
+  // bias tiles: queries x keys in the dQ kernel, keys x queries in the dK/dV kernel
+  const int bm1 = bias_mode(a.bias, a.bh, a.bq, a.bk, 0, a.Lq, a.Lk);
+  const int bm2 = bias_mode(a.bias, a.bh, a.bk, a.bq, 0, a.Lk, a.Lq);
+#define EVO_DQ(BMV, _) \
+  EVO_LAUNCH(n1.c_str(), f1, b1, (attn_bwd_dq_kernel<T, D, BMV>), g1, dim3(256), lds, c.stream, a, g, sl2, sc)
+  EVO_BIAS_SWITCH(bm1, EVO_DQ, 0)
+#undef EVO_DQ
   EVO_TRY(check_launch("attn_bwd_dq"));
   // batches per dK/dV workgroup: the bias tile is shared across them (one batch when there is no bias)
   int32_t kgroup = a.bias ? DkvGroup<D>::GM : 1;
   const int64_t kblocks = (a.Lk + 63) / 64;
   while (kgroup > 1 && kblocks * a.H * ((a.nbatch + kgroup - 1) / kgroup) < 512) kgroup /= 2;
   dim3 g2((unsigned)kblocks, (unsigned)a.H, (unsigned)((a.nbatch + kgroup - 1) / kgroup));
-  EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D>), g2, dim3(256), 0, c.stream, a, g, sl2, sc, kgroup);
+#define EVO_DKDV(BMV, _)                                                                                  \
+  EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D, BMV>), g2, dim3(256), 0, c.stream, a, g, sl2, sc, \
+             kgroup)
+  EVO_BIAS_SWITCH(bm2, EVO_DKDV, 0)
+#undef EVO_DKDV
   return check_launch("attn_bwd_dkdv");
 }
 
