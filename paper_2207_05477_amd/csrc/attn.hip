@@ -7,7 +7,11 @@
 // single query; the online softmax (exp2 domain, FP32 statistics) needs only
 // a 4-lane reduction, and the context O^T = V^T P^T is accumulated with P
 // taken straight from registers.  Masked keys get the logit kMaskLogit
-// (replacement); keys past the end get -inf.
+// (replacement); keys past the end get -inf; both through a per-key
+// multiplier and addend, two operations per logit.  The running maximum moves
+// lazily (only by more than kLazy), and in BF16 the row sums come out of the
+// context product as one more MFMA tile.  The bias tile layout (which stride
+// is 1, whether vector loads apply) is a template parameter fixed per launch.
 //
 // Backward: probabilities are recomputed from the saved row max and
 // 1/row-sum.  One kernel produces dQ and, summed over a group of batches
@@ -188,69 +192,7 @@ struct RowsStage {
   }
 };
 
-// Bias tile in LDS, log2 domain: sb[r * BP + c] = log2(e) * bias[(r0 + r) * sr + (c0 + c) * sc]
-// for rows r < 64 and columns c < 64 in range (0 elsewhere); the loads run
-// along whichever of the two strides is 1.  Register staged like RowsStage.
-constexpr int BP = 68;
-struct BiasStage {
-  f32x4 v[4];
-  // Element (r, c) of the tile for slot `it` of thread `tid` (a lane covers 4
-  // consecutive elements along the unit-stride axis):
-  //   sc == 1: row r = e >> 4, columns c = 4 (e & 15) .. + 3;
-  //   sr == 1: column c = 16 it + (tid & 15), rows r = 4 (tid >> 4) .. + 3, so
-  //            that the 16 lanes of a group store 16 consecutive columns of one
-  //            row (transposing stores without bank conflicts).
-  EVO_DEV void load(const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend, int64_t c0,
-                    int64_t cend, int tid) {
-    if (sc != 1 && sr != 1) return;   // strided both ways: read in store()
-    const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
-    const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
-    const int64_t so = sc == 1 ? sr : sc;   // stride between the vectors
-    const int nvec = sc == 1 ? nr : nc, nlen = sc == 1 ? nc : nr;
-    const float* base = bias + r0 * sr + c0 * sc;
-    const bool vec = (nlen == 64) && ((((uintptr_t)base) | (uintptr_t)(so * 4)) % 16 == 0);
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int e = tid + 256 * it;
-      const int av = sc == 1 ? e >> 4 : 16 * it + (tid & 15);   // vector index (row or column)
-      const int l = sc == 1 ? (e & 15) * 4 : (tid >> 4) * 4;    // offset along the vector
-      v[it] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (av < nvec) {
-        const float* src = base + av * so + l;
-        if (vec) {
-          v[it] = *(const f32x4*)src;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) v[it][i] = l + i < nlen ? src[i] : 0.f;
-        }
-      }
-    }
-  }
-  EVO_DEV void store(float* sb, const float* bias, int64_t sr, int64_t sc, int64_t r0, int64_t rend,
-                     int64_t c0, int64_t cend, int tid) const {
-    if (sc == 1) {
-#pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int e = tid + 256 * it;
-        *(f32x4*)(sb + (e >> 4) * BP + (e & 15) * 4) = v[it] * kLog2e;
-      }
-    } else if (sr == 1) {
-#pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int c = 16 * it + (tid & 15), r = (tid >> 4) * 4;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[it][i] * kLog2e;
-      }
-    } else {
-      const int nr = rend - r0 < 64 ? (int)(rend - r0) : 64;
-      const int nc = cend - c0 < 64 ? (int)(cend - c0) : 64;
-      for (int e = tid; e < 64 * 64; e += 256) {
-        const int c = e >> 6, r = e & 63;
-        sb[r * BP + c] = (r < nr && c < nc) ? bias[(c0 + c) * sc + (r0 + r) * sr] * kLog2e : 0.f;
-      }
-    }
-  }
-};
+constexpr int BP = 68;   // LDS row pitch of the bias tile (floats)
 
 template <typename T, int D>
 EVO_DEV void zero_pad_rows(T* dst_t, int tid) {
@@ -283,12 +225,17 @@ EVO_DEV void key_fold(const float* mask, int64_t mk, int64_t k, int64_t kend, fl
 // scalar loads.
 enum { BIAS_NONE = 0, BIAS_ROWS = 1, BIAS_COLS = 2, BIAS_STRIDED = 3 };
 
-// Bias tile (rows = queries, columns = keys) in the log2 domain:
+// 64 x 64 bias tile in LDS, log2 domain:
 // sb[r * BP + c] = log2(e) * bias[(r0 + r) * sr + (c0 + c) * sc].  Loads clamp
 // rows and columns into range (out-of-range entries are finite copies, never
 // used: their keys get -inf, their queries are discarded), so no lane
-// zero-fills or branches per element.  Register staged; element mapping as in
-// BiasStage (BIAS_ROWS like sc == 1, the other layouts like sr == 1).
+// zero-fills or branches per element.  Register staged like RowsStage: load()
+// issues the global loads, store() writes LDS.  Element (r, c) of slot `it` of
+// thread `tid` (4 consecutive elements along the unit-stride axis per slot):
+//   BIAS_ROWS: row r = e >> 4 (e = tid + 256 it), columns c = 4 (e & 15) .. + 3;
+//   otherwise: column c = 16 it + (tid & 15), rows r = 4 (tid >> 4) .. + 3, so
+//              that the 16 lanes of a group store 16 consecutive columns of
+//              one row (transposing stores without bank conflicts).
 template <int BM>
 struct LogBiasStage {
   f32x4 v[4];

@@ -249,12 +249,14 @@ __global__ __launch_bounds__(256) void rowproj_dw_kernel(const T* __restrict__ x
 // Vectorised backward (C % 8 == 0, C <= 512, H <= HM): LPR = C / 8 lanes per
 // row, each owning 8 channels (16-byte accesses).  A block owns RB rows; their
 // dout values are staged in LDS as [row][HM] (coalesced loads along the rows),
-// so a lane reads a row's HM values with vector broadcasts.
-constexpr int RPV_RB = 256;
-template <int HM>
+// so a lane reads a row's HM values with vector broadcasts.  A lane's global
+// loads of several rows are issued together before they are used.
+constexpr int RPV_RB = 256;   // rows per block of the weight-gradient kernel
+constexpr int RPX_RB = 64;    // rows per block of the input-gradient kernel
+template <int HM, int RB>
 EVO_DEV void stage_dout_rows(const float* dout, int64_t rows, int64_t r0, int H, float* sd, int tid) {
-  for (int e = tid; e < HM * RPV_RB; e += 256) {
-    const int h = e / RPV_RB, rr = e - h * RPV_RB;
+  for (int e = tid; e < HM * RB; e += 256) {
+    const int h = e / RB, rr = e - h * RB;
     sd[rr * HM + h] = (h < H && r0 + rr < rows) ? dout[(int64_t)h * rows + r0 + rr] : 0.f;
   }
 }
@@ -264,20 +266,31 @@ template <int LPR, int HM>
 __global__ __launch_bounds__(256) void rowproj_dx_vec_kernel(int64_t rows, int C, const float* __restrict__ W,
                                                              int H, const float* __restrict__ dout, float* dx,
                                                              int accumulate) {
-  __shared__ __attribute__((aligned(16))) float sd[RPV_RB * HM];
-  constexpr int RPI = 256 / LPR;
+  __shared__ __attribute__((aligned(16))) float sd[RPX_RB * HM];
+  constexpr int RPI = 256 / LPR, NR = RPX_RB / RPI;   // rows per block iteration, rows per lane
   const int tid = threadIdx.x, l = tid & (LPR - 1);
   const int c0 = l * 8;
   const bool cok = c0 < C;
-  const int64_t r0 = (int64_t)blockIdx.x * RPV_RB;
-  stage_dout_rows<HM>(dout, rows, r0, H, sd, tid);
+  const int64_t r0 = (int64_t)blockIdx.x * RPX_RB;
+  stage_dout_rows<HM, RPX_RB>(dout, rows, r0, H, sd, tid);
   float w[8][HM];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int h = 0; h < HM; ++h) w[i][h] = (cok && h < H) ? W[(c0 + i) * H + h] : 0.f;
+  float prev[NR][8];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int64_t row = r0 + tid / LPR + j * RPI;
+    if (accumulate && cok && row < rows) ld8(dx + row * C + c0, prev[j]);
+    else
+#pragma unroll
+      for (int i = 0; i < 8; ++i) prev[j][i] = 0.f;
+  }
   __syncthreads();
-  for (int rr = tid / LPR; rr < RPV_RB; rr += RPI) {
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int rr = tid / LPR + j * RPI;
     const int64_t row = r0 + rr;
     if (row >= rows || !cok) continue;
     float d[HM];
@@ -292,16 +305,9 @@ __global__ __launch_bounds__(256) void rowproj_dx_vec_kernel(int64_t rows, int C
       float t = 0.f;
 #pragma unroll
       for (int h = 0; h < HM; ++h) t += d[h] * w[i][h];
-      o[i] = t;
+      o[i] = t + prev[j][i];
     }
-    float* px = dx + row * C + c0;
-    if (accumulate) {
-      float prev[8];
-      ld8(px, prev);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) o[i] += prev[i];
-    }
-    st8(px, o);
+    st8(dx + row * C + c0, o);
   }
 }
 
@@ -320,27 +326,40 @@ __global__ __launch_bounds__(256) void rowproj_dw_vec_kernel(const T* __restrict
   const int c0 = l * 8;
   const bool cok = c0 < C;
   const int64_t r0 = (int64_t)blockIdx.x * RPV_RB;
-  stage_dout_rows<HM>(dout, rows, r0, H, sd, tid);
+  stage_dout_rows<HM, RPV_RB>(dout, rows, r0, H, sd, tid);
   __syncthreads();
   float acc[8][HM];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int h = 0; h < HM; ++h) acc[i][h] = 0.f;
-  for (int rr = tid / LPR; rr < RPV_RB; rr += RPI) {
-    const int64_t row = r0 + rr;
-    if (row >= rows || !cok) continue;
-    float v[8], d[HM];
-    ld8(x + row * C + c0, v);
+  // rows in batches of NB per lane, loads first; rows past the end read the
+  // last row (in range) and meet dout = 0 staged for them
+  constexpr int NR = RPV_RB / RPI, NB = NR < 4 ? NR : 4;
+  if (cok) {
+    for (int j0 = 0; j0 < NR; j0 += NB) {
+      float v[NB][8];
 #pragma unroll
-    for (int h = 0; h < HM; h += 4) {
-      const f32x4 q = *(const f32x4*)(sd + rr * HM + h);
-      d[h] = q[0]; d[h + 1] = q[1]; d[h + 2] = q[2]; d[h + 3] = q[3];
+      for (int jj = 0; jj < NB; ++jj) {
+        int64_t row = r0 + tid / LPR + (j0 + jj) * RPI;
+        row = row < rows ? row : rows - 1;
+        ld8(x + row * C + c0, v[jj]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) {
+        const int rr = tid / LPR + (j0 + jj) * RPI;
+        float d[HM];
+#pragma unroll
+        for (int h = 0; h < HM; h += 4) {
+          const f32x4 q = *(const f32x4*)(sd + rr * HM + h);
+          d[h] = q[0]; d[h + 1] = q[1]; d[h + 2] = q[2]; d[h + 3] = q[3];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int h = 0; h < HM; ++h) acc[i][h] += v[jj][i] * d[h];
+      }
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-      for (int h = 0; h < HM; ++h) acc[i][h] += v[i] * d[h];
   }
   // lanes l, l + LPR, ... of a wave hold the same channels
 #pragma unroll
@@ -366,7 +385,7 @@ template <typename T, int LPR, int HM>
 static void rowproj_bwd_vec_launch(const Ctx& c, const T* x, int64_t rows, int C, const float* W, int H,
                                    const float* dout, float* dx, bool accumulate, float* part, int64_t nblk) {
   if (dx)
-    EVO_LAUNCH("rowproj_dx_vec_kernel", 2.0 * (double)rows * C * H, (double)rows * C * (accumulate ? 8.0 : 4.0) + (double)H * rows * 4.0, (rowproj_dx_vec_kernel<LPR, HM>), dim3((unsigned)nblk), dim3(256), 0, c.stream,
+    EVO_LAUNCH("rowproj_dx_vec_kernel", 2.0 * (double)rows * C * H, (double)rows * C * (accumulate ? 8.0 : 4.0) + (double)H * rows * 4.0, (rowproj_dx_vec_kernel<LPR, HM>), dim3((unsigned)((rows + RPX_RB - 1) / RPX_RB)), dim3(256), 0, c.stream,
                rows, C, W, H, dout, dx, accumulate ? 1 : 0);
   EVO_LAUNCH(EVO_KNAME("rowproj_dw_vec_kernel", T), 2.0 * (double)rows * C * H, (double)rows * C * sizeof(T) + (double)H * rows * 4.0, (rowproj_dw_vec_kernel<T, LPR, HM>), dim3((unsigned)nblk), dim3(256), 0, c.stream,
              x, rows, C, H, dout, part);

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void ln_rowproj_kernel(const TI* __restrict__ 
 // (8 channels x HM heads) stays in registers while a thread walks RIT rows
 // spaced 256 / LPR apart; the H dot products are summed over the row's lanes by
 // xor shuffles.
-constexpr int LRP_RIT = 8;
+constexpr int LRP_RIT = 4;   // rows per thread: all their loads are issued first
 template <typename TI, typename T, int LPR, int HM>
 __global__ __launch_bounds__(256) void ln_rowproj_vec_kernel(const TI* __restrict__ x, int64_t rows, int C,
                                                              const float* __restrict__ g,
@@ -240,14 +240,20 @@ __global__ __launch_bounds__(256) void ln_rowproj_vec_kernel(const TI* __restric
 #pragma unroll
     for (int h = 0; h < HM; ++h) w[i][h] = (cok && h < H) ? W[(c0 + i) * H + h] : 0.f;
   }
+  float vr[LRP_RIT][8];
+#pragma unroll
+  for (int it = 0; it < LRP_RIT; ++it) {
+    const int64_t row = ((int64_t)blockIdx.x * LRP_RIT + it) * RPI + threadIdx.x / LPR;
+    if (row < rows && cok) ld8(x + row * C + c0, vr[it]);
+    else
+#pragma unroll
+      for (int i = 0; i < 8; ++i) vr[it][i] = 0.f;
+  }
+#pragma unroll
   for (int it = 0; it < LRP_RIT; ++it) {
     const int64_t row = ((int64_t)blockIdx.x * LRP_RIT + it) * RPI + threadIdx.x / LPR;
     const bool ok = row < rows;
-    float v[8];
-    if (ok && cok) ld8(x + row * C + c0, v);
-    else
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = 0.f;
+    const float* v = vr[it];
     float s = 0.f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) s += v[i];
@@ -975,12 +981,21 @@ __global__ __launch_bounds__(256) void colsum_vec_kernel(const T* __restrict__ x
   float s[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) s[i] = 0.f;
+  // four rows per lane in flight: rows past r1 read row r1 - 1 and count 0
   if (c0 < C)
-    for (int64_t r = r0 + tr; r < r1; r += RG) {
-      float v[8];
-      ld8(x + r * ld + c0, v);
+    for (int64_t rb = r0 + tr; rb < r1; rb += 4 * RG) {
+      float v[4][8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) s[i] += v[i];
+      for (int j = 0; j < 4; ++j) {
+        const int64_t r = rb + j * RG;
+        ld8(x + (r < r1 ? r : r1 - 1) * ld + c0, v[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float f = rb + j * RG < r1 ? 1.f : 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = fmaf(v[j][i], f, s[i]);
+      }
     }
 #pragma unroll
   for (int i = 0; i < 8; ++i) red[tr][tc * 8 + i] = s[i];
