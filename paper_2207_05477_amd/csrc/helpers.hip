@@ -273,11 +273,12 @@ __global__ __launch_bounds__(256) void rowproj_dx_vec_kernel(int64_t rows, int C
   const bool cok = c0 < C;
   const int64_t r0 = (int64_t)blockIdx.x * RPX_RB;
   stage_dout_rows<HM, RPX_RB>(dout, rows, r0, H, sd, tid);
-  float w[8][HM];
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int h = 0; h < HM; ++h) w[i][h] = (cok && h < H) ? W[(c0 + i) * H + h] : 0.f;
+  // W staged once per block as [c][HM] (coalesced), the lane's slice read back as vectors
+  __shared__ __attribute__((aligned(16))) float sw[8 * LPR * HM];
+  for (int e = tid; e < 8 * LPR * HM; e += 256) {
+    const int cc = e / HM, h = e - cc * HM;
+    sw[e] = (cc < C && h < H) ? W[cc * H + h] : 0.f;
+  }
   float prev[NR][8];
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
@@ -288,6 +289,14 @@ __global__ __launch_bounds__(256) void rowproj_dx_vec_kernel(int64_t rows, int C
       for (int i = 0; i < 8; ++i) prev[j][i] = 0.f;
   }
   __syncthreads();
+  float w[8][HM];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int h = 0; h < HM; h += 4) {
+      const f32x4 q = *(const f32x4*)(sw + (c0 + i) * HM + h);
+      w[i][h] = q[0]; w[i][h + 1] = q[1]; w[i][h + 2] = q[2]; w[i][h + 3] = q[3];
+    }
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     const int rr = tid / LPR + j * RPI;

@@ -229,17 +229,29 @@ __global__ __launch_bounds__(256) void ln_rowproj_vec_kernel(const TI* __restric
                                                              const float* __restrict__ W, int H,
                                                              float* __restrict__ out) {
   constexpr int RPI = 256 / LPR;   // rows per iteration of the block
+  // W staged once per block as [c][HM] (coalesced), the lane's slice read back as vectors
+  __shared__ __attribute__((aligned(16))) float sw[8 * LPR * HM];
   const int l = threadIdx.x & (LPR - 1);
   const int c0 = l * 8;
   const bool cok = c0 < C;
+  for (int e = threadIdx.x; e < 8 * LPR * HM; e += 256) {
+    const int cc = e / HM, h = e - cc * HM;
+    sw[e] = (cc < C && h < H) ? W[cc * H + h] : 0.f;
+  }
   float w[8][HM], gg[8], bb[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     gg[i] = cok ? g[c0 + i] : 0.f;
     bb[i] = cok ? b[c0 + i] : 0.f;
-#pragma unroll
-    for (int h = 0; h < HM; ++h) w[i][h] = (cok && h < H) ? W[(c0 + i) * H + h] : 0.f;
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int h = 0; h < HM; h += 4) {
+      const f32x4 q = *(const f32x4*)(sw + (c0 + i) * HM + h);
+      w[i][h] = q[0]; w[i][h + 1] = q[1]; w[i][h + 2] = q[2]; w[i][h + 3] = q[3];
+    }
   float vr[LRP_RIT][8];
 #pragma unroll
   for (int it = 0; it < LRP_RIT; ++it) {
