@@ -732,7 +732,15 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= C) return;
   float s = 0.f;
-  for (int64_t i = 0; i < n; ++i) s += part[i * ld + j];
+  int64_t i = 0;
+  for (; i + 4 <= n; i += 4) {   // four partials in flight, summed in order
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[(i + u) * ld + j];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u];
+  }
+  for (; i < n; ++i) s += part[i * ld + j];
   out[j] = accumulate ? out[j] + s : s;
 }
 
@@ -850,7 +858,22 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const RedBatchArgs a)
   f32x4 s = {0.f, 0.f, 0.f, 0.f};
   if (e0 < E) {
     if (a.jobs[j].vec4) {
-      for (int64_t i = tr; i < n; i += rg) s += *(const f32x4*)(part + i * stride + e0);
+      // four partials per lane in flight (same summation order): indices past
+      // the end read partial n - 1 and count 0
+      for (int64_t i0 = tr; i0 < n; i0 += 4 * rg) {
+        f32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = i0 + u * rg;
+          v[u] = *(const f32x4*)(part + (i < n ? i : n - 1) * stride + e0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float f = i0 + u * rg < n ? 1.f : 0.f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) s[q] = fmaf(v[u][q], f, s[q]);
+        }
+      }
     } else {
       for (int64_t i = tr; i < n; i += rg)
 #pragma unroll
@@ -1299,6 +1322,74 @@ __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int
   }
 }
 
+// Vector form (ch, cz multiples of 8; ld_ab a multiple of 8; 16-byte
+// aligned): tiles of 64 positions x 64 channels; raw is read as 16-byte
+// vectors of 8 channels, a and b are written as 16-byte vectors of 8
+// positions.
+template <typename T>
+__global__ __launch_bounds__(256) void trimul_proj_vec_kernel(int64_t P, int ch, int cz, const float* raw,
+                                                              const float* mask, T* a, T* b, int64_t ld_ab) {
+  __shared__ float ta[64][65], tb[64][65];
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int ld = 4 * ch + cz;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int item = tid + 256 * k;
+    const int pp = item >> 3, cg = (item & 7) * 8;
+    const int64_t p = p0 + pp;
+    const int c = c0 + cg;
+    float va[8], vb[8];
+    if (p < P && c < ch) {
+      const float* r = raw + p * ld;
+      const float mk = mask ? mask[p] : 1.f;
+      float ap[8], ag[8], bp[8], bg[8];
+      ld8(r + c, ap);
+      ld8(r + ch + c, ag);
+      ld8(r + 2 * ch + c, bp);
+      ld8(r + 3 * ch + c, bg);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        va[i] = mk * sigmoidf_(ag[i]) * ap[i];
+        vb[i] = mk * sigmoidf_(bg[i]) * bp[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) va[i] = vb[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      ta[cg + i][pp] = va[i];
+      tb[cg + i][pp] = vb[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int item = tid + 256 * k;
+    const int cc = item >> 3, pg = (item & 7) * 8;
+    const int64_t p = p0 + pg;
+    const int c = c0 + cc;
+    if (c >= ch || p >= P) continue;
+    float va[8], vb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      va[i] = ta[cc][pg + i];
+      vb[i] = tb[cc][pg + i];
+    }
+    if (p + 8 <= P) {
+      st8(a + (int64_t)c * ld_ab + p, va);
+      st8(b + (int64_t)c * ld_ab + p, vb);
+    } else {
+      for (int i = 0; p + i < P; ++i) {
+        a[(int64_t)c * ld_ab + p + i] = from_f32<T>(va[i]);
+        b[(int64_t)c * ld_ab + p + i] = from_f32<T>(vb[i]);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void sigmoid_cols_kernel(int64_t P, int ch, int cz, const float* raw,
                                                            float* g) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1312,8 +1403,14 @@ template <typename T>
 evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* raw, const float* mask,
                          T* a, T* b, int64_t ld_ab, float* g) {
   if (c.dry || P == 0) return EVO_OK;
-  dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
-  EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * (16.0 + 2 * sizeof(T)), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
+  if (ch % 8 == 0 && cz % 8 == 0 && ld_ab % 8 == 0 && aligned16(raw) && aligned16(a) && aligned16(b)) {
+    dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 63) / 64));
+    EVO_LAUNCH(EVO_KNAME("trimul_proj_vec_kernel", T), 0.0, (double)P * ch * (16.0 + 2 * sizeof(T)),
+               (trimul_proj_vec_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
+  } else {
+    dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
+    EVO_LAUNCH(EVO_KNAME("trimul_proj_kernel", T), 0.0, (double)P * ch * (16.0 + 2 * sizeof(T)), (trimul_proj_kernel<T>), grid, dim3(256), 0, c.stream, P, ch, cz, raw, mask, a, b, ld_ab);
+  }
   EVO_TRY(check_launch("trimul_proj"));
   if (!g) return EVO_OK;
   const int64_t n = P * cz;
@@ -1380,11 +1477,41 @@ __global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch,
   draw[p * (4 * ch + cz) + 4 * ch + n] = from_f32<T>(d * tv * gv * (1.f - gv));
 }
 
+// Vector form: 8 consecutive channels per lane (cz, ch, ld_g multiples of 8).
+template <typename T, typename X>
+__global__ __launch_bounds__(256) void trimul_gate_bwd_vec_kernel(int64_t P, int ch, int cz, const X* dz,
+                                                                  const float* t, const float* g, int64_t ld_g,
+                                                                  T* dt, T* draw) {
+  const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  if (e >= P * cz) return;
+  const int64_t p = e / cz;
+  const int n = (int)(e - p * cz);
+  float d[8], gv[8], tv[8], o1[8], o2[8];
+  ld8(dz + e, d);
+  ld8(g + p * ld_g + n, gv);
+  ld8(t + e, tv);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    o1[i] = d[i] * gv[i];
+    o2[i] = d[i] * tv[i] * gv[i] * (1.f - gv[i]);
+  }
+  st8(dt + e, o1);
+  st8(draw + p * (4 * ch + cz) + 4 * ch + n, o2);
+}
+
 template <typename T, typename X>
 evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
                              const float* g, int64_t ld_g, T* dt, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   const int64_t n = P * cz;
+  if (cz % 8 == 0 && ch % 8 == 0 && ld_g % 8 == 0 && aligned16(dz) && aligned16(t) && aligned16(g) &&
+      aligned16(dt) && aligned16(draw)) {
+    const int64_t n8 = n / 8;
+    EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_vec_kernel", X), 0.0, (double)n * (sizeof(X) + 8.0 + 2 * sizeof(T)),
+               (trimul_gate_bwd_vec_kernel<T, X>), dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, c.stream, P,
+               ch, cz, dz, t, g, ld_g, dt, draw);
+    return check_launch("trimul_gate_bwd");
+  }
   EVO_LAUNCH(EVO_KNAME("trimul_gate_bwd_kernel", X), 0.0, (double)n * (sizeof(X) + 8.0 + 2 * sizeof(T)), (trimul_gate_bwd_kernel<T, X>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      c.stream, P, ch, cz, dz, t, g, ld_g, dt, draw);
   return check_launch("trimul_gate_bwd");
