@@ -804,8 +804,11 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
   // were measured to double the bytes written to HBM.
   constexpr int TPO = BN + 8;   // LDS row pitch of the staged output tile (elements)
   static_assert(sizeof(T) != 2 || BM * TPO <= (BM + BN) * LDK, "staged output tile fits the operand LDS");
-  const bool stage = sizeof(T) == 2 && !of32 && e.m_shift < 0 && e.n_shift < 0 && (N & 7) == 0 &&
-                     (mlo & 7) == 0 && ((((uintptr_t)e.out) + (uintptr_t)zo * osz) & 15) == 0;
+  // (two-level layouts too: a 16-byte chunk of 8 columns stays contiguous when
+  // the column blocks hold a multiple of 8, and rows start 16-byte aligned)
+  const bool stage = sizeof(T) == 2 && !of32 && (N & 7) == 0 && (mlo & 7) == 0 &&
+                     (e.m_shift < 0 || (mhi & 7) == 0) && (e.n_shift < 0 || (e.n_shift >= 3 && (nhi & 7) == 0)) &&
+                     ((((uintptr_t)e.out) + (uintptr_t)zo * osz) & 15) == 0;
   T* sto = &lds[0][0];
   if (stage) __syncthreads();   // the operand tiles are no longer read
   // row and column offsets of the lane's outputs, once per row / column block
@@ -881,7 +884,9 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
       for (int c2 = tid; c2 < BM * CPR; c2 += 256) {
         const int r = c2 / CPR, cl = (c2 - r * CPR) * 8;
         const int m = m0 + r, n = n0 + cl;
-        const uint32_t off = (m < M && n < N) ? (uint32_t)(m * mlo + n) * 2u : kOOB;
+        const int mo = PlainLoader<T, BM, KCA>::a32(m, mlo, mhi, e.m_shift);
+        const int no = PlainLoader<T, BM, KCA>::a32(n, 1, nhi, e.n_shift);
+        const uint32_t off = (m < M && n < N) ? (uint32_t)(mo + no) * 2u : kOOB;
         __builtin_amdgcn_raw_buffer_store_b128(*(const i32x4*)(sto + r * TPO + cl), ro, off, 0, 0);
       }
     }
