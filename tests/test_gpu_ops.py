@@ -36,12 +36,15 @@ def _check_param_grads(tag, dpar, gref, tol):
         check(f"{tag} d{k}", dpar[k], gref[k], tol)
 
 
+# N_res = 64: whole 64-wide tiles, so the attention kernels stage the pair
+# bias with vector loads (keys contiguous in the forward and dQ kernels,
+# queries contiguous in the dK/dV kernel); N_res = 40 takes the general path.
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("hd", [8, 16, 32, 64])
-def test_row_attn(dtype, hd):
+@pytest.mark.parametrize("hd,n_res", [(8, 40), (16, 40), (32, 40), (64, 40), (32, 64)])
+def test_row_attn(dtype, hd, n_res):
     from paper_2207_05477_amd import binding as B, _abi as A
-    cfg = OPCFG.replace(msa_head_dim=hd, msa_heads=2 if hd < 64 else 1)
-    say(f"row_attn dtype={dtype} hd={hd}")
+    cfg = OPCFG.replace(msa_head_dim=hd, msa_heads=2 if hd < 64 else 1, n_res=n_res)
+    say(f"row_attn dtype={dtype} hd={hd} n_res={n_res}")
     inp = _setup(dtype, cfg)
     tol = TOL[dtype]
     H, D = cfg.msa_heads, cfg.msa_head_dim
@@ -126,12 +129,13 @@ def test_col_global_attn(dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("kind", ["start", "end"])
-def test_tri_attn(dtype, kind):
+@pytest.mark.parametrize("n_res", [40, 64])
+def test_tri_attn(dtype, kind, n_res):
     from paper_2207_05477_amd import binding as B, _abi as A
-    say(f"tri_attn_{kind} dtype={dtype}")
-    inp = _setup(dtype)
+    say(f"tri_attn_{kind} dtype={dtype} n_res={n_res}")
+    cfg = OPCFG.replace(n_res=n_res)
+    inp = _setup(dtype, cfg)
     tol = TOL[dtype]
-    cfg = OPCFG
     H, D = cfg.tri_heads, cfg.tri_head_dim
     sub = "tri_att_start" if kind == "start" else "tri_att_end"
     fn = O.tri_att_start if kind == "start" else O.tri_att_end
