@@ -194,6 +194,26 @@ struct RowsStage {
 
 constexpr int BP = 68;   // LDS row pitch of the bias tile (floats)
 
+// XCD-aware workgroup coordinates.  Workgroups are dealt round-robin over the
+// 8 XCDs (each with its own L2) in linear launch order; the linear index is
+// remapped so that each XCD receives a contiguous run of (x, y, z), x fastest:
+// the x blocks of one (y, z) -- which read the same key/value (or query)
+// rows -- and neighbouring heads y, whose rows share cache lines, then meet in
+// one L2.  Grids whose size is not a multiple of 8 keep the launch order.
+struct WgCoord { int x, y, z; };
+EVO_DEV WgCoord xcd_coord() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int n = gx * gy * gridDim.z;
+  int l = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
+  WgCoord c;
+  c.x = l % gx;
+  l /= gx;
+  c.y = l % gy;
+  c.z = l / gy;
+  return c;
+}
+
 template <typename T, int D>
 EVO_DEV void zero_pad_rows(T* dst_t, int tid) {
   using F = DF<T, D>;
@@ -303,11 +323,12 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
   __shared__ __attribute__((aligned(16))) float sKa[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t b = blockIdx.z;
-  const int h = blockIdx.y;
+  const WgCoord wg = xcd_coord();
+  const int64_t b = wg.z;
+  const int h = wg.y;
   const int64_t qend0 = a.q_count < 0 ? a.Lq : a.q_begin + a.q_count;
   const int64_t qend = qend0 < a.Lq ? qend0 : a.Lq;
-  const int64_t q0 = a.q_begin + (int64_t)blockIdx.x * 64;
+  const int64_t q0 = a.q_begin + (int64_t)wg.x * 64;
   const int ql = wave * 16 + lr;
   const int64_t qi = q0 + ql;
   const bool qok = qi < qend;
@@ -469,12 +490,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   __shared__ __attribute__((aligned(16))) float sKa[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int h = blockIdx.y;
-  const int64_t grp = blockIdx.z;
+  const WgCoord wg = xcd_coord();
+  const int h = wg.y;
+  const int64_t grp = wg.z;
   const int64_t b0 = grp * gr.group;
   const int64_t b1 = b0 + gr.group < a.nbatch ? b0 + gr.group : a.nbatch;
   const int qloc = wave * 16 + lr;
-  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  const int64_t q0 = (int64_t)wg.x * 64;
   const int64_t qi = q0 + qloc;
   const bool qok = qi < a.Lq;
   const bool dbias = gr.dbias_part != nullptr;
@@ -616,11 +638,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
   __shared__ __attribute__((aligned(16))) float sD[KB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int h = blockIdx.y;
-  const int64_t b0 = (int64_t)blockIdx.z * group;
+  const WgCoord wg = xcd_coord();
+  const int h = wg.y;
+  const int64_t b0 = (int64_t)wg.z * group;
   const int64_t b1 = b0 + group < a.nbatch ? b0 + group : a.nbatch;
   const int kl = wave * 16 + lr;
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int64_t k0 = (int64_t)wg.x * 64;
   const int64_t key = k0 + kl;
   const bool kok = key < a.Lk;
   const float* bias = BM != BIAS_NONE ? a.bias + h * a.bh : nullptr;
