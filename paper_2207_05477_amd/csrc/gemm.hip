@@ -659,12 +659,18 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  int tile = blockIdx.x;
+  // XCD-aware order over (tile, batch or k-slice): workgroups are dealt
+  // round-robin over the 8 XCDs in linear launch order; each XCD gets a
+  // contiguous run of (tile, z), tile fastest, so the tiles sharing a row or
+  // column panel of one problem meet in one L2.
   const int ntiles = gridDim.x;
-  if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
+  const int nwg = ntiles * gridDim.z;
+  int lin = blockIdx.x + ntiles * blockIdx.z;
+  if ((nwg & 7) == 0) lin = (lin & 7) * (nwg >> 3) + (lin >> 3);
+  const int tile = lin % ntiles;
   const int m0 = (tile / ntn) * BM;
   const int n0 = (tile % ntn) * BN;
-  const int z = blockIdx.z;
+  const int z = lin / ntiles;
   const int M = (int)g.M, N = (int)g.N;
 
   const T* Ap = (const T*)g.A.ptr;
