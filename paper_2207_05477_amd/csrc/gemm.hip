@@ -824,15 +824,25 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
     mrow[i] = m0 + wm * WM + i * 16 + lr;
     moff[i] = PlainLoader<T, BM, KCA>::a32(mrow[i], mlo, mhi, e.m_shift);
   }
+  // rows outer, column blocks inner: the two halves of a row's 128-byte line
+  // (FP32 outputs, residual and gate inputs) are touched back to back
+  int ncol[TN], noff[TN];
+  f32x4 bias4[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
-    const int n = n0 + wn * WN + j * 16 + lg * 4;
-    const bool colok = n < N;
-    const int no = PlainLoader<T, BM, KCA>::a32(n, 1, nhi, e.n_shift);
-    f32x4 bj = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (e.bias && colok) bj = *(const f32x4*)(e.bias + n);
+    ncol[j] = n0 + wn * WN + j * 16 + lg * 4;
+    noff[j] = PlainLoader<T, BM, KCA>::a32(ncol[j], 1, nhi, e.n_shift);
+    bias4[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (e.bias && ncol[j] < N) bias4[j] = *(const f32x4*)(e.bias + ncol[j]);
+  }
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = ncol[j];
+      const bool colok = n < N;
+      const int no = noff[j];
+      const f32x4 bj = bias4[j];
       const int m = mrow[i];
       const bool ok = colok && m < M;
       f32x4 v = acc[j][i] * alpha + bj;
@@ -893,7 +903,7 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
         const int mo = PlainLoader<T, BM, KCA>::a32(m, mlo, mhi, e.m_shift);
         const int no = PlainLoader<T, BM, KCA>::a32(n, 1, nhi, e.n_shift);
         const uint32_t off = (m < M && n < N) ? (uint32_t)(mo + no) * 2u : kOOB;
-        __builtin_amdgcn_raw_buffer_store_b128(*(const i32x4*)(sto + r * TPO + cl), ro, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(*(const i32x4*)(sto + r * TPO + cl), ro, off, 0, 2);
       }
     }
   }
