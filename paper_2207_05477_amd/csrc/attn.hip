@@ -194,18 +194,14 @@ struct RowsStage {
 
 constexpr int BP = 68;   // LDS row pitch of the bias tile (floats)
 
-// XCD-aware workgroup coordinates.  Workgroups are dealt round-robin over the
-// 8 XCDs (each with its own L2) in linear launch order; the linear index is
-// remapped so that each XCD receives a contiguous run of (x, y, z), x fastest:
-// the x blocks of one (y, z) -- which read the same key/value (or query)
-// rows -- and neighbouring heads y, whose rows share cache lines, then meet in
-// one L2.  Grids whose size is not a multiple of 8 keep the launch order.
+// XCD-aware workgroup coordinates (see xcd_order): each XCD receives a
+// contiguous run of (x, y, z), x fastest, so the x blocks of one (y, z) --
+// which read the same key/value (or query) rows -- and neighbouring heads y,
+// whose rows share cache lines, meet in one L2.
 struct WgCoord { int x, y, z; };
 EVO_DEV WgCoord xcd_coord() {
   const int gx = gridDim.x, gy = gridDim.y;
-  const int n = gx * gy * gridDim.z;
-  int l = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  if ((n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
+  int l = xcd_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
   WgCoord c;
   c.x = l % gx;
   l /= gx;

@@ -82,6 +82,18 @@ EVO_DEV float wave_max(float v) {
   return v;
 }
 
+// ---------------------------------------------------------------- XCD-aware order
+// Workgroups are dealt round-robin over the 8 XCDs (each with its own L2) in
+// linear launch order: workgroup l runs on XCD l % 8.  xcd_order(l, n) maps
+// the launch index to a logical index so that each XCD receives one
+// contiguous run of logical indices (XCD x gets ceil or floor of n / 8 of
+// them, in order); a bijection on [0, n) for any n.
+EVO_DEV int xcd_order(int l, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = l & 7, i = l >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // ---------------------------------------------------------------- MFMA wrappers
 // 16x16 output tiles for both precisions.  Lane l of a wave holds output rows
 // 4*(l/16)+i (i = 0..3) of column l%16.  An operand fragment of lane l holds

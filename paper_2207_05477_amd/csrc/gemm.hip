@@ -339,11 +339,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int32_t ntn, int3
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; give
-  // each XCD a contiguous run of tiles (shared row panels stay in its L2).
-  int tile = blockIdx.x;
-  const int ntiles = gridDim.x;
-  if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
+  // XCD-aware order (see xcd_order): each XCD gets a contiguous run of tiles,
+  // so shared row panels stay in its L2
+  const int tile = xcd_order(blockIdx.x, gridDim.x);
   const int64_t m0 = (int64_t)(tile / ntn) * BM;
   const int64_t n0 = (int64_t)(tile % ntn) * BN;
   const int z = blockIdx.z;
@@ -664,9 +662,7 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
   // contiguous run of (tile, z), tile fastest, so the tiles sharing a row or
   // column panel of one problem meet in one L2.
   const int ntiles = gridDim.x;
-  const int nwg = ntiles * gridDim.z;
-  int lin = blockIdx.x + ntiles * blockIdx.z;
-  if ((nwg & 7) == 0) lin = (lin & 7) * (nwg >> 3) + (lin >> 3);
+  const int lin = xcd_order(blockIdx.x + ntiles * blockIdx.z, ntiles * gridDim.z);
   const int tile = lin % ntiles;
   const int m0 = (tile / ntn) * BM;
   const int n0 = (tile % ntn) * BN;
