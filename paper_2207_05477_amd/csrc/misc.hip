@@ -1092,10 +1092,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackBatch b) {
   const int ntot = b.ntot[q];
   const int e = ((int)blockIdx.x - b.start[q]) * 256 + (int)threadIdx.x;
   if (e >= a.K * ntot) return;
-  // k fastest when only the transposed copy is written (its stores then
-  // coalesce; the parameter reads are strided, but reads do not rewrite lines)
-  const bool kfast = a.dst_t && !a.dst;
-  const int k = kfast ? e % a.K : e / ntot, n = kfast ? e / a.K : e - k * ntot;
+  const int k = e / ntot, n = e - k * ntot;
   int s = 0, nl = n;
   while (s < a.nseg - 1 && nl >= a.seg[s].n) { nl -= a.seg[s].n; ++s; }
   const float v = a.seg[s].w[(int64_t)k * a.seg[s].n + nl];
