@@ -126,22 +126,23 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dg
                       const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
                       T* dgpre, int64_t ld_dg, float* D);
 
-// Triangle multiplication projections, forward: FP32 raw[p][4*ch + cz] (ap | ag | bp | bg | g)
+// Triangle multiplication projections, forward: raw[p][4*ch + cz] (ap | ag | bp | bg | g, compute type)
 // -> a[c][p], b[c][p] (channel-major, masked, gated), and, when g is not null,
-// FP32 g[p][cz] = sigmoid(raw g).  a and b have channel stride ld_ab (>= P;
-// pointers may be offset into larger tensors).
+// a copy of the output-gate columns in FP32, g[p][cz] (the projection's
+// epilogue has already applied their sigmoid).  a and b have channel stride
+// ld_ab (>= P; pointers may be offset into larger tensors).
 template <typename T>
-evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* raw, const float* mask,
+evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
                          T* a, T* b, int64_t ld_ab, float* g);
 // Backward: FP32 da, db channel-major -> draw[p][4*ch] columns of ap, ag, bp, bg.
 template <typename T>
-evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const float* raw,
+evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
                              const float* mask, const float* da, const float* db, T* draw);
-// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g)  (t, g FP32;
-// g[p * ld_g + n]).
+// Output gate backward: dt = dz * g;  draw[p][4ch + n] = dz * t * g (1 - g)  (t FP32, g in
+// the compute type at g[p * ld_g + n]).
 template <typename T, typename X = T>
 evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
-                             const float* g, int64_t ld_g, T* dt, T* draw);
+                             const T* g, int64_t ld_g, T* dt, T* draw);
 
 // Outer-product-mean input gradients from split-K partials:
 //   dab[s][i][off + p] = mask[s][i] * sum_k part[k][s][i][p]   (part FP32 [nsplit][S][R][ch],

@@ -1289,7 +1289,7 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dg
 // Tiles of 64 positions x 32 channels, transposed through LDS so that both the
 // row-major projection output and the channel-major operands move coalesced.
 template <typename T>
-__global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int cz, const float* raw,
+__global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int cz, const T* raw,
                                                           const float* mask, T* a, T* b, int64_t ld_ab) {
   __shared__ float ta[32][65], tb[32][65];
   const int tid = threadIdx.x;
@@ -1302,10 +1302,10 @@ __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int
     const int c = c0 + cc;
     float va = 0.f, vb = 0.f;
     if (p < P && c < ch) {
-      const float* r = raw + p * ld;
+      const T* r = raw + p * ld;
       const float mk = mask ? mask[p] : 1.f;
-      va = mk * sigmoidf_(r[ch + c]) * r[c];
-      vb = mk * sigmoidf_(r[3 * ch + c]) * r[2 * ch + c];
+      va = mk * sigmoidf_(to_f32(r[ch + c])) * to_f32(r[c]);
+      vb = mk * sigmoidf_(to_f32(r[3 * ch + c])) * to_f32(r[2 * ch + c]);
     }
     ta[cc][pp] = va;
     tb[cc][pp] = vb;
@@ -1327,7 +1327,7 @@ __global__ __launch_bounds__(256) void trimul_proj_kernel(int64_t P, int ch, int
 // vectors of 8 channels, a and b are written as 16-byte vectors of 8
 // positions.
 template <typename T>
-__global__ __launch_bounds__(256) void trimul_proj_vec_kernel(int64_t P, int ch, int cz, const float* raw,
+__global__ __launch_bounds__(256) void trimul_proj_vec_kernel(int64_t P, int ch, int cz, const T* raw,
                                                               const float* mask, T* a, T* b, int64_t ld_ab) {
   __shared__ float ta[64][65], tb[64][65];
   const int tid = threadIdx.x;
@@ -1342,7 +1342,7 @@ __global__ __launch_bounds__(256) void trimul_proj_vec_kernel(int64_t P, int ch,
     const int c = c0 + cg;
     float va[8], vb[8];
     if (p < P && c < ch) {
-      const float* r = raw + p * ld;
+      const T* r = raw + p * ld;
       const float mk = mask ? mask[p] : 1.f;
       float ap[8], ag[8], bp[8], bg[8];
       ld8(r + c, ap);
@@ -1390,17 +1390,17 @@ __global__ __launch_bounds__(256) void trimul_proj_vec_kernel(int64_t P, int ch,
   }
 }
 
-__global__ __launch_bounds__(256) void sigmoid_cols_kernel(int64_t P, int ch, int cz, const float* raw,
-                                                           float* g) {
+template <typename T>
+__global__ __launch_bounds__(256) void gate_cols_kernel(int64_t P, int ch, int cz, const T* raw, float* g) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= P * cz) return;
   const int64_t p = e / cz;
   const int n = (int)(e % cz);
-  g[e] = sigmoidf_(raw[p * (4 * ch + cz) + 4 * ch + n]);
+  g[e] = to_f32(raw[p * (4 * ch + cz) + 4 * ch + n]);
 }
 
 template <typename T>
-evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* raw, const float* mask,
+evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const T* raw, const float* mask,
                          T* a, T* b, int64_t ld_ab, float* g) {
   if (c.dry || P == 0) return EVO_OK;
   if (ch % 8 == 0 && cz % 8 == 0 && ld_ab % 8 == 0 && aligned16(raw) && aligned16(a) && aligned16(b)) {
@@ -1414,13 +1414,13 @@ evo_status_t trimul_proj(const Ctx& c, int64_t P, int ch, int cz, const float* r
   EVO_TRY(check_launch("trimul_proj"));
   if (!g) return EVO_OK;
   const int64_t n = P * cz;
-  EVO_LAUNCH("sigmoid_cols_kernel", 0.0, (double)n * 8.0, sigmoid_cols_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream,
-                     P, ch, cz, raw, g);
+  EVO_LAUNCH(EVO_KNAME("gate_cols_kernel", T), 0.0, (double)n * (4.0 + sizeof(T)), (gate_cols_kernel<T>),
+             dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, P, ch, cz, raw, g);
   return check_launch("trimul_gate");
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch, int cz, const float* raw,
+__global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch, int cz, const T* raw,
                                                               const float* mask, const float* da,
                                                               const float* db, T* draw) {
   __shared__ float ta[32][65], tb[32][65];
@@ -1441,11 +1441,11 @@ __global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch,
     const int64_t p = p0 + pp;
     const int c = c0 + cc;
     if (p < P && c < ch) {
-      const float* r = raw + p * ld;
+      const T* r = raw + p * ld;
       T* d = draw + p * ld;
       const float mk = mask ? mask[p] : 1.f;
-      const float ap = r[c], sa = sigmoidf_(r[ch + c]);
-      const float bp = r[2 * ch + c], sb = sigmoidf_(r[3 * ch + c]);
+      const float ap = to_f32(r[c]), sa = sigmoidf_(to_f32(r[ch + c]));
+      const float bp = to_f32(r[2 * ch + c]), sb = sigmoidf_(to_f32(r[3 * ch + c]));
       const float dav = ta[cc][pp] * mk, dbv = tb[cc][pp] * mk;
       d[c] = from_f32<T>(dav * sa);
       d[ch + c] = from_f32<T>(dav * ap * sa * (1.f - sa));
@@ -1456,7 +1456,7 @@ __global__ __launch_bounds__(256) void trimul_proj_bwd_kernel(int64_t P, int ch,
 }
 
 template <typename T>
-evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const float* raw,
+evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const T* raw,
                              const float* mask, const float* da, const float* db, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((ch + 31) / 32));
@@ -1466,13 +1466,13 @@ evo_status_t trimul_proj_bwd(const Ctx& c, int64_t P, int ch, int cz, const floa
 
 template <typename T, typename X>
 __global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch, int cz, const X* dz,
-                                                              const float* t, const float* g, int64_t ld_g,
+                                                              const float* t, const T* g, int64_t ld_g,
                                                               T* dt, T* draw) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= P * cz) return;
   const int64_t p = e / cz;
   const int n = (int)(e % cz);
-  const float d = to_f32(dz[e]), gv = g[p * ld_g + n], tv = t[e];
+  const float d = to_f32(dz[e]), gv = to_f32(g[p * ld_g + n]), tv = t[e];
   dt[e] = from_f32<T>(d * gv);
   draw[p * (4 * ch + cz) + 4 * ch + n] = from_f32<T>(d * tv * gv * (1.f - gv));
 }
@@ -1480,7 +1480,7 @@ __global__ __launch_bounds__(256) void trimul_gate_bwd_kernel(int64_t P, int ch,
 // Vector form: 8 consecutive channels per lane (cz, ch, ld_g multiples of 8).
 template <typename T, typename X>
 __global__ __launch_bounds__(256) void trimul_gate_bwd_vec_kernel(int64_t P, int ch, int cz, const X* dz,
-                                                                  const float* t, const float* g, int64_t ld_g,
+                                                                  const float* t, const T* g, int64_t ld_g,
                                                                   T* dt, T* draw) {
   const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
   if (e >= P * cz) return;
@@ -1501,7 +1501,7 @@ __global__ __launch_bounds__(256) void trimul_gate_bwd_vec_kernel(int64_t P, int
 
 template <typename T, typename X>
 evo_status_t trimul_gate_bwd(const Ctx& c, int64_t P, int ch, int cz, const X* dz, const float* t,
-                             const float* g, int64_t ld_g, T* dt, T* draw) {
+                             const T* g, int64_t ld_g, T* dt, T* draw) {
   if (c.dry || P == 0) return EVO_OK;
   const int64_t n = P * cz;
   if (cz % 8 == 0 && ch % 8 == 0 && ld_g % 8 == 0 && aligned16(dz) && aligned16(t) && aligned16(g) &&
@@ -1609,12 +1609,12 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
   template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t, const T*, \
                                     int64_t, const T*, int64_t, T*, int64_t, T*, int64_t, float*); \
-  template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const float*, const float*,  \
+  template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const T*, const float*,      \
                                        T*, T*, int64_t, float*);                                   \
-  template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const float*,           \
+  template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const T*,               \
                                            const float*, const float*, const float*, T*);          \
   template evo_status_t trimul_gate_bwd<T, T>(const Ctx&, int64_t, int, int, const T*,           \
-                                              const float*, const float*, int64_t, T*, T*);
+                                              const float*, const T*, int64_t, T*, T*);
 
 EVO_INST(float)
 EVO_INST(bf16)
@@ -1627,7 +1627,7 @@ template evo_status_t ln_fwd_rows<float, bf16>(const Ctx&, const float*, int64_t
 template evo_status_t ln_rowproj<float, bf16>(const Ctx&, const float*, int64_t, int, const float*,
                                               const float*, float, const float*, int, float*);
 template evo_status_t trimul_gate_bwd<bf16, float>(const Ctx&, int64_t, int, int, const float*, const float*,
-                                                   const float*, int64_t, bf16*, bf16*);
+                                                   const bf16*, int64_t, bf16*, bf16*);
 template evo_status_t convert_elems<float, bf16>(const Ctx&, const float*, bf16*, int64_t);
 template evo_status_t convert_elems<bf16, float>(const Ctx&, const bf16*, float*, int64_t);
 template evo_status_t convert_elems<float, float>(const Ctx&, const float*, float*, int64_t);

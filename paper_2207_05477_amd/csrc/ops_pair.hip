@@ -272,17 +272,17 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
 // ============================================================== triangle multiplication
 template <typename T>
 struct TriSaved {
-  // raw (projection output; its last cz columns hold the output gate after
-  // the sigmoid) and x (contraction output) feed only elementwise work and
-  // LayerNorm: FP32 whatever the compute type.
-  T* y; float* mean; float* rstd; float* raw; T* a; T* b; float* x; T* xn; float* mean2;
+  // raw: projection output in the compute type (its last cz columns hold the
+  // output gate after the sigmoid); x (contraction output) feeds only the
+  // output LayerNorm: FP32 whatever the compute type.
+  T* y; float* mean; float* rstd; T* raw; T* a; T* b; float* x; T* xn; float* mean2;
   float* rstd2;
   void carve(Arena& ar, const evo_trimul_desc_t& d) {
     const int64_t P = d.n_res * d.n_res, ch = d.c_hidden, cz = d.c_z;
     y = ar.take_n<T>(P * cz);
     mean = ar.take_n<float>(P);
     rstd = ar.take_n<float>(P);
-    raw = ar.take_n<float>(P * (4 * ch + cz));
+    raw = ar.take_n<T>(P * (4 * ch + cz));
     a = ar.take_n<T>(P * ch);
     b = ar.take_n<T>(P * ch);
     x = ar.take_n<float>(P * ch);
@@ -310,7 +310,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
   T* y = ws.take_n<T>(CR * cz);
   float* mean = ws.take_n<float>(CR);
   float* rstd = ws.take_n<float>(CR);
-  float* raw = ws.take_n<float>(CR * NP);
+  T* raw = ws.take_n<T>(CR * NP);
   float* x = ws.take_n<float>(CR * ch);
   T* xn = ws.take_n<T>(CR * ch);
   if (c.dry) return EVO_OK;
@@ -333,11 +333,13 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
     gp.M = CR; gp.N = NP; gp.K = cz;
     gp.A = op_rowmajor(y, cz);
     gp.B = op_rowmajor(wt_p, cz);
-    gp.epi = epi_rowmajor(raw, NP, true);
+    gp.epi = epi_rowmajor(raw, NP, false);
     gp.epi.bias = b_p;
+    gp.epi.act = ACT_SIGMOID;   // output gate columns, as in the unchunked forward
+    gp.epi.act_n0 = 4 * ch;
     EVO_TRY(gemm<T>(c, gp));
     EVO_TRY(trimul_proj<T>(c, CR, (int)ch, (int)cz, raw, mask ? mask + p0 : nullptr, a + p0, b + p0, P,
-                           g + p0 * cz));   // (raw is per chunk: the gate is kept apart)
+                           g + p0 * cz));   // (raw is per chunk: the gate is copied apart)
   }
   float* mean2 = mean;
   float* rstd2 = rstd;
@@ -399,7 +401,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     g.M = P; g.N = NP; g.K = cz;
     g.A = op_rowmajor(S.y, cz);
     g.B = op_rowmajor(wt_p, cz);
-    g.epi = epi_rowmajor(S.raw, NP, true);
+    g.epi = epi_rowmajor(S.raw, NP, false);
     g.epi.bias = b_p;
     g.epi.act = ACT_SIGMOID;   // output gate columns: sigmoid in the epilogue
     g.epi.act_n0 = 4 * ch;
@@ -429,7 +431,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   g.B = op_rowmajor(wt_o, ch);
   epi_out<X>(g.epi, zout, cz);
   g.epi.bias = w.b_o;
-  g.epi.gate = S.raw + 4 * ch; g.epi.g_m = NP; g.epi.g_n = 1; g.epi.gate_f32 = 1;
+  g.epi.gate = S.raw + 4 * ch; g.epi.g_m = NP; g.epi.g_n = 1; g.epi.gate_f32 = 0;
   epi_resid<X>(g.epi, z, cz, 1);
   return gemm<T>(c, g);
 }
