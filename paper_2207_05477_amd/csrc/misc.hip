@@ -47,58 +47,70 @@ __global__ __launch_bounds__(256) void ln_fwd_kernel(const TI* __restrict__ x, i
 // Vectorised form (C % 8 == 0, C <= 1024, 16-byte aligned rows): LPR lanes
 // share a row, lane l owning the 8-channel chunks j*LPR + l (j < NC), so a wave
 // normalises 64 / LPR rows at once with 16-byte accesses.
+constexpr int LNF_ROWS = 2;   // rows per lane group in the vectorised LayerNorm forward
 template <typename TI, typename T, int LPR, int NC>
 __global__ __launch_bounds__(256) void ln_fwd_vec_kernel(const TI* __restrict__ x, int64_t rows, int C,
                                                          const float* __restrict__ g,
                                                          const float* __restrict__ b, float eps,
                                                          T* __restrict__ y, float* __restrict__ mean,
                                                          float* __restrict__ rstd, int rshift, int64_t rhi) {
+  // LNF_ROWS rows per lane group, RPB rows apart: all their loads are issued
+  // before any is used (rows past the end read the last row, never stored)
   constexpr int RPB = 256 / LPR;
   const int l = threadIdx.x & (LPR - 1);
-  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
-  const bool ok = row < rows;
-  const TI* xr = x + (rshift < 0 ? row * C : (row >> rshift) * rhi + (row & ((1LL << rshift) - 1)) * C);
-  float v[NC][8];
-  float s = 0.f;
+  float v[LNF_ROWS][NC][8];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c0 = (j * LPR + l) * 8;
-    if (ok && c0 < C) ld8(xr + c0, v[j]);
-    else
+  for (int q = 0; q < LNF_ROWS; ++q) {
+    int64_t row = ((int64_t)blockIdx.x * LNF_ROWS + q) * RPB + threadIdx.x / LPR;
+    row = row < rows ? row : rows - 1;
+    const TI* xr = x + (rshift < 0 ? row * C : (row >> rshift) * rhi + (row & ((1LL << rshift) - 1)) * C);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[j][i] = 0.f;
+    for (int j = 0; j < NC; ++j) {
+      const int c0 = (j * LPR + l) * 8;
+      if (c0 < C) ld8(xr + c0, v[q][j]);
+      else
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s += v[j][i];
-  }
-  const float mu = group_sum<LPR>(s) / (float)C;
-  float q = 0.f;
-#pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c0 = (j * LPR + l) * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float d = c0 < C ? v[j][i] - mu : 0.f;
-      q += d * d;
+        for (int i = 0; i < 8; ++i) v[q][j][i] = 0.f;
     }
   }
-  const float rs = 1.0f / sqrtf(group_sum<LPR>(q) / (float)C + eps);
-  if (!ok) return;
-  T* yr = y + row * C;
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c0 = (j * LPR + l) * 8;
-    if (c0 < C) {
-      float gg[8], bb[8], o[8];
-      ld8(g + c0, gg);
-      ld8(b + c0, bb);
+  for (int q = 0; q < LNF_ROWS; ++q) {
+    const int64_t row = ((int64_t)blockIdx.x * LNF_ROWS + q) * RPB + threadIdx.x / LPR;
+    float s = 0.f;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) o[i] = (v[j][i] - mu) * rs * gg[i] + bb[i];
-      st8(yr + c0, o);
+    for (int j = 0; j < NC; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += v[q][j][i];
+    const float mu = group_sum<LPR>(s) / (float)C;
+    float sq = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c0 = (j * LPR + l) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float d = c0 < C ? v[q][j][i] - mu : 0.f;
+        sq += d * d;
+      }
     }
-  }
-  if (l == 0) {
-    if (mean) mean[row] = mu;
-    if (rstd) rstd[row] = rs;
+    const float rs = 1.0f / sqrtf(group_sum<LPR>(sq) / (float)C + eps);
+    if (row >= rows) continue;
+    T* yr = y + row * C;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c0 = (j * LPR + l) * 8;
+      if (c0 < C) {
+        float gg[8], bb[8], o[8];
+        ld8(g + c0, gg);
+        ld8(b + c0, bb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = (v[q][j][i] - mu) * rs * gg[i] + bb[i];
+        st8(yr + c0, o);
+      }
+    }
+    if (l == 0) {
+      if (mean) mean[row] = mu;
+      if (rstd) rstd[row] = rs;
+    }
   }
 }
 
@@ -114,7 +126,7 @@ template <typename TI, typename T, int LPR>
 static void ln_fwd_vec_launch(const Ctx& c, double bytes, const TI* x, int64_t rows, int C, int rshift,
                               int64_t rhi, const float* g, const float* b, float eps, T* y, float* mean,
                               float* rstd) {
-  constexpr int RPB = 256 / LPR;
+  constexpr int RPB = 256 / LPR * LNF_ROWS;
   dim3 grid((unsigned)((rows + RPB - 1) / RPB));
   if (C <= 8 * LPR)
     EVO_LAUNCH(EVO_KNAME("ln_fwd_vec_kernel", TI), 0.0, bytes, (ln_fwd_vec_kernel<TI, T, LPR, 1>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, y, mean, rstd, rshift, rhi);
