@@ -1179,22 +1179,32 @@ __global__ __launch_bounds__(256) void convert_kernel(const TI* __restrict__ s, 
   if (e < n) d[e] = from_f32<TO>(to_f32(s[e]));
 }
 
+// EPT elements per thread: 8 when narrowing, 4 when widening, so that a
+// wave's widening stores are contiguous 16-byte pieces lane after lane
+// (measured faster; narrowing measured faster with 8).
 template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void convert_vec_kernel(const TI* __restrict__ s, TO* __restrict__ d, int64_t n8) {
+__global__ __launch_bounds__(256) void convert_vec_kernel(const TI* __restrict__ s, TO* __restrict__ d, int64_t nv) {
+  constexpr int EPT = sizeof(TI) < sizeof(TO) ? 4 : 8;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n8) return;
-  float v[8];
-  ld8(s + e * 8, v);
-  st8(d + e * 8, v);
+  if (e >= nv) return;
+  if constexpr (EPT == 4) {
+    const bf16x4 a = *(const bf16x4*)(s + e * 4);
+    store4<TO>(d + e * 4, f32x4{(float)a[0], (float)a[1], (float)a[2], (float)a[3]});
+  } else {
+    float v[8];
+    ld8(s + e * 8, v);
+    st8(d + e * 8, v);
+  }
 }
 
 template <typename TI, typename TO>
 evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n) {
   if (c.dry || n == 0) return EVO_OK;
+  constexpr int EPT = sizeof(TI) < sizeof(TO) ? 4 : 8;
   if (n % 8 == 0 && aligned16(src) && aligned16(dst)) {
-    const int64_t n8 = n / 8;
+    const int64_t nv = n / EPT;
     EVO_LAUNCH(EVO_KNAME("convert_vec_kernel", TO), 0.0, (double)n * (sizeof(TI) + sizeof(TO)),
-               (convert_vec_kernel<TI, TO>), dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, c.stream, src, dst, n8);
+               (convert_vec_kernel<TI, TO>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, c.stream, src, dst, nv);
     return check_launch("convert");
   }
   EVO_LAUNCH(EVO_KNAME("convert_kernel", TO), 0.0, (double)n * (sizeof(TI) + sizeof(TO)),
