@@ -664,8 +664,16 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
   const int ntiles = gridDim.x;
   const int lin = xcd_order(blockIdx.x + ntiles * blockIdx.z, ntiles * gridDim.z);
   const int tile = lin % ntiles;
-  const int m0 = (tile / ntn) * BM;
-  const int n0 = (tile % ntn) * BN;
+  // grouped order: bands of 8 row blocks, column blocks outer within a band,
+  // so consecutive tiles share a column panel and a band's row panels are
+  // reused across all columns while they are still in L2
+  constexpr int GRP = 8;
+  const int ntm = ntiles / ntn;
+  const int band = tile / (GRP * ntn), first = band * GRP;
+  const int gs = ntm - first < GRP ? ntm - first : GRP;
+  const int tib = tile - band * GRP * ntn;
+  const int m0 = (first + tib % gs) * BM;
+  const int n0 = (tib / gs) * BN;
   const int z = lin / ntiles;
   const int M = (int)g.M, N = (int)g.N;
 
