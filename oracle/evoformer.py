@@ -35,10 +35,14 @@ The readings taken where the paper is silent:
   bias not divided, eps a runtime argument (default 1e-3).
 * Incoming triangle multiplication: x_ij = sum_k a_ki * b_kj.
 * Dropout is the identity.
-* The ReLU of the transitions decides on the exact pre-activation, or, when
-  compared with a BF16 implementation, on the BF16-formed pre-activation
-  (relu_decision="bf16"): a discrete decision is taken in the precision of the
-  implementation under test, the values stay float64.
+* The ReLU of the transitions decides on the exact pre-activation.  Its
+  derivative jumps at zero, so a gradient is only precision-independent where
+  no pre-activation lies within rounding of zero.  For gradient parity the
+  tests therefore build inputs whose ReLU decisions are clear:
+  with_relu_margins() re-chooses each transition's b_1, on this oracle's own
+  forward, so that every pre-activation is at least a given margin away from
+  zero, and asserts the margin it reached (test-input construction; the
+  definition itself is unchanged).
 * Block order: row attention, column attention, MSA transition, outer product
   mean, outgoing and incoming triangle multiplication, triangle attention
   around the starting and the ending node, pair transition.
@@ -132,25 +136,51 @@ def _bf16(t):
     return t.detach().to(torch.bfloat16).to(F64)
 
 
-def transition(x, p, eps=1e-5, relu_decision=None):
-    """Two-layer MLP with ReLU on the LayerNormed input.
+def transition(x, p, eps=1e-5, probe=None):
+    """Two-layer MLP with ReLU on the LayerNormed input:
+    Linear_2(ReLU(Linear_1(LayerNorm(x)))).
 
-    The ReLU is a discrete decision taken by floating point.  With
-    relu_decision="bf16" the decision (which hidden units are active) is taken
-    on the pre-activation formed from the BF16-rounded LayerNorm output and
-    BF16-rounded W_1, as a BF16 implementation forms it; the values that pass
-    stay the exact float64 ones.  None takes the decision on the exact value."""
+    ``probe`` (test-input construction only, see with_relu_margins): a dict;
+    with probe["choose"] = margin, b_1 is first replaced (in ``p``) by
+    relu_margin_bias of this call's pre-activations; every call appends
+    min |pre-activation| to probe["min_abs"]."""
     y = layer_norm(x, p["ln_g"], p["ln_b"], eps)
-    pre = y @ p["w_1"] + p["b_1"]
-    if relu_decision is None:
-        h = torch.relu(pre)
-    elif relu_decision == "bf16":
+    if probe is not None and probe.get("choose") is not None:
         with torch.no_grad():
-            active = (_bf16(y) @ _bf16(p["w_1"]) + p["b_1"].detach()) > 0
-        h = pre * active.to(F64)
-    else:
-        raise ValueError(relu_decision)
-    return h @ p["w_2"] + p["b_2"]
+            u = p["w_1"].shape[1]
+            p["b_1"] = relu_margin_bias((y @ p["w_1"]).reshape(-1, u), probe["choose"])
+    pre = y @ p["w_1"] + p["b_1"]
+    if probe is not None:
+        probe.setdefault("min_abs", []).append(pre.detach().abs().min().item())
+    return torch.relu(pre) @ p["w_2"] + p["b_2"]
+
+
+# Active fractions the hidden units of a margin-constructed transition aim at,
+# cycled over the units: always off, always on, and mixed decisions.
+MARGIN_TARGETS = (0.0, 1.0, 0.5, 0.1, 0.9)
+
+
+def relu_margin_bias(pre, margin):
+    """Bias b[u] for the hidden units of one transition such that every
+    pre[r, u] + b[u] is at least ``margin`` away from zero.
+
+    pre: [rows, units] pre-activations without the bias.  The unit's threshold
+    -b[u] is below all of its values (always on), above all of them (always
+    off), or the midpoint of two consecutive sorted values at least 2 * margin
+    apart (on for the rows above it); of these, the one whose active fraction
+    is closest to MARGIN_TARGETS[u % 5] is taken."""
+    n, units = pre.shape
+    v, _ = torch.sort(pre.detach(), dim=0)
+    ok = torch.ones(n + 1, units, dtype=torch.bool)
+    ok[1:n] = (v[1:] - v[:-1]) >= 2 * margin
+    frac = (n - torch.arange(n + 1, dtype=F64)) / n            # rows above threshold k
+    tgt = torch.tensor(MARGIN_TARGETS, dtype=F64)[torch.arange(units) % len(MARGIN_TARGETS)]
+    score = (frac[:, None] - tgt[None, :]).abs()
+    score[~ok] = math.inf
+    k = score.argmin(0)
+    below = torch.where(k == 0, v[0] - 2 * margin, v[(k - 1).clamp(min=0), torch.arange(units)])
+    above = torch.where(k == n, v[n - 1] + 2 * margin, v[k.clamp(max=n - 1), torch.arange(units)])
+    return -(below + above) / 2
 
 
 def outer_product_mean(m, msa_mask, p, eps=1e-5, opm_eps=1e-3):
@@ -223,7 +253,7 @@ def tri_att_end(z, pair_mask, p, heads, head_dim, eps=1e-5):
     return (g * o).reshape(R, R, H * c) @ p["w_o"] + p["b_o"]
 
 
-def block(m, z, msa_mask, pair_mask, p, cfg, relu_decision=None):
+def block(m, z, msa_mask, pair_mask, p, cfg, probe=None):
     """One Evoformer block (the extra-MSA block when cfg.extra_msa): residual
     MSA stack, outer product mean, residual pair stack."""
     eps = cfg.ln_eps
@@ -233,13 +263,13 @@ def block(m, z, msa_mask, pair_mask, p, cfg, relu_decision=None):
                                 eps, cfg.global_eps)
     else:
         m = m + col_attn(m, msa_mask, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim, eps)
-    m = m + transition(m, p["msa_trans"], eps, relu_decision)
+    m = m + transition(m, p["msa_trans"], eps, probe)
     z = z + outer_product_mean(m, msa_mask, p["opm"], eps, cfg.opm_eps)
     z = z + tri_mul_out(z, pair_mask, p["tri_mul_out"], eps)
     z = z + tri_mul_in(z, pair_mask, p["tri_mul_in"], eps)
     z = z + tri_att_start(z, pair_mask, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps)
     z = z + tri_att_end(z, pair_mask, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps)
-    z = z + transition(z, p["pair_trans"], eps, relu_decision)
+    z = z + transition(z, p["pair_trans"], eps, probe)
     return m, z
 
 
@@ -252,12 +282,12 @@ def _store(t, boundary):
     raise ValueError(boundary)
 
 
-def stack(m, z, msa_mask, pair_mask, blocks, cfg, relu_decision=None, boundary=None):
+def stack(m, z, msa_mask, pair_mask, blocks, cfg, boundary=None, probe=None):
     """Blocks applied in sequence with independent parameters."""
     for i, p in enumerate(blocks):
         if i > 0:
             m, z = _store(m, boundary), _store(z, boundary)
-        m, z = block(m, z, msa_mask, pair_mask, p, cfg, relu_decision)
+        m, z = block(m, z, msa_mask, pair_mask, p, cfg, probe)
     return m, z
 
 
@@ -265,7 +295,7 @@ def _leaf(t):
     return t.detach().clone().to(F64).requires_grad_(True)
 
 
-def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None, boundary=None):
+def stack_fwd_bwd(inp, cfg, want_param_grads=True, boundary=None):
     """Forward and backward of the stack on float64 copies of ``inp``.
 
     Returns (m_out, z_out, grads) with grads = {"m", "z", "params"} where
@@ -284,7 +314,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None, boundary=
             if i > 0:
                 mi, zi = _store(mi, boundary), _store(zi, boundary)
                 acts[-1] = (mi, zi)
-            acts.append(block(mi, zi, msa_mask, pair_mask, p, cfg, relu_decision))
+            acts.append(block(mi, zi, msa_mask, pair_mask, p, cfg))
     dm = inp["dm_out"].to(F64)
     dz = inp["dz_out"].to(F64)
     pgrads = [None] * len(inp["params"])
@@ -294,7 +324,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None, boundary=
         blk = inp["params"][i]
         leaves = {s: {k: (_leaf(v) if want_param_grads else v.detach().to(F64))
                       for k, v in blk[s].items()} for s in blk}
-        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg, relu_decision)
+        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg)
         ((mo * dm).sum() + (zo * dz).sum()).backward()
         dm, dz = m.grad, z.grad
         if i > 0:
@@ -307,7 +337,101 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, relu_decision=None, boundary=
     return acts[-1][0], acts[-1][1], grads
 
 
-def stack_fwd(inp, cfg, relu_decision=None, boundary=None):
+def stack_fwd(inp, cfg, boundary=None, probe=None):
     with torch.no_grad():
         return stack(inp["m"].to(F64), inp["z"].to(F64), inp["msa_mask"].to(F64),
-                     inp["pair_mask"].to(F64), inp["params"], cfg, relu_decision, boundary)
+                     inp["pair_mask"].to(F64), inp["params"], cfg, boundary, probe)
+
+
+def relu_margin(inp, cfg, boundary=None):
+    """Smallest |pre-activation| over every transition of the stack's forward."""
+    probe = {}
+    stack_fwd(inp, cfg, boundary, probe)
+    return min(probe["min_abs"])
+
+
+def with_relu_margins(inp, cfg, margin, boundary=None):
+    """A copy of ``inp`` whose transitions' b_1 are re-chosen (relu_margin_bias)
+    on this oracle's forward of the stack, transition by transition in forward
+    order, so that every ReLU pre-activation is at least ``margin`` from zero:
+    gradients are then unambiguous at any precision whose pre-activation error
+    stays below the margin.  Asserts the margin on a fresh forward."""
+    out = dict(inp)
+    out["params"] = [{s: {k: v.clone() for k, v in blk[s].items()} for s in blk} for blk in inp["params"]]
+    stack_fwd(out, cfg, boundary, {"choose": margin})
+    got = relu_margin(out, cfg, boundary)
+    assert got >= margin * (1 - 1e-9), f"ReLU margin {got} < {margin}"
+    return out
+
+
+# ---------------------------------------------------------------- selected output rows
+# The pair-stack operators evaluated for a few output rows only, from the full
+# input: the same definitions as above with the query (or output) row index
+# restricted to ``rows``.  They let a long chain (N_res = 1024, whose full
+# triangle-attention logits would take tens of GB in float64) be checked on
+# sampled rows.  Each returns the update for those rows, [len(rows), R, C]
+# (columns [R, len(cols), C] for the ending-node attention).
+
+def tri_att_start_rows(z, pair_mask, p, heads, head_dim, rows, eps=1e-5):
+    """Rows i in ``rows`` of tri_att_start: o_ij = g_ij * sum_k softmax_k(q_ij . k_ik /
+    sqrt(c) + b_jk) v_ik; the bias b_jk needs LayerNorm(z) at every (j, k)."""
+    R = z.shape[0]
+    H, c = heads, head_dim
+    rows = torch.as_tensor(rows)
+    y = layer_norm(z, p["ln_g"], p["ln_b"], eps)
+    bias = (y @ p["w_bias"]).permute(2, 0, 1)                      # [H, j, k]
+    yr = y[rows]                                                   # [n, R, C]
+    n = yr.shape[0]
+    q = (yr @ p["w_q"]).reshape(n, R, H, c)
+    k = (yr @ p["w_k"]).reshape(n, R, H, c)
+    v = (yr @ p["w_v"]).reshape(n, R, H, c)
+    logits = torch.einsum("ijhc,ikhc->ihjk", q, k) / math.sqrt(c) + bias[None]
+    a = masked_softmax(logits, pair_mask[rows][:, None, None, :])
+    o = torch.einsum("ihjk,ikhc->ijhc", a, v)
+    g = torch.sigmoid(yr @ p["w_g"] + p["b_g"]).reshape(n, R, H, c)
+    return (g * o).reshape(n, R, H * c) @ p["w_o"] + p["b_o"]
+
+
+def tri_att_end_cols(z, pair_mask, p, heads, head_dim, cols, eps=1e-5):
+    """Columns j in ``cols`` of tri_att_end: o_ij = g_ij * sum_k softmax_k(q_ij . k_kj /
+    sqrt(c) + b_ki) v_kj, keys masked by P_kj; returns [R, len(cols), C]."""
+    R = z.shape[0]
+    H, c = heads, head_dim
+    cols = torch.as_tensor(cols)
+    y = layer_norm(z, p["ln_g"], p["ln_b"], eps)
+    bias = (y @ p["w_bias"]).permute(2, 0, 1)                      # [H, k, i]
+    yc = y[:, cols]                                                # [R, n, C]
+    n = yc.shape[1]
+    q = (yc @ p["w_q"]).reshape(R, n, H, c)
+    k = (yc @ p["w_k"]).reshape(R, n, H, c)
+    v = (yc @ p["w_v"]).reshape(R, n, H, c)
+    logits = torch.einsum("ijhc,kjhc->jhik", q, k) / math.sqrt(c) + bias.transpose(1, 2)[None]
+    a = masked_softmax(logits, pair_mask[:, cols].t()[:, None, None, :])
+    o = torch.einsum("jhik,kjhc->ijhc", a, v)
+    g = torch.sigmoid(yc @ p["w_g"] + p["b_g"]).reshape(R, n, H, c)
+    return (g * o).reshape(R, n, H * c) @ p["w_o"] + p["b_o"]
+
+
+def tri_mul_rows(z, pair_mask, p, direction, rows, eps=1e-5):
+    """Rows i in ``rows`` of tri_mul_out (x_ij = sum_k a_ik b_jk) or tri_mul_in
+    (x_ij = sum_k a_ki b_kj), then g * Linear_o(LayerNorm_out(x))."""
+    rows = torch.as_tensor(rows)
+    a, b, g = _tri_mul_proj(z, pair_mask, p, eps)
+    if direction == "out":
+        x = torch.einsum("ikc,jkc->ijc", a[rows], b)
+    else:
+        x = torch.einsum("kic,kjc->ijc", a[:, rows], b)
+    return g[rows] * (layer_norm(x, p["ln_out_g"], p["ln_out_b"], eps) @ p["w_o"] + p["b_o"])
+
+
+def outer_product_mean_rows(m, msa_mask, p, rows, eps=1e-5, opm_eps=1e-3):
+    """Rows i in ``rows`` of outer_product_mean: O_ij = sum_s a_si (x) b_sj / (eps + n_ij)."""
+    rows = torch.as_tensor(rows)
+    R = m.shape[1]
+    y = layer_norm(m, p["ln_g"], p["ln_b"], eps)
+    a = msa_mask[..., None] * (y @ p["w_a"] + p["b_a"])
+    b = msa_mask[..., None] * (y @ p["w_b"] + p["b_b"])
+    c = a.shape[-1]
+    outer = torch.einsum("sip,sjq->ijpq", a[:, rows], b).reshape(len(rows), R, c * c)
+    norm = msa_mask[:, rows].t() @ msa_mask
+    return (outer / (opm_eps + norm[..., None])) @ p["w_o"] + p["b_o"]

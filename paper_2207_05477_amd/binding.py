@@ -32,6 +32,33 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check(t, what: str, dtype=None, numel=None, device=None):
+    """Raise ValueError unless `t` (None allowed) has the dtype, element count
+    and device the descriptor implies: the ABI takes raw pointers and cannot
+    tell a wrong buffer from a right one."""
+    if t is None:
+        return
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {numel}")
+    if device is not None and t.device != torch.device(device):
+        raise ValueError(f"{what}: on {t.device}, expected {device}")
+
+
+def _acts(dtype_code: int, device, **tensors):
+    """Activation tensors: the descriptor's dtype, the given element counts, one device."""
+    dt = torch.bfloat16 if dtype_code == A.EVO_BF16 else torch.float32
+    for name, (t, n) in tensors.items():
+        _check(t, name, dt, n, device)
+
+
+def _masks(device, **tensors):
+    """Masks: FP32 0/1 arrays of the given element counts (None = all ones)."""
+    for name, (t, n) in tensors.items():
+        _check(t, name, torch.float32, n, device)
+
+
 def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -177,6 +204,11 @@ def evoformer_block_fwd(cfg, flat: FlatParams, m, z, msa_mask=None, pair_mask=No
     w = flat.block_struct()
     m_out = torch.empty_like(m) if m_out is None else m_out
     z_out = torch.empty_like(z) if z_out is None else z_out
+    SR, RR = d.n_seq * d.n_res, d.n_res * d.n_res
+    _acts(d.dtype, m.device, m=(m, SR * d.c_m), z=(z, RR * d.c_z), m_out=(m_out, SR * d.c_m),
+          z_out=(z_out, RR * d.c_z))
+    _masks(m.device, msa_mask=(msa_mask, SR), pair_mask=(pair_mask, RR))
+    _check(flat.buffer, "parameters", torch.float32, flat.numel, m.device)
     nbytes = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_FWD)
     if nbytes == 0:
         A.check(A.EVO_ESHAPE, "evoformer_block_workspace_bytes")
@@ -197,6 +229,12 @@ def evoformer_block_bwd(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, dm_out
     dw = flat.block_struct(dflat)
     dm = torch.empty_like(dm_out) if dm is None else dm
     dz = torch.empty_like(dz_out) if dz is None else dz
+    SR, RR = d.n_seq * d.n_res, d.n_res * d.n_res
+    _acts(d.dtype, m.device, m=(m, SR * d.c_m), z=(z, RR * d.c_z), dm_out=(dm_out, SR * d.c_m),
+          dz_out=(dz_out, RR * d.c_z), dm=(dm, SR * d.c_m), dz=(dz, RR * d.c_z))
+    _masks(m.device, msa_mask=(msa_mask, SR), pair_mask=(pair_mask, RR))
+    _check(flat.buffer, "parameters", torch.float32, flat.numel, m.device)
+    _check(dflat, "parameter gradients", torch.float32, flat.numel, m.device)
     nbytes = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
     if nbytes == 0:
         A.check(A.EVO_ESHAPE, "evoformer_block_workspace_bytes")
@@ -209,9 +247,19 @@ def evoformer_block_bwd(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, dm_out
 
 
 # ------------------------------------------------------------------ per-op entry points
+def _attn_check(desc, x, pair, mask, **acts):
+    rows = desc.n_outer * desc.n_inner
+    _acts(desc.dtype, x.device, x=(x, rows * desc.c_in),
+          **{k: (t, rows * desc.c_in) for k, t in acts.items()})
+    if desc.kind == A.EVO_ATTN_ROW:
+        _acts(desc.dtype, x.device, pair=(pair, desc.n_inner * desc.n_inner * desc.c_pair))
+    _masks(x.device, mask=(mask, rows))
+
+
 def evo_attn_fwd(desc, w_struct, x, pair=None, mask=None, out=None, keep_saved=True):
     lib = _lib()
     out = torch.empty_like(x) if out is None else out
+    _attn_check(desc, x, pair, mask, out=out)
     saved = None
     if keep_saved:
         saved = torch.empty(max(lib.evo_attn_saved_bytes(ctypes.byref(desc)), 256), dtype=torch.uint8,
@@ -226,6 +274,9 @@ def evo_attn_fwd(desc, w_struct, x, pair=None, mask=None, out=None, keep_saved=T
 def evo_attn_bwd(desc, w_struct, x, pair, mask, saved, d_out, dw_struct, d_x=None, d_pair=None):
     lib = _lib()
     d_x = torch.empty_like(d_out) if d_x is None else d_x
+    _attn_check(desc, x, pair, mask, d_out=d_out, d_x=d_x)
+    if desc.kind == A.EVO_ATTN_ROW:
+        _acts(desc.dtype, x.device, d_pair=(d_pair, desc.n_inner * desc.n_inner * desc.c_pair))
     nbytes = lib.evo_attn_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD)
     ws = workspace(nbytes, x.device)
     A.check(lib.evo_attn_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(x), _ptr(pair), _ptr(mask),
@@ -237,6 +288,7 @@ def evo_attn_bwd(desc, w_struct, x, pair, mask, saved, d_out, dw_struct, d_x=Non
 def evo_transition_fwd(desc, w_struct, x, out=None, keep_saved=True):
     lib = _lib()
     out = torch.empty_like(x) if out is None else out
+    _acts(desc.dtype, x.device, x=(x, desc.rows * desc.c), out=(out, desc.rows * desc.c))
     saved = None
     if keep_saved:
         saved = torch.empty(max(lib.evo_transition_saved_bytes(ctypes.byref(desc)), 256),
@@ -251,6 +303,8 @@ def evo_transition_fwd(desc, w_struct, x, out=None, keep_saved=True):
 def evo_transition_bwd(desc, w_struct, x, saved, d_out, dw_struct, d_x=None):
     lib = _lib()
     d_x = torch.empty_like(d_out) if d_x is None else d_x
+    n = desc.rows * desc.c
+    _acts(desc.dtype, x.device, x=(x, n), d_out=(d_out, n), d_x=(d_x, n))
     ws = workspace(lib.evo_transition_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD), x.device)
     A.check(lib.evo_transition_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(x), _ptr(saved),
                                    _ptr(d_out), _ptr(d_x), ctypes.byref(dw_struct), _ptr(ws), ws.numel(),
@@ -261,6 +315,9 @@ def evo_transition_bwd(desc, w_struct, x, saved, d_out, dw_struct, d_x=None):
 def opm_fwd(desc, w_struct, m, msa_mask, z_in, z_out=None, keep_saved=True):
     lib = _lib()
     z_out = torch.empty_like(z_in) if z_out is None else z_out
+    SR, RR = desc.n_seq * desc.n_res, desc.n_res * desc.n_res
+    _acts(desc.dtype, m.device, m=(m, SR * desc.c_m), z_in=(z_in, RR * desc.c_z), z_out=(z_out, RR * desc.c_z))
+    _masks(m.device, msa_mask=(msa_mask, SR))
     saved = None
     if keep_saved:
         saved = torch.empty(max(lib.opm_saved_bytes(ctypes.byref(desc)), 256), dtype=torch.uint8,
@@ -274,6 +331,9 @@ def opm_fwd(desc, w_struct, m, msa_mask, z_in, z_out=None, keep_saved=True):
 def opm_bwd(desc, w_struct, m, msa_mask, saved, dz_out, d_m, dw_struct):
     """d_m is accumulated into."""
     lib = _lib()
+    SR, RR = desc.n_seq * desc.n_res, desc.n_res * desc.n_res
+    _acts(desc.dtype, m.device, m=(m, SR * desc.c_m), dz_out=(dz_out, RR * desc.c_z), d_m=(d_m, SR * desc.c_m))
+    _masks(m.device, msa_mask=(msa_mask, SR))
     ws = workspace(lib.opm_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD), m.device)
     A.check(lib.opm_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(m), _ptr(msa_mask), _ptr(saved),
                         _ptr(dz_out), _ptr(d_m), ctypes.byref(dw_struct), _ptr(ws), ws.numel(),
@@ -284,6 +344,9 @@ def opm_bwd(desc, w_struct, m, msa_mask, saved, dz_out, d_m, dw_struct):
 def tri_mul_fwd(desc, w_struct, z, pair_mask, z_out=None, keep_saved=True):
     lib = _lib()
     z_out = torch.empty_like(z) if z_out is None else z_out
+    RR = desc.n_res * desc.n_res
+    _acts(desc.dtype, z.device, z=(z, RR * desc.c_z), z_out=(z_out, RR * desc.c_z))
+    _masks(z.device, pair_mask=(pair_mask, RR))
     saved = None
     if keep_saved:
         saved = torch.empty(max(lib.tri_mul_saved_bytes(ctypes.byref(desc)), 256), dtype=torch.uint8,
@@ -297,6 +360,9 @@ def tri_mul_fwd(desc, w_struct, z, pair_mask, z_out=None, keep_saved=True):
 def tri_mul_bwd(desc, w_struct, z, pair_mask, saved, dz_out, dw_struct, dz=None):
     lib = _lib()
     dz = torch.empty_like(dz_out) if dz is None else dz
+    RR = desc.n_res * desc.n_res
+    _acts(desc.dtype, z.device, z=(z, RR * desc.c_z), dz_out=(dz_out, RR * desc.c_z), dz=(dz, RR * desc.c_z))
+    _masks(z.device, pair_mask=(pair_mask, RR))
     ws = workspace(lib.tri_mul_workspace_bytes(ctypes.byref(desc), A.EVO_PHASE_BWD), z.device)
     A.check(lib.tri_mul_bwd(ctypes.byref(desc), ctypes.byref(w_struct), _ptr(z), _ptr(pair_mask),
                             _ptr(saved), _ptr(dz_out), _ptr(dz), ctypes.byref(dw_struct), _ptr(ws),

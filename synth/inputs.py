@@ -117,23 +117,11 @@ def to_storage(x: torch.Tensor, dtype: str) -> torch.Tensor:
     raise ValueError(dtype)
 
 
-# Weight matrices a BF16 implementation feeds to its matrix cores (the pair-bias
-# projections w_bias are applied in FP32 and are not among them).
-def is_matrix_operand(name: str) -> bool:
-    return name.startswith("w_") and name != "w_bias"
-
-
-def round_inputs(inp: dict, dtype: str, params_dtype: str = "f32", weights_dtype: str | None = None) -> dict:
-    """The same inputs as the device computes with: activations and upstream
-    gradients rounded to ``dtype``, parameters to ``params_dtype`` and, if
-    given, the matrix-operand weights to ``weights_dtype``; masks exact."""
+def round_inputs(inp: dict, dtype: str, params_dtype: str = "f32") -> dict:
+    """The same inputs as the device receives them: activations and upstream
+    gradients rounded to ``dtype``, parameters to ``params_dtype``; masks exact."""
     out = dict(inp)
-
-    def rp(name, v):
-        if weights_dtype is not None and is_matrix_operand(name):
-            return to_storage(v, weights_dtype)
-        return to_storage(v, params_dtype)
-    out["params"] = [{s: {k: rp(k, v) for k, v in blk[s].items()}
+    out["params"] = [{s: {k: to_storage(v, params_dtype) for k, v in blk[s].items()}
                       for s in blk} for blk in inp["params"]]
     for k in ("m", "z", "dm_out", "dz_out"):
         if k in inp:

@@ -154,3 +154,21 @@ def test_workspace_query_matches_a_real_call(name):
                                      _fake(5), _fake(6), _fake(7), _fake(8), ctypes.byref(dw), _fake(9), need_b,
                                      None)
         assert st in (A.EVO_EHIP, A.EVO_EUNSUPPORTED), lib.evo_last_error()
+
+
+def test_binding_rejects_wrong_dtype_shape_and_device():
+    # the binding checks what the raw-pointer ABI cannot: dtype, element count, device
+    import torch
+    from paper_2207_05477_amd import binding as B
+    m = torch.zeros(2, 8, 8)
+    with pytest.raises(ValueError, match="dtype"):
+        B._acts(B.A.EVO_BF16, m.device, m=(m, m.numel()))
+    with pytest.raises(ValueError, match="elements"):
+        B._acts(B.A.EVO_F32, m.device, m=(m, 7))
+    with pytest.raises(ValueError, match="dtype"):
+        B._masks(m.device, msa_mask=(torch.ones(16, dtype=torch.bool), 16))
+    with pytest.raises(ValueError, match="elements"):
+        B._masks(m.device, msa_mask=(torch.ones(15), 16))
+    with pytest.raises(ValueError, match="on cpu"):
+        B._check(m, "m", torch.float32, m.numel(), "meta")
+    B._acts(B.A.EVO_F32, m.device, m=(m, m.numel()), z=(None, 3))

@@ -4,8 +4,10 @@ The paper's Subbatch splits a batch-like axis whose computation is
 independent (Section "Subbatch VS DAP"), so chunking must not change the
 result.  Checked per op against the oracle at a small shape, per op and per
 block chunked vs unchunked on the GPU (same per-row arithmetic, so equal to the
-last bit), and for the whole block at the long-chain shape N_res = 1024 with
-128-row chunks.
+last bit), for the whole block at the long-chain shape N_res = 1024 with
+128-row chunks, and per op at that shape against the oracle on sampled output
+rows (the first, a middle and the last row of the chunk grid, where whole and
+ragged query blocks and the chunk seams meet).
 """
 import pytest
 import torch
@@ -81,7 +83,7 @@ def test_chunked_block_equals_unchunked_small(dtype):
     (m0, z0), (m1, z1), inp = _block_chunk_pair(CCFG.replace(chunk=16), dtype, seed=12)
     assert torch.equal(m0, m1)
     assert torch.equal(z0, z1)
-    mo_ref, zo_ref = O.stack_fwd(inp, CCFG, relu_decision="bf16" if dtype == "bf16" else None)
+    mo_ref, zo_ref = O.stack_fwd(inp, CCFG)
     check("z update", z1.double().cpu() - inp["z"], zo_ref - inp["z"], TOL[dtype])
 
 
@@ -93,3 +95,51 @@ def test_chunked_block_long_chain_bf16():
     assert torch.isfinite(z1.float()).all()
     assert torch.equal(m0, m1)
     assert torch.equal(z0, z1)
+
+
+# rows of the long chain checked against the oracle: first and last row, the
+# two rows on either side of a chunk seam, and one inside a chunk
+C4B_ROWS = [0, 127, 128, 511, 1023]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("op", ["tri_att_start", "tri_att_end", "tri_mul_out", "tri_mul_in", "opm"])
+def test_chunked_op_long_chain_sampled_rows_vs_oracle(op):
+    from paper_2207_05477_amd import binding as B, _abi as A
+    cfg = get("C4b")
+    dtype = "bf16"
+    say(f"long chain {op}: N_res={cfg.n_res}, chunk {cfg.chunk}")
+    inp = device_view(make_inputs(cfg, seed=32, with_grads=False), dtype)
+    p = inp["params"][0][op]
+    w = B.weight_struct(op, params_dev(p))
+    z = to_dev(inp["z"], dtype)
+    P = inp["pair_mask"].float().cuda()
+    R = cfg.n_res
+    if op.startswith("tri_att"):
+        kind = A.EVO_ATTN_TRI_START if op.endswith("start") else A.EVO_ATTN_TRI_END
+        d = B.attn_desc(kind, dtype, R, R, cfg.c_z, cfg.tri_heads, cfg.tri_head_dim, chunk=cfg.chunk)
+        out, _ = B.evo_attn_fwd(d, w, z, None, P, keep_saved=False)
+    elif op.startswith("tri_mul"):
+        dirn = A.EVO_TRI_OUT if op.endswith("out") else A.EVO_TRI_IN
+        d = B.trimul_desc(dtype, dirn, R, cfg.c_z, cfg.tri_mul_hidden, chunk=cfg.chunk)
+        out, _ = B.tri_mul_fwd(d, w, z, P, keep_saved=False)
+    else:
+        m, M = to_dev(inp["m"], dtype), inp["msa_mask"].float().cuda()
+        d = B.opm_desc(dtype, cfg.n_seq, R, cfg.c_m, cfg.opm_hidden, cfg.c_z, opm_eps=cfg.opm_eps,
+                       chunk=cfg.chunk)
+        out, _ = B.opm_fwd(d, w, m, M, z, keep_saved=False)
+    torch.cuda.synchronize()
+    rows = torch.tensor(C4B_ROWS)
+    say("  oracle rows", C4B_ROWS)
+    if op == "tri_att_end":
+        got = out[:, rows].double().cpu() - inp["z"][:, rows]
+        ref = O.tri_att_end_cols(inp["z"], inp["pair_mask"], p, cfg.tri_heads, cfg.tri_head_dim, rows)
+    else:
+        got = out[rows].double().cpu() - inp["z"][rows]
+        if op == "tri_att_start":
+            ref = O.tri_att_start_rows(inp["z"], inp["pair_mask"], p, cfg.tri_heads, cfg.tri_head_dim, rows)
+        elif op.startswith("tri_mul"):
+            ref = O.tri_mul_rows(inp["z"], inp["pair_mask"], p, op[-3:].strip("_"), rows)
+        else:
+            ref = O.outer_product_mean_rows(inp["m"], inp["msa_mask"], p, rows, 1e-5, cfg.opm_eps)
+    check(f"{op} sampled rows", got, ref, TOL[dtype])

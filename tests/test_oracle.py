@@ -422,19 +422,79 @@ def test_golden_logits_memory_example():
         assert math.isclose(got, exp, rel_tol=1e-12), (cse, got)
 
 
-def test_transition_bf16_relu_decision_only_moves_near_zero_units():
-    # The BF16 decision mode changes the ReLU mask only where the exact
-    # pre-activation is within BF16 rounding of zero; elsewhere the output is
-    # the exact one.
-    inp = _inp(TINY.replace(n_seq=6, n_res=7, c_m=16), mask_mode="full")
-    p = inp["params"][0]["msa_trans"]
-    x = inp["m"]
-    exact = O.transition(x, p)
-    dec = O.transition(x, p, 1e-5, "bf16")
-    y = F.layer_norm(x, (x.shape[-1],), p["ln_g"], p["ln_b"], eps=1e-5)
-    pre = y @ p["w_1"] + p["b_1"]
-    pre_b = y.to(torch.bfloat16).double() @ p["w_1"].to(torch.bfloat16).double() + p["b_1"]
-    flips = (pre > 0) != (pre_b > 0)
-    assert torch.all(pre[flips].abs() < 0.05)
-    rows_clean = ~flips.any(-1)
-    _close(dec[rows_clean], exact[rows_clean], 1e-12)
+# ---------------------------------------------------------------- margin-constructed inputs
+
+def test_relu_margin_bias_clears_zero_and_follows_targets():
+    g = torch.Generator().manual_seed(3)
+    pre = torch.randn(400, 10, dtype=F64, generator=g)
+    for margin in (1e-3, 0.05):
+        b = O.relu_margin_bias(pre, margin)
+        x = pre + b
+        assert x.abs().min().item() >= margin * (1 - 1e-12)
+        frac = (x > 0).to(F64).mean(0)
+        for u in range(10):
+            t = O.MARGIN_TARGETS[u % len(O.MARGIN_TARGETS)]
+            if t in (0.0, 1.0):
+                assert frac[u].item() == t            # always-off / always-on units
+        # a unit aiming at 0.5 ends on a feasible gap, so its decisions are mixed
+        # whenever one exists (400 normal samples have gaps of 2e-3 near the tails)
+        assert 0.0 < frac[2].item() < 1.0 or margin == 0.05
+
+
+def test_relu_margin_bias_brute_force_small():
+    # brute force over every threshold between sorted values
+    pre = torch.tensor([[0.0, 1.0], [0.5, 1.02], [2.0, 3.0], [2.1, 5.0]], dtype=F64)
+    b = O.relu_margin_bias(pre, 0.2)
+    # unit 0 aims at 0.0 (always off): threshold above 2.1 by the margin
+    assert math.isclose(b[0].item(), -(2.1 + 0.2), rel_tol=1e-12)
+    # unit 1 aims at 1.0 (always on): threshold below 1.0 by the margin
+    assert math.isclose(b[1].item(), -(1.0 - 0.2), rel_tol=1e-12)
+    pre3 = torch.tensor([[0.0] * 3, [0.1] * 3, [1.0] * 3, [1.1] * 3], dtype=F64)
+    b3 = O.relu_margin_bias(pre3, 0.2)
+    # unit 2 aims at 0.5: the only interior gap >= 0.4 is (0.1, 1.0), midpoint 0.55
+    assert math.isclose(b3[2].item(), -0.55, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("boundary", [None, "bf16"])
+def test_with_relu_margins_changes_only_b1_and_holds_margin(boundary):
+    cfg = TINY.replace(n_blocks=2, n_seq=5, n_res=6)
+    inp = make_inputs(cfg, seed=9, perturb=True)
+    out = O.with_relu_margins(inp, cfg, 0.05, boundary)
+    assert O.relu_margin(out, cfg, boundary) >= 0.05 * (1 - 1e-9)
+    for bi, (pa, pb) in enumerate(zip(inp["params"], out["params"])):
+        for sub in pa:
+            for k in pa[sub]:
+                same = torch.equal(pa[sub][k], pb[sub][k])
+                assert same == (not (sub in ("msa_trans", "pair_trans") and k == "b_1")), (bi, sub, k)
+    # the oracle's gradients on the constructed inputs agree with a central
+    # difference taken with steps that stay inside the margin
+    m_out, z_out, grads = O.stack_fwd_bwd(out, cfg, boundary=None)
+    g = torch.Generator().manual_seed(2)
+    vm = torch.randn(inp["m"].shape, dtype=F64, generator=g)
+    h = 1e-6
+
+    def loss(dm_):
+        x = dict(out); x["m"] = out["m"] + dm_
+        mo, zo = O.stack_fwd(x, cfg)
+        return (mo * out["dm_out"]).sum() + (zo * out["dz_out"]).sum()
+    fd = (loss(h * vm) - loss(-h * vm)) / (2 * h)
+    an = (grads["m"] * vm).sum()
+    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+# ---------------------------------------------------------------- selected rows
+
+def test_row_restricted_pair_ops_equal_full_ops():
+    cfg = TINY.replace(n_res=7, c_z=6, n_seq=4)
+    inp = make_inputs(cfg, seed=17, perturb=True)
+    z, P, M, m = inp["z"], inp["pair_mask"], inp["msa_mask"], inp["m"]
+    blk = inp["params"][0]
+    rows = [0, 3, 6]
+    H, c = cfg.tri_heads, cfg.tri_head_dim
+    _close(O.tri_att_start_rows(z, P, blk["tri_att_start"], H, c, rows),
+           O.tri_att_start(z, P, blk["tri_att_start"], H, c)[rows], 1e-12)
+    _close(O.tri_att_end_cols(z, P, blk["tri_att_end"], H, c, rows),
+           O.tri_att_end(z, P, blk["tri_att_end"], H, c)[:, rows], 1e-12)
+    _close(O.tri_mul_rows(z, P, blk["tri_mul_out"], "out", rows), O.tri_mul_out(z, P, blk["tri_mul_out"])[rows], 1e-12)
+    _close(O.tri_mul_rows(z, P, blk["tri_mul_in"], "in", rows), O.tri_mul_in(z, P, blk["tri_mul_in"])[rows], 1e-12)
+    _close(O.outer_product_mean_rows(m, M, blk["opm"], rows), O.outer_product_mean(m, M, blk["opm"])[rows], 1e-12)
