@@ -253,24 +253,77 @@ def tri_att_end(z, pair_mask, p, heads, head_dim, eps=1e-5):
     return (g * o).reshape(R, R, H * c) @ p["w_o"] + p["b_o"]
 
 
-def block(m, z, msa_mask, pair_mask, p, cfg, probe=None):
+# Sub-operation numbers of a block (the dropout generator's counter word 1).
+SUBOP_ID = {"row_attn": 0, "col_attn": 1, "msa_trans": 2, "opm": 3, "tri_mul_out": 4, "tri_mul_in": 5,
+            "tri_att_start": 6, "tri_att_end": 7, "pair_trans": 8}
+
+
+def drop(x, dropout, sub, orient, rate, template=0):
+    """Shared dropout of a residual update x [A, B, C] (AlphaFold2's dropout,
+    which the paper keeps by following its settings): one multiplier per
+    (B, C) shared along axis 0 ("row"), or per (A, C) shared along axis 1
+    ("col"), 0 or 1 / (1 - rate), drawn by oracle.philox from the counter
+    (element, sub-operation | template << 8, offset).  dropout: None (off) or
+    (seed, offset)."""
+    if dropout is None or rate == 0.0:
+        return x
+    from . import philox
+    seed, offset = dropout
+    n_idx = x.shape[1] if orient == "row" else x.shape[0]
+    word = SUBOP_ID[sub] | (template << 8)
+    mask = torch.from_numpy(philox.dropout_mask(seed, offset, word, n_idx, x.shape[-1], rate))
+    return x * (mask[None] if orient == "row" else mask[:, None])
+
+
+def block(m, z, msa_mask, pair_mask, p, cfg, probe=None, dropout=None):
     """One Evoformer block (the extra-MSA block when cfg.extra_msa): residual
-    MSA stack, outer product mean, residual pair stack."""
+    MSA stack, outer product mean, residual pair stack.  cfg.opm_first puts the
+    outer product mean first (z <- z + OPM(m) on the block's input m): the MSA
+    stack and the pair stack then depend only on (m, z + OPM(m)), the two
+    independent branches Branch Parallelism runs on two devices (Section
+    "Branch Parallelism").  dropout: None or (seed, offset), see drop()."""
     eps = cfg.ln_eps
-    m = m + row_attn(m, z, msa_mask, p["row_attn"], cfg.msa_heads, cfg.msa_head_dim, eps)
+    if cfg.opm_first:
+        z = z + outer_product_mean(m, msa_mask, p["opm"], eps, cfg.opm_eps)
+    m = m + drop(row_attn(m, z, msa_mask, p["row_attn"], cfg.msa_heads, cfg.msa_head_dim, eps),
+                 dropout, "row_attn", "row", cfg.drop_row_attn)
     if cfg.extra_msa:
         m = m + col_global_attn(m, msa_mask, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim,
                                 eps, cfg.global_eps)
     else:
         m = m + col_attn(m, msa_mask, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim, eps)
     m = m + transition(m, p["msa_trans"], eps, probe)
-    z = z + outer_product_mean(m, msa_mask, p["opm"], eps, cfg.opm_eps)
-    z = z + tri_mul_out(z, pair_mask, p["tri_mul_out"], eps)
-    z = z + tri_mul_in(z, pair_mask, p["tri_mul_in"], eps)
-    z = z + tri_att_start(z, pair_mask, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps)
-    z = z + tri_att_end(z, pair_mask, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps)
+    if not cfg.opm_first:
+        z = z + outer_product_mean(m, msa_mask, p["opm"], eps, cfg.opm_eps)
+    z = z + drop(tri_mul_out(z, pair_mask, p["tri_mul_out"], eps), dropout, "tri_mul_out", "row",
+                 cfg.drop_tri_mul)
+    z = z + drop(tri_mul_in(z, pair_mask, p["tri_mul_in"], eps), dropout, "tri_mul_in", "row",
+                 cfg.drop_tri_mul)
+    z = z + drop(tri_att_start(z, pair_mask, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps),
+                 dropout, "tri_att_start", "row", cfg.drop_tri_att)
+    z = z + drop(tri_att_end(z, pair_mask, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps),
+                 dropout, "tri_att_end", "col", cfg.drop_tri_att)
     z = z + transition(z, p["pair_trans"], eps, probe)
     return m, z
+
+
+def template_pair_block(t, pair_mask, p, cfg, probe=None, dropout=None, template=0):
+    """One block of the template pair stack (AlphaFold2's TemplatePairStack,
+    which the paper's initial-training forward includes as TemplateEmbedding):
+    the pair-stack operators on one template's pair features t [R, R, c_t],
+    in the order triangle attention around the starting node, around the
+    ending node, outgoing and incoming triangle multiplication, transition."""
+    eps = cfg.ln_eps
+    H, c = cfg.tri_heads, cfg.tri_head_dim
+    t = t + drop(tri_att_start(t, pair_mask, p["tri_att_start"], H, c, eps), dropout, "tri_att_start", "row",
+                 cfg.drop_tri_att, template)
+    t = t + drop(tri_att_end(t, pair_mask, p["tri_att_end"], H, c, eps), dropout, "tri_att_end", "col",
+                 cfg.drop_tri_att, template)
+    t = t + drop(tri_mul_out(t, pair_mask, p["tri_mul_out"], eps), dropout, "tri_mul_out", "row",
+                 cfg.drop_tri_mul, template)
+    t = t + drop(tri_mul_in(t, pair_mask, p["tri_mul_in"], eps), dropout, "tri_mul_in", "row",
+                 cfg.drop_tri_mul, template)
+    return t + transition(t, p["pair_trans"], eps, probe)
 
 
 def _store(t, boundary):
@@ -282,12 +335,17 @@ def _store(t, boundary):
     raise ValueError(boundary)
 
 
-def stack(m, z, msa_mask, pair_mask, blocks, cfg, boundary=None, probe=None):
+def _block_dropout(dropout, i):
+    """Block i of a stack draws its dropout masks at offset + i."""
+    return None if dropout is None else (dropout[0], dropout[1] + i)
+
+
+def stack(m, z, msa_mask, pair_mask, blocks, cfg, boundary=None, probe=None, dropout=None):
     """Blocks applied in sequence with independent parameters."""
     for i, p in enumerate(blocks):
         if i > 0:
             m, z = _store(m, boundary), _store(z, boundary)
-        m, z = block(m, z, msa_mask, pair_mask, p, cfg, probe)
+        m, z = block(m, z, msa_mask, pair_mask, p, cfg, probe, _block_dropout(dropout, i))
     return m, z
 
 
@@ -295,7 +353,7 @@ def _leaf(t):
     return t.detach().clone().to(F64).requires_grad_(True)
 
 
-def stack_fwd_bwd(inp, cfg, want_param_grads=True, boundary=None):
+def stack_fwd_bwd(inp, cfg, want_param_grads=True, boundary=None, dropout=None):
     """Forward and backward of the stack on float64 copies of ``inp``.
 
     Returns (m_out, z_out, grads) with grads = {"m", "z", "params"} where
@@ -314,7 +372,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, boundary=None):
             if i > 0:
                 mi, zi = _store(mi, boundary), _store(zi, boundary)
                 acts[-1] = (mi, zi)
-            acts.append(block(mi, zi, msa_mask, pair_mask, p, cfg))
+            acts.append(block(mi, zi, msa_mask, pair_mask, p, cfg, None, _block_dropout(dropout, i)))
     dm = inp["dm_out"].to(F64)
     dz = inp["dz_out"].to(F64)
     pgrads = [None] * len(inp["params"])
@@ -324,7 +382,7 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, boundary=None):
         blk = inp["params"][i]
         leaves = {s: {k: (_leaf(v) if want_param_grads else v.detach().to(F64))
                       for k, v in blk[s].items()} for s in blk}
-        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg)
+        mo, zo = block(m, z, msa_mask, pair_mask, leaves, cfg, None, _block_dropout(dropout, i))
         ((mo * dm).sum() + (zo * dz).sum()).backward()
         dm, dz = m.grad, z.grad
         if i > 0:
@@ -337,10 +395,33 @@ def stack_fwd_bwd(inp, cfg, want_param_grads=True, boundary=None):
     return acts[-1][0], acts[-1][1], grads
 
 
-def stack_fwd(inp, cfg, boundary=None, probe=None):
+def stack_fwd(inp, cfg, boundary=None, probe=None, dropout=None):
     with torch.no_grad():
         return stack(inp["m"].to(F64), inp["z"].to(F64), inp["msa_mask"].to(F64),
-                     inp["pair_mask"].to(F64), inp["params"], cfg, boundary, probe)
+                     inp["pair_mask"].to(F64), inp["params"], cfg, boundary, probe, dropout)
+
+
+def template_stack_fwd_bwd(inp, cfg, dropout=None, want_param_grads=True):
+    """Forward and backward of the template pair stack on float64 copies of
+    ``inp`` (synth.make_template_inputs): every template t[n] goes through the
+    same blocks (template index n in the dropout counter); the loss is
+    <t_out, dt_out>.  Returns (t_out, grads) with grads = {"t", "params"}."""
+    t = inp["t"].detach().to(F64).requires_grad_(True)
+    P = inp["pair_mask"].to(F64)
+    leaves = [{s: {k: (v.detach().clone().to(F64).requires_grad_(want_param_grads))
+                   for k, v in blk[s].items()} for s in blk} for blk in inp["params"]]
+    outs = []
+    for n in range(t.shape[0]):
+        x = t[n]
+        for i, p in enumerate(leaves):
+            x = template_pair_block(x, P[n], p, cfg, None, _block_dropout(dropout, i), n)
+        outs.append(x)
+    out = torch.stack(outs)
+    (out * inp["dt_out"].to(F64)).sum().backward()
+    grads = {"t": t.grad}
+    if want_param_grads:
+        grads["params"] = [{s: {k: v.grad for k, v in blk[s].items()} for s in blk} for blk in leaves]
+    return out.detach(), grads
 
 
 def relu_margin(inp, cfg, boundary=None):

@@ -42,6 +42,12 @@ class EvoConfig:
     ln_eps: float = 1e-5
     opm_eps: float = 1e-3
     global_eps: float = 1e-10
+    opm_first: bool = False   # outer product mean before the MSA stack (branch-independent order)
+    # dropout rates, applied only when a run passes a (seed, offset) pair
+    drop_row_attn: float = 0.15
+    drop_tri_mul: float = 0.25
+    drop_tri_att: float = 0.25
+    n_templ: int = 4          # templates (template pair stack only)
 
     def replace(self, **kw) -> "EvoConfig":
         return dataclasses.replace(self, **kw)
@@ -83,8 +89,17 @@ C4A = C1.replace(name="c4a_finetune_bf16_stack8", n_seq=512, n_res=384, dtype="b
 C4B = C1.replace(name="c4b_long_bf16_fwd_chunked", n_seq=128, n_res=1024, dtype="bf16",
                  backward=False, chunk=128)
 
-PRESETS = {c.name: c for c in (C0, C1, C2, C3, C4A, C4B)}
-ALIASES = {"C0": C0, "C1": C1, "C2": C2, "C3": C3, "C4a": C4A, "C4b": C4B}
+# Extra-MSA block at the fine-tuning crop: N_extra = 5120, N_res = 384.
+C5 = C3.replace(name="c5_extra_msa_finetune_bf16", n_seq=5120, n_res=384)
+
+# Template pair stack block at the initial-training crop: 4 templates, c_t = 64,
+# triangle attention 4 x 16, triangle-multiplication hidden 64, transition x2.
+TEMPLATE = EvoConfig("template_pair_bf16", n_seq=1, n_res=256, c_m=8, c_z=64, msa_heads=1,
+                     msa_head_dim=8, tri_heads=4, tri_head_dim=16, tri_mul_hidden=64, opm_hidden=8,
+                     transition_factor=2, dtype="bf16", n_templ=4)
+
+PRESETS = {c.name: c for c in (C0, C1, C2, C3, C4A, C4B, C5, TEMPLATE)}
+ALIASES = {"C0": C0, "C1": C1, "C2": C2, "C3": C3, "C4a": C4A, "C4b": C4B, "C5": C5, "T": TEMPLATE}
 
 
 def get(name: str) -> EvoConfig:
@@ -96,6 +111,8 @@ def get(name: str) -> EvoConfig:
 # Sub-operations of one block, in the order the block applies them.
 SUBOPS = ("row_attn", "col_attn", "msa_trans", "opm", "tri_mul_out", "tri_mul_in",
           "tri_att_start", "tri_att_end", "pair_trans")
+# Sub-operations of one template pair stack block, in order.
+TEMPLATE_SUBOPS = ("tri_att_start", "tri_att_end", "tri_mul_out", "tri_mul_in", "pair_trans")
 
 
 def param_spec(cfg: EvoConfig):

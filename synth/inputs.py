@@ -22,7 +22,7 @@ import math
 
 import torch
 
-from .configs import EvoConfig, SUBOPS, param_spec
+from .configs import EvoConfig, SUBOPS, TEMPLATE_SUBOPS, param_spec
 
 SEED = 32
 F64 = torch.float64
@@ -48,6 +48,37 @@ def make_params(cfg: EvoConfig, gen: torch.Generator, perturb: bool = False):
             p[sub][name] = _draw_param(gen, shape, init, perturb)
         blocks.append(p)
     return blocks
+
+
+def make_template_params(cfg: EvoConfig, gen: torch.Generator, perturb: bool = False):
+    """Parameters of ``cfg.n_blocks`` template pair stack blocks (the pair-stack
+    sub-operations' tables of param_spec, in TEMPLATE_SUBOPS order)."""
+    spec = [e for e in param_spec(cfg) if e[0] in TEMPLATE_SUBOPS]
+    blocks = []
+    for _ in range(cfg.n_blocks):
+        p = {s: {} for s in TEMPLATE_SUBOPS}
+        for sub in TEMPLATE_SUBOPS:
+            for s_, name, shape, init in spec:
+                if s_ == sub:
+                    p[sub][name] = _draw_param(gen, shape, init, perturb)
+        blocks.append(p)
+    return blocks
+
+
+def make_template_inputs(cfg: EvoConfig, seed: int = SEED, perturb: bool = False, with_grads: bool = True):
+    """Template pair stack inputs: parameters, t [n_templ, R, R, c_t] ~ N(0, 1),
+    pair masks [n_templ, R, R] (all ones, or ``cfg.mask_mode`` "random" per
+    template), upstream gradient dt_out ~ N(0, 1)."""
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+    params = make_template_params(cfg, gen, perturb)
+    T, R, C = cfg.n_templ, cfg.n_res, cfg.c_z
+    t = torch.randn(T, R, R, C, generator=gen, dtype=F64)
+    masks = torch.stack([make_masks(cfg, gen)[1] for _ in range(T)])
+    out = {"params": params, "t": t, "pair_mask": masks}
+    if with_grads:
+        out["dt_out"] = torch.randn(t.shape, generator=gen, dtype=F64)
+    return out
 
 
 def make_masks(cfg: EvoConfig, gen: torch.Generator, mode: str | None = None):
@@ -123,7 +154,7 @@ def round_inputs(inp: dict, dtype: str, params_dtype: str = "f32") -> dict:
     out = dict(inp)
     out["params"] = [{s: {k: to_storage(v, params_dtype) for k, v in blk[s].items()}
                       for s in blk} for blk in inp["params"]]
-    for k in ("m", "z", "dm_out", "dz_out"):
+    for k in ("m", "z", "dm_out", "dz_out", "t", "dt_out"):
         if k in inp:
             out[k] = to_storage(inp[k], dtype)
     return out

@@ -247,19 +247,46 @@ def _add(x, u):
     return x + u
 
 
-def block(m, z, M, P, p, cfg):
+def _masked(u, mask, orient):
+    """u[a][b][c] times mask[b][c] ("row": shared along a) or mask[a][c] ("col")."""
+    if mask is None:
+        return u
+    return [[[u[a][b][c] * (mask[b][c] if orient == "row" else mask[a][c]) for c in range(len(u[a][b]))]
+             for b in range(len(u[a]))] for a in range(len(u))]
+
+
+def block(m, z, M, P, p, cfg, masks=None):
+    """masks: None or {sub-operation: [index][channel] multipliers} (dropout)."""
     eps = cfg.ln_eps
-    m = _add(m, row_attn(m, z, M, p["row_attn"], cfg.msa_heads, cfg.msa_head_dim, eps))
+    mk = masks or {}
+    if cfg.opm_first:
+        z = _add(z, outer_product_mean(m, M, p["opm"], eps, cfg.opm_eps))
+    m = _add(m, _masked(row_attn(m, z, M, p["row_attn"], cfg.msa_heads, cfg.msa_head_dim, eps),
+                        mk.get("row_attn"), "row"))
     if cfg.extra_msa:
         m = _add(m, col_global_attn(m, M, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim,
                                     eps, cfg.global_eps))
     else:
         m = _add(m, col_attn(m, M, p["col_attn"], cfg.msa_heads, cfg.msa_head_dim, eps))
     m = _add(m, transition(m, p["msa_trans"], eps))
-    z = _add(z, outer_product_mean(m, M, p["opm"], eps, cfg.opm_eps))
-    z = _add(z, tri_mul_out(z, P, p["tri_mul_out"], eps))
-    z = _add(z, tri_mul_in(z, P, p["tri_mul_in"], eps))
-    z = _add(z, tri_att_start(z, P, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps))
-    z = _add(z, tri_att_end(z, P, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps))
+    if not cfg.opm_first:
+        z = _add(z, outer_product_mean(m, M, p["opm"], eps, cfg.opm_eps))
+    z = _add(z, _masked(tri_mul_out(z, P, p["tri_mul_out"], eps), mk.get("tri_mul_out"), "row"))
+    z = _add(z, _masked(tri_mul_in(z, P, p["tri_mul_in"], eps), mk.get("tri_mul_in"), "row"))
+    z = _add(z, _masked(tri_att_start(z, P, p["tri_att_start"], cfg.tri_heads, cfg.tri_head_dim, eps),
+                        mk.get("tri_att_start"), "row"))
+    z = _add(z, _masked(tri_att_end(z, P, p["tri_att_end"], cfg.tri_heads, cfg.tri_head_dim, eps),
+                        mk.get("tri_att_end"), "col"))
     z = _add(z, transition(z, p["pair_trans"], eps))
     return m, z
+
+
+def template_block(t, P, p, cfg, masks=None):
+    eps = cfg.ln_eps
+    mk = masks or {}
+    H, c = cfg.tri_heads, cfg.tri_head_dim
+    t = _add(t, _masked(tri_att_start(t, P, p["tri_att_start"], H, c, eps), mk.get("tri_att_start"), "row"))
+    t = _add(t, _masked(tri_att_end(t, P, p["tri_att_end"], H, c, eps), mk.get("tri_att_end"), "col"))
+    t = _add(t, _masked(tri_mul_out(t, P, p["tri_mul_out"], eps), mk.get("tri_mul_out"), "row"))
+    t = _add(t, _masked(tri_mul_in(t, P, p["tri_mul_in"], eps), mk.get("tri_mul_in"), "row"))
+    return _add(t, transition(t, p["pair_trans"], eps))

@@ -498,3 +498,124 @@ def test_row_restricted_pair_ops_equal_full_ops():
     _close(O.tri_mul_rows(z, P, blk["tri_mul_out"], "out", rows), O.tri_mul_out(z, P, blk["tri_mul_out"])[rows], 1e-12)
     _close(O.tri_mul_rows(z, P, blk["tri_mul_in"], "in", rows), O.tri_mul_in(z, P, blk["tri_mul_in"])[rows], 1e-12)
     _close(O.outer_product_mean_rows(m, M, blk["opm"], rows), O.outer_product_mean(m, M, blk["opm"])[rows], 1e-12)
+
+
+# ---------------------------------------------------------------- dropout generator
+
+def test_philox_known_answer_vectors():
+    from oracle import philox
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")
+    with open(path) as f:
+        cases = json.load(f)["cases"]
+    for cse in cases:
+        ctr = [int(x, 16) for x in cse["ctr"]]
+        key = [int(x, 16) for x in cse["key"]]
+        got = philox.philox4x32_10([ctr], key)[0].tolist()
+        assert got == [int(x, 16) for x in cse["out"]], cse
+
+
+def test_dropout_mask_rate_and_scale():
+    from oracle import philox
+    m = philox.dropout_mask(seed=123, offset=7, subop=4, n_idx=256, channels=128, rate=0.25)
+    vals = set(m.ravel().tolist())
+    assert vals <= {0.0, 1.0 / (1.0 - float(torch.tensor(0.25, dtype=torch.float32)))}
+    frac = (m == 0).mean()
+    assert abs(frac - 0.25) < 0.01                    # 32768 draws: 4 sigma ~ 0.01
+    assert philox.dropout_mask(123, 7, 4, 4, 4, 0.0).min() == 1.0
+    # counters differ by sub-op and offset: the masks differ
+    a = philox.dropout_mask(1, 0, 0, 16, 16, 0.5)
+    assert not (a == philox.dropout_mask(1, 0, 1, 16, 16, 0.5)).all()
+    assert not (a == philox.dropout_mask(1, 1, 0, 16, 16, 0.5)).all()
+
+
+
+# ---------------------------------------------------------------- block variants
+
+def _dropout_masks(cfg, seed, offset, R, template=0):
+    """The dropout multipliers of each sub-operation, drawn straight from the generator."""
+    from oracle import philox
+    rates = {"row_attn": cfg.drop_row_attn, "tri_mul_out": cfg.drop_tri_mul, "tri_mul_in": cfg.drop_tri_mul,
+             "tri_att_start": cfg.drop_tri_att, "tri_att_end": cfg.drop_tri_att}
+    chans = {"row_attn": cfg.c_m}
+    return {s: philox.dropout_mask(seed, offset, O.SUBOP_ID[s] | (template << 8), R, chans.get(s, cfg.c_z),
+                                   r).tolist()
+            for s, r in rates.items()}
+
+
+@pytest.mark.parametrize("opm_first", [False, True], ids=["af2_order", "opm_first"])
+@pytest.mark.parametrize("dropout", [False, True], ids=["no_dropout", "dropout"])
+def test_block_variants_vs_brute(opm_first, dropout):
+    cfg = TINY.replace(opm_first=opm_first, drop_row_attn=0.3, drop_tri_mul=0.4, drop_tri_att=0.5)
+    inp = _inp(cfg)
+    p = inp["params"][0]
+    dr = (77, 5) if dropout else None
+    m, z = O.block(inp["m"], inp["z"], inp["msa_mask"], inp["pair_mask"], p, cfg, dropout=dr)
+    pl = {s: _pl(p[s]) for s in p}
+    masks = _dropout_masks(cfg, 77, 5, cfg.n_res) if dropout else None
+    if dropout:   # the masks really drop something at these rates
+        assert any(v == 0.0 for row in masks["tri_att_end"] for v in row)
+    bm, bz = brute.block(brute.t2l(inp["m"]), brute.t2l(inp["z"]), brute.t2l(inp["msa_mask"]),
+                         brute.t2l(inp["pair_mask"]), pl, cfg, masks)
+    _close(m, bm)
+    _close(z, bz)
+
+
+def test_opm_first_makes_the_branches_independent():
+    # OPM first: the pair stack's output does not depend on the MSA stack's
+    # parameters, and the MSA stack's output does not depend on the pair stack's
+    # (in the AlphaFold2 order the pair stack reads the updated MSA)
+    inp = _inp(TINY)
+    p = inp["params"][0]
+    p2 = {s: dict(v) for s, v in p.items()}
+    p2["msa_trans"]["w_2"] = p2["msa_trans"]["w_2"] * 3.0
+    p3 = {s: dict(v) for s, v in p.items()}
+    p3["tri_mul_out"]["w_o"] = p3["tri_mul_out"]["w_o"] * 3.0
+    args = (inp["m"], inp["z"], inp["msa_mask"], inp["pair_mask"])
+    for first in (True, False):
+        cfg = TINY.replace(opm_first=first)
+        m1, z1 = O.block(*args, p, cfg)
+        m2, z2 = O.block(*args, p2, cfg)
+        m3, z3 = O.block(*args, p3, cfg)
+        assert torch.equal(m1, m3)                     # MSA output never reads the pair stack
+        assert torch.equal(z1, z2) == first            # pair output ignores the MSA stack only when OPM is first
+
+
+def test_dropout_rate_zero_is_identity_and_masks_are_shared_along_their_axis():
+    cfg = TINY.replace(drop_row_attn=0.0, drop_tri_mul=0.0, drop_tri_att=0.0)
+    inp = _inp(cfg)
+    p = inp["params"][0]
+    args = (inp["m"], inp["z"], inp["msa_mask"], inp["pair_mask"], p)
+    a = O.block(*args, cfg)
+    b = O.block(*args, cfg, dropout=(3, 4))
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # row-wise: one multiplier per (j, c) for every i; column-wise: per (i, c) for every j
+    x = torch.ones(5, 6, 7, dtype=F64)
+    r = O.drop(x, (9, 1), "tri_mul_out", "row", 0.5)
+    assert torch.equal(r, r[:1].expand_as(r))
+    c = O.drop(x, (9, 1), "tri_att_end", "col", 0.5)
+    assert torch.equal(c, c[:, :1].expand_as(c))
+
+
+def test_template_block_vs_brute_and_gradcheck():
+    from synth import make_template_inputs
+    cfg = TINY.replace(n_templ=2, c_z=4, tri_heads=2, tri_head_dim=2, tri_mul_hidden=3, transition_factor=2)
+    inp = make_template_inputs(cfg, seed=8, perturb=True)
+    p = inp["params"][0]
+    pl = {s: _pl(p[s]) for s in p}
+    for n in range(cfg.n_templ):
+        for dr in (None, (5, 2)):
+            got = O.template_pair_block(inp["t"][n], inp["pair_mask"][n], p, cfg, dropout=dr, template=n)
+            masks = None
+            if dr is not None:
+                masks = _dropout_masks(cfg, 5, 2, cfg.n_res, template=n)
+                masks.pop("row_attn")
+            ref = brute.template_block(brute.t2l(inp["t"][n]), brute.t2l(inp["pair_mask"][n]), pl, cfg, masks)
+            _close(got, ref)
+    t = inp["t"][0].clone().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x: O.template_pair_block(x, inp["pair_mask"][0], p, cfg, dropout=(5, 2)),
+                                    (t,), eps=1e-6, atol=1e-6)
+    # the stack helper: same outputs as the block applied per template
+    out, g = O.template_stack_fwd_bwd(inp, cfg, dropout=(5, 2))
+    for n in range(cfg.n_templ):
+        ref = O.template_pair_block(inp["t"][n], inp["pair_mask"][n], p, cfg, dropout=(5, 2), template=n)
+        _close(out[n], ref.detach(), 1e-12)
