@@ -9,7 +9,13 @@ BF16 storage with FP32 accumulation is timed beside it.
 
 Prints one JSON line: the FP32 throughput in TFLOP/s of algorithmic work
 (value), the BF16 twin, the roofline of the dominant kernel measured with HIP
-events around its launches, and the FP64 oracle's throughput on the host.
+events around its launches, the per-class rooflines (attention forward,
+attention backward, triangle contraction: algorithmic FLOPs over their summed
+launch times against the MFMA peak of the dtype), mean and median step times
+with the forward / backward split, the other crop shapes of the paper's
+model-settings table (stack of 4 blocks, extra MSA, fine-tuning stack of 8
+blocks, long-chain chunked forward, extra MSA at the fine-tuning crop, template
+pair stack), and the FP64 oracle's throughput on the host.
 """
 from __future__ import annotations
 
@@ -51,6 +57,17 @@ def block_flops(cfg) -> float:
     return float(f)
 
 
+def template_block_flops(cfg) -> float:
+    """Algorithmic forward FLOPs of one template pair stack block on one template."""
+    R, cz = cfg.n_res, cfg.c_z
+    ht, dt, ch, tf = cfg.tri_heads, cfg.tri_head_dim, cfg.tri_mul_hidden, cfg.transition_factor
+    RR = R * R
+    f = 2 * (2 * RR * cz * (4 * ch + cz) + 2 * ch * R * R * R + 2 * RR * ch * cz)
+    f += 2 * (2 * RR * cz * (4 * ht * dt + ht) + 4 * R * ht * R * R * dt + 2 * RR * ht * dt * cz)
+    f += 2 * RR * cz * tf * cz * 2
+    return float(f)
+
+
 def make_workload(cfg, dtype, device):
     import synth
     from paper_2207_05477_amd import binding as B
@@ -78,18 +95,37 @@ def step(cfg, dtype, flat, w):
                           w["dm"], w["dz"], dtype=dtype)
 
 
-def time_steps(cfg, dtype, flat, w, steps, warmup):
+def fwd_only(cfg, dtype, flat, w):
+    from paper_2207_05477_amd import binding as B
+    B.evoformer_block_fwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["mo"], w["zo"], dtype=dtype)
+
+
+def bwd_only(cfg, dtype, flat, w):
+    from paper_2207_05477_amd import binding as B
+    B.evoformer_block_bwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["dmo"], w["dzo"], w["dflat"],
+                          w["dm"], w["dz"], dtype=dtype)
+
+
+def timed(fn, steps, warmup):
+    """Per-call HIP-event times (ms) of `steps` calls after `warmup` untimed ones:
+    (total-window mean, median of the per-call events)."""
     for _ in range(warmup):
-        step(cfg, dtype, flat, w)
+        fn()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
-        step(cfg, dtype, flat, w)
-    t1.record()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    mean = ev[0].elapsed_time(ev[steps]) / steps
+    med = per[steps // 2] if steps % 2 else 0.5 * (per[steps // 2 - 1] + per[steps // 2])
+    return mean, med
+
+
+def time_steps(cfg, dtype, flat, w, steps, warmup):
+    return timed(lambda: step(cfg, dtype, flat, w), steps, warmup)[0]
 
 
 def profile_steps(cfg, dtype, flat, w, steps, detail=False):
@@ -141,6 +177,37 @@ def roofline_of(stats, dtype):
     peak = HBM_PEAK / 1e9
     return {"kernel": top["name"], "bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s",
             "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms, "launches_per_step": None}
+
+
+def kernel_class(name: str):
+    """Kernel class of a detail-mode profiler key "kernel@sub-operation tags"."""
+    k, _, tag = name.partition("@")
+    if k.startswith("attn_fwd_kernel"):
+        return "attention_fwd"
+    if k.startswith("attn_bwd_"):
+        return "attention_bwd"
+    if k.startswith("gemm") and "contract" in tag:
+        return "triangle_contraction"
+    return None
+
+
+def class_rooflines(stats, dtype, steps):
+    """Per-class algorithmic TFLOP/s (FLOPs of the class's launches over their
+    summed event times) and fraction of the dtype's dense MFMA peak."""
+    out = {}
+    for s in stats:
+        c = kernel_class(s["name"])
+        if c is None:
+            continue
+        e = out.setdefault(c, {"launches_per_step": 0.0, "ms_per_step": 0.0, "gflop_per_step": 0.0})
+        e["launches_per_step"] += s["launches"] / steps
+        e["ms_per_step"] += s["total_ms"] / steps
+        e["gflop_per_step"] += s["flops"] / steps / 1e9
+    for e in out.values():
+        e["tflops"] = e["gflop_per_step"] / e["ms_per_step"] if e["ms_per_step"] > 0 else None
+        e["peak_tflops"] = PEAK[dtype] / 1e12
+        e["frac"] = e["tflops"] / e["peak_tflops"] if e["tflops"] else None
+    return out
 
 
 def print_breakdown(stats, dtype, steps, file=sys.stderr):
@@ -204,6 +271,116 @@ def cpu_baseline(cfg, flops_step):
             "ms_per_step": dt * 1e3}
 
 
+def measure_block(cfg, dtype, dev, steps, warmup, profile_steps_n, breakdown=False):
+    """One block fwd+bwd at `cfg` in `dtype`: mean / median step, forward and
+    backward alone, the dominant kernel's roofline and the class rooflines."""
+    inp, flat, w = make_workload(cfg, dtype, dev)
+    flops_step = 3.0 * block_flops(cfg)
+    ms, med = timed(lambda: step(cfg, dtype, flat, w), steps, warmup)
+    fms, fmed = timed(lambda: fwd_only(cfg, dtype, flat, w), steps, 2)
+    bms, bmed = timed(lambda: bwd_only(cfg, dtype, flat, w), steps, 2)
+    print(f"{dtype} step {ms:.3f} ms (median {med:.3f}); forward {fms:.3f}, backward {bms:.3f}", file=sys.stderr,
+          flush=True)
+    stats = profile_steps(cfg, dtype, flat, w, profile_steps_n)
+    roof = roofline_of(stats, dtype)
+    roof["launches_per_step"] = stats[0]["launches"] / profile_steps_n
+    roof["traffic"] = recorded_traffic(roof["kernel"], roof["launches_per_step"])
+    detail = profile_steps(cfg, dtype, flat, w, profile_steps_n, detail=True)
+    classes = class_rooflines(detail, dtype, profile_steps_n)
+    if breakdown:
+        print_breakdown(detail, dtype, profile_steps_n)
+    res = {"ms_per_step": ms, "ms_per_step_median": med, "tflops": flops_step / (ms * 1e-3) / 1e12,
+           "fwd_ms": fms, "fwd_ms_median": fmed, "bwd_ms": bms, "bwd_ms_median": bmed,
+           "roofline": roof, "roofline_by_class": classes,
+           "top_kernels": [{k: s_[k] for k in ("name", "launches", "total_ms")} for s_ in stats[:8]]}
+    del w, flat, inp
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_stack(cfg, dtype, dev, steps, warmup):
+    """A stack of cfg.n_blocks blocks: every block's forward, then the backward
+    chain (each block's backward recomputes its forward); returns ms per step
+    and algorithmic TFLOP/s (3 x forward per block)."""
+    import synth
+    from paper_2207_05477_amd import binding as B
+    inp = synth.round_inputs(synth.make_inputs(cfg), dtype)
+    dt = B.act_dtype(dtype)
+    flats = [B.FlatParams(p, dev) for p in inp["params"]]
+    del inp["params"]
+    m = inp["m"].to(device=dev, dtype=dt)
+    z = inp["z"].to(device=dev, dtype=dt)
+    mm, pm = inp["msa_mask"].float().to(dev), inp["pair_mask"].float().to(dev)
+    dmo, dzo = inp["dm_out"].to(device=dev, dtype=dt), inp["dz_out"].to(device=dev, dtype=dt)
+    del inp
+    acts = [(m, z)] + [(torch.empty_like(m), torch.empty_like(z)) for _ in flats]
+    dflats = [f.zeros_like() for f in flats]
+    gm, gz = torch.empty_like(m), torch.empty_like(z)
+
+    def one():
+        for i, f in enumerate(flats):
+            B.evoformer_block_fwd(cfg, f, acts[i][0], acts[i][1], mm, pm, acts[i + 1][0], acts[i + 1][1],
+                                  dtype=dtype)
+        if not cfg.backward:
+            return
+        gm.copy_(dmo)
+        gz.copy_(dzo)
+        for i in reversed(range(len(flats))):
+            B.evoformer_block_bwd(cfg, flats[i], acts[i][0], acts[i][1], mm, pm, gm, gz, dflats[i], gm, gz,
+                                  dtype=dtype)
+
+    ms, med = timed(one, steps, warmup)
+    f = block_flops(cfg) * len(flats) * (3.0 if cfg.backward else 1.0)
+    del acts, flats, dflats
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms, "ms_per_step_median": med, "tflops": f / (ms * 1e-3) / 1e12,
+            "algorithmic_gflop_per_step": f / 1e9}
+
+
+def bench_template(cfg, dtype, dev, steps, warmup):
+    """The template pair stack: every template through cfg.n_blocks blocks,
+    forward then backward (with recompute)."""
+    import synth
+    from paper_2207_05477_amd import binding as B
+    inp = synth.round_inputs(synth.make_template_inputs(cfg), dtype)
+    dt = B.act_dtype(dtype)
+    flats = [B.FlatParams(p, dev, subops=B.TEMPLATE_SUBOPS) for p in inp["params"]]
+    t = inp["t"].to(device=dev, dtype=dt)
+    P = inp["pair_mask"].float().to(dev)
+    dto = inp["dt_out"].to(device=dev, dtype=dt)
+    T = cfg.n_templ
+    acts = [[t[n]] + [torch.empty_like(t[n]) for _ in flats] for n in range(T)]
+    dflats = [f.zeros_like() for f in flats]
+    g = torch.empty_like(t[0])
+
+    def one():
+        for n in range(T):
+            for i, f in enumerate(flats):
+                B.template_pair_block_fwd(cfg, f, acts[n][i], P[n], acts[n][i + 1], dtype=dtype, template_index=n)
+        for n in range(T):
+            g.copy_(dto[n])
+            for i in reversed(range(len(flats))):
+                B.template_pair_block_bwd(cfg, flats[i], acts[n][i], P[n], g, dflats[i], g, dtype=dtype,
+                                          template_index=n)
+
+    ms, med = timed(one, steps, warmup)
+    f = template_block_flops(cfg) * len(flats) * T * 3.0
+    del acts, flats, dflats
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms, "ms_per_step_median": med, "tflops": f / (ms * 1e-3) / 1e12,
+            "algorithmic_gflop_per_step": f / 1e9}
+
+
+OTHER_CONFIGS = (
+    ("C2", "stack of 4 blocks, N_seq=128, N_res=256, fwd+bwd"),
+    ("C3", "extra-MSA block, N_extra=1024, N_res=256, c_e=64, fwd+bwd"),
+    ("C4a", "fine-tuning stack of 8 blocks, N_seq=512, N_res=384, fwd+bwd"),
+    ("C4b", "long-chain block forward, N_seq=128, N_res=1024, 128-row chunks"),
+    ("C5", "extra-MSA block at the fine-tuning crop, N_extra=5120, N_res=384, fwd+bwd"),
+    ("T", "template pair stack, 4 templates x 2 blocks, c_t=64, N_res=256, fwd+bwd"),
+)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +388,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other crop shapes")
+    ap.add_argument("--config-steps", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -236,38 +415,30 @@ def main():
     cfg = synth.get("C1")
     flops_step = 3.0 * block_flops(cfg)       # forward + backward (2x forward), algorithmic
 
-    ms, roof, stats = None, None, []
+    f32 = None
     if args.only != "bf16":
-        inp, flat, w = make_workload(cfg, "f32", dev)
-        ms = time_steps(cfg, "f32", flat, w, args.steps, args.warmup)
-        print(f"f32 step {ms:.3f} ms", file=sys.stderr, flush=True)
-        stats = profile_steps(cfg, "f32", flat, w, args.profile_steps)
-        roof = roofline_of(stats, "f32")
-        roof["launches_per_step"] = stats[0]["launches"] / args.profile_steps
-        roof["traffic"] = recorded_traffic(roof["kernel"], roof["launches_per_step"])
-        if args.breakdown:
-            print_breakdown(profile_steps(cfg, "f32", flat, w, args.profile_steps, detail=True), "f32",
-                            args.profile_steps)
-        del w, flat, inp
-
+        f32 = measure_block(cfg, "f32", dev, args.steps, args.warmup, args.profile_steps, args.breakdown)
     bf16 = None
     if not args.no_bf16 and args.only != "f32":
-        cfg16 = cfg.replace(dtype="bf16")
-        inp, flat, w = make_workload(cfg16, "bf16", dev)
-        ms16 = time_steps(cfg16, "bf16", flat, w, args.steps, args.warmup)
-        st16 = profile_steps(cfg16, "bf16", flat, w, args.profile_steps)
-        r16 = roofline_of(st16, "bf16")
-        r16["launches_per_step"] = st16[0]["launches"] / args.profile_steps
-        r16["traffic"] = recorded_traffic(r16["kernel"], r16["launches_per_step"])
-        if args.breakdown:
-            print_breakdown(profile_steps(cfg16, "bf16", flat, w, args.profile_steps, detail=True), "bf16",
-                            args.profile_steps)
-        print(f"bf16 step {ms16:.3f} ms", file=sys.stderr, flush=True)
-        bf16 = {"ms_per_step": ms16, "tflops": flops_step / (ms16 * 1e-3) / 1e12,
-                "speedup_vs_f32": (ms / ms16) if ms else None, "roofline": r16,
-                "top_kernels": [{k: s[k] for k in ("name", "launches", "total_ms")} for s in st16[:8]]}
-        del w, flat, inp
+        bf16 = measure_block(cfg.replace(dtype="bf16"), "bf16", dev, args.steps, args.warmup, args.profile_steps,
+                             args.breakdown)
+        if f32:
+            bf16["speedup_vs_f32"] = f32["ms_per_step"] / bf16["ms_per_step"]
+    others = {}
+    if not args.no_configs and args.only is None:
+        for name, what in OTHER_CONFIGS:
+            c = synth.get(name)
+            print(f"config {name}: {what}", file=sys.stderr, flush=True)
+            if name == "T":
+                r = bench_template(c.replace(n_blocks=2), "bf16", dev, args.config_steps, 1)
+            else:
+                r = bench_stack(c.replace(dtype="bf16"), "bf16", dev, args.config_steps, 1)
+            r["workload"] = what
+            r["dtype"] = "bf16"
+            others[name] = r
+            print(f"  {r['ms_per_step']:.2f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
 
+    ms = f32["ms_per_step"] if f32 else None
     out = {
         "metric": "Evoformer block fwd+bwd ms & TFLOP/s at N_res=256, BF16 vs FP32, % MFMA peak",
         "value": flops_step / (ms * 1e-3) / 1e12 if ms else None,
@@ -285,11 +456,14 @@ def main():
                    "n_res": cfg.n_res, "c_m": cfg.c_m, "c_z": cfg.c_z, "msa_heads": "8x32",
                    "tri_heads": "4x32", "tri_mul_hidden": cfg.tri_mul_hidden,
                    "opm_hidden": cfg.opm_hidden, "blocks": 1, "algorithmic_gflop_per_step": flops_step / 1e9},
-        "roofline": roof,
-        "top_kernels": [{k: s[k] for k in ("name", "launches", "total_ms")} for s in stats[:8]],
-        "bf16": bf16,
+        "roofline": f32["roofline"] if f32 else None,
     }
-    if not args.no_cpu_baseline:
+    if f32:
+        out.update({k: f32[k] for k in ("ms_per_step_median", "fwd_ms", "fwd_ms_median", "bwd_ms", "bwd_ms_median",
+                                        "roofline_by_class", "top_kernels")})
+    out["bf16"] = bf16
+    out["other_configs"] = others or None
+    if not args.no_cpu_baseline and args.only != "bf16":
         out["cpu_baseline"] = cpu_baseline(cfg, flops_step)
     print(json.dumps(out))
 

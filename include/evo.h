@@ -237,6 +237,23 @@ typedef struct {
                                  (paper, Section "Subbatch VS DAP": the split axis is
                                  independent). */
   float ln_eps, opm_eps, global_eps;
+  int32_t opm_first;          /* 1: the outer product mean runs first, on the block's input m, and
+                                 both branches read z + OPM(m): the MSA stack and the pair stack are
+                                 then independent, as Branch Parallelism needs (paper, Section
+                                 "Branch Parallelism"); 0: AlphaFold2's order above */
+  int32_t dropout;            /* 1: training dropout of the residual updates (AlphaFold2's settings,
+                                 paper Section "Hyperparameter setting"): row attention at
+                                 drop_row_attn with one multiplier per (residue, channel) shared along
+                                 the MSA rows; the triangle multiplications and starting-node attention
+                                 at drop_tri_mul / drop_tri_att shared along the first residue axis;
+                                 ending-node attention shared along the second.  Multipliers are 0 or
+                                 1 / (1 - rate), from Philox4x32-10 with key drop_seed, counter
+                                 (element, sub-op number [row 0, tri-mul out 4, in 5, attention start
+                                 6, end 7], drop_offset low, high words); a stack gives block l the
+                                 offset drop_offset + l.  Forward and backward of one step must pass
+                                 the same values.  Not with chunk. */
+  float drop_row_attn, drop_tri_mul, drop_tri_att;   /* rates in [0, 1) */
+  uint64_t drop_seed, drop_offset;
 } evo_block_desc_t;
 
 typedef struct {
@@ -261,6 +278,91 @@ evo_status_t evoformer_block_bwd(const evo_block_desc_t* desc, const evo_block_w
                                  const float* pair_mask, const void* dm_out, const void* dz_out,
                                  void* dm, void* dz, const evo_block_w_t* d_w,
                                  void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ template pair stack block
+ * One block of AlphaFold2's template pair stack, which the paper's initial-training
+ * forward includes (its template embedding): the pair-stack operators on one
+ * template's pair features t [N_res, N_res, c_t], in the order
+ *   t <- t + TriAttnStart(t); t <- t + TriAttnEnd(t); t <- t + TriMulOut(t);
+ *   t <- t + TriMulIn(t); t <- t + Transition(t).
+ * Templates are independent: the caller runs every template through the same
+ * blocks; template_index enters the dropout counter (sub-op number | index << 8).
+ * Like the Evoformer block it is a checkpoint boundary (forward saves nothing).
+ */
+typedef struct {
+  int32_t dtype;
+  int64_t n_res, c_t;
+  int32_t tri_heads, tri_head_dim;
+  int64_t tri_mul_hidden, transition_factor;
+  int64_t chunk;              /* forward only, as in evo_block_desc_t */
+  float ln_eps;
+  int32_t dropout;            /* as in evo_block_desc_t (no row attention here) */
+  int32_t template_index;     /* 0 .. 2^24 - 1 */
+  float drop_tri_mul, drop_tri_att;
+  uint64_t drop_seed, drop_offset;
+} evo_template_desc_t;
+
+typedef struct {
+  evo_attn_w_t tri_att_start, tri_att_end;
+  evo_trimul_w_t tri_mul_out, tri_mul_in;
+  evo_trans_w_t pair_trans;
+} evo_template_w_t;
+
+size_t template_pair_block_workspace_bytes(const evo_template_desc_t* desc, int32_t phase);
+/* t_out may alias t. */
+evo_status_t template_pair_block_fwd(const evo_template_desc_t* desc, const evo_template_w_t* w,
+                                     const void* t, const float* pair_mask, void* t_out,
+                                     void* ws, size_t ws_bytes, void* stream);
+/* dt = dt_out + J^T dt_out (dt may alias dt_out); d_w += parameter gradients. */
+evo_status_t template_pair_block_bwd(const evo_template_desc_t* desc, const evo_template_w_t* w,
+                                     const void* t, const float* pair_mask, const void* dt_out, void* dt,
+                                     const evo_template_w_t* d_w, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ optimizer step
+ * The optimizer stages over fused (flat) FP32 buffers of n elements: the
+ * parameters, their gradients, the Adam moments m and v, and the exponential
+ * moving average of the parameters (paper, Section "Tensor Fusion" and its
+ * table of kernel launches per stage: gradient clipping by global norm, Adam,
+ * EMA; update rules as in AlphaFold2, Section "Hyperparameter setting"):
+ *   clip   norm = sqrt(sum_i g_i^2);  g <- g * max_norm / max(norm, max_norm)
+ *   Adam   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ *          p <- p - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ *   EMA    e <- decay e + (1 - decay) p
+ * All buffers are caller-owned device pointers, 16-byte aligned, n >= 0
+ * elements each (n = 0: buffers may be NULL; launches touch nothing).  The norm is
+ * accumulated in FP64 in a fixed order (deterministic).  The workspace holds
+ * the norm's partial sums: evo_optim_workspace_bytes(n) bytes, 16-byte
+ * aligned, contents undefined on entry and after the call.
+ */
+typedef struct {
+  double lr, beta1, beta2, eps;  /* Adam; 0 <= beta < 1, eps > 0 */
+  double max_norm;               /* clip threshold; <= 0: no clipping */
+  double ema_decay;              /* in [0, 1]; used only when an EMA buffer is given */
+  int64_t step;                  /* Adam step counter, from 1 */
+} evo_optim_desc_t;
+/* The hyperparameters are double so that 1 - beta, 1 - decay and the bias
+ * corrections are formed exactly on the host; the kernels compute in FP32. */
+
+size_t evo_optim_workspace_bytes(int64_t n);
+/* *norm_out (device) = ||grads||_2.  2 launches. */
+evo_status_t evo_grad_global_norm(const float* grads, int64_t n, float* norm_out, void* ws, size_t ws_bytes,
+                                  void* stream);
+/* grads scaled in place to global norm at most max_norm (> 0); *norm_out (device, may
+ * be NULL) = the norm before clipping.  2 launches. */
+evo_status_t evo_clip_by_global_norm(float* grads, int64_t n, double max_norm, float* norm_out, void* ws,
+                                     size_t ws_bytes, void* stream);
+/* One Adam update of params, m, v in place (desc->max_norm ignored).  1 launch. */
+evo_status_t evo_adam_step(const evo_optim_desc_t* desc, float* params, const float* grads, float* m,
+                           float* v, int64_t n, void* stream);
+/* ema updated in place from params.  1 launch. */
+evo_status_t evo_ema_update(float* ema, const float* params, int64_t n, double decay, void* stream);
+/* The whole step: clip (when desc->max_norm > 0; the clipped gradient is applied in
+ * registers, grads is not modified), Adam, and the EMA of the updated parameters
+ * when ema is not NULL.  *norm_out (may be NULL) = the gradient norm before clipping.
+ * 2 launches with clipping, 1 without (then ws may be NULL). */
+evo_status_t evo_optimizer_step(const evo_optim_desc_t* desc, float* params, const float* grads, float* m,
+                                float* v, float* ema, int64_t n, float* norm_out, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* ------------------------------------------------------------------ launch profiler
  * Optional per-launch timing for roofline reports.  Between evo_profile_begin

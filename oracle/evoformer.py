@@ -424,14 +424,14 @@ def template_stack_fwd_bwd(inp, cfg, dropout=None, want_param_grads=True):
     return out.detach(), grads
 
 
-def relu_margin(inp, cfg, boundary=None):
+def relu_margin(inp, cfg, boundary=None, dropout=None):
     """Smallest |pre-activation| over every transition of the stack's forward."""
     probe = {}
-    stack_fwd(inp, cfg, boundary, probe)
+    stack_fwd(inp, cfg, boundary, probe, dropout)
     return min(probe["min_abs"])
 
 
-def with_relu_margins(inp, cfg, margin, boundary=None):
+def with_relu_margins(inp, cfg, margin, boundary=None, dropout=None):
     """A copy of ``inp`` whose transitions' b_1 are re-chosen (relu_margin_bias)
     on this oracle's forward of the stack, transition by transition in forward
     order, so that every ReLU pre-activation is at least ``margin`` from zero:
@@ -439,8 +439,58 @@ def with_relu_margins(inp, cfg, margin, boundary=None):
     stays below the margin.  Asserts the margin on a fresh forward."""
     out = dict(inp)
     out["params"] = [{s: {k: v.clone() for k, v in blk[s].items()} for s in blk} for blk in inp["params"]]
-    stack_fwd(out, cfg, boundary, {"choose": margin})
-    got = relu_margin(out, cfg, boundary)
+    stack_fwd(out, cfg, boundary, {"choose": margin}, dropout)
+    got = relu_margin(out, cfg, boundary, dropout)
+    assert got >= margin * (1 - 1e-9), f"ReLU margin {got} < {margin}"
+    return out
+
+
+def template_stack_fwd(inp, cfg, dropout=None, probe=None):
+    """Forward of the template pair stack (every template through the same
+    blocks), block by block.  probe (test-input construction): as in
+    transition(); with probe["choose"], each block's pair-transition b_1 is
+    chosen on the pre-activations of all templates together, so one b_1 clears
+    the margin for every template."""
+    P = inp["pair_mask"].to(F64)
+    xs = [inp["t"][n].detach().to(F64) for n in range(inp["t"].shape[0])]
+    eps = cfg.ln_eps
+    H, c = cfg.tri_heads, cfg.tri_head_dim
+    with torch.no_grad():
+        for i, p in enumerate(inp["params"]):
+            dr = _block_dropout(dropout, i)
+            for n in range(len(xs)):
+                x = xs[n]
+                x = x + drop(tri_att_start(x, P[n], p["tri_att_start"], H, c, eps), dr, "tri_att_start", "row",
+                             cfg.drop_tri_att, n)
+                x = x + drop(tri_att_end(x, P[n], p["tri_att_end"], H, c, eps), dr, "tri_att_end", "col",
+                             cfg.drop_tri_att, n)
+                x = x + drop(tri_mul_out(x, P[n], p["tri_mul_out"], eps), dr, "tri_mul_out", "row",
+                             cfg.drop_tri_mul, n)
+                x = x + drop(tri_mul_in(x, P[n], p["tri_mul_in"], eps), dr, "tri_mul_in", "row",
+                             cfg.drop_tri_mul, n)
+                xs[n] = x
+            pt = p["pair_trans"]
+            if probe is not None and probe.get("choose") is not None:
+                u = pt["w_1"].shape[1]
+                pre = torch.cat([(layer_norm(x, pt["ln_g"], pt["ln_b"], eps) @ pt["w_1"]).reshape(-1, u)
+                                 for x in xs])
+                pt["b_1"] = relu_margin_bias(pre, probe["choose"])
+            sub = None if probe is None else {}
+            xs = [x + transition(x, pt, eps, sub) for x in xs]
+            if probe is not None:
+                probe.setdefault("min_abs", []).extend(sub["min_abs"])
+    return torch.stack(xs)
+
+
+def with_template_relu_margins(inp, cfg, margin, dropout=None):
+    """with_relu_margins for the template pair stack: a copy of ``inp`` whose
+    pair transitions' b_1 clear ``margin`` on every template; asserts it."""
+    out = dict(inp)
+    out["params"] = [{s: {k: v.clone() for k, v in blk[s].items()} for s in blk} for blk in inp["params"]]
+    template_stack_fwd(out, cfg, dropout, {"choose": margin})
+    probe = {}
+    template_stack_fwd(out, cfg, dropout, probe)
+    got = min(probe["min_abs"])
     assert got >= margin * (1 - 1e-9), f"ReLU margin {got} < {margin}"
     return out
 

@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_float, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libevo.so")
 
@@ -67,7 +67,9 @@ class BlockDesc(ctypes.Structure):
                 ("msa_head_dim", c_int32), ("tri_heads", c_int32), ("tri_head_dim", c_int32),
                 ("tri_mul_hidden", c_int64), ("opm_hidden", c_int64),
                 ("transition_factor", c_int64), ("chunk", c_int64), ("ln_eps", c_float),
-                ("opm_eps", c_float), ("global_eps", c_float)]
+                ("opm_eps", c_float), ("global_eps", c_float), ("opm_first", c_int32),
+                ("dropout", c_int32), ("drop_row_attn", c_float), ("drop_tri_mul", c_float),
+                ("drop_tri_att", c_float), ("drop_seed", c_uint64), ("drop_offset", c_uint64)]
 
 
 class BlockW(ctypes.Structure):
@@ -76,9 +78,27 @@ class BlockW(ctypes.Structure):
                 ("tri_att_end", AttnW), ("pair_trans", TransW)]
 
 
+class TemplateDesc(ctypes.Structure):
+    _fields_ = [("dtype", c_int32), ("n_res", c_int64), ("c_t", c_int64), ("tri_heads", c_int32),
+                ("tri_head_dim", c_int32), ("tri_mul_hidden", c_int64), ("transition_factor", c_int64),
+                ("chunk", c_int64), ("ln_eps", c_float), ("dropout", c_int32), ("template_index", c_int32),
+                ("drop_tri_mul", c_float), ("drop_tri_att", c_float), ("drop_seed", c_uint64),
+                ("drop_offset", c_uint64)]
+
+
+class TemplateW(ctypes.Structure):
+    _fields_ = [("tri_att_start", AttnW), ("tri_att_end", AttnW), ("tri_mul_out", TrimulW),
+                ("tri_mul_in", TrimulW), ("pair_trans", TransW)]
+
+
 SUBOP_STRUCT = {"row_attn": AttnW, "col_attn": AttnW, "msa_trans": TransW, "opm": OpmW,
                 "tri_mul_out": TrimulW, "tri_mul_in": TrimulW, "tri_att_start": AttnW,
                 "tri_att_end": AttnW, "pair_trans": TransW}
+
+class OptimDesc(ctypes.Structure):
+    _fields_ = [("lr", c_double), ("beta1", c_double), ("beta2", c_double), ("eps", c_double),
+                ("max_norm", c_double), ("ema_decay", c_double), ("step", c_int64)]
+
 
 # name -> (argtypes, restype)
 _P = c_void_p
@@ -111,6 +131,18 @@ _SIGS = {
                              _P], c_int32),
     "evoformer_block_bwd": ([POINTER(BlockDesc), POINTER(BlockW), _P, _P, _P, _P, _P, _P, _P, _P,
                              POINTER(BlockW), _P, c_size_t, _P], c_int32),
+    "template_pair_block_workspace_bytes": ([POINTER(TemplateDesc), c_int32], c_size_t),
+    "template_pair_block_fwd": ([POINTER(TemplateDesc), POINTER(TemplateW), _P, _P, _P, _P, c_size_t, _P],
+                                c_int32),
+    "template_pair_block_bwd": ([POINTER(TemplateDesc), POINTER(TemplateW), _P, _P, _P, _P, POINTER(TemplateW),
+                                 _P, c_size_t, _P], c_int32),
+    "evo_optim_workspace_bytes": ([c_int64], c_size_t),
+    "evo_grad_global_norm": ([_P, c_int64, _P, _P, c_size_t, _P], c_int32),
+    "evo_clip_by_global_norm": ([_P, c_int64, c_double, _P, _P, c_size_t, _P], c_int32),
+    "evo_adam_step": ([POINTER(OptimDesc), _P, _P, _P, _P, c_int64, _P], c_int32),
+    "evo_ema_update": ([_P, _P, c_int64, c_double, _P], c_int32),
+    "evo_optimizer_step": ([POINTER(OptimDesc), _P, _P, _P, _P, _P, c_int64, _P, _P, c_size_t, _P],
+                           c_int32),
 }
 
 EXPORTS = tuple(_SIGS)

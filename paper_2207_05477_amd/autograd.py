@@ -15,12 +15,12 @@ from . import binding
 
 class EvoformerBlockFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, m, z, flat_buffer, cfg, flat, msa_mask, pair_mask, dtype):
+    def forward(ctx, m, z, flat_buffer, cfg, flat, msa_mask, pair_mask, dtype, dropout=None):
         assert flat_buffer is flat.buffer
         m_out, z_out = binding.evoformer_block_fwd(cfg, flat, m.contiguous(), z.contiguous(), msa_mask,
-                                                   pair_mask, dtype=dtype)
+                                                   pair_mask, dtype=dtype, dropout=dropout)
         ctx.save_for_backward(m, z)
-        ctx.cfg, ctx.flat, ctx.masks, ctx.dtype = cfg, flat, (msa_mask, pair_mask), dtype
+        ctx.cfg, ctx.flat, ctx.masks, ctx.dtype, ctx.dropout = cfg, flat, (msa_mask, pair_mask), dtype, dropout
         return m_out, z_out
 
     @staticmethod
@@ -32,12 +32,13 @@ class EvoformerBlockFn(torch.autograd.Function):
             dz_out = torch.zeros_like(z)
         dm, dz, dflat = binding.evoformer_block_bwd(ctx.cfg, ctx.flat, m.contiguous(), z.contiguous(),
                                                     ctx.masks[0], ctx.masks[1], dm_out.contiguous(),
-                                                    dz_out.contiguous(), dtype=ctx.dtype)
-        return dm, dz, dflat, None, None, None, None, None
+                                                    dz_out.contiguous(), dtype=ctx.dtype, dropout=ctx.dropout)
+        return dm, dz, dflat, None, None, None, None, None, None
 
 
-def evoformer_block(cfg, flat, m, z, msa_mask=None, pair_mask=None, dtype=None):
-    return EvoformerBlockFn.apply(m, z, flat.buffer, cfg, flat, msa_mask, pair_mask, dtype)
+def evoformer_block(cfg, flat, m, z, msa_mask=None, pair_mask=None, dtype=None, dropout=None):
+    """dropout: None or (seed, offset) of the dropout generator (training)."""
+    return EvoformerBlockFn.apply(m, z, flat.buffer, cfg, flat, msa_mask, pair_mask, dtype, dropout)
 
 
 class EvoformerStack(torch.nn.Module):
@@ -53,11 +54,63 @@ class EvoformerStack(torch.nn.Module):
             f.buffer = torch.nn.Parameter(f.buffer)
             self.buffers_.append(f.buffer)
 
-    def forward(self, m, z, msa_mask=None, pair_mask=None, dtype=None):
-        for f in self.flats:
-            m, z = evoformer_block(self.cfg, f, m, z, msa_mask, pair_mask, dtype)
+    def forward(self, m, z, msa_mask=None, pair_mask=None, dtype=None, dropout=None):
+        """dropout: None or (seed, offset); block l draws its masks at offset + l."""
+        for i, f in enumerate(self.flats):
+            dr = None if dropout is None else (dropout[0], dropout[1] + i)
+            m, z = evoformer_block(self.cfg, f, m, z, msa_mask, pair_mask, dtype, dr)
         return m, z
 
     def param_grads(self) -> list:
         """Per-block {subop: {name: grad view}} of the fused gradient buffers."""
+        return [f.views(f.buffer.grad) for f in self.flats]
+
+
+class TemplatePairBlockFn(torch.autograd.Function):
+    """One template's pair features through one template pair stack block."""
+
+    @staticmethod
+    def forward(ctx, t, flat_buffer, cfg, flat, pair_mask, dtype, dropout, template_index):
+        assert flat_buffer is flat.buffer
+        t_out = binding.template_pair_block_fwd(cfg, flat, t.contiguous(), pair_mask, dtype=dtype,
+                                                dropout=dropout, template_index=template_index)
+        ctx.save_for_backward(t)
+        ctx.args = (cfg, flat, pair_mask, dtype, dropout, template_index)
+        return t_out
+
+    @staticmethod
+    def backward(ctx, dt_out):
+        (t,) = ctx.saved_tensors
+        cfg, flat, pair_mask, dtype, dropout, template_index = ctx.args
+        dt, dflat = binding.template_pair_block_bwd(cfg, flat, t.contiguous(), pair_mask, dt_out.contiguous(),
+                                                    dtype=dtype, dropout=dropout, template_index=template_index)
+        return dt, dflat, None, None, None, None, None, None
+
+
+class TemplatePairStack(torch.nn.Module):
+    """The template pair stack: every template t[n] [R, R, c_t] through the same
+    blocks (one fused FP32 parameter buffer per block); template n enters the
+    dropout counter, block l draws at offset + l."""
+
+    def __init__(self, cfg, block_params: list, device):
+        super().__init__()
+        self.cfg = cfg
+        self.flats = [binding.FlatParams(p, device, subops=binding.TEMPLATE_SUBOPS) for p in block_params]
+        self.buffers_ = torch.nn.ParameterList()
+        for f in self.flats:
+            f.buffer = torch.nn.Parameter(f.buffer)
+            self.buffers_.append(f.buffer)
+
+    def forward(self, t, pair_mask=None, dtype=None, dropout=None):
+        outs = []
+        for n in range(t.shape[0]):
+            x = t[n]
+            pm = None if pair_mask is None else pair_mask[n]
+            for i, f in enumerate(self.flats):
+                dr = None if dropout is None else (dropout[0], dropout[1] + i)
+                x = TemplatePairBlockFn.apply(x, f.buffer, self.cfg, f, pm, dtype, dr, n)
+            outs.append(x)
+        return torch.stack(outs)
+
+    def param_grads(self) -> list:
         return [f.views(f.buffer.grad) for f in self.flats]

@@ -15,6 +15,7 @@ from . import _abi as A
 DTYPES = {"f32": (A.EVO_F32, torch.float32), "bf16": (A.EVO_BF16, torch.bfloat16)}
 BLOCK_SUBOPS = ("row_attn", "col_attn", "msa_trans", "opm", "tri_mul_out", "tri_mul_in",
                 "tri_att_start", "tri_att_end", "pair_trans")
+TEMPLATE_SUBOPS = ("tri_att_start", "tri_att_end", "tri_mul_out", "tri_mul_in", "pair_trans")
 _ALIGN = 64  # FP32 elements = 256 bytes
 
 
@@ -136,6 +137,13 @@ class FlatParams:
         w._keep = self.buffer if buffer is None else buffer
         return w
 
+    def template_struct(self, buffer: torch.Tensor | None = None) -> A.TemplateW:
+        w = A.TemplateW()
+        for sub in TEMPLATE_SUBOPS:
+            setattr(w, sub, self.substruct(sub, buffer))
+        w._keep = self.buffer if buffer is None else buffer
+        return w
+
 
 def weight_struct(sub: str, params: dict):
     """C weight struct of one sub-op from individual FP32 device tensors."""
@@ -149,8 +157,22 @@ def weight_struct(sub: str, params: dict):
 
 
 # ------------------------------------------------------------------ descriptors
-def block_desc(cfg, dtype: str | None = None, chunk: int | None = None) -> A.BlockDesc:
+def _set_dropout(d, cfg, dropout):
+    """dropout: None (off) or (seed, offset) of the counter-based generator."""
+    if dropout is None:
+        d.dropout = 0
+        return
+    d.dropout = 1
+    d.drop_seed, d.drop_offset = int(dropout[0]), int(dropout[1])
+    d.drop_tri_mul, d.drop_tri_att = cfg.drop_tri_mul, cfg.drop_tri_att
+
+
+def block_desc(cfg, dtype: str | None = None, chunk: int | None = None, dropout=None) -> A.BlockDesc:
     d = A.BlockDesc()
+    d.opm_first = 1 if cfg.opm_first else 0
+    _set_dropout(d, cfg, dropout)
+    if dropout is not None:
+        d.drop_row_attn = cfg.drop_row_attn
     d.dtype = DTYPES[dtype or cfg.dtype][0]
     d.extra_msa = 1 if cfg.extra_msa else 0
     d.n_seq, d.n_res, d.c_m, d.c_z = cfg.n_seq, cfg.n_res, cfg.c_m, cfg.c_z
@@ -198,9 +220,9 @@ def trimul_desc(dtype: str, direction: int, n_res: int, c_z: int, c_hidden: int,
 
 # ------------------------------------------------------------------ block
 def evoformer_block_fwd(cfg, flat: FlatParams, m, z, msa_mask=None, pair_mask=None, m_out=None,
-                        z_out=None, dtype: str | None = None, chunk: int | None = None):
+                        z_out=None, dtype: str | None = None, chunk: int | None = None, dropout=None):
     lib = _lib()
-    d = block_desc(cfg, dtype, chunk)
+    d = block_desc(cfg, dtype, chunk, dropout)
     w = flat.block_struct()
     m_out = torch.empty_like(m) if m_out is None else m_out
     z_out = torch.empty_like(z) if z_out is None else z_out
@@ -220,10 +242,10 @@ def evoformer_block_fwd(cfg, flat: FlatParams, m, z, msa_mask=None, pair_mask=No
 
 
 def evoformer_block_bwd(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, dm_out, dz_out, dflat=None,
-                        dm=None, dz=None, dtype: str | None = None):
+                        dm=None, dz=None, dtype: str | None = None, dropout=None):
     """Returns (dm, dz, dflat); dflat (same layout as flat.buffer) is accumulated into."""
     lib = _lib()
-    d = block_desc(cfg, dtype, 0)
+    d = block_desc(cfg, dtype, 0, dropout)
     w = flat.block_struct()
     dflat = flat.zeros_like() if dflat is None else dflat
     dw = flat.block_struct(dflat)
@@ -244,6 +266,64 @@ def evoformer_block_bwd(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, dm_out
                                     ctypes.byref(dw), _ptr(ws), ws.numel(), _stream(m.device)),
             "evoformer_block_bwd")
     return dm, dz, dflat
+
+
+# ------------------------------------------------------------------ template pair stack block
+def template_desc(cfg, dtype: str | None = None, chunk: int | None = None, dropout=None,
+                  template_index: int = 0) -> A.TemplateDesc:
+    d = A.TemplateDesc()
+    d.dtype = DTYPES[dtype or cfg.dtype][0]
+    d.n_res, d.c_t = cfg.n_res, cfg.c_z
+    d.tri_heads, d.tri_head_dim = cfg.tri_heads, cfg.tri_head_dim
+    d.tri_mul_hidden, d.transition_factor = cfg.tri_mul_hidden, cfg.transition_factor
+    d.chunk = cfg.chunk if chunk is None else chunk
+    d.ln_eps = cfg.ln_eps
+    d.template_index = template_index
+    _set_dropout(d, cfg, dropout)
+    return d
+
+
+def template_pair_block_fwd(cfg, flat: FlatParams, t, pair_mask=None, t_out=None, dtype: str | None = None,
+                            chunk: int | None = None, dropout=None, template_index: int = 0):
+    """One template's pair features t [R, R, c_t] through one template pair stack block."""
+    lib = _lib()
+    d = template_desc(cfg, dtype, chunk, dropout, template_index)
+    w = flat.template_struct()
+    t_out = torch.empty_like(t) if t_out is None else t_out
+    RR = d.n_res * d.n_res
+    _acts(d.dtype, t.device, t=(t, RR * d.c_t), t_out=(t_out, RR * d.c_t))
+    _masks(t.device, pair_mask=(pair_mask, RR))
+    _check(flat.buffer, "parameters", torch.float32, flat.numel, t.device)
+    nbytes = lib.template_pair_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_FWD)
+    if nbytes == 0:
+        A.check(A.EVO_ESHAPE, "template_pair_block_workspace_bytes")
+    ws = workspace(nbytes, t.device)
+    A.check(lib.template_pair_block_fwd(ctypes.byref(d), ctypes.byref(w), _ptr(t), _ptr(pair_mask), _ptr(t_out),
+                                        _ptr(ws), ws.numel(), _stream(t.device)), "template_pair_block_fwd")
+    return t_out
+
+
+def template_pair_block_bwd(cfg, flat: FlatParams, t, pair_mask, dt_out, dflat=None, dt=None,
+                            dtype: str | None = None, dropout=None, template_index: int = 0):
+    """Returns (dt, dflat); dflat is accumulated into."""
+    lib = _lib()
+    d = template_desc(cfg, dtype, 0, dropout, template_index)
+    w = flat.template_struct()
+    dflat = flat.zeros_like() if dflat is None else dflat
+    dw = flat.template_struct(dflat)
+    dt = torch.empty_like(dt_out) if dt is None else dt
+    RR = d.n_res * d.n_res
+    _acts(d.dtype, t.device, t=(t, RR * d.c_t), dt_out=(dt_out, RR * d.c_t), dt=(dt, RR * d.c_t))
+    _masks(t.device, pair_mask=(pair_mask, RR))
+    _check(dflat, "parameter gradients", torch.float32, flat.numel, t.device)
+    nbytes = lib.template_pair_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
+    if nbytes == 0:
+        A.check(A.EVO_ESHAPE, "template_pair_block_workspace_bytes")
+    ws = workspace(nbytes, t.device)
+    A.check(lib.template_pair_block_bwd(ctypes.byref(d), ctypes.byref(w), _ptr(t), _ptr(pair_mask), _ptr(dt_out),
+                                        _ptr(dt), ctypes.byref(dw), _ptr(ws), ws.numel(), _stream(t.device)),
+            "template_pair_block_bwd")
+    return dt, dflat
 
 
 # ------------------------------------------------------------------ per-op entry points
@@ -368,3 +448,71 @@ def tri_mul_bwd(desc, w_struct, z, pair_mask, saved, dz_out, dw_struct, dz=None)
                             _ptr(saved), _ptr(dz_out), _ptr(dz), ctypes.byref(dw_struct), _ptr(ws),
                             ws.numel(), _stream(z.device)), "tri_mul_bwd")
     return dz
+
+
+# ------------------------------------------------------------------ optimizer (fused flat buffers)
+def _flat(t, what, n=None, device=None):
+    _check(t, what, torch.float32, n, device)
+
+
+def optim_desc(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-6, max_norm=0.0, ema_decay=0.999, step=1):
+    """evo_optim_desc_t; the defaults are AlphaFold2's Adam settings."""
+    return A.OptimDesc(lr, beta1, beta2, eps, max_norm, ema_decay, step)
+
+
+def _optim_ws(n, device):
+    return workspace(_lib().evo_optim_workspace_bytes(n), device)
+
+
+def evo_grad_global_norm(grads):
+    """The global norm of a flat FP32 gradient buffer, as a 1-element device tensor."""
+    n = grads.numel()
+    _flat(grads, "grads")
+    out = torch.empty(1, dtype=torch.float32, device=grads.device)
+    ws = _optim_ws(n, grads.device)
+    A.check(_lib().evo_grad_global_norm(_ptr(grads), n, _ptr(out), _ptr(ws), ws.numel(), _stream(grads.device)),
+            "evo_grad_global_norm")
+    return out
+
+
+def evo_clip_by_global_norm(grads, max_norm):
+    """Scales grads in place; returns the norm before clipping (device tensor)."""
+    n = grads.numel()
+    _flat(grads, "grads")
+    out = torch.empty(1, dtype=torch.float32, device=grads.device)
+    ws = _optim_ws(n, grads.device)
+    A.check(_lib().evo_clip_by_global_norm(_ptr(grads), n, float(max_norm), _ptr(out), _ptr(ws), ws.numel(),
+                                           _stream(grads.device)), "evo_clip_by_global_norm")
+    return out
+
+
+def evo_adam_step(desc, params, grads, m, v):
+    n = params.numel()
+    for name, t in (("grads", grads), ("m", m), ("v", v)):
+        _flat(t, name, n, params.device)
+    _flat(params, "params")
+    A.check(_lib().evo_adam_step(ctypes.byref(desc), _ptr(params), _ptr(grads), _ptr(m), _ptr(v), n,
+                                 _stream(params.device)), "evo_adam_step")
+
+
+def evo_ema_update(ema, params, decay):
+    n = params.numel()
+    _flat(params, "params")
+    _flat(ema, "ema", n, params.device)
+    A.check(_lib().evo_ema_update(_ptr(ema), _ptr(params), n, float(decay), _stream(params.device)),
+            "evo_ema_update")
+
+
+def evo_optimizer_step(desc, params, grads, m, v, ema=None):
+    """Clip (desc.max_norm > 0) + Adam + EMA (ema not None) in place; returns the
+    gradient norm before clipping as a device tensor (zeros without clipping)."""
+    n = params.numel()
+    _flat(params, "params")
+    for name, t in (("grads", grads), ("m", m), ("v", v), ("ema", ema)):
+        _flat(t, name, n, params.device)
+    norm = torch.zeros(1, dtype=torch.float32, device=params.device)
+    ws = _optim_ws(n, params.device)
+    A.check(_lib().evo_optimizer_step(ctypes.byref(desc), _ptr(params), _ptr(grads), _ptr(m), _ptr(v), _ptr(ema),
+                                      n, _ptr(norm), _ptr(ws), ws.numel(), _stream(params.device)),
+            "evo_optimizer_step")
+    return norm

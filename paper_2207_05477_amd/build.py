@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libevo.so")
 
 SOURCES = ["gemm.hip", "misc.hip", "attn.hip", "gattn.hip", "helpers.hip", "ops_attn.hip",
-           "ops_pair.hip", "block.hip", "api.hip"]
+           "ops_pair.hip", "block.hip", "dropout.hip", "optim.hip", "api.hip"]
 
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -28,6 +28,12 @@ evo_status_t check_attn_desc(const evo_attn_desc_t* d) {
     REQ(mult8(d->c_pair) && d->c_pair <= 256 && 256 % d->c_pair == 0, EVO_ESHAPE,
         "attention: c_pair %lld must divide 256 and be a multiple of 8", (long long)d->c_pair);
   }
+  if (d->kind == EVO_ATTN_COL_GLOBAL) {
+    // one lane per (column, head) with a column's heads on adjacent lanes of a wave
+    REQ(d->heads == 1 || d->heads == 2 || d->heads == 4 || d->heads == 8 || d->heads == 16, EVO_ESHAPE,
+        "global attention: heads %d not a power of two <= 16", d->heads);
+    REQ(d->head_dim <= 32, EVO_ESHAPE, "global attention: head_dim %d not in {8, 16, 32}", d->head_dim);
+  }
   if (d->kind == EVO_ATTN_TRI_START || d->kind == EVO_ATTN_TRI_END) {
     REQ(d->n_outer == d->n_inner, EVO_ESHAPE, "triangle attention: pair representation must be square");
     REQ(d->c_in <= 256 && 256 % d->c_in == 0, EVO_ESHAPE, "triangle attention: c_in must divide 256");
@@ -88,6 +94,35 @@ evo_status_t check_block_desc(const evo_block_desc_t* d) {
   EVO_TRY(check_opm_desc(&o));
   evo_trimul_desc_t m = block_trimul_desc(*d, EVO_TRI_OUT);
   EVO_TRY(check_trimul_desc(&m));
+  REQ(d->opm_first == 0 || d->opm_first == 1, EVO_EINVAL, "block: opm_first must be 0 or 1");
+  REQ(d->dropout == 0 || d->dropout == 1, EVO_EINVAL, "block: dropout must be 0 or 1");
+  if (d->dropout) {
+    REQ(d->chunk == 0, EVO_EINVAL, "block: dropout (training) with the chunked (inference) forward");
+    for (float r : {d->drop_row_attn, d->drop_tri_mul, d->drop_tri_att})
+      REQ(r >= 0.f && r < 1.f, EVO_EINVAL, "block: dropout rate %g outside [0, 1)", (double)r);
+    REQ(d->c_m % 4 == 0 && d->c_z % 4 == 0, EVO_ESHAPE, "block: dropout needs channels divisible by 4");
+  }
+  return EVO_OK;
+}
+
+evo_status_t check_template_desc(const evo_template_desc_t* d) {
+  REQ(d, EVO_EINVAL, "template block: null descriptor");
+  const evo_block_desc_t b = template_as_block(*d);
+  evo_attn_desc_t a = block_attn_desc(b, EVO_ATTN_TRI_START);
+  EVO_TRY(check_attn_desc(&a));
+  evo_trans_desc_t t = block_trans_desc(b, false);
+  EVO_TRY(check_trans_desc(&t));
+  evo_trimul_desc_t m = block_trimul_desc(b, EVO_TRI_OUT);
+  EVO_TRY(check_trimul_desc(&m));
+  REQ(d->dropout == 0 || d->dropout == 1, EVO_EINVAL, "template block: dropout must be 0 or 1");
+  REQ(d->template_index >= 0 && d->template_index < (1 << 24), EVO_EINVAL,
+      "template block: template_index %d outside [0, 2^24)", d->template_index);
+  if (d->dropout) {
+    REQ(d->chunk == 0, EVO_EINVAL, "template block: dropout (training) with the chunked (inference) forward");
+    for (float r : {d->drop_tri_mul, d->drop_tri_att})
+      REQ(r >= 0.f && r < 1.f, EVO_EINVAL, "template block: dropout rate %g outside [0, 1)", (double)r);
+    REQ(d->c_t % 4 == 0, EVO_ESHAPE, "template block: dropout needs c_t divisible by 4");
+  }
   return EVO_OK;
 }
 
@@ -110,6 +145,8 @@ static evo_status_t device_ok() {
   if (!cache[dev]) { set_error("device is not gfx950"); return EVO_EUNSUPPORTED; }
   return EVO_OK;
 }
+
+evo_status_t check_device() { return device_ok(); }
 
 static evo_status_t ptrs_ok(std::initializer_list<const void*> req, std::initializer_list<const void*> opt) {
   for (const void* p : req) {
@@ -155,6 +192,17 @@ static evo_status_t weights_ok(const evo_block_w_t* w, const evo_block_desc_t* d
   EVO_TRY(weights_ok(&w->tri_mul_out));
   EVO_TRY(weights_ok(&w->tri_mul_in));
   return EVO_OK;
+}
+
+static evo_status_t weights_ok(const evo_template_w_t* w, const evo_template_desc_t* d) {
+  REQ(w, EVO_EINVAL, "template block: null weights");
+  const evo_block_desc_t b = template_as_block(*d);
+  const evo_attn_desc_t a = block_attn_desc(b, EVO_ATTN_TRI_START);
+  EVO_TRY(weights_ok(&w->tri_att_start, &a));
+  EVO_TRY(weights_ok(&w->tri_att_end, &a));
+  EVO_TRY(weights_ok(&w->tri_mul_out));
+  EVO_TRY(weights_ok(&w->tri_mul_in));
+  return weights_ok(&w->pair_trans);
 }
 
 static Arena live_arena(void* p, size_t bytes) {
@@ -484,6 +532,49 @@ evo_status_t evoformer_block_bwd(const evo_block_desc_t* d, const evo_block_w_t*
                                 (const bf16*)dm_out, (const bf16*)dz_out, (bf16*)dm, (bf16*)dz, *d_w);
     return block_bwd_op<float>(c, a, *d, *w, (const float*)m, (const float*)z, msa_mask, pair_mask,
                                (const float*)dm_out, (const float*)dz_out, (float*)dm, (float*)dz, *d_w);
+  });
+}
+
+// ------------------------------------------------------------------ template pair stack block
+size_t template_pair_block_workspace_bytes(const evo_template_desc_t* d, int32_t phase) {
+  if (check_template_desc(d) != EVO_OK) return 0;
+  Ctx c; c.dry = true;
+  Arena ws; ws.dry = true;
+  evo_template_w_t w; memset(&w, 0, sizeof(w));
+  if (phase == EVO_PHASE_FWD) {
+    if (d->dtype == EVO_BF16) template_fwd_op<bf16>(c, ws, *d, w, nullptr, nullptr, nullptr);
+    else template_fwd_op<float>(c, ws, *d, w, nullptr, nullptr, nullptr);
+  } else {
+    if (d->dtype == EVO_BF16) template_bwd_op<bf16>(c, ws, *d, w, nullptr, nullptr, nullptr, nullptr, w);
+    else template_bwd_op<float>(c, ws, *d, w, nullptr, nullptr, nullptr, nullptr, w);
+  }
+  return ws.off;
+}
+
+evo_status_t template_pair_block_fwd(const evo_template_desc_t* d, const evo_template_w_t* w, const void* t,
+                                     const float* pair_mask, void* t_out, void* ws, size_t ws_bytes, void* stream) {
+  EVO_TRY(check_template_desc(d));
+  EVO_TRY(weights_ok(w, d));
+  EVO_TRY(ptrs_ok({t, t_out}, {pair_mask}));
+  return run_checked(stream, ws, ws_bytes, [&](const Ctx& c, Arena& a) -> evo_status_t {
+    if (d->dtype == EVO_BF16)
+      return template_fwd_op<bf16>(c, a, *d, *w, (const bf16*)t, pair_mask, (bf16*)t_out);
+    return template_fwd_op<float>(c, a, *d, *w, (const float*)t, pair_mask, (float*)t_out);
+  });
+}
+
+evo_status_t template_pair_block_bwd(const evo_template_desc_t* d, const evo_template_w_t* w, const void* t,
+                                     const float* pair_mask, const void* dt_out, void* dt,
+                                     const evo_template_w_t* d_w, void* ws, size_t ws_bytes, void* stream) {
+  EVO_TRY(check_template_desc(d));
+  EVO_TRY(weights_ok(w, d));
+  EVO_TRY(weights_ok(d_w, d));
+  EVO_TRY(ptrs_ok({t, dt_out, dt}, {pair_mask}));
+  REQ(d->chunk == 0, EVO_EINVAL, "template block backward: chunked execution is forward-only");
+  return run_checked(stream, ws, ws_bytes, [&](const Ctx& c, Arena& a) -> evo_status_t {
+    if (d->dtype == EVO_BF16)
+      return template_bwd_op<bf16>(c, a, *d, *w, (const bf16*)t, pair_mask, (const bf16*)dt_out, (bf16*)dt, *d_w);
+    return template_bwd_op<float>(c, a, *d, *w, (const float*)t, pair_mask, (const float*)dt_out, (float*)dt, *d_w);
   });
 }
 

@@ -15,7 +15,8 @@ struct AttnCore {
   // q, k, v, g element (b, p, h, d) at ptr + b*sb + p*sp + h*D + d
   const void* q = nullptr; const void* k = nullptr; const void* v = nullptr; const void* g = nullptr;
   int64_t sb = 0, sp = 0;
-  // per-(b, p, h) output rows: o (pre-gate context), go (gated context), stride osb/osp
+  // per-(b, p, h) output rows: o (pre-gate context, FP32; null: not kept), go (gated
+  // context), stride osb/osp
   void* o = nullptr; void* go = nullptr;
   int64_t osb = 0, osp = 0;
   // bias[h*bh + q*bq + k*bk] (FP32) or null

@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
 
   if (!qok) return;
   const float inv = 1.0f / l_run;
-  T* O = (T*)a.o + b * a.osb + qi * a.osp + h * D;
+  float* O = a.o ? (float*)a.o + b * a.osb + qi * a.osp + h * D : nullptr;
   T* GO = a.go ? (T*)a.go + b * a.osb + qi * a.osp + h * D : nullptr;
   const T* G = a.g ? (const T*)a.g + b * a.sb + qi * a.sp + h * D : nullptr;
 #pragma unroll
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
     const int d0 = 16 * dt + 4 * lg;
     if (d0 < D) {
       f32x4 o = oacc[dt] * inv;
-      store4<T>(O + d0, o);
+      if (O) store4<float>(O + d0, o);
       if (GO) {
         f32x4 gv;
 #pragma unroll

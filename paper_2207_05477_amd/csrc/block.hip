@@ -58,6 +58,57 @@ evo_trimul_desc_t block_trimul_desc(const evo_block_desc_t& b, int dir) {
   return d;
 }
 
+// Training dropout of a block: the multiplier tables of the sub-operations
+// with dropout (counter word = sub-operation number | template << 8), carved
+// from the workspace and formed in one launch.  Row attention shares its
+// multipliers along the MSA rows, the triangle multiplications and the
+// starting-node attention along the first residue axis, the ending-node
+// attention along the second.
+struct DropCfg {
+  bool on = false;
+  uint64_t seed = 0, offset = 0;
+  float rate_row = 0.f, rate_mul = 0.f, rate_att = 0.f;
+  uint32_t tmpl = 0;
+};
+enum { SUB_ROW = 0, SUB_TMO = 4, SUB_TMI = 5, SUB_TAS = 6, SUB_TAE = 7 };
+struct BlockDrop {
+  DropSpec row, tmo, tmi, tas, tae;
+};
+
+static evo_status_t make_block_drop(const Ctx& c, Arena& ws, const DropCfg& dc, int64_t R, int64_t cm, int64_t cz,
+                                    bool msa, BlockDrop* bd) {
+  *bd = BlockDrop();
+  if (!dc.on) return EVO_OK;
+  float* out[5];
+  int64_t len[5];
+  uint32_t word[5];
+  float rate[5];
+  DropSpec* spec[5];
+  int n = 0;
+  auto add = [&](DropSpec* sp, int sub, float r, int64_t C, int64_t div, int64_t mod) {
+    if (r <= 0.f) return;
+    float* t = ws.take_n<float>(R * C);
+    sp->tbl = t; sp->div = div; sp->mod = mod;
+    out[n] = t; len[n] = R * C; word[n] = (uint32_t)sub | (dc.tmpl << 8); rate[n] = r; spec[n] = sp;
+    ++n;
+  };
+  if (msa) add(&bd->row, SUB_ROW, dc.rate_row, cm, 1, R);
+  add(&bd->tmo, SUB_TMO, dc.rate_mul, cz, 1, R);
+  add(&bd->tmi, SUB_TMI, dc.rate_mul, cz, 1, R);
+  add(&bd->tas, SUB_TAS, dc.rate_att, cz, 1, R);
+  add(&bd->tae, SUB_TAE, dc.rate_att, cz, R, 0);
+  (void)spec;
+  return dropout_tables(c, dc.seed, dc.offset, n, out, len, word, rate);
+}
+
+static DropCfg block_drop_cfg(const evo_block_desc_t& d) {
+  DropCfg dc;
+  dc.on = d.dropout != 0;
+  dc.seed = d.drop_seed; dc.offset = d.drop_offset;
+  dc.rate_row = d.drop_row_attn; dc.rate_mul = d.drop_tri_mul; dc.rate_att = d.drop_tri_att;
+  return dc;
+}
+
 // Sequential scratch: every sub-op starts at the same base; the high-water mark is kept.
 struct Scratch {
   Arena base;
@@ -77,6 +128,8 @@ struct Scratch {
 template <typename T, typename X>
 static evo_status_t block_fwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
                                 const X* m, const X* z, const float* mm, const float* pm, X* mo, X* zo) {
+  BlockDrop bd;
+  EVO_TRY(make_block_drop(c, ws, block_drop_cfg(d), d.n_res, d.c_m, d.c_z, true, &bd));
   Scratch sc;
   sc.base = ws;
   const int col_kind = d.extra_msa ? EVO_ATTN_COL_GLOBAL : EVO_ATTN_COL;
@@ -87,14 +140,18 @@ static evo_status_t block_fwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
     EVO_TRY(call);                \
     sc.done(a);                   \
   } while (0)
-  EVO_STEP("row.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_ROW), w.row_attn, m, z, mm, mo)));
+  // the outer-product-mean-first order reads the block's input m and hands
+  // z + OPM(m) to both branches (the pair bias of row attention included)
+  if (d.opm_first) EVO_STEP("opm.fwd", (opm_fwd_op<T, X>(c, a, a, block_opm_desc(d), w.opm, m, mm, z, zo)));
+  const X* zpair = d.opm_first ? zo : z;
+  EVO_STEP("row.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_ROW), w.row_attn, m, zpair, mm, mo, &bd.row)));
   EVO_STEP("col.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, col_kind), w.col_attn, mo, nullptr, mm, mo)));
   EVO_STEP("msa_trans.fwd", (trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, true), w.msa_trans, mo, mo)));
-  EVO_STEP("opm.fwd", (opm_fwd_op<T, X>(c, a, a, block_opm_desc(d), w.opm, mo, mm, z, zo)));
-  EVO_STEP("tri_mul_out.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, zo, pm, zo)));
-  EVO_STEP("tri_mul_in.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, zo, pm, zo)));
-  EVO_STEP("tri_att_start.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, zo, nullptr, pm, zo)));
-  EVO_STEP("tri_att_end.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, zo, nullptr, pm, zo)));
+  if (!d.opm_first) EVO_STEP("opm.fwd", (opm_fwd_op<T, X>(c, a, a, block_opm_desc(d), w.opm, mo, mm, z, zo)));
+  EVO_STEP("tri_mul_out.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, zo, pm, zo, &bd.tmo)));
+  EVO_STEP("tri_mul_in.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, zo, pm, zo, &bd.tmi)));
+  EVO_STEP("tri_att_start.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, zo, nullptr, pm, zo, &bd.tas)));
+  EVO_STEP("tri_att_end.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, zo, nullptr, pm, zo, &bd.tae)));
   EVO_STEP("pair_trans.fwd", (trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, false), w.pair_trans, zo, zo)));
 #undef EVO_STEP
   ws.off = sc.end();
@@ -116,7 +173,13 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   evo_trimul_desc_t d_mo = block_trimul_desc(d, EVO_TRI_OUT), d_mi = block_trimul_desc(d, EVO_TRI_IN);
   d_mo.chunk = 0; d_mi.chunk = 0;
 
-  // activations between sub-ops
+  BlockDrop bd;
+  EVO_TRY(make_block_drop(c, ws, block_drop_cfg(d), d.n_res, d.c_m, d.c_z, true, &bd));
+  const bool of = d.opm_first != 0;
+  // activations between sub-ops.  A0 order: m -> m1 -> m2 -> m3 (row, column,
+  // transition), z -> z1 (outer product mean of m3) -> z2 ... z6 (pair stack).
+  // Outer-product-mean first: z -> z1 (outer product mean of m), then the MSA
+  // stack m -> m1 -> m2 -> m3 with the pair bias from z1, and the pair stack.
   X* m1 = ws.take_n<X>(SRc);
   X* m2 = ws.take_n<X>(SRc);
   X* m3 = ws.take_n<X>(SRc);
@@ -135,7 +198,7 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
     attn_fwd_op<T, X>(dry, junk, sv[0], d_row, w.row_attn, m, z, mm, m1);
     attn_fwd_op<T, X>(dry, junk, sv[1], d_col, w.col_attn, m1, nullptr, mm, m2);
     trans_fwd_op<T, X>(dry, junk, sv[2], d_tm, w.msa_trans, m2, m3);
-    opm_fwd_op<T, X>(dry, junk, sv[3], d_opm, w.opm, m3, mm, z, z1);
+    opm_fwd_op<T, X>(dry, junk, sv[3], d_opm, w.opm, m3, mm, z, z1);   // sizes only: order immaterial
     trimul_fwd_op<T, X>(dry, junk, sv[4], d_mo, w.tri_mul_out, z1, pm, z2);
     trimul_fwd_op<T, X>(dry, junk, sv[5], d_mi, w.tri_mul_in, z2, pm, z3);
     attn_fwd_op<T, X>(dry, junk, sv[6], d_tas, w.tri_att_start, z3, nullptr, pm, z4);
@@ -163,14 +226,17 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
     sc.done(a);                                                                \
   } while (0)
   // recompute the forward, keeping what the backward needs
-  EVO_STEPS(0, "row.recompute", (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, m1)));
+  const X* m_opm = of ? m : m3;     // the outer product mean's input
+  const X* z_row = of ? z1 : z;     // the pair representation row attention reads
+  if (of) EVO_STEPS(3, "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, z, z1)));
+  EVO_STEPS(0, "row.recompute", (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z_row, mm, m1, &bd.row)));
   EVO_STEPS(1, "col.recompute", (attn_fwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, m2)));
   EVO_STEPS(2, "msa_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, m3)));
-  EVO_STEPS(3, "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m3, mm, z, z1)));
-  EVO_STEPS(4, "tri_mul_out.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, z2)));
-  EVO_STEPS(5, "tri_mul_in.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, z3)));
-  EVO_STEPS(6, "tri_att_start.recompute", (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, z4)));
-  EVO_STEPS(7, "tri_att_end.recompute", (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, z5)));
+  if (!of) EVO_STEPS(3, "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, z, z1)));
+  EVO_STEPS(4, "tri_mul_out.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, z2, &bd.tmo)));
+  EVO_STEPS(5, "tri_mul_in.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, z3, &bd.tmi)));
+  EVO_STEPS(6, "tri_att_start.recompute", (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, z4, &bd.tas)));
+  EVO_STEPS(7, "tri_att_end.recompute", (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, z5, &bd.tae)));
   EVO_STEPS(8, "pair_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, z6)));
   // backward in reverse order; the pair gradient is updated in place in dz
   if (!c.dry) {
@@ -178,14 +244,16 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
     EVO_TRY(copy_elems<X>(c, dmo, dm, SRc));
   }
   EVO_STEPS(8, "pair_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, dz, dz, dw.pair_trans)));
-  EVO_STEPS(7, "tri_att_end.bwd", (attn_bwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, dz, dz, nullptr, dw.tri_att_end)));
-  EVO_STEPS(6, "tri_att_start.bwd", (attn_bwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, dz, dz, nullptr, dw.tri_att_start)));
-  EVO_STEPS(5, "tri_mul_in.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, dz, dz, dw.tri_mul_in)));
-  EVO_STEPS(4, "tri_mul_out.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, dz, dz, dw.tri_mul_out)));
-  EVO_STEPS(3, "opm.bwd", (opm_bwd_op<T, X>(c, a, s, d_opm, w.opm, m3, mm, dz, dm, dw.opm)));
+  EVO_STEPS(7, "tri_att_end.bwd", (attn_bwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, dz, dz, nullptr, dw.tri_att_end, &bd.tae)));
+  EVO_STEPS(6, "tri_att_start.bwd", (attn_bwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, dz, dz, nullptr, dw.tri_att_start, &bd.tas)));
+  EVO_STEPS(5, "tri_mul_in.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, dz, dz, dw.tri_mul_in, &bd.tmi)));
+  EVO_STEPS(4, "tri_mul_out.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, dz, dz, dw.tri_mul_out, &bd.tmo)));
+  // dz now holds the gradient at z1; the outer product mean passes it on to z
+  if (!of) EVO_STEPS(3, "opm.bwd", (opm_bwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, dz, dm, dw.opm)));
   EVO_STEPS(2, "msa_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, dm, dm, dw.msa_trans)));
   EVO_STEPS(1, "col.bwd", (attn_bwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, dm, dm, nullptr, dw.col_attn)));
-  EVO_STEPS(0, "row.bwd", (attn_bwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z, mm, dm, dm, dz, dw.row_attn)));
+  EVO_STEPS(0, "row.bwd", (attn_bwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z_row, mm, dm, dm, dz, dw.row_attn, &bd.row)));
+  if (of) EVO_STEPS(3, "opm.bwd", (opm_bwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, dz, dm, dw.opm)));
 #undef EVO_STEPS
   ws.off = sc.end();
   return EVO_OK;
@@ -232,6 +300,161 @@ evo_status_t block_bwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, co
     return convert_elems<float, T>(c, dzx, dz, RRc);
   }
 }
+
+// ============================================================== template pair stack block
+// The pair-stack sub-operations on one template's pair features, in the
+// template order (attention around the starting and the ending node, outgoing
+// and incoming multiplication, transition); sub-op descriptors come from an
+// Evoformer block descriptor with c_z = c_t.
+evo_block_desc_t template_as_block(const evo_template_desc_t& t) {
+  evo_block_desc_t b;
+  memset(&b, 0, sizeof(b));
+  b.dtype = t.dtype;
+  b.n_seq = 1; b.n_res = t.n_res; b.c_m = 8; b.c_z = t.c_t;
+  b.msa_heads = 1; b.msa_head_dim = 8;
+  b.tri_heads = t.tri_heads; b.tri_head_dim = t.tri_head_dim;
+  b.tri_mul_hidden = t.tri_mul_hidden; b.opm_hidden = 8; b.transition_factor = t.transition_factor;
+  b.chunk = t.chunk;
+  b.ln_eps = t.ln_eps; b.opm_eps = 1e-3f; b.global_eps = 1e-10f;
+  return b;
+}
+
+static DropCfg template_drop_cfg(const evo_template_desc_t& d) {
+  DropCfg dc;
+  dc.on = d.dropout != 0;
+  dc.seed = d.drop_seed; dc.offset = d.drop_offset;
+  dc.rate_mul = d.drop_tri_mul; dc.rate_att = d.drop_tri_att;
+  dc.tmpl = (uint32_t)d.template_index;
+  return dc;
+}
+
+template <typename T, typename X>
+static evo_status_t template_fwd_x(const Ctx& c, Arena& ws, const evo_template_desc_t& td, const evo_template_w_t& w,
+                                   const X* t, const float* pm, X* to) {
+  const evo_block_desc_t d = template_as_block(td);
+  BlockDrop bd;
+  EVO_TRY(make_block_drop(c, ws, template_drop_cfg(td), d.n_res, 0, d.c_z, false, &bd));
+  Scratch sc;
+  sc.base = ws;
+#define EVO_STEP(tag, call)       \
+  do {                            \
+    ProfTag pt_(tag);             \
+    Arena a = sc.fresh();         \
+    EVO_TRY(call);                \
+    sc.done(a);                   \
+  } while (0)
+  EVO_STEP("tri_att_start.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, t, nullptr, pm, to, &bd.tas)));
+  EVO_STEP("tri_att_end.fwd", (attn_fwd_op<T, X>(c, a, a, block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, to, nullptr, pm, to, &bd.tae)));
+  EVO_STEP("tri_mul_out.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, to, pm, to, &bd.tmo)));
+  EVO_STEP("tri_mul_in.fwd", (trimul_fwd_op<T, X>(c, a, a, block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, to, pm, to, &bd.tmi)));
+  EVO_STEP("pair_trans.fwd", (trans_fwd_op<T, X>(c, a, a, block_trans_desc(d, false), w.pair_trans, to, to)));
+#undef EVO_STEP
+  ws.off = sc.end();
+  return EVO_OK;
+}
+
+template <typename T, typename X>
+static evo_status_t template_bwd_x(const Ctx& c, Arena& ws, const evo_template_desc_t& td, const evo_template_w_t& w,
+                                   const X* t, const float* pm, const X* dto, X* dt, const evo_template_w_t& dw) {
+  evo_block_desc_t d = template_as_block(td);
+  d.chunk = 0;
+  const int64_t RRc = d.n_res * d.n_res * d.c_z;
+  const evo_attn_desc_t d_tas = block_attn_desc(d, EVO_ATTN_TRI_START), d_tae = block_attn_desc(d, EVO_ATTN_TRI_END);
+  const evo_trimul_desc_t d_mo = block_trimul_desc(d, EVO_TRI_OUT), d_mi = block_trimul_desc(d, EVO_TRI_IN);
+  const evo_trans_desc_t d_tz = block_trans_desc(d, false);
+  BlockDrop bd;
+  EVO_TRY(make_block_drop(c, ws, template_drop_cfg(td), d.n_res, 0, d.c_z, false, &bd));
+  // t -> t1 (start) -> t2 (end) -> t3 (out) -> t4 (in) -> t5 (transition)
+  X* t1 = ws.take_n<X>(RRc);
+  X* t2 = ws.take_n<X>(RRc);
+  X* t3 = ws.take_n<X>(RRc);
+  X* t4 = ws.take_n<X>(RRc);
+  X* t5 = ws.take_n<X>(RRc);
+  Arena sv[5];
+  for (int i = 0; i < 5; ++i) sv[i].dry = true;
+  {
+    Ctx dry = c; dry.dry = true;
+    Arena junk; junk.dry = true;
+    attn_fwd_op<T, X>(dry, junk, sv[0], d_tas, w.tri_att_start, t, nullptr, pm, t1);
+    attn_fwd_op<T, X>(dry, junk, sv[1], d_tae, w.tri_att_end, t1, nullptr, pm, t2);
+    trimul_fwd_op<T, X>(dry, junk, sv[2], d_mo, w.tri_mul_out, t2, pm, t3);
+    trimul_fwd_op<T, X>(dry, junk, sv[3], d_mi, w.tri_mul_in, t3, pm, t4);
+    trans_fwd_op<T, X>(dry, junk, sv[4], d_tz, w.pair_trans, t4, t5);
+  }
+  char* svbase[5];
+  for (int i = 0; i < 5; ++i) svbase[i] = (char*)ws.take(sv[i].off);
+  auto S = [&](int i) {
+    Arena a;
+    a.dry = c.dry;
+    a.base = svbase[i];
+    a.cap = sv[i].off;
+    return a;
+  };
+  Scratch sc;
+  sc.base = ws;
+#define EVO_STEPS(i, tag, call)                                                \
+  do {                                                                         \
+    ProfTag pt_(tag);                                                          \
+    Arena a = sc.fresh();                                                      \
+    Arena s = S(i);                                                            \
+    EVO_TRY(with_batched_reductions(c, [&](const Ctx& c) { return call; })); \
+    sc.done(a);                                                                \
+  } while (0)
+  EVO_STEPS(0, "tri_att_start.recompute", (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, t, nullptr, pm, t1, &bd.tas)));
+  EVO_STEPS(1, "tri_att_end.recompute", (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, t1, nullptr, pm, t2, &bd.tae)));
+  EVO_STEPS(2, "tri_mul_out.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, t2, pm, t3, &bd.tmo)));
+  EVO_STEPS(3, "tri_mul_in.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, t3, pm, t4, &bd.tmi)));
+  EVO_STEPS(4, "pair_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tz, w.pair_trans, t4, t5)));
+  if (!c.dry) EVO_TRY(copy_elems<X>(c, dto, dt, RRc));
+  EVO_STEPS(4, "pair_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tz, w.pair_trans, t4, dt, dt, dw.pair_trans)));
+  EVO_STEPS(3, "tri_mul_in.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, t3, pm, dt, dt, dw.tri_mul_in, &bd.tmi)));
+  EVO_STEPS(2, "tri_mul_out.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, t2, pm, dt, dt, dw.tri_mul_out, &bd.tmo)));
+  EVO_STEPS(1, "tri_att_end.bwd", (attn_bwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, t1, nullptr, pm, dt, dt, nullptr, dw.tri_att_end, &bd.tae)));
+  EVO_STEPS(0, "tri_att_start.bwd", (attn_bwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, t, nullptr, pm, dt, dt, nullptr, dw.tri_att_start, &bd.tas)));
+#undef EVO_STEPS
+  ws.off = sc.end();
+  return EVO_OK;
+}
+
+template <typename T>
+evo_status_t template_fwd_op(const Ctx& c, Arena& ws, const evo_template_desc_t& d, const evo_template_w_t& w,
+                             const T* t, const float* pm, T* to) {
+  if constexpr (std::is_same<T, float>::value) {
+    return template_fwd_x<T, float>(c, ws, d, w, t, pm, to);
+  } else {
+    const int64_t RRc = d.n_res * d.n_res * d.c_t;
+    float* tx = ws.take_n<float>(RRc);
+    EVO_TRY((convert_elems<T, float>(c, t, tx, RRc)));
+    EVO_TRY((template_fwd_x<T, float>(c, ws, d, w, tx, pm, tx)));
+    return convert_elems<float, T>(c, tx, to, RRc);
+  }
+}
+
+template <typename T>
+evo_status_t template_bwd_op(const Ctx& c, Arena& ws, const evo_template_desc_t& d, const evo_template_w_t& w,
+                             const T* t, const float* pm, const T* dto, T* dt, const evo_template_w_t& dw) {
+  if constexpr (std::is_same<T, float>::value) {
+    return template_bwd_x<T, float>(c, ws, d, w, t, pm, dto, dt, dw);
+  } else {
+    const int64_t RRc = d.n_res * d.n_res * d.c_t;
+    float* tx = ws.take_n<float>(RRc);
+    float* dtx = ws.take_n<float>(RRc);
+    EVO_TRY((convert_elems<T, float>(c, t, tx, RRc)));
+    EVO_TRY((convert_elems<T, float>(c, dto, dtx, RRc)));
+    EVO_TRY((template_bwd_x<T, float>(c, ws, d, w, tx, pm, dtx, dtx, dw)));
+    return convert_elems<float, T>(c, dtx, dt, RRc);
+  }
+}
+
+template evo_status_t template_fwd_op<float>(const Ctx&, Arena&, const evo_template_desc_t&, const evo_template_w_t&,
+                                             const float*, const float*, float*);
+template evo_status_t template_fwd_op<bf16>(const Ctx&, Arena&, const evo_template_desc_t&, const evo_template_w_t&,
+                                            const bf16*, const float*, bf16*);
+template evo_status_t template_bwd_op<float>(const Ctx&, Arena&, const evo_template_desc_t&, const evo_template_w_t&,
+                                             const float*, const float*, const float*, float*,
+                                             const evo_template_w_t&);
+template evo_status_t template_bwd_op<bf16>(const Ctx&, Arena&, const evo_template_desc_t&, const evo_template_w_t&,
+                                            const bf16*, const float*, const bf16*, bf16*, const evo_template_w_t&);
 
 #define EVO_INST_B(T)                                                                              \
   template evo_status_t block_fwd_op<T>(const Ctx&, Arena&, const evo_block_desc_t&,               \

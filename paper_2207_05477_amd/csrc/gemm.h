@@ -38,9 +38,10 @@ struct GemmEpilogue {
   const float* bias = nullptr;         // [N]
   int32_t act = ACT_NONE;
   int32_t act_n0 = 0;
-  const float* scale = nullptr;        // scale[(m >> sm_shift) * sm_ld + (n >> sn_shift) * sn_ld]
-  int32_t sm_shift = 0, sn_shift = 0;
-  int64_t sm_ld = 0, sn_ld = 0;
+  const float* scale = nullptr;        // scale[srow(m) * sm_ld + (n >> sn_shift) * sn_ld],
+  int32_t sm_shift = 0, sn_shift = 0;  // srow(m) = ((m >> sm_shift) / sm_div) % sm_mod
+  int64_t sm_ld = 0, sn_ld = 0;        // (sm_mod = 0: no modulo)
+  int64_t sm_div = 1, sm_mod = 0;
   const void* relu_ref = nullptr;      // kernel type, addressed like resid
   const void* gate = nullptr;          // kernel type (FP32 if gate_f32), gate[m * g_m + n * g_n]
   int64_t g_m = 0, g_n = 0;
@@ -50,6 +51,14 @@ struct GemmEpilogue {
   int64_t r_m = 0, r_n = 0;
   int32_t resid_f32 = 0;
 };
+
+// Row index of the epilogue scale table (32-bit: output rows stay below 2^31).
+EVO_DEV int64_t scale_row(const GemmEpilogue& e, int64_t m) {
+  uint32_t q = (uint32_t)(m >> e.sm_shift);
+  if (e.sm_div > 1) q /= (uint32_t)e.sm_div;
+  if (e.sm_mod > 0) q %= (uint32_t)e.sm_mod;
+  return (int64_t)q;
+}
 
 struct GemmArgs {
   int64_t M = 0, N = 0, K = 0;

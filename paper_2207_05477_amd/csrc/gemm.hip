@@ -155,7 +155,7 @@ template <typename T>
 EVO_DEV float epi_value(const GemmEpilogue& e, int64_t zo, int64_t off, int64_t m, int64_t n, float acc) {
   float v = e.alpha * acc;
   if (e.bias) v += e.bias[n];
-  if (e.scale) v *= e.scale[(m >> e.sm_shift) * e.sm_ld + (n >> e.sn_shift) * e.sn_ld];
+  if (e.scale) v *= e.scale[scale_row(e, m) * e.sm_ld + (n >> e.sn_shift) * e.sn_ld];
   if (e.act == ACT_RELU) v = fmaxf(v, 0.0f);
   else if (e.act == ACT_SIGMOID && n >= e.act_n0) v = sigmoidf_(v);
   // auxiliary inputs: own plain strides, or the output's addressing when the m-stride is < 0
@@ -860,12 +860,12 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
       }
       const int mo = moff[i];
       if (e.scale) {
+        const int64_t sr = scale_row(e, m) * e.sm_ld;
         if (e.sn_shift >= 2) {   // n is a multiple of 4: the lane's 4 columns share one entry
-          v *= ok ? e.scale[(m >> e.sm_shift) * e.sm_ld + (n >> e.sn_shift) * e.sn_ld] : 0.f;
+          v *= ok ? e.scale[sr + (n >> e.sn_shift) * e.sn_ld] : 0.f;
         } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            v[r] *= ok ? e.scale[(m >> e.sm_shift) * e.sm_ld + ((n + r) >> e.sn_shift) * e.sn_ld] : 0.f;
+          for (int r = 0; r < 4; ++r) v[r] *= ok ? e.scale[sr + ((n + r) >> e.sn_shift) * e.sn_ld] : 0.f;
         }
       }
       const uint32_t eo = (uint32_t)(e.r_m < 0 ? mo + no : m * pi.ldr + n);   // aux element offset

@@ -123,7 +123,7 @@ evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n);
 // go/o/g/dgo have row pitches; dctx written with pitch ld_dctx, dgpre with ld_dg.  dgo is FP32.
 template <typename T>
 evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
-                      const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
+                      const float* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
                       T* dgpre, int64_t ld_dg, float* D);
 
 // Triangle multiplication projections, forward: raw[p][4*ch + cz] (ap | ag | bp | bg | g, compute type)

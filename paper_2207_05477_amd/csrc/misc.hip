@@ -1215,7 +1215,7 @@ evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n) {
 // ============================================================== attention gate backward
 template <typename T>
 __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int hd, const float* dgo,
-                                                       int64_t ld_dgo, const T* o, int64_t ld_o,
+                                                       int64_t ld_dgo, const float* o, int64_t ld_o,
                                                        const T* g, int64_t ld_g, T* dctx,
                                                        int64_t ld_dctx, T* dgp, int64_t ld_dg,
                                                        float* D) {
@@ -1242,7 +1242,7 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int 
 // lanes per head, consecutive and aligned inside the wave).
 template <typename T, int LPH>
 __global__ __launch_bounds__(256) void gate_bwd_vec_kernel(int64_t rows, int H, int hd, const float* dgo,
-                                                           int64_t ld_dgo, const T* o, int64_t ld_o,
+                                                           int64_t ld_dgo, const float* o, int64_t ld_o,
                                                            const T* g, int64_t ld_g, T* dctx,
                                                            int64_t ld_dctx, T* dgp, int64_t ld_dg,
                                                            float* D) {
@@ -1271,7 +1271,7 @@ __global__ __launch_bounds__(256) void gate_bwd_vec_kernel(int64_t rows, int H, 
 
 template <typename T>
 evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
-                      const T* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
+                      const float* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
                       T* dgpre, int64_t ld_dg, float* D) {
   if (c.dry || rows == 0) return EVO_OK;
   const int64_t n = rows * H * hd;
@@ -1629,7 +1629,7 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<const PackArgs*>);        \
   template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \
   template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
-  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t, const T*, \
+  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t, const float*, \
                                     int64_t, const T*, int64_t, T*, int64_t, T*, int64_t, float*); \
   template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const T*, const float*,      \
                                        T*, T*, int64_t, float*);                                   \

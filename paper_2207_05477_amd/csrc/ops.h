@@ -60,14 +60,39 @@ inline const T* as_compute(const Ctx& c, Arena& ws, const X* p, int64_t n, evo_s
 }
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// ---- training dropout of a residual update (dropout.hip)
+// Multiplier of update element (row r, channel c): tbl[((r / div) % mod) * C + c]
+// (mod = 0: no modulo).  On z rows r = i * R + j: shared along i (a table over
+// j) is div = 1, mod = R; shared along j (a table over i) is div = R, mod = 0.
+struct DropSpec {
+  const float* tbl = nullptr;
+  int64_t div = 1, mod = 0;
+};
+// Multiplier tables from Philox4x32-10: table t has len[t] entries drawn at
+// counter word word[t] (0 or 1 / (1 - rate[t])); one launch for all tables.
+evo_status_t dropout_tables(const Ctx& c, uint64_t seed, uint64_t offset, int n, float* const* out,
+                            const int64_t* len, const uint32_t* word, const float* rate);
+// dst = src * multiplier (rows x C, C a multiple of 4); dst may alias src.
+template <typename X>
+evo_status_t dropout_apply(const Ctx& c, const X* src, X* dst, int64_t rows, int C, const DropSpec& d);
+inline void epi_dropout(GemmEpilogue& e, const DropSpec* d, int64_t C) {
+  if (!d || !d->tbl) return;
+  e.scale = d->tbl; e.sm_shift = 0; e.sm_div = d->div; e.sm_mod = d->mod; e.sm_ld = C;
+  e.sn_shift = 0; e.sn_ld = 1;
+}
+
 // ---- ops (T = float or bf16; X = residual-stream type, T or float)
+// drop: optional training dropout of the op's residual update (attention of
+// the MSA rows and both triangle kinds, both triangle multiplications).
 template <typename T, typename X = T>
 evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
-                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask, X* out);
+                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask, X* out,
+                         const DropSpec* drop = nullptr);
 template <typename T, typename X = T>
 evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
                          const evo_attn_w_t& w, const X* x, const X* pair, const float* mask,
-                         const X* dout, X* dx, X* dpair, const evo_attn_w_t& dw);
+                         const X* dout, X* dx, X* dpair, const evo_attn_w_t& dw,
+                         const DropSpec* drop = nullptr);
 
 template <typename T, typename X = T>
 evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_desc_t& d,
@@ -87,11 +112,12 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
 
 template <typename T, typename X = T>
 evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
-                           const evo_trimul_w_t& w, const X* z, const float* mask, X* zout);
+                           const evo_trimul_w_t& w, const X* z, const float* mask, X* zout,
+                           const DropSpec* drop = nullptr);
 template <typename T, typename X = T>
 evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
                            const evo_trimul_w_t& w, const X* z, const float* mask, const X* dzo,
-                           X* dz, const evo_trimul_w_t& dw);
+                           X* dz, const evo_trimul_w_t& dw, const DropSpec* drop = nullptr);
 
 // ---- argument validation shared by the ABI entry points
 evo_status_t check_attn_desc(const evo_attn_desc_t* d);
@@ -113,5 +139,15 @@ template <typename T>
 evo_status_t block_bwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
                           const T* m, const T* z, const float* mm, const float* pm, const T* dmo,
                           const T* dzo, T* dm, T* dz, const evo_block_w_t& dw);
+
+// Template pair stack block (block.hip).
+evo_block_desc_t template_as_block(const evo_template_desc_t& t);
+evo_status_t check_template_desc(const evo_template_desc_t* d);
+template <typename T>
+evo_status_t template_fwd_op(const Ctx& c, Arena& ws, const evo_template_desc_t& d, const evo_template_w_t& w,
+                             const T* t, const float* pm, T* to);
+template <typename T>
+evo_status_t template_bwd_op(const Ctx& c, Arena& ws, const evo_template_desc_t& d, const evo_template_w_t& w,
+                             const T* t, const float* pm, const T* dto, T* dt, const evo_template_w_t& dw);
 
 }  // namespace evo

@@ -34,24 +34,27 @@ struct AttnSaved {
   T* yz; float* zmean; float* zrstd;
   T* qkvg;
   float* bias;
-  T* o; T* go;
+  float* o;   // pre-gate context, FP32
+  T* go;
   float* st_max; float* st_inv;
-  float* gctx;
+  float* gctx; float* qbar; float* minv;
   void carve(Arena& a, const AttnShape& s) {
     y = a.take_n<T>(s.rows * s.cin);
     mean = a.take_n<float>(s.rows);
     rstd = a.take_n<float>(s.rows);
-    yz = nullptr; zmean = zrstd = nullptr; bias = nullptr; gctx = nullptr;
+    yz = nullptr; zmean = zrstd = nullptr; bias = nullptr; gctx = qbar = minv = nullptr;
     if (s.row) bias = a.take_n<float>((int64_t)s.H * s.ni * s.ni);
     if (s.tri) bias = a.take_n<float>((int64_t)s.H * s.rows);
     qkvg = a.take_n<T>(s.rows * s.NQ);
     if (s.global) {
       gctx = a.take_n<float>(s.ni * s.HC);
+      qbar = a.take_n<float>(s.ni * s.HC);
+      minv = a.take_n<float>(s.ni);
       st_max = a.take_n<float>(s.ni * s.H);
       st_inv = a.take_n<float>(s.ni * s.H);
       o = nullptr;
     } else {
-      o = a.take_n<T>(s.rows * s.HC);
+      o = a.take_n<float>(s.rows * s.HC);
       st_max = a.take_n<float>(s.rows * s.H);
       st_inv = a.take_n<float>(s.rows * s.H);
     }
@@ -97,13 +100,19 @@ void set_qkvg(AttnCore& a, const T* qkvg, const AttnShape& s) {
 
 }  // namespace
 
+// Global column attention (gattn.hip): forward scratch size in FP32 elements,
+// forward and backward.  qbar [R][H*D] is the masked-mean query, minv[i] =
+// 1 / (sum_s M_si + eps), gctx [R][H*D] the context, smax / sinv [R][H] the
+// softmax statistics.
+int64_t gattn_fwd_scratch(int64_t S, int64_t R, int H, int D);
 template <typename T>
-evo_status_t gattn_fwd(const Ctx& c, int64_t S, int64_t R, int H, int D, const T* qkvg, const float* mask,
-                       float eps, float* gctx, float* smax, float* sinv, T* go);
+evo_status_t gattn_fwd(const Ctx& c, float* scratch, int64_t S, int64_t R, int H, int D, const T* qkvg,
+                       const float* mask, float eps, float* qbar, float* minv, float* gctx, float* smax,
+                       float* sinv, T* go);
 template <typename T>
 evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int D, const T* qkvg,
-                       const float* mask, float eps, const float* gctx, const float* smax,
-                       const float* sinv, const float* dgo, T* dqkvg);
+                       const float* mask, const float* qbar, const float* minv, const float* gctx,
+                       const float* smax, const float* sinv, const float* dgo, T* dqkvg);
 
 // Forward of triangle attention in chunks of `chunk` batch rows (starting node:
 // rows i; ending node: columns j), keeping no saved state.  Only the chunk's
@@ -124,7 +133,6 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
   float* mean = ws.take_n<float>(CR);
   float* rstd = ws.take_n<float>(CR);
   T* qkvg = ws.take_n<T>(CR * s.NQ);
-  T* o = ws.take_n<T>(CR * s.HC);
   T* go = ws.take_n<T>(CR * s.HC);
   if (c.dry) return EVO_OK;
   PackArgs pk;
@@ -159,7 +167,7 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
     g.epi.act_n0 = s.NQ - s.HC;
     EVO_TRY(gemm<T>(c, g));
     AttnCore a;
-    a.H = s.H; a.D = s.D; a.o = o; a.go = go; a.bias = bias; a.bh = R * R;
+    a.H = s.H; a.D = s.D; a.o = nullptr; a.go = go; a.bias = bias; a.bh = R * R;
     a.nbatch = C; a.Lq = a.Lk = R;
     if (start) {
       a.sb = R * s.NQ; a.sp = s.NQ; a.osb = R * s.HC; a.osp = s.HC;
@@ -195,14 +203,19 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
 
 template <typename T, typename X>
 evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
-                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask, X* out) {
+                         const evo_attn_w_t& w, const X* x, const X* pair, const float* mask, X* out,
+                         const DropSpec* drop) {
   const AttnShape s = attn_shape(d);
-  if (s.tri && d.chunk > 0 && d.chunk < s.ni) return attn_fwd_tri_chunked<T, X>(c, ws, d, s, w, x, mask, out);
+  if (s.tri && d.chunk > 0 && d.chunk < s.ni) {
+    if (drop && drop->tbl) { set_error("attention: the chunked forward has no dropout"); return EVO_EINVAL; }
+    return attn_fwd_tri_chunked<T, X>(c, ws, d, s, w, x, mask, out);
+  }
   AttnSaved<T> S;
   S.carve(sv, s);
   T* wt_qkvg = ws.take_n<T>((int64_t)s.NQ * s.cin);
   float* b_qkvg = ws.take_n<float>(s.NQ);
   T* wt_o = ws.take_n<T>((int64_t)s.cin * s.HC);
+  float* ga_scratch = s.global ? ws.take_n<float>(gattn_fwd_scratch(s.no, s.ni, s.H, s.D)) : nullptr;
   if (c.dry) return EVO_OK;
 
   // parameters: forward operands [n][k] in the compute type
@@ -241,8 +254,8 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY((ln_rowproj<X, T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, S.bias)));
   }
   if (s.global) {
-    EVO_TRY(gattn_fwd<T>(c, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
-                         S.st_inv, S.go));
+    EVO_TRY(gattn_fwd<T>(c, ga_scratch, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.qbar, S.minv,
+                         S.gctx, S.st_max, S.st_inv, S.go));
   } else {
     AttnCore a = core_for(s, S.qkvg, S.o, S.go, S.bias, mask, S.st_max, S.st_inv);
     set_qkvg<T>(a, S.qkvg, s);
@@ -255,6 +268,7 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     g.B = op_rowmajor(wt_o, s.HC);
     epi_out<X>(g.epi, out, s.cin);
     g.epi.bias = w.b_o;
+    epi_dropout(g.epi, drop, s.cin);
     epi_resid<X>(g.epi, x, s.cin, 1);
     EVO_TRY(gemm<T>(c, g));
   }
@@ -264,10 +278,17 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
 template <typename T, typename X>
 evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc_t& d,
                          const evo_attn_w_t& w, const X* x, const X* pair, const float* mask,
-                         const X* dout, X* dx, X* dpair, const evo_attn_w_t& dw) {
+                         const X* dout, X* dx, X* dpair, const evo_attn_w_t& dw, const DropSpec* drop) {
   const AttnShape s = attn_shape(d);
   AttnSaved<T> S;
   S.carve(sv, s);
+  // with dropout the update's gradient is drop * dout; the residual passes dout on
+  const X* dres = dout;
+  if (drop && drop->tbl) {
+    X* dd = ws.take_n<X>(s.rows * s.cin);
+    EVO_TRY(dropout_apply<X>(c, dout, dd, s.rows, (int)s.cin, *drop));
+    dout = dd;
+  }
   evo_status_t cst;
   const T* dout_t = as_compute<T, X>(c, ws, dout, s.rows * s.cin, &cst);
   EVO_TRY(cst);
@@ -327,7 +348,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   }
   if (s.global) {
     ProfTag t_("core");
-    EVO_TRY(gattn_bwd<T>(c, ws, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.gctx, S.st_max,
+    EVO_TRY(gattn_bwd<T>(c, ws, s.no, s.ni, s.H, s.D, S.qkvg, mask, S.qbar, S.minv, S.gctx, S.st_max,
                          S.st_inv, dgo, dqkvg));
   } else {
     // gate and attention core
@@ -387,17 +408,18 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   // input LayerNorm and residual
   float* part = ws.take_n<float>((size_t)ln_bwd_partials(s.rows) * 2 * s.cin);
   int nb = 0;
-  EVO_TRY(ln_bwd<X>(c, x, S.mean, S.rstd, w.ln_g, dy, s.rows, (int)s.cin, dout, false, dx, part, &nb));
+  EVO_TRY(ln_bwd<X>(c, x, S.mean, S.rstd, w.ln_g, dy, s.rows, (int)s.cin, dres, false, dx, part, &nb));
   if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)s.cin, dw.ln_g, dw.ln_b));
   return EVO_OK;
 }
 
 #define EVO_INST_A(T, X)                                                                           \
   template evo_status_t attn_fwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,      \
-                                          const evo_attn_w_t&, const X*, const X*, const float*, X*); \
+                                          const evo_attn_w_t&, const X*, const X*, const float*, X*, \
+                                          const DropSpec*);                                          \
   template evo_status_t attn_bwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_attn_desc_t&,      \
                                           const evo_attn_w_t&, const X*, const X*, const float*,   \
-                                          const X*, X*, X*, const evo_attn_w_t&);
+                                          const X*, X*, X*, const evo_attn_w_t&, const DropSpec*);
 
 EVO_INST_A(float, float)
 EVO_INST_A(bf16, bf16)

@@ -374,8 +374,15 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
 
 template <typename T, typename X>
 evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
-                           const evo_trimul_w_t& w, const X* z, const float* mask, X* zout) {
-  if (d.chunk > 0 && d.chunk < d.n_res) return trimul_fwd_chunked<T, X>(c, ws, d, w, z, mask, zout);
+                           const evo_trimul_w_t& w, const X* z, const float* mask, X* zout,
+                           const DropSpec* drop) {
+  if (d.chunk > 0 && d.chunk < d.n_res) {
+    if (drop && drop->tbl) {
+      set_error("triangle multiplication: the chunked forward has no dropout");
+      return EVO_EINVAL;
+    }
+    return trimul_fwd_chunked<T, X>(c, ws, d, w, z, mask, zout);
+  }
   TriSaved<T> S;
   S.carve(sv, d);
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
@@ -432,6 +439,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   epi_out<X>(g.epi, zout, cz);
   g.epi.bias = w.b_o;
   g.epi.gate = S.raw + 4 * ch; g.epi.g_m = NP; g.epi.g_n = 1; g.epi.gate_f32 = 0;
+  epi_dropout(g.epi, drop, cz);
   epi_resid<X>(g.epi, z, cz, 1);
   return gemm<T>(c, g);
 }
@@ -439,10 +447,17 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
 template <typename T, typename X>
 evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_desc_t& d,
                            const evo_trimul_w_t& w, const X* z, const float* mask, const X* dzo,
-                           X* dz, const evo_trimul_w_t& dw) {
+                           X* dz, const evo_trimul_w_t& dw, const DropSpec* drop) {
   TriSaved<T> S;
   S.carve(sv, d);
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
+  // with dropout the update's gradient is drop * dzo; the residual passes dzo on
+  const X* dres = dzo;
+  if (drop && drop->tbl) {
+    X* dd = ws.take_n<X>(P * cz);
+    EVO_TRY(dropout_apply<X>(c, dzo, dd, P, (int)cz, *drop));
+    dzo = dd;
+  }
   T* w_p = ws.take_n<T>(cz * NP);      // [cz][NP]
   T* wt_o = ws.take_n<T>(cz * ch);     // [cz][ch]
   T* w_o = ws.take_n<T>(ch * cz);      // [ch][cz]
@@ -547,7 +562,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   }
   float* part = ws.take_n<float>((size_t)ln_bwd_partials(P) * 2 * cz);
   int nb = 0;
-  EVO_TRY(ln_bwd<X>(c, z, S.mean, S.rstd, w.ln_g, dy, P, (int)cz, dzo, false, dz, part, &nb));
+  EVO_TRY(ln_bwd<X>(c, z, S.mean, S.rstd, w.ln_g, dy, P, (int)cz, dres, false, dz, part, &nb));
   if (!c.dry) EVO_TRY(reduce_partials2(c, part, nb, (int)cz, dw.ln_g, dw.ln_b));
   return EVO_OK;
 }
@@ -564,10 +579,11 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
                                          const evo_opm_w_t&, const X*, const float*, const X*, X*, \
                                          const evo_opm_w_t&);                                      \
   template evo_status_t trimul_fwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,  \
-                                            const evo_trimul_w_t&, const X*, const float*, X*);    \
+                                            const evo_trimul_w_t&, const X*, const float*, X*,     \
+                                            const DropSpec*);                                      \
   template evo_status_t trimul_bwd_op<T, X>(const Ctx&, Arena&, Arena&, const evo_trimul_desc_t&,  \
                                             const evo_trimul_w_t&, const X*, const float*,         \
-                                            const X*, X*, const evo_trimul_w_t&);
+                                            const X*, X*, const evo_trimul_w_t&, const DropSpec*);
 
 EVO_INST_P(float, float)
 EVO_INST_P(bf16, bf16)

@@ -16,7 +16,7 @@ import torch
 from oracle import evoformer as O
 from synth import EvoConfig, get, make_inputs
 
-from gpu_util import TOL, check, device_view, margin_view, say, to_dev
+from gpu_util import TOL, bf16_weight_view, check, check_quant, check_update, device_view, margin_view, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -26,18 +26,24 @@ SMALL = EvoConfig("small", n_seq=12, n_res=40, c_m=32, c_z=16, msa_heads=2, msa_
 torch.set_num_threads(min(32, os.cpu_count() or 8))
 
 
-def check_block_grads(tag, views, gref, tol, report=None):
-    """Every parameter gradient of one block, tensor by tensor."""
+def check_block_grads(tag, views, gref, tol, report=None, gref_q=None):
+    """Every parameter gradient of one block, tensor by tensor (with gref_q, the
+    oracle's gradients under BF16-rounded matrix weights: see check_quant)."""
     for sub, ps in gref.items():
         for name, ref in ps.items():
             # zero by an identity (the pair-bias gradient sums to zero over
             # keys): bounded by the magnitude of the matching gamma gradient
             floor = ps["ln_z_g"].norm().item() if name == "ln_z_b" else 0.0
             efloor = ps["ln_z_g"].abs().max().item() if name == "ln_z_b" else 0.0
-            check(f"{tag}{sub}.{name}", views[sub][name], ref, tol, report, floor=floor, efloor=efloor)
+            if gref_q is None:
+                check(f"{tag}{sub}.{name}", views[sub][name], ref, tol, report, floor=floor, efloor=efloor)
+            else:
+                check_quant(f"{tag}{sub}.{name}", views[sub][name], ref, gref_q[sub][name], tol, report,
+                            floor=floor, efloor=efloor)
 
 
-def _run(cfg, dtype, seed=32, backward=True, perturb=False, mask_mode=None, report=None, margins=True):
+def _run(cfg, dtype, seed=32, backward=True, perturb=False, mask_mode=None, report=None, margins=True,
+         quant=False):
     from paper_2207_05477_amd import binding as B
     inp = make_inputs(cfg, seed=seed, perturb=perturb, mask_mode=mask_mode)
     inp = margin_view(inp, cfg, dtype) if margins else device_view(inp, dtype)
@@ -53,14 +59,21 @@ def _run(cfg, dtype, seed=32, backward=True, perturb=False, mask_mode=None, repo
     mm, pm = inp["msa_mask"].float().cuda(), inp["pair_mask"].float().cuda()
     mo, zo = B.evoformer_block_fwd(cfg, flat, m, z, mm, pm, dtype=dtype)
     torch.cuda.synchronize()
-    check("m update", mo.double().cpu() - inp["m"], mo_ref - inp["m"], tol, report)
-    check("z update", zo.double().cpu() - inp["z"], zo_ref - inp["z"], tol, report)
+    check_update("m update", mo, inp["m"], mo_ref - inp["m"], dtype, report)
+    check_update("z update", zo, inp["z"], zo_ref - inp["z"], dtype, report)
     if not backward:
         return
     del mo, zo
     dm, dz, dflat = B.evoformer_block_bwd(cfg, flat, m, z, mm, pm, to_dev(inp["dm_out"], dtype),
                                           to_dev(inp["dz_out"], dtype), dtype=dtype)
     torch.cuda.synchronize()
+    if quant:   # small fan-ins: the BF16 weight quantization's own effect (see check_quant)
+        say("  oracle with BF16-rounded matrix weights")
+        _, _, gq = O.stack_fwd_bwd(bf16_weight_view(inp), cfg)
+        check_quant("dm", dm, g["m"], gq["m"], tol, report)
+        check_quant("dz", dz, g["z"], gq["z"], tol, report)
+        check_block_grads("", flat.views(dflat), g["params"][0], tol, report, gq["params"][0])
+        return
     check("dm", dm, g["m"], tol, report)
     check("dz", dz, g["z"], tol, report)
     check_block_grads("", flat.views(dflat), g["params"][0], tol, report)
@@ -79,14 +92,14 @@ def test_block_c0_forward_f32():
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_block_small_fwd_bwd(dtype):
-    _run(SMALL, dtype, seed=5, perturb=True)
+    _run(SMALL, dtype, seed=5, perturb=True, quant=dtype == "bf16")
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_extra_msa_block_small_fwd_bwd(dtype):
     cfg = SMALL.replace(name="small_extra", extra_msa=True, msa_heads=4, msa_head_dim=8,
                         msa_input="onehot23")
-    _run(cfg, dtype, seed=6, perturb=True)
+    _run(cfg, dtype, seed=6, perturb=True, quant=dtype == "bf16")
 
 
 def test_block_c1_fwd_bwd_f32():

@@ -14,7 +14,7 @@ import torch
 from oracle import evoformer as O
 from synth import EvoConfig, make_inputs
 
-from gpu_util import MARGIN, TOL, check, device_view, oracle_grads, params_dev, say, to_dev
+from gpu_util import MARGIN, TOL, check, check_update, device_view, oracle_grads, params_dev, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def test_row_attn(dtype, hd, n_res):
     x, pair, mask = to_dev(inp["m"], dtype), to_dev(inp["z"], dtype), M.float().cuda()
     out, saved = B.evo_attn_fwd(desc, w, x, pair, mask)
     torch.cuda.synchronize()
-    check("row fwd", out.double().cpu() - inp["m"], upd, tol)
+    check_update("row fwd", out, inp["m"], upd, dtype)
     dpar = _zeros_like(pd)
     dpair = torch.zeros_like(pair)
     dx = B.evo_attn_bwd(desc, w, x, pair, mask, saved, to_dev(inp["dm_out"], dtype),
@@ -93,7 +93,7 @@ def test_col_attn(dtype):
     x, mask = to_dev(inp["m"], dtype), M.float().cuda()
     out, saved = B.evo_attn_fwd(desc, w, x, None, mask)
     torch.cuda.synchronize()
-    check("col fwd", out.double().cpu() - inp["m"], upd, tol)
+    check_update("col fwd", out, inp["m"], upd, dtype)
     dpar = _zeros_like(pd)
     dx = B.evo_attn_bwd(desc, w, x, None, mask, saved, to_dev(inp["dm_out"], dtype),
                         B.weight_struct("col_attn", dpar))
@@ -121,7 +121,7 @@ def test_col_global_attn(dtype):
     x, mask = to_dev(inp["m"], dtype), M.float().cuda()
     out, saved = B.evo_attn_fwd(desc, w, x, None, mask)
     torch.cuda.synchronize()
-    check("gcol fwd", out.double().cpu() - inp["m"], upd, tol)
+    check_update("gcol fwd", out, inp["m"], upd, dtype)
     dpar = _zeros_like(pd)
     dx = B.evo_attn_bwd(desc, w, x, None, mask, saved, to_dev(inp["dm_out"], dtype),
                         B.weight_struct("col_attn", dpar))
@@ -152,7 +152,7 @@ def test_tri_attn(dtype, kind, n_res):
     x, mask = to_dev(inp["z"], dtype), P.float().cuda()
     out, saved = B.evo_attn_fwd(desc, w, x, None, mask)
     torch.cuda.synchronize()
-    check(f"{sub} fwd", out.double().cpu() - inp["z"], upd, tol)
+    check_update(f"{sub} fwd", out, inp["z"], upd, dtype)
     dpar = _zeros_like(pd)
     dx = B.evo_attn_bwd(desc, w, x, None, mask, saved, to_dev(inp["dz_out"], dtype),
                         B.weight_struct(sub, dpar))
@@ -181,7 +181,7 @@ def test_tri_mul(dtype, direction):
     x, mask = to_dev(inp["z"], dtype), P.float().cuda()
     out, saved = B.tri_mul_fwd(desc, w, x, mask)
     torch.cuda.synchronize()
-    check(f"{sub} fwd", out.double().cpu() - inp["z"], upd, tol)
+    check_update(f"{sub} fwd", out, inp["z"], upd, dtype)
     dpar = _zeros_like(pd)
     dz = B.tri_mul_bwd(desc, w, x, mask, saved, to_dev(inp["dz_out"], dtype), B.weight_struct(sub, dpar))
     torch.cuda.synchronize()
@@ -246,7 +246,7 @@ def test_transition(dtype, which):
     x = to_dev(x64, dtype)
     out, saved = B.evo_transition_fwd(desc, w, x)
     torch.cuda.synchronize()
-    check(f"{sub} fwd", out.double().cpu() - x64, upd, tol)
+    check_update(f"{sub} fwd", out, x64, upd, dtype)
     dpar = _zeros_like(pd)
     dx = B.evo_transition_bwd(desc, w, x, saved, to_dev(up, dtype), B.weight_struct(sub, dpar))
     torch.cuda.synchronize()

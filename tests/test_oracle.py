@@ -619,3 +619,32 @@ def test_template_block_vs_brute_and_gradcheck():
     for n in range(cfg.n_templ):
         ref = O.template_pair_block(inp["t"][n], inp["pair_mask"][n], p, cfg, dropout=(5, 2), template=n)
         _close(out[n], ref.detach(), 1e-12)
+
+
+def test_template_stack_forward_and_relu_margins():
+    # the block-by-block template forward equals the per-template chain, and the
+    # margin construction clears the margin on every template at once
+    from synth import make_template_inputs
+    cfg = TINY.replace(n_templ=3, n_blocks=2, c_z=4, tri_heads=2, tri_head_dim=2, tri_mul_hidden=3,
+                       transition_factor=2)
+    inp = make_template_inputs(cfg, seed=9, perturb=True)
+    out, _ = O.template_stack_fwd_bwd(inp, cfg, dropout=(3, 1), want_param_grads=False)
+    _close(O.template_stack_fwd(inp, cfg, dropout=(3, 1)), out, 1e-12)
+    m = O.with_template_relu_margins(inp, cfg, 0.05, dropout=(3, 1))
+    probe = {}
+    O.template_stack_fwd(m, cfg, dropout=(3, 1), probe=probe)
+    assert min(probe["min_abs"]) >= 0.05 * (1 - 1e-9)
+    assert len(probe["min_abs"]) == cfg.n_blocks * cfg.n_templ
+    # only the transitions' b_1 change
+    for b0, b1 in zip(inp["params"], m["params"]):
+        for s in b0:
+            for k in b0[s]:
+                if not (s == "pair_trans" and k == "b_1"):
+                    assert torch.equal(b0[s][k], b1[s][k])
+
+
+def test_relu_margins_with_dropout():
+    cfg = TINY.replace(n_blocks=2)
+    inp = make_inputs(cfg, seed=10, perturb=True)
+    m = O.with_relu_margins(inp, cfg, 0.05, dropout=(4, 7))
+    assert O.relu_margin(m, cfg, dropout=(4, 7)) >= 0.05 * (1 - 1e-9)
