@@ -223,6 +223,16 @@ static evo_status_t run_checked(void* stream, void* ws, size_t ws_bytes, F fn) {
   REQ(dw.off <= ws_bytes, EVO_EWORKSPACE, "workspace too small: %zu bytes needed, %zu given", dw.off, ws_bytes);
   REQ(dw.off == 0 || ws != nullptr, EVO_EINVAL, "workspace pointer is null");
   REQ(aligned16(ws), EVO_EINVAL, "workspace not 16-byte aligned");
+  {
+    // Shadow pass: the same code without launches, carving the caller's real
+    // workspace, so that every branch on a carved pointer goes the way the live
+    // pass goes.  A live pass needing more than the sizing pass found would
+    // write past the end of the workspace: refuse it before anything runs.
+    Arena sh = live_arena(ws, ws_bytes);
+    EVO_TRY(fn(dry, sh));
+    REQ(!sh.overflow(), EVO_EWORKSPACE, "internal: the workspace sizing (%zu bytes) is short of what the call carves "
+        "(%zu bytes)", dw.off, sh.off);
+  }
   EVO_TRY(device_ok());
   Ctx c;
   c.stream = (hipStream_t)stream;

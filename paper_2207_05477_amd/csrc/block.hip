@@ -87,8 +87,8 @@ static evo_status_t make_block_drop(const Ctx& c, Arena& ws, const DropCfg& dc, 
   int n = 0;
   auto add = [&](DropSpec* sp, int sub, float r, int64_t C, int64_t div, int64_t mod) {
     if (r <= 0.f) return;
-    float* t = ws.take_n<float>(R * C);
-    sp->tbl = t; sp->div = div; sp->mod = mod;
+    float* t = ws.take_n<float>(R * C);   // null in the sizing pass; `on` holds in both
+    sp->tbl = t; sp->div = div; sp->mod = mod; sp->on = true;
     out[n] = t; len[n] = R * C; word[n] = (uint32_t)sub | (dc.tmpl << 8); rate[n] = r; spec[n] = sp;
     ++n;
   };

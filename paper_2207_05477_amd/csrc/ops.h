@@ -64,9 +64,13 @@ inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 // Multiplier of update element (row r, channel c): tbl[((r / div) % mod) * C + c]
 // (mod = 0: no modulo).  On z rows r = i * R + j: shared along i (a table over
 // j) is div = 1, mod = R; shared along j (a table over i) is div = R, mod = 0.
+// `on` says whether the op has dropout at all: it holds in the sizing pass too,
+// where tbl (carved from a dry arena) is null, so that both passes carve the
+// same scratch.
 struct DropSpec {
   const float* tbl = nullptr;
   int64_t div = 1, mod = 0;
+  bool on = false;
 };
 // Multiplier tables from Philox4x32-10: table t has len[t] entries drawn at
 // counter word word[t] (0 or 1 / (1 - rate[t])); one launch for all tables.
@@ -76,7 +80,7 @@ evo_status_t dropout_tables(const Ctx& c, uint64_t seed, uint64_t offset, int n,
 template <typename X>
 evo_status_t dropout_apply(const Ctx& c, const X* src, X* dst, int64_t rows, int C, const DropSpec& d);
 inline void epi_dropout(GemmEpilogue& e, const DropSpec* d, int64_t C) {
-  if (!d || !d->tbl) return;
+  if (!d || !d->on) return;
   e.scale = d->tbl; e.sm_shift = 0; e.sm_div = d->div; e.sm_mod = d->mod; e.sm_ld = C;
   e.sn_shift = 0; e.sn_ld = 1;
 }

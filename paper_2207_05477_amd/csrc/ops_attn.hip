@@ -207,7 +207,7 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
                          const DropSpec* drop) {
   const AttnShape s = attn_shape(d);
   if (s.tri && d.chunk > 0 && d.chunk < s.ni) {
-    if (drop && drop->tbl) { set_error("attention: the chunked forward has no dropout"); return EVO_EINVAL; }
+    if (drop && drop->on) { set_error("attention: the chunked forward has no dropout"); return EVO_EINVAL; }
     return attn_fwd_tri_chunked<T, X>(c, ws, d, s, w, x, mask, out);
   }
   AttnSaved<T> S;
@@ -284,7 +284,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   S.carve(sv, s);
   // with dropout the update's gradient is drop * dout; the residual passes dout on
   const X* dres = dout;
-  if (drop && drop->tbl) {
+  if (drop && drop->on) {
     X* dd = ws.take_n<X>(s.rows * s.cin);
     EVO_TRY(dropout_apply<X>(c, dout, dd, s.rows, (int)s.cin, *drop));
     dout = dd;

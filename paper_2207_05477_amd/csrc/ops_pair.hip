@@ -377,7 +377,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
                            const evo_trimul_w_t& w, const X* z, const float* mask, X* zout,
                            const DropSpec* drop) {
   if (d.chunk > 0 && d.chunk < d.n_res) {
-    if (drop && drop->tbl) {
+    if (drop && drop->on) {
       set_error("triangle multiplication: the chunked forward has no dropout");
       return EVO_EINVAL;
     }
@@ -453,7 +453,7 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   const int64_t R = d.n_res, P = R * R, ch = d.c_hidden, cz = d.c_z, NP = 4 * ch + cz;
   // with dropout the update's gradient is drop * dzo; the residual passes dzo on
   const X* dres = dzo;
-  if (drop && drop->tbl) {
+  if (drop && drop->on) {
     X* dd = ws.take_n<X>(P * cz);
     EVO_TRY(dropout_apply<X>(c, dzo, dd, P, (int)cz, *drop));
     dzo = dd;

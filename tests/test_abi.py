@@ -172,3 +172,53 @@ def test_binding_rejects_wrong_dtype_shape_and_device():
     with pytest.raises(ValueError, match="on cpu"):
         B._check(m, "m", torch.float32, m.numel(), "meta")
     B._acts(B.A.EVO_F32, m.device, m=(m, m.numel()), z=(None, 3))
+
+
+@pytest.mark.parametrize("variant", ["dropout", "opm_first+dropout"])
+def test_workspace_query_matches_a_real_call_with_dropout(variant):
+    # Dropout tables are carved from the workspace; a sizing pass that took
+    # them for absent would size the backward short of the live pass (whose
+    # per-op gradient scaling carves a buffer of its own) and the call would
+    # run past the end of the workspace.  The entry points' shadow pass checks
+    # the live carving against the size: with exactly the queried size the
+    # call must get past the workspace check (and stop at the device check).
+    A, lib = _lib()
+    from paper_2207_05477_amd import binding as B
+    cfg = synth.get("C0").replace(opm_first="opm_first" in variant, backward=True)
+    d = B.block_desc(cfg, dropout=(7, 3))
+    w = A.BlockW()
+    dw = A.BlockW()
+    for i, (sub, cls) in enumerate(A.BlockW._fields_):
+        setattr(w, sub, _full_weights(A, cls, i))
+        setattr(dw, sub, _full_weights(A, cls, i + 32))
+    for phase in (A.EVO_PHASE_FWD, A.EVO_PHASE_BWD):
+        need = lib.evoformer_block_workspace_bytes(ctypes.byref(d), phase)
+        assert need > 0
+        if phase == A.EVO_PHASE_FWD:
+            st = lib.evoformer_block_fwd(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), _fake(3), _fake(4),
+                                         _fake(5), _fake(6), _fake(7), need, None)
+        else:
+            st = lib.evoformer_block_bwd(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), _fake(3), _fake(4),
+                                         _fake(5), _fake(6), _fake(7), _fake(8), ctypes.byref(dw), _fake(9), need,
+                                         None)
+        assert st in (A.EVO_EHIP, A.EVO_EUNSUPPORTED), lib.evo_last_error()
+
+
+def test_template_workspace_query_matches_a_real_call_with_dropout():
+    A, lib = _lib()
+    from paper_2207_05477_amd import binding as B
+    cfg = synth.get("T").replace(n_res=40)
+    d = B.template_desc(cfg, dropout=(7, 3), template_index=2)
+    w = A.TemplateW()
+    dw = A.TemplateW()
+    for i, (sub, cls) in enumerate(A.TemplateW._fields_):
+        setattr(w, sub, _full_weights(A, cls, i))
+        setattr(dw, sub, _full_weights(A, cls, i + 32))
+    need = lib.template_pair_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_FWD)
+    st = lib.template_pair_block_fwd(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), _fake(3), _fake(4), need,
+                                     None)
+    assert st in (A.EVO_EHIP, A.EVO_EUNSUPPORTED), lib.evo_last_error()
+    need = lib.template_pair_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
+    st = lib.template_pair_block_bwd(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), _fake(3), _fake(4),
+                                     ctypes.byref(dw), _fake(6), need, None)
+    assert st in (A.EVO_EHIP, A.EVO_EUNSUPPORTED), lib.evo_last_error()
