@@ -27,6 +27,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from emitting packed FP32 VALU ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results in ordinary VGPRs: no AGPR round trips around the
+         # VALU work on accumulators (softmax, epilogues) and fewer registers
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
 
 
