@@ -137,7 +137,13 @@ evo_status_t evo_attn_bwd(const evo_attn_desc_t* desc, const evo_attn_w_t* w,
                           const evo_attn_w_t* d_w, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ transition
- * x + ReLU(LayerNorm(x) W_1 + b_1) W_2 + b_2, hidden = factor * c; x = [rows, c]. */
+ * The MSA and pair transitions of the two stacks of a block (paper, Section
+ * "Branch Parallelism": the MSA stack and the pair stack each end in one; the
+ * operator is AlphaFold2's, which the paper follows, Section "Hyperparameter
+ * setting"):
+ *   out = x + ReLU(LayerNorm(x) W_1 + b_1) W_2 + b_2,  hidden = factor * c;  x = [rows, c]
+ *   (rows = N_seq * N_res for the MSA transition, N_res^2 for the pair transition).
+ * Errors: EVO_ESHAPE unless c is a positive multiple of 8 at most 512 and factor >= 1. */
 typedef struct {
   int32_t dtype;
   int64_t rows, c, factor;
@@ -182,6 +188,9 @@ evo_status_t opm_bwd(const evo_opm_desc_t* desc, const evo_opm_w_t* w, const voi
                      const evo_opm_w_t* d_w, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ triangle multiplication
+ * The triangle multiplicative updates of the pair stack, outgoing and incoming edges (paper,
+ * Section "Branch Parallelism": the pair stack of a block, run on its own device under BP; the
+ * operator is AlphaFold2's, Section "Hyperparameter setting"):
  *   y = LayerNorm(z); a = P * sigmoid(y W_ag + b_ag) * (y W_ap + b_ap); b likewise;
  *   g = sigmoid(y W_g + b_g)
  *   OUT: x_ij = sum_k a_ik b_jk      IN: x_ij = sum_k a_ki b_kj
