@@ -373,6 +373,19 @@ evo_status_t evo_optimizer_step(const evo_optim_desc_t* desc, float* params, con
                                 float* v, float* ema, int64_t n, float* norm_out, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight training loops, harnesses that forbid hipMalloc): evo_optimizer_step
+ * without a workspace.  The norm's partial sums go to a static device array of
+ * the library (1024 doubles = 8 KiB per GPU, held until the process ends); the
+ * partial count is min(1024, ceil(n / 16384)), so every n fits, and a count
+ * above the array would be rejected with EVO_ESHAPE.  The call allocates
+ * nothing.  Every call on one GPU shares that array: calls that overlap on one
+ * GPU (other streams, other threads) race.  Its contents before a call do not
+ * matter (the partials are written before they are read). */
+evo_status_t evo_optimizer_step_noalloc(const evo_optim_desc_t* desc, float* params, const float* grads,
+                                        float* m, float* v, float* ema, int64_t n, float* norm_out,
+                                        void* stream);
+
 /* ------------------------------------------------------------------ launch profiler
  * Optional per-launch timing for roofline reports.  Between evo_profile_begin
  * and evo_profile_end every kernel the library enqueues is bracketed by two

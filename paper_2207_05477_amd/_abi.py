@@ -143,6 +143,7 @@ _SIGS = {
     "evo_ema_update": ([_P, _P, c_int64, c_double, _P], c_int32),
     "evo_optimizer_step": ([POINTER(OptimDesc), _P, _P, _P, _P, _P, c_int64, _P, _P, c_size_t, _P],
                            c_int32),
+    "evo_optimizer_step_noalloc": ([POINTER(OptimDesc), _P, _P, _P, _P, _P, c_int64, _P, _P], c_int32),
 }
 
 EXPORTS = tuple(_SIGS)

@@ -516,3 +516,16 @@ def evo_optimizer_step(desc, params, grads, m, v, ema=None):
                                       n, _ptr(norm), _ptr(ws), ws.numel(), _stream(params.device)),
             "evo_optimizer_step")
     return norm
+
+
+def evo_optimizer_step_noalloc(desc, params, grads, m, v, ema=None):
+    """evo_optimizer_step without a workspace (the library's static scratch)."""
+    n = params.numel()
+    _flat(params, "params")
+    for name, t in (("grads", grads), ("m", m), ("v", v), ("ema", ema)):
+        _flat(t, name, n, params.device)
+    norm = torch.zeros(1, dtype=torch.float32, device=params.device)
+    A.check(_lib().evo_optimizer_step_noalloc(ctypes.byref(desc), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                                              _ptr(ema), n, _ptr(norm), _stream(params.device)),
+            "evo_optimizer_step_noalloc")
+    return norm

@@ -16,6 +16,8 @@
 //                 updated in the same pass.
 // The fused step is therefore two launches: the norm partials and one pass of
 // clip + Adam + EMA.  Deterministic: no atomics, fixed reduction orders.
+#include <mutex>
+
 #include "ops.h"
 
 namespace evo {
@@ -231,6 +233,33 @@ static evo_status_t vec_ptrs_ok(std::initializer_list<const void*> req, std::ini
   return EVO_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation variant
+// Scratch of evo_optimizer_step_noalloc: the global norm's partial sums, one
+// static array per device (OPT_MAX_PARTS doubles = 8 KiB, whatever n).  Host
+// code never passes the array's name to a kernel: its device address is
+// taken once per device with hipGetSymbolAddress and kept here.
+static __device__ __align__(256) double scratch[OPT_MAX_PARTS];
+
+constexpr int OPT_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[OPT_MAX_DEVICES];
+
+static evo_status_t scratch_address(double** out) {
+  int dev = 0;
+  EVO_CHECK_ARG(hipGetDevice(&dev) == hipSuccess, EVO_EHIP, "optimizer: no HIP device");
+  EVO_CHECK_ARG(dev >= 0 && dev < OPT_MAX_DEVICES, EVO_EHIP, "optimizer: device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    EVO_CHECK_ARG(e == hipSuccess && ptr, EVO_EHIP, "optimizer: hipGetSymbolAddress(scratch): %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (double*)g_scratch_ptr[dev];
+  return EVO_OK;
+}
+
 evo_status_t check_device();
 
 }  // namespace evo
@@ -314,6 +343,20 @@ evo_status_t evo_optimizer_step(const evo_optim_desc_t* d, float* params, const 
     part = (double*)ws;
   }
   EVO_TRY(check_device());
+  return optim_step((hipStream_t)stream, *d, params, grads, m, v, ema, n, norm_out, part);
+}
+
+evo_status_t evo_optimizer_step_noalloc(const evo_optim_desc_t* d, float* params, const float* grads, float* m,
+                                        float* v, float* ema, int64_t n, float* norm_out, void* stream) {
+  EVO_TRY(check_optim_desc(d));
+  EVO_CHECK_ARG(n >= 0, EVO_ESHAPE, "optimizer: negative length");
+  EVO_TRY(vec_ptrs_ok({params, grads, m, v}, {ema, norm_out}, n == 0));
+  // the norm's partial sums live in the static scratch (at most OPT_MAX_PARTS of them)
+  EVO_CHECK_ARG(norm_parts(n) <= OPT_MAX_PARTS, EVO_ESHAPE,
+                "optimizer: %d norm partials exceed the static scratch of %d", norm_parts(n), OPT_MAX_PARTS);
+  EVO_TRY(check_device());
+  double* part = nullptr;
+  if (d->max_norm > 0.0) EVO_TRY(scratch_address(&part));
   return optim_step((hipStream_t)stream, *d, params, grads, m, v, ema, n, norm_out, part);
 }
 
