@@ -182,7 +182,7 @@ def roofline_of(stats, dtype):
 def kernel_class(name: str):
     """Kernel class of a detail-mode profiler key "kernel@sub-operation tags"."""
     k, _, tag = name.partition("@")
-    if k.startswith("attn_fwd_kernel"):
+    if k.startswith("attn_fwd_"):
         return "attention_fwd"
     if k.startswith("attn_bwd_"):
         return "attention_bwd"

@@ -10,16 +10,19 @@ namespace evo {
 
 // Logit given to masked keys (replaces the logit; fully masked rows average uniformly).
 constexpr float kMaskLogit = -1e30f;
+// The kernels work in the log2 domain: logits and the bias are scaled by log2(e).
+constexpr float kLog2e = 1.4426950408889634f;
 
 struct AttnCore {
   // q, k, v, g element (b, p, h, d) at ptr + b*sb + p*sp + h*D + d
   const void* q = nullptr; const void* k = nullptr; const void* v = nullptr; const void* g = nullptr;
   int64_t sb = 0, sp = 0;
-  // per-(b, p, h) output rows: o (pre-gate context, FP32; null: not kept), go (gated
-  // context), stride osb/osp
+  // per-(b, p, h) output rows: o (pre-gate context, FP32: the backward's row sums
+  // of the context gradient with it need more than 16-bit precision; null: not
+  // kept), go (gated context), stride osb/osp
   void* o = nullptr; void* go = nullptr;
   int64_t osb = 0, osp = 0;
-  // bias[h*bh + q*bq + k*bk] (FP32) or null
+  // log2(e) * bias, at [h*bh + q*bq + k*bk] (FP32), or null
   const float* bias = nullptr; int64_t bh = 0, bq = 0, bk = 0;
   // key mask[b*mb + k*mk] (FP32 0/1) or null
   const float* mask = nullptr; int64_t mb = 0, mk = 0;
@@ -37,8 +40,11 @@ struct AttnGrad {
   // outputs: dq, dk, dv with addressing (b, p, h, d) -> ptr + b*dsb + p*dsp + h*D + d
   void* dq = nullptr; void* dk = nullptr; void* dv = nullptr;
   int64_t dsb = 0, dsp = 0;
-  // bias-gradient partials [group][H][Lq][Lk] FP32 (null: no bias gradient)
+  // bias-gradient partials [group][H][Lq*Lk] FP32, element (q, k) of a slice at
+  // q*dbq + k*dbk (null: no bias gradient); the gradient is with respect to the
+  // bias itself, not log2(e) * bias
   float* dbias_part = nullptr;
+  int64_t dbq = 0, dbk = 0;
   int64_t group = 1;             // batches summed per partial
 };
 

@@ -24,7 +24,6 @@
 
 namespace evo {
 
-constexpr float kLog2e = 1.4426950408889634f;
 constexpr int KB = 64;   // keys (or queries, in the dK/dV kernel) per LDS tile
 constexpr float kLazy = 8.0f;   // forward: log2 headroom before the running maximum moves
 
@@ -241,8 +240,8 @@ EVO_DEV void key_fold(const float* mask, int64_t mk, int64_t k, int64_t kend, fl
 // scalar loads.
 enum { BIAS_NONE = 0, BIAS_ROWS = 1, BIAS_COLS = 2, BIAS_STRIDED = 3 };
 
-// 64 x 64 bias tile in LDS, log2 domain:
-// sb[r * BP + c] = log2(e) * bias[(r0 + r) * sr + (c0 + c) * sc].  Loads clamp
+// 64 x 64 bias tile in LDS (the bias is stored in the log2 domain):
+// sb[r * BP + c] = bias[(r0 + r) * sr + (c0 + c) * sc].  Loads clamp
 // rows and columns into range (out-of-range entries are finite copies, never
 // used: their keys get -inf, their queries are discarded), so no lane
 // zero-fills or branches per element.  Register staged like RowsStage: load()
@@ -295,14 +294,14 @@ struct LogBiasStage {
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
         const int e = tid + 256 * it;
-        *(f32x4*)(sb + (e >> 4) * BP + (e & 15) * 4) = v[it] * kLog2e;
+        *(f32x4*)(sb + (e >> 4) * BP + (e & 15) * 4) = v[it];
       }
     } else if constexpr (BM != BIAS_NONE) {
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
         const int c = 16 * it + (tid & 15), r = (tid >> 4) * 4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[it][i] * kLog2e;
+        for (int i = 0; i < 4; ++i) sb[(r + i) * BP + c] = v[it][i];
       }
     }
   }
@@ -462,6 +461,332 @@ __global__ __launch_bounds__(256) void attn_fwd_kernel(AttnCore a, float scale_l
   }
 }
 
+// ============================================================== forward, keys resident in LDS
+// When all keys of one (batch, head) fit in LDS (BF16), a workgroup stages K
+// (row-major), V^T and the per-key multipliers once, behind one barrier, and
+// its waves then run on their own: wave w takes the 16-query subtiles w,
+// w + 4, ... of the workgroup's qb queries, each through every key tile.  The
+// bias has unit stride along keys, so every lane reads the 16 bias values of
+// its query's logits in a tile as four 16-byte vectors straight from memory,
+// one tile ahead of their use.  Key tiles with no masked key and no key past
+// the end (a per-tile flag) form their logits as fma(s, scale, bias) without
+// the per-key multipliers.  Logits, the lazily moved maximum, the BF16 row
+// sums and the epilogue are those of attn_fwd_kernel, operation for operation.
+struct ResLayout {
+  int64_t lkp;          // keys rounded up to whole 64-key tiles
+  int64_t tp;           // pitch of V^T rows (elements)
+  int64_t off_vt, off_ks, off_ka, off_flag, bytes;
+};
+template <int D>
+__host__ __device__ inline ResLayout res_layout(int64_t Lk) {
+  using F = DF<bf16, D>;
+  ResLayout L;
+  L.lkp = (Lk + 63) / 64 * 64;
+  L.tp = L.lkp + 4;   // row pitch 2 lkp + 8 bytes: the 8-byte reads of 16 rows fall on distinct banks
+  L.off_vt = L.lkp * F::DP * 2;
+  L.off_ks = L.off_vt + (int64_t)F::DR * L.tp * 2;
+  L.off_ka = L.off_ks + L.lkp * 4;
+  L.off_flag = L.off_ka + L.lkp * 4;
+  L.bytes = (L.off_flag + L.lkp / 64 * 4 + 15) / 16 * 16;
+  return L;
+}
+
+// Transposed store of two key rows r, r + 1 (8 elements of d from dv each)
+// into V^T: consecutive keys of one d share a 4-byte word.
+EVO_DEV void store_vt_pair(bf16* dst_t, int64_t pitch, int r, int dv, const uint4& v0, const uint4& v1) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t w0 = u4word(v0, i >> 1), w1 = u4word(v1, i >> 1);
+    *(uint32_t*)(dst_t + (dv + i) * pitch + r) =
+        (i & 1) ? ((w0 >> 16) | (w1 & 0xffff0000u)) : ((w0 & 0xffffu) | (w1 << 16));
+  }
+}
+
+// Maximum over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the 16-lane rows of a
+// wave), with the row swaps of gfx950 (v_permlane16_swap: rows 0 <-> 1 and
+// 2 <-> 3; v_permlane32_swap: rows 0, 1 <-> 2, 3) instead of LDS permutes.
+EVO_DEV float rows_max(float v) {
+  const auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = fmaxf(__uint_as_float(p16[0]), __uint_as_float(p16[1]));
+  const auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(p32[0]), __uint_as_float(p32[1]));
+}
+
+// Raw buffer resource over `bytes` bytes (loads past the extent return zeros).
+EVO_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+EVO_DEV f32x4 buf_load_f32x4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4_t;
+  const i32x4_t q = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return f32x4{__int_as_float(q[0]), __int_as_float(q[1]), __int_as_float(q[2]), __int_as_float(q[3])};
+}
+
+template <int D, int BM, int NB>
+__global__ __launch_bounds__(256 * NB) __attribute__((amdgpu_waves_per_eu(4))) void attn_fwd_res_kernel(
+    AttnCore a, float scale_log2, int qb) {
+  using T = bf16;
+  using F = DF<T, D>;
+  static_assert(BM == BIAS_NONE || BM == BIAS_ROWS, "resident-key forward: bias with unit key stride only");
+  constexpr int NT = 256 * NB, NW = 4 * NB;   // threads and waves of the workgroup
+  extern __shared__ __attribute__((aligned(16))) unsigned char res_smem[];
+  const ResLayout L = res_layout<D>(a.Lk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const WgCoord wg = xcd_coord();
+  const int64_t b0 = (int64_t)wg.z * NB;
+  const int nb = a.nbatch - b0 < NB ? (int)(a.nbatch - b0) : NB;   // batches of this workgroup
+  const int h = wg.y;
+  const int lkp = (int)L.lkp, nkt = lkp / 64, Lk = (int)a.Lk;
+  auto sK = [&](int g) { return (T*)(res_smem + g * L.bytes); };
+  auto sVt = [&](int g) { return (T*)(res_smem + g * L.bytes + L.off_vt); };
+  auto sKs = [&](int g) { return (float*)(res_smem + g * L.bytes + L.off_ks); };
+  auto sKa = [&](int g) { return (float*)(res_smem + g * L.bytes + L.off_ka); };
+  auto sFlag = [&](int g) { return (int*)(res_smem + g * L.bytes + L.off_flag); };
+
+  // ---- stage K, V^T and the key multipliers of each batch (rows from Lk on
+  // repeat row Lk - 1: finite, and their keys get -inf)
+  constexpr int VPR = D / F::VEC;
+  const int nk = lkp * VPR, nv = (lkp / 2) * VPR, half = lkp / 2;
+#pragma unroll
+  for (int g = 0; g < NB; ++g) {
+    if (g >= nb) break;
+    const T* K = (const T*)a.k + (b0 + g) * a.sb + h * D;
+    const T* V = (const T*)a.v + (b0 + g) * a.sb + h * D;
+    for (int e0 = 0; e0 < nk; e0 += 4 * NT) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + NT * u + tid, r = e / VPR, dv = (e % VPR) * F::VEC;
+        v[u] = make_uint4(0, 0, 0, 0);
+        if (e < nk) v[u] = *(const uint4*)(K + (int64_t)(r < Lk ? r : Lk - 1) * a.sp + dv);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + NT * u + tid, r = e / VPR, dv = (e % VPR) * F::VEC;
+        if (e < nk) *(uint4*)(sK(g) + r * F::DP + dv) = v[u];
+      }
+    }
+    for (int e0 = 0; e0 < nv; e0 += 2 * NT) {
+      uint4 v0[2], v1[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + NT * u + tid, r = 2 * (e % half), dv = (e / half) * F::VEC;
+        v0[u] = v1[u] = make_uint4(0, 0, 0, 0);
+        if (e < nv) {
+          v0[u] = *(const uint4*)(V + (int64_t)(r < Lk ? r : Lk - 1) * a.sp + dv);
+          v1[u] = *(const uint4*)(V + (int64_t)(r + 1 < Lk ? r + 1 : Lk - 1) * a.sp + dv);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + NT * u + tid, r = 2 * (e % half), dv = (e / half) * F::VEC;
+        if (e < nv) store_vt_pair(sVt(g), L.tp, r, dv, v0[u], v1[u]);
+      }
+    }
+    if constexpr (F::DR > D) {
+      for (int e = tid; e < (F::DR - D) * L.tp; e += NT) sVt(g)[D * L.tp + e] = from_f32<T>(0.f);
+    }
+    const float* mask = a.mask ? a.mask + (b0 + g) * a.mb : nullptr;
+    // key k = tid + NT i: the 64 lanes of a wave cover exactly one key tile
+    for (int k = tid; k < lkp; k += NT) {
+      float km, ka;
+      key_fold(mask, a.mk, k, a.Lk, scale_log2, km, ka);
+      sKs(g)[k] = km;
+      sKa(g)[k] = ka;
+      const bool all_valid = __builtin_amdgcn_ballot_w64(km == 0.f) == 0;
+      if (lane == 0) sFlag(g)[k >> 6] = all_valid ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  uint64_t fastmask[NB];
+#pragma unroll
+  for (int g = 0; g < NB; ++g)
+    fastmask[g] = g < nb ? __builtin_amdgcn_ballot_w64(lane < nkt && sFlag(g)[lane < nkt ? lane : 0] != 0) : 0;
+
+  // ---- this wave's subtiles (wave-uniform counters live in scalar registers)
+  const int64_t qend0 = a.q_count < 0 ? a.Lq : a.q_begin + a.q_count;
+  const int64_t qend = qend0 < a.Lq ? qend0 : a.Lq;
+  const int64_t qw0 = a.q_begin + (int64_t)wg.x * qb;
+  const int64_t qw1 = qw0 + qb < qend ? qw0 + qb : qend;
+  const int nsub = (int)((qw1 - qw0 + 15) / 16);
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  if (wv >= nsub) return;
+
+  // Bias of this head through a buffer resource: a lane's query row and key
+  // group as the vector offset, the subtile and key tile as scalar offsets.
+  // Rows past qend and keys past Lk read zeros or neighbouring finite values
+  // (results discarded, logits -inf), so the loads need no clamping or branch:
+  // the next tile's bias is fetched on every step, past the last one too.  One
+  // load serves all batches of the workgroup.
+  const __amdgpu_buffer_rsrc_t brs =
+      buf_rsrc(BM != BIAS_NONE ? a.bias + h * a.bh : nullptr,
+               BM != BIAS_NONE ? (uint32_t)(((a.Lq - 1) * a.bq + a.Lk) * 4) : 0u);
+  uint32_t bvo = 0, bsub = 0;
+  if constexpr (BM != BIAS_NONE) {
+    bvo = (uint32_t)(((qw0 + lr) * a.bq + 4 * lg) * 4);
+    bsub = (uint32_t)(16 * a.bq * 4);
+  }
+  auto load_bias = [&](int j, int kt, f32x4* xb) {
+    if constexpr (BM != BIAS_NONE) {
+      const uint32_t so = (uint32_t)j * bsub + (uint32_t)kt * 256u;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) xb[t] = buf_load_f32x4(brs, bvo + 64u * t, so);
+    }
+  };
+  // query row of subtile j for this lane, clamped into the workgroup's range
+  auto qrow = [&](int j) -> int64_t {
+    const int64_t q = qw0 + 16 * j + lr;
+    return q < qw1 ? q : qw1 - 1;
+  };
+  auto qbase = [&](int g) { return (const T*)a.q + (b0 + g) * a.sb + h * D; };
+  auto gbase = [&](int g) { return (const T*)a.g + (b0 + g) * a.sb + h * D; };
+
+  int j = wv, kt = 0;              // current subtile and key tile
+  int jn = wv, ktn = 0;            // next bias to fetch
+  typename F::Frag qf[NB][F::NKS], qn[NB][F::NKS];
+  float m_run[NB];
+  f32x4 oacc[NB][F::NDT], lacc[NB];
+#pragma unroll
+  for (int g = 0; g < NB; ++g) {
+    load_dfrag<T, D>(qbase(g < nb ? g : 0) + qrow(j) * a.sp, lg, true, qf[g]);
+    m_run[g] = -INFINITY;
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) oacc[g][dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    lacc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  f32x4 xb[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) xb[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  load_bias(jn, ktn, xb);
+  if (++ktn == nkt) { ktn = 0; jn += NW; }
+
+  // One key tile of subtile j for every batch in turn.  Once the last batch's
+  // logits are formed the bias registers are free and take the next tile's
+  // bias, whose load runs under that batch's softmax and context products and
+  // the next tile's first products.
+  while (j < nsub) {
+    if (kt == 0 && j + NW < nsub) {
+      // the next subtile's queries, a whole subtile ahead of their use
+#pragma unroll
+      for (int g = 0; g < NB; ++g) load_dfrag<T, D>(qbase(g < nb ? g : 0) + qrow(j + NW) * a.sp, lg, true, qn[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < NB; ++g) {
+      if (g >= nb) break;
+      f32x4 s[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        typename F::Frag kf[F::NKS];
+        load_dfrag<T, D>(sK(g) + (kt * 64 + 16 * t + lr) * F::DP, lg, true, kf);
+        s[t] = mfma_d<T, D>(kf, qf[g]);
+      }
+      float mloc = -INFINITY;
+      if ((fastmask[g] >> kt) & 1) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float x = BM != BIAS_NONE ? fmaf(s[t][i], scale_log2, xb[t][i]) : s[t][i] * scale_log2;
+            s[t][i] = x;
+            mloc = fmaxf(mloc, x);
+          }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const f32x4 km = *(const f32x4*)(sKs(g) + kt * 64 + 16 * t + 4 * lg);
+          const f32x4 ka = *(const f32x4*)(sKa(g) + kt * 64 + 16 * t + 4 * lg);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float x =
+                BM != BIAS_NONE ? fmaf(s[t][i], km[i], xb[t][i]) + ka[i] : fmaf(s[t][i], km[i], ka[i]);
+            s[t][i] = x;
+            mloc = fmaxf(mloc, x);
+          }
+        }
+      }
+      if (g == nb - 1) {
+        load_bias(jn, ktn, xb);
+        if (++ktn == nkt) { ktn = 0; jn += NW; }
+      }
+      mloc = rows_max(mloc);
+      const bool grow = mloc > m_run[g] + kLazy;
+      if (__builtin_amdgcn_ballot_w64(grow)) {
+        const float m_new = grow ? mloc : m_run[g];
+        const float alpha = exp2_hw(m_run[g] - m_new);
+        m_run[g] = m_new;
+#pragma unroll
+        for (int dt = 0; dt < F::NDT; ++dt) oacc[g][dt] = oacc[g][dt] * alpha;
+        lacc[g] = lacc[g] * alpha;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[t][i] = exp2_hw(s[t][i] - m_run[g]);
+#pragma unroll
+      for (int dt = 0; dt < F::NDT; ++dt) {
+        const int dr = 16 * dt + lr;
+        oacc[g][dt] = contract64<T, D>(sVt(g) + dr * L.tp + kt * 64, true, s, lg, oacc[g][dt]);
+      }
+      const bf16 one = lr == 0 ? (bf16)1.0f : (bf16)0.0f;
+      const bf16x8 ones = bf16x8{one, one, one, one, one, one, one, one};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const f32x4 p0 = s[2 * u], p1 = s[2 * u + 1];
+        const bf16x8 pb = bf16x8{(bf16)p0[0], (bf16)p0[1], (bf16)p0[2], (bf16)p0[3],
+                                 (bf16)p1[0], (bf16)p1[1], (bf16)p1[2], (bf16)p1[3]};
+        lacc[g] = mfma_bf16(ones, pb, lacc[g]);
+      }
+    }
+    if (kt == nkt - 1) {
+      const int64_t qi = qw0 + 16 * j + lr;
+#pragma unroll
+      for (int g = 0; g < NB; ++g) {
+        if (g >= nb) break;
+        const int64_t b = b0 + g;
+        const float l_run = __shfl(lacc[g][0], lr, 64);   // row 0 of the sum tile: lanes 0..15
+        if (qi < qw1) {
+          const float inv = 1.0f / l_run;
+          float* O = a.o ? (float*)a.o + b * a.osb + qi * a.osp + h * D : nullptr;
+          T* GO = a.go ? (T*)a.go + b * a.osb + qi * a.osp + h * D : nullptr;
+          const T* G = a.g ? gbase(g) + qi * a.sp : nullptr;
+#pragma unroll
+          for (int dt = 0; dt < F::NDT; ++dt) {
+            const int d0 = 16 * dt + 4 * lg;
+            if (d0 < D) {
+              const f32x4 o = oacc[g][dt] * inv;
+              if (O) store4<float>(O + d0, o);
+              if (GO) {
+                const bf16x4 gq = *(const bf16x4*)(G + d0);
+                f32x4 gv;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) gv[i] = to_f32(gq[i]) * o[i];
+                store4<T>(GO + d0, gv);
+              }
+            }
+          }
+          if (lg == 0 && a.st_max) {
+            const int64_t si = (b * a.stb + qi * a.stq) * a.H + h;
+            a.st_max[si] = m_run[g];
+            a.st_inv[si] = inv;
+          }
+        }
+        // next subtile
+#pragma unroll
+        for (int ks = 0; ks < F::NKS; ++ks) qf[g][ks] = qn[g][ks];
+        m_run[g] = -INFINITY;
+#pragma unroll
+        for (int dt = 0; dt < F::NDT; ++dt) oacc[g][dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        lacc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      kt = 0;
+      j += NW;
+    } else {
+      ++kt;
+    }
+  }
+}
+
 // ============================================================== backward: dQ and bias partials
 // A workgroup owns 64 queries of one head for a group of up to GM batches
 // (bias shared across the batch axis).  Key tiles run in the outer loop so
@@ -581,18 +906,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         dq[bi][dt] = contract64<T, D>(sKt + dr * F::TP, true, ds, lg, dq[bi][dt]);
       }
     }
-    // this group's bias-gradient partial for the tile, laid out like the bias
+    // this group's bias-gradient partial for the tile (layout: dbq, dbk)
     if (dbias && qok) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t key = kb0 + 16 * t + 4 * lg;
-        const int64_t off = qi * a.bq + key * a.bk;
-        if (a.bk == 1 && key + 3 < a.Lk && (off & 3) == 0) {
+        const int64_t off = qi * gr.dbq + key * gr.dbk;
+        if (gr.dbk == 1 && key + 3 < a.Lk && (off & 3) == 0) {
           *(f32x4*)(dbp + off) = dbacc[t];
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (key + i < a.Lk) dbp[off + i * a.bk] = dbacc[t][i];
+            if (key + i < a.Lk) dbp[off + i * gr.dbk] = dbacc[t][i];
         }
       }
     }
@@ -775,17 +1100,69 @@ static int bias_mode(const float* bias, int64_t bh, int64_t sr, int64_t sc, int6
     default: KERNEL(BIAS_STRIDED, __VA_ARGS__); break;  \
   }
 
+// Resident-key forward (BF16): LDS bound for it (at least two workgroups per CU)
+// and the workgroup count it aims for (four per CU).
+constexpr int64_t kResLdsMax = 80 * 1024;
+constexpr int64_t kResTargetWgs = 1024;
+
+template <int D>
+static bool launch_fwd_res(const Ctx& c, const AttnCore& a, int64_t nq, float sl2, double flops, double bytes) {
+  int bm = BIAS_NONE;
+  if (a.bias) {
+    // unit stride along keys, 16-byte rows, and 32-bit byte offsets (buffer loads)
+    const bool rows = a.bk == 1 && a.bq % 4 == 0 && a.bh % 4 == 0 && ((uintptr_t)a.bias % 16) == 0 &&
+                      a.Lk % 4 == 0 && a.Lk >= 4 && (a.Lq + 128) * a.bq * 4 < (1LL << 31);
+    if (!rows) return false;
+    bm = BIAS_ROWS;
+  }
+  const ResLayout L = res_layout<D>(a.Lk);
+  if (L.lkp / 64 > 64) return false;
+  // two batches per workgroup (eight waves) when both fit in LDS: one bias
+  // load then serves both
+  // (head dim <= 32: the registers of two batches' state fit without spilling)
+  const int nb = (D <= 32 && a.nbatch >= 2 && 2 * L.bytes <= kResLdsMax) ? 2 : 1;
+  if (nb * L.bytes > kResLdsMax) return false;
+  const int64_t ngroups = (a.nbatch + nb - 1) / nb;
+  // queries per workgroup: the most (256, 128, 64) that still gives enough workgroups
+  int qb = 64;
+  for (int cand : {256, 128}) {
+    if ((nq + cand - 1) / cand * a.H * ngroups * nb >= kResTargetWgs) { qb = cand; break; }
+  }
+  const dim3 grid((unsigned)((nq + qb - 1) / qb), (unsigned)a.H, (unsigned)ngroups);
+  static const std::string nm = kname<bf16, D>("attn_fwd_res_kernel");
+  const size_t lds = (size_t)(nb * L.bytes);
+#define EVO_RES(BMV, NBV)                                                                                    \
+  EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_res_kernel<D, BMV, NBV>), grid, dim3(256 * NBV), lds, c.stream, \
+             a, sl2, qb)
+  if constexpr (D <= 32) {
+    if (nb == 2) {
+      if (bm == BIAS_NONE) EVO_RES(BIAS_NONE, 2);
+      else EVO_RES(BIAS_ROWS, 2);
+      return true;
+    }
+  }
+  {
+    if (bm == BIAS_NONE) EVO_RES(BIAS_NONE, 1);
+    else EVO_RES(BIAS_ROWS, 1);
+  }
+#undef EVO_RES
+  return true;
+}
+
 template <typename T, int D>
 static void launch_fwd(const Ctx& c, const AttnCore& a) {
   static const std::string nm = kname<T, D>("attn_fwd_kernel");
   const int64_t nq = a.q_count < 0 ? a.Lq : a.q_count;
-  const int bm = bias_mode(a.bias, a.bh, a.bq, a.bk, a.q_begin, nq, a.Lk);
-  dim3 grid((unsigned)((nq + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
   const float sl2 = kLog2e / sqrtf((float)D);
   const double bh = (double)a.nbatch * a.H;
   const double flops = 4.0 * bh * nq * a.Lk * D;
   const double bytes = bh * ((double)nq * D * 4 + (double)a.Lk * D * 2) * sizeof(T) +
                        (a.bias ? (double)a.H * nq * a.Lk * 4.0 : 0.0) + bh * nq * 8.0;
+  if constexpr (std::is_same<T, bf16>::value) {
+    if (launch_fwd_res<D>(c, a, nq, sl2, flops, bytes)) return;
+  }
+  const int bm = bias_mode(a.bias, a.bh, a.bq, a.bk, a.q_begin, nq, a.Lk);
+  dim3 grid((unsigned)((nq + 63) / 64), (unsigned)a.H, (unsigned)a.nbatch);
 #define EVO_FWD(BMV, _) \
   EVO_LAUNCH(nm.c_str(), flops, bytes, (attn_fwd_kernel<T, D, BMV>), grid, dim3(256), 0, c.stream, a, sl2)
   EVO_BIAS_SWITCH(bm, EVO_FWD, 0)

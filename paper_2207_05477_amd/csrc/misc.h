@@ -15,14 +15,15 @@ evo_status_t ln_fwd(const Ctx& c, const TI* x, int64_t rows, int C, const float*
 template <typename TI, typename TO = TI>
 evo_status_t ln_fwd_rows(const Ctx& c, const TI* x, int64_t rows, int C, int rshift, int64_t rhi,
                          const float* g, const float* b, float eps, TO* y, float* mean, float* rstd);
-// out[h][row] = sum_c LayerNorm(x)[row][c] W[c][h] without storing the LayerNorm output
-// (the LayerNorm output is rounded to TO first, as a stored one would be).
+// out[h][row] = out_scale * sum_c LayerNorm(x)[row][c] W[c][h] without storing the
+// LayerNorm output (the LayerNorm output is rounded to TO first, as a stored one
+// would be).  tr_n > 0 (rows = tr_n^2): row a * tr_n + b goes to out[h][b][a].
 template <typename TI, typename TO = TI>
 evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
-                        float eps, const float* W, int H, float* out);
-// Channel-major FP32 input x[C][P] -> y[P][C].
+                        float eps, const float* W, int H, float* out, float out_scale = 1.f, int64_t tr_n = 0);
+// Channel-major input x[C][P] (compute type) -> y[P][C].
 template <typename T>
-evo_status_t ln_fwd_cm(const Ctx& c, const float* x, int64_t P, int C, const float* g, const float* b,
+evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
                        float eps, T* y, float* mean, float* rstd);
 // dx = base + LayerNorm_backward(dy): base = resid (may alias dx) when given, else dx itself
 // when accumulate, else 0.  dgamma/dbeta partial sums go to part[nblk][2*C].
@@ -31,9 +32,9 @@ evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rs
                     const float* dy, int64_t rows, int C, const T* resid, bool accumulate, T* dx,
                     float* part, int* nblk);
 int64_t ln_bwd_partials(int64_t rows);
-// Channel-major FP32 x[C][P], dy[P][C] -> dx[C][P].
+// Channel-major x[C][P] (compute type), dy[P][C] -> dx[C][P].
 template <typename T>
-evo_status_t ln_bwd_cm(const Ctx& c, const float* x, const float* mean, const float* rstd, const float* g,
+evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
                        const float* dy, int64_t P, int C, T* dx, float* part, int* nblk);
 int64_t ln_bwd_cm_partials(int64_t P);
 
@@ -123,8 +124,8 @@ evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n);
 // go/o/g/dgo have row pitches; dctx written with pitch ld_dctx, dgpre with ld_dg.  dgo is FP32.
 template <typename T>
 evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
-                      const float* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
-                      T* dgpre, int64_t ld_dg, float* D);
+                      const float* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx,
+                      int64_t ld_dctx, T* dgpre, int64_t ld_dg, float* D);
 
 // Triangle multiplication projections, forward: raw[p][4*ch + cz] (ap | ag | bp | bg | g, compute type)
 // -> a[c][p], b[c][p] (channel-major, masked, gated), and, when g is not null,

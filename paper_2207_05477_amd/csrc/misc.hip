@@ -165,6 +165,14 @@ evo_status_t ln_fwd(const Ctx& c, const TI* x, int64_t rows, int C, const float*
   return ln_fwd_rows<TI, T>(c, x, rows, C, -1, 0, g, b, eps, y, mean, rstd);
 }
 
+// Output index of head h, row `row` of the projection: [H][rows], or with
+// tr_n > 0 (rows = tr_n^2, row = a * tr_n + b) the transposed [H][b][a].
+EVO_DEV int64_t rowproj_dst(int h, int64_t rows, int64_t row, int64_t tr_n) {
+  if (tr_n <= 0) return (int64_t)h * rows + row;
+  const int64_t a = row / tr_n;
+  return (int64_t)h * rows + (row - a * tr_n) * tr_n + a;
+}
+
 // Fused LayerNorm + small projection (pair bias): a block owns RPB rows; the
 // row tile goes through LDS (coalesced loads), then 256 / RPB lanes share a
 // row: each reduces an interleaved share of the channels for the statistics
@@ -174,7 +182,8 @@ __global__ __launch_bounds__(256) void ln_rowproj_kernel(const TI* __restrict__ 
                                                          const float* __restrict__ g,
                                                          const float* __restrict__ b, float eps,
                                                          const float* __restrict__ W, int H,
-                                                         float* __restrict__ out) {
+                                                         float* __restrict__ out, float out_scale,
+                                                         int64_t tr_n) {
   constexpr int LPR = 256 / RPB;          // lanes per row
   extern __shared__ float sm[];           // tile [RPB][C + 4], then W [C][H]
   const int ldt = C + 4;
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(256) void ln_rowproj_kernel(const TI* __restrict__ 
   if (rr < nrow) {
 #pragma unroll
     for (int h = 0; h < 16; ++h)
-      if (h < H && h % LPR == q) out[(int64_t)h * rows + r0 + rr] = acc[h];
+      if (h < H && h % LPR == q) out[rowproj_dst(h, rows, r0 + rr, tr_n)] = acc[h] * out_scale;
   }
 }
 
@@ -239,7 +248,8 @@ __global__ __launch_bounds__(256) void ln_rowproj_vec_kernel(const TI* __restric
                                                              const float* __restrict__ g,
                                                              const float* __restrict__ b, float eps,
                                                              const float* __restrict__ W, int H,
-                                                             float* __restrict__ out) {
+                                                             float* __restrict__ out, float out_scale,
+                                                             int64_t tr_n) {
   constexpr int RPI = 256 / LPR;   // rows per iteration of the block
   // W staged once per block as [c][HM] (coalesced), the lane's slice read back as vectors
   __shared__ __attribute__((aligned(16))) float sw[8 * LPR * HM];
@@ -302,53 +312,61 @@ __global__ __launch_bounds__(256) void ln_rowproj_vec_kernel(const TI* __restric
 #pragma unroll
     for (int h = 0; h < HM; ++h) {
       acc[h] = group_sum<LPR>(acc[h]);
-      if (ok && h < H && l == h % LPR) out[(int64_t)h * rows + row] = acc[h];
+      if (ok && h < H && l == h % LPR) out[rowproj_dst(h, rows, row, tr_n)] = acc[h] * out_scale;
     }
   }
 }
 
 template <typename TI, typename T, int LPR>
 static void ln_rowproj_vec_launch(const Ctx& c, double flops, double bytes, const TI* x, int64_t rows, int C,
-                                  const float* g, const float* b, float eps, const float* W, int H, float* out) {
+                                  const float* g, const float* b, float eps, const float* W, int H, float* out,
+                                  float out_scale, int64_t tr_n) {
   constexpr int RPB = 256 / LPR * LRP_RIT;
   const dim3 grid((unsigned)((rows + RPB - 1) / RPB));
   if (H <= 4)
-    EVO_LAUNCH(EVO_KNAME("ln_rowproj_vec_kernel", TI), flops, bytes, (ln_rowproj_vec_kernel<TI, T, LPR, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+    EVO_LAUNCH(EVO_KNAME("ln_rowproj_vec_kernel", TI), flops, bytes, (ln_rowproj_vec_kernel<TI, T, LPR, 4>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out, out_scale, tr_n);
   else
-    EVO_LAUNCH(EVO_KNAME("ln_rowproj_vec_kernel", TI), flops, bytes, (ln_rowproj_vec_kernel<TI, T, LPR, 8>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out);
+    EVO_LAUNCH(EVO_KNAME("ln_rowproj_vec_kernel", TI), flops, bytes, (ln_rowproj_vec_kernel<TI, T, LPR, 8>), grid, dim3(256), 0, c.stream, x, rows, C, g, b, eps, W, H, out, out_scale, tr_n);
 }
 
 template <typename TI, typename T>
 evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const float* g, const float* b,
-                        float eps, const float* W, int H, float* out) {
+                        float eps, const float* W, int H, float* out, float out_scale, int64_t tr_n) {
   if (c.dry || rows == 0) return EVO_OK;
   if (C > 256 || H > 16) { set_error("layernorm projection: C=%d H=%d unsupported", C, H); return EVO_ESHAPE; }
+  if (tr_n < 0 || (tr_n > 0 && tr_n * tr_n != rows)) {
+    set_error("layernorm projection: transposed output needs rows = n^2 (rows=%lld, n=%lld)", (long long)rows,
+              (long long)tr_n);
+    return EVO_ESHAPE;
+  }
   const double bytes = (double)rows * C * sizeof(TI) + (double)rows * H * 4.0;
   const double flops = 2.0 * rows * C * H;
   if (C % 8 == 0 && H <= 8 && aligned16(x)) {
     switch (C / 8 <= 4 ? 4 : C / 8 <= 8 ? 8 : C / 8 <= 16 ? 16 : 32) {
-      case 4: ln_rowproj_vec_launch<TI, T, 4>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
-      case 8: ln_rowproj_vec_launch<TI, T, 8>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
-      case 16: ln_rowproj_vec_launch<TI, T, 16>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
-      default: ln_rowproj_vec_launch<TI, T, 32>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out); break;
+      case 4: ln_rowproj_vec_launch<TI, T, 4>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out, out_scale, tr_n); break;
+      case 8: ln_rowproj_vec_launch<TI, T, 8>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out, out_scale, tr_n); break;
+      case 16: ln_rowproj_vec_launch<TI, T, 16>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out, out_scale, tr_n); break;
+      default: ln_rowproj_vec_launch<TI, T, 32>(c, flops, bytes, x, rows, C, g, b, eps, W, H, out, out_scale, tr_n); break;
     }
     return check_launch("ln_rowproj");
   }
   if (C <= 128) {
     const size_t lds = ((size_t)64 * (C + 4) + (size_t)C * H) * sizeof(float);
     EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 64>),
-               dim3((unsigned)((rows + 63) / 64)), dim3(256), lds, c.stream, x, rows, C, g, b, eps, W, H, out);
+               dim3((unsigned)((rows + 63) / 64)), dim3(256), lds, c.stream, x, rows, C, g, b, eps, W, H, out,
+               out_scale, tr_n);
   } else {
     const size_t lds = ((size_t)32 * (C + 4) + (size_t)C * H) * sizeof(float);
     EVO_LAUNCH(EVO_KNAME("ln_rowproj_kernel", TI), flops, bytes, (ln_rowproj_kernel<TI, T, 32>),
-               dim3((unsigned)((rows + 31) / 32)), dim3(256), lds, c.stream, x, rows, C, g, b, eps, W, H, out);
+               dim3((unsigned)((rows + 31) / 32)), dim3(256), lds, c.stream, x, rows, C, g, b, eps, W, H, out,
+               out_scale, tr_n);
   }
   return check_launch("ln_rowproj");
 }
 
 // Channel-major forward: a block owns 64 positions; x tile [C][64] staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const float* __restrict__ x, int64_t P, int C,
+__global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const T* __restrict__ x, int64_t P, int C,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ b, float eps,
                                                         T* __restrict__ y, float* __restrict__ mean,
@@ -359,7 +377,7 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const float* __restrict_
   for (int e = tid; e < C * 64; e += 256) {
     const int cc = e >> 6, pp = e & 63;
     const int64_t p = p0 + pp;
-    tile[cc * 65 + pp] = p < P ? x[(int64_t)cc * P + p] : 0.f;
+    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
   }
   __syncthreads();
   for (int pp = wave * 16; pp < wave * 16 + 16; ++pp) {
@@ -384,7 +402,7 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const float* __restrict_
 // the per-position sums (partials combined through LDS in a fixed order), and
 // the output moves as 8-channel row vectors of y[P][C].
 template <typename T>
-__global__ __launch_bounds__(256) void ln_fwd_cm_vec_kernel(const float* __restrict__ x, int64_t P, int C,
+__global__ __launch_bounds__(256) void ln_fwd_cm_vec_kernel(const T* __restrict__ x, int64_t P, int C,
                                                             const float* __restrict__ g,
                                                             const float* __restrict__ b, float eps,
                                                             T* __restrict__ y, float* __restrict__ mean,
@@ -398,7 +416,7 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_vec_kernel(const float* __restr
   const int np = P - p0 < 64 ? (int)(P - p0) : 64;
   for (int e = tid; e < C * 64; e += 256) {
     const int cc = e >> 6, pp = e & 63;
-    tile[cc * 65 + pp] = pp < np ? x[(int64_t)cc * P + p0 + pp] : 0.f;
+    tile[cc * 65 + pp] = pp < np ? to_f32(x[(int64_t)cc * P + p0 + pp]) : 0.f;
   }
   __syncthreads();
   const int cq = C / 4, c0 = wave * cq;   // this wave's channels, position = lane
@@ -440,18 +458,18 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_vec_kernel(const float* __restr
 }
 
 template <typename T>
-evo_status_t ln_fwd_cm(const Ctx& c, const float* x, int64_t P, int C, const float* g, const float* b,
+evo_status_t ln_fwd_cm(const Ctx& c, const T* x, int64_t P, int C, const float* g, const float* b,
                        float eps, T* y, float* mean, float* rstd) {
   if (c.dry || P == 0) return EVO_OK;
   if (C % 8 == 0 && C <= 256 && aligned16(y) && aligned16(g) && aligned16(b)) {
     const size_t lds = ((size_t)C * 65 + 6 * 64) * sizeof(float);
-    EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_vec_kernel", T), 0.0, (double)P * C * (4.0 + sizeof(T)) + P * 8.0, (ln_fwd_cm_vec_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
+    EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_vec_kernel", T), 0.0, (double)P * C * 2.0 * sizeof(T) + P * 8.0, (ln_fwd_cm_vec_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
                x, P, C, g, b, eps, y, mean, rstd);
     return check_launch("ln_fwd_cm");
   }
   if (C > 512) { set_error("layernorm(cm): C=%d > 512", C); return EVO_ESHAPE; }
   size_t lds = (size_t)C * 65 * sizeof(float);
-  EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_kernel", T), 0.0, (double)P * C * (4.0 + sizeof(T)) + P * 8.0, (ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
+  EVO_LAUNCH(EVO_KNAME("ln_fwd_cm_kernel", T), 0.0, (double)P * C * 2.0 * sizeof(T) + P * 8.0, (ln_fwd_cm_kernel<T>), dim3((unsigned)((P + 63) / 64)), dim3(256), lds, c.stream,
                      x, P, C, g, b, eps, y, mean, rstd);
   return check_launch("ln_fwd_cm");
 }
@@ -662,11 +680,11 @@ evo_status_t ln_bwd(const Ctx& c, const T* x, const float* mean, const float* rs
   return check_launch("ln_bwd");
 }
 
-// Channel-major backward: x[C][P], dy[P][C] -> dx[C][P]; 64 positions per block.
+// Channel-major backward: x[C][P] (compute type), dy[P][C] -> dx[C][P]; 64 positions per block.
 int64_t ln_bwd_cm_partials(int64_t P) { return (P + 63) / 64; }
 
 template <typename T>
-__global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const float* __restrict__ x,
+__global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const T* __restrict__ x,
                                                         const float* __restrict__ mean,
                                                         const float* __restrict__ rstd,
                                                         const float* __restrict__ g,
@@ -681,7 +699,7 @@ __global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const float* __restrict_
   for (int e = tid; e < C * 64; e += 256) {
     const int cc = e >> 6, pp = e & 63;
     const int64_t p = p0 + pp;
-    tile[cc * 65 + pp] = p < P ? x[(int64_t)cc * P + p] : 0.f;
+    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
   }
   for (int e = tid; e < 8 * C; e += 256) red[e] = 0.f;
   __syncthreads();
@@ -722,13 +740,13 @@ __global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const float* __restrict_
 }
 
 template <typename T>
-evo_status_t ln_bwd_cm(const Ctx& c, const float* x, const float* mean, const float* rstd, const float* g,
+evo_status_t ln_bwd_cm(const Ctx& c, const T* x, const float* mean, const float* rstd, const float* g,
                        const float* dy, int64_t P, int C, T* dx, float* part, int* nblk) {
   *nblk = (int)ln_bwd_cm_partials(P);
   if (c.dry || P == 0) return EVO_OK;
   if (C > 256) { set_error("layernorm bwd(cm): C=%d > 256", C); return EVO_ESHAPE; }
   size_t lds = ((size_t)C * 65 + 8 * C) * sizeof(float);
-  EVO_LAUNCH(EVO_KNAME("ln_bwd_cm_kernel", T), 0.0, (double)P * C * (8.0 + sizeof(T)) + P * 8.0, (ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
+  EVO_LAUNCH(EVO_KNAME("ln_bwd_cm_kernel", T), 0.0, (double)P * C * (4.0 + 2.0 * sizeof(T)) + P * 8.0, (ln_bwd_cm_kernel<T>), dim3((unsigned)*nblk), dim3(256), lds, c.stream, x, mean,
                      rstd, g, dy, P, C, dx, part);
   return check_launch("ln_bwd_cm");
 }
@@ -1215,7 +1233,8 @@ evo_status_t convert_elems(const Ctx& c, const TI* src, TO* dst, int64_t n) {
 // ============================================================== attention gate backward
 template <typename T>
 __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int hd, const float* dgo,
-                                                       int64_t ld_dgo, const float* o, int64_t ld_o,
+                                                       int64_t ld_dgo, const float* o,
+                                                       int64_t ld_o,
                                                        const T* g, int64_t ld_g, T* dctx,
                                                        int64_t ld_dctx, T* dgp, int64_t ld_dg,
                                                        float* D) {
@@ -1242,7 +1261,8 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(int64_t rows, int H, int 
 // lanes per head, consecutive and aligned inside the wave).
 template <typename T, int LPH>
 __global__ __launch_bounds__(256) void gate_bwd_vec_kernel(int64_t rows, int H, int hd, const float* dgo,
-                                                           int64_t ld_dgo, const float* o, int64_t ld_o,
+                                                           int64_t ld_dgo, const float* o,
+                                                           int64_t ld_o,
                                                            const T* g, int64_t ld_g, T* dctx,
                                                            int64_t ld_dctx, T* dgp, int64_t ld_dg,
                                                            float* D) {
@@ -1271,8 +1291,8 @@ __global__ __launch_bounds__(256) void gate_bwd_vec_kernel(int64_t rows, int H, 
 
 template <typename T>
 evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dgo, int64_t ld_dgo,
-                      const float* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx, int64_t ld_dctx,
-                      T* dgpre, int64_t ld_dg, float* D) {
+                      const float* o, int64_t ld_o, const T* g, int64_t ld_g, T* dctx,
+                      int64_t ld_dctx, T* dgpre, int64_t ld_dg, float* D) {
   if (c.dry || rows == 0) return EVO_OK;
   const int64_t n = rows * H * hd;
   const bool vec = (hd == 8 || hd == 16 || hd == 32 || hd == 64) && ld_dgo % 8 == 0 && ld_o % 8 == 0 && ld_g % 8 == 0 &&
@@ -1281,7 +1301,7 @@ evo_status_t gate_bwd(const Ctx& c, int64_t rows, int H, int hd, const float* dg
   if (vec) {
     const int64_t n8 = n / 8;
     const dim3 grid((unsigned)((n8 + 255) / 256));
-    const double bytes = (double)n * (4.0 + 4 * sizeof(T)) + rows * H * 4.0;
+    const double bytes = (double)n * (8.0 + 3 * sizeof(T)) + rows * H * 4.0;
     switch (hd / 8) {
       case 1:
         EVO_LAUNCH(EVO_KNAME("gate_bwd_vec_kernel", T), 0.0, bytes, (gate_bwd_vec_kernel<T, 1>), grid, dim3(256), 0,
@@ -1613,12 +1633,13 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t ln_fwd_rows<T, T>(const Ctx&, const T*, int64_t, int, int, int64_t,         \
                                           const float*, const float*, float, T*, float*, float*);  \
   template evo_status_t ln_rowproj<T, T>(const Ctx&, const T*, int64_t, int, const float*,         \
-                                         const float*, float, const float*, int, float*);          \
-  template evo_status_t ln_fwd_cm<T>(const Ctx&, const float*, int64_t, int, const float*,         \
+                                         const float*, float, const float*, int, float*, float,    \
+                                         int64_t);                                                 \
+  template evo_status_t ln_fwd_cm<T>(const Ctx&, const T*, int64_t, int, const float*,             \
                                      const float*, float, T*, float*, float*);                     \
   template evo_status_t ln_bwd<T>(const Ctx&, const T*, const float*, const float*, const float*,  \
                                   const float*, int64_t, int, const T*, bool, T*, float*, int*);   \
-  template evo_status_t ln_bwd_cm<T>(const Ctx&, const float*, const float*, const float*,         \
+  template evo_status_t ln_bwd_cm<T>(const Ctx&, const T*, const float*, const float*,             \
                                      const float*, const float*, int64_t, int, T*, float*, int*);  \
   template evo_status_t colsum_partial<T>(const Ctx&, const T*, int64_t, int, int64_t, float*,     \
                                           int*);                                                   \
@@ -1629,8 +1650,9 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<const PackArgs*>);        \
   template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \
   template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
-  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t, const float*, \
-                                    int64_t, const T*, int64_t, T*, int64_t, T*, int64_t, float*); \
+  template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t,                \
+                                    const float*, int64_t, const T*, int64_t, T*,   \
+                                    int64_t, T*, int64_t, float*);                                       \
   template evo_status_t trimul_proj<T>(const Ctx&, int64_t, int, int, const T*, const float*,      \
                                        T*, T*, int64_t, float*);                                   \
   template evo_status_t trimul_proj_bwd<T>(const Ctx&, int64_t, int, int, const T*,               \
@@ -1647,7 +1669,7 @@ template evo_status_t ln_fwd<float, bf16>(const Ctx&, const float*, int64_t, int
 template evo_status_t ln_fwd_rows<float, bf16>(const Ctx&, const float*, int64_t, int, int, int64_t,
                                                const float*, const float*, float, bf16*, float*, float*);
 template evo_status_t ln_rowproj<float, bf16>(const Ctx&, const float*, int64_t, int, const float*,
-                                              const float*, float, const float*, int, float*);
+                                              const float*, float, const float*, int, float*, float, int64_t);
 template evo_status_t trimul_gate_bwd<bf16, float>(const Ctx&, int64_t, int, int, const float*, const float*,
                                                    const bf16*, int64_t, bf16*, bf16*);
 template evo_status_t convert_elems<float, bf16>(const Ctx&, const float*, bf16*, int64_t);

@@ -85,9 +85,22 @@ AttnCore core_for(const AttnShape& s, const void* qkvg, void* o, void* go, const
     a.sb = ld; a.sp = s.ni * ld; a.osb = HC; a.osp = s.ni * HC;
     a.stb = 1; a.stq = s.ni;
     a.mb = 1; a.mk = s.ni;
-    a.bh = s.no * s.no; a.bq = 1; a.bk = s.no;
+    // TRI_END: the bias b_ki of query i, key k is stored transposed (see
+    // pair_bias), so that it has unit stride along keys like the other kinds
+    a.bh = s.no * s.no; a.bq = s.no; a.bk = 1;
   }
   return a;
+}
+
+// Pair bias of the attention core, log2(e) * (LayerNorm(x) W_bias), [H][n][n]:
+// b[h][q][k] for the row and starting-node kinds; the ending-node kind's bias of
+// query i and key k is the projection of pair entry (k, i), written transposed
+// so that the core reads it at q*n + k as well.  The bias gradient comes back
+// in the projection's own row order (AttnGrad dbq, dbk).
+template <typename X, typename T>
+evo_status_t pair_bias(const Ctx& c, bool tri_end, const X* x, int64_t n, int C, const float* ln_g,
+                       const float* ln_b, float eps, const float* W, int H, float* bias) {
+  return ln_rowproj<X, T>(c, x, n * n, C, ln_g, ln_b, eps, W, H, bias, kLog2e, tri_end ? n : 0);
 }
 
 template <typename T>
@@ -150,7 +163,7 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
   po.nseg = 1;
   po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, {&pk, &po}));
-  EVO_TRY((ln_rowproj<X, T>(c, x, R * R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias)));
+  EVO_TRY((pair_bias<X, T>(c, !start, x, R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias)));
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     // chunk rows: starting node (i, j) = (c0 + ii, j) contiguous; ending node
     // (i, j) = (i, c0 + jj) with local row i*C + jj
@@ -169,14 +182,13 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
     AttnCore a;
     a.H = s.H; a.D = s.D; a.o = nullptr; a.go = go; a.bias = bias; a.bh = R * R;
     a.nbatch = C; a.Lq = a.Lk = R;
+    a.bq = R; a.bk = 1;   // both kinds (pair_bias)
     if (start) {
       a.sb = R * s.NQ; a.sp = s.NQ; a.osb = R * s.HC; a.osp = s.HC;
       a.mask = mask ? mask + c0 * R : nullptr; a.mb = R; a.mk = 1;
-      a.bq = R; a.bk = 1;
     } else {
       a.sb = s.NQ; a.sp = C * s.NQ; a.osb = s.HC; a.osp = C * s.HC;
       a.mask = mask ? mask + c0 : nullptr; a.mb = 1; a.mk = R;
-      a.bq = 1; a.bk = R;
     }
     set_qkvg<T>(a, qkvg, s);
     EVO_TRY(attn_fwd<T>(c, a));
@@ -210,6 +222,10 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     if (drop && drop->on) { set_error("attention: the chunked forward has no dropout"); return EVO_EINVAL; }
     return attn_fwd_tri_chunked<T, X>(c, ws, d, s, w, x, mask, out);
   }
+  // saved state handed to a backward only when it has an arena of its own; a
+  // forward whose intermediates live in its workspace (a checkpointed block's
+  // forward, an op called without saved state) skips the context and statistics
+  const bool keep = &sv != &ws;
   AttnSaved<T> S;
   S.carve(sv, s);
   T* wt_qkvg = ws.take_n<T>((int64_t)s.NQ * s.cin);
@@ -248,16 +264,18 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY(gemm<T>(c, g));
   }
   if (s.row) {
-    EVO_TRY((ln_rowproj<X, T>(c, pair, s.ni * s.ni, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, w.w_bias,
-                              s.H, S.bias)));
+    EVO_TRY((pair_bias<X, T>(c, false, pair, s.ni, (int)s.cpair, w.ln_z_g, w.ln_z_b, d.ln_eps, w.w_bias, s.H,
+                             S.bias)));
   } else if (s.tri) {
-    EVO_TRY((ln_rowproj<X, T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, S.bias)));
+    EVO_TRY((pair_bias<X, T>(c, s.kind == EVO_ATTN_TRI_END, x, s.ni, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps,
+                             w.w_bias, s.H, S.bias)));
   }
   if (s.global) {
     EVO_TRY(gattn_fwd<T>(c, ga_scratch, s.no, s.ni, s.H, s.D, S.qkvg, mask, d.global_eps, S.qbar, S.minv,
                          S.gctx, S.st_max, S.st_inv, S.go));
   } else {
-    AttnCore a = core_for(s, S.qkvg, S.o, S.go, S.bias, mask, S.st_max, S.st_inv);
+    AttnCore a = core_for(s, S.qkvg, keep ? S.o : nullptr, S.go, S.bias, mask, keep ? S.st_max : nullptr,
+                          keep ? S.st_inv : nullptr);
     set_qkvg<T>(a, S.qkvg, s);
     EVO_TRY(attn_fwd<T>(c, a));
   }
@@ -361,6 +379,10 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     gr.dq = dqkvg; gr.dk = dqkvg + s.HC; gr.dv = dqkvg + 2 * s.HC;
     gr.dsb = a.sb; gr.dsp = a.sp;
     gr.dbias_part = dbias_part;
+    // partials in the projection's row order: (q, k) -> pair entry (k, q) for the ending node
+    const bool tend = s.kind == EVO_ATTN_TRI_END;
+    gr.dbq = tend ? 1 : a.bq;
+    gr.dbk = tend ? a.Lq : a.bk;
     EVO_TRY(attn_bwd<T>(c, a, gr));
     if (dbias_part) {
       const int64_t nb = s.H * a.Lq * a.Lk;

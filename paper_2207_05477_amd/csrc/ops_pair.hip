@@ -273,9 +273,9 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
 template <typename T>
 struct TriSaved {
   // raw: projection output in the compute type (its last cz columns hold the
-  // output gate after the sigmoid); x (contraction output) feeds only the
-  // output LayerNorm: FP32 whatever the compute type.
-  T* y; float* mean; float* rstd; T* raw; T* a; T* b; float* x; T* xn; float* mean2;
+  // output gate after the sigmoid); x (contraction output, channel-major) feeds
+  // only the output LayerNorm, in the compute type like its operands.
+  T* y; float* mean; float* rstd; T* raw; T* a; T* b; T* x; T* xn; float* mean2;
   float* rstd2;
   void carve(Arena& ar, const evo_trimul_desc_t& d) {
     const int64_t P = d.n_res * d.n_res, ch = d.c_hidden, cz = d.c_z;
@@ -285,7 +285,7 @@ struct TriSaved {
     raw = ar.take_n<T>(P * (4 * ch + cz));
     a = ar.take_n<T>(P * ch);
     b = ar.take_n<T>(P * ch);
-    x = ar.take_n<float>(P * ch);
+    x = ar.take_n<T>(P * ch);
     xn = ar.take_n<T>(P * ch);
     mean2 = ar.take_n<float>(P);
     rstd2 = ar.take_n<float>(P);
@@ -311,7 +311,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
   float* mean = ws.take_n<float>(CR);
   float* rstd = ws.take_n<float>(CR);
   T* raw = ws.take_n<T>(CR * NP);
-  float* x = ws.take_n<float>(CR * ch);
+  T* x = ws.take_n<T>(CR * ch);
   T* xn = ws.take_n<T>(CR * ch);
   if (c.dry) return EVO_OK;
   PackArgs pp;
@@ -355,7 +355,7 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
       gx.B = op_colmajor(b, R);
     }
     gx.A.batch = P; gx.B.batch = P;
-    gx.epi = epi_rowmajor(x, R, true);
+    gx.epi = epi_rowmajor(x, R, false);
     gx.epi.batch = CR;
     EVO_TRY(gemm<T>(c, gx));
     EVO_TRY(ln_fwd_cm<T>(c, x, CR, (int)ch, w.ln_out_g, w.ln_out_b, d.ln_eps, xn, mean2, rstd2));
@@ -427,7 +427,7 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
       g.B = op_colmajor(S.b, R);
     }
     g.A.batch = P; g.B.batch = P;
-    g.epi = epi_rowmajor(S.x, R, true);
+    g.epi = epi_rowmajor(S.x, R, false);
     g.epi.batch = P;
     EVO_TRY(gemm<T>(c, g));
   }
