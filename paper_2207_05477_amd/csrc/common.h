@@ -64,23 +64,46 @@ EVO_DEV void store4(T* dst, f32x4 v) {
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // ---------------------------------------------------------------- wave reductions (wave64)
-EVO_DEV float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Lane exchanges on the VALU, no LDS round trips: DPP within 16-lane rows
+// (quad permutations for partners l ^ 1 and l ^ 2, half-row mirror l ^ 7 and
+// row mirror l ^ 15 of an 8- / 16-lane group, each landing in the other half of
+// the group once the halves hold their own totals), and the gfx950 row swaps
+// across rows (v_permlane16_swap: rows 0 <-> 1 and 2 <-> 3; v_permlane32_swap:
+// the two halves of the wave).  Each step combines a lane's value with its
+// partner's, a op b on one side and b op a on the other, so that with a
+// commutative op every lane of a group ends with the same bits.
+namespace dppc {
+constexpr int XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int HALF_MIRROR = 0x141;
+constexpr int MIRROR = 0x140;
+}  // namespace dppc
+template <int CTRL> EVO_DEV float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// op over aligned groups of G lanes (G a power of two <= 64); every lane of a
+// group gets the result.
+template <int G, typename Op> EVO_DEV float group_reduce(float v, Op op) {
+  static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group size");
+  if constexpr (G >= 2) v = op(v, dpp_f32<dppc::XOR1>(v));
+  if constexpr (G >= 4) v = op(v, dpp_f32<dppc::XOR2>(v));
+  if constexpr (G >= 8) v = op(v, dpp_f32<dppc::HALF_MIRROR>(v));
+  if constexpr (G >= 16) v = op(v, dpp_f32<dppc::MIRROR>(v));
+  if constexpr (G >= 32) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = op(__uint_as_float(p[0]), __uint_as_float(p[1]));
+  }
+  if constexpr (G >= 64) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = op(__uint_as_float(p[0]), __uint_as_float(p[1]));
+  }
   return v;
 }
-// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of a
-// group gets the group's sum.
-template <int G> EVO_DEV float group_sum(float v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-EVO_DEV float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
+struct AddOp { EVO_DEV float operator()(float a, float b) const { return a + b; } };
+struct MaxOp { EVO_DEV float operator()(float a, float b) const { return fmaxf(a, b); } };
+template <int G> EVO_DEV float group_sum(float v) { return group_reduce<G>(v, AddOp()); }
+EVO_DEV float wave_sum(float v) { return group_reduce<64>(v, AddOp()); }
+EVO_DEV float wave_max(float v) { return group_reduce<64>(v, MaxOp()); }
 
 // ---------------------------------------------------------------- XCD-aware order
 // Workgroups are dealt round-robin over the 8 XCDs (each with its own L2) in

@@ -169,8 +169,9 @@ evo_status_t ln_fwd(const Ctx& c, const TI* x, int64_t rows, int C, const float*
 // tr_n > 0 (rows = tr_n^2, row = a * tr_n + b) the transposed [H][b][a].
 EVO_DEV int64_t rowproj_dst(int h, int64_t rows, int64_t row, int64_t tr_n) {
   if (tr_n <= 0) return (int64_t)h * rows + row;
-  const int64_t a = row / tr_n;
-  return (int64_t)h * rows + (row - a * tr_n) * tr_n + a;
+  // rows = tr_n^2 < 2^31 (checked by the launcher): 32-bit division
+  const uint32_t r = (uint32_t)row, n = (uint32_t)tr_n, a = r / n;
+  return (int64_t)h * rows + (int64_t)(r - a * n) * tr_n + a;
 }
 
 // Fused LayerNorm + small projection (pair bias): a block owns RPB rows; the
@@ -334,7 +335,7 @@ evo_status_t ln_rowproj(const Ctx& c, const TI* x, int64_t rows, int C, const fl
                         float eps, const float* W, int H, float* out, float out_scale, int64_t tr_n) {
   if (c.dry || rows == 0) return EVO_OK;
   if (C > 256 || H > 16) { set_error("layernorm projection: C=%d H=%d unsupported", C, H); return EVO_ESHAPE; }
-  if (tr_n < 0 || (tr_n > 0 && tr_n * tr_n != rows)) {
+  if (tr_n < 0 || (tr_n > 0 && (tr_n * tr_n != rows || rows >= (1LL << 31)))) {
     set_error("layernorm projection: transposed output needs rows = n^2 (rows=%lld, n=%lld)", (long long)rows,
               (long long)tr_n);
     return EVO_ESHAPE;
