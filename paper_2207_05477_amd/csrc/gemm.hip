@@ -828,74 +828,146 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
     mrow[i] = m0 + wm * WM + i * 16 + lr;
     moff[i] = PlainLoader<T, BM, KCA>::a32(mrow[i], mlo, mhi, e.m_shift);
   }
-  // rows outer, column blocks inner: the two halves of a row's 128-byte line
-  // (FP32 outputs, residual and gate inputs) are touched back to back
   int ncol[TN], noff[TN];
-  f32x4 bias4[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     ncol[j] = n0 + wn * WN + j * 16 + lg * 4;
     noff[j] = PlainLoader<T, BM, KCA>::a32(ncol[j], 1, nhi, e.n_shift);
-    bias4[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (e.bias && ncol[j] < N) bias4[j] = *(const f32x4*)(e.bias + ncol[j]);
   }
+  // The epilogue runs one feature at a time over all of the lane's outputs,
+  // each behind one uniform test, in the order of GemmEpilogue; the outputs
+  // stay in the accumulators.  (Out-of-range elements load zeros through the
+  // buffer resources and are dropped at the store.)
+  auto inb = [&](int i, int j) { return ncol[j] < N && mrow[i] < M; };
+  if (alpha != 1.0f) {
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) acc[j][i] = acc[j][i] * alpha;
+  }
+  if (e.bias) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      const int n = ncol[j];
-      const bool colok = n < N;
-      const int no = noff[j];
-      const f32x4 bj = bias4[j];
-      const int m = mrow[i];
-      const bool ok = colok && m < M;
-      f32x4 v = acc[j][i] * alpha + bj;
-      if (e.act == ACT_RELU) {
+      const f32x4 bj = ncol[j] < N ? *(const f32x4*)(e.bias + ncol[j]) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.0f);
-      } else if (e.act == ACT_SIGMOID) {
+      for (int i = 0; i < TM; ++i) acc[j][i] = acc[j][i] + bj;
+    }
+  }
+  if (e.scale) {
+    if (e.sn_shift >= 2) {   // n is a multiple of 4: the lane's 4 columns share one entry
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (n + r >= e.act_n0) v[r] = sigmoidf_(v[r]);
+      for (int i = 0; i < TM; ++i) {
+        const int64_t sr = scale_row(e, mrow[i]) * e.sm_ld;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[j][i] *= inb(i, j) ? e.scale[sr + (ncol[j] >> e.sn_shift) * e.sn_ld] : 0.f;
       }
-      const int mo = moff[i];
-      if (e.scale) {
-        const int64_t sr = scale_row(e, m) * e.sm_ld;
-        if (e.sn_shift >= 2) {   // n is a multiple of 4: the lane's 4 columns share one entry
-          v *= ok ? e.scale[sr + (n >> e.sn_shift) * e.sn_ld] : 0.f;
-        } else {
+    } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] *= ok ? e.scale[sr + ((n + r) >> e.sn_shift) * e.sn_ld] : 0.f;
-        }
-      }
-      const uint32_t eo = (uint32_t)(e.r_m < 0 ? mo + no : m * pi.ldr + n);   // aux element offset
-      if (e.relu_ref) {
-        const f32x4 q = load4<T>(rrl, ok ? eo * (uint32_t)sizeof(T) : kOOB, false);
+      for (int i = 0; i < TM; ++i) {
+        const int64_t sr = scale_row(e, mrow[i]) * e.sm_ld;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = q[r] > 0.0f ? v[r] : 0.0f;
-      }
-      if (e.gate)
-        v *= load4<T>(rg, ok ? (uint32_t)(e.g_m < 0 ? mo + no : m * pi.ldg + n) * (uint32_t)gsz : kOOB,
-                      e.gate_f32 != 0);
-      if (e.resid) v += load4<T>(rr, ok ? eo * (uint32_t)rsz : kOOB, e.resid_f32 != 0);
-      const uint32_t oo = ok ? (uint32_t)(mo + no) * (uint32_t)osz : kOOB;
-      if (of32) {
-        if (e.accumulate) v += load4<T>(ro, oo, true);
-        const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
-        __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
-      } else if constexpr (sizeof(T) == 2) {
-        union { i32x2 q; T e4[4]; } u;
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) u.e4[r] = from_f32<T>(v[r]);
-        if (stage)
-          *(i32x2*)(sto + (wm * WM + i * 16 + lr) * TPO + wn * WN + j * 16 + lg * 4) = u.q;
-        else
-          __builtin_amdgcn_raw_buffer_store_b64(u.q, ro, oo, 0, 0);
-      } else {
-        const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
-        __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
+          for (int r = 0; r < 4; ++r)
+            acc[j][i][r] *= inb(i, j) ? e.scale[sr + ((ncol[j] + r) >> e.sn_shift) * e.sn_ld] : 0.f;
       }
     }
+  }
+  if (e.act == ACT_RELU) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[j][i][r] = fmaxf(acc[j][i][r], 0.0f);
+  } else if (e.act == ACT_SIGMOID) {
+    // columns from act_n0 on (a lane's four columns share the test when act_n0 is a multiple of 4)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      if (ncol[j] >= e.act_n0 && (e.act_n0 & 3) == 0) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[j][i][r] = sigmoidf_(acc[j][i][r]);
+      } else if (ncol[j] + 3 >= e.act_n0) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (ncol[j] + r >= e.act_n0) acc[j][i][r] = sigmoidf_(acc[j][i][r]);
+      }
+    }
+  }
+  // auxiliary element offsets: the output's addressing (m-stride < 0) or plain rows
+  auto aux_off = [&](int i, int j, int64_t sm, int ld) -> uint32_t {
+    return (uint32_t)(sm < 0 ? moff[i] + noff[j] : mrow[i] * ld + ncol[j]);
+  };
+  if (e.relu_ref) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const f32x4 q = load4<T>(rrl, inb(i, j) ? aux_off(i, j, e.r_m, pi.ldr) * (uint32_t)sizeof(T) : kOOB, false);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[j][i][r] = q[r] > 0.0f ? acc[j][i][r] : 0.0f;
+      }
+  }
+  // (one loop per element type of the auxiliary input, so that the loads carry no test)
+#define EVO_AUX_PASS(COND, RS, SM, LD, ESZ, F32, OP)                                                   \
+  if (COND) {                                                                                       \
+    _Pragma("unroll") for (int j = 0; j < TN; ++j)                                                  \
+    _Pragma("unroll") for (int i = 0; i < TM; ++i)                                                  \
+      acc[j][i] OP load4<T>(RS, inb(i, j) ? aux_off(i, j, SM, LD) * (uint32_t)(ESZ) : kOOB, F32);    \
+  }
+  if (e.gate) {
+    EVO_AUX_PASS(e.gate_f32 != 0, rg, e.g_m, pi.ldg, 4, true, *=)
+    else EVO_AUX_PASS(true, rg, e.g_m, pi.ldg, sizeof(T), false, *=)
+  }
+  if (e.resid) {
+    EVO_AUX_PASS(e.resid_f32 != 0, rr, e.r_m, pi.ldr, 4, true, +=)
+    else EVO_AUX_PASS(true, rr, e.r_m, pi.ldr, sizeof(T), false, +=)
+  }
+#undef EVO_AUX_PASS
+  // stores: rows outer, column blocks inner, so that the two halves of a row's
+  // 128-byte line (FP32 outputs) are written back to back
+  if (of32) {
+    const bool accu = e.accumulate != 0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const uint32_t oo = inb(i, j) ? (uint32_t)(moff[i] + noff[j]) * 4u : kOOB;
+        f32x4 v = acc[j][i];
+        if (accu) v += load4<T>(ro, oo, true);
+        const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
+      }
+  } else if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        union { i32x2 q; T e4[4]; } u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u.e4[r] = from_f32<T>(acc[j][i][r]);
+        if (stage) {
+          *(i32x2*)(sto + (wm * WM + i * 16 + lr) * TPO + wn * WN + j * 16 + lg * 4) = u.q;
+        } else {
+          const uint32_t oo = inb(i, j) ? (uint32_t)(moff[i] + noff[j]) * 2u : kOOB;
+          __builtin_amdgcn_raw_buffer_store_b64(u.q, ro, oo, 0, 0);
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const uint32_t oo = inb(i, j) ? (uint32_t)(moff[i] + noff[j]) * (uint32_t)osz : kOOB;
+        const f32x4 v = acc[j][i];
+        const i32x4 w = i32x4{__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]), __float_as_int(v[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(w, ro, oo, 0, 0);
+      }
   }
   if constexpr (sizeof(T) == 2) {
     if (stage) {
