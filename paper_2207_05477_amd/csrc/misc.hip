@@ -399,6 +399,48 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_kernel(const T* __restrict__ x,
   }
 }
 
+// Channel-major tile of 64 positions: x[c][p0 .. p0 + 63] -> tile[c * 65 + pp] (FP32)
+// and back, moving 16-byte vectors of 8 positions when the rows allow it
+// (P % 8 == 0, x 16-byte aligned) and single elements otherwise; positions
+// from P on read as zeros and are not written.
+template <typename T>
+EVO_DEV void cm_tile_load(const T* __restrict__ x, int64_t P, int C, int64_t p0, float* tile, int tid) {
+  const bool vec = (P & 7) == 0 && (((uintptr_t)x) & 15) == 0;
+  for (int e = tid; e < C * 8; e += 256) {
+    const int cc = e >> 3, pv = (e & 7) * 8;
+    const int64_t p = p0 + pv;
+    const T* src = x + (int64_t)cc * P + p;
+    float v[8];
+    if (vec && p + 8 <= P) {
+      ld8(src, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = p + i < P ? to_f32(src[i]) : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tile[cc * 65 + pv + i] = v[i];
+  }
+}
+template <typename T>
+EVO_DEV void cm_tile_store(T* __restrict__ x, int64_t P, int C, int64_t p0, const float* tile, int tid) {
+  const bool vec = (P & 7) == 0 && (((uintptr_t)x) & 15) == 0;
+  for (int e = tid; e < C * 8; e += 256) {
+    const int cc = e >> 3, pv = (e & 7) * 8;
+    const int64_t p = p0 + pv;
+    T* dst = x + (int64_t)cc * P + p;
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = tile[cc * 65 + pv + i];
+    if (vec && p + 8 <= P) {
+      st8(dst, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (p + i < P) dst[i] = from_f32<T>(v[i]);
+    }
+  }
+}
+
 // Vectorised form (C % 8 == 0, C <= 256): the 4 waves split the channels for
 // the per-position sums (partials combined through LDS in a fixed order), and
 // the output moves as 8-channel row vectors of y[P][C].
@@ -415,10 +457,7 @@ __global__ __launch_bounds__(256) void ln_fwd_cm_vec_kernel(const T* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * 64;
   const int np = P - p0 < 64 ? (int)(P - p0) : 64;
-  for (int e = tid; e < C * 64; e += 256) {
-    const int cc = e >> 6, pp = e & 63;
-    tile[cc * 65 + pp] = pp < np ? to_f32(x[(int64_t)cc * P + p0 + pp]) : 0.f;
-  }
+  cm_tile_load(x, P, C, p0, tile, tid);
   __syncthreads();
   const int cq = C / 4, c0 = wave * cq;   // this wave's channels, position = lane
   float s = 0.f;
@@ -697,41 +736,45 @@ __global__ __launch_bounds__(256) void ln_bwd_cm_kernel(const T* __restrict__ x,
   float* red = sm + C * 65;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * 64;
-  for (int e = tid; e < C * 64; e += 256) {
-    const int cc = e >> 6, pp = e & 63;
-    const int64_t p = p0 + pp;
-    tile[cc * 65 + pp] = p < P ? to_f32(x[(int64_t)cc * P + p]) : 0.f;
-  }
-  for (int e = tid; e < 8 * C; e += 256) red[e] = 0.f;
+  cm_tile_load(x, P, C, p0, tile, tid);
   __syncthreads();
-  float* myred = red + wave * 2 * C;
+  // channels lane, lane + 64, ... (C <= 256): the parameter-gradient sums of
+  // this wave's 16 positions stay in registers
+  float rgs[4] = {0.f, 0.f, 0.f, 0.f}, rbs[4] = {0.f, 0.f, 0.f, 0.f}, gl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gl[k] = lane + 64 * k < C ? g[lane + 64 * k] : 0.f;
   for (int pp = wave * 16; pp < wave * 16 + 16; ++pp) {
     const int64_t p = p0 + pp;
     if (p >= P) break;
     const float mu = mean[p], rs = rstd[p];
+    float d[4], xh[4];
     float s1 = 0.f, s2 = 0.f;
-    for (int cc = lane; cc < C; cc += 64) {
-      const float d = dy[p * C + cc];
-      const float xh = (tile[cc * 65 + pp] - mu) * rs;
-      const float gd = d * g[cc];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int cc = lane + 64 * k;
+      d[k] = cc < C ? dy[p * C + cc] : 0.f;
+      xh[k] = cc < C ? (tile[cc * 65 + pp] - mu) * rs : 0.f;
+      const float gd = d[k] * gl[k];
       s1 += gd;
-      s2 += gd * xh;
-      myred[cc] += d * xh;
-      myred[C + cc] += d;
+      s2 += gd * xh[k];
+      rgs[k] += d[k] * xh[k];
+      rbs[k] += d[k];
     }
     const float a = wave_sum(s1) / (float)C, bb = wave_sum(s2) / (float)C;
-    for (int cc = lane; cc < C; cc += 64) {
-      const float d = dy[p * C + cc];
-      const float xh = (tile[cc * 65 + pp] - mu) * rs;
-      tile[cc * 65 + pp] = rs * (d * g[cc] - a - xh * bb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int cc = lane + 64 * k;
+      if (cc < C) tile[cc * 65 + pp] = rs * (d[k] * gl[k] - a - xh[k] * bb);
     }
   }
-  __syncthreads();
-  for (int e = tid; e < C * 64; e += 256) {
-    const int cc = e >> 6, pp = e & 63;
-    const int64_t p = p0 + pp;
-    if (p < P) dx[(int64_t)cc * P + p] = from_f32<T>(tile[cc * 65 + pp]);
+  float* myred = red + wave * 2 * C;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int cc = lane + 64 * k;
+    if (cc < C) { myred[cc] = rgs[k]; myred[C + cc] = rbs[k]; }
   }
+  __syncthreads();
+  cm_tile_store(dx, P, C, p0, tile, tid);
   for (int cc = tid; cc < C; cc += 256) {
     float sg = 0.f, sb = 0.f;
     for (int w = 0; w < 4; ++w) { sg += red[w * 2 * C + cc]; sb += red[w * 2 * C + C + cc]; }
