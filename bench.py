@@ -85,25 +85,36 @@ def make_workload(cfg, dtype, device):
     w["dflat"] = flat.zeros_like()
     w["mo"], w["zo"] = torch.empty_like(w["m"]), torch.empty_like(w["z"])
     w["dm"], w["dz"] = torch.empty_like(w["m"]), torch.empty_like(w["z"])
+    w["saved"] = torch.empty(B.evoformer_block_saved_bytes(cfg, dtype), dtype=torch.uint8, device=device)
     return inp, flat, w
 
 
-def step(cfg, dtype, flat, w):
+# One step = the block forward + the block backward on one batch.  Default: the
+# forward keeps the block's intermediates (a few GB at this shape) and the
+# backward consumes them; checkpoint=True: the forward keeps nothing and the
+# backward recomputes it (the form a deep stack uses; one more forward).
+def fwd_only(cfg, dtype, flat, w, checkpoint=False):
     from paper_2207_05477_amd import binding as B
-    B.evoformer_block_fwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["mo"], w["zo"], dtype=dtype)
-    B.evoformer_block_bwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["dmo"], w["dzo"], w["dflat"],
-                          w["dm"], w["dz"], dtype=dtype)
+    if checkpoint:
+        B.evoformer_block_fwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["mo"], w["zo"], dtype=dtype)
+    else:
+        B.evoformer_block_fwd_save(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["mo"], w["zo"], w["saved"],
+                                   dtype=dtype)
 
 
-def fwd_only(cfg, dtype, flat, w):
+def bwd_only(cfg, dtype, flat, w, checkpoint=False):
     from paper_2207_05477_amd import binding as B
-    B.evoformer_block_fwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["mo"], w["zo"], dtype=dtype)
+    if checkpoint:
+        B.evoformer_block_bwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["dmo"], w["dzo"], w["dflat"],
+                              w["dm"], w["dz"], dtype=dtype)
+    else:
+        B.evoformer_block_bwd_saved(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["saved"], w["dmo"], w["dzo"],
+                                    w["dflat"], w["dm"], w["dz"], dtype=dtype)
 
 
-def bwd_only(cfg, dtype, flat, w):
-    from paper_2207_05477_amd import binding as B
-    B.evoformer_block_bwd(cfg, flat, w["m"], w["z"], w["mm"], w["pm"], w["dmo"], w["dzo"], w["dflat"],
-                          w["dm"], w["dz"], dtype=dtype)
+def step(cfg, dtype, flat, w, checkpoint=False):
+    fwd_only(cfg, dtype, flat, w, checkpoint)
+    bwd_only(cfg, dtype, flat, w, checkpoint)
 
 
 def timed(fn, steps, warmup):
@@ -281,6 +292,11 @@ def measure_block(cfg, dtype, dev, steps, warmup, profile_steps_n, breakdown=Fal
     bms, bmed = timed(lambda: bwd_only(cfg, dtype, flat, w), steps, 2)
     print(f"{dtype} step {ms:.3f} ms (median {med:.3f}); forward {fms:.3f}, backward {bms:.3f}", file=sys.stderr,
           flush=True)
+    cms, cmed = timed(lambda: step(cfg, dtype, flat, w, True), steps, 2)
+    cfms, _ = timed(lambda: fwd_only(cfg, dtype, flat, w, True), steps, 2)
+    cbms, _ = timed(lambda: bwd_only(cfg, dtype, flat, w, True), steps, 2)
+    print(f"{dtype} checkpointed step {cms:.3f} ms (median {cmed:.3f}); forward {cfms:.3f}, backward "
+          f"{cbms:.3f} (recomputes the forward)", file=sys.stderr, flush=True)
     stats = profile_steps(cfg, dtype, flat, w, profile_steps_n)
     roof = roofline_of(stats, dtype)
     roof["launches_per_step"] = stats[0]["launches"] / profile_steps_n
@@ -292,6 +308,9 @@ def measure_block(cfg, dtype, dev, steps, warmup, profile_steps_n, breakdown=Fal
     res = {"ms_per_step": ms, "ms_per_step_median": med, "tflops": flops_step / (ms * 1e-3) / 1e12,
            "fwd_ms": fms, "fwd_ms_median": fmed, "bwd_ms": bms, "bwd_ms_median": bmed,
            "roofline": roof, "roofline_by_class": classes,
+           "saved_state_gib": w["saved"].numel() / 2**30,
+           "checkpointed": {"ms_per_step": cms, "ms_per_step_median": cmed, "fwd_ms": cfms, "bwd_ms": cbms,
+                            "tflops": flops_step / (cms * 1e-3) / 1e12},
            "top_kernels": [{k: s_[k] for k in ("name", "launches", "total_ms")} for s_ in stats[:8]]}
     del w, flat, inp
     torch.cuda.empty_cache()
@@ -455,12 +474,13 @@ def main():
         "config": {"workload": "evoformer_block_fwd_bwd_initial_crop", "n_seq": cfg.n_seq,
                    "n_res": cfg.n_res, "c_m": cfg.c_m, "c_z": cfg.c_z, "msa_heads": "8x32",
                    "tri_heads": "4x32", "tri_mul_hidden": cfg.tri_mul_hidden,
-                   "opm_hidden": cfg.opm_hidden, "blocks": 1, "algorithmic_gflop_per_step": flops_step / 1e9},
+                   "opm_hidden": cfg.opm_hidden, "blocks": 1, "block_checkpoint": False,
+                   "algorithmic_gflop_per_step": flops_step / 1e9},
         "roofline": f32["roofline"] if f32 else None,
     }
     if f32:
         out.update({k: f32[k] for k in ("ms_per_step_median", "fwd_ms", "fwd_ms_median", "bwd_ms", "bwd_ms_median",
-                                        "roofline_by_class", "top_kernels")})
+                                        "saved_state_gib", "checkpointed", "roofline_by_class", "top_kernels")})
     out["bf16"] = bf16
     out["other_configs"] = others or None
     if not args.no_cpu_baseline and args.only != "bf16":

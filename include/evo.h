@@ -288,6 +288,36 @@ evo_status_t evoformer_block_bwd(const evo_block_desc_t* desc, const evo_block_w
                                  void* dm, void* dz, const evo_block_w_t* d_w,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ block without its checkpoint
+ * The same block for callers with memory to spare (paper, Section "Recompute":
+ * recomputation trades one more forward per block for the memory of the
+ * block's intermediates; at N_seq=128, N_res=256 they are a few GB of the
+ * 288 GB of HBM).  evoformer_block_fwd_save computes the forward of
+ * evoformer_block_fwd and keeps the block's state in `saved`: the dropout
+ * multipliers, the packed parameters, the activations between sub-operations
+ * and every sub-operation's saved tensors (evoformer_block_saved_bytes(desc)
+ * bytes, 16-byte aligned, owned by the caller; 0 for an invalid or chunked
+ * desc).  evoformer_block_bwd_saved is evoformer_block_bwd without the
+ * recomputation: it reads `saved` as the forward left it (the same desc, w,
+ * m, z and masks; `saved` unchanged in between) and gives bit-identical
+ * results.  Here m_out / z_out must not alias m / z (the backward reads them).
+ * Workspaces: evoformer_block_save_workspace_bytes(desc, EVO_PHASE_FWD) for the
+ * forward, (desc, EVO_PHASE_BWD) for the backward.  chunk must be 0.
+ */
+size_t evoformer_block_saved_bytes(const evo_block_desc_t* desc);
+size_t evoformer_block_save_workspace_bytes(const evo_block_desc_t* desc, int32_t phase);
+evo_status_t evoformer_block_fwd_save(const evo_block_desc_t* desc, const evo_block_w_t* w,
+                                      const void* m, const void* z, const float* msa_mask,
+                                      const float* pair_mask, void* m_out, void* z_out,
+                                      void* saved, size_t saved_bytes,
+                                      void* ws, size_t ws_bytes, void* stream);
+evo_status_t evoformer_block_bwd_saved(const evo_block_desc_t* desc, const evo_block_w_t* w,
+                                       const void* m, const void* z, const float* msa_mask,
+                                       const float* pair_mask, const void* saved,
+                                       const void* dm_out, const void* dz_out, void* dm, void* dz,
+                                       const evo_block_w_t* d_w, void* ws, size_t ws_bytes,
+                                       void* stream);
+
 /* ------------------------------------------------------------------ template pair stack block
  * One block of AlphaFold2's template pair stack, which the paper's initial-training
  * forward includes (its template embedding): the pair-stack operators on one

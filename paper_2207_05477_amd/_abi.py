@@ -131,6 +131,12 @@ _SIGS = {
                              _P], c_int32),
     "evoformer_block_bwd": ([POINTER(BlockDesc), POINTER(BlockW), _P, _P, _P, _P, _P, _P, _P, _P,
                              POINTER(BlockW), _P, c_size_t, _P], c_int32),
+    "evoformer_block_saved_bytes": ([POINTER(BlockDesc)], c_size_t),
+    "evoformer_block_save_workspace_bytes": ([POINTER(BlockDesc), c_int32], c_size_t),
+    "evoformer_block_fwd_save": ([POINTER(BlockDesc), POINTER(BlockW), _P, _P, _P, _P, _P, _P, _P, c_size_t,
+                                  _P, c_size_t, _P], c_int32),
+    "evoformer_block_bwd_saved": ([POINTER(BlockDesc), POINTER(BlockW), _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                   POINTER(BlockW), _P, c_size_t, _P], c_int32),
     "template_pair_block_workspace_bytes": ([POINTER(TemplateDesc), c_int32], c_size_t),
     "template_pair_block_fwd": ([POINTER(TemplateDesc), POINTER(TemplateW), _P, _P, _P, _P, c_size_t, _P],
                                 c_int32),

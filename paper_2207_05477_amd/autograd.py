@@ -4,7 +4,9 @@ A block is the activation-checkpoint boundary (paper, Section "Recompute"):
 its forward keeps only the block input (m, z); its backward calls
 evoformer_block_bwd, which recomputes the block forward on the GPU before
 running the backward kernels.  A stack of blocks therefore stores one (m, z)
-pair per block.
+pair per block.  With checkpoint=False a block keeps its whole state instead
+(evoformer_block_fwd_save / evoformer_block_bwd_saved): no recomputation, at
+the memory cost of the block's intermediates.
 """
 from __future__ import annotations
 
@@ -15,10 +17,16 @@ from . import binding
 
 class EvoformerBlockFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, m, z, flat_buffer, cfg, flat, msa_mask, pair_mask, dtype, dropout=None):
+    def forward(ctx, m, z, flat_buffer, cfg, flat, msa_mask, pair_mask, dtype, dropout=None, checkpoint=True):
         assert flat_buffer is flat.buffer
-        m_out, z_out = binding.evoformer_block_fwd(cfg, flat, m.contiguous(), z.contiguous(), msa_mask,
-                                                   pair_mask, dtype=dtype, dropout=dropout)
+        m, z = m.contiguous(), z.contiguous()
+        if checkpoint:
+            m_out, z_out = binding.evoformer_block_fwd(cfg, flat, m, z, msa_mask, pair_mask, dtype=dtype,
+                                                       dropout=dropout)
+            ctx.state = None
+        else:
+            m_out, z_out, ctx.state = binding.evoformer_block_fwd_save(cfg, flat, m, z, msa_mask, pair_mask,
+                                                                       dtype=dtype, dropout=dropout)
         ctx.save_for_backward(m, z)
         ctx.cfg, ctx.flat, ctx.masks, ctx.dtype, ctx.dropout = cfg, flat, (msa_mask, pair_mask), dtype, dropout
         return m_out, z_out
@@ -30,15 +38,22 @@ class EvoformerBlockFn(torch.autograd.Function):
             dm_out = torch.zeros_like(m)
         if dz_out is None:
             dz_out = torch.zeros_like(z)
-        dm, dz, dflat = binding.evoformer_block_bwd(ctx.cfg, ctx.flat, m.contiguous(), z.contiguous(),
-                                                    ctx.masks[0], ctx.masks[1], dm_out.contiguous(),
-                                                    dz_out.contiguous(), dtype=ctx.dtype, dropout=ctx.dropout)
-        return dm, dz, dflat, None, None, None, None, None, None
+        if ctx.state is None:
+            dm, dz, dflat = binding.evoformer_block_bwd(ctx.cfg, ctx.flat, m, z, ctx.masks[0], ctx.masks[1],
+                                                        dm_out.contiguous(), dz_out.contiguous(), dtype=ctx.dtype,
+                                                        dropout=ctx.dropout)
+        else:
+            dm, dz, dflat = binding.evoformer_block_bwd_saved(ctx.cfg, ctx.flat, m, z, ctx.masks[0], ctx.masks[1],
+                                                              ctx.state, dm_out.contiguous(), dz_out.contiguous(),
+                                                              dtype=ctx.dtype, dropout=ctx.dropout)
+            ctx.state = None
+        return dm, dz, dflat, None, None, None, None, None, None, None
 
 
-def evoformer_block(cfg, flat, m, z, msa_mask=None, pair_mask=None, dtype=None, dropout=None):
-    """dropout: None or (seed, offset) of the dropout generator (training)."""
-    return EvoformerBlockFn.apply(m, z, flat.buffer, cfg, flat, msa_mask, pair_mask, dtype, dropout)
+def evoformer_block(cfg, flat, m, z, msa_mask=None, pair_mask=None, dtype=None, dropout=None, checkpoint=True):
+    """dropout: None or (seed, offset) of the dropout generator (training); checkpoint=False keeps
+    the block's state for the backward instead of recomputing the forward."""
+    return EvoformerBlockFn.apply(m, z, flat.buffer, cfg, flat, msa_mask, pair_mask, dtype, dropout, checkpoint)
 
 
 class EvoformerStack(torch.nn.Module):
@@ -54,11 +69,11 @@ class EvoformerStack(torch.nn.Module):
             f.buffer = torch.nn.Parameter(f.buffer)
             self.buffers_.append(f.buffer)
 
-    def forward(self, m, z, msa_mask=None, pair_mask=None, dtype=None, dropout=None):
+    def forward(self, m, z, msa_mask=None, pair_mask=None, dtype=None, dropout=None, checkpoint=True):
         """dropout: None or (seed, offset); block l draws its masks at offset + l."""
         for i, f in enumerate(self.flats):
             dr = None if dropout is None else (dropout[0], dropout[1] + i)
-            m, z = evoformer_block(self.cfg, f, m, z, msa_mask, pair_mask, dtype, dr)
+            m, z = evoformer_block(self.cfg, f, m, z, msa_mask, pair_mask, dtype, dr, checkpoint)
         return m, z
 
     def param_grads(self) -> list:

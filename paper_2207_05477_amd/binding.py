@@ -268,6 +268,71 @@ def evoformer_block_bwd(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, dm_out
     return dm, dz, dflat
 
 
+def evoformer_block_saved_bytes(cfg, dtype: str | None = None, dropout=None) -> int:
+    """Bytes of the state evoformer_block_fwd_save keeps for evoformer_block_bwd_saved."""
+    d = block_desc(cfg, dtype, 0, dropout)
+    n = _lib().evoformer_block_saved_bytes(ctypes.byref(d))
+    if n == 0:
+        A.check(A.EVO_ESHAPE, "evoformer_block_saved_bytes")
+    return n
+
+
+def evoformer_block_fwd_save(cfg, flat: FlatParams, m, z, msa_mask=None, pair_mask=None, m_out=None,
+                             z_out=None, saved=None, dtype: str | None = None, dropout=None):
+    """The block forward without its checkpoint: returns (m_out, z_out, saved), where `saved`
+    (a uint8 device tensor) holds what evoformer_block_bwd_saved needs instead of a recomputation."""
+    lib = _lib()
+    d = block_desc(cfg, dtype, 0, dropout)
+    w = flat.block_struct()
+    m_out = torch.empty_like(m) if m_out is None else m_out
+    z_out = torch.empty_like(z) if z_out is None else z_out
+    SR, RR = d.n_seq * d.n_res, d.n_res * d.n_res
+    _acts(d.dtype, m.device, m=(m, SR * d.c_m), z=(z, RR * d.c_z), m_out=(m_out, SR * d.c_m),
+          z_out=(z_out, RR * d.c_z))
+    _masks(m.device, msa_mask=(msa_mask, SR), pair_mask=(pair_mask, RR))
+    _check(flat.buffer, "parameters", torch.float32, flat.numel, m.device)
+    nsv = evoformer_block_saved_bytes(cfg, dtype, dropout)
+    saved = torch.empty(nsv, dtype=torch.uint8, device=m.device) if saved is None else saved
+    _check(saved, "saved state", torch.uint8, nsv, m.device)
+    nbytes = lib.evoformer_block_save_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_FWD)
+    if nbytes == 0:
+        A.check(A.EVO_ESHAPE, "evoformer_block_save_workspace_bytes")
+    ws = workspace(nbytes, m.device)
+    A.check(lib.evoformer_block_fwd_save(ctypes.byref(d), ctypes.byref(w), _ptr(m), _ptr(z), _ptr(msa_mask),
+                                         _ptr(pair_mask), _ptr(m_out), _ptr(z_out), _ptr(saved), saved.numel(),
+                                         _ptr(ws), ws.numel(), _stream(m.device)), "evoformer_block_fwd_save")
+    return m_out, z_out, saved
+
+
+def evoformer_block_bwd_saved(cfg, flat: FlatParams, m, z, msa_mask, pair_mask, saved, dm_out, dz_out,
+                              dflat=None, dm=None, dz=None, dtype: str | None = None, dropout=None):
+    """evoformer_block_bwd over the state of evoformer_block_fwd_save (no recomputation);
+    returns (dm, dz, dflat), dflat accumulated into."""
+    lib = _lib()
+    d = block_desc(cfg, dtype, 0, dropout)
+    w = flat.block_struct()
+    dflat = flat.zeros_like() if dflat is None else dflat
+    dw = flat.block_struct(dflat)
+    dm = torch.empty_like(dm_out) if dm is None else dm
+    dz = torch.empty_like(dz_out) if dz is None else dz
+    SR, RR = d.n_seq * d.n_res, d.n_res * d.n_res
+    _acts(d.dtype, m.device, m=(m, SR * d.c_m), z=(z, RR * d.c_z), dm_out=(dm_out, SR * d.c_m),
+          dz_out=(dz_out, RR * d.c_z), dm=(dm, SR * d.c_m), dz=(dz, RR * d.c_z))
+    _masks(m.device, msa_mask=(msa_mask, SR), pair_mask=(pair_mask, RR))
+    _check(flat.buffer, "parameters", torch.float32, flat.numel, m.device)
+    _check(dflat, "parameter gradients", torch.float32, flat.numel, m.device)
+    _check(saved, "saved state", torch.uint8, evoformer_block_saved_bytes(cfg, dtype, dropout), m.device)
+    nbytes = lib.evoformer_block_save_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
+    if nbytes == 0:
+        A.check(A.EVO_ESHAPE, "evoformer_block_save_workspace_bytes")
+    ws = workspace(nbytes, m.device)
+    A.check(lib.evoformer_block_bwd_saved(ctypes.byref(d), ctypes.byref(w), _ptr(m), _ptr(z), _ptr(msa_mask),
+                                          _ptr(pair_mask), _ptr(saved), _ptr(dm_out), _ptr(dz_out), _ptr(dm),
+                                          _ptr(dz), ctypes.byref(dw), _ptr(ws), ws.numel(), _stream(m.device)),
+            "evoformer_block_bwd_saved")
+    return dm, dz, dflat
+
+
 # ------------------------------------------------------------------ template pair stack block
 def template_desc(cfg, dtype: str | None = None, chunk: int | None = None, dropout=None,
                   template_index: int = 0) -> A.TemplateDesc:

@@ -545,6 +545,85 @@ evo_status_t evoformer_block_bwd(const evo_block_desc_t* d, const evo_block_w_t*
   });
 }
 
+// ------------------------------------------------------------------ block without its checkpoint
+size_t evoformer_block_saved_bytes(const evo_block_desc_t* d) {
+  if (check_block_desc(d) != EVO_OK || d->chunk != 0) return 0;
+  Ctx c; c.dry = true;
+  Arena ws; ws.dry = true;
+  Arena sv; sv.dry = true;
+  evo_block_w_t w; memset(&w, 0, sizeof(w));
+  if (d->dtype == EVO_BF16)
+    block_fwd_save_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  else
+    block_fwd_save_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return sv.off;
+}
+
+size_t evoformer_block_save_workspace_bytes(const evo_block_desc_t* d, int32_t phase) {
+  if (check_block_desc(d) != EVO_OK || d->chunk != 0) return 0;
+  Ctx c; c.dry = true;
+  Arena ws; ws.dry = true;
+  Arena sv; sv.dry = true;
+  evo_block_w_t w; memset(&w, 0, sizeof(w));
+  if (phase == EVO_PHASE_FWD) {
+    if (d->dtype == EVO_BF16) block_fwd_save_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    else block_fwd_save_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  } else {
+    if (d->dtype == EVO_BF16)
+      block_bwd_saved_op<bf16>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w);
+    else
+      block_bwd_saved_op<float>(c, ws, sv, *d, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w);
+  }
+  return ws.off;
+}
+
+evo_status_t evoformer_block_fwd_save(const evo_block_desc_t* d, const evo_block_w_t* w, const void* m, const void* z,
+                                      const float* msa_mask, const float* pair_mask, void* m_out, void* z_out,
+                                      void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
+  EVO_TRY(check_block_desc(d));
+  EVO_TRY(weights_ok(w, d));
+  EVO_TRY(ptrs_ok({m, z, m_out, z_out, saved}, {msa_mask, pair_mask}));
+  REQ(d->chunk == 0, EVO_EINVAL, "block forward with saved state: chunked execution keeps no state");
+  REQ(m_out != m && z_out != z, EVO_EINVAL, "block forward with saved state: outputs must not alias the inputs");
+  const size_t need_sv = evoformer_block_saved_bytes(d);
+  REQ(saved_bytes >= need_sv, EVO_EWORKSPACE, "saved buffer too small: %zu bytes needed, %zu given", need_sv,
+      saved_bytes);
+  return run_checked(stream, ws, ws_bytes, [&](const Ctx& c, Arena& a) -> evo_status_t {
+    Arena sv = live_arena(saved, need_sv);
+    const evo_status_t st =
+        d->dtype == EVO_BF16
+            ? block_fwd_save_op<bf16>(c, a, sv, *d, *w, (const bf16*)m, (const bf16*)z, msa_mask, pair_mask,
+                                      (bf16*)m_out, (bf16*)z_out)
+            : block_fwd_save_op<float>(c, a, sv, *d, *w, (const float*)m, (const float*)z, msa_mask, pair_mask,
+                                       (float*)m_out, (float*)z_out);
+    REQ(st != EVO_OK || !sv.overflow(), EVO_EWORKSPACE, "internal: saved state larger than its sizing");
+    return st;
+  });
+}
+
+evo_status_t evoformer_block_bwd_saved(const evo_block_desc_t* d, const evo_block_w_t* w, const void* m,
+                                       const void* z, const float* msa_mask, const float* pair_mask,
+                                       const void* saved, const void* dm_out, const void* dz_out, void* dm, void* dz,
+                                       const evo_block_w_t* d_w, void* ws, size_t ws_bytes, void* stream) {
+  EVO_TRY(check_block_desc(d));
+  EVO_TRY(weights_ok(w, d));
+  EVO_TRY(weights_ok(d_w, d));
+  EVO_TRY(ptrs_ok({m, z, saved, dm_out, dz_out, dm, dz}, {msa_mask, pair_mask}));
+  REQ(d->chunk == 0, EVO_EINVAL, "block backward: chunked execution is forward-only");
+  const size_t need_sv = evoformer_block_saved_bytes(d);
+  return run_checked(stream, ws, ws_bytes, [&](const Ctx& c, Arena& a) -> evo_status_t {
+    Arena sv = live_arena(const_cast<void*>(saved), need_sv);
+    const evo_status_t st =
+        d->dtype == EVO_BF16
+            ? block_bwd_saved_op<bf16>(c, a, sv, *d, *w, (const bf16*)m, (const bf16*)z, msa_mask, pair_mask,
+                                       (const bf16*)dm_out, (const bf16*)dz_out, (bf16*)dm, (bf16*)dz, *d_w)
+            : block_bwd_saved_op<float>(c, a, sv, *d, *w, (const float*)m, (const float*)z, msa_mask, pair_mask,
+                                        (const float*)dm_out, (const float*)dz_out, (float*)dm, (float*)dz, *d_w);
+    REQ(st != EVO_OK || !sv.overflow(), EVO_EWORKSPACE, "internal: saved state larger than its sizing");
+    return st;
+  });
+}
+
 // ------------------------------------------------------------------ template pair stack block
 size_t template_pair_block_workspace_bytes(const evo_template_desc_t* d, int32_t phase) {
   if (check_template_desc(d) != EVO_OK) return 0;

@@ -76,7 +76,7 @@ struct BlockDrop {
 };
 
 static evo_status_t make_block_drop(const Ctx& c, Arena& ws, const DropCfg& dc, int64_t R, int64_t cm, int64_t cz,
-                                    bool msa, BlockDrop* bd) {
+                                    bool msa, BlockDrop* bd, bool fill = true) {
   *bd = BlockDrop();
   if (!dc.on) return EVO_OK;
   float* out[5];
@@ -98,7 +98,7 @@ static evo_status_t make_block_drop(const Ctx& c, Arena& ws, const DropCfg& dc, 
   add(&bd->tas, SUB_TAS, dc.rate_att, cz, 1, R);
   add(&bd->tae, SUB_TAE, dc.rate_att, cz, R, 0);
   (void)spec;
-  return dropout_tables(c, dc.seed, dc.offset, n, out, len, word, rate);
+  return fill ? dropout_tables(c, dc.seed, dc.offset, n, out, len, word, rate) : EVO_OK;
 }
 
 static DropCfg block_drop_cfg(const evo_block_desc_t& d) {
@@ -125,11 +125,67 @@ struct Scratch {
   size_t end() const { return start() + high; }
 };
 
+// Parameter groups of a block call packed ahead, in a few launches: the
+// forward layout (and bias rows) for forwards and recomputed forwards, in a
+// backward also the backward layout.  The sub-operations then find their
+// groups in the cache instead of packing their own (one launch each).
+template <typename T>
+static evo_status_t prepack_groups(const Ctx& c, Arena& ws, PackArgs* g, int n, bool bwd, bool fill,
+                                   PackCache* pc) {
+  PackArgs* list[PackCache::MAX];
+  pc->n = 0;
+  for (int i = 0; i < n; ++i) {
+    int64_t ntot = 0;
+    for (int s = 0; s < g[i].nseg; ++s) ntot += g[i].seg[s].n;
+    g[i].dst_t = ws.take_n<T>((int64_t)g[i].K * ntot);
+    g[i].bias = ws.take_n<float>(ntot);
+    g[i].dst = bwd ? ws.take_n<T>((int64_t)g[i].K * ntot) : nullptr;
+    list[i] = &g[i];
+  }
+  if (c.dry) return EVO_OK;
+  if (fill) EVO_TRY(pack_groups<T>(c, list, n));
+  for (int i = 0; i < n; ++i) pc->e[pc->n++] = g[i];
+  return EVO_OK;
+}
+
+template <typename T>
+static evo_status_t prepack_block(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
+                                  bool bwd, bool fill, PackCache* pc) {
+  PackArgs g[18];
+  const int col_kind = d.extra_msa ? EVO_ATTN_COL_GLOBAL : EVO_ATTN_COL;
+  attn_pack_groups(block_attn_desc(d, EVO_ATTN_ROW), w.row_attn, &g[0], &g[1]);
+  attn_pack_groups(block_attn_desc(d, col_kind), w.col_attn, &g[2], &g[3]);
+  trans_pack_groups(block_trans_desc(d, true), w.msa_trans, &g[4], &g[5]);
+  opm_pack_groups(block_opm_desc(d), w.opm, &g[6], &g[7]);
+  trimul_pack_groups(block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, &g[8], &g[9]);
+  trimul_pack_groups(block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, &g[10], &g[11]);
+  attn_pack_groups(block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, &g[12], &g[13]);
+  attn_pack_groups(block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, &g[14], &g[15]);
+  trans_pack_groups(block_trans_desc(d, false), w.pair_trans, &g[16], &g[17]);
+  return prepack_groups<T>(c, ws, g, 18, bwd, fill, pc);
+}
+
+template <typename T>
+static evo_status_t prepack_template(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_template_w_t& w,
+                                     bool bwd, PackCache* pc) {
+  PackArgs g[10];
+  attn_pack_groups(block_attn_desc(d, EVO_ATTN_TRI_START), w.tri_att_start, &g[0], &g[1]);
+  attn_pack_groups(block_attn_desc(d, EVO_ATTN_TRI_END), w.tri_att_end, &g[2], &g[3]);
+  trimul_pack_groups(block_trimul_desc(d, EVO_TRI_OUT), w.tri_mul_out, &g[4], &g[5]);
+  trimul_pack_groups(block_trimul_desc(d, EVO_TRI_IN), w.tri_mul_in, &g[6], &g[7]);
+  trans_pack_groups(block_trans_desc(d, false), w.pair_trans, &g[8], &g[9]);
+  return prepack_groups<T>(c, ws, g, 10, bwd, true, pc);
+}
+
 template <typename T, typename X>
-static evo_status_t block_fwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
+static evo_status_t block_fwd_x(const Ctx& c0, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
                                 const X* m, const X* z, const float* mm, const float* pm, X* mo, X* zo) {
   BlockDrop bd;
-  EVO_TRY(make_block_drop(c, ws, block_drop_cfg(d), d.n_res, d.c_m, d.c_z, true, &bd));
+  EVO_TRY(make_block_drop(c0, ws, block_drop_cfg(d), d.n_res, d.c_m, d.c_z, true, &bd));
+  PackCache pc;
+  EVO_TRY(prepack_block<T>(c0, ws, d, w, false, true, &pc));
+  Ctx c = c0;
+  c.packed = &pc;
   Scratch sc;
   sc.base = ws;
   const int col_kind = d.extra_msa ? EVO_ATTN_COL_GLOBAL : EVO_ATTN_COL;
@@ -158,10 +214,21 @@ static evo_status_t block_fwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   return EVO_OK;
 }
 
+// A block's training pass.  BLK_FULL: the checkpointed backward (recompute the
+// forward into the workspace, then the backward ops in reverse order).
+// BLK_SAVE: only the recomputation, as a forward that keeps the block's state
+// (dropout tables, packed parameters, the activations between sub-ops and
+// every sub-op's saved tensors) in `kp` and writes the block's outputs to
+// mo / zo.  BLK_SAVED: only the backward, over the state a BLK_SAVE call left
+// in `kp` (carved in the same order, nothing recomputed).  In BLK_FULL `kp` is
+// the workspace itself.
+enum { BLK_FULL = 0, BLK_SAVE = 1, BLK_SAVED = 2 };
+
 template <typename T, typename X>
-static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
-                                const X* m, const X* z, const float* mm, const float* pm, const X* dmo,
-                                const X* dzo, X* dm, X* dz, const evo_block_w_t& dw) {
+static evo_status_t block_train_x(const Ctx& c0, Arena& ws, Arena& kp, int mode, const evo_block_desc_t& d,
+                                  const evo_block_w_t& w, const X* m, const X* z, const float* mm, const float* pm,
+                                  const X* dmo, const X* dzo, X* dm, X* dz, const evo_block_w_t& dw, X* mo,
+                                  X* zo, const X** fin = nullptr) {
   const int64_t SRc = d.n_seq * d.n_res * d.c_m, RRc = d.n_res * d.n_res * d.c_z;
   const int col_kind = d.extra_msa ? EVO_ATTN_COL_GLOBAL : EVO_ATTN_COL;
   const evo_attn_desc_t d_row = block_attn_desc(d, EVO_ATTN_ROW), d_col = block_attn_desc(d, col_kind);
@@ -173,22 +240,27 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   evo_trimul_desc_t d_mo = block_trimul_desc(d, EVO_TRI_OUT), d_mi = block_trimul_desc(d, EVO_TRI_IN);
   d_mo.chunk = 0; d_mi.chunk = 0;
 
+  const bool fill = mode != BLK_SAVED, save = mode == BLK_SAVE;
   BlockDrop bd;
-  EVO_TRY(make_block_drop(c, ws, block_drop_cfg(d), d.n_res, d.c_m, d.c_z, true, &bd));
+  EVO_TRY(make_block_drop(c0, kp, block_drop_cfg(d), d.n_res, d.c_m, d.c_z, true, &bd, fill));
+  PackCache pc;
+  EVO_TRY(prepack_block<T>(c0, kp, d, w, true, fill, &pc));
+  Ctx c = c0;
+  c.packed = &pc;
   const bool of = d.opm_first != 0;
   // activations between sub-ops.  A0 order: m -> m1 -> m2 -> m3 (row, column,
   // transition), z -> z1 (outer product mean of m3) -> z2 ... z6 (pair stack).
   // Outer-product-mean first: z -> z1 (outer product mean of m), then the MSA
   // stack m -> m1 -> m2 -> m3 with the pair bias from z1, and the pair stack.
-  X* m1 = ws.take_n<X>(SRc);
-  X* m2 = ws.take_n<X>(SRc);
-  X* m3 = ws.take_n<X>(SRc);
-  X* z1 = ws.take_n<X>(RRc);
-  X* z2 = ws.take_n<X>(RRc);
-  X* z3 = ws.take_n<X>(RRc);
-  X* z4 = ws.take_n<X>(RRc);
-  X* z5 = ws.take_n<X>(RRc);
-  X* z6 = ws.take_n<X>(RRc);
+  X* m1 = kp.take_n<X>(SRc);
+  X* m2 = kp.take_n<X>(SRc);
+  X* m3 = kp.take_n<X>(SRc);
+  X* z1 = kp.take_n<X>(RRc);
+  X* z2 = kp.take_n<X>(RRc);
+  X* z3 = kp.take_n<X>(RRc);
+  X* z4 = kp.take_n<X>(RRc);
+  X* z5 = kp.take_n<X>(RRc);
+  X* z6 = kp.take_n<X>(RRc);
   // saved regions: carved by the ops themselves from per-op sub-arenas
   Arena sv[9];
   for (int i = 0; i < 9; ++i) { sv[i].dry = true; }
@@ -206,7 +278,7 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
     trans_fwd_op<T, X>(dry, junk, sv[8], d_tz, w.pair_trans, z5, z6);
   }
   char* svbase[9];
-  for (int i = 0; i < 9; ++i) svbase[i] = (char*)ws.take(sv[i].off);
+  for (int i = 0; i < 9; ++i) svbase[i] = (char*)kp.take(sv[i].off);
   auto S = [&](int i) {
     Arena a;
     a.dry = c.dry;
@@ -228,16 +300,26 @@ static evo_status_t block_bwd_x(const Ctx& c, Arena& ws, const evo_block_desc_t&
   // recompute the forward, keeping what the backward needs
   const X* m_opm = of ? m : m3;     // the outer product mean's input
   const X* z_row = of ? z1 : z;     // the pair representation row attention reads
-  if (of) EVO_STEPS(3, "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, z, z1)));
-  EVO_STEPS(0, "row.recompute", (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z_row, mm, m1, &bd.row)));
-  EVO_STEPS(1, "col.recompute", (attn_fwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, m2)));
-  EVO_STEPS(2, "msa_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, m3)));
-  if (!of) EVO_STEPS(3, "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, z, z1)));
-  EVO_STEPS(4, "tri_mul_out.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, z2, &bd.tmo)));
-  EVO_STEPS(5, "tri_mul_in.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, z3, &bd.tmi)));
-  EVO_STEPS(6, "tri_att_start.recompute", (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, z4, &bd.tas)));
-  EVO_STEPS(7, "tri_att_end.recompute", (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, z5, &bd.tae)));
-  EVO_STEPS(8, "pair_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, z6)));
+  if (mode != BLK_SAVED) {
+  if (of) EVO_STEPS(3, save ? "opm.fwd" : "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, z, z1)));
+  EVO_STEPS(0, save ? "row.fwd" : "row.recompute", (attn_fwd_op<T, X>(c, a, s, d_row, w.row_attn, m, z_row, mm, m1, &bd.row)));
+  EVO_STEPS(1, save ? "col.fwd" : "col.recompute", (attn_fwd_op<T, X>(c, a, s, d_col, w.col_attn, m1, nullptr, mm, m2)));
+  EVO_STEPS(2, save ? "msa_trans.fwd" : "msa_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tm, w.msa_trans, m2, m3)));
+  if (!of) EVO_STEPS(3, save ? "opm.fwd" : "opm.recompute", (opm_fwd_op<T, X>(c, a, s, d_opm, w.opm, m_opm, mm, z, z1)));
+  EVO_STEPS(4, save ? "tri_mul_out.fwd" : "tri_mul_out.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mo, w.tri_mul_out, z1, pm, z2, &bd.tmo)));
+  EVO_STEPS(5, save ? "tri_mul_in.fwd" : "tri_mul_in.recompute", (trimul_fwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, z3, &bd.tmi)));
+  EVO_STEPS(6, save ? "tri_att_start.fwd" : "tri_att_start.recompute", (attn_fwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, z4, &bd.tas)));
+  EVO_STEPS(7, save ? "tri_att_end.fwd" : "tri_att_end.recompute", (attn_fwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, z5, &bd.tae)));
+  EVO_STEPS(8, save ? "pair_trans.fwd" : "pair_trans.recompute", (trans_fwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, z6)));
+  }
+  if (mode == BLK_SAVE) {
+    // outputs: copied to mo / zo, or handed back in place (fin)
+    if (fin) { fin[0] = m3; fin[1] = z6; }
+    if (!c.dry && mo) EVO_TRY(copy_elems<X>(c, m3, mo, SRc));
+    if (!c.dry && zo) EVO_TRY(copy_elems<X>(c, z6, zo, RRc));
+    ws.off = sc.end();
+    return EVO_OK;
+  }
   // backward in reverse order; the pair gradient is updated in place in dz
   if (!c.dry) {
     EVO_TRY(copy_elems<X>(c, dzo, dz, RRc));
@@ -279,26 +361,60 @@ evo_status_t block_fwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, co
   }
 }
 
+// The training pass in the activation type T: FP32 residual streams inside
+// (BF16 inputs converted into the workspace; the converted inputs are formed
+// again, identically, by a BLK_SAVED call).
+template <typename T>
+static evo_status_t block_train_op(const Ctx& c, Arena& ws, Arena& kp, int mode, const evo_block_desc_t& d,
+                                   const evo_block_w_t& w, const T* m, const T* z, const float* mm, const float* pm,
+                                   const T* dmo, const T* dzo, T* dm, T* dz, const evo_block_w_t& dw, T* mo, T* zo) {
+  if constexpr (std::is_same<T, float>::value) {
+    return block_train_x<T, float>(c, ws, kp, mode, d, w, m, z, mm, pm, dmo, dzo, dm, dz, dw, mo, zo);
+  } else {
+    const int64_t SRc = d.n_seq * d.n_res * d.c_m, RRc = d.n_res * d.n_res * d.c_z;
+    const bool bwd = mode != BLK_SAVE;
+    float* mx = ws.take_n<float>(SRc);
+    float* zx = ws.take_n<float>(RRc);
+    float* dmx = bwd ? ws.take_n<float>(SRc) : nullptr;
+    float* dzx = bwd ? ws.take_n<float>(RRc) : nullptr;
+    EVO_TRY((convert_elems<T, float>(c, m, mx, SRc)));
+    EVO_TRY((convert_elems<T, float>(c, z, zx, RRc)));
+    if (bwd) {
+      EVO_TRY((convert_elems<T, float>(c, dmo, dmx, SRc)));
+      EVO_TRY((convert_elems<T, float>(c, dzo, dzx, RRc)));
+    }
+    const float* fin[2] = {nullptr, nullptr};
+    EVO_TRY((block_train_x<T, float>(c, ws, kp, mode, d, w, mx, zx, mm, pm, dmx, dzx, dmx, dzx, dw, nullptr, nullptr,
+                                     fin)));
+    if (!bwd) {
+      EVO_TRY((convert_elems<float, T>(c, fin[0], mo, SRc)));
+      return convert_elems<float, T>(c, fin[1], zo, RRc);
+    }
+    EVO_TRY((convert_elems<float, T>(c, dmx, dm, SRc)));
+    return convert_elems<float, T>(c, dzx, dz, RRc);
+  }
+}
+
 template <typename T>
 evo_status_t block_bwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
                           const T* m, const T* z, const float* mm, const float* pm, const T* dmo,
                           const T* dzo, T* dm, T* dz, const evo_block_w_t& dw) {
-  if constexpr (std::is_same<T, float>::value) {
-    return block_bwd_x<T, float>(c, ws, d, w, m, z, mm, pm, dmo, dzo, dm, dz, dw);
-  } else {
-    const int64_t SRc = d.n_seq * d.n_res * d.c_m, RRc = d.n_res * d.n_res * d.c_z;
-    float* mx = ws.take_n<float>(SRc);
-    float* zx = ws.take_n<float>(RRc);
-    float* dmx = ws.take_n<float>(SRc);
-    float* dzx = ws.take_n<float>(RRc);
-    EVO_TRY((convert_elems<T, float>(c, m, mx, SRc)));
-    EVO_TRY((convert_elems<T, float>(c, z, zx, RRc)));
-    EVO_TRY((convert_elems<T, float>(c, dmo, dmx, SRc)));
-    EVO_TRY((convert_elems<T, float>(c, dzo, dzx, RRc)));
-    EVO_TRY((block_bwd_x<T, float>(c, ws, d, w, mx, zx, mm, pm, dmx, dzx, dmx, dzx, dw)));
-    EVO_TRY((convert_elems<float, T>(c, dmx, dm, SRc)));
-    return convert_elems<float, T>(c, dzx, dz, RRc);
-  }
+  return block_train_op<T>(c, ws, ws, BLK_FULL, d, w, m, z, mm, pm, dmo, dzo, dm, dz, dw, nullptr, nullptr);
+}
+
+template <typename T>
+evo_status_t block_fwd_save_op(const Ctx& c, Arena& ws, Arena& saved, const evo_block_desc_t& d,
+                               const evo_block_w_t& w, const T* m, const T* z, const float* mm, const float* pm,
+                               T* mo, T* zo) {
+  return block_train_op<T>(c, ws, saved, BLK_SAVE, d, w, m, z, mm, pm, nullptr, nullptr, nullptr, nullptr, w, mo,
+                           zo);
+}
+
+template <typename T>
+evo_status_t block_bwd_saved_op(const Ctx& c, Arena& ws, Arena& saved, const evo_block_desc_t& d,
+                                const evo_block_w_t& w, const T* m, const T* z, const float* mm, const float* pm,
+                                const T* dmo, const T* dzo, T* dm, T* dz, const evo_block_w_t& dw) {
+  return block_train_op<T>(c, ws, saved, BLK_SAVED, d, w, m, z, mm, pm, dmo, dzo, dm, dz, dw, nullptr, nullptr);
 }
 
 // ============================================================== template pair stack block
@@ -329,11 +445,15 @@ static DropCfg template_drop_cfg(const evo_template_desc_t& d) {
 }
 
 template <typename T, typename X>
-static evo_status_t template_fwd_x(const Ctx& c, Arena& ws, const evo_template_desc_t& td, const evo_template_w_t& w,
+static evo_status_t template_fwd_x(const Ctx& c0, Arena& ws, const evo_template_desc_t& td, const evo_template_w_t& w,
                                    const X* t, const float* pm, X* to) {
   const evo_block_desc_t d = template_as_block(td);
   BlockDrop bd;
-  EVO_TRY(make_block_drop(c, ws, template_drop_cfg(td), d.n_res, 0, d.c_z, false, &bd));
+  EVO_TRY(make_block_drop(c0, ws, template_drop_cfg(td), d.n_res, 0, d.c_z, false, &bd));
+  PackCache pc;
+  EVO_TRY(prepack_template<T>(c0, ws, d, w, false, &pc));
+  Ctx c = c0;
+  c.packed = &pc;
   Scratch sc;
   sc.base = ws;
 #define EVO_STEP(tag, call)       \
@@ -354,7 +474,7 @@ static evo_status_t template_fwd_x(const Ctx& c, Arena& ws, const evo_template_d
 }
 
 template <typename T, typename X>
-static evo_status_t template_bwd_x(const Ctx& c, Arena& ws, const evo_template_desc_t& td, const evo_template_w_t& w,
+static evo_status_t template_bwd_x(const Ctx& c0, Arena& ws, const evo_template_desc_t& td, const evo_template_w_t& w,
                                    const X* t, const float* pm, const X* dto, X* dt, const evo_template_w_t& dw) {
   evo_block_desc_t d = template_as_block(td);
   d.chunk = 0;
@@ -363,7 +483,11 @@ static evo_status_t template_bwd_x(const Ctx& c, Arena& ws, const evo_template_d
   const evo_trimul_desc_t d_mo = block_trimul_desc(d, EVO_TRI_OUT), d_mi = block_trimul_desc(d, EVO_TRI_IN);
   const evo_trans_desc_t d_tz = block_trans_desc(d, false);
   BlockDrop bd;
-  EVO_TRY(make_block_drop(c, ws, template_drop_cfg(td), d.n_res, 0, d.c_z, false, &bd));
+  EVO_TRY(make_block_drop(c0, ws, template_drop_cfg(td), d.n_res, 0, d.c_z, false, &bd));
+  PackCache pc;
+  EVO_TRY(prepack_template<T>(c0, ws, d, w, true, &pc));
+  Ctx c = c0;
+  c.packed = &pc;
   // t -> t1 (start) -> t2 (end) -> t3 (out) -> t4 (in) -> t5 (transition)
   X* t1 = ws.take_n<X>(RRc);
   X* t2 = ws.take_n<X>(RRc);
@@ -463,7 +587,14 @@ template evo_status_t template_bwd_op<bf16>(const Ctx&, Arena&, const evo_templa
   template evo_status_t block_bwd_op<T>(const Ctx&, Arena&, const evo_block_desc_t&,               \
                                         const evo_block_w_t&, const T*, const T*, const float*,    \
                                         const float*, const T*, const T*, T*, T*,                  \
-                                        const evo_block_w_t&);
+                                        const evo_block_w_t&);                                     \
+  template evo_status_t block_fwd_save_op<T>(const Ctx&, Arena&, Arena&, const evo_block_desc_t&,  \
+                                             const evo_block_w_t&, const T*, const T*,             \
+                                             const float*, const float*, T*, T*);                  \
+  template evo_status_t block_bwd_saved_op<T>(const Ctx&, Arena&, Arena&, const evo_block_desc_t&, \
+                                              const evo_block_w_t&, const T*, const T*,            \
+                                              const float*, const float*, const T*, const T*, T*,  \
+                                              T*, const evo_block_w_t&);
 
 EVO_INST_B(float)
 EVO_INST_B(bf16)

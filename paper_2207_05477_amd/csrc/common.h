@@ -196,12 +196,15 @@ struct Arena {
 };
 
 struct RedQueue;
+struct PackCache;
 struct Ctx {
   hipStream_t stream = nullptr;
   bool dry = false;      // size only: allocate from the arenas, launch nothing
   // When set, parameter-gradient reductions are queued here and run as one
   // batched launch by flush_reductions (see misc.h).
   RedQueue* defer = nullptr;
+  // When set, parameter groups already packed for this call (see misc.h).
+  const PackCache* packed = nullptr;
 };
 
 inline size_t dtype_bytes(int dt) { return dt == EVO_BF16 ? 2 : 4; }

@@ -95,21 +95,34 @@ template <typename T>
 evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
                         float* out);
 
-// Parameter packing: up to 8 FP32 segments W_i[K][n_i] concatenated along n.
+// Parameter packing: up to 5 FP32 segments W_i[K][n_i] concatenated along n.
 struct PackSeg { const float* w; const float* bias; int32_t n; };
 struct PackArgs {
-  PackSeg seg[8];
+  PackSeg seg[5];
   int32_t nseg = 0;
   int32_t K = 0;
   void* dst_t = nullptr;   // [sum n][K], kernel type   (forward B operand)
   void* dst = nullptr;     // [K][sum n], kernel type   (backward B operand)
   float* bias = nullptr;   // [sum n] FP32 (missing segment biases are 0)
 };
+// Groups packed ahead of the operations that use them (a block packs the
+// parameters of all its sub-operations in one pass at the start of a call).
+// find() matches a request by its segments (weights, widths and, when the
+// request wants the bias row, the segment biases) and by the layouts it asks
+// for, and points the request's destinations at the packed copies.
+struct PackCache {
+  static constexpr int MAX = 40;
+  int n = 0;
+  PackArgs e[MAX];
+  bool find(PackArgs& a) const;
+};
+// Packs the groups in `list` (any number, in launches of a few groups each);
+// with c.packed set, groups found there are taken from it and not packed: the
+// caller then reads the destinations back from the PackArgs.
 template <typename T>
-evo_status_t pack_params(const Ctx& c, const PackArgs& a);
-// Several groups (up to 3) in one launch.
+evo_status_t pack_params(const Ctx& c, std::initializer_list<PackArgs*> list);
 template <typename T>
-evo_status_t pack_params(const Ctx& c, std::initializer_list<const PackArgs*> list);
+evo_status_t pack_groups(const Ctx& c, PackArgs* const* g, int n);
 
 template <typename T>
 evo_status_t fill_zero(const Ctx& c, T* p, int64_t n);

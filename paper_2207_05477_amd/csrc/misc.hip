@@ -1150,7 +1150,7 @@ evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t l
 // ============================================================== packing / fill
 // Up to PACK_MAX parameter groups in one launch: blocks [start_g, start_{g+1})
 // pack group g, one element (k, n) of its [K][sum n] concatenation per thread.
-constexpr int PACK_MAX = 3;
+constexpr int PACK_MAX = 10;
 struct PackBatch {
   PackArgs a[PACK_MAX];
   int32_t ntot[PACK_MAX];
@@ -1175,38 +1175,66 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackBatch b) {
   if (a.bias && k == 0) a.bias[n] = a.seg[s].bias ? a.seg[s].bias[nl] : 0.f;
 }
 
-template <typename T>
-evo_status_t pack_params(const Ctx& c, std::initializer_list<const PackArgs*> list) {
-  if (c.dry) return EVO_OK;
-  EVO_CHECK_ARG(list.size() <= (size_t)PACK_MAX, EVO_EINVAL, "pack: %zu groups > %d", list.size(), PACK_MAX);
-  PackBatch b;
-  memset(&b, 0, sizeof(b));
-  double bytes = 0.0;
-  int nblk = 0;
-  for (const PackArgs* a : list) {
-    int ntot = 0;
-    for (int s = 0; s < a->nseg; ++s) {
-      EVO_CHECK_ARG(a->seg[s].w != nullptr, EVO_EINVAL, "null parameter pointer (segment %d)", s);
-      ntot += a->seg[s].n;
-    }
-    const int64_t n = (int64_t)a->K * ntot;
-    EVO_CHECK_ARG(n < (1LL << 30), EVO_EINVAL, "pack: %lld elements too many", (long long)n);
-    b.a[b.n] = *a;
-    b.ntot[b.n] = ntot;
-    b.start[b.n] = nblk;
-    ++b.n;
-    nblk += (int)((n + 255) / 256);
-    bytes += (double)n * (4.0 + sizeof(T) * ((a->dst ? 1 : 0) + (a->dst_t ? 1 : 0)));
+bool PackCache::find(PackArgs& a) const {
+  for (int i = 0; i < n; ++i) {
+    const PackArgs& h = e[i];
+    if (h.K != a.K || h.nseg != a.nseg) continue;
+    if ((a.dst && !h.dst) || (a.dst_t && !h.dst_t) || (a.bias && !h.bias)) continue;
+    bool same = true;
+    for (int s = 0; s < a.nseg; ++s)
+      same = same && h.seg[s].w == a.seg[s].w && h.seg[s].n == a.seg[s].n &&
+             (!a.bias || h.seg[s].bias == a.seg[s].bias);
+    if (!same) continue;
+    if (a.dst) a.dst = h.dst;
+    if (a.dst_t) a.dst_t = h.dst_t;
+    if (a.bias) a.bias = h.bias;
+    return true;
   }
-  b.start[b.n] = nblk;
-  if (nblk == 0) return EVO_OK;
-  EVO_LAUNCH(EVO_KNAME("pack_kernel", T), 0.0, bytes, (pack_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, b);
-  return check_launch("pack_params");
+  return false;
 }
 
 template <typename T>
-evo_status_t pack_params(const Ctx& c, const PackArgs& a) {
-  return pack_params<T>(c, {&a});
+evo_status_t pack_groups(const Ctx& c, PackArgs* const* g, int ng) {
+  if (c.dry) return EVO_OK;
+  for (int i0 = 0; i0 < ng; i0 += PACK_MAX) {
+    PackBatch b;
+    memset(&b, 0, sizeof(b));
+    double bytes = 0.0;
+    int nblk = 0;
+    for (int i = i0; i < ng && i < i0 + PACK_MAX; ++i) {
+      const PackArgs* a = g[i];
+      EVO_CHECK_ARG(a->nseg >= 1 && a->nseg <= 5, EVO_EINVAL, "pack: %d segments", a->nseg);
+      int ntot = 0;
+      for (int s = 0; s < a->nseg; ++s) {
+        EVO_CHECK_ARG(a->seg[s].w != nullptr, EVO_EINVAL, "null parameter pointer (segment %d)", s);
+        ntot += a->seg[s].n;
+      }
+      const int64_t n = (int64_t)a->K * ntot;
+      EVO_CHECK_ARG(n < (1LL << 30), EVO_EINVAL, "pack: %lld elements too many", (long long)n);
+      b.a[b.n] = *a;
+      b.ntot[b.n] = ntot;
+      b.start[b.n] = nblk;
+      ++b.n;
+      nblk += (int)((n + 255) / 256);
+      bytes += (double)n * (4.0 + sizeof(T) * ((a->dst ? 1 : 0) + (a->dst_t ? 1 : 0)));
+    }
+    b.start[b.n] = nblk;
+    if (nblk == 0) continue;
+    EVO_LAUNCH(EVO_KNAME("pack_kernel", T), 0.0, bytes, (pack_kernel<T>), dim3((unsigned)nblk), dim3(256), 0, c.stream, b);
+    EVO_TRY(check_launch("pack_params"));
+  }
+  return EVO_OK;
+}
+
+template <typename T>
+evo_status_t pack_params(const Ctx& c, std::initializer_list<PackArgs*> list) {
+  if (c.dry) return EVO_OK;
+  PackArgs* todo[8];
+  int n = 0;
+  EVO_CHECK_ARG(list.size() <= 8, EVO_EINVAL, "pack: %zu groups", list.size());
+  for (PackArgs* a : list)
+    if (!(c.packed && c.packed->find(*a))) todo[n++] = a;
+  return pack_groups<T>(c, todo, n);
 }
 
 template <typename T>
@@ -1231,6 +1259,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const T* __restrict__ s, T* _
 template <typename T>
 evo_status_t copy_elems(const Ctx& c, const T* src, T* dst, int64_t n) {
   if (c.dry || n == 0 || src == dst) return EVO_OK;
+  if (n % 8 == 0 && aligned16(src) && aligned16(dst)) return convert_elems<T, T>(c, src, dst, n);
   EVO_LAUNCH(EVO_KNAME("copy_kernel", T), 0.0, (double)n * 2 * sizeof(T), (copy_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, src, dst, n);
   return check_launch("copy");
 }
@@ -1690,8 +1719,8 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
   template evo_status_t colsum_add<T>(const Ctx&, const T*, int64_t, int, int64_t, float*, float*); \
   template evo_status_t opm_dab_reduce<T>(const Ctx&, const float*, int, int64_t, int64_t, int,       \
                                           const float*, T*, int);                                  \
-  template evo_status_t pack_params<T>(const Ctx&, const PackArgs&);                               \
-  template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<const PackArgs*>);        \
+  template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<PackArgs*>);              \
+  template evo_status_t pack_groups<T>(const Ctx&, PackArgs* const*, int);                         \
   template evo_status_t fill_zero<T>(const Ctx&, T*, int64_t);                                     \
   template evo_status_t copy_elems<T>(const Ctx&, const T*, T*, int64_t);                          \
   template evo_status_t gate_bwd<T>(const Ctx&, int64_t, int, int, const float*, int64_t,                \

@@ -123,6 +123,12 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
                            const evo_trimul_w_t& w, const X* z, const float* mask, const X* dzo,
                            X* dz, const evo_trimul_w_t& dw, const DropSpec* drop = nullptr);
 
+// Parameter groups of each op (segments only; see PackArgs in misc.h).
+void attn_pack_groups(const evo_attn_desc_t& d, const evo_attn_w_t& w, PackArgs* in, PackArgs* out);
+void trans_pack_groups(const evo_trans_desc_t& d, const evo_trans_w_t& w, PackArgs* p1, PackArgs* p2);
+void opm_pack_groups(const evo_opm_desc_t& d, const evo_opm_w_t& w, PackArgs* pa, PackArgs* po);
+void trimul_pack_groups(const evo_trimul_desc_t& d, const evo_trimul_w_t& w, PackArgs* pp, PackArgs* po);
+
 // ---- argument validation shared by the ABI entry points
 evo_status_t check_attn_desc(const evo_attn_desc_t* d);
 evo_status_t check_trans_desc(const evo_trans_desc_t* d);
@@ -143,6 +149,17 @@ template <typename T>
 evo_status_t block_bwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, const evo_block_w_t& w,
                           const T* m, const T* z, const float* mm, const float* pm, const T* dmo,
                           const T* dzo, T* dm, T* dz, const evo_block_w_t& dw);
+// The block without its checkpoint: a forward that keeps the block's state in
+// `saved` (sized by a dry call) and a backward that consumes it instead of
+// recomputing the forward.
+template <typename T>
+evo_status_t block_fwd_save_op(const Ctx& c, Arena& ws, Arena& saved, const evo_block_desc_t& d,
+                               const evo_block_w_t& w, const T* m, const T* z, const float* mm, const float* pm,
+                               T* mo, T* zo);
+template <typename T>
+evo_status_t block_bwd_saved_op(const Ctx& c, Arena& ws, Arena& saved, const evo_block_desc_t& d,
+                                const evo_block_w_t& w, const T* m, const T* z, const float* mm, const float* pm,
+                                const T* dmo, const T* dzo, T* dm, T* dz, const evo_block_w_t& dw);
 
 // Template pair stack block (block.hip).
 evo_block_desc_t template_as_block(const evo_template_desc_t& t);

@@ -127,6 +127,23 @@ evo_status_t gattn_bwd(const Ctx& c, Arena& ws, int64_t S, int64_t R, int H, int
                        const float* mask, const float* qbar, const float* minv, const float* gctx,
                        const float* smax, const float* sinv, const float* dgo, T* dqkvg);
 
+// Parameter groups of an attention op: the fused q|k|v|g projection (the
+// gate bias as its bias row) and the output projection.
+void attn_pack_groups(const evo_attn_desc_t& d, const evo_attn_w_t& w, PackArgs* in, PackArgs* out) {
+  const AttnShape s = attn_shape(d);
+  *in = PackArgs();
+  in->K = (int)s.cin;
+  in->seg[0] = {w.w_q, nullptr, s.HC};
+  in->seg[1] = {w.w_k, nullptr, s.global ? s.D : s.HC};
+  in->seg[2] = {w.w_v, nullptr, s.global ? s.D : s.HC};
+  in->seg[3] = {w.w_g, w.b_g, s.HC};
+  in->nseg = 4;
+  *out = PackArgs();
+  out->K = s.HC;
+  out->seg[0] = {w.w_o, nullptr, (int)s.cin};
+  out->nseg = 1;
+}
+
 // Forward of triangle attention in chunks of `chunk` batch rows (starting node:
 // rows i; ending node: columns j), keeping no saved state.  Only the chunk's
 // LayerNorm / projection / context buffers exist; the pair bias (all rows) is
@@ -148,21 +165,15 @@ static evo_status_t attn_fwd_tri_chunked(const Ctx& c, Arena& ws, const evo_attn
   T* qkvg = ws.take_n<T>(CR * s.NQ);
   T* go = ws.take_n<T>(CR * s.HC);
   if (c.dry) return EVO_OK;
-  PackArgs pk;
-  pk.K = (int)cin;
-  pk.seg[0] = {w.w_q, nullptr, s.HC};
-  pk.seg[1] = {w.w_k, nullptr, s.HC};
-  pk.seg[2] = {w.w_v, nullptr, s.HC};
-  pk.seg[3] = {w.w_g, w.b_g, s.HC};
-  pk.nseg = 4;
+  PackArgs pk, po;
+  attn_pack_groups(d, w, &pk, &po);
   pk.dst_t = wt_qkvg;
   pk.bias = b_qkvg;
-  PackArgs po;
-  po.K = s.HC;
-  po.seg[0] = {w.w_o, nullptr, (int)cin};
-  po.nseg = 1;
   po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, {&pk, &po}));
+  wt_qkvg = (T*)pk.dst_t;
+  b_qkvg = pk.bias;
+  wt_o = (T*)po.dst_t;
   EVO_TRY((pair_bias<X, T>(c, !start, x, R, (int)cin, w.ln_g, w.ln_b, d.ln_eps, w.w_bias, s.H, bias)));
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     // chunk rows: starting node (i, j) = (c0 + ii, j) contiguous; ending node
@@ -235,21 +246,15 @@ evo_status_t attn_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   if (c.dry) return EVO_OK;
 
   // parameters: forward operands [n][k] in the compute type
-  PackArgs pk;
-  pk.K = (int)s.cin;
-  pk.seg[0] = {w.w_q, nullptr, s.HC};
-  pk.seg[1] = {w.w_k, nullptr, s.global ? s.D : s.HC};
-  pk.seg[2] = {w.w_v, nullptr, s.global ? s.D : s.HC};
-  pk.seg[3] = {w.w_g, w.b_g, s.HC};
-  pk.nseg = 4;
+  PackArgs pk, po;
+  attn_pack_groups(d, w, &pk, &po);
   pk.dst_t = wt_qkvg;
   pk.bias = b_qkvg;
-  PackArgs po;
-  po.K = s.HC;
-  po.seg[0] = {w.w_o, nullptr, (int)s.cin};
-  po.nseg = 1;
   po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, {&pk, &po}));
+  wt_qkvg = (T*)pk.dst_t;
+  b_qkvg = pk.bias;
+  wt_o = (T*)po.dst_t;
 
   EVO_TRY((ln_fwd<X, T>(c, x, s.rows, (int)s.cin, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {
@@ -334,20 +339,13 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   (void)mark;
 
   if (!c.dry) {
-    PackArgs pk;
-    pk.K = (int)s.cin;
-    pk.seg[0] = {w.w_q, nullptr, s.HC};
-    pk.seg[1] = {w.w_k, nullptr, s.global ? s.D : s.HC};
-    pk.seg[2] = {w.w_v, nullptr, s.global ? s.D : s.HC};
-    pk.seg[3] = {w.w_g, nullptr, s.HC};
-    pk.nseg = 4;
+    PackArgs pk, po;
+    attn_pack_groups(d, w, &pk, &po);
     pk.dst = w_qkvg;
-    PackArgs po;
-    po.K = s.HC;
-    po.seg[0] = {w.w_o, nullptr, (int)s.cin};
-    po.nseg = 1;
     po.dst = w_o;
     EVO_TRY(pack_params<T>(c, {&pk, &po}));
+    w_qkvg = (T*)pk.dst;
+    w_o = (T*)po.dst;
   }
 
   // output projection

@@ -3,6 +3,35 @@
 
 namespace evo {
 
+// Parameter groups of the pair-stack ops (segments only; callers add the
+// destinations).  Transition: W_1 with b_1 as its bias row, W_2.
+void trans_pack_groups(const evo_trans_desc_t& d, const evo_trans_w_t& w, PackArgs* p1, PackArgs* p2) {
+  const int C = (int)d.c, HID = (int)(d.c * d.factor);
+  *p1 = PackArgs(); p1->K = C; p1->seg[0] = {w.w_1, w.b_1, HID}; p1->nseg = 1;
+  *p2 = PackArgs(); p2->K = HID; p2->seg[0] = {w.w_2, nullptr, C}; p2->nseg = 1;
+}
+// Outer product mean: W_a | W_b with their biases, the output projection.
+void opm_pack_groups(const evo_opm_desc_t& d, const evo_opm_w_t& w, PackArgs* pa, PackArgs* po) {
+  const int ch = (int)d.c_hidden;
+  *pa = PackArgs(); pa->K = (int)d.c_m; pa->seg[0] = {w.w_a, w.b_a, ch}; pa->seg[1] = {w.w_b, w.b_b, ch};
+  pa->nseg = 2;
+  *po = PackArgs(); po->K = ch * ch; po->seg[0] = {w.w_o, nullptr, (int)d.c_z}; po->nseg = 1;
+}
+// Triangle multiplication: a, b projections and gates with the output gate
+// (one GEMM), the output projection.
+void trimul_pack_groups(const evo_trimul_desc_t& d, const evo_trimul_w_t& w, PackArgs* pp, PackArgs* po) {
+  const int ch = (int)d.c_hidden, cz = (int)d.c_z;
+  *pp = PackArgs();
+  pp->K = cz;
+  pp->seg[0] = {w.w_ap, w.b_ap, ch};
+  pp->seg[1] = {w.w_ag, w.b_ag, ch};
+  pp->seg[2] = {w.w_bp, w.b_bp, ch};
+  pp->seg[3] = {w.w_bg, w.b_bg, ch};
+  pp->seg[4] = {w.w_g, w.b_g, cz};
+  pp->nseg = 5;
+  *po = PackArgs(); po->K = ch; po->seg[0] = {w.w_o, nullptr, cz}; po->nseg = 1;
+}
+
 // ============================================================== transition
 template <typename T>
 static void trans_carve(Arena& a, const evo_trans_desc_t& d, T** y, float** mean, float** rstd, T** h) {
@@ -22,9 +51,13 @@ evo_status_t trans_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   T* wt2 = ws.take_n<T>(C * HID);
   float* b1 = ws.take_n<float>(HID);
   if (c.dry) return EVO_OK;
-  PackArgs p1; p1.K = (int)C; p1.seg[0] = {w.w_1, w.b_1, (int)HID}; p1.nseg = 1; p1.dst_t = wt1; p1.bias = b1;
-  PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst_t = wt2;
+  PackArgs p1, p2;
+  trans_pack_groups(d, w, &p1, &p2);
+  p1.dst_t = wt1; p1.bias = b1;
+  p2.dst_t = wt2;
   EVO_TRY(pack_params<T>(c, {&p1, &p2}));
+  wt1 = (T*)p1.dst_t; b1 = p1.bias;
+  wt2 = (T*)p2.dst_t;
   EVO_TRY((ln_fwd<X, T>(c, x, d.rows, (int)C, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd)));
   {
     GemmArgs g;
@@ -61,9 +94,13 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
   T* dh = ws.take_n<T>(d.rows * HID);
   float* dy = ws.take_n<float>(d.rows * C);
   if (!c.dry) {
-    PackArgs p1; p1.K = (int)C; p1.seg[0] = {w.w_1, nullptr, (int)HID}; p1.nseg = 1; p1.dst = w1;
-    PackArgs p2; p2.K = (int)HID; p2.seg[0] = {w.w_2, nullptr, (int)C}; p2.nseg = 1; p2.dst = w2;
+    PackArgs p1, p2;
+    trans_pack_groups(d, w, &p1, &p2);
+    p1.dst = w1;
+    p2.dst = w2;
     EVO_TRY(pack_params<T>(c, {&p1, &p2}));
+    w1 = (T*)p1.dst;
+    w2 = (T*)p2.dst;
   }
   int off0 = 0, nC = (int)C, nH = (int)HID;
   float* ob2[1] = {dw.b_2};
@@ -134,10 +171,13 @@ evo_status_t opm_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   float* b_ab = ws.take_n<float>(2 * ch);
   T* wt_o = ws.take_n<T>(cz * ch2);
   if (c.dry) return EVO_OK;
-  PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, w.b_a, (int)ch}; pa.seg[1] = {w.w_b, w.b_b, (int)ch};
-  pa.nseg = 2; pa.dst_t = wt_ab; pa.bias = b_ab;
-  PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
+  PackArgs pa, po;
+  opm_pack_groups(d, w, &pa, &po);
+  pa.dst_t = wt_ab; pa.bias = b_ab;
+  po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, {&pa, &po}));
+  wt_ab = (T*)pa.dst_t; b_ab = pa.bias;
+  wt_o = (T*)po.dst_t;
   EVO_TRY((ln_fwd<X, T>(c, m, SR, (int)cm, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {  // a | b = mask * (y W + b)
     GemmArgs g;
@@ -198,10 +238,13 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
   constexpr int OPM_SPLIT = 4;
   float* dpart = ws.take_n<float>((size_t)OPM_SPLIT * SR * ch);
   if (!c.dry) {
-    PackArgs pa; pa.K = (int)cm; pa.seg[0] = {w.w_a, nullptr, (int)ch}; pa.seg[1] = {w.w_b, nullptr, (int)ch};
-    pa.nseg = 2; pa.dst = w_ab;
-    PackArgs po; po.K = (int)ch2; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst = w_o;
+    PackArgs pa, po;
+    opm_pack_groups(d, w, &pa, &po);
+    pa.dst = w_ab;
+    po.dst = w_o;
     EVO_TRY(pack_params<T>(c, {&pa, &po}));
+    w_ab = (T*)pa.dst;
+    w_o = (T*)po.dst;
   }
   int off0 = 0, ncz = (int)cz;
   float* obo[1] = {dw.b_o};
@@ -314,18 +357,15 @@ static evo_status_t trimul_fwd_chunked(const Ctx& c, Arena& ws, const evo_trimul
   T* x = ws.take_n<T>(CR * ch);
   T* xn = ws.take_n<T>(CR * ch);
   if (c.dry) return EVO_OK;
-  PackArgs pp;
-  pp.K = (int)cz;
-  pp.seg[0] = {w.w_ap, w.b_ap, (int)ch};
-  pp.seg[1] = {w.w_ag, w.b_ag, (int)ch};
-  pp.seg[2] = {w.w_bp, w.b_bp, (int)ch};
-  pp.seg[3] = {w.w_bg, w.b_bg, (int)ch};
-  pp.seg[4] = {w.w_g, w.b_g, (int)cz};
-  pp.nseg = 5;
+  PackArgs pp, po;
+  trimul_pack_groups(d, w, &pp, &po);
   pp.dst_t = wt_p;
   pp.bias = b_p;
-  PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
+  po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, {&pp, &po}));
+  wt_p = (T*)pp.dst_t;
+  b_p = pp.bias;
+  wt_o = (T*)po.dst_t;
   for (int64_t c0 = 0; c0 < R; c0 += C) {
     const int64_t p0 = c0 * R;
     EVO_TRY((ln_fwd<X, T>(c, z + p0 * cz, CR, (int)cz, w.ln_g, w.ln_b, d.ln_eps, y, mean, rstd)));
@@ -390,18 +430,15 @@ evo_status_t trimul_fwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   float* b_p = ws.take_n<float>(NP);
   T* wt_o = ws.take_n<T>(cz * ch);
   if (c.dry) return EVO_OK;
-  PackArgs pp;
-  pp.K = (int)cz;
-  pp.seg[0] = {w.w_ap, w.b_ap, (int)ch};
-  pp.seg[1] = {w.w_ag, w.b_ag, (int)ch};
-  pp.seg[2] = {w.w_bp, w.b_bp, (int)ch};
-  pp.seg[3] = {w.w_bg, w.b_bg, (int)ch};
-  pp.seg[4] = {w.w_g, w.b_g, (int)cz};
-  pp.nseg = 5;
+  PackArgs pp, po;
+  trimul_pack_groups(d, w, &pp, &po);
   pp.dst_t = wt_p;
   pp.bias = b_p;
-  PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o;
+  po.dst_t = wt_o;
   EVO_TRY(pack_params<T>(c, {&pp, &po}));
+  wt_p = (T*)pp.dst_t;
+  b_p = pp.bias;
+  wt_o = (T*)po.dst_t;
   EVO_TRY((ln_fwd<X, T>(c, z, P, (int)cz, w.ln_g, w.ln_b, d.ln_eps, S.y, S.mean, S.rstd)));
   {
     GemmArgs g;
@@ -470,17 +507,15 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   float* db = ws.take_n<float>(P * ch);
   float* dy = ws.take_n<float>(P * cz);
   if (!c.dry) {
-    PackArgs pp;
-    pp.K = (int)cz;
-    pp.seg[0] = {w.w_ap, nullptr, (int)ch};
-    pp.seg[1] = {w.w_ag, nullptr, (int)ch};
-    pp.seg[2] = {w.w_bp, nullptr, (int)ch};
-    pp.seg[3] = {w.w_bg, nullptr, (int)ch};
-    pp.seg[4] = {w.w_g, nullptr, (int)cz};
-    pp.nseg = 5;
+    PackArgs pp, po;
+    trimul_pack_groups(d, w, &pp, &po);
     pp.dst = w_p;
-    PackArgs po; po.K = (int)ch; po.seg[0] = {w.w_o, nullptr, (int)cz}; po.nseg = 1; po.dst_t = wt_o; po.dst = w_o;
+    po.dst_t = wt_o;
+    po.dst = w_o;
     EVO_TRY(pack_params<T>(c, {&pp, &po}));
+    w_p = (T*)pp.dst;
+    wt_o = (T*)po.dst_t;
+    w_o = (T*)po.dst;
     {  // t = LN_out(x) W_o + b_o
       GemmArgs g;
       g.M = P; g.N = cz; g.K = ch;

@@ -101,6 +101,36 @@ def test_block_fwd_rejects_small_workspace_and_misalignment():
     assert "aligned" in lib.evo_last_error().decode()
 
 
+@pytest.mark.parametrize("name", ["C0", "C1", "C3"])
+def test_saved_block_sizes_and_validation(name):
+    # the checkpoint-free pair: the state holds at least the nine activations;
+    # chunked descriptors have no state; aliased outputs and a short state
+    # buffer are refused before anything runs
+    A, lib = _lib()
+    from paper_2207_05477_amd import binding as B
+    cfg = synth.get(name)
+    d = B.block_desc(cfg)
+    sv = lib.evoformer_block_saved_bytes(ctypes.byref(d))
+    act = 2 if cfg.dtype == "bf16" else 4
+    assert sv >= (3 * cfg.n_seq * cfg.n_res * cfg.c_m + 6 * cfg.n_res ** 2 * cfg.c_z) * act
+    assert lib.evoformer_block_save_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD) > 0
+    # the saved state plus the saved backward's workspace is the checkpointed backward's workspace
+    # less the recomputation's scratch: never more than the two together
+    ck = lib.evoformer_block_workspace_bytes(ctypes.byref(d), A.EVO_PHASE_BWD)
+    assert sv < ck
+    d_chunk = B.block_desc(cfg, chunk=16)
+    assert lib.evoformer_block_saved_bytes(ctypes.byref(d_chunk)) == 0
+    w = A.BlockW()
+    for i, (sub, cls) in enumerate(A.BlockW._fields_):
+        setattr(w, sub, _full_weights(A, cls, i))
+    st = lib.evoformer_block_fwd_save(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), None, None,
+                                      _fake(1), _fake(4), _fake(5), sv, _fake(6), 1 << 40, None)
+    assert st == A.EVO_EINVAL and "alias" in lib.evo_last_error().decode()
+    st = lib.evoformer_block_fwd_save(ctypes.byref(d), ctypes.byref(w), _fake(1), _fake(2), None, None,
+                                      _fake(3), _fake(4), _fake(5), sv - 1, _fake(6), 1 << 40, None)
+    assert st == A.EVO_EWORKSPACE and "saved" in lib.evo_last_error().decode()
+
+
 def test_op_descriptor_validation():
     A, lib = _lib()
     from paper_2207_05477_amd import binding as B
