@@ -46,10 +46,17 @@ struct AttnGrad {
   float* dbias_part = nullptr;
   int64_t dbq = 0, dbk = 0;
   int64_t group = 1;             // batches summed per partial
+  // FP32 only: buffer of the logit gradients dS [b][h][q][k] (FP32,
+  // attn_bwd_ds_elems elements).  Set: the dK/dV kernel stores dS and dQ and
+  // the bias partials are taken from it; null: the dQ kernel recomputes them.
+  float* ds = nullptr;
 };
 
 template <typename T> evo_status_t attn_fwd(const Ctx& c, const AttnCore& a);
 template <typename T> evo_status_t attn_bwd(const Ctx& c, const AttnCore& a, const AttnGrad& g);
 template <typename T> int64_t attn_bwd_groups(const AttnCore& a);   // number of bias-gradient partial slices
+// Elements of the logit-gradient buffer (AttnGrad::ds) the backward of `a` uses,
+// 0 when it recomputes the logits in the dQ kernel instead.
+template <typename T> int64_t attn_bwd_ds_elems(const AttnCore& a);
 
 }  // namespace evo

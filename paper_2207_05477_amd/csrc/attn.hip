@@ -794,9 +794,10 @@ __global__ __launch_bounds__(256 * NB) __attribute__((amdgpu_waves_per_eu(4))) v
 // over the group's batches in registers, is written once as this group's
 // partial; the dQ accumulators of the group's batches stay in registers.
 // Batches per dQ workgroup: FP32 halves the group (its fragments are twice as
-// large; a larger group costs occupancy, measured slower).
+// large; a larger group costs occupancy, measured slower).  Groups of 8 at
+// head dims 8 and 16, and of 4 at head dim 64, spilled registers to scratch.
 template <typename T, int D> struct DqGroup {
-  static constexpr int GM = (D <= 16 ? 8 : 4) / (sizeof(T) == 2 ? 1 : 2);
+  static constexpr int GM = (D >= 64 ? 2 : 4) / (sizeof(T) == 2 ? 1 : 2);
 };
 
 template <typename T, int D, int BM>
@@ -1042,6 +1043,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
         dv[bi][dt] = contract64<T, D>(sOt + dr * F::TP, true, P, lg, dv[bi][dt]);
         dk[bi][dt] = contract64<T, D>(sQt + dr * F::TP, true, DS, lg, dk[bi][dt]);
       }
+      if constexpr (!F::BF) {
+        // the logit gradients for the dQ pass, through a buffer resource over
+        // this (batch, head) slice: query row and key in the lane's offset,
+        // the row step of (t, i) in the scalar offset on whole query tiles; on
+        // the last, partial tile the whole offset is in the vector operand,
+        // which the range check covers, so that rows past the end are dropped.
+        // A wave's store covers 16 consecutive keys (64 bytes) of one query row.
+        if (gr.ds && kok) {
+          const __amdgpu_buffer_rsrc_t rs =
+              buf_rsrc(gr.ds + (b * a.H + h) * a.Lq * a.Lk, (uint32_t)(a.Lq * a.Lk * 4));
+          const uint32_t vo = (uint32_t)(((qb0 + 4 * lg) * a.Lk + key) * 4), row = (uint32_t)(a.Lk * 4);
+          if (qb0 + KB <= a.Lq) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(DS[t][i]), rs, vo, (16 * t + i) * row, 0);
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(DS[t][i]), rs, vo + (16 * t + i) * row, 0, 0);
+          }
+        }
+      }
     }
   }
   if (!kok) return;
@@ -1058,6 +1085,104 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
         store4<T>(DK + d0, dk[bi][dt] * scale);
         store4<T>(DV + d0, dv[bi][dt]);
       }
+    }
+  }
+}
+
+// ============================================================== backward: dQ from stored logit gradients (FP32)
+// The FP32 backward keeps the logit gradients dS that the dK/dV kernel forms
+// and takes dQ = dS K / sqrt(c) and the bias-gradient partials from them, so
+// that the logits and dP, two of the three FP32 products of
+// attn_bwd_dq_kernel, are formed once per backward instead of twice.  Same
+// workgroups (64 queries of one head), batch groups and partial layout as
+// attn_bwd_dq_kernel; a lane reads its query's 16 dS values of a key tile as
+// four 16-byte vectors.
+template <int D>
+__global__ __launch_bounds__(256) void attn_bwd_dq_ds_kernel(AttnCore a, AttnGrad gr, float scale) {
+  using T = float;
+  using F = DF<T, D>;
+  constexpr int GM = DqGroup<T, D>::GM;
+  __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const WgCoord wg = xcd_coord();
+  const int h = wg.y;
+  const int64_t grp = wg.z;
+  const int64_t b0 = grp * gr.group;
+  const int64_t b1 = b0 + gr.group < a.nbatch ? b0 + gr.group : a.nbatch;
+  const int64_t qi = (int64_t)wg.x * 64 + wave * 16 + lr;
+  const bool qok = qi < a.Lq;
+  const bool dbias = gr.dbias_part != nullptr;
+  float* dbp = dbias ? gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk : nullptr;
+
+  zero_pad_rows<T, D>(sKt, tid);
+  f32x4 dq[GM][F::NDT];
+#pragma unroll
+  for (int bi = 0; bi < GM; ++bi)
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) dq[bi][dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
+    f32x4 dbacc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dbacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int bi = 0; bi < GM; ++bi) {
+      const int64_t b = b0 + bi;
+      if (b >= b1) break;
+      const T* K = (const T*)a.k + b * a.sb + h * D;
+      RowsStage<T, D, true> stK;
+      stK.load(K, a.sp, kb0, a.Lk, tid);
+      // dS of query qi at keys kb0 + 16 t + 4 lg + i (zeros past the ends)
+      const float* drow = gr.ds + ((b * a.H + h) * a.Lq + (qok ? qi : 0)) * a.Lk;
+      f32x4 ds[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t key = kb0 + 16 * t + 4 * lg;
+        if (qok && key + 3 < a.Lk) {
+          ds[t] = *(const f32x4*)(drow + key);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) ds[t][i] = qok && key + i < a.Lk ? drow[key + i] : 0.f;
+        }
+      }
+      __syncthreads();
+      stK.store(nullptr, sKt, tid);
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) dbacc[t] = dbacc[t] + ds[t];
+#pragma unroll
+      for (int dt = 0; dt < F::NDT; ++dt) {
+        const int dr = 16 * dt + lr;
+        dq[bi][dt] = contract64<T, D>(sKt + dr * F::TP, true, ds, lg, dq[bi][dt]);
+      }
+    }
+    // this group's bias-gradient partial for the tile (layout: dbq, dbk)
+    if (dbias && qok) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t key = kb0 + 16 * t + 4 * lg;
+        const int64_t off = qi * gr.dbq + key * gr.dbk;
+        if (gr.dbk == 1 && key + 3 < a.Lk && (off & 3) == 0) {
+          *(f32x4*)(dbp + off) = dbacc[t];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (key + i < a.Lk) dbp[off + i * gr.dbk] = dbacc[t][i];
+        }
+      }
+    }
+  }
+  if (!qok) return;
+#pragma unroll
+  for (int bi = 0; bi < GM; ++bi) {
+    const int64_t b = b0 + bi;
+    if (b >= b1) break;
+    T* DQ = (T*)gr.dq + b * gr.dsb + qi * gr.dsp + h * D;
+#pragma unroll
+    for (int dt = 0; dt < F::NDT; ++dt) {
+      const int d0 = 16 * dt + 4 * lg;
+      if (d0 < D) store4<T>(DQ + d0, dq[bi][dt] * scale);
     }
   }
 }
@@ -1190,7 +1315,11 @@ int64_t attn_bwd_groups(const AttnCore& a) {
   if (target < 1) target = 1;
   if (target > a.nbatch) target = a.nbatch;
   int64_t group = (a.nbatch + target - 1) / target;
-  const int64_t gmax = a.D <= 16 ? DqGroup<T, 16>::GM : DqGroup<T, 64>::GM;
+  // at most the group of the dQ kernel instance for this head dim
+  const int64_t gmax = a.D == 8    ? DqGroup<T, 8>::GM
+                       : a.D == 16 ? DqGroup<T, 16>::GM
+                       : a.D == 32 ? DqGroup<T, 32>::GM
+                                   : DqGroup<T, 64>::GM;
   if (group > gmax) group = gmax;
   return (a.nbatch + group - 1) / group;
 }
@@ -1201,6 +1330,8 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   const float sc = 1.0f / sqrtf((float)D);
   const int64_t ngroups = attn_bwd_groups<T>(a);
   g.group = (a.nbatch + ngroups - 1) / ngroups;
+  constexpr int gm = DqGroup<T, D>::GM;
+  EVO_CHECK_ARG(g.group <= gm, EVO_EINVAL, "attention backward: group of %lld batches > %d", (long long)g.group, gm);
   const size_t lds = 0;
   static const std::string n1 = kname<T, D>("attn_bwd_dq_kernel");
   static const std::string n2 = kname<T, D>("attn_bwd_dkdv_kernel");
@@ -1215,23 +1346,50 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
   // bias tiles: queries x keys in the dQ kernel, keys x queries in the dK/dV kernel
   const int bm1 = bias_mode(a.bias, a.bh, a.bq, a.bk, 0, a.Lq, a.Lk);
   const int bm2 = bias_mode(a.bias, a.bh, a.bk, a.bq, 0, a.Lk, a.Lq);
-#define EVO_DQ(BMV, _) \
-  EVO_LAUNCH(n1.c_str(), f1, b1, (attn_bwd_dq_kernel<T, D, BMV>), g1, dim3(256), lds, c.stream, a, g, sl2, sc)
-  EVO_BIAS_SWITCH(bm1, EVO_DQ, 0)
-#undef EVO_DQ
-  EVO_TRY(check_launch("attn_bwd_dq"));
   // batches per dK/dV workgroup: the bias tile is shared across them (one batch when there is no bias)
   int32_t kgroup = a.bias ? DkvGroup<D>::GM : 1;
   const int64_t kblocks = (a.Lk + 63) / 64;
   while (kgroup > 1 && kblocks * a.H * ((a.nbatch + kgroup - 1) / kgroup) < 512) kgroup /= 2;
   dim3 g2((unsigned)kblocks, (unsigned)a.H, (unsigned)((a.nbatch + kgroup - 1) / kgroup));
-#define EVO_DKDV(BMV, _)                                                                                  \
-  EVO_LAUNCH(n2.c_str(), f2, b2, (attn_bwd_dkdv_kernel<T, D, BMV>), g2, dim3(256), 0, c.stream, a, g, sl2, sc, \
-             kgroup)
-  EVO_BIAS_SWITCH(bm2, EVO_DKDV, 0)
+  auto dkdv = [&](double flops, double bytes) -> evo_status_t {
+#define EVO_DKDV(BMV, _)                                                                                        \
+  EVO_LAUNCH(n2.c_str(), flops, bytes, (attn_bwd_dkdv_kernel<T, D, BMV>), g2, dim3(256), 0, c.stream, a, g, sl2, \
+             sc, kgroup)
+    EVO_BIAS_SWITCH(bm2, EVO_DKDV, 0)
 #undef EVO_DKDV
-  return check_launch("attn_bwd_dkdv");
+    return check_launch("attn_bwd_dkdv");
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (g.ds) {
+      // dK, dV and the stored dS (dP formed here only), then dQ and the bias partials from dS
+      static const std::string n3 = kname<T, D>("attn_bwd_dq_ds_kernel");
+      const double sbytes = bh * ll * 4.0;
+      EVO_TRY(dkdv(f2 + 0.5 * f1, b2 + sbytes));
+      const double b3 = bh * ((double)a.Lk * D * 4 + (double)a.Lq * D * 4) + sbytes +
+                        (g.dbias_part ? (double)ngroups * a.H * ll * 4.0 : 0.0);
+      EVO_LAUNCH(n3.c_str(), 0.5 * f1, b3, (attn_bwd_dq_ds_kernel<D>), g1, dim3(256), 0, c.stream, a, g, sc);
+      return check_launch("attn_bwd_dq_ds");
+    }
+  }
+#define EVO_DQ(BMV, _) \
+  EVO_LAUNCH(n1.c_str(), f1, b1, (attn_bwd_dq_kernel<T, D, BMV>), g1, dim3(256), lds, c.stream, a, g, sl2, sc)
+  EVO_BIAS_SWITCH(bm1, EVO_DQ, 0)
+#undef EVO_DQ
+  EVO_TRY(check_launch("attn_bwd_dq"));
+  return dkdv(f2, b2);
 }
+
+template <typename T>
+int64_t attn_bwd_ds_elems(const AttnCore& a) {
+  // FP32 only (in BF16 the recomputed products are cheap and the stored FP32
+  // dS would double the kernels' memory traffic); up to 2 GiB of dS, and keys
+  // in whole 16-byte vectors
+  if (sizeof(T) != 4 || a.Lk % 4 != 0) return 0;
+  const int64_t n = a.nbatch * a.H * a.Lq * a.Lk;
+  return n * 4 <= (int64_t)1 << 31 ? n : 0;
+}
+template int64_t attn_bwd_ds_elems<float>(const AttnCore&);
+template int64_t attn_bwd_ds_elems<bf16>(const AttnCore&);
 
 template int64_t attn_bwd_groups<float>(const AttnCore&);
 template int64_t attn_bwd_groups<bf16>(const AttnCore&);

@@ -1148,11 +1148,13 @@ evo_status_t gemm(const Ctx& ctx, const GemmArgs& g) {
   if (g.big_tiles && g.M > 16) launch<T, 128, 128, 2, 2>(ctx, g);
   else if (g.M <= 16) launch<T, 16, 128, 1, 4>(ctx, g);
   else if (g.N <= 64 || g.M * g.N <= (int64_t)128 * 128 * 128) launch<T, 64, 64, 2, 2>(ctx, g);
-  // BF16: 128 x 64 tiles also for wide outputs when both operands are contiguous
-  // along k (twice the workgroups of the short-K projections, which are bound by
-  // memory latency: measured 9 % faster per launch at K = 128-256); a transposing
-  // operand, and FP32 (matrix-core bound), keep 128 x 128
-  else if (g.N <= 128 || (sizeof(T) == 2 && g.A.k_contig && g.B.k_contig)) launch<T, 128, 64, 2, 2>(ctx, g);
+  // 128 x 64 tiles also for wide outputs when both operands are contiguous
+  // along k, in BF16 (twice the workgroups of the short-K projections, which are
+  // bound by memory latency: measured 9 % faster per launch at K = 128-256) and
+  // in FP32 at K <= 128 (3-6 % faster there, slower at K >= 256); a transposing
+  // operand keeps 128 x 128
+  else if (g.N <= 128 || (g.A.k_contig && g.B.k_contig && (sizeof(T) == 2 || g.K <= 128)))
+    launch<T, 128, 64, 2, 2>(ctx, g);
   else launch<T, 128, 128, 2, 2>(ctx, g);
   return check_launch("gemm");
 }

@@ -98,12 +98,15 @@ evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, co
   if (hi <= lo) return EVO_OK;
   const int64_t N = hi - lo;
   // BF16: 128 x 128 tiles split for about 256 workgroups (at least 1024 rows
-  // per slice) when both extents allow; else 64 x 64 tiles for about 512
-  // (measured faster for FP32, whose k-tiles are half as deep)
+  // per slice) when both extents allow; else 64 x 64 tiles for about 1024
+  // (measured faster for FP32, whose k-tiles are half as deep).  FP32 at four
+  // workgroups per CU: the FP32 weight-gradient GEMMs of a C1 step took 1.84 ms
+  // split for 512 workgroups, 1.67 ms for 1024 (the partial sums they add cost
+  // 0.03 ms more); BF16 split for 512 gained nothing measurable
   const bool big = sizeof(T) == 2 && M >= 128 && N >= 128;
   const int64_t tm = big ? 128 : 64;
   const int64_t tiles = ((M + tm - 1) / tm) * ((N + tm - 1) / tm);
-  const int64_t target = big ? 256 : 512;
+  const int64_t target = big ? 256 : 1024;
   int64_t split = (target + tiles - 1) / tiles;
   int64_t maxsplit = rows / (big ? 1024 : 256) > 0 ? rows / (big ? 1024 : 256) : 1;
   if (split > maxsplit) split = maxsplit;

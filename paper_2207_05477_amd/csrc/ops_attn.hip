@@ -324,6 +324,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   float* dy = ws.take_n<float>(s.rows * s.cin);
   float* dbias = nullptr;
   float* dbias_part = nullptr;
+  float* ds = nullptr;   // FP32 logit gradients (see AttnGrad::ds)
   AttnCore a;
   int64_t ngroups = 0;
   if (!s.global) {
@@ -334,6 +335,8 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
       dbias_part = ws.take_n<float>((size_t)ngroups * s.H * a.Lq * a.Lk);
       dbias = ws.take_n<float>((size_t)s.H * a.Lq * a.Lk);
     }
+    const int64_t nds = attn_bwd_ds_elems<T>(a);
+    ds = nds ? ws.take_n<float>(nds) : nullptr;
   }
   const int64_t mark = ws.off;   // scratch below is reused by each step
   (void)mark;
@@ -377,6 +380,7 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     gr.dq = dqkvg; gr.dk = dqkvg + s.HC; gr.dv = dqkvg + 2 * s.HC;
     gr.dsb = a.sb; gr.dsp = a.sp;
     gr.dbias_part = dbias_part;
+    gr.ds = ds;
     // partials in the projection's row order: (q, k) -> pair entry (k, q) for the ending node
     const bool tend = s.kind == EVO_ATTN_TRI_END;
     gr.dbq = tend ? 1 : a.bq;
