@@ -295,7 +295,8 @@ evo_status_t evoformer_block_bwd(const evo_block_desc_t* desc, const evo_block_w
  * 288 GB of HBM).  evoformer_block_fwd_save computes the forward of
  * evoformer_block_fwd and keeps the block's state in `saved`: the dropout
  * multipliers, the packed parameters, the activations between sub-operations
- * and every sub-operation's saved tensors (evoformer_block_saved_bytes(desc)
+ * (with BF16, also the FP32 copies of m and z the block computes in) and every
+ * sub-operation's saved tensors (evoformer_block_saved_bytes(desc)
  * bytes, 16-byte aligned, owned by the caller; 0 for an invalid or chunked
  * desc).  evoformer_block_bwd_saved is evoformer_block_bwd without the
  * recomputation: it reads `saved` as the forward left it (the same desc, w,

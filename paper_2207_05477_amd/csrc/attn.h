@@ -46,7 +46,7 @@ struct AttnGrad {
   float* dbias_part = nullptr;
   int64_t dbq = 0, dbk = 0;
   int64_t group = 1;             // batches summed per partial
-  // FP32 only: buffer of the logit gradients dS [b][h][q][k] (FP32,
+  // FP32 only: buffer of the logit gradients dS, keys-major [b][h][k][q] (FP32,
   // attn_bwd_ds_elems elements).  Set: the dK/dV kernel stores dS and dQ and
   // the bias partials are taken from it; null: the dQ kernel recomputes them.
   float* ds = nullptr;

@@ -1044,28 +1044,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
         dk[bi][dt] = contract64<T, D>(sQt + dr * F::TP, true, DS, lg, dk[bi][dt]);
       }
       if constexpr (!F::BF) {
-        // the logit gradients for the dQ pass, through a buffer resource over
-        // this (batch, head) slice: query row and key in the lane's offset,
-        // the row step of (t, i) in the scalar offset on whole query tiles; on
-        // the last, partial tile the whole offset is in the vector operand,
-        // which the range check covers, so that rows past the end are dropped.
-        // A wave's store covers 16 consecutive keys (64 bytes) of one query row.
+        // the logit gradients for the dQ pass, keys-major ([b][h][k][q]): a
+        // lane's four consecutive queries of tile t as one 16-byte store, a
+        // wave's store 64 contiguous bytes of each of its 16 keys' rows; the
+        // last, partial query tile stores element by element
         if (gr.ds && kok) {
-          const __amdgpu_buffer_rsrc_t rs =
-              buf_rsrc(gr.ds + (b * a.H + h) * a.Lq * a.Lk, (uint32_t)(a.Lq * a.Lk * 4));
-          const uint32_t vo = (uint32_t)(((qb0 + 4 * lg) * a.Lk + key) * 4), row = (uint32_t)(a.Lk * 4);
+          float* drow = gr.ds + ((b * a.H + h) * a.Lk + key) * a.Lq + qb0 + 4 * lg;
           if (qb0 + KB <= a.Lq) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(DS[t][i]), rs, vo, (16 * t + i) * row, 0);
+            for (int t = 0; t < 4; ++t) *(f32x4*)(drow + 16 * t) = DS[t];
           } else {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
               for (int i = 0; i < 4; ++i)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(DS[t][i]), rs, vo + (16 * t + i) * row, 0, 0);
+                if (qb0 + 16 * t + 4 * lg + i < a.Lq) drow[16 * t + i] = DS[t][i];
           }
         }
       }
@@ -1095,14 +1088,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
 // that the logits and dP, two of the three FP32 products of
 // attn_bwd_dq_kernel, are formed once per backward instead of twice.  Same
 // workgroups (64 queries of one head), batch groups and partial layout as
-// attn_bwd_dq_kernel; a lane reads its query's 16 dS values of a key tile as
-// four 16-byte vectors.
+// attn_bwd_dq_kernel; the dS tile (keys-major, as the dK/dV kernel stores it)
+// comes in as 16-byte vectors and through LDS to the lanes' query columns.
 template <int D>
 __global__ __launch_bounds__(256) void attn_bwd_dq_ds_kernel(AttnCore a, AttnGrad gr, float scale) {
   using T = float;
   using F = DF<T, D>;
   constexpr int GM = DqGroup<T, D>::GM;
+  constexpr int SP = KB + 4;   // LDS pitch of the dS tile (keys x queries)
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
+  __shared__ __attribute__((aligned(16))) float sDs[KB * SP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const WgCoord wg = xcd_coord();
@@ -1110,10 +1105,14 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_ds_kernel(AttnCore a, AttnGra
   const int64_t grp = wg.z;
   const int64_t b0 = grp * gr.group;
   const int64_t b1 = b0 + gr.group < a.nbatch ? b0 + gr.group : a.nbatch;
-  const int64_t qi = (int64_t)wg.x * 64 + wave * 16 + lr;
+  const int64_t q0 = (int64_t)wg.x * 64;
+  const int64_t qi = q0 + wave * 16 + lr;
   const bool qok = qi < a.Lq;
   const bool dbias = gr.dbias_part != nullptr;
   float* dbp = dbias ? gr.dbias_part + (grp * a.H + h) * a.Lq * a.Lk : nullptr;
+  // the thread's four 16-byte pieces of a dS tile: key row tr + 16 u, queries tc..tc+3
+  const int tr = tid >> 4, tc = (tid & 15) * 4;
+  const bool cok = q0 + tc + 3 < a.Lq;
 
   zero_pad_rows<T, D>(sKt, tid);
   f32x4 dq[GM][F::NDT];
@@ -1133,22 +1132,32 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_ds_kernel(AttnCore a, AttnGra
       const T* K = (const T*)a.k + b * a.sb + h * D;
       RowsStage<T, D, true> stK;
       stK.load(K, a.sp, kb0, a.Lk, tid);
-      // dS of query qi at keys kb0 + 16 t + 4 lg + i (zeros past the ends)
-      const float* drow = gr.ds + ((b * a.H + h) * a.Lq + (qok ? qi : 0)) * a.Lk;
-      f32x4 ds[4];
+      // the dS tile (keys kb0.., queries q0..): zeros past either end
+      const float* dsb = gr.ds + (b * a.H + h) * a.Lk * a.Lq;
+      f32x4 piece[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t key = kb0 + 16 * t + 4 * lg;
-        if (qok && key + 3 < a.Lk) {
-          ds[t] = *(const f32x4*)(drow + key);
+      for (int u = 0; u < 4; ++u) {
+        const int64_t key = kb0 + tr + 16 * u;
+        const float* src = dsb + (key < a.Lk ? key : 0) * a.Lq + q0 + tc;
+        if (key < a.Lk && cok) {
+          piece[u] = *(const f32x4*)src;
         } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) ds[t][i] = qok && key + i < a.Lk ? drow[key + i] : 0.f;
+          for (int i = 0; i < 4; ++i) piece[u][i] = key < a.Lk && q0 + tc + i < a.Lq ? src[i] : 0.f;
         }
       }
       __syncthreads();
       stK.store(nullptr, sKt, tid);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) *(f32x4*)(sDs + (tr + 16 * u) * SP + tc) = piece[u];
       __syncthreads();
+      // dS of query qi at keys kb0 + 16 t + 4 lg + i
+      const int ql = wave * 16 + lr;
+      f32x4 ds[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ds[t][i] = sDs[(16 * t + 4 * lg + i) * SP + ql];
 #pragma unroll
       for (int t = 0; t < 4; ++t) dbacc[t] = dbacc[t] + ds[t];
 #pragma unroll
@@ -1382,9 +1391,9 @@ static evo_status_t launch_bwd(const Ctx& c, const AttnCore& a, AttnGrad g) {
 template <typename T>
 int64_t attn_bwd_ds_elems(const AttnCore& a) {
   // FP32 only (in BF16 the recomputed products are cheap and the stored FP32
-  // dS would double the kernels' memory traffic); up to 2 GiB of dS, and keys
-  // in whole 16-byte vectors
-  if (sizeof(T) != 4 || a.Lk % 4 != 0) return 0;
+  // dS would double the kernels' memory traffic); up to 2 GiB of dS, and
+  // queries in whole 16-byte vectors
+  if (sizeof(T) != 4 || a.Lq % 4 != 0) return 0;
   const int64_t n = a.nbatch * a.H * a.Lq * a.Lk;
   return n * 4 <= (int64_t)1 << 31 ? n : 0;
 }

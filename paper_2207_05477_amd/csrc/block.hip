@@ -362,8 +362,9 @@ evo_status_t block_fwd_op(const Ctx& c, Arena& ws, const evo_block_desc_t& d, co
 }
 
 // The training pass in the activation type T: FP32 residual streams inside
-// (BF16 inputs converted into the workspace; the converted inputs are formed
-// again, identically, by a BLK_SAVED call).
+// (BF16 inputs converted into FP32: in the workspace for a checkpointed
+// backward, in the saved state, ahead of everything else the state holds, for
+// a BLK_SAVE call, whose BLK_SAVED backward takes them from there).
 template <typename T>
 static evo_status_t block_train_op(const Ctx& c, Arena& ws, Arena& kp, int mode, const evo_block_desc_t& d,
                                    const evo_block_w_t& w, const T* m, const T* z, const float* mm, const float* pm,
@@ -373,12 +374,15 @@ static evo_status_t block_train_op(const Ctx& c, Arena& ws, Arena& kp, int mode,
   } else {
     const int64_t SRc = d.n_seq * d.n_res * d.c_m, RRc = d.n_res * d.n_res * d.c_z;
     const bool bwd = mode != BLK_SAVE;
-    float* mx = ws.take_n<float>(SRc);
-    float* zx = ws.take_n<float>(RRc);
+    Arena& ia = mode == BLK_FULL ? ws : kp;
+    float* mx = ia.take_n<float>(SRc);
+    float* zx = ia.take_n<float>(RRc);
     float* dmx = bwd ? ws.take_n<float>(SRc) : nullptr;
     float* dzx = bwd ? ws.take_n<float>(RRc) : nullptr;
-    EVO_TRY((convert_elems<T, float>(c, m, mx, SRc)));
-    EVO_TRY((convert_elems<T, float>(c, z, zx, RRc)));
+    if (mode != BLK_SAVED) {
+      EVO_TRY((convert_elems<T, float>(c, m, mx, SRc)));
+      EVO_TRY((convert_elems<T, float>(c, z, zx, RRc)));
+    }
     if (bwd) {
       EVO_TRY((convert_elems<T, float>(c, dmo, dmx, SRc)));
       EVO_TRY((convert_elems<T, float>(c, dzo, dzx, RRc)));
