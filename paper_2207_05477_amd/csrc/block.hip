@@ -320,12 +320,10 @@ static evo_status_t block_train_x(const Ctx& c0, Arena& ws, Arena& kp, int mode,
     ws.off = sc.end();
     return EVO_OK;
   }
-  // backward in reverse order; the pair gradient is updated in place in dz
-  if (!c.dry) {
-    EVO_TRY(copy_elems<X>(c, dzo, dz, RRc));
-    EVO_TRY(copy_elems<X>(c, dmo, dm, SRc));
-  }
-  EVO_STEPS(8, "pair_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, dz, dz, dw.pair_trans)));
+  // backward in reverse order; the pair gradient moves from dz_out into dz at
+  // the pair transition and is then updated in place in dz
+  if (!c.dry) EVO_TRY(copy_elems<X>(c, dmo, dm, SRc));
+  EVO_STEPS(8, "pair_trans.bwd", (trans_bwd_op<T, X>(c, a, s, d_tz, w.pair_trans, z5, dzo, dz, dw.pair_trans)));
   EVO_STEPS(7, "tri_att_end.bwd", (attn_bwd_op<T, X>(c, a, s, d_tae, w.tri_att_end, z4, nullptr, pm, dz, dz, nullptr, dw.tri_att_end, &bd.tae)));
   EVO_STEPS(6, "tri_att_start.bwd", (attn_bwd_op<T, X>(c, a, s, d_tas, w.tri_att_start, z3, nullptr, pm, dz, dz, nullptr, dw.tri_att_start, &bd.tas)));
   EVO_STEPS(5, "tri_mul_in.bwd", (trimul_bwd_op<T, X>(c, a, s, d_mi, w.tri_mul_in, z2, pm, dz, dz, dw.tri_mul_in, &bd.tmi)));

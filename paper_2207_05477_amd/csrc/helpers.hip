@@ -470,6 +470,34 @@ evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, 
   return reduce_segments(c, part, nb, 1, span, rs, true);
 }
 
+template <typename T, typename X>
+evo_status_t colsum_as_compute(const Ctx& c, Arena& ws, const X* dout, int64_t rows, int C, float* out,
+                               const T** dst) {
+  const int off = 0;
+  float* const outs[1] = {out};
+  if constexpr (std::is_same<T, X>::value) {
+    *dst = dout;
+    return colsum_segments<X>(c, ws, dout, rows, C, 1, &off, &C, outs);
+  } else {
+    T* b = ws.take_n<T>(rows * C);
+    *dst = b;
+    float* part = ws.take_n<float>((size_t)colsum_partials(rows) * C);
+    if (c.dry) return EVO_OK;
+    if (!out) return convert_elems<X, T>(c, dout, b, rows * C);
+    int nb = 0;
+    EVO_TRY(colsum_convert_partial(c, dout, rows, C, b, part, &nb));
+    RedSegs rs;
+    rs.nseg = 1; rs.off[0] = 0; rs.n[0] = C; rs.out[0] = out;
+    return reduce_segments(c, part, nb, 1, C, rs, true);
+  }
+}
+template evo_status_t colsum_as_compute<float, float>(const Ctx&, Arena&, const float*, int64_t, int, float*,
+                                                      const float**);
+template evo_status_t colsum_as_compute<bf16, float>(const Ctx&, Arena&, const float*, int64_t, int, float*,
+                                                     const bf16**);
+template evo_status_t colsum_as_compute<bf16, bf16>(const Ctx&, Arena&, const bf16*, int64_t, int, float*,
+                                                    const bf16**);
+
 #define EVO_INST_H(T)                                                                              \
   template evo_status_t wgrad<T>(const Ctx&, Arena&, const T*, int64_t, const T*, int64_t, int64_t, \
                                  int64_t, int64_t, float*);                                        \

@@ -90,6 +90,10 @@ template <typename T>
 evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
                             int* nblk);
 int64_t colsum_partials(int64_t rows);
+// colsum_partial of a dense FP32 x[rows][C] that also writes x converted to
+// BF16 into copy[rows][C] (one pass over x).
+evo_status_t colsum_convert_partial(const Ctx& c, const float* x, int64_t rows, int C, bf16* copy, float* part,
+                                   int* nblk);
 // out += column sums (convenience: partial + reduce, scratch from `part`).
 template <typename T>
 evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,

@@ -1078,9 +1078,10 @@ __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ x, in
 // cover 8 * TPR consecutive columns of a row, so the 256 threads stride over
 // the block's CS_ROWS rows 256 / TPR rows at a time; the row groups are summed
 // through LDS in a fixed order.
-template <typename T, int TPR>
+template <typename T, int TPR, typename TC = T>
 __global__ __launch_bounds__(256) void colsum_vec_kernel(const T* __restrict__ x, int64_t rows, int C,
-                                                         int64_t ld, float* __restrict__ part) {
+                                                         int64_t ld, float* __restrict__ part,
+                                                         TC* __restrict__ copy = nullptr) {
   constexpr int RG = 256 / TPR;
   __shared__ float red[RG][TPR * 8 + 4];
   const int tc = threadIdx.x & (TPR - 1), tr = threadIdx.x / TPR;
@@ -1104,6 +1105,12 @@ __global__ __launch_bounds__(256) void colsum_vec_kernel(const T* __restrict__ x
         const float f = rb + j * RG < r1 ? 1.f : 0.f;
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = fmaf(v[j][i], f, s[i]);
+      }
+      if constexpr (!std::is_same<TC, T>::value) {
+        // the rows converted to the narrower type on the way (dense rows of C)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (rb + j * RG < r1) st8(copy + (rb + j * RG) * C + c0, v[j]);
       }
     }
 #pragma unroll
@@ -1137,6 +1144,26 @@ evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64
   EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>),
              dim3((unsigned)((C + 63) / 64), (unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
   return check_launch("colsum");
+}
+
+evo_status_t colsum_convert_partial(const Ctx& c, const float* x, int64_t rows, int C, bf16* copy, float* part,
+                                   int* nblk) {
+  *nblk = (int)colsum_partials(rows);
+  if (c.dry || rows == 0) return EVO_OK;
+  if (!(C % 8 == 0 && aligned16(x) && aligned16(copy))) {
+    EVO_TRY((convert_elems<float, bf16>(c, x, copy, rows * C)));
+    return colsum_partial<float>(c, x, rows, C, C, part, nblk);
+  }
+  const double bytes = (double)rows * C * (4.0 + 2.0);
+  const unsigned nb = (unsigned)*nblk;
+  const char* nm = "colsum_convert_kernel";
+  if (C <= 64)
+    EVO_LAUNCH(nm, 0.0, bytes, (colsum_vec_kernel<float, 8, bf16>), dim3((unsigned)((C + 63) / 64), nb), dim3(256), 0, c.stream, x, rows, C, (int64_t)C, part, copy);
+  else if (C <= 128)
+    EVO_LAUNCH(nm, 0.0, bytes, (colsum_vec_kernel<float, 16, bf16>), dim3(1, nb), dim3(256), 0, c.stream, x, rows, C, (int64_t)C, part, copy);
+  else
+    EVO_LAUNCH(nm, 0.0, bytes, (colsum_vec_kernel<float, 32, bf16>), dim3((unsigned)((C + 255) / 256), nb), dim3(256), 0, c.stream, x, rows, C, (int64_t)C, part, copy);
+  return check_launch("colsum_convert");
 }
 
 template <typename T>

@@ -59,6 +59,12 @@ inline const T* as_compute(const Ctx& c, Arena& ws, const X* p, int64_t n, evo_s
   }
 }
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+// The bias gradient of an output projection, out += column sums of dout
+// [rows][C] (null out: none), and dout as a compute-type tensor (*dst): with a
+// wider residual type both come from one pass over dout.
+template <typename T, typename X>
+evo_status_t colsum_as_compute(const Ctx& c, Arena& ws, const X* dout, int64_t rows, int C, float* out,
+                               const T** dst);
 
 // ---- training dropout of a residual update (dropout.hip)
 // Multiplier of update element (row r, channel c): tbl[((r / div) % mod) * C + c]

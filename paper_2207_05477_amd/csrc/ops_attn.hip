@@ -312,9 +312,9 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY(dropout_apply<X>(c, dout, dd, s.rows, (int)s.cin, *drop));
     dout = dd;
   }
-  evo_status_t cst;
-  const T* dout_t = as_compute<T, X>(c, ws, dout, s.rows * s.cin, &cst);
-  EVO_TRY(cst);
+  // the output bias gradient and dout in the compute type, in one pass
+  const T* dout_t = nullptr;
+  EVO_TRY((colsum_as_compute<T, X>(c, ws, dout, s.rows, (int)s.cin, dw.b_o, &dout_t)));
   T* w_qkvg = ws.take_n<T>((int64_t)s.cin * s.NQ);     // [c_in][NQ]
   T* w_o = ws.take_n<T>((int64_t)s.HC * s.cin);        // [HC][c_in]
   float* dgo = ws.take_n<float>(s.rows * s.HC);   // FP32: consumed by the gate backward only
@@ -354,9 +354,6 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   // output projection
   {
     ProfTag t_("out_proj");
-    int off = 0, n = (int)s.cin;
-    float* outs[1] = {dw.b_o};
-    EVO_TRY(colsum_segments<X>(c, ws, dout, s.rows, s.cin, 1, &off, &n, outs));
     EVO_TRY(wgrad<T>(c, ws, S.go, s.HC, dout_t, s.cin, s.rows, s.HC, s.cin, dw.w_o));
     GemmArgs g;
     g.M = s.rows; g.N = s.HC; g.K = s.cin;

@@ -85,9 +85,9 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
                           const evo_trans_w_t& dw) {
   T *y, *h; float *mean, *rstd;
   trans_carve<T>(sv, d, &y, &mean, &rstd, &h);
-  evo_status_t cst;
-  const T* dout_t = as_compute<T, X>(c, ws, dout, d.rows * d.c, &cst);
-  EVO_TRY(cst);
+  // the second bias's gradient and dout in the compute type, in one pass
+  const T* dout_t = nullptr;
+  EVO_TRY((colsum_as_compute<T, X>(c, ws, dout, d.rows, (int)d.c, dw.b_2, &dout_t)));
   const int64_t C = d.c, HID = d.c * d.factor;
   T* w1 = ws.take_n<T>(C * HID);     // [C][HID]
   T* w2 = ws.take_n<T>(HID * C);     // [HID][C]
@@ -102,9 +102,7 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
     w1 = (T*)p1.dst;
     w2 = (T*)p2.dst;
   }
-  int off0 = 0, nC = (int)C, nH = (int)HID;
-  float* ob2[1] = {dw.b_2};
-  EVO_TRY(colsum_segments<X>(c, ws, dout, d.rows, C, 1, &off0, &nC, ob2));
+  int off0 = 0, nH = (int)HID;
   EVO_TRY(wgrad<T>(c, ws, h, HID, dout_t, C, d.rows, HID, C, dw.w_2));
   {
     GemmArgs g;
@@ -222,9 +220,9 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
                         const evo_opm_w_t& dw) {
   OpmSaved<T> S;
   S.carve(sv, d);
-  evo_status_t cst;
-  const T* dz = as_compute<T, X>(c, ws, dz_x, d.n_res * d.n_res * d.c_z, &cst);
-  EVO_TRY(cst);
+  // the output bias gradient and dz in the compute type, in one pass
+  const T* dz = nullptr;
+  EVO_TRY((colsum_as_compute<T, X>(c, ws, dz_x, d.n_res * d.n_res, (int)d.c_z, dw.b_o, &dz)));
   const int64_t S_ = d.n_seq, R = d.n_res, SR = S_ * R, RR = R * R, ch = d.c_hidden, cm = d.c_m,
                 cz = d.c_z, ch2 = ch * ch;
   const int sh = ilog2(ch);
@@ -246,9 +244,6 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
     w_ab = (T*)pa.dst;
     w_o = (T*)po.dst;
   }
-  int off0 = 0, ncz = (int)cz;
-  float* obo[1] = {dw.b_o};
-  EVO_TRY(colsum_segments<X>(c, ws, dz_x, RR, cz, 1, &off0, &ncz, obo));
   EVO_TRY(wgrad<T>(c, ws, S.on, ch2, dz, cz, RR, ch2, cz, dw.w_o));
   if (!c.dry) {
     {  // dO = (dz W_o^T) / (eps + n_ij)

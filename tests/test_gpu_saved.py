@@ -24,12 +24,18 @@ torch.set_num_threads(min(32, os.cpu_count() or 8))
 DROP = (1234567890123, 7)
 
 
+SMALL_EXTRA = SMALL.replace(name="small_extra", extra_msa=True, msa_heads=4, msa_head_dim=8)
+
+
 @pytest.mark.parametrize("cfg,dtype,variant", [
     (SMALL, "f32", ""),
     (SMALL, "bf16", "opm_first+dropout"),
+    (SMALL_EXTRA, "f32", "dropout"),
     (get("C1"), "f32", ""),
     (get("C1"), "bf16", "dropout"),
-], ids=["small_f32", "small_bf16_opm_first_dropout", "c1_f32", "c1_bf16_dropout"])
+    (get("C3"), "bf16", ""),
+], ids=["small_f32", "small_bf16_opm_first_dropout", "small_extra_f32_dropout", "c1_f32", "c1_bf16_dropout",
+        "c3_bf16"])
 def test_saved_block_equals_checkpointed(cfg, dtype, variant):
     from paper_2207_05477_amd import binding as B
     cfg = cfg.replace(n_blocks=1, opm_first="opm_first" in variant)
