@@ -67,6 +67,10 @@ struct GemmArgs {
   int32_t big_tiles = 0;   // 1: 128 x 128 tiles whatever M x N (split-K problems with few tiles)
   GemmOperand A, B;        // A rows = m, B rows = n
   GemmEpilogue epi;
+  // Optional: column sums of B over the reduction, colsum[z * N + n] =
+  // sum_k B[n][k] over slice z's k range (split-K) or problem z's (batch),
+  // FP32.  Plain operand layouts with B row-contiguous (not along k) only.
+  float* colsum = nullptr;
 };
 
 template <typename T>

@@ -586,6 +586,22 @@ struct PlainLoader {
         regs[S][q] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[0] + q * krow, so, 0);
     }
   }
+  // Adds slot S's values to the thread's column sums (row-contiguous layout:
+  // VEC consecutive rows r0.. at KB reduction indices), with the tail-tile
+  // indices at krem and beyond counted as zeros, as store() writes them.
+  template <int S>
+  EVO_DEV void colsum_acc(float* cs, int tid, int krem) const {
+    if constexpr (!KC) {
+      if (tid >= NBLK) return;
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        if (krem < BK && kk_[0] + q >= krem) continue;
+        const T* e = (const T*)&regs[S][q];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) cs[i] += to_f32(e[i]);
+      }
+    }
+  }
   // Slot S to LDS; `krem` = reduction indices left from the tile start: on a
   // tail tile (krem < BK) the indices beyond it are stored as zeros.
   template <int S>
@@ -701,11 +717,17 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   const int kspan = kend - kbeg;
+  // column sums of B (workgroups of the first row block only)
+  const bool csum = !KCB && g.colsum != nullptr && m0 == 0;
+  float cs[VEC];
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) cs[i] = 0.f;
   if (nk > 0) {
     la.template load<0>(0);
     lb.template load<0>(0);
     la.template store<0>(lds[0], tid, kspan);
     lb.template store<0>(lds[0] + BM * LDK, tid, kspan);
+    if (csum) lb.template colsum_acc<0>(cs, tid, kspan);
   }
   if (nk > 1) {
     la.template load<0>(1);
@@ -766,6 +788,7 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
         const int krem = kspan - (kt + 1) * BK;
         la.template store<0>(lds[0], tid, krem);
         lb.template store<0>(lds[0] + BM * LDK, tid, krem);
+        if (csum) lb.template colsum_acc<0>(cs, tid, krem);
         if (kt + 2 < nk) {
           la.template load<0>(kt + 2);
           lb.template load<0>(kt + 2);
@@ -785,6 +808,7 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
         const int krem = kspan - (kt + 1) * BK;
         la.template store<0>(dst, tid, krem);
         lb.template store<0>(dst + BM * LDK, tid, krem);
+        if (csum) lb.template colsum_acc<0>(cs, tid, krem);
         if (kt + 2 < nk) {
           la.template load<0>(kt + 2);
           lb.template load<0>(kt + 2);
@@ -795,6 +819,25 @@ void gemm_plain_kernel(GemmArgs g, PlainInfo pi, int32_t ntn) {
     }
   }
 
+  if (csum) {
+    // threads of one column block (tid % RB) hold partial sums over their k
+    // offsets (tid / RB): summed through the idle LDS in a fixed order
+    using LB = PlainLoader<T, BN, KCB>;
+    float* red = (float*)&lds[0][0];
+    __syncthreads();
+    if (tid < LB::NBLK) {
+      const int rb = tid % LB::RB, kb = tid / LB::RB;
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) red[kb * BN + rb * VEC + i] = cs[i];
+    }
+    __syncthreads();
+    if (tid < BN && n0 + tid < N) {
+      float t = 0.f;
+      for (int kb = 0; kb < LB::NBLK / LB::RB; ++kb) t += red[kb * BN + tid];
+      g.colsum[(int64_t)z * N + n0 + tid] = t;
+    }
+    __syncthreads();
+  }
   // epilogue straight from the accumulators: lane holds n..n+3 of row m
   const GemmEpilogue& e = g.epi;
   const int64_t zo = (int64_t)z * e.batch;
@@ -1145,6 +1188,13 @@ evo_status_t gemm(const Ctx& ctx, const GemmArgs& g) {
   if (!operand_ok(g.A, g.M, VEC, "A") || !operand_ok(g.B, g.N, VEC, "B")) return EVO_ESHAPE;
   if (!g.epi.out) { set_error("gemm: null output"); return EVO_EINVAL; }
   if (g.split_k > 1 && !g.epi.out_f32) { set_error("gemm: split-K needs FP32 partials"); return EVO_EINVAL; }
+  if (g.colsum) {
+    PlainInfo pi;
+    if (g.B.k_contig || !plain_info<T>(g, pi)) {
+      set_error("gemm: column sums need plain operand layouts with B row-contiguous");
+      return EVO_EINVAL;
+    }
+  }
   if (g.big_tiles && g.M > 16) launch<T, 128, 128, 2, 2>(ctx, g);
   else if (g.M <= 16) launch<T, 16, 128, 1, 4>(ctx, g);
   else if (g.N <= 64 || g.M * g.N <= (int64_t)128 * 128 * 128) launch<T, 64, 64, 2, 2>(ctx, g);

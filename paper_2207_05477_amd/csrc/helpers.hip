@@ -87,7 +87,7 @@ void prof_end(int slot, hipStream_t s) {
 template <typename T>
 evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
                             int64_t rows, int64_t M, int nseg, const int* seg_off, const int* seg_n,
-                            float* const* dW) {
+                            float* const* dW, float* const* dB) {
   // the span covers every segment (null outputs included): a size query with
   // null gradient pointers carves the same scratch as a real call
   int lo = 1 << 30, hi = 0;
@@ -113,24 +113,42 @@ evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, co
   if (split < 1) split = 1;
   const bool direct = split == 1 && nseg == 1;
   float* part = direct ? nullptr : ws.take_n<float>((size_t)split * M * N);
+  // bias gradients: the column sums of dY, taken by the GEMM from the dY tiles
+  // it loads anyway (one FP32 row per slice), then reduced like dW
+  float* cpart = dB ? ws.take_n<float>((size_t)split * N) : nullptr;
   if (c.dry) return EVO_OK;
-  bool any = false;
-  for (int s = 0; s < nseg; ++s) any = any || dW[s];
-  if (!any) return EVO_OK;
+  bool any = false, anyb = false;
+  for (int s = 0; s < nseg; ++s) {
+    any = any || dW[s];
+    anyb = anyb || (dB && dB[s]);
+  }
+  if (!any && !anyb) return EVO_OK;
   GemmArgs g;
   g.M = M; g.N = N; g.K = rows;
   g.split_k = (int)split;
   g.big_tiles = big ? 1 : 0;
   g.A = op_colmajor(X, ldx);
   g.B = op_colmajor(dY + lo, ldy);
+  g.colsum = anyb ? cpart : nullptr;
   if (direct) {   // single slice, single segment: accumulate straight into dW
-    g.epi = epi_rowmajor(dW[0], N, true);
+    g.epi = epi_rowmajor(dW[0] ? dW[0] : part, N, true);
     g.epi.accumulate = 1;
-    return gemm<T>(c, g);
+  } else {
+    g.epi = epi_rowmajor(part, N, true);
+    g.epi.batch = M * N;
   }
-  g.epi = epi_rowmajor(part, N, true);
-  g.epi.batch = M * N;
+  if (direct && !dW[0]) {
+    set_error("wgrad: a bias gradient without its weight gradient");
+    return EVO_EINVAL;
+  }
   EVO_TRY(gemm<T>(c, g));
+  if (anyb) {
+    RedSegs rb;
+    rb.nseg = nseg;
+    for (int s = 0; s < nseg; ++s) { rb.off[s] = seg_off[s] - lo; rb.n[s] = seg_n[s]; rb.out[s] = dB[s]; }
+    EVO_TRY(reduce_segments(c, cpart, split, 1, N, rb, true));
+  }
+  if (direct || !any) return EVO_OK;
   RedSegs rs;
   rs.nseg = nseg;
   for (int s = 0; s < nseg; ++s) { rs.off[s] = seg_off[s] - lo; rs.n[s] = seg_n[s]; rs.out[s] = dW[s]; }
@@ -139,9 +157,9 @@ evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, co
 
 template <typename T>
 evo_status_t wgrad(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
-                   int64_t rows, int64_t M, int64_t N, float* dW) {
+                   int64_t rows, int64_t M, int64_t N, float* dW, float* const* dB) {
   const int off = 0, n = (int)N;
-  return wgrad_segments<T>(c, ws, X, ldx, dY, ldy, rows, M, 1, &off, &n, &dW);
+  return wgrad_segments<T>(c, ws, X, ldx, dY, ldy, rows, M, 1, &off, &n, &dW, dB);
 }
 
 // ============================================================== pair-bias projection
@@ -444,71 +462,15 @@ evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int 
 }
 
 // ============================================================== segmented column sums
-template <typename T>
-evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, int64_t ld, int nseg,
-                             const int* seg_off, const int* seg_n, float* const* outs) {
-  // the span covers every segment (null outputs included) so that a size
-  // query with null gradient pointers carves the same scratch as a real call
-  int lo = 1 << 30, hi = 0;
-  for (int s = 0; s < nseg; ++s) {
-    lo = seg_off[s] < lo ? seg_off[s] : lo;
-    hi = seg_off[s] + seg_n[s] > hi ? seg_off[s] + seg_n[s] : hi;
-  }
-  if (hi <= lo) return EVO_OK;
-  const int span = hi - lo;
-  const int64_t nblk = colsum_partials(rows);
-  float* part = ws.take_n<float>((size_t)nblk * span);
-  if (c.dry || rows == 0) return EVO_OK;
-  bool any = false;
-  for (int s = 0; s < nseg; ++s) any = any || outs[s];
-  if (!any) return EVO_OK;
-  int nb = 0;
-  EVO_TRY(colsum_partial<T>(c, x + lo, rows, span, ld, part, &nb));
-  RedSegs rs;
-  rs.nseg = nseg;
-  for (int s = 0; s < nseg; ++s) { rs.off[s] = seg_off[s] - lo; rs.n[s] = seg_n[s]; rs.out[s] = outs[s]; }
-  return reduce_segments(c, part, nb, 1, span, rs, true);
-}
-
-template <typename T, typename X>
-evo_status_t colsum_as_compute(const Ctx& c, Arena& ws, const X* dout, int64_t rows, int C, float* out,
-                               const T** dst) {
-  const int off = 0;
-  float* const outs[1] = {out};
-  if constexpr (std::is_same<T, X>::value) {
-    *dst = dout;
-    return colsum_segments<X>(c, ws, dout, rows, C, 1, &off, &C, outs);
-  } else {
-    T* b = ws.take_n<T>(rows * C);
-    *dst = b;
-    float* part = ws.take_n<float>((size_t)colsum_partials(rows) * C);
-    if (c.dry) return EVO_OK;
-    if (!out) return convert_elems<X, T>(c, dout, b, rows * C);
-    int nb = 0;
-    EVO_TRY(colsum_convert_partial(c, dout, rows, C, b, part, &nb));
-    RedSegs rs;
-    rs.nseg = 1; rs.off[0] = 0; rs.n[0] = C; rs.out[0] = out;
-    return reduce_segments(c, part, nb, 1, C, rs, true);
-  }
-}
-template evo_status_t colsum_as_compute<float, float>(const Ctx&, Arena&, const float*, int64_t, int, float*,
-                                                      const float**);
-template evo_status_t colsum_as_compute<bf16, float>(const Ctx&, Arena&, const float*, int64_t, int, float*,
-                                                     const bf16**);
-template evo_status_t colsum_as_compute<bf16, bf16>(const Ctx&, Arena&, const bf16*, int64_t, int, float*,
-                                                    const bf16**);
-
 #define EVO_INST_H(T)                                                                              \
   template evo_status_t wgrad<T>(const Ctx&, Arena&, const T*, int64_t, const T*, int64_t, int64_t, \
-                                 int64_t, int64_t, float*);                                        \
+                                 int64_t, int64_t, float*, float* const*);                         \
   template evo_status_t wgrad_segments<T>(const Ctx&, Arena&, const T*, int64_t, const T*, int64_t, \
                                           int64_t, int64_t, int, const int*, const int*,            \
-                                          float* const*);                                          \
+                                          float* const*, float* const*);                           \
   template evo_status_t rowproj<T>(const Ctx&, const T*, int64_t, int, const float*, int, float*); \
   template evo_status_t rowproj_bwd<T>(const Ctx&, Arena&, const T*, int64_t, int, const float*,   \
                                        int, const float*, float*, bool, float*);                   \
-  template evo_status_t colsum_segments<T>(const Ctx&, Arena&, const T*, int64_t, int64_t, int,     \
-                                           const int*, const int*, float* const*);
 
 EVO_INST_H(float)
 EVO_INST_H(bf16)

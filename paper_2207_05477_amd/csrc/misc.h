@@ -85,20 +85,6 @@ evo_status_t with_batched_reductions(const Ctx& c, F&& f) {
 // Two outputs from one [n][2C] partial buffer (LayerNorm gamma / beta).
 evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C, float* out_a,
                               float* out_b);
-// part[blk][C] = column sums of x[rows][C] (row pitch ld) over the rows of block blk.
-template <typename T>
-evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
-                            int* nblk);
-int64_t colsum_partials(int64_t rows);
-// colsum_partial of a dense FP32 x[rows][C] that also writes x converted to
-// BF16 into copy[rows][C] (one pass over x).
-evo_status_t colsum_convert_partial(const Ctx& c, const float* x, int64_t rows, int C, bf16* copy, float* part,
-                                   int* nblk);
-// out += column sums (convenience: partial + reduce, scratch from `part`).
-template <typename T>
-evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
-                        float* out);
-
 // Parameter packing: up to 5 FP32 segments W_i[K][n_i] concatenated along n.
 struct PackSeg { const float* w; const float* bias; int32_t n; };
 struct PackArgs {

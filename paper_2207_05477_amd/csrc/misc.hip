@@ -1051,128 +1051,6 @@ evo_status_t reduce_partials2(const Ctx& c, const float* part, int64_t n, int C,
   return reduce_segments(c, part, n, 1, 2 * C, s, true);
 }
 
-// Column sums over blocks of CS_ROWS rows.  A workgroup owns 64 columns x
-// CS_ROWS rows (grid: column tiles x row blocks); its 256 threads are 64
-// columns x 4 row groups, reduced through LDS in a fixed order.
-constexpr int CS_ROWS = 256;
-int64_t colsum_partials(int64_t rows) { return (rows + CS_ROWS - 1) / CS_ROWS; }
-
-template <typename T>
-__global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ x, int64_t rows, int C,
-                                                     int64_t ld, float* __restrict__ part) {
-  __shared__ float red[4][64];
-  const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
-  const int cc = blockIdx.x * 64 + tc;
-  const int64_t r0 = (int64_t)blockIdx.y * CS_ROWS;
-  const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
-  float s = 0.f;
-  if (cc < C)
-    for (int64_t r = r0 + tr; r < r1; r += 4) s += to_f32(x[r * ld + cc]);
-  red[tr][tc] = s;
-  __syncthreads();
-  if (tr == 0 && cc < C)
-    part[(int64_t)blockIdx.y * C + cc] = (red[0][tc] + red[1][tc]) + (red[2][tc] + red[3][tc]);
-}
-
-// Vectorised form (C % 8 == 0, ld % 8 == 0, 16-byte aligned x): TPR threads
-// cover 8 * TPR consecutive columns of a row, so the 256 threads stride over
-// the block's CS_ROWS rows 256 / TPR rows at a time; the row groups are summed
-// through LDS in a fixed order.
-template <typename T, int TPR, typename TC = T>
-__global__ __launch_bounds__(256) void colsum_vec_kernel(const T* __restrict__ x, int64_t rows, int C,
-                                                         int64_t ld, float* __restrict__ part,
-                                                         TC* __restrict__ copy = nullptr) {
-  constexpr int RG = 256 / TPR;
-  __shared__ float red[RG][TPR * 8 + 4];
-  const int tc = threadIdx.x & (TPR - 1), tr = threadIdx.x / TPR;
-  const int c0 = (blockIdx.x * TPR + tc) * 8;
-  const int64_t r0 = (int64_t)blockIdx.y * CS_ROWS;
-  const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
-  float s[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) s[i] = 0.f;
-  // four rows per lane in flight: rows past r1 read row r1 - 1 and count 0
-  if (c0 < C)
-    for (int64_t rb = r0 + tr; rb < r1; rb += 4 * RG) {
-      float v[4][8];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t r = rb + j * RG;
-        ld8(x + (r < r1 ? r : r1 - 1) * ld + c0, v[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float f = rb + j * RG < r1 ? 1.f : 0.f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) s[i] = fmaf(v[j][i], f, s[i]);
-      }
-      if constexpr (!std::is_same<TC, T>::value) {
-        // the rows converted to the narrower type on the way (dense rows of C)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (rb + j * RG < r1) st8(copy + (rb + j * RG) * C + c0, v[j]);
-      }
-    }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) red[tr][tc * 8 + i] = s[i];
-  __syncthreads();
-  for (int e = threadIdx.x; e < TPR * 8; e += 256) {
-    const int cc = blockIdx.x * TPR * 8 + e;
-    if (cc >= C) continue;
-    float t = 0.f;
-    for (int q = 0; q < RG; ++q) t += red[q][e];
-    part[(int64_t)blockIdx.y * C + cc] = t;
-  }
-}
-
-template <typename T>
-evo_status_t colsum_partial(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
-                            int* nblk) {
-  *nblk = (int)colsum_partials(rows);
-  if (c.dry || rows == 0) return EVO_OK;
-  if (C % 8 == 0 && ld % 8 == 0 && aligned16(x)) {
-    const double bytes = (double)rows * C * sizeof(T);
-    const unsigned nb = (unsigned)*nblk;
-    if (C <= 64)
-      EVO_LAUNCH(EVO_KNAME("colsum_vec_kernel", T), 0.0, bytes, (colsum_vec_kernel<T, 8>), dim3((unsigned)((C + 63) / 64), nb), dim3(256), 0, c.stream, x, rows, C, ld, part);
-    else if (C <= 128)
-      EVO_LAUNCH(EVO_KNAME("colsum_vec_kernel", T), 0.0, bytes, (colsum_vec_kernel<T, 16>), dim3(1, nb), dim3(256), 0, c.stream, x, rows, C, ld, part);
-    else
-      EVO_LAUNCH(EVO_KNAME("colsum_vec_kernel", T), 0.0, bytes, (colsum_vec_kernel<T, 32>), dim3((unsigned)((C + 255) / 256), nb), dim3(256), 0, c.stream, x, rows, C, ld, part);
-    return check_launch("colsum");
-  }
-  EVO_LAUNCH(EVO_KNAME("colsum_kernel", T), 0.0, (double)rows * C * sizeof(T), (colsum_kernel<T>),
-             dim3((unsigned)((C + 63) / 64), (unsigned)*nblk), dim3(256), 0, c.stream, x, rows, C, ld, part);
-  return check_launch("colsum");
-}
-
-evo_status_t colsum_convert_partial(const Ctx& c, const float* x, int64_t rows, int C, bf16* copy, float* part,
-                                   int* nblk) {
-  *nblk = (int)colsum_partials(rows);
-  if (c.dry || rows == 0) return EVO_OK;
-  if (!(C % 8 == 0 && aligned16(x) && aligned16(copy))) {
-    EVO_TRY((convert_elems<float, bf16>(c, x, copy, rows * C)));
-    return colsum_partial<float>(c, x, rows, C, C, part, nblk);
-  }
-  const double bytes = (double)rows * C * (4.0 + 2.0);
-  const unsigned nb = (unsigned)*nblk;
-  const char* nm = "colsum_convert_kernel";
-  if (C <= 64)
-    EVO_LAUNCH(nm, 0.0, bytes, (colsum_vec_kernel<float, 8, bf16>), dim3((unsigned)((C + 63) / 64), nb), dim3(256), 0, c.stream, x, rows, C, (int64_t)C, part, copy);
-  else if (C <= 128)
-    EVO_LAUNCH(nm, 0.0, bytes, (colsum_vec_kernel<float, 16, bf16>), dim3(1, nb), dim3(256), 0, c.stream, x, rows, C, (int64_t)C, part, copy);
-  else
-    EVO_LAUNCH(nm, 0.0, bytes, (colsum_vec_kernel<float, 32, bf16>), dim3((unsigned)((C + 255) / 256), nb), dim3(256), 0, c.stream, x, rows, C, (int64_t)C, part, copy);
-  return check_launch("colsum_convert");
-}
-
-template <typename T>
-evo_status_t colsum_add(const Ctx& c, const T* x, int64_t rows, int C, int64_t ld, float* part,
-                        float* out) {
-  int nb = 0;
-  EVO_TRY(colsum_partial<T>(c, x, rows, C, ld, part, &nb));
-  return reduce_partials(c, part, nb, C, C, out, true);
-}
 
 // ============================================================== packing / fill
 // Up to PACK_MAX parameter groups in one launch: blocks [start_g, start_{g+1})
@@ -1741,9 +1619,6 @@ evo_status_t opm_norm(const Ctx& c, const float* mask, int64_t S, int64_t R, flo
                                   const float*, int64_t, int, const T*, bool, T*, float*, int*);   \
   template evo_status_t ln_bwd_cm<T>(const Ctx&, const T*, const float*, const float*,             \
                                      const float*, const float*, int64_t, int, T*, float*, int*);  \
-  template evo_status_t colsum_partial<T>(const Ctx&, const T*, int64_t, int, int64_t, float*,     \
-                                          int*);                                                   \
-  template evo_status_t colsum_add<T>(const Ctx&, const T*, int64_t, int, int64_t, float*, float*); \
   template evo_status_t opm_dab_reduce<T>(const Ctx&, const float*, int, int64_t, int64_t, int,       \
                                           const float*, T*, int);                                  \
   template evo_status_t pack_params<T>(const Ctx&, std::initializer_list<PackArgs*>);              \

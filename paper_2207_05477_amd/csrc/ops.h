@@ -12,16 +12,20 @@
 namespace evo {
 
 // ---- helpers shared by the ops
-// dW[M][N] += X^T dY over `rows` rows; X[row][m] (pitch ldx), dY[row][n] (pitch ldy).
+// dW[M][N] += X^T dY over `rows` rows; X[row][m] (pitch ldx), dY[row][n] (pitch ldy);
+// with dB (a pointer to one output, itself nullable) also the bias gradient
+// dB[0][n] += sum over rows of dY, from the same GEMM.
 template <typename T>
 evo_status_t wgrad(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
-                   int64_t rows, int64_t M, int64_t N, float* dW);
+                   int64_t rows, int64_t M, int64_t N, float* dW, float* const* dB = nullptr);
 // Segments of one weight-gradient GEMM: dW_s[M][n_s] += X^T dY[:, off_s : off_s + n_s]
-// for each s (one GEMM over the span of all segments, one segmented reduction).
+// for each s (one GEMM over the span of all segments, one segmented reduction),
+// and with dB the bias gradients dB_s[n] += column sums of the same dY columns
+// (null entries skipped).
 template <typename T>
 evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, const T* dY, int64_t ldy,
                             int64_t rows, int64_t M, int nseg, const int* seg_off, const int* seg_n,
-                            float* const* dW);
+                            float* const* dW, float* const* dB = nullptr);
 // out[h][row] = sum_c x[row][c] W[c][h]  (H <= 16), FP32 out.
 template <typename T>
 evo_status_t rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float* W, int H, float* out);
@@ -29,11 +33,6 @@ evo_status_t rowproj(const Ctx& c, const T* x, int64_t rows, int C, const float*
 template <typename T>
 evo_status_t rowproj_bwd(const Ctx& c, Arena& ws, const T* x, int64_t rows, int C, const float* W,
                          int H, const float* dout, float* dx, bool accumulate, float* dW);
-// Column sums of x[rows][ld] restricted to segments, accumulated into outs[i] (+=).
-template <typename T>
-evo_status_t colsum_segments(const Ctx& c, Arena& ws, const T* x, int64_t rows, int64_t ld,
-                             int nseg, const int* seg_off, const int* seg_n, float* const* outs);
-
 inline int ilog2(int64_t v) { int s = 0; while ((1LL << s) < v) ++s; return s; }
 
 // Residual-stream type X (x, out, d_out, d_x) may be wider than the compute
@@ -59,12 +58,6 @@ inline const T* as_compute(const Ctx& c, Arena& ws, const X* p, int64_t n, evo_s
   }
 }
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-// The bias gradient of an output projection, out += column sums of dout
-// [rows][C] (null out: none), and dout as a compute-type tensor (*dst): with a
-// wider residual type both come from one pass over dout.
-template <typename T, typename X>
-evo_status_t colsum_as_compute(const Ctx& c, Arena& ws, const X* dout, int64_t rows, int C, float* out,
-                               const T** dst);
 
 // ---- training dropout of a residual update (dropout.hip)
 // Multiplier of update element (row r, channel c): tbl[((r / div) % mod) * C + c]

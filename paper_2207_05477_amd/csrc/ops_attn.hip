@@ -312,9 +312,9 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
     EVO_TRY(dropout_apply<X>(c, dout, dd, s.rows, (int)s.cin, *drop));
     dout = dd;
   }
-  // the output bias gradient and dout in the compute type, in one pass
-  const T* dout_t = nullptr;
-  EVO_TRY((colsum_as_compute<T, X>(c, ws, dout, s.rows, (int)s.cin, dw.b_o, &dout_t)));
+  evo_status_t cst;
+  const T* dout_t = as_compute<T, X>(c, ws, dout, s.rows * s.cin, &cst);
+  EVO_TRY(cst);
   T* w_qkvg = ws.take_n<T>((int64_t)s.cin * s.NQ);     // [c_in][NQ]
   T* w_o = ws.take_n<T>((int64_t)s.HC * s.cin);        // [HC][c_in]
   float* dgo = ws.take_n<float>(s.rows * s.HC);   // FP32: consumed by the gate backward only
@@ -354,7 +354,8 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   // output projection
   {
     ProfTag t_("out_proj");
-    EVO_TRY(wgrad<T>(c, ws, S.go, s.HC, dout_t, s.cin, s.rows, s.HC, s.cin, dw.w_o));
+    float* const ob[1] = {dw.b_o};
+    EVO_TRY(wgrad<T>(c, ws, S.go, s.HC, dout_t, s.cin, s.rows, s.HC, s.cin, dw.w_o, ob));
     GemmArgs g;
     g.M = s.rows; g.N = s.HC; g.K = s.cin;
     g.A = op_rowmajor(dout_t, s.cin);
@@ -391,14 +392,12 @@ evo_status_t attn_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_attn_desc
   // gate bias and projection weights
   {
     ProfTag t_("in_proj");
-    int off = (int)(s.NQ - s.HC), n = s.HC;
-    float* outs[1] = {dw.b_g};
-    EVO_TRY(colsum_segments<T>(c, ws, dqkvg, s.rows, s.NQ, 1, &off, &n, outs));
     const int kv = s.global ? s.D : s.HC;
     const int woff[4] = {0, s.HC, s.HC + kv, (int)(s.NQ - s.HC)};
     const int wn[4] = {s.HC, kv, kv, s.HC};
     float* const wout[4] = {dw.w_q, dw.w_k, dw.w_v, dw.w_g};
-    EVO_TRY(wgrad_segments<T>(c, ws, S.y, s.cin, dqkvg, s.NQ, s.rows, s.cin, 4, woff, wn, wout));
+    float* const bout[4] = {nullptr, nullptr, nullptr, dw.b_g};
+    EVO_TRY(wgrad_segments<T>(c, ws, S.y, s.cin, dqkvg, s.NQ, s.rows, s.cin, 4, woff, wn, wout, bout));
     GemmArgs g;
     g.M = s.rows; g.N = s.cin; g.K = s.NQ;
     g.A = op_rowmajor(dqkvg, s.NQ);

@@ -85,9 +85,9 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
                           const evo_trans_w_t& dw) {
   T *y, *h; float *mean, *rstd;
   trans_carve<T>(sv, d, &y, &mean, &rstd, &h);
-  // the second bias's gradient and dout in the compute type, in one pass
-  const T* dout_t = nullptr;
-  EVO_TRY((colsum_as_compute<T, X>(c, ws, dout, d.rows, (int)d.c, dw.b_2, &dout_t)));
+  evo_status_t cst;
+  const T* dout_t = as_compute<T, X>(c, ws, dout, d.rows * d.c, &cst);
+  EVO_TRY(cst);
   const int64_t C = d.c, HID = d.c * d.factor;
   T* w1 = ws.take_n<T>(C * HID);     // [C][HID]
   T* w2 = ws.take_n<T>(HID * C);     // [HID][C]
@@ -102,8 +102,8 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
     w1 = (T*)p1.dst;
     w2 = (T*)p2.dst;
   }
-  int off0 = 0, nH = (int)HID;
-  EVO_TRY(wgrad<T>(c, ws, h, HID, dout_t, C, d.rows, HID, C, dw.w_2));
+  float* const ob2[1] = {dw.b_2};
+  EVO_TRY(wgrad<T>(c, ws, h, HID, dout_t, C, d.rows, HID, C, dw.w_2, ob2));
   {
     GemmArgs g;
     g.M = d.rows; g.N = HID; g.K = C;
@@ -113,9 +113,8 @@ evo_status_t trans_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trans_de
     g.epi.relu_ref = h; g.epi.r_m = HID; g.epi.r_n = 1;
     if (!c.dry) EVO_TRY(gemm<T>(c, g));
   }
-  float* ob1[1] = {dw.b_1};
-  EVO_TRY(colsum_segments<T>(c, ws, dh, d.rows, HID, 1, &off0, &nH, ob1));
-  EVO_TRY(wgrad<T>(c, ws, y, C, dh, HID, d.rows, C, HID, dw.w_1));
+  float* const ob1[1] = {dw.b_1};
+  EVO_TRY(wgrad<T>(c, ws, y, C, dh, HID, d.rows, C, HID, dw.w_1, ob1));
   {
     GemmArgs g;
     g.M = d.rows; g.N = C; g.K = HID;
@@ -220,9 +219,9 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
                         const evo_opm_w_t& dw) {
   OpmSaved<T> S;
   S.carve(sv, d);
-  // the output bias gradient and dz in the compute type, in one pass
-  const T* dz = nullptr;
-  EVO_TRY((colsum_as_compute<T, X>(c, ws, dz_x, d.n_res * d.n_res, (int)d.c_z, dw.b_o, &dz)));
+  evo_status_t cst;
+  const T* dz = as_compute<T, X>(c, ws, dz_x, d.n_res * d.n_res * d.c_z, &cst);
+  EVO_TRY(cst);
   const int64_t S_ = d.n_seq, R = d.n_res, SR = S_ * R, RR = R * R, ch = d.c_hidden, cm = d.c_m,
                 cz = d.c_z, ch2 = ch * ch;
   const int sh = ilog2(ch);
@@ -244,7 +243,8 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
     w_ab = (T*)pa.dst;
     w_o = (T*)po.dst;
   }
-  EVO_TRY(wgrad<T>(c, ws, S.on, ch2, dz, cz, RR, ch2, cz, dw.w_o));
+  float* const obo[1] = {dw.b_o};
+  EVO_TRY(wgrad<T>(c, ws, S.on, ch2, dz, cz, RR, ch2, cz, dw.w_o, obo));
   if (!c.dry) {
     {  // dO = (dz W_o^T) / (eps + n_ij)
       GemmArgs g;
@@ -284,13 +284,11 @@ evo_status_t opm_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_opm_desc_t
       EVO_TRY(opm_dab_reduce<T>(c, dpart, OPM_SPLIT, S_, R, (int)ch, mask, dab, (int)ch));
     }
   }
-  int offs[2] = {0, (int)ch}, ns[2] = {(int)ch, (int)ch};
-  float* obab[2] = {dw.b_a, dw.b_b};
-  EVO_TRY(colsum_segments<T>(c, ws, dab, SR, 2 * ch, 2, offs, ns, obab));
   {
     const int woff[2] = {0, (int)ch}, wn[2] = {(int)ch, (int)ch};
     float* const wout[2] = {dw.w_a, dw.w_b};
-    EVO_TRY(wgrad_segments<T>(c, ws, S.y, cm, dab, 2 * ch, SR, cm, 2, woff, wn, wout));
+    float* const bout[2] = {dw.b_a, dw.b_b};
+    EVO_TRY(wgrad_segments<T>(c, ws, S.y, cm, dab, 2 * ch, SR, cm, 2, woff, wn, wout, bout));
   }
   if (!c.dry) {
     GemmArgs g;
@@ -522,10 +520,8 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
     }
     EVO_TRY((trimul_gate_bwd<T, X>(c, P, (int)ch, (int)cz, dzo, t, S.raw + 4 * ch, NP, dt, draw)));
   }
-  int off0 = 0, ncz = (int)cz;
-  float* obo[1] = {dw.b_o};
-  EVO_TRY(colsum_segments<T>(c, ws, dt, P, cz, 1, &off0, &ncz, obo));
-  EVO_TRY(wgrad<T>(c, ws, S.xn, ch, dt, cz, P, ch, cz, dw.w_o));
+  float* const obo[1] = {dw.b_o};
+  EVO_TRY(wgrad<T>(c, ws, S.xn, ch, dt, cz, P, ch, cz, dw.w_o, obo));
   if (!c.dry) {
     GemmArgs g;
     g.M = P; g.N = ch; g.K = cz;
@@ -575,12 +571,11 @@ evo_status_t trimul_bwd_op(const Ctx& c, Arena& ws, Arena& sv, const evo_trimul_
   }
   int offs[5] = {0, (int)ch, (int)(2 * ch), (int)(3 * ch), (int)(4 * ch)};
   int ns[5] = {(int)ch, (int)ch, (int)ch, (int)ch, (int)cz};
-  float* obp[5] = {dw.b_ap, dw.b_ag, dw.b_bp, dw.b_bg, dw.b_g};
-  EVO_TRY(colsum_segments<T>(c, ws, draw, P, NP, 5, offs, ns, obp));
+  float* const obp[5] = {dw.b_ap, dw.b_ag, dw.b_bp, dw.b_bg, dw.b_g};
   float* owp[5] = {dw.w_ap, dw.w_ag, dw.w_bp, dw.w_bg, dw.w_g};
   {
     ProfTag t_("wgrad_proj");
-    EVO_TRY(wgrad_segments<T>(c, ws, S.y, cz, draw, NP, P, cz, 5, offs, ns, owp));
+    EVO_TRY(wgrad_segments<T>(c, ws, S.y, cz, draw, NP, P, cz, 5, offs, ns, owp, obp));
   }
   if (!c.dry) {
     GemmArgs g;
