@@ -103,7 +103,9 @@ evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, co
   // workgroups per CU: the FP32 weight-gradient GEMMs of a C1 step took 1.84 ms
   // split for 512 workgroups, 1.67 ms for 1024 (the partial sums they add cost
   // 0.03 ms more); BF16 split for 512 gained nothing measurable
-  const bool big = sizeof(T) == 2 && M >= 128 && N >= 128;
+  // (BF16 outputs of at most 256 x 256 on 64 x 64 tiles too: 28-30 -> 15-20 us
+  // per C1 launch; the larger ones measured slower there)
+  const bool big = sizeof(T) == 2 && M >= 128 && N >= 128 && M * N > 256 * 256;
   const int64_t tm = big ? 128 : 64;
   const int64_t tiles = ((M + tm - 1) / tm) * ((N + tm - 1) / tm);
   const int64_t target = big ? 256 : 1024;
