@@ -978,6 +978,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
 #pragma unroll
     for (int dt = 0; dt < F::NDT; ++dt) { dk[bi][dt] = f32x4{0.f, 0.f, 0.f, 0.f}; dv[bi][dt] = dk[bi][dt]; }
 
+  // one batch per workgroup: its key and value fragments and the key's mask
+  // stay in registers across the query tiles
+  typename F::Frag kf1[F::NKS], vf1[F::NKS];
+  bool kmasked1 = false;
+  if constexpr (GM == 1) {
+    kmasked1 = kok && a.mask && a.mask[b0 * a.mb + key * a.mk] == 0.f;
+    load_dfrag<T, D>((const T*)a.k + b0 * a.sb + h * D + key * a.sp, lg, kok, kf1);
+    load_dfrag<T, D>((const T*)a.v + b0 * a.sb + h * D + key * a.sp, lg, kok, vf1);
+  }
   for (int64_t qb0 = 0; qb0 < a.Lq; qb0 += KB) {
 #pragma unroll
     for (int bi = 0; bi < GM; ++bi) {
@@ -987,7 +996,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
       const T* K = (const T*)a.k + b * a.sb + h * D;
       const T* V = (const T*)a.v + b * a.sb + h * D;
       const T* DO = (const T*)gr.dctx + b * a.osb + h * D;
-      const bool kmasked = kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
+      const bool kmasked = GM == 1 ? kmasked1 : kok && a.mask && a.mask[b * a.mb + key * a.mk] == 0.f;
       // a masked key's logit is the replacement value, a key past the end
       // (its lane's results are discarded) gets -inf so that P stays finite
       const bool krep = kmasked || !kok;
@@ -1005,8 +1014,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
         mv = a.st_max[si]; iv = a.st_inv[si]; dvv = gr.Dsum[si];
       }
       typename F::Frag kf[F::NKS], vf[F::NKS];
-      load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
-      load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
+      if constexpr (GM == 1) {
+#pragma unroll
+        for (int ks = 0; ks < F::NKS; ++ks) { kf[ks] = kf1[ks]; vf[ks] = vf1[ks]; }
+      } else {
+        load_dfrag<T, D>(K + key * a.sp, lg, kok, kf);
+        load_dfrag<T, D>(V + key * a.sp, lg, kok, vf);
+      }
       __syncthreads();
       stQ.store(sQ, sQt, tid);
       stO.store(sO, sOt, tid);
