@@ -810,6 +810,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   __shared__ __attribute__((aligned(16))) T sKt[F::DR * F::TP];
   __shared__ __attribute__((aligned(16))) float sB[64 * BP];
   __shared__ __attribute__((aligned(16))) float sKa[KB];
+  // BF16 at head dims up to 32: the query and context-gradient rows of the
+  // group's batches, staged in LDS once, since they are the same for every key tile
+  constexpr bool QO_LDS = F::BF && D <= 32;
+  __shared__ __attribute__((aligned(16))) T sQO[QO_LDS ? 2 * GM * KB * F::DP : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const WgCoord wg = xcd_coord();
@@ -832,6 +836,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 #pragma unroll
     for (int dt = 0; dt < F::NDT; ++dt) dq[bi][dt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  if constexpr (QO_LDS) {
+#pragma unroll
+    for (int bi = 0; bi < GM; ++bi) {
+      const int64_t b = b0 + bi;
+      if (b >= b1) break;
+      RowsStage<T, D, false> sq, so;
+      sq.load((const T*)a.q + b * a.sb + h * D, a.sp, q0, a.Lq, tid);
+      so.load((const T*)gr.dctx + b * a.osb + h * D, a.osp, q0, a.Lq, tid);
+      sq.store(sQO + (2 * bi) * KB * F::DP, nullptr, tid);
+      so.store(sQO + (2 * bi + 1) * KB * F::DP, nullptr, tid);
+    }
+  }
   for (int64_t kb0 = 0; kb0 < a.Lk; kb0 += KB) {
     f32x4 dbacc[4];
 #pragma unroll
@@ -864,8 +880,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         kadd = (in && !(mask && mask[(kb0 + tid) * a.mk] == 0.f)) ? 0.f : -INFINITY;
       }
       typename F::Frag qf[F::NKS], of[F::NKS];
-      load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
-      load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
+      if constexpr (!QO_LDS) {
+        load_dfrag<T, D>(Q + qi * a.sp, lg, qok, qf);
+        load_dfrag<T, D>(DO + qi * a.osp, lg, qok, of);
+      }
       // queries past the end: mrow = +inf and irow = 0 give dS = 0 exactly
       float mrow = INFINITY, irow = 0.f, drow = 0.f;
       if (qok) {
@@ -881,6 +899,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
       if (BM != BIAS_NONE && bi == 0) stB.store(sB, tid);
       if (tid < KB) sKa[tid] = kadd;
       __syncthreads();
+      if constexpr (QO_LDS) {   // (rows past the end were staged as zeros)
+        load_dfrag<T, D>(sQO + (2 * bi) * KB * F::DP + qloc * F::DP, lg, true, qf);
+        load_dfrag<T, D>(sQO + (2 * bi + 1) * KB * F::DP + qloc * F::DP, lg, true, of);
+      }
       // dS = P (dP - D); exactly 0 for masked keys, keys past the end and
       // queries past the end (see kadd, mrow, irow)
       f32x4 ds[4];
