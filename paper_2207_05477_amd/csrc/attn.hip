@@ -968,10 +968,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 // bias tile (keys x queries) is staged once for the group.  GM = 1: measured
 // on gfx950, the registers of more batches cost more occupancy than the shared
 // bias tile saves.
+// BF16 requests four waves per SIMD (head dim 32: 127 registers, 81 -> 74 us per
+// row-attention launch at N_seq = 128, N_res = 256); FP32 needs 160 and keeps three.
 template <int D> struct DkvGroup { static constexpr int GM = 1; };
 
 template <typename T, int D, int BM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 ? 4 : 3))) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                             float scale, int32_t group) {
   using F = DF<T, D>;
   constexpr int GM = DkvGroup<D>::GM;
