@@ -968,12 +968,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 // bias tile (keys x queries) is staged once for the group.  GM = 1: measured
 // on gfx950, the registers of more batches cost more occupancy than the shared
 // bias tile saves.
-// BF16 requests four waves per SIMD (head dim 32: 127 registers, 81 -> 74 us per
-// row-attention launch at N_seq = 128, N_res = 256); FP32 needs 160 and keeps three.
+// BF16 at head dim 32 requests four waves per SIMD (127 registers, 81 -> 74 us
+// per row-attention launch at N_seq = 128, N_res = 256); at head dims 8 and 16,
+// and with a strided bias, that request spills, and FP32 needs 160: three waves.
 template <int D> struct DkvGroup { static constexpr int GM = 1; };
 
 template <typename T, int D, int BM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 ? 4 : 3))) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 && D == 32 && BM != BIAS_STRIDED ? 4 : 3))) void attn_bwd_dkdv_kernel(AttnCore a, AttnGrad gr, float scale_log2,
                                                             float scale, int32_t group) {
   using F = DF<T, D>;
   constexpr int GM = DkvGroup<D>::GM;
