@@ -109,10 +109,23 @@ evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, co
   const int64_t tm = big ? 128 : 64;
   const int64_t tiles = ((M + tm - 1) / tm) * ((N + tm - 1) / tm);
   const int64_t target = big ? 256 : 1024;
-  int64_t split = (target + tiles - 1) / tiles;
-  int64_t maxsplit = rows / (big ? 1024 : 256) > 0 ? rows / (big ? 1024 : 256) : 1;
-  if (split > maxsplit) split = maxsplit;
-  if (split < 1) split = 1;
+  auto split_of = [&](int64_t r) {
+    int64_t sp = (target + tiles - 1) / tiles;
+    const int64_t mx = r / (big ? 1024 : 256) > 0 ? r / (big ? 1024 : 256) : 1;
+    if (sp > mx) sp = mx;
+    return sp < 1 ? (int64_t)1 : sp;
+  };
+  // Operands past 2 GiB (the plain GEMM kernel, which also takes the column
+  // sums, addresses them with 32-bit buffer offsets): row chunks that fit, each
+  // with slices of its own in the partial buffers, all reduced together.
+  const int64_t lim = (1LL << 31) - 4096;
+  const int64_t ldm = ldx > ldy ? ldx : ldy;
+  int64_t crow = rows;
+  if ((rows + 1) * ldm * (int64_t)sizeof(T) > lim) crow = (lim / ((int64_t)sizeof(T) * ldm) - 1) / 256 * 256;
+  if (crow < 1) { set_error("wgrad: rows of %lld elements too long", (long long)ldm); return EVO_ESHAPE; }
+  const int64_t nch = (rows + crow - 1) / crow;
+  int64_t split = 0;
+  for (int64_t ch = 0; ch < nch; ++ch) split += split_of(rows - ch * crow < crow ? rows - ch * crow : crow);
   const bool direct = split == 1 && nseg == 1;
   float* part = direct ? nullptr : ws.take_n<float>((size_t)split * M * N);
   // bias gradients: the column sums of dY, taken by the GEMM from the dY tiles
@@ -125,25 +138,30 @@ evo_status_t wgrad_segments(const Ctx& c, Arena& ws, const T* X, int64_t ldx, co
     anyb = anyb || (dB && dB[s]);
   }
   if (!any && !anyb) return EVO_OK;
-  GemmArgs g;
-  g.M = M; g.N = N; g.K = rows;
-  g.split_k = (int)split;
-  g.big_tiles = big ? 1 : 0;
-  g.A = op_colmajor(X, ldx);
-  g.B = op_colmajor(dY + lo, ldy);
-  g.colsum = anyb ? cpart : nullptr;
-  if (direct) {   // single slice, single segment: accumulate straight into dW
-    g.epi = epi_rowmajor(dW[0] ? dW[0] : part, N, true);
-    g.epi.accumulate = 1;
-  } else {
-    g.epi = epi_rowmajor(part, N, true);
-    g.epi.batch = M * N;
-  }
   if (direct && !dW[0]) {
     set_error("wgrad: a bias gradient without its weight gradient");
     return EVO_EINVAL;
   }
-  EVO_TRY(gemm<T>(c, g));
+  int64_t s0 = 0;
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t r0 = ch * crow, r = rows - r0 < crow ? rows - r0 : crow, sp = split_of(r);
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = r;
+    g.split_k = (int)sp;
+    g.big_tiles = big ? 1 : 0;
+    g.A = op_colmajor(X + r0 * ldx, ldx);
+    g.B = op_colmajor(dY + r0 * ldy + lo, ldy);
+    g.colsum = anyb ? cpart + s0 * N : nullptr;
+    if (direct) {   // single slice, single segment: accumulate straight into dW
+      g.epi = epi_rowmajor(dW[0], N, true);
+      g.epi.accumulate = 1;
+    } else {
+      g.epi = epi_rowmajor(part + s0 * M * N, N, true);
+      g.epi.batch = M * N;
+    }
+    EVO_TRY(gemm<T>(c, g));
+    s0 += sp;
+  }
   if (anyb) {
     RedSegs rb;
     rb.nseg = nseg;

@@ -218,9 +218,78 @@ def test_opm(dtype):
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("which", ["msa", "pair"])
 def test_transition(dtype, which):
-    from paper_2207_05477_amd import binding as B
     say(f"transition_{which} dtype={dtype}")
-    inp = _setup(dtype)
+    _transition_case(dtype, which, OPCFG)
+
+
+def _profiled_kernels(fn):
+    """Names of the kernels the library launches inside fn() (its launch profiler)."""
+    import ctypes
+    from paper_2207_05477_amd import _abi as A
+    lib = A.load()
+
+    class Stat(ctypes.Structure):
+        _fields_ = [("name", ctypes.c_char * 120), ("launches", ctypes.c_int64),
+                    ("total_ms", ctypes.c_double), ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+    lib.evo_profile_begin.restype = None
+    lib.evo_profile_end.argtypes = [ctypes.POINTER(Stat), ctypes.c_int32]
+    lib.evo_profile_end.restype = ctypes.c_int32
+    torch.cuda.synchronize()
+    lib.evo_profile_begin()
+    try:
+        fn()
+    finally:
+        recs = (Stat * 1024)()
+        n = lib.evo_profile_end(recs, 1024)
+    assert n >= 0, lib.evo_last_error().decode()
+    return [r.name.decode() for r in recs[:n]]
+
+
+def test_transition_generic_gemm():
+    """Rows x channels past 2 GiB (FP32, 1048581 rows of 512, ragged): the plain
+    GEMM kernel addresses its operands through 32-bit buffer offsets and rejects
+    them, so the general two-level kernel runs the transition's GEMMs.  The
+    transition is row-wise, so its forward and input gradient are checked
+    against the oracle on sampled rows (first, last, middle)."""
+    from paper_2207_05477_amd import binding as B
+    dtype = "f32"
+    cfg = OPCFG.replace(c_m=512)
+    say("transition_generic_gemm dtype=f32 rows=1048581 c=512")
+    inp = _setup(dtype, cfg)
+    C = 512
+    rows = (1 << 31) // (C * 4) + 5
+    gen = torch.Generator().manual_seed(11)
+    x32 = torch.randn(rows, C, generator=gen)
+    up32 = torch.randn(rows, C, generator=gen)
+    idx = torch.tensor([0, 1, 777777, rows // 2, rows - 2, rows - 1])
+    x64, up = x32[idx].double(), up32[idx].double()
+    p = dict(inp["params"][0]["msa_trans"])
+    probe = {"choose": MARGIN[dtype]}
+    with torch.no_grad():
+        O.transition(x64, p, 1e-5, probe)
+    p["b_1"] = p["b_1"].to(torch.float32).to(torch.float64)
+    upd, g = oracle_grads(lambda x, p: O.transition(x, p, 1e-5), {"x": x64, "p": p}, up)
+    desc = B.trans_desc(dtype, rows, C, cfg.transition_factor)
+    pd = params_dev(p)
+    w = B.weight_struct("msa_trans", pd)
+    x = x32.cuda()
+    res = {}
+
+    def run():
+        res["out"], saved = B.evo_transition_fwd(desc, w, x)
+        dpar = _zeros_like(pd)
+        res["dx"] = B.evo_transition_bwd(desc, w, x, saved, up32.cuda(), B.weight_struct("msa_trans", dpar))
+        torch.cuda.synchronize()
+    names = _profiled_kernels(run)
+    assert any(n.startswith("gemm_kernel<") for n in names), names
+    di = idx.cuda()
+    check_update("msa_trans fwd (sampled rows)", res["out"][di], x64, upd, dtype)
+    check("msa_trans dx (sampled rows)", res["dx"][di], up + g["x"], TOL[dtype])
+
+
+def _transition_case(dtype, which, cfg):
+    from paper_2207_05477_amd import binding as B
+    inp = _setup(dtype, cfg)
     tol = TOL[dtype]
     sub = "msa_trans" if which == "msa" else "pair_trans"
     x64 = inp["m"] if which == "msa" else inp["z"]
@@ -240,7 +309,7 @@ def test_transition(dtype, which):
     upd, g = oracle_grads(lambda x, p: O.transition(x, p, 1e-5), {"x": x64, "p": p}, up)
     C = x64.shape[-1]
     rows = x64.numel() // C
-    desc = B.trans_desc(dtype, rows, C, OPCFG.transition_factor)
+    desc = B.trans_desc(dtype, rows, C, cfg.transition_factor)
     pd = params_dev(p)
     w = B.weight_struct(sub, pd)
     x = to_dev(x64, dtype)
